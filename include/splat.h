@@ -1,0 +1,261 @@
+/*
+ * splat.h -- C ABI of libsplat: a differentiable, tile-based Gaussian rasterizer for cameras
+ * and spinning lidars on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the rendering core of SplatAD (arXiv 2411.16816):
+ *   - Gaussians with opacity o, mean mu, covariance from scale + quaternion, and features
+ *     (Sec. 3.1) are projected into a camera image plane (Sec. 3.2) or into lidar spherical
+ *     coordinates (azimuth, elevation, range) (Sec. 3.3, Eq. spherical_projection),
+ *     with rolling-shutter velocities (Eq. pixel_velocity, App. D and the lidar v^S);
+ *   - binned into tiles (16x16 pixels in the paper; lidar tiles of N_phi azimuth steps by
+ *     N_omega channels, App. A) and depth-sorted per tile (z for cameras, range for lidar);
+ *   - alpha-composited front to back per pixel or per supplied lidar ray (Eqs. t_pix,
+ *     alpha_blend, alpha, delta), also blending depth / rolling-shutter corrected range and
+ *     opacity, with an optional median range (Sec. 3.3);
+ *   - differentiated by a hand-written adjoint (Sec. 3.4, "Implementation").
+ *
+ * Conventions for every call
+ *   - Return value: SPLAT_OK or an error code; no C++ exception crosses the ABI.  Arguments are
+ *     validated on the host before anything is launched; an invalid call launches nothing.
+ *   - All array pointers inside SplatGaussians, SplatProjected, SplatTileLists, SplatRenderOut
+ *     and SplatGrads are DEVICE pointers owned by the caller (float32 row-major, int32 indices,
+ *     int64 offsets).  Host structs themselves are read during the call only.
+ *   - Every call is stream-ordered and asynchronous on `stream` (a hipStream_t, NULL = default
+ *     stream).  No call synchronises the host or allocates device memory, so every call may be
+ *     captured into a hipGraph.  Scratch memory comes from a caller-provided workspace.
+ *   - Asynchronous conditions (intersection overflow, non-finite Gaussians, invalid rays) are
+ *     recorded in a caller-provided device SplatStatus; read it after the stream completes.
+ *   - Inputs are never modified.  Gradients are ACCUMULATED (+=) into SplatGrads.
+ *   - A call covers the sensors [first, first + count) of a rig.  Such a call is self-contained:
+ *     its records, tile ids, ray ids and outputs are numbered from the first sensor of the call
+ *     ("local" numbering), so one-sensor calls (plain mode) and all-sensor calls (batched mode)
+ *     use the same layout rules.  SplatRigLayout gives every offset.
+ */
+#ifndef SPLAT_H_
+#define SPLAT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPLAT_OK 0
+#define SPLAT_ERR_INVALID_ARG 1
+#define SPLAT_ERR_CAPACITY 2
+#define SPLAT_ERR_DEVICE 3
+#define SPLAT_ERR_UNSUPPORTED 4
+
+#define SPLAT_MAX_EL_TILES 64         /* lidar elevation tiles (M_omega) per sensor */
+#define SPLAT_MAX_SENSORS 1024        /* sensors per rig */
+#define SPLAT_MAX_CHANNELS 64         /* blended feature channels per sensor */
+#define SPLAT_RAYS_PER_ITEM 256       /* lidar rays per rasterisation work item (App. A) */
+
+/* candidate rule of the rasterisers */
+#define SPLAT_SUPPORT_BOX 0   /* Gaussians whose 3-sigma + rolling-shutter box contains the ray */
+#define SPLAT_SUPPORT_TILE 1  /* every Gaussian listed for the ray's tile (paper-literal) */
+
+/* Status written by the device.  Zero it before a sequence of calls; fields accumulate. */
+typedef struct SplatStatus {
+  unsigned long long n_isect;     /* intersections (tile, Gaussian) of the last bin/sort      */
+  unsigned long long k_cap;       /* capacity the last bin/sort was given                      */
+  unsigned int overflow;          /* non-zero if n_isect exceeded k_cap (lists truncated)      */
+  unsigned int n_nonfinite;       /* projections culled because of non-finite values           */
+  unsigned int n_rays_invalid;    /* lidar rays outside [0, 2pi) x [b_0, b_M): output zeros    */
+  unsigned int n_rays_time;       /* lidar rays with |t| > t_rs / 2 (still rendered)           */
+} SplatStatus;
+
+/* Gaussians (Sec. 3.1).  Device arrays. */
+typedef struct SplatGaussians {
+  int64_t n;
+  const float* means;       /* [n,3] world frame                                              */
+  const float* log_scales;  /* [n,3] scale = exp(log_scale)                                   */
+  const float* quats;       /* [n,4] (w,x,y,z), normalised inside                             */
+  const float* opacities;   /* [n]   in (0,1)                                                  */
+  const float* velocities;  /* [n,3] world-frame velocity of each Gaussian, or NULL (zero)     */
+  const float* features;    /* [n,c_total] base colour and features                           */
+  int32_t c_total;
+} SplatGaussians;
+
+/* Pinhole camera (Sec. 3.2).  x_c = R x_w + t with x right, y down, z forward.  Velocities are
+ * in the camera frame.  t_rs is the rolling-shutter time between first and last row; pixel
+ * row v is captured at t = ((v + 1/2) / height - 1/2) t_rs (Eq. t_pix, pixel centres). */
+typedef struct SplatCamera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float lin_vel[3];
+  float ang_vel[3];
+  float t_rs;
+  float eps2d;       /* EWA dilation s of Eq. alpha (0.3 in the paper)                           */
+  float near_plane;  /* cull z <= near_plane                                                    */
+  float far_plane;   /* cull z >= far_plane                                                     */
+  float jac_clamp;   /* x/z, y/z clamped to +-jac_clamp * (size/2)/f inside J (0 = off)        */
+  int32_t feat_offset, n_channels;  /* blended feature columns [offset, offset + n_channels)   */
+  int32_t tile_w, tile_h;           /* pixels per tile; tile_w * tile_h <= 256, both >= 1      */
+} SplatCamera;
+
+/* Spinning lidar (Sec. 3.3, App. A).  x_l = R x_w + t with x forward, y left, z up.
+ * Azimuth tiles are tile_az * az_res wide and there are n_az_tiles of them (M_phi, with
+ * M_phi * tile_az * az_res >= 2 pi); elevation tiles are [elev_bounds[k], elev_bounds[k+1]).
+ * Rays are supplied (azimuth in [0, 2pi), elevation, time relative to the middle of the sweep). */
+typedef struct SplatLidar {
+  float R[9];
+  float t[3];
+  float lin_vel[3];
+  float ang_vel[3];
+  float t_rs;        /* sweep duration                                                         */
+  float eps2d;       /* dilation in rad^2                                                      */
+  float r_min, r_max;
+  float az_res;      /* azimuth step [rad]                                                     */
+  int32_t tile_az;   /* N_phi                                                                  */
+  int32_t n_az_tiles;/* M_phi                                                                  */
+  int32_t n_el_tiles;/* M_omega (<= SPLAT_MAX_EL_TILES)                                        */
+  const float* elev_bounds;  /* HOST array [n_el_tiles + 1], strictly increasing [rad]          */
+  int64_t n_rays;
+  const float* ray_az;       /* device [n_rays] */
+  const float* ray_el;       /* device [n_rays] */
+  const float* ray_t;        /* device [n_rays] */
+  int32_t feat_offset, n_channels;
+} SplatLidar;
+
+/* Opaque rig: a device-resident table of sensors (cameras first, then lidars). */
+typedef struct SplatRig SplatRig;
+
+/* Offsets of every sensor in the rig's global numbering (host copy). */
+typedef struct SplatRigLayout {
+  int32_t n_sensors;       /* n_cameras + n_lidars; sensor s < n_cameras is a camera          */
+  int32_t n_cameras;
+  int64_t tile_base[SPLAT_MAX_SENSORS + 1];      /* first tile of each sensor; [n] = total      */
+  int64_t ray_base[SPLAT_MAX_SENSORS + 1];       /* first ray (pixel) of each sensor           */
+  int64_t feat_base[SPLAT_MAX_SENSORS + 1];      /* first float of each sensor's feature rows  */
+} SplatRigLayout;
+
+/* Projected records, one per (sensor, Gaussian): record = (s - first) * n + gaussian.
+ * Device arrays, caller-allocated with count * n records. */
+typedef struct SplatProjected {
+  int64_t n_records;
+  float* mv;        /* [n_records,4] mean (u,v) | (phi,omega), and its velocity               */
+  float* cn;        /* [n_records,4] conic (a,b,c) of (Sigma + sI)^-1 = [[a,b],[b,c]], o_eff    */
+  float* box;       /* [n_records,4] lo_u, lo_v, hi_u, hi_v of the 3-sigma + RS box          */
+  float* dv;        /* [n_records,2] depth (z | range) and range velocity (lidar; 0 camera)    */
+  int32_t* rect;    /* [n_records,4] tiles: camera (x0, y0, nx, ny); lidar (az0, el0, naz, nel) */
+  int32_t* n_tiles; /* [n_records] tiles touched (0 = culled)                                 */
+} SplatProjected;
+
+/* Per-tile depth-ordered lists.  Tile ids are local to the call. */
+typedef struct SplatTileLists {
+  int64_t k_cap;          /* capacity of gauss[]                                             */
+  int32_t* gauss;         /* [k_cap] Gaussian ids, grouped by tile, by (depth, id) inside      */
+  int32_t* tile_range;    /* [n_tiles, 2] [start, end) into gauss                             */
+  /* lidar only (NULL for camera calls): */
+  int32_t* ray_order;     /* [n_rays] local ray ids grouped by tile (invalid rays last)         */
+  int32_t* ray_range;     /* [n_tiles + 1, 2] [start, end) into ray_order; entry n_tiles =
+                             invalid rays                                                      */
+  int32_t* work;          /* [work_cap, 2] work items (tile, first position in ray_order)      */
+  int32_t* n_work;        /* [1] number of work items                                          */
+  int64_t work_cap;       /* >= n_tiles + ceil(n_rays / 256) + 1                               */
+} SplatTileLists;
+
+/* Rendered outputs (local ray numbering).  feat rows are n_channels of the ray's sensor. */
+typedef struct SplatRenderOut {
+  float* feat;      /* [sum_s rays_s * C_s]                                                   */
+  float* depth;     /* [n_rays] blended z (camera) or RS-corrected range (lidar)              */
+  float* alpha;     /* [n_rays] 1 - T_final                                                   */
+  float* t_final;   /* [n_rays] final transmittance (saved for the adjoint)                   */
+  int32_t* last;    /* [n_rays] 1 + position in the tile list of the last blended Gaussian    */
+  float* median;    /* [n_rays] median range (lidar) or NULL                                  */
+} SplatRenderOut;
+
+/* Gradient accumulators (+=), device arrays shaped like SplatGaussians. */
+typedef struct SplatGrads {
+  float* means;       /* [n,3] */
+  float* log_scales;  /* [n,3] */
+  float* quats;       /* [n,4] */
+  float* opacities;   /* [n]   */
+  float* velocities;  /* [n,3] or NULL */
+  float* features;    /* [n,c_total] */
+} SplatGrads;
+
+const char* splat_status_string(int code);
+int splat_version(void);
+
+/* Host-only validation of one sensor description (no device call): SPLAT_OK or
+ * SPLAT_ERR_INVALID_ARG.  splat_rig_set applies the same checks. */
+int splat_check_camera(const SplatCamera* cam);
+int splat_check_lidar(const SplatLidar* lidar);
+
+/* ---- rig -------------------------------------------------------------------------------
+ * splat_rig_create allocates the rig's device table (not a hot-path call).  splat_rig_set
+ * validates the sensors on the host and uploads them asynchronously on `stream` from pinned
+ * host memory (it waits only for the rig's previous upload).  Cameras get sensor ids
+ * 0..n_cameras-1, lidars n_cameras..n_cameras+n_lidars-1. */
+int splat_rig_create(int32_t n_cameras, int32_t n_lidars, SplatRig** out);
+int splat_rig_set(SplatRig* rig, const SplatCamera* cams, const SplatLidar* lidars, void* stream);
+int splat_rig_layout(const SplatRig* rig, SplatRigLayout* out);
+void splat_rig_destroy(SplatRig* rig);
+
+/* Workspace bytes needed by any call on sensors [first, first+count) of `rig` with
+ * `n_gaussians` Gaussians and list capacity k_cap. */
+size_t splat_workspace_bytes(const SplatRig* rig, int32_t first, int32_t count, int64_t n_gaussians,
+                             int64_t k_cap);
+
+/* ---- a1 / a2: projection (Sec. 3.2 "Projection, tiling, and sorting", "Rolling shutter";
+ * Sec. 3.3 "Projection"; App. D).  Per (Gaussian, sensor): sensor-frame mean and covariance,
+ * projected mean, J Sigma J^T, RS velocity J(-w x mu - v + R v_g), dilation, conic,
+ * o_eff = o sqrt(det(Sigma2) / det(Sigma2 + sI)), box = mean +- (3 sqrt(diag(Sigma2 + sI)) +
+ * |v| t_rs / 2), culling (depth / range limits, box outside the image or elevation span,
+ * o_eff < 1/255, non-finite) and the tile rectangle.  Culled records get n_tiles = 0 and no
+ * other field; non-finite projections are counted in status->n_nonfinite (status may be NULL).
+ * Sensors of the call must be all cameras (resp. all lidars). */
+int splat_project_camera(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
+                         const SplatProjected* out, SplatStatus* status, void* stream);
+int splat_project_lidar(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
+                        const SplatProjected* out, SplatStatus* status, void* stream);
+
+/* ---- a3 / a4: tile binning + depth sort (Sec. 3.2; Sec. 3.3 "Tiling and sorting"; App. A).
+ * Orders records by depth (stable, so equal depths keep Gaussian-id order), emits one
+ * (tile, Gaussian) pair per touched tile, stably sorts the pairs by tile and writes per-tile
+ * ranges.  The lidar variant also bins the supplied rays into their tiles (a ray is a box of
+ * zero extent, App. A) and cuts every tile's rays into work items of <= 256 rays.  More than
+ * k_cap pairs: the lists are truncated (memory-safe), status->overflow is set and
+ * status->n_isect holds the needed capacity. */
+int splat_bin_sort_camera(const SplatRig* rig, int32_t first, int32_t count, int64_t n_gaussians,
+                          const SplatProjected* proj, const SplatTileLists* lists, void* ws,
+                          size_t ws_bytes, SplatStatus* status, void* stream);
+int splat_bin_sort_lidar(const SplatRig* rig, int32_t first, int32_t count, int64_t n_gaussians,
+                         const SplatProjected* proj, const SplatTileLists* lists, void* ws,
+                         size_t ws_bytes, SplatStatus* status, void* stream);
+
+/* ---- a5 / a6: rasterisation forward (Eqs. t_pix, alpha_blend, alpha, delta; Sec. 3.3 for
+ * the range blend r + v_r t and the median).  alpha = min(0.99, o_eff exp(-sigma)); alpha <
+ * 1/255 is skipped; blending stops before a Gaussian that would take T below 1e-4. */
+int splat_rasterize_fwd_camera(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
+                               const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                               const SplatRenderOut* out, void* stream);
+int splat_rasterize_fwd_lidar(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
+                              const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                              const SplatRenderOut* out, SplatStatus* status, void* stream);
+
+/* ---- a7: rasterisation backward + projection adjoint.  Walks each ray's list back to front
+ * from `last`, recovering T_i = T_{i+1} / (1 - alpha_i) from the saved T_final, reduces
+ * per-Gaussian gradients across a wavefront before global atomics, then chains the 2-D
+ * gradients to means, log-scales, quaternions, opacities, velocities and features.
+ * d_feat / d_depth / d_alpha are the upstream gradients of SplatRenderOut feat/depth/alpha. */
+int splat_rasterize_bwd_camera(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
+                               const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                               const SplatRenderOut* saved, const float* d_feat, const float* d_depth,
+                               const float* d_alpha, const SplatGrads* grads, void* ws, size_t ws_bytes,
+                               void* stream);
+int splat_rasterize_bwd_lidar(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
+                              const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                              const SplatRenderOut* saved, const float* d_feat, const float* d_depth,
+                              const float* d_alpha, const SplatGrads* grads, void* ws, size_t ws_bytes,
+                              void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPLAT_H_ */

@@ -1,0 +1,359 @@
+"""Thin ctypes binding of libsplat (include/splat.h).
+
+Argument marshalling only: every step of projection, binning, sorting and compositing runs in
+the library's HIP kernels.  PyTorch provides device memory and the stream.  Loading fails loudly
+when the library has not been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import structs as st
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsplat.so")
+
+_lib = None
+
+BOX = st.SUPPORT_BOX
+TILE = st.SUPPORT_TILE
+KIND_CAMERA = 0
+KIND_LIDAR = 1
+
+_P = C.c_void_p
+
+
+def _declare(lib):
+    vp = C.c_void_p
+    i32, i64 = C.c_int32, C.c_int64
+    sig = {
+        "splat_status_string": (C.c_char_p, [C.c_int]),
+        "splat_version": (C.c_int, []),
+        "splat_check_camera": (C.c_int, [vp]),
+        "splat_check_lidar": (C.c_int, [vp]),
+        "splat_rig_create": (C.c_int, [i32, i32, C.POINTER(vp)]),
+        "splat_rig_set": (C.c_int, [vp, vp, vp, vp]),
+        "splat_rig_layout": (C.c_int, [vp, vp]),
+        "splat_rig_destroy": (None, [vp]),
+        "splat_workspace_bytes": (C.c_size_t, [vp, i32, i32, i64, i64]),
+        "splat_project_camera": (C.c_int, [vp, vp, i32, i32, vp, vp, vp]),
+        "splat_project_lidar": (C.c_int, [vp, vp, i32, i32, vp, vp, vp]),
+        "splat_bin_sort_camera": (C.c_int, [vp, i32, i32, i64, vp, vp, vp, C.c_size_t, vp, vp]),
+        "splat_bin_sort_lidar": (C.c_int, [vp, i32, i32, i64, vp, vp, vp, C.c_size_t, vp, vp]),
+        "splat_rasterize_fwd_camera": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp]),
+        "splat_rasterize_fwd_lidar": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp]),
+        "splat_rasterize_bwd_camera": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+        "splat_rasterize_bwd_lidar": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+def load(path: str = LIB_PATH):
+    """Load libsplat.so (built by `python -m paper_2411_16816_amd.build`)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2411_16816_amd.build`")
+        _lib = _declare(C.CDLL(path))
+    return _lib
+
+
+class SplatError(RuntimeError):
+    pass
+
+
+def check(rc: int, what: str):
+    if rc != 0:
+        raise SplatError(f"{what}: {load().splat_status_string(rc).decode()} ({rc})")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+# ----------------------------------------------------------------------------------------
+@dataclass
+class GaussTensors:
+    means: torch.Tensor
+    log_scales: torch.Tensor
+    quats: torch.Tensor
+    opacities: torch.Tensor
+    velocities: Optional[torch.Tensor]
+    features: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @staticmethod
+    def from_numpy(g, device="cuda") -> "GaussTensors":
+        f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        return GaussTensors(f(g.means), f(g.log_scales), f(g.quats), f(g.opacities),
+                            None if g.velocities is None else f(g.velocities), f(g.features))
+
+    def struct(self) -> st.SplatGaussians:
+        s = st.SplatGaussians()
+        s.n = self.n
+        s.means, s.log_scales, s.quats = _ptr(self.means), _ptr(self.log_scales), _ptr(self.quats)
+        s.opacities, s.velocities, s.features = _ptr(self.opacities), _ptr(self.velocities), _ptr(self.features)
+        s.c_total = int(self.features.shape[1])
+        return s
+
+
+class Rig:
+    """A SplatRig: cameras first, then lidars; lidar ray arrays are uploaded and kept alive."""
+
+    def __init__(self, cameras: Sequence, lidars: Sequence, device="cuda"):
+        lib = load()
+        self.lib = lib
+        self.cameras = list(cameras)
+        self.lidars = list(lidars)
+        self.n_cam, self.n_lid = len(self.cameras), len(self.lidars)
+        h = C.c_void_p()
+        check(lib.splat_rig_create(self.n_cam, self.n_lid, C.byref(h)), "splat_rig_create")
+        self.handle = h
+        self._keep = []
+        self.ray_tensors = []
+        cams = (st.SplatCamera * max(1, self.n_cam))()
+        for i, c in enumerate(self.cameras):
+            cams[i] = st.camera_struct(c)
+        lids = (st.SplatLidar * max(1, self.n_lid))()
+        for i, l in enumerate(self.lidars):
+            az = torch.from_numpy(np.ascontiguousarray(l.ray_az, np.float32)).to(device)
+            el = torch.from_numpy(np.ascontiguousarray(l.ray_el, np.float32)).to(device)
+            tt = torch.from_numpy(np.ascontiguousarray(l.ray_t, np.float32)).to(device)
+            self.ray_tensors.append((az, el, tt))
+            lids[i] = st.lidar_struct(l, (az.data_ptr(), el.data_ptr(), tt.data_ptr()), self._keep)
+        self._cams, self._lids = cams, lids
+        check(lib.splat_rig_set(h, cams if self.n_cam else None, lids if self.n_lid else None, _stream()),
+              "splat_rig_set")
+        lay = st.SplatRigLayout()
+        check(lib.splat_rig_layout(h, C.byref(lay)), "splat_rig_layout")
+        n = self.n_cam + self.n_lid
+        self.tile_base = np.array(lay.tile_base[:n + 1], np.int64)
+        self.ray_base = np.array(lay.ray_base[:n + 1], np.int64)
+        self.feat_base = np.array(lay.feat_base[:n + 1], np.int64)
+        self.sensors = self.cameras + self.lidars
+
+    def kind(self, s: int) -> int:
+        return KIND_CAMERA if s < self.n_cam else KIND_LIDAR
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                torch.cuda.synchronize()
+                self.lib.splat_rig_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+def _status_tensor(device) -> torch.Tensor:
+    return torch.zeros(C.sizeof(st.SplatStatus), dtype=torch.uint8, device=device)
+
+
+def read_status(t: torch.Tensor) -> st.SplatStatus:
+    b = t.cpu().numpy().tobytes()
+    return st.SplatStatus.from_buffer_copy(b)
+
+
+class SensorPass:
+    """All buffers of one call range [first, first + count) of a rig (all cameras or all lidars),
+    and the four library calls.  `count == 1` is the plain per-sensor form; larger counts are
+    the batched multi-sensor form of the same calls."""
+
+    def __init__(self, rig: Rig, first: int, count: int, n_gauss: int, k_cap: int, device="cuda"):
+        self.rig, self.first, self.count = rig, first, count
+        self.lib = rig.lib
+        kinds = {rig.kind(s) for s in range(first, first + count)}
+        assert len(kinds) == 1, "a call range holds one sensor kind"
+        self.kind = kinds.pop()
+        self.lidar = self.kind == KIND_LIDAR
+        self.device = device
+        self.n_gauss = n_gauss
+        tb, rb, fb = rig.tile_base, rig.ray_base, rig.feat_base
+        self.n_tiles = int(tb[first + count] - tb[first])
+        self.n_rays = int(rb[first + count] - rb[first])
+        self.n_feat = int(fb[first + count] - fb[first])
+        self.ray_off = rb[first:first + count + 1] - rb[first]
+        self.feat_off = fb[first:first + count + 1] - fb[first]
+        R = count * n_gauss
+        i32 = dict(dtype=torch.int32, device=device)
+        f32 = dict(dtype=torch.float32, device=device)
+        self.mv = torch.empty((R, 4), **f32)
+        self.cn = torch.empty((R, 4), **f32)
+        self.box = torch.empty((R, 4), **f32)
+        self.dv = torch.empty((R, 2), **f32)
+        self.rect = torch.empty((R, 4), **i32)
+        self.ntiles = torch.empty((R,), **i32)
+        self.tile_range = torch.empty((max(1, self.n_tiles), 2), **i32)
+        if self.lidar:
+            self.work_cap = self.n_tiles + (self.n_rays + 255) // 256 + 1
+            self.ray_order = torch.empty((max(1, self.n_rays),), **i32)
+            self.ray_range = torch.empty((self.n_tiles + 1, 2), **i32)
+            self.work = torch.empty((self.work_cap, 2), **i32)
+            self.n_work = torch.zeros((1,), **i32)
+        else:
+            self.work_cap = 0
+            self.ray_order = self.ray_range = self.work = self.n_work = None
+        self.feat = torch.empty((max(1, self.n_feat),), **f32)
+        self.depth = torch.empty((max(1, self.n_rays),), **f32)
+        self.alpha = torch.empty((max(1, self.n_rays),), **f32)
+        self.t_final = torch.empty((max(1, self.n_rays),), **f32)
+        self.last = torch.empty((max(1, self.n_rays),), **i32)
+        self.median = torch.empty((max(1, self.n_rays),), **f32) if self.lidar else None
+        self.status = _status_tensor(device)
+        self.set_capacity(k_cap)
+
+    # ---- structs -------------------------------------------------------------------------
+    def set_capacity(self, k_cap: int):
+        self.k_cap = int(k_cap)
+        self.gauss = torch.empty((max(1, self.k_cap),), dtype=torch.int32, device=self.device)
+        nbytes = int(self.lib.splat_workspace_bytes(self.rig.handle, self.first, self.count, self.n_gauss, self.k_cap))
+        if nbytes == 0:
+            raise SplatError("splat_workspace_bytes returned 0")
+        self.ws = torch.empty((nbytes + 256,), dtype=torch.uint8, device=self.device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.ws_bytes = nbytes
+
+    def proj_struct(self):
+        p = st.SplatProjected()
+        p.n_records = self.count * self.n_gauss
+        p.mv, p.cn, p.box, p.dv = _ptr(self.mv), _ptr(self.cn), _ptr(self.box), _ptr(self.dv)
+        p.rect, p.n_tiles = _ptr(self.rect), _ptr(self.ntiles)
+        return p
+
+    def lists_struct(self):
+        L = st.SplatTileLists()
+        L.k_cap = self.k_cap
+        L.gauss, L.tile_range = _ptr(self.gauss), _ptr(self.tile_range)
+        L.ray_order, L.ray_range, L.work, L.n_work = (_ptr(self.ray_order), _ptr(self.ray_range),
+                                                      _ptr(self.work), _ptr(self.n_work))
+        L.work_cap = self.work_cap
+        return L
+
+    def out_struct(self):
+        o = st.SplatRenderOut()
+        o.feat, o.depth, o.alpha = _ptr(self.feat), _ptr(self.depth), _ptr(self.alpha)
+        o.t_final, o.last, o.median = _ptr(self.t_final), _ptr(self.last), _ptr(self.median)
+        return o
+
+    # ---- the four calls -------------------------------------------------------------------
+    def project(self, g: GaussTensors, stream=None):
+        fn = self.lib.splat_project_lidar if self.lidar else self.lib.splat_project_camera
+        check(fn(C.byref(g.struct()), self.rig.handle, self.first, self.count, C.byref(self.proj_struct()),
+                 _ptr(self.status), _stream(stream)), "splat_project")
+
+    def bin_sort(self, stream=None):
+        fn = self.lib.splat_bin_sort_lidar if self.lidar else self.lib.splat_bin_sort_camera
+        check(fn(self.rig.handle, self.first, self.count, self.n_gauss, C.byref(self.proj_struct()),
+                 C.byref(self.lists_struct()), C.c_void_p(self.ws_ptr), self.ws_bytes, _ptr(self.status),
+                 _stream(stream)), "splat_bin_sort")
+
+    def raster_fwd(self, g: GaussTensors, support=BOX, stream=None):
+        if self.lidar:
+            check(self.lib.splat_rasterize_fwd_lidar(C.byref(g.struct()), self.rig.handle, self.first, self.count,
+                                                     C.byref(self.proj_struct()), C.byref(self.lists_struct()),
+                                                     support, C.byref(self.out_struct()), _ptr(self.status),
+                                                     _stream(stream)), "splat_rasterize_fwd_lidar")
+        else:
+            check(self.lib.splat_rasterize_fwd_camera(C.byref(g.struct()), self.rig.handle, self.first, self.count,
+                                                      C.byref(self.proj_struct()), C.byref(self.lists_struct()),
+                                                      support, C.byref(self.out_struct()), _stream(stream)),
+                  "splat_rasterize_fwd_camera")
+
+    def raster_bwd(self, g: GaussTensors, dF, dD, dA, grads: GaussTensors, support=BOX, stream=None):
+        gr = st.SplatGrads()
+        gr.means, gr.log_scales, gr.quats = _ptr(grads.means), _ptr(grads.log_scales), _ptr(grads.quats)
+        gr.opacities, gr.velocities, gr.features = _ptr(grads.opacities), _ptr(grads.velocities), _ptr(grads.features)
+        fn = self.lib.splat_rasterize_bwd_lidar if self.lidar else self.lib.splat_rasterize_bwd_camera
+        check(fn(C.byref(g.struct()), self.rig.handle, self.first, self.count, C.byref(self.proj_struct()),
+                 C.byref(self.lists_struct()), support, C.byref(self.out_struct()), _ptr(dF), _ptr(dD), _ptr(dA),
+                 C.byref(gr), C.c_void_p(self.ws_ptr), self.ws_bytes, _stream(stream)), "splat_rasterize_bwd")
+
+    # ---- conveniences ---------------------------------------------------------------------
+    def fit_capacity(self, g: GaussTensors, margin: float = 1.1, stream=None) -> int:
+        """Project, bin with zero capacity to learn K, and size the lists (host sync)."""
+        self.status.zero_()
+        self.project(g, stream)
+        old = self.k_cap
+        if old != 0:
+            self.set_capacity(0)
+        self.bin_sort(stream)
+        torch.cuda.synchronize()
+        K = int(read_status(self.status).n_isect)
+        self.set_capacity(max(1, int(K * margin) + 1024))
+        self.status.zero_()
+        return K
+
+    def render(self, g: GaussTensors, support=BOX, stream=None):
+        """project -> bin/sort -> rasterise (no host sync).  Returns the output tensors."""
+        self.project(g, stream)
+        self.bin_sort(stream)
+        self.raster_fwd(g, support, stream)
+        return self.outputs()
+
+    def outputs(self):
+        n = self.n_rays
+        return dict(feat=self.feat[:self.n_feat], depth=self.depth[:n], alpha=self.alpha[:n],
+                    t_final=self.t_final[:n], last=self.last[:n],
+                    median=None if self.median is None else self.median[:n])
+
+    def sensor_slices(self, k: int):
+        """(ray slice, feature slice, channels) of the k-th sensor of the call."""
+        s = self.rig.sensors[self.first + k]
+        return (slice(int(self.ray_off[k]), int(self.ray_off[k + 1])),
+                slice(int(self.feat_off[k]), int(self.feat_off[k + 1])), s.n_channels)
+
+
+def zeros_like_grads(g: GaussTensors) -> GaussTensors:
+    z = torch.zeros_like
+    return GaussTensors(z(g.means), z(g.log_scales), z(g.quats), z(g.opacities),
+                        None if g.velocities is None else z(g.velocities), z(g.features))
+
+
+class SplatRenderFn(torch.autograd.Function):
+    """Differentiable render of one call range.  Inputs are the Gaussian tensors; outputs are the
+    flat feature rows, depth and alpha of the call (see SensorPass.sensor_slices).  The pass's
+    buffers hold the forward state, so backward must run before the pass renders again."""
+
+    @staticmethod
+    def forward(ctx, sp: SensorPass, support: int, means, log_scales, quats, opacities, velocities, features):
+        g = GaussTensors(means.contiguous(), log_scales.contiguous(), quats.contiguous(), opacities.contiguous(),
+                         None if velocities is None else velocities.contiguous(), features.contiguous())
+        sp.status.zero_()
+        sp.project(g)
+        sp.bin_sort()
+        st_ = read_status(sp.status)
+        if st_.overflow:
+            sp.set_capacity(int(st_.n_isect * 1.1) + 1024)
+            sp.bin_sort()
+        sp.raster_fwd(g, support)
+        ctx.sp, ctx.support, ctx.g = sp, support, g
+        ctx.has_vel = velocities is not None
+        o = sp.outputs()
+        return o["feat"].clone(), o["depth"].clone(), o["alpha"].clone()
+
+    @staticmethod
+    def backward(ctx, dF, dD, dA):
+        sp, g = ctx.sp, ctx.g
+        grads = zeros_like_grads(g)
+        f32 = lambda t, n: torch.zeros(n, dtype=torch.float32, device=g.means.device) if t is None else t.contiguous()
+        sp.raster_bwd(g, f32(dF, sp.n_feat), f32(dD, sp.n_rays), f32(dA, sp.n_rays), grads, ctx.support)
+        return (None, None, grads.means, grads.log_scales, grads.quats, grads.opacities,
+                grads.velocities if ctx.has_vel else None, grads.features)

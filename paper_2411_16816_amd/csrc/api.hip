@@ -1,0 +1,304 @@
+// api.hip -- the C ABI of libsplat (declared in include/splat.h): host-side validation, the rig
+// (device sensor table), workspace sizing, and dispatch to the kernel launchers.
+#include <new>
+#include <string.h>
+#include <vector>
+
+#include "kernels.hpp"
+#include "rig_build.hpp"
+
+using namespace splat;
+
+struct SplatRig {
+  int32_t n_cam = 0, n_lid = 0;
+  DevSensor* d_table = nullptr;     // device copy, read by every kernel
+  DevSensor* h_pinned = nullptr;    // pinned staging for asynchronous uploads
+  std::vector<DevSensor> host;      // host copy used for launch configuration
+  hipEvent_t uploaded = nullptr;
+  bool upload_pending = false;
+  bool is_set = false;
+  SplatRigLayout layout;
+};
+
+extern "C" {
+
+const char* splat_status_string(int code) {
+  switch (code) {
+    case SPLAT_OK: return "ok";
+    case SPLAT_ERR_INVALID_ARG: return "invalid argument";
+    case SPLAT_ERR_CAPACITY: return "capacity exceeded";
+    case SPLAT_ERR_DEVICE: return "device error";
+    case SPLAT_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+int splat_version(void) { return 1; }
+
+int splat_check_camera(const SplatCamera* c) {
+  if (!c) return SPLAT_ERR_INVALID_ARG;
+  DevSensor d;
+  return build_camera(*c, d);
+}
+
+int splat_check_lidar(const SplatLidar* l) {
+  if (!l) return SPLAT_ERR_INVALID_ARG;
+  DevSensor d;
+  return build_lidar(*l, d);
+}
+
+int splat_rig_create(int32_t n_cameras, int32_t n_lidars, SplatRig** out) {
+  if (!out || n_cameras < 0 || n_lidars < 0 || n_cameras + n_lidars <= 0 || n_cameras + n_lidars > SPLAT_MAX_SENSORS)
+    return SPLAT_ERR_INVALID_ARG;
+  *out = nullptr;
+  SplatRig* r = new (std::nothrow) SplatRig();
+  if (!r) return SPLAT_ERR_DEVICE;
+  r->n_cam = n_cameras;
+  r->n_lid = n_lidars;
+  const int n = n_cameras + n_lidars;
+  r->host.resize(n);
+  size_t bytes = sizeof(DevSensor) * n;
+  if (hipMalloc((void**)&r->d_table, bytes) != hipSuccess) { delete r; return SPLAT_ERR_DEVICE; }
+  if (hipHostMalloc((void**)&r->h_pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(r->d_table);
+    delete r;
+    return SPLAT_ERR_DEVICE;
+  }
+  if (hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming) != hipSuccess) {
+    (void)hipFree(r->d_table);
+    (void)hipHostFree(r->h_pinned);
+    delete r;
+    return SPLAT_ERR_DEVICE;
+  }
+  memset(&r->layout, 0, sizeof(r->layout));
+  *out = r;
+  return SPLAT_OK;
+}
+
+void splat_rig_destroy(SplatRig* r) {
+  if (!r) return;
+  if (r->upload_pending) (void)hipEventSynchronize(r->uploaded);
+  (void)hipEventDestroy(r->uploaded);
+  (void)hipFree(r->d_table);
+  (void)hipHostFree(r->h_pinned);
+  delete r;
+}
+
+int splat_rig_set(SplatRig* r, const SplatCamera* cams, const SplatLidar* lidars, void* stream) {
+  if (!r) return SPLAT_ERR_INVALID_ARG;
+  if ((r->n_cam > 0 && !cams) || (r->n_lid > 0 && !lidars)) return SPLAT_ERR_INVALID_ARG;
+  const int n = r->n_cam + r->n_lid;
+  std::vector<DevSensor> tab(n);
+  for (int i = 0; i < r->n_cam; ++i)
+    if (build_camera(cams[i], tab[i]) != SPLAT_OK) return SPLAT_ERR_INVALID_ARG;
+  for (int i = 0; i < r->n_lid; ++i)
+    if (build_lidar(lidars[i], tab[r->n_cam + i]) != SPLAT_OK) return SPLAT_ERR_INVALID_ARG;
+  SplatRigLayout L;
+  memset(&L, 0, sizeof(L));
+  L.n_sensors = n;
+  L.n_cameras = r->n_cam;
+  for (int i = 0; i < n; ++i) {
+    tab[i].tile_base = L.tile_base[i];
+    tab[i].ray_base = L.ray_base[i];
+    tab[i].feat_base = L.feat_base[i];
+    L.tile_base[i + 1] = L.tile_base[i] + tab[i].n_tiles;
+    L.ray_base[i + 1] = L.ray_base[i] + tab[i].n_rays;
+    L.feat_base[i + 1] = L.feat_base[i] + tab[i].n_rays * tab[i].n_ch;
+  }
+  if (L.tile_base[n] >= ((int64_t)1 << 31) - 1 || L.ray_base[n] >= ((int64_t)1 << 31) - 1) return SPLAT_ERR_UNSUPPORTED;
+  if (r->upload_pending && hipEventSynchronize(r->uploaded) != hipSuccess) return SPLAT_ERR_DEVICE;
+  memcpy(r->h_pinned, tab.data(), sizeof(DevSensor) * n);
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(r->d_table, r->h_pinned, sizeof(DevSensor) * n, hipMemcpyHostToDevice, s) != hipSuccess)
+    return SPLAT_ERR_DEVICE;
+  if (hipEventRecord(r->uploaded, s) != hipSuccess) return SPLAT_ERR_DEVICE;
+  r->upload_pending = true;
+  r->host = tab;
+  r->layout = L;
+  r->is_set = true;
+  return SPLAT_OK;
+}
+
+int splat_rig_layout(const SplatRig* r, SplatRigLayout* out) {
+  if (!r || !out || !r->is_set) return SPLAT_ERR_INVALID_ARG;
+  *out = r->layout;
+  return SPLAT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+static int make_view(const SplatRig* r, int32_t first, int32_t count, int kind, int64_t n_gauss, CallView& v) {
+  if (!r || !r->is_set || count <= 0 || first < 0 || first + count > r->n_cam + r->n_lid || n_gauss < 0)
+    return SPLAT_ERR_INVALID_ARG;
+  v.sens = r->d_table + first;
+  v.host = r->host.data() + first;
+  v.count = count;
+  v.n_gauss = n_gauss;
+  v.n_tiles = 0;
+  v.n_rays = 0;
+  v.c_max = 0;
+  for (int i = 0; i < count; ++i) {
+    const DevSensor& d = v.host[i];
+    if (kind >= 0 && d.kind != kind) return SPLAT_ERR_INVALID_ARG;
+    v.n_tiles += d.n_tiles;
+    v.n_rays += d.n_rays;
+    v.c_max = d.n_ch > v.c_max ? d.n_ch : v.c_max;
+  }
+  v.lidar = (kind == kLidar);
+  if ((int64_t)count * n_gauss >= ((int64_t)1 << 32)) return SPLAT_ERR_UNSUPPORTED;
+  return SPLAT_OK;
+}
+
+static int check_gaussians(const SplatGaussians* g, const CallView& v) {
+  if (!g || g->n != v.n_gauss || g->n < 0) return SPLAT_ERR_INVALID_ARG;
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacities)) return SPLAT_ERR_INVALID_ARG;
+  if (g->c_total < 0) return SPLAT_ERR_INVALID_ARG;
+  for (int i = 0; i < v.count; ++i) {
+    const DevSensor& d = v.host[i];
+    if (d.n_ch > 0 && (d.feat_off + d.n_ch > g->c_total || (g->n > 0 && !g->features))) return SPLAT_ERR_INVALID_ARG;
+  }
+  if (((uintptr_t)g->quats & 15) != 0) return SPLAT_ERR_INVALID_ARG;   // read as float4 rows
+  return SPLAT_OK;
+}
+
+static int check_proj(const SplatProjected* p, const CallView& v) {
+  if (!p || p->n_records != (int64_t)v.count * v.n_gauss) return SPLAT_ERR_INVALID_ARG;
+  if (p->n_records > 0 && (!p->mv || !p->cn || !p->box || !p->dv || !p->rect || !p->n_tiles)) return SPLAT_ERR_INVALID_ARG;
+  if ((((uintptr_t)p->mv | (uintptr_t)p->cn | (uintptr_t)p->box | (uintptr_t)p->rect) & 15) != 0 ||
+      ((uintptr_t)p->dv & 7) != 0)
+    return SPLAT_ERR_INVALID_ARG;
+  return SPLAT_OK;
+}
+
+static int check_lists(const SplatTileLists* L, const CallView& v) {
+  if (!L || L->k_cap < 0 || L->k_cap >= ((int64_t)1 << 31)) return SPLAT_ERR_INVALID_ARG;
+  if ((L->k_cap > 0 && !L->gauss) || !L->tile_range) return SPLAT_ERR_INVALID_ARG;
+  if (((uintptr_t)L->tile_range & 7) != 0) return SPLAT_ERR_INVALID_ARG;
+  if (v.lidar) {
+    if (!L->ray_order || !L->ray_range || !L->work || !L->n_work) return SPLAT_ERR_INVALID_ARG;
+    if ((((uintptr_t)L->ray_range | (uintptr_t)L->work) & 7) != 0) return SPLAT_ERR_INVALID_ARG;
+    int64_t need = v.n_tiles + (v.n_rays + SPLAT_RAYS_PER_ITEM - 1) / SPLAT_RAYS_PER_ITEM + 1;
+    if (L->work_cap < need) return SPLAT_ERR_INVALID_ARG;
+  }
+  return SPLAT_OK;
+}
+
+static int check_out(const SplatRenderOut* o, const CallView& v) {
+  if (!o || !o->depth || !o->alpha || !o->t_final || !o->last) return SPLAT_ERR_INVALID_ARG;
+  if (v.c_max > 0 && !o->feat) return SPLAT_ERR_INVALID_ARG;
+  return SPLAT_OK;
+}
+
+static int dev_err(hipError_t e) { return e == hipSuccess ? SPLAT_OK : SPLAT_ERR_DEVICE; }
+
+static int project_impl(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count, int kind,
+                        const SplatProjected* out, SplatStatus* st, void* stream) {
+  CallView v;
+  int rc = make_view(r, first, count, kind, g ? g->n : -1, v);
+  if (rc) return rc;
+  if ((rc = check_gaussians(g, v)) || (rc = check_proj(out, v))) return rc;
+  return dev_err(launch_project(v, *g, *out, st, (hipStream_t)stream));
+}
+
+static int bin_sort_impl(const SplatRig* r, int32_t first, int32_t count, int kind, int64_t n_gaussians,
+                         const SplatProjected* proj, const SplatTileLists* lists, void* ws, size_t ws_bytes,
+                         SplatStatus* st, void* stream) {
+  CallView v;
+  int rc = make_view(r, first, count, kind, n_gaussians, v);
+  if (rc) return rc;
+  if ((rc = check_proj(proj, v)) || (rc = check_lists(lists, v))) return rc;
+  Workspace w = carve_workspace(nullptr, (int64_t)count * n_gaussians, lists->k_cap, v.n_tiles, v.n_rays);
+  if (!ws || ws_bytes < w.bytes || ((uintptr_t)ws & 255) != 0) return SPLAT_ERR_INVALID_ARG;
+  w = carve_workspace(ws, (int64_t)count * n_gaussians, lists->k_cap, v.n_tiles, v.n_rays);
+  return dev_err(launch_bin_sort(v, *proj, *lists, w, st, (hipStream_t)stream));
+}
+
+static int raster_fwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count, int kind,
+                           const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                           const SplatRenderOut* out, void* stream) {
+  CallView v;
+  int rc = make_view(r, first, count, kind, g ? g->n : -1, v);
+  if (rc) return rc;
+  if (support != SPLAT_SUPPORT_BOX && support != SPLAT_SUPPORT_TILE) return SPLAT_ERR_INVALID_ARG;
+  if ((rc = check_gaussians(g, v)) || (rc = check_proj(proj, v)) || (rc = check_lists(lists, v)) ||
+      (rc = check_out(out, v)))
+    return rc;
+  return dev_err(launch_raster_fwd(v, *g, *proj, *lists, support, *out, (hipStream_t)stream));
+}
+
+static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count, int kind,
+                           const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                           const SplatRenderOut* saved, const float* dF, const float* dD, const float* dA,
+                           const SplatGrads* gr, void* ws, size_t ws_bytes, void* stream) {
+  CallView v;
+  int rc = make_view(r, first, count, kind, g ? g->n : -1, v);
+  if (rc) return rc;
+  if (support != SPLAT_SUPPORT_BOX && support != SPLAT_SUPPORT_TILE) return SPLAT_ERR_INVALID_ARG;
+  if ((rc = check_gaussians(g, v)) || (rc = check_proj(proj, v)) || (rc = check_lists(lists, v))) return rc;
+  if (!saved || !saved->t_final || !saved->last || !dD || !dA || (v.c_max > 0 && !dF)) return SPLAT_ERR_INVALID_ARG;
+  if (!gr || !gr->means || !gr->log_scales || !gr->quats || !gr->opacities || (v.c_max > 0 && !gr->features))
+    return SPLAT_ERR_INVALID_ARG;
+  Workspace w = carve_workspace(nullptr, (int64_t)count * g->n, lists->k_cap, v.n_tiles, v.n_rays);
+  if (!ws || ws_bytes < w.bytes || ((uintptr_t)ws & 255) != 0) return SPLAT_ERR_INVALID_ARG;
+  w = carve_workspace(ws, (int64_t)count * g->n, lists->k_cap, v.n_tiles, v.n_rays);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_fill_f32(w.g2d, (int64_t)count * g->n * 10, 0.f, s);
+  if (e == hipSuccess) e = launch_raster_bwd(v, *g, *proj, *lists, support, *saved, dF, dD, dA, w.g2d, gr->features, s);
+  if (e == hipSuccess) e = launch_project_bwd(v, *g, *proj, w.g2d, *gr, s);
+  return dev_err(e);
+}
+
+extern "C" {
+
+size_t splat_workspace_bytes(const SplatRig* r, int32_t first, int32_t count, int64_t n_gaussians, int64_t k_cap) {
+  CallView v;
+  if (make_view(r, first, count, -1, n_gaussians, v) != SPLAT_OK || k_cap < 0) return 0;
+  return carve_workspace(nullptr, (int64_t)count * n_gaussians, k_cap, v.n_tiles, v.n_rays).bytes;
+}
+
+int splat_project_camera(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,
+                         const SplatProjected* out, SplatStatus* st, void* stream) {
+  return project_impl(g, r, first, count, kCamera, out, st, stream);
+}
+int splat_project_lidar(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,
+                        const SplatProjected* out, SplatStatus* st, void* stream) {
+  return project_impl(g, r, first, count, kLidar, out, st, stream);
+}
+int splat_bin_sort_camera(const SplatRig* r, int32_t first, int32_t count, int64_t n_gaussians,
+                          const SplatProjected* proj, const SplatTileLists* lists, void* ws, size_t ws_bytes,
+                          SplatStatus* st, void* stream) {
+  return bin_sort_impl(r, first, count, kCamera, n_gaussians, proj, lists, ws, ws_bytes, st, stream);
+}
+int splat_bin_sort_lidar(const SplatRig* r, int32_t first, int32_t count, int64_t n_gaussians,
+                         const SplatProjected* proj, const SplatTileLists* lists, void* ws, size_t ws_bytes,
+                         SplatStatus* st, void* stream) {
+  return bin_sort_impl(r, first, count, kLidar, n_gaussians, proj, lists, ws, ws_bytes, st, stream);
+}
+int splat_rasterize_fwd_camera(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,
+                               const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                               const SplatRenderOut* out, void* stream) {
+  return raster_fwd_impl(g, r, first, count, kCamera, proj, lists, support, out, stream);
+}
+int splat_rasterize_fwd_lidar(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,
+                              const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                              const SplatRenderOut* out, SplatStatus* st, void* stream) {
+  (void)st;
+  return raster_fwd_impl(g, r, first, count, kLidar, proj, lists, support, out, stream);
+}
+int splat_rasterize_bwd_camera(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,
+                               const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                               const SplatRenderOut* saved, const float* d_feat, const float* d_depth,
+                               const float* d_alpha, const SplatGrads* grads, void* ws, size_t ws_bytes, void* stream) {
+  return raster_bwd_impl(g, r, first, count, kCamera, proj, lists, support, saved, d_feat, d_depth, d_alpha, grads,
+                         ws, ws_bytes, stream);
+}
+int splat_rasterize_bwd_lidar(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,
+                              const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                              const SplatRenderOut* saved, const float* d_feat, const float* d_depth,
+                              const float* d_alpha, const SplatGrads* grads, void* ws, size_t ws_bytes, void* stream) {
+  return raster_bwd_impl(g, r, first, count, kLidar, proj, lists, support, saved, d_feat, d_depth, d_alpha, grads,
+                         ws, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,557 @@
+// binsort.hip -- tile binning and depth sorting (SplatAD, arXiv 2411.16816: Sec. 3.2
+// "Projection, tiling, and sorting"; Sec. 3.3 "Tiling and sorting"; App. A).
+//
+// Pipeline of one call (all on the stream, no host synchronisation):
+//   1. records are stably sorted by depth (float32 bits; culled records get the largest key),
+//      so equal depths keep record (= Gaussian id) order;
+//   2. an exclusive scan of n_tiles in that order gives every record its slot range;
+//   3. every record emits (local tile id, Gaussian id) pairs into its slots;
+//   4. a stable LSD radix sort on the tile id groups the pairs by tile; inside a tile they stay in
+//      (depth, id) order, which is the ordering the paper obtains from its (tile | depth) keys;
+//   5. per-tile [start, end) ranges;
+//   6. lidar: rays are binned into their tiles (a ray is a box of zero extent, App. A), invalid
+//      rays go to an extra bin, and every tile's rays are cut into work items of <= 256 rays.
+//
+// The radix sort is an LDS-histogram reduce-then-scan sort with 8-bit digits: per-block digit
+// histograms (wavefront ballots aggregate equal digits before LDS atomics), a device-wide
+// scan, and a stable per-block scatter that ranks equal digits with 64-lane ballots.  No pass
+// depends on inter-workgroup forward progress.
+#include "kernels.hpp"
+
+namespace splat {
+
+// ------------------------------------------------------------------------------------------
+// small helpers
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+template <typename T>
+hipError_t fill(T* p, int64_t n, T v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = div_up(n, 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) { return fill<float>(p, n, v, s); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__device__ __forceinline__ int64_t shfl_up_i64(int64_t v, int d) {
+  int lo = __shfl_up((int)(uint32_t)(uint64_t)v, d, 64);
+  int hi = __shfl_up((int)(uint32_t)((uint64_t)v >> 32), d, 64);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+__device__ __forceinline__ uint32_t shfl_up_t(uint32_t v, int d) { return (uint32_t)__shfl_up((int)v, d, 64); }
+__device__ __forceinline__ int64_t shfl_up_t(int64_t v, int d) { return shfl_up_i64(v, d); }
+
+// exclusive scan across a 256-thread block; `tmp` holds 4 entries
+template <typename T>
+__device__ T block_exclusive_scan(T v, T* tmp, T& total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    T y = shfl_up_t(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) tmp[wid] = x;
+  __syncthreads();
+  T pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    T s = tmp[w];
+    pre += (w < wid) ? s : (T)0;
+    tot += s;
+  }
+  total = tot;
+  __syncthreads();
+  return pre + x - v;
+}
+
+// ------------------------------------------------------------------------------------------
+// device-wide exclusive scan (reduce, scan of partials, downsweep); Load(i) gives element i
+// ------------------------------------------------------------------------------------------
+struct LoadU32 {
+  const uint32_t* p;
+  __device__ uint32_t operator()(int64_t i) const { return p[i]; }
+};
+struct LoadTilesByOrder {   // n_tiles of the i-th record in depth order
+  const int32_t* n_tiles;
+  const uint32_t* order;
+  __device__ int64_t operator()(int64_t i) const { return (int64_t)n_tiles[order[i]]; }
+};
+struct LoadI64 {
+  const int64_t* p;
+  __device__ int64_t operator()(int64_t i) const { return p[i]; }
+};
+
+template <typename T, typename Load>
+__global__ __launch_bounds__(256) void k_scan_reduce(Load ld, int64_t n, T* __restrict__ part) {
+  __shared__ T tmp[4];
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  T acc = 0;
+#pragma unroll 4
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
+    if (i < n) acc += ld(i);
+  }
+  T total;
+  block_exclusive_scan<T>(acc, tmp, total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of part[0..nb) in place, part[nb] = total
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan_partials(T* __restrict__ part, int64_t nb) {
+  __shared__ T tmp[4];
+  T carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+    int64_t i = b0 + threadIdx.x;
+    T v = i < nb ? part[i] : (T)0;
+    T total;
+    T ex = block_exclusive_scan<T>(v, tmp, total);
+    if (i < nb) part[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) part[nb] = carry;
+}
+
+template <typename T, typename Load>
+__global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, const T* __restrict__ part, T* __restrict__ out) {
+  __shared__ T tile[kScanTile];
+  __shared__ T tmp[4];
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll 4
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
+    tile[r * kScanThreads + threadIdx.x] = i < n ? ld(i) : (T)0;
+  }
+  __syncthreads();
+  T loc[kScanItems];
+  T acc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    loc[k] = acc;
+    acc += tile[threadIdx.x * kScanItems + k];
+  }
+  T total;
+  T pre = block_exclusive_scan<T>(acc, tmp, total) + part[blockIdx.x];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) tile[threadIdx.x * kScanItems + k] = pre + loc[k];
+  __syncthreads();
+#pragma unroll 4
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
+    if (i < n) out[i] = tile[r * kScanThreads + threadIdx.x];
+  }
+}
+
+// exclusive scan of n elements into out[0..n); part[nb] receives the total
+template <typename T, typename Load>
+hipError_t device_scan(Load ld, int64_t n, T* out, T* part, hipStream_t s) {
+  int64_t nb = div_up(n, kScanTile);
+  if (nb == 0) {
+    hipLaunchKernelGGL((k_fill<T>), dim3(1), dim3(64), 0, s, part, (int64_t)1, (T)0);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_scan_reduce<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, part);
+  hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(256), 0, s, part, nb);
+  hipLaunchKernelGGL((k_scan_down<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, (const T*)part, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// radix sort: stable, 8-bit digits, keys and values uint32
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int bits) {
+  uint64_t m = __ballot(valid);
+  for (int b = 0; b < bits; ++b) {
+    bool bit = (d >> b) & 1u;
+    uint64_t bb = __ballot(valid && bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+__device__ __forceinline__ int64_t sort_count(const int64_t* n_ptr, int64_t n_cap) {
+  if (!n_ptr) return n_cap;
+  int64_t n = *n_ptr;
+  return n < n_cap ? n : n_cap;
+}
+
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap,
+                                                    int shift, int bits, uint32_t* __restrict__ hist, int64_t nb) {
+  __shared__ uint32_t cnt[kRadixBins];
+  const int tid = threadIdx.x;
+  cnt[tid] = 0;
+  __syncthreads();
+  const int64_t n = sort_count(n_ptr, n_cap);
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  const uint32_t mask = (1u << bits) - 1u;
+  const uint64_t lt = lanemask_lt();
+  if (base < n) {
+    for (int r = 0; r < kScanItems; ++r) {
+      int64_t i = base + (int64_t)r * kScanThreads + tid;
+      if (base + (int64_t)r * kScanThreads >= n) break;
+      bool valid = i < n;
+      uint32_t d = valid ? ((keys[i] >> shift) & mask) : 0u;
+      uint64_t m = match_digit(d, valid, bits);
+      if (valid && (m & lt) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(m));
+    }
+  }
+  __syncthreads();
+  hist[(int64_t)tid * nb + blockIdx.x] = cnt[tid];
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                       uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                       const int64_t* n_ptr, int64_t n_cap, int shift, int bits,
+                                                       const uint32_t* __restrict__ hist, int64_t nb) {
+  __shared__ uint32_t run[kRadixBins];
+  __shared__ uint32_t wc[4][kRadixBins];
+  const int tid = threadIdx.x, wid = tid >> 6;
+  const int64_t n = sort_count(n_ptr, n_cap);
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= n) return;   // uniform over the block
+  run[tid] = hist[(int64_t)tid * nb + blockIdx.x];
+  wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
+  __syncthreads();
+  const uint32_t mask = (1u << bits) - 1u;
+  const uint64_t lt = lanemask_lt();
+  for (int r = 0; r < kScanItems; ++r) {
+    if (base + (int64_t)r * kScanThreads >= n) break;   // uniform
+    int64_t i = base + (int64_t)r * kScanThreads + tid;
+    bool valid = i < n;
+    uint32_t key = valid ? kin[i] : 0u;
+    uint32_t val = valid ? vin[i] : 0u;
+    uint32_t d = (key >> shift) & mask;
+    uint64_t m = match_digit(d, valid, bits);
+    uint32_t rank = (uint32_t)__popcll(m & lt);
+    if (valid && rank == 0) wc[wid][d] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int w = 0; w < wid; ++w) pos += wc[w][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+    wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
+    __syncthreads();
+  }
+}
+
+// Sorts (k[cur], v[cur]) by the low `total_bits` bits of the key.  On return `cur` indexes the
+// sorted keys; the sorted values are in v[cur], or in `final_vals` when it is non-null.
+static hipError_t radix_sort(uint32_t* k[2], uint32_t* v[2], int& cur, const int64_t* n_ptr, int64_t n_cap,
+                             int total_bits, uint32_t* hist, uint32_t* hist_part, uint32_t* final_vals,
+                             hipStream_t s) {
+  if (total_bits < 1) total_bits = 1;
+  const int passes = (total_bits + kRadixBits - 1) / kRadixBits;
+  const int64_t nb = div_up(n_cap, kScanTile);
+  if (nb == 0) return hipSuccess;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * kRadixBits;
+    const int bits = (total_bits - shift) < kRadixBits ? (total_bits - shift) : kRadixBits;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(256), 0, s, (const uint32_t*)k[cur], n_ptr, n_cap, shift,
+                       bits, hist, nb);
+    hipError_t e = device_scan<uint32_t>(LoadU32{hist}, (int64_t)kRadixBins * nb, hist, hist_part, s);
+    if (e != hipSuccess) return e;
+    uint32_t* vdst = (p == passes - 1 && final_vals) ? final_vals : v[1 - cur];
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(256), 0, s, (const uint32_t*)k[cur],
+                       (const uint32_t*)v[cur], k[1 - cur], vdst, n_ptr, n_cap, shift, bits, (const uint32_t*)hist, nb);
+    cur = 1 - cur;
+  }
+  return hipGetLastError();
+}
+
+static int bits_for(int64_t n_values) {   // bits needed for values 0..n_values-1
+  int b = 0;
+  while (b < 31 && ((int64_t)1 << b) < n_values) ++b;
+  return b < 1 ? 1 : b;
+}
+
+// ------------------------------------------------------------------------------------------
+// binning kernels
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ int64_t local_tile_base(const DevSensor* sens, int s) {
+  return sens[s].tile_base - sens[0].tile_base;
+}
+
+// depth keys: float32 bits of a positive depth sort like the numbers; culled -> 0xFFFFFFFF
+__global__ void k_depth_keys(const int32_t* __restrict__ n_tiles, const float2* __restrict__ dv, int64_t n_rec,
+                             uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rec) return;
+  bool vis = n_tiles[i] > 0;
+  keys[i] = vis ? __float_as_uint(dv[i].x) : 0xFFFFFFFFu;   // dv of culled records is not written
+  vals[i] = (uint32_t)i;
+}
+
+__global__ void k_finalize_count(const int64_t* __restrict__ total, int64_t k_cap, int64_t* __restrict__ n_sort,
+                                 SplatStatus* st) {
+  int64_t K = *total;
+  *n_sort = K < k_cap ? K : k_cap;
+  if (st) {
+    st->n_isect = (unsigned long long)K;
+    st->k_cap = (unsigned long long)k_cap;
+    if (K > k_cap) st->overflow = 1u;
+  }
+}
+
+__device__ __forceinline__ uint32_t tile_of(const DevSensor& S, int64_t base, const int4 r, int j) {
+  if (S.kind == kCamera) {
+    int tx = r.x + j % r.z, ty = r.y + j / r.z;
+    return (uint32_t)(base + (int64_t)ty * S.tiles_x + tx);
+  }
+  int a = (r.x + j % r.z) % S.m_az, e = r.y + j / r.z;
+  return (uint32_t)(base + (int64_t)e * S.m_az + a);
+}
+
+constexpr int kBigRecord = 32;   // records touching more tiles are emitted by a whole wavefront
+
+__global__ void k_emit(const DevSensor* __restrict__ sens, int64_t N, const int32_t* __restrict__ n_tiles,
+                       const int4* __restrict__ rect, const uint32_t* __restrict__ order, const int64_t* __restrict__ offs,
+                       int64_t n_rec, int64_t k_cap, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                       int32_t* __restrict__ big, int32_t* __restrict__ n_big) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rec) return;
+  uint32_t rec = order[i];
+  int n = n_tiles[rec];
+  if (n <= 0) return;
+  if (n > kBigRecord) {
+    int slot = atomicAdd(n_big, 1);
+    big[slot] = (int32_t)i;
+    return;
+  }
+  int64_t off = offs[i];
+  int s = (int)(rec / (uint64_t)N);
+  uint32_t g = (uint32_t)(rec - (uint64_t)s * N);
+  const DevSensor& S = sens[s];
+  int64_t base = local_tile_base(sens, s);
+  int4 r = rect[rec];
+  for (int j = 0; j < n; ++j) {
+    int64_t k = off + j;
+    if (k >= k_cap) break;
+    keys[k] = tile_of(S, base, r, j);
+    vals[k] = g;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_emit_big(const DevSensor* __restrict__ sens, int64_t N,
+                                                  const int32_t* __restrict__ n_tiles, const int4* __restrict__ rect,
+                                                  const uint32_t* __restrict__ order, const int64_t* __restrict__ offs,
+                                                  int64_t k_cap, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                  const int32_t* __restrict__ big, const int32_t* __restrict__ n_big) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t nb = *n_big;
+  for (int64_t b = wave; b < nb; b += n_waves) {
+    int64_t i = big[b];
+    uint32_t rec = order[i];
+    int n = n_tiles[rec];
+    int64_t off = offs[i];
+    int s = (int)(rec / (uint64_t)N);
+    uint32_t g = (uint32_t)(rec - (uint64_t)s * N);
+    const DevSensor& S = sens[s];
+    int64_t base = local_tile_base(sens, s);
+    int4 r = rect[rec];
+    for (int j = lane; j < n; j += 64) {
+      int64_t k = off + j;
+      if (k < k_cap) {
+        keys[k] = tile_of(S, base, r, j);
+        vals[k] = g;
+      }
+    }
+  }
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap, int2* __restrict__ range) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t n = sort_count(n_ptr, n_cap);
+  if (i >= n) return;
+  uint32_t t = keys[i];
+  if (i == 0 || keys[i - 1] != t) range[t].x = (int)i;
+  if (i == n - 1 || keys[i + 1] != t) range[t].y = (int)(i + 1);
+}
+
+// ---- lidar rays ------------------------------------------------------------------------------
+__device__ __forceinline__ int sensor_of_ray(const DevSensor* sens, int count, int64_t r) {
+  int lo = 0, hi = count - 1;
+  const int64_t b0 = sens[0].ray_base;
+  while (lo < hi) {   // last sensor whose local ray base <= r
+    int mid = (lo + hi + 1) >> 1;
+    if (sens[mid].ray_base - b0 <= r) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_ray_keys(const DevSensor* __restrict__ sens, int count, int64_t n_rays, int64_t n_tiles,
+                           uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, SplatStatus* st) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rays) return;
+  int s = sensor_of_ray(sens, count, r);
+  const DevSensor& S = sens[s];
+  int64_t j = r - (S.ray_base - sens[0].ray_base);
+  float az = S.ray_az[j], el = S.ray_el[j], t = S.ray_t[j];
+  bool ok = (az >= 0.f) && (az < kTwoPi) && (el >= S.bounds[0]) && (el < S.bounds[S.m_el]) && finite_f(t);
+  uint32_t tile = (uint32_t)n_tiles;
+  if (ok) {
+    int a = floor_div_clamped(az, S.az_w) % S.m_az;
+    int e = count_le(S, el) - 1;
+    tile = (uint32_t)(local_tile_base(sens, s) + (int64_t)e * S.m_az + a);
+  } else if (st) {
+    atomicAdd(&st->n_rays_invalid, 1u);
+  }
+  if (ok && st && fabsf(t) > 0.5f * S.t_rs * (1.0f + 1e-6f) + 1e-9f) atomicAdd(&st->n_rays_time, 1u);
+  keys[r] = tile;
+  vals[r] = (uint32_t)r;
+}
+
+__global__ void k_work_count(const int2* __restrict__ range, int64_t n_bins, int64_t* __restrict__ cnt) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_bins) return;
+  int2 r = range[t];
+  int64_t c = r.y - r.x;
+  cnt[t] = c > 0 ? (c + SPLAT_RAYS_PER_ITEM - 1) / SPLAT_RAYS_PER_ITEM : 0;
+}
+
+__global__ void k_copy_i64(const int64_t* __restrict__ src, int64_t* __restrict__ dst) { *dst = *src; }
+
+__global__ void k_work_emit(const int2* __restrict__ range, int64_t n_bins, const int64_t* __restrict__ woff,
+                            int64_t work_cap, int2* __restrict__ work, int32_t* __restrict__ n_work) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    int64_t tot = woff[n_bins];
+    *n_work = (int32_t)(tot < work_cap ? tot : work_cap);
+  }
+  if (t >= n_bins) return;
+  int2 r = range[t];
+  int64_t o = woff[t];
+  for (int p = r.x; p < r.y; p += SPLAT_RAYS_PER_ITEM, ++o)
+    if (o < work_cap) work[o] = make_int2((int)t, p);
+}
+
+// ------------------------------------------------------------------------------------------
+// host driver
+// ------------------------------------------------------------------------------------------
+static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_tiles, int64_t n_rays) {
+  Workspace w;
+  char* p = (char*)base;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* r = base ? (void*)(p + off) : nullptr;
+    off += align256(bytes);
+    return r;
+  };
+  int64_t nrec = n_rec < 1 ? 1 : n_rec;
+  int64_t kc = k_cap < 1 ? 1 : k_cap;
+  int64_t nr = n_rays < 1 ? 1 : n_rays;
+  int64_t max_n = nrec > kc ? nrec : kc;
+  max_n = max_n > nr ? max_n : nr;
+  int64_t max_blocks = div_up(max_n, kScanTile);
+  for (int i = 0; i < 2; ++i) w.dkeys[i] = (uint32_t*)take(nrec * 4);
+  for (int i = 0; i < 2; ++i) w.dvals[i] = (uint32_t*)take(nrec * 4);
+  w.offs = (int64_t*)take((nrec + 1) * 8);
+  w.scan_part = (int64_t*)take((div_up(nrec > n_tiles + 2 ? nrec : n_tiles + 2, kScanTile) + 2) * 8);
+  for (int i = 0; i < 2; ++i) w.tkeys[i] = (uint32_t*)take(kc * 4);
+  w.tvals = (uint32_t*)take(kc * 4);
+  w.hist = (uint32_t*)take((size_t)kRadixBins * max_blocks * 4 + 64);
+  w.hist_part = (uint32_t*)take((div_up((int64_t)kRadixBins * max_blocks, kScanTile) + 2) * 4);
+  for (int i = 0; i < 2; ++i) w.rkeys[i] = (uint32_t*)take(nr * 4);
+  for (int i = 0; i < 2; ++i) w.rvals[i] = (uint32_t*)take(nr * 4);
+  w.wcount = (int64_t*)take((n_tiles + 2) * 8);
+  w.wpart = (int64_t*)take((div_up(n_tiles + 2, kScanTile) + 2) * 8);
+  w.big = (int32_t*)take(nrec * 4);
+  w.n_big = (int32_t*)take(8 * 4);
+  w.g2d = (float*)take(nrec * 10 * 4);
+  w.bytes = off;
+  return w;
+}
+
+hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const SplatTileLists& L, const Workspace& w,
+                           SplatStatus* st, hipStream_t s) {
+  const int64_t n_rec = (int64_t)v.count * v.n_gauss;
+  hipError_t e;
+  int64_t* n_sort = (int64_t*)(w.n_big + 4);   // spare slots next to the big-record counter
+  // 1. depth order of the records
+  if (n_rec > 0) {
+    hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, (const int32_t*)p.n_tiles,
+                       (const float2*)p.dv, n_rec, w.dkeys[0], w.dvals[0]);
+  }
+  uint32_t* dk[2] = {w.dkeys[0], w.dkeys[1]};
+  uint32_t* dvv[2] = {w.dvals[0], w.dvals[1]};
+  int cur = 0;
+  if ((e = radix_sort(dk, dvv, cur, nullptr, n_rec, 32, w.hist, w.hist_part, nullptr, s)) != hipSuccess) return e;
+  const uint32_t* order = dvv[cur];
+  // 2. slot ranges
+  if ((e = device_scan<int64_t>(LoadTilesByOrder{p.n_tiles, order}, n_rec, w.offs, w.scan_part, s)) != hipSuccess) return e;
+  int64_t nb = div_up(n_rec, kScanTile);
+  hipLaunchKernelGGL(k_finalize_count, dim3(1), dim3(1), 0, s, (const int64_t*)(w.scan_part + nb), L.k_cap, n_sort, st);
+  // 3. emit: the final tile-sort pass must land its values in lists->gauss
+  const int tbits = bits_for(v.n_tiles);
+  const int passes = (tbits + kRadixBits - 1) / kRadixBits;
+  uint32_t* tv[2];
+  if (passes % 2 == 0) { tv[0] = (uint32_t*)L.gauss; tv[1] = w.tvals; }
+  else { tv[0] = w.tvals; tv[1] = (uint32_t*)L.gauss; }
+  if ((e = fill<int32_t>(w.n_big, 1, 0, s)) != hipSuccess) return e;
+  if (n_rec > 0) {
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, v.sens, v.n_gauss,
+                       (const int32_t*)p.n_tiles, (const int4*)p.rect, order, (const int64_t*)w.offs, n_rec, L.k_cap,
+                       w.tkeys[0], tv[0], w.big, w.n_big);
+    hipLaunchKernelGGL(k_emit_big, dim3(1024), dim3(256), 0, s, v.sens, v.n_gauss, (const int32_t*)p.n_tiles,
+                       (const int4*)p.rect, order, (const int64_t*)w.offs, L.k_cap, w.tkeys[0], tv[0],
+                       (const int32_t*)w.big, (const int32_t*)w.n_big);
+  }
+  // 4. stable sort by tile
+  uint32_t* tk[2] = {w.tkeys[0], w.tkeys[1]};
+  int tcur = 0;
+  if ((e = radix_sort(tk, tv, tcur, n_sort, L.k_cap, tbits, w.hist, w.hist_part, nullptr, s)) != hipSuccess) return e;
+  // 5. ranges
+  if ((e = fill<int32_t>(L.tile_range, 2 * v.n_tiles, 0, s)) != hipSuccess) return e;
+  if (L.k_cap > 0)
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(L.k_cap, 256)), dim3(256), 0, s, (const uint32_t*)tk[tcur],
+                       (const int64_t*)n_sort, L.k_cap, (int2*)L.tile_range);
+  // 6. lidar rays and work items
+  if (v.lidar) {
+    const int64_t nr = v.n_rays;
+    const int64_t bins = v.n_tiles + 1;
+    if ((e = fill<int32_t>(L.ray_range, 2 * bins, 0, s)) != hipSuccess) return e;
+    if (nr > 0) {
+      hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)div_up(nr, 256)), dim3(256), 0, s, v.sens, v.count, nr, v.n_tiles,
+                         w.rkeys[0], w.rvals[0], st);
+      uint32_t* rk[2] = {w.rkeys[0], w.rkeys[1]};
+      uint32_t* rv[2] = {w.rvals[0], w.rvals[1]};
+      int rcur = 0;
+      if ((e = radix_sort(rk, rv, rcur, nullptr, nr, bits_for(bins), w.hist, w.hist_part, (uint32_t*)L.ray_order, s)) !=
+          hipSuccess)
+        return e;
+      hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(nr, 256)), dim3(256), 0, s, (const uint32_t*)rk[rcur],
+                         (const int64_t*)nullptr, nr, (int2*)L.ray_range);
+    }
+    hipLaunchKernelGGL(k_work_count, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, (const int2*)L.ray_range, bins,
+                       w.wcount);
+    if ((e = device_scan<int64_t>(LoadI64{w.wcount}, bins, w.wcount, w.wpart, s)) != hipSuccess) return e;
+    // the total lands in wpart[nb]; copy it behind the per-bin offsets for k_work_emit
+    int64_t wnb = div_up(bins, kScanTile);
+    hipLaunchKernelGGL(k_copy_i64, dim3(1), dim3(1), 0, s, (const int64_t*)(w.wpart + wnb), w.wcount + bins);
+    hipLaunchKernelGGL(k_work_emit, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, (const int2*)L.ray_range, bins,
+                       (const int64_t*)w.wcount, L.work_cap, (int2*)L.work, L.n_work);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace splat

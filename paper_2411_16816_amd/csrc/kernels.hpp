@@ -1,0 +1,70 @@
+// kernels.hpp -- launchers of the libsplat kernels (host side), called by the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "splat_common.hpp"
+
+namespace splat {
+
+// tile sizes of the sort / scan kernels
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;     // 4096 elements per block
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+
+inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Views of the device buffers of one call (local numbering), shared by the launchers.
+struct CallView {
+  const DevSensor* sens;   // device table entries [first, first + count)
+  const DevSensor* host;   // host copies of the same entries
+  int32_t count;
+  int64_t n_gauss;
+  int64_t n_tiles;         // tiles of the call
+  int64_t n_rays;          // rays of the call
+  bool lidar;              // all sensors are lidars (false: all cameras)
+  int c_max;               // max n_channels over the call
+};
+
+// ---- workspace carving (sizes in bytes, 256-aligned) ----------------------------------------
+struct Workspace {
+  // bin/sort
+  uint32_t* dkeys[2];
+  uint32_t* dvals[2];
+  int64_t* offs;          // [n_rec + 1] exclusive scan of n_tiles in depth order
+  int64_t* scan_part;     // block partials of the int64 scan
+  uint32_t* tkeys[2];     // [k_cap]
+  uint32_t* tvals;        // [k_cap] (ping-pong partner of lists->gauss)
+  uint32_t* hist;         // [256 * max_blocks + partials]
+  uint32_t* hist_part;
+  uint32_t* rkeys[2];     // [n_rays]
+  uint32_t* rvals[2];
+  int64_t* wcount;        // [n_tiles + 2]
+  int64_t* wpart;
+  int32_t* big;           // [n_rec] records with many tiles, emitted one wavefront each
+  int32_t* n_big;
+  // adjoint
+  float* g2d;             // [n_rec, 10]
+  size_t bytes;
+};
+
+Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_tiles, int64_t n_rays);
+
+// ---- launchers ------------------------------------------------------------------------------
+hipError_t launch_project(const CallView& v, const SplatGaussians& g, const SplatProjected& p, SplatStatus* st,
+                          hipStream_t s);
+hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p, const float* g2d,
+                              const SplatGrads& gr, hipStream_t s);
+hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const SplatTileLists& L, const Workspace& w,
+                           SplatStatus* st, hipStream_t s);
+hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
+                             const SplatTileLists& L, int support, const SplatRenderOut& o, hipStream_t s);
+hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
+                             const SplatTileLists& L, int support, const SplatRenderOut& saved, const float* dF,
+                             const float* dD, const float* dA, float* g2d, float* dfeat, hipStream_t s);
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+
+}  // namespace splat

@@ -1,0 +1,117 @@
+// project.hip -- projection of Gaussians into cameras and lidars, and its adjoint
+// (SplatAD, arXiv 2411.16816: Sec. 3.1; Sec. 3.2 "Projection, tiling, and sorting" and
+// "Rolling shutter"; Sec. 3.3 "Projection"; App. D).
+//
+// One thread per Gaussian.  Its parameters are read once (coalesced: consecutive threads read
+// consecutive rows) and projected into every sensor of the call, so a batched call over S
+// sensors reads the Gaussian arrays once instead of S times.  Records are written SoA
+// (record = sensor * N + gaussian); culled records only write n_tiles = 0.
+#include "kernels.hpp"
+
+namespace splat {
+
+struct GaussLoad {
+  float mu[3], ls[3], q[4], vg[3], op;
+};
+
+__device__ __forceinline__ void load_gaussian(const SplatGaussians& g, int64_t i, GaussLoad& o) {
+  o.mu[0] = g.means[3 * i + 0]; o.mu[1] = g.means[3 * i + 1]; o.mu[2] = g.means[3 * i + 2];
+  o.ls[0] = g.log_scales[3 * i + 0]; o.ls[1] = g.log_scales[3 * i + 1]; o.ls[2] = g.log_scales[3 * i + 2];
+  float4 q = reinterpret_cast<const float4*>(g.quats)[i];
+  o.q[0] = q.x; o.q[1] = q.y; o.q[2] = q.z; o.q[3] = q.w;
+  o.op = g.opacities[i];
+  if (g.velocities) {
+    o.vg[0] = g.velocities[3 * i + 0]; o.vg[1] = g.velocities[3 * i + 1]; o.vg[2] = g.velocities[3 * i + 2];
+  } else {
+    o.vg[0] = o.vg[1] = o.vg[2] = 0.f;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_project(const DevSensor* __restrict__ sens, int count, SplatGaussians g,
+                                                 float4* __restrict__ mv, float4* __restrict__ cn,
+                                                 float4* __restrict__ box, float2* __restrict__ dv,
+                                                 int4* __restrict__ rect, int32_t* __restrict__ n_tiles,
+                                                 SplatStatus* st) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  GaussLoad G;
+  load_gaussian(g, i, G);
+  QuatRot qr;
+  float s[3], M[9];
+  gaussian_M(G.q, G.ls, qr, s, M);
+  unsigned nonfin = 0;
+  for (int k = 0; k < count; ++k) {
+    ProjInter I;
+    ProjOut o;
+    project_one(sens[k], G.mu, M, G.vg, G.op, I, o);
+    const int64_t r = (int64_t)k * g.n + i;
+    n_tiles[r] = o.n_tiles;
+    nonfin += o.nonfinite ? 1u : 0u;
+    if (o.n_tiles > 0) {
+      mv[r] = make_float4(o.mean[0], o.mean[1], o.vel[0], o.vel[1]);
+      cn[r] = make_float4(o.conic[0], o.conic[1], o.conic[2], o.o_eff);
+      box[r] = make_float4(o.box[0], o.box[1], o.box[2], o.box[3]);
+      dv[r] = make_float2(o.depth, o.v_r);
+      rect[r] = make_int4(o.rect[0], o.rect[1], o.rect[2], o.rect[3]);
+    }
+  }
+  if (nonfin && st) atomicAdd(&st->n_nonfinite, nonfin);
+}
+
+// g2d: per record (mean.x, mean.y, vel.x, vel.y, conic a, b, c, o_eff, depth (z | r), v_r)
+__global__ __launch_bounds__(256) void k_project_bwd(const DevSensor* __restrict__ sens, int count, SplatGaussians g,
+                                                     const int32_t* __restrict__ n_tiles, const float* __restrict__ g2d,
+                                                     SplatGrads gr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  GaussLoad G;
+  load_gaussian(g, i, G);
+  QuatRot qr;
+  float s[3], M[9];
+  gaussian_M(G.q, G.ls, qr, s, M);
+  float dmu[3] = {0.f, 0.f, 0.f}, dM[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, dvg[3] = {0.f, 0.f, 0.f};
+  float dop = 0.f;
+  bool any = false;
+  for (int k = 0; k < count; ++k) {
+    const int64_t r = (int64_t)k * g.n + i;
+    if (n_tiles[r] <= 0) continue;
+    const float* q = g2d + r * 10;
+    RecGrad rg;
+    rg.mean[0] = q[0]; rg.mean[1] = q[1]; rg.vel[0] = q[2]; rg.vel[1] = q[3];
+    rg.conic[0] = q[4]; rg.conic[1] = q[5]; rg.conic[2] = q[6]; rg.o_eff = q[7];
+    rg.depth = q[8]; rg.v_r = q[9];
+    ProjInter I;
+    ProjOut o;
+    project_one(sens[k], G.mu, M, G.vg, G.op, I, o);
+    project_one_vjp(sens[k], M, G.op, I, o, rg, dmu, dM, dvg, &dop);
+    any = true;
+  }
+  if (!any) return;
+  float dq[4], dls[3];
+  gaussian_M_vjp(qr, s, dM, dq, dls);
+  gr.means[3 * i + 0] += dmu[0]; gr.means[3 * i + 1] += dmu[1]; gr.means[3 * i + 2] += dmu[2];
+  gr.log_scales[3 * i + 0] += dls[0]; gr.log_scales[3 * i + 1] += dls[1]; gr.log_scales[3 * i + 2] += dls[2];
+  gr.quats[4 * i + 0] += dq[0]; gr.quats[4 * i + 1] += dq[1]; gr.quats[4 * i + 2] += dq[2]; gr.quats[4 * i + 3] += dq[3];
+  gr.opacities[i] += dop;
+  if (gr.velocities) {
+    gr.velocities[3 * i + 0] += dvg[0]; gr.velocities[3 * i + 1] += dvg[1]; gr.velocities[3 * i + 2] += dvg[2];
+  }
+}
+
+hipError_t launch_project(const CallView& v, const SplatGaussians& g, const SplatProjected& p, SplatStatus* st,
+                          hipStream_t s) {
+  if (g.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_project, dim3((unsigned)div_up(g.n, 256)), dim3(256), 0, s, v.sens, v.count, g, (float4*)p.mv,
+                     (float4*)p.cn, (float4*)p.box, (float2*)p.dv, (int4*)p.rect, p.n_tiles, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p, const float* g2d,
+                              const SplatGrads& gr, hipStream_t s) {
+  if (g.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)div_up(g.n, 256)), dim3(256), 0, s, v.sens, v.count, g,
+                     (const int32_t*)p.n_tiles, g2d, gr);
+  return hipGetLastError();
+}
+
+}  // namespace splat

@@ -1,0 +1,490 @@
+// raster.hip -- tile rasterisation of cameras and lidars, forward and adjoint
+// (SplatAD, arXiv 2411.16816: Sec. 3.2 "Rasterization", Eqs. t_pix, alpha_blend, alpha, delta;
+// Sec. 3.3 "Rasterization" with the rolling-shutter range r + v_r t and the median range;
+// App. A for rays supplied per tile and idle lanes helping to stage Gaussians).
+//
+// One 256-lane workgroup (4 x wave64) per work item: a camera tile (one lane per pixel) or a
+// lidar tile chunk of <= 256 supplied rays.  The tile's depth-ordered list is walked in batches
+// of 256 Gaussians; every lane (idle ones too) stages one Gaussian's record and features into
+// LDS, then every lane composites the batch front to back.  A wavefront stops iterating once
+// all its lanes are saturated (ballot), the workgroup once all lanes are (barrier count).
+//
+// The adjoint walks the same list back to front from each ray's `last`, recovering
+// T_i = T_{i+1} / (1 - alpha_i) from the saved final transmittance.  Per-Gaussian gradients
+// are summed across the wavefront with DPP row operations, across the workgroup in LDS, and
+// reach global memory with one atomic per (Gaussian, tile, value).
+#include "kernels.hpp"
+
+namespace splat {
+
+constexpr int kNV = 10;   // geometric gradient values per record (see k_project_bwd)
+
+struct RasterArgs {
+  const DevSensor* sens;
+  int count;
+  int64_t N;
+  int64_t n_tiles;           // tiles of the call (lidar: also the invalid-ray bin id)
+  const float4* mv;
+  const float4* cn;
+  const float4* box;
+  const float2* dv;
+  const int32_t* gauss;
+  const int2* tile_range;
+  const float* features;
+  int c_total;
+  const int32_t* ray_order;
+  const int2* ray_range;
+  const int2* work;
+  const int32_t* n_work;
+};
+
+struct FwdOut {
+  float* feat;
+  float* depth;
+  float* alpha;
+  float* t_final;
+  int32_t* last;
+  float* median;
+};
+
+struct BwdIn {
+  const float* t_final;
+  const int32_t* last;
+  const float* dF;
+  const float* dD;
+  const float* dA;
+  float* g2d;
+  float* dfeat;
+};
+
+__device__ __forceinline__ int sensor_of_tile(const DevSensor* sens, int count, int64_t t) {
+  int lo = 0, hi = count - 1;
+  const int64_t b0 = sens[0].tile_base;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sens[mid].tile_base - b0 <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int sensor_of_ray_r(const DevSensor* sens, int count, int64_t r) {
+  int lo = 0, hi = count - 1;
+  const int64_t b0 = sens[0].ray_base;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sens[mid].ray_base - b0 <= r) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// What one lane of a work item renders.
+struct RayCtx {
+  bool valid;
+  float px, py, t;
+  int64_t ray;        // local ray id of the call
+  int64_t feat_off;   // first float of this ray's feature row in the output
+  int s;              // sensor (call-local index)
+  int C;              // channels
+  int64_t start, end; // the tile's list range
+  bool invalid_bin;   // lidar work item of rays outside every tile
+};
+
+template <bool LIDAR>
+__device__ __forceinline__ bool setup_item(const RasterArgs& a, RayCtx& c) {
+  const int tid = threadIdx.x;
+  int64_t tile;
+  if (!LIDAR) {
+    tile = blockIdx.x;
+    c.s = sensor_of_tile(a.sens, a.count, tile);
+    const DevSensor& S = a.sens[c.s];
+    int64_t tl = tile - (S.tile_base - a.sens[0].tile_base);
+    int tx = (int)(tl % S.tiles_x), ty = (int)(tl / S.tiles_x);
+    int lx = tid % S.tile_w, ly = tid / S.tile_w;
+    int x = tx * S.tile_w + lx, y = ty * S.tile_h + ly;
+    c.valid = (tid < S.tile_w * S.tile_h) && x < S.width && y < S.height;
+    c.px = (float)x + 0.5f;
+    c.py = (float)y + 0.5f;
+    c.t = (c.py / (float)S.height - 0.5f) * S.t_rs;   // Eq. t_pix at the pixel centre
+    int64_t pix = (int64_t)y * S.width + x;
+    c.ray = (S.ray_base - a.sens[0].ray_base) + pix;
+    c.feat_off = (S.feat_base - a.sens[0].feat_base) + pix * S.n_ch;
+    c.C = S.n_ch;
+    c.invalid_bin = false;
+  } else {
+    if ((int64_t)blockIdx.x >= (int64_t)*a.n_work) return false;
+    int2 w = a.work[blockIdx.x];
+    tile = w.x;
+    int2 rr = a.ray_range[tile];
+    int64_t p = (int64_t)w.y + tid;
+    c.valid = p < rr.y;
+    c.invalid_bin = (tile == a.n_tiles);
+    int64_t r = c.valid ? (int64_t)a.ray_order[p] : 0;
+    c.ray = r;
+    c.s = c.invalid_bin ? sensor_of_ray_r(a.sens, a.count, r) : sensor_of_tile(a.sens, a.count, tile);
+    const DevSensor& S = a.sens[c.s];
+    int64_t j = r - (S.ray_base - a.sens[0].ray_base);
+    c.feat_off = (S.feat_base - a.sens[0].feat_base) + j * S.n_ch;
+    c.C = S.n_ch;
+    if (c.valid) {
+      c.px = S.ray_az[j];
+      c.py = S.ray_el[j];
+      c.t = S.ray_t[j];
+    } else {
+      c.px = c.py = c.t = 0.f;
+    }
+  }
+  // the invalid-ray bin (tile == n_tiles) has no Gaussian list: read an in-bounds entry and drop it
+  const int2 tr = a.tile_range[(LIDAR && c.invalid_bin) ? 0 : tile];
+  c.start = (LIDAR && c.invalid_bin) ? 0 : tr.x;
+  c.end = (LIDAR && c.invalid_bin) ? 0 : tr.y;
+  return true;
+}
+
+template <int CMAX>
+__device__ __forceinline__ void stage_batch(const RasterArgs& a, const RayCtx& c, int64_t b0, int64_t b1,
+                                            float4* s_mv, float4* s_cn, float4* s_box, float2* s_dv, float4* s_f) {
+  const int tid = threadIdx.x;
+  const int64_t idx = b0 + tid;
+  if (idx < b1) {
+    const int64_t g = a.gauss[idx];
+    const int64_t rec = (int64_t)c.s * a.N + g;
+    s_mv[tid] = a.mv[rec];
+    s_cn[tid] = a.cn[rec];
+    s_box[tid] = a.box[rec];
+    s_dv[tid] = a.dv[rec];
+    const DevSensor& S = a.sens[c.s];
+    const float* f = a.features + g * a.c_total + S.feat_off;
+#pragma unroll
+    for (int c4 = 0; c4 < CMAX / 4; ++c4) {
+      float4 v;
+      v.x = (4 * c4 + 0 < c.C) ? f[4 * c4 + 0] : 0.f;
+      v.y = (4 * c4 + 1 < c.C) ? f[4 * c4 + 1] : 0.f;
+      v.z = (4 * c4 + 2 < c.C) ? f[4 * c4 + 2] : 0.f;
+      v.w = (4 * c4 + 3 < c.C) ? f[4 * c4 + 3] : 0.f;
+      s_f[tid * (CMAX / 4) + c4] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// forward
+// ------------------------------------------------------------------------------------------
+template <int CMAX, bool LIDAR, bool TILE>
+__global__ __launch_bounds__(kBlock) void k_raster_fwd(RasterArgs a, FwdOut o) {
+  __shared__ float4 s_mv[kBlock], s_cn[kBlock], s_box[kBlock];
+  __shared__ float2 s_dv[kBlock];
+  __shared__ float4 s_f[kBlock * (CMAX / 4)];
+  RayCtx c;
+  if (!setup_item<LIDAR>(a, c)) return;   // uniform over the workgroup
+  float T = 1.f, D = 0.f, med = 0.f;
+  float F[CMAX];
+#pragma unroll
+  for (int k = 0; k < CMAX; ++k) F[k] = 0.f;
+  int last = 0;
+  bool done = !c.valid;
+  bool med_set = false;
+  for (int64_t b0 = c.start; b0 < c.end; b0 += kBlock) {
+    if (__syncthreads_count(!done) == 0) break;
+    const int64_t b1 = (b0 + kBlock < c.end) ? b0 + kBlock : c.end;
+    stage_batch<CMAX>(a, c, b0, b1, s_mv, s_cn, s_box, s_dv, s_f);
+    __syncthreads();
+    const int nb = (int)(b1 - b0);
+    for (int j = 0; j < nb; ++j) {
+      if (__ballot(!done) == 0) break;
+      if (done) continue;
+      const float4 bx = s_box[j];
+      const float bxa[4] = {bx.x, bx.y, bx.z, bx.w};
+      if (!TILE && !box_contains(LIDAR, c.px, c.py, bxa)) continue;
+      const float4 m = s_mv[j], q = s_cn[j];
+      const float mva[4] = {m.x, m.y, m.z, m.w}, cna[4] = {q.x, q.y, q.z, q.w};
+      PairEval e;
+      eval_pair(LIDAR, c.px, c.py, c.t, mva, cna, e);
+      if (e.alpha < kAlphaMin) continue;
+      const float Tn = T * (1.f - e.alpha);
+      if (Tn < kTStop) {
+        done = true;
+        continue;
+      }
+      const float w = e.alpha * T;
+      const float2 d = s_dv[j];
+      const float gv = LIDAR ? SPLAT_FMA(d.y, c.t, d.x) : d.x;
+#pragma unroll
+      for (int c4 = 0; c4 < CMAX / 4; ++c4) {
+        const float4 f = s_f[j * (CMAX / 4) + c4];
+        F[4 * c4 + 0] = SPLAT_FMA(w, f.x, F[4 * c4 + 0]);
+        F[4 * c4 + 1] = SPLAT_FMA(w, f.y, F[4 * c4 + 1]);
+        F[4 * c4 + 2] = SPLAT_FMA(w, f.z, F[4 * c4 + 2]);
+        F[4 * c4 + 3] = SPLAT_FMA(w, f.w, F[4 * c4 + 3]);
+      }
+      D = SPLAT_FMA(w, gv, D);
+      if (LIDAR && !med_set && Tn < 0.5f) {
+        med = gv;
+        med_set = true;
+      }
+      T = Tn;
+      last = (int)(b0 + j - c.start) + 1;
+    }
+  }
+  if (!c.valid) return;
+  float* fo = o.feat + c.feat_off;
+#pragma unroll
+  for (int k = 0; k < CMAX; ++k)
+    if (k < c.C) fo[k] = F[k];
+  o.depth[c.ray] = D;
+  o.alpha[c.ray] = 1.f - T;
+  o.t_final[c.ray] = T;
+  o.last[c.ray] = last;
+  if (LIDAR && o.median) o.median[c.ray] = med;
+}
+
+// ------------------------------------------------------------------------------------------
+// adjoint
+// ------------------------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+}
+
+// sum over the 64 lanes; the total is valid in lane 63
+__device__ __forceinline__ float wave_sum_to_63(float v) {
+  v += dpp_f<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f<0x141, 0xf>(v);   // row_half_mirror
+  v += dpp_f<0x140, 0xf>(v);   // row_mirror
+  v += dpp_f<0x142, 0xa>(v);   // row_bcast:15 -> rows 1, 3
+  v += dpp_f<0x143, 0xc>(v);   // row_bcast:31 -> rows 2, 3
+  return v;
+}
+
+template <int CMAX, bool LIDAR, bool TILE>
+__global__ __launch_bounds__(kBlock) void k_raster_bwd(RasterArgs a, BwdIn b) {
+  __shared__ float4 s_mv[kBlock], s_cn[kBlock], s_box[kBlock];
+  __shared__ float2 s_dv[kBlock];
+  __shared__ float4 s_f[kBlock * (CMAX / 4)];
+  __shared__ float s_acc[kNV + CMAX][kBlock];
+  __shared__ int s_used[kBlock];
+  __shared__ int s_maxlast;
+  RayCtx c;
+  if (!setup_item<LIDAR>(a, c)) return;
+  if (LIDAR && c.invalid_bin) return;    // uniform over the workgroup
+  const int tid = threadIdx.x, lane = tid & 63;
+  float T = 1.f, Tf = 1.f, dD = 0.f, dA = 0.f, bufD = 0.f;
+  float dF[CMAX], buf[CMAX];
+  int last_l = 0;
+#pragma unroll
+  for (int k = 0; k < CMAX; ++k) {
+    dF[k] = 0.f;
+    buf[k] = 0.f;
+  }
+  if (c.valid) {
+    T = Tf = b.t_final[c.ray];
+    last_l = b.last[c.ray];
+    dD = b.dD[c.ray];
+    dA = b.dA[c.ray];
+    const float* g = b.dF + c.feat_off;
+#pragma unroll
+    for (int k = 0; k < CMAX; ++k)
+      if (k < c.C) dF[k] = g[k];
+  }
+  if (tid == 0) s_maxlast = 0;
+#pragma unroll
+  for (int k = 0; k < kNV + CMAX; ++k) s_acc[k][tid] = 0.f;
+  s_used[tid] = 0;
+  __syncthreads();
+  if (last_l > 0) atomicMax(&s_maxlast, last_l);
+  __syncthreads();
+  const int64_t n_proc = s_maxlast;
+  if (n_proc == 0) return;   // uniform
+  const DevSensor& S = a.sens[c.s];
+  for (int64_t b0 = c.start + ((n_proc - 1) / kBlock) * kBlock; b0 >= c.start; b0 -= kBlock) {
+    const int64_t b1 = (b0 + kBlock < c.start + n_proc) ? b0 + kBlock : c.start + n_proc;
+    stage_batch<CMAX>(a, c, b0, b1, s_mv, s_cn, s_box, s_dv, s_f);
+    __syncthreads();
+    const int nb = (int)(b1 - b0);
+    for (int j = nb - 1; j >= 0; --j) {
+      const int pos = (int)(b0 + j - c.start);
+      bool act = c.valid && pos < last_l;
+      const float4 bx = s_box[j];
+      const float bxa[4] = {bx.x, bx.y, bx.z, bx.w};
+      if (!TILE) act = act && box_contains(LIDAR, c.px, c.py, bxa);
+      const float4 m = s_mv[j], q = s_cn[j];
+      const float mva[4] = {m.x, m.y, m.z, m.w}, cna[4] = {q.x, q.y, q.z, q.w};
+      PairEval e;
+      e.alpha = 0.f;
+      if (act) {
+        eval_pair(LIDAR, c.px, c.py, c.t, mva, cna, e);
+        act = e.alpha >= kAlphaMin;
+      }
+      if (__ballot(act) == 0) continue;   // uniform over the wavefront
+      float v[kNV];
+      float fg[CMAX];
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) v[k] = 0.f;
+#pragma unroll
+      for (int k = 0; k < CMAX; ++k) fg[k] = 0.f;
+      if (act) {
+        const float ra = 1.f / (1.f - e.alpha);
+        T = T * ra;                       // transmittance in front of this Gaussian
+        const float w = e.alpha * T;
+        float acc = 0.f;
+#pragma unroll
+        for (int c4 = 0; c4 < CMAX / 4; ++c4) {
+          const float4 f = s_f[j * (CMAX / 4) + c4];
+          const float fa[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int k = 4 * c4 + u;
+            fg[k] = w * dF[k];
+            acc += (fa[u] - buf[k]) * dF[k];
+            buf[k] += e.alpha * (fa[u] - buf[k]);
+          }
+        }
+        const float2 d = s_dv[j];
+        const float gv = LIDAR ? SPLAT_FMA(d.y, c.t, d.x) : d.x;
+        acc += (gv - bufD) * dD;
+        bufD += e.alpha * (gv - bufD);
+        const float dalpha = T * acc + dA * Tf * ra;
+        const float dg = w * dD;
+        const float d_oeff = e.clamped ? 0.f : dalpha * e.G;
+        const float dsig = e.clamped ? 0.f : -dalpha * e.alpha;
+        const float ddx = (q.x * e.dx + q.y * e.dy) * dsig;
+        const float ddy = (q.y * e.dx + q.z * e.dy) * dsig;
+        v[0] = -ddx;
+        v[1] = -ddy;
+        v[2] = -ddx * c.t;
+        v[3] = -ddy * c.t;
+        v[4] = 0.5f * e.dx * e.dx * dsig;
+        v[5] = e.dx * e.dy * dsig;
+        v[6] = 0.5f * e.dy * e.dy * dsig;
+        v[7] = d_oeff;
+        v[8] = dg;
+        v[9] = LIDAR ? dg * c.t : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) {
+        const float r = wave_sum_to_63(v[k]);
+        if (lane == 63) atomicAdd(&s_acc[k][j], r);
+      }
+#pragma unroll
+      for (int k = 0; k < CMAX; ++k) {
+        if (k < c.C) {
+          const float r = wave_sum_to_63(fg[k]);
+          if (lane == 63) atomicAdd(&s_acc[kNV + k][j], r);
+        }
+      }
+      if (lane == 63) s_used[j] = 1;
+    }
+    __syncthreads();
+    if (tid < nb && s_used[tid]) {
+      const int64_t g = a.gauss[b0 + tid];
+      const int64_t rec = (int64_t)c.s * a.N + g;
+      float* gp = b.g2d + rec * kNV;
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) {
+        atomicAdd(gp + k, s_acc[k][tid]);
+        s_acc[k][tid] = 0.f;
+      }
+      float* fp = b.dfeat + g * a.c_total + S.feat_off;
+#pragma unroll
+      for (int k = 0; k < CMAX; ++k) {
+        if (k < c.C) atomicAdd(fp + k, s_acc[kNV + k][tid]);
+        s_acc[kNV + k][tid] = 0.f;
+      }
+      s_used[tid] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// launch
+// ------------------------------------------------------------------------------------------
+static RasterArgs make_args(const CallView& v, const SplatGaussians& g, const SplatProjected& p, const SplatTileLists& L) {
+  RasterArgs a;
+  a.sens = v.sens;
+  a.count = v.count;
+  a.N = v.n_gauss;
+  a.n_tiles = v.n_tiles;
+  a.mv = (const float4*)p.mv;
+  a.cn = (const float4*)p.cn;
+  a.box = (const float4*)p.box;
+  a.dv = (const float2*)p.dv;
+  a.gauss = L.gauss;
+  a.tile_range = (const int2*)L.tile_range;
+  a.features = g.features;
+  a.c_total = g.c_total;
+  a.ray_order = L.ray_order;
+  a.ray_range = (const int2*)L.ray_range;
+  a.work = (const int2*)L.work;
+  a.n_work = L.n_work;
+  return a;
+}
+
+template <int CMAX, bool LIDAR>
+static void fwd_dispatch(dim3 grid, hipStream_t s, int support, const RasterArgs& a, const FwdOut& o) {
+  if (support == SPLAT_SUPPORT_TILE)
+    hipLaunchKernelGGL((k_raster_fwd<CMAX, LIDAR, true>), grid, dim3(kBlock), 0, s, a, o);
+  else
+    hipLaunchKernelGGL((k_raster_fwd<CMAX, LIDAR, false>), grid, dim3(kBlock), 0, s, a, o);
+}
+
+template <int CMAX, bool LIDAR>
+static void bwd_dispatch(dim3 grid, hipStream_t s, int support, const RasterArgs& a, const BwdIn& b) {
+  if (support == SPLAT_SUPPORT_TILE)
+    hipLaunchKernelGGL((k_raster_bwd<CMAX, LIDAR, true>), grid, dim3(kBlock), 0, s, a, b);
+  else
+    hipLaunchKernelGGL((k_raster_bwd<CMAX, LIDAR, false>), grid, dim3(kBlock), 0, s, a, b);
+}
+
+static int cmax_bucket(int c) { return c <= 4 ? 4 : c <= 8 ? 8 : c <= 16 ? 16 : c <= 32 ? 32 : 64; }
+
+hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
+                             const SplatTileLists& L, int support, const SplatRenderOut& out, hipStream_t s) {
+  RasterArgs a = make_args(v, g, p, L);
+  FwdOut o{out.feat, out.depth, out.alpha, out.t_final, out.last, out.median};
+  const int64_t items = v.lidar ? L.work_cap : v.n_tiles;
+  if (items <= 0) return hipSuccess;
+  dim3 grid((unsigned)items);
+  const int cm = cmax_bucket(v.c_max);
+#define FWD_CASE(CM)                                           \
+  case CM:                                                     \
+    if (v.lidar) fwd_dispatch<CM, true>(grid, s, support, a, o); \
+    else fwd_dispatch<CM, false>(grid, s, support, a, o);      \
+    break;
+  switch (cm) {
+    FWD_CASE(4)
+    FWD_CASE(8)
+    FWD_CASE(16)
+    FWD_CASE(32)
+    FWD_CASE(64)
+  }
+#undef FWD_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
+                             const SplatTileLists& L, int support, const SplatRenderOut& saved, const float* dF,
+                             const float* dD, const float* dA, float* g2d, float* dfeat, hipStream_t s) {
+  RasterArgs a = make_args(v, g, p, L);
+  BwdIn b{saved.t_final, saved.last, dF, dD, dA, g2d, dfeat};
+  const int64_t items = v.lidar ? L.work_cap : v.n_tiles;
+  if (items <= 0) return hipSuccess;
+  dim3 grid((unsigned)items);
+  const int cm = cmax_bucket(v.c_max);
+#define BWD_CASE(CM)                                           \
+  case CM:                                                     \
+    if (v.lidar) bwd_dispatch<CM, true>(grid, s, support, a, b); \
+    else bwd_dispatch<CM, false>(grid, s, support, a, b);      \
+    break;
+  switch (cm) {
+    BWD_CASE(4)
+    BWD_CASE(8)
+    BWD_CASE(16)
+    BWD_CASE(32)
+    BWD_CASE(64)
+  }
+#undef BWD_CASE
+  return hipGetLastError();
+}
+
+}  // namespace splat

@@ -1,0 +1,400 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: culling and tile assignment bit-exact under the library's documented float32 arithmetic
+(stage check) and within near-threshold exclusions end to end; sorted per-tile lists
+bit-exact; rendered features / depth / opacity / median within 1e-5 + 1e-4 |ref| per element on
+rays with no near-threshold decision; gradients within 1e-3 relative (per tensor, and per
+element with atol = 1e-5 max |ref|)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import geometry as geo
+from oracle import grad as ogr
+from oracle import render as rd
+from oracle import tiles as tl
+from scenes import synthetic as S
+from tests.gpu_helpers import gpu_outputs, last_ids_gpu, rtol_check, tile_lists_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _binding():
+    from paper_2411_16816_amd import binding
+    binding.load()
+    return binding
+
+
+# ------------------------------------------------------------------------------------------
+# scenes (seeded)
+# ------------------------------------------------------------------------------------------
+def cam_scene(seed=101, n=20000, W=333, H=245, tile=(16, 16), t_rs=0.03):
+    rng = np.random.default_rng(seed)
+    mu = S.road_slab(rng, n, (0.5, 60.0), (-20.0, 20.0), 6.0)
+    g = S.random_gaussians(rng, mu, 16, rgb=True, moving_frac=0.3)
+    cam = S.make_camera((0, 0, 1.5), 3.0, W, H, 250.0, t_rs=t_rs, ego_vel_world=(12.0, 0.5, 0.0),
+                        ego_yaw_rate=0.2, n_channels=16, tile=tile)
+    return g, cam
+
+
+def lidar_rs_scene(seed=102, n=3000):
+    rng = np.random.default_rng(seed)
+    mu = S.uniform_box(rng, n, (-30, -30, -3), (30, 30, 3))
+    g = S.random_gaussians(rng, mu, 16, rgb=True, moving_frac=0.3)
+    lid = S.make_lidar((0, 0, 0), 7.0, 32, -25.0, 15.0, 512, t_sweep=0.1, ego_vel_world=(15.0, 0, 0),
+                       ego_yaw_rate=0.3, feat_offset=3, n_channels=8)
+    return g, lid
+
+
+def _pass(cams, lids, g, k=0, count=1, margin=1.2):
+    b = _binding()
+    rig = b.Rig(cams, lids)
+    G = b.GaussTensors.from_numpy(g)
+    sp = b.SensorPass(rig, k, count, g.n, k_cap=1)
+    sp.fit_capacity(G, margin)
+    return rig, G, sp
+
+
+# ------------------------------------------------------------------------------------------
+# a1 / a2: projection
+# ------------------------------------------------------------------------------------------
+def _check_projection(sp, g, sensor):
+    torch.cuda.synchronize()
+    nt = sp.ntiles.cpu().numpy()
+    keep = nt > 0
+    pr = geo.project(geo.Params.from_gaussians(g), sensor)
+    valid = pr.valid.numpy()
+    lo, hi = pr.lo.detach().numpy(), pr.hi.detach().numpy()
+    # box edge within 1e-5 relative of the domain edge: culling may legitimately differ
+    if hasattr(sensor, "ray_az"):
+        b = sensor.elev_bounds.astype(np.float64)
+        edge = np.minimum(np.abs(hi[:, 1] - b[0]), np.abs(lo[:, 1] - b[-1]))
+        near = pr.near_cull.numpy() | (edge <= 1e-5)
+    else:
+        edge = np.minimum.reduce([np.abs(hi[:, 0]), np.abs(lo[:, 0] - sensor.width),
+                                  np.abs(hi[:, 1]), np.abs(lo[:, 1] - sensor.height)])
+        near = pr.near_cull.numpy() | (edge <= 1e-2)
+    mism = (keep != valid) & ~near
+    assert mism.sum() == 0, f"{mism.sum()} culling mismatches"
+    both = keep & valid
+    assert both.sum() > 0.5 * valid.sum()
+    mv = sp.mv.cpu().numpy()[both]
+    cn = sp.cn.cpu().numpy()[both]
+    bx = sp.box.cpu().numpy()[both]
+    dv = sp.dv.cpu().numpy()[both]
+    ref = dict(mean=pr.mean2d.detach().numpy()[both], vel=pr.vel2d.detach().numpy()[both],
+               conic=pr.conic.detach().numpy()[both], o=pr.o_eff.detach().numpy()[both],
+               lo=lo[both], hi=hi[both], depth=pr.depth.detach().numpy()[both], vr=pr.v_r.detach().numpy()[both])
+    got = dict(mean=mv[:, :2], vel=mv[:, 2:], conic=cn[:, :3], o=cn[:, 3], lo=bx[:, :2], hi=bx[:, 2:],
+               depth=dv[:, 0], vr=dv[:, 1])
+    for k in ref:
+        scale = max(1e-12, float(np.abs(ref[k]).max()))
+        bad = rtol_check(got[k], ref[k], rtol=2e-5, atol=2e-6 * scale)
+        assert bad.mean() < 1e-3 and (np.abs(got[k] - ref[k]) <= 1e-4 * scale + 1e-3 * np.abs(ref[k])).all(), k
+    # stage check: tile rectangles bit-exact with the documented float32 arithmetic
+    rect = sp.rect.cpu().numpy()[keep]
+    gb = sp.box.cpu().numpy()[keep]
+    if hasattr(sensor, "ray_az"):
+        st, naz, e0, e1 = tl.lidar_tile_rect_f32(gb[:, :2], gb[:, 2:], sensor)
+        np.testing.assert_array_equal(rect[:, 0], st)
+        np.testing.assert_array_equal(rect[:, 1], e0)
+        np.testing.assert_array_equal(rect[:, 2], naz)
+        np.testing.assert_array_equal(rect[:, 3], e1 - e0)
+    else:
+        x0, x1, y0, y1 = tl.camera_tile_rect_f32(gb[:, :2], gb[:, 2:], sensor)
+        np.testing.assert_array_equal(rect, np.stack([x0, y0, x1 - x0, y1 - y0], 1))
+    np.testing.assert_array_equal(nt[keep], rect[:, 2] * rect[:, 3])
+    return keep
+
+
+def test_project_camera():
+    g, cam = cam_scene()
+    rig, G, sp = _pass([cam], [], g)
+    _check_projection(sp, g, cam)
+
+
+def test_project_lidar():
+    g, lid = lidar_rs_scene()
+    rig, G, sp = _pass([], [lid], g)
+    _check_projection(sp, g, lid)
+
+
+# ------------------------------------------------------------------------------------------
+# a3 / a4: binning and sorting, bit-exact against the stage check
+# ------------------------------------------------------------------------------------------
+def _expected_lists(sp, sensor, g_n):
+    nt = sp.ntiles.cpu().numpy()[:g_n]
+    keep = nt > 0
+    box = sp.box.cpu().numpy()[:g_n]
+    depth = sp.dv.cpu().numpy()[:g_n, 0].astype(np.float32)
+    if hasattr(sensor, "ray_az"):
+        rect = tl.lidar_tile_rect_f32(box[:, :2], box[:, 2:], sensor)
+        per = tl.lidar_tiles_of(rect, sensor)
+        n_t = sensor.n_az_tiles * sensor.n_el_tiles
+    else:
+        rect = tl.camera_tile_rect_f32(box[:, :2], box[:, 2:], sensor)
+        per = tl.camera_tiles_of(rect, sensor)
+        n_t = (-(-sensor.width // sensor.tile_w)) * (-(-sensor.height // sensor.tile_h))
+    per = [p if k else [] for p, k in zip(per, keep)]
+    return tl.tile_lists(per, depth, keep, n_t)
+
+
+@pytest.mark.parametrize("kind", ["camera", "lidar"])
+def test_bin_sort_bit_exact(kind):
+    if kind == "camera":
+        g, sensor = cam_scene(n=8000)
+        rig, G, sp = _pass([sensor], [], g)
+    else:
+        g, sensor = lidar_rs_scene()
+        rig, G, sp = _pass([], [sensor], g)
+    sp.render(G)
+    torch.cuda.synchronize()
+    st = _binding().read_status(sp.status)
+    assert st.overflow == 0 and st.n_isect > 0
+    want = _expected_lists(sp, sensor, g.n)
+    got = tile_lists_gpu(sp)
+    assert sum(len(x) for x in want) == st.n_isect
+    assert got == want
+    if kind == "lidar":
+        a, e, v = tl.lidar_ray_tiles_f32(sensor.ray_az, sensor.ray_el, sensor)
+        tiles = np.where(v, e * sensor.n_az_tiles + a, sensor.n_az_tiles * sensor.n_el_tiles)
+        order = sp.ray_order.cpu().numpy()[:sensor.n_rays]
+        rr = sp.ray_range.cpu().numpy()
+        for t in range(rr.shape[0]):
+            ids = order[rr[t, 0]:rr[t, 1]]
+            np.testing.assert_array_equal(ids, np.nonzero(tiles == t)[0])
+        nw = int(sp.n_work.cpu()[0])
+        work = sp.work.cpu().numpy()[:nw]
+        counts = rr[:, 1] - rr[:, 0]
+        assert nw == int(np.sum((counts + 255) // 256))
+
+
+def test_overflow_is_reported_and_safe():
+    g, cam = cam_scene(n=4000)
+    b = _binding()
+    rig = b.Rig([cam], [])
+    G = b.GaussTensors.from_numpy(g)
+    sp = b.SensorPass(rig, 0, 1, g.n, k_cap=1000)
+    sp.status.zero_()
+    sp.render(G)
+    torch.cuda.synchronize()
+    st = b.read_status(sp.status)
+    assert st.overflow == 1 and st.n_isect > 1000 and st.k_cap == 1000
+    assert int(sp.tile_range.max()) <= 1000
+
+
+# ------------------------------------------------------------------------------------------
+# a5 / a6: forward rendering
+# ------------------------------------------------------------------------------------------
+def _compare_render(sp, k, sensor, g, ray_idx, support=0, out=None):
+    gout = gpu_outputs(sp, k)
+    ref = rd.render_sensor(g, sensor, ray_idx, mode="box" if support == 0 else "tile")
+    near = ref["near"]
+    ok = ~near
+    assert near.mean() < 0.05, near.mean()
+    for key in ("F", "D", "A"):
+        a = gout[key][ray_idx]
+        r = ref[key].detach().numpy()
+        bad = rtol_check(a, r, 1e-4, 1e-5, ok)
+        assert not bad.any(), (key, int(bad.sum()))
+    np.testing.assert_allclose(gout["T"][ray_idx][ok], ref["T"].numpy()[ok], rtol=1e-4, atol=1e-5)
+    if "median" in gout:
+        bad = rtol_check(gout["median"][ray_idx], ref["median"].numpy(), 1e-4, 1e-5, ok)
+        assert not bad.any()
+    lid = last_ids_gpu(sp, k, sensor, ray_idx, gout["last"][ray_idx])
+    assert np.array_equal(lid[ok], ref["last_id"].numpy()[ok])
+    return ref
+
+
+def test_forward_lidar_config1_all_rays():
+    sc = S.config_1()
+    lid = sc.lidars[0]
+    rig, G, sp = _pass([], [lid], sc.gaussians)
+    sp.render(G)
+    torch.cuda.synchronize()
+    _compare_render(sp, 0, lid, sc.gaussians, np.arange(lid.n_rays))
+
+
+def test_forward_lidar_rolling_shutter():
+    g, lid = lidar_rs_scene()
+    rig, G, sp = _pass([], [lid], g)
+    sp.render(G)
+    torch.cuda.synchronize()
+    _compare_render(sp, 0, lid, g, np.arange(0, lid.n_rays, 3))
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 8), (8, 8)])
+def test_forward_camera_ragged(tile):
+    g, cam = cam_scene(n=12000, tile=tile)
+    rig, G, sp = _pass([cam], [], g)
+    sp.render(G)
+    torch.cuda.synchronize()
+    idx = np.arange(0, cam.n_rays, 7)
+    _compare_render(sp, 0, cam, g, idx)
+
+
+def test_forward_tile_mode():
+    g, cam = cam_scene(n=3000, W=96, H=80)
+    rig, G, sp = _pass([cam], [], g)
+    sp.render(G, support=1)
+    torch.cuda.synchronize()
+    _compare_render(sp, 0, cam, g, np.arange(cam.n_rays), support=1)
+
+
+def test_box_result_independent_of_tile_shape():
+    outs = []
+    for tile in [(16, 16), (32, 8), (8, 32), (8, 8)]:
+        g, cam = cam_scene(n=6000, tile=tile)
+        rig, G, sp = _pass([cam], [], g)
+        sp.render(G)
+        torch.cuda.synchronize()
+        o = gpu_outputs(sp, 0)
+        outs.append(o)
+    for o in outs[1:]:
+        for k in ("F", "D", "A", "T"):
+            np.testing.assert_array_equal(o[k], outs[0][k])
+
+
+def test_empty_scene_and_invalid_rays():
+    g, cam = cam_scene(n=500)
+    g.means[:, 0] = -np.abs(g.means[:, 0]) - 1.0          # everything behind the camera
+    rig, G, sp = _pass([cam], [], g)
+    sp.render(G)
+    torch.cuda.synchronize()
+    o = gpu_outputs(sp, 0)
+    assert np.all(o["F"] == 0) and np.all(o["A"] == 0) and np.all(o["T"] == 1)
+    g2, lid = lidar_rs_scene(n=500)
+    lid.ray_el = lid.ray_el.copy()
+    lid.ray_el[:100] = np.float32(1.2)                     # far above the top boundary
+    lid.ray_az = lid.ray_az.copy()
+    lid.ray_az[100:150] = np.float32(7.0)                  # outside [0, 2pi)
+    rig, G, sp = _pass([], [lid], g2)
+    sp.status.zero_()
+    sp.render(G)
+    torch.cuda.synchronize()
+    st = _binding().read_status(sp.status)
+    assert st.n_rays_invalid == 150
+    o = gpu_outputs(sp, 0)
+    assert np.all(o["F"][:150] == 0) and np.all(o["A"][:150] == 0) and np.all(o["D"][:150] == 0)
+
+
+def test_batched_equals_plain():
+    g, cam = cam_scene(n=6000)
+    cam2 = S.make_camera((0, 0, 1.5), -25.0, 200, 130, 180.0, t_rs=0.02, ego_vel_world=(10.0, 0, 0), n_channels=16)
+    b = _binding()
+    rig = b.Rig([cam, cam2], [])
+    G = b.GaussTensors.from_numpy(g)
+    both = b.SensorPass(rig, 0, 2, g.n, 1)
+    both.fit_capacity(G)
+    both.render(G)
+    plain = []
+    for k in range(2):
+        sp = b.SensorPass(rig, k, 1, g.n, 1)
+        sp.fit_capacity(G)
+        sp.render(G)
+        plain.append(sp)
+    torch.cuda.synchronize()
+    for k in range(2):
+        a = gpu_outputs(both, k)
+        p = gpu_outputs(plain[k], 0)
+        for key in ("F", "D", "A", "T", "last"):
+            np.testing.assert_array_equal(a[key], p[key])
+    g2, lid = lidar_rs_scene()
+    lid2 = S.make_lidar((1.0, 2.0, 0), -40.0, 16, -20.0, 10.0, 300, t_sweep=0.1, ego_vel_world=(8.0, 0, 0),
+                        tile_az=16, feat_offset=3, n_channels=8)
+    rig = b.Rig([], [lid, lid2])
+    G = b.GaussTensors.from_numpy(g2)
+    both = b.SensorPass(rig, 0, 2, g2.n, 1)
+    both.fit_capacity(G)
+    both.render(G)
+    for k in range(2):
+        sp = b.SensorPass(rig, k, 1, g2.n, 1)
+        sp.fit_capacity(G)
+        sp.render(G)
+        torch.cuda.synchronize()
+        a = gpu_outputs(both, k)
+        p = gpu_outputs(sp, 0)
+        for key in ("F", "D", "A", "T", "last", "median"):
+            np.testing.assert_array_equal(a[key], p[key])
+
+
+# ------------------------------------------------------------------------------------------
+# a7: adjoint
+# ------------------------------------------------------------------------------------------
+def _grad_check(kind, seed):
+    b = _binding()
+    rng = np.random.default_rng(seed)
+    if kind == "camera":
+        sensor = S.make_camera((0, 0, 0), 0.0, 64, 48, 60.0, t_rs=0.04, ego_vel_world=(6.0, 0.5, 0),
+                               ego_yaw_rate=0.3, n_channels=16)
+        n = 250
+        mu = np.stack([rng.uniform(2, 12, n), rng.uniform(-5, 5, n), rng.uniform(-3.5, 3.5, n)], 1)
+        rig = b.Rig([sensor], [])
+    else:
+        sensor = S.make_lidar((0, 0, 0), 0.0, 16, -15.0, 15.0, 256, tile_az=16, tile_el=8, t_sweep=0.1,
+                              ego_vel_world=(10.0, 1.0, 0), feat_offset=3, n_channels=8)
+        n = 300
+        mu = np.stack([rng.uniform(-10, 10, n), rng.uniform(-10, 10, n), rng.uniform(-1.5, 1.5, n)], 1)
+        rig = b.Rig([], [sensor])
+    g = S.random_gaussians(rng, mu, 16, rgb=True, moving_frac=0.5, log_scale_mean=-0.6)
+    G = b.GaussTensors.from_numpy(g)
+    sp = b.SensorPass(rig, 0, 1, g.n, 1)
+    sp.fit_capacity(G)
+    sp.render(G)
+    R = sensor.n_rays
+    C = sensor.n_channels
+    up = np.random.default_rng(seed + 1)
+    dF = up.normal(size=(R, C)).astype(np.float32)
+    dD = (0.1 * up.normal(size=R)).astype(np.float32)
+    dA = up.normal(size=R).astype(np.float32)
+    grads = b.zeros_like_grads(G)
+    t = lambda a: torch.from_numpy(a.reshape(-1)).cuda()
+    sp.raster_bwd(G, t(dF), t(dD), t(dA), grads)
+    torch.cuda.synchronize()
+    ref, out = ogr.reference_grads(g, sensor, np.arange(R), dF, dD, dA)
+    near = out["near"]
+    assert near.mean() < 0.05
+    # the reference gradient counts every ray; re-run excluding near-decision rays on both sides
+    if near.any():
+        keep = ~near
+        dF2, dD2, dA2 = dF * keep[:, None], dD * keep, dA * keep
+        ref, _ = ogr.reference_grads(g, sensor, np.arange(R), dF2, dD2, dA2)
+        grads = b.zeros_like_grads(G)
+        sp.raster_bwd(G, t(dF2.astype(np.float32)), t(dD2.astype(np.float32)), t(dA2.astype(np.float32)), grads)
+        torch.cuda.synchronize()
+    got = dict(means=grads.means, log_scales=grads.log_scales, quats=grads.quats, opacities=grads.opacities,
+               velocities=grads.velocities, features=grads.features)
+    for name in geo.Params.names:
+        gg = got[name].cpu().numpy().astype(np.float64)
+        rr = ref[name]
+        nrm = np.linalg.norm(rr)
+        assert nrm > 0, name
+        rel = np.linalg.norm(gg - rr) / nrm
+        assert rel <= 1e-3, (name, rel)
+        bad = np.abs(gg - rr) > 1e-3 * np.abs(rr) + 1e-5 * np.abs(rr).max()
+        assert bad.mean() < 2e-3, (name, int(bad.sum()))
+
+
+def test_backward_camera():
+    _grad_check("camera", 7)
+
+
+def test_backward_lidar():
+    _grad_check("lidar", 8)
+
+
+def test_autograd_function_camera():
+    b = _binding()
+    g, cam = cam_scene(n=2000, W=96, H=64)
+    rig = b.Rig([cam], [])
+    G = b.GaussTensors.from_numpy(g)
+    sp = b.SensorPass(rig, 0, 1, g.n, 16)      # too small: the Function grows it
+    ps = [t.clone().requires_grad_(True) for t in (G.means, G.log_scales, G.quats, G.opacities, G.velocities, G.features)]
+    F, D, A = b.SplatRenderFn.apply(sp, 0, *ps)
+    loss = (F ** 2).sum() + D.sum() * 0.01 + A.sum()
+    loss.backward()
+    for p in ps:
+        assert p.grad is not None and torch.isfinite(p.grad).all()
+    assert float(ps[0].grad.abs().sum()) > 0
