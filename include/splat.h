@@ -49,7 +49,7 @@ extern "C" {
 
 #define SPLAT_MAX_EL_TILES 64         /* lidar elevation tiles (M_omega) per sensor */
 #define SPLAT_MAX_SENSORS 1024        /* sensors per rig */
-#define SPLAT_MAX_CHANNELS 64         /* blended feature channels per sensor */
+#define SPLAT_MAX_CHANNELS 48         /* blended feature channels per sensor */
 #define SPLAT_RAYS_PER_ITEM 256       /* lidar rays per rasterisation work item (App. A) */
 
 /* candidate rule of the rasterisers */
@@ -141,6 +141,9 @@ typedef struct SplatProjected {
   float* cn;        /* [n_records,4] conic (a,b,c) of (Sigma + sI)^-1 = [[a,b],[b,c]], o_eff    */
   float* box;       /* [n_records,4] lo_u, lo_v, hi_u, hi_v of the 3-sigma + RS box          */
   float* dv;        /* [n_records,2] depth (z | range) and range velocity (lidar; 0 camera)    */
+  unsigned long long* dkey; /* [n_records] depth sort key: IEEE bits of the depth (z | range)
+                       evaluated in float64 from the float32 inputs; Gaussians are ordered by
+                       its upper 48 bits (2^-36 relative), ties by Gaussian id               */
   int32_t* rect;    /* [n_records,4] tiles: camera (x0, y0, nx, ny); lidar (az0, el0, naz, nel) */
   int32_t* n_tiles; /* [n_records] tiles touched (0 = culled)                                 */
 } SplatProjected;
@@ -154,8 +157,9 @@ typedef struct SplatTileLists {
   int32_t* ray_order;     /* [n_rays] local ray ids grouped by tile (invalid rays last)         */
   int32_t* ray_range;     /* [n_tiles + 1, 2] [start, end) into ray_order; entry n_tiles =
                              invalid rays                                                      */
-  int32_t* work;          /* [work_cap, 2] work items (tile, first position in ray_order)      */
-  int32_t* n_work;        /* [1] number of work items                                          */
+  int32_t* work;          /* [work_cap, 2] work items (tile, first position in ray_order; camera
+                             tiles of a batched call are items (tile, 0))                       */
+  int32_t* n_work;        /* [2] number of work items; queue counter of the persistent kernels  */
   int64_t work_cap;       /* >= n_tiles + ceil(n_rays / 256) + 1                               */
 } SplatTileLists;
 
@@ -238,6 +242,26 @@ int splat_rasterize_fwd_camera(const SplatGaussians* g, const SplatRig* rig, int
 int splat_rasterize_fwd_lidar(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
                               const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
                               const SplatRenderOut* out, SplatStatus* status, void* stream);
+
+/* ---- a8: batched form.  The same four steps for any mix of the rig's sensors in one call
+ * (cameras and lidars together): one projection launch reading every Gaussian once for all
+ * sensors; one bin/sort over every sensor's tiles that also builds a global work queue of
+ * camera tiles and lidar ray chunks ordered by descending list length; and persistent
+ * rasterisers (forward and adjoint) whose workgroups drain that queue.  Lists need ray_order
+ * (if any lidar), ray_range, work and n_work.  Results are bit-identical to the per-sensor
+ * calls (BOX support); the adjoint accumulates in a different order (float atomics). */
+int splat_project(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
+                  const SplatProjected* out, SplatStatus* status, void* stream);
+int splat_bin_sort(const SplatRig* rig, int32_t first, int32_t count, int64_t n_gaussians,
+                   const SplatProjected* proj, const SplatTileLists* lists, void* ws, size_t ws_bytes,
+                   SplatStatus* status, void* stream);
+int splat_rasterize_fwd(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
+                        const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                        const SplatRenderOut* out, void* stream);
+int splat_rasterize_bwd(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
+                        const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                        const SplatRenderOut* saved, const float* d_feat, const float* d_depth,
+                        const float* d_alpha, const SplatGrads* grads, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- a7: rasterisation backward + projection adjoint.  Walks each ray's list back to front
  * from `last`, recovering T_i = T_{i+1} / (1 - alpha_i) from the saved T_final, reduces

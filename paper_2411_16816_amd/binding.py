@@ -50,6 +50,10 @@ def _declare(lib):
         "splat_rasterize_fwd_lidar": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp]),
         "splat_rasterize_bwd_camera": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
         "splat_rasterize_bwd_lidar": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+        "splat_project": (C.c_int, [vp, vp, i32, i32, vp, vp, vp]),
+        "splat_bin_sort": (C.c_int, [vp, i32, i32, i64, vp, vp, vp, C.c_size_t, vp, vp]),
+        "splat_rasterize_fwd": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp]),
+        "splat_rasterize_bwd": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -173,17 +177,23 @@ def read_status(t: torch.Tensor) -> st.SplatStatus:
 
 
 class SensorPass:
-    """All buffers of one call range [first, first + count) of a rig (all cameras or all lidars),
-    and the four library calls.  `count == 1` is the plain per-sensor form; larger counts are
-    the batched multi-sensor form of the same calls."""
+    """All buffers of one call range [first, first + count) of a rig, and the four library calls.
 
-    def __init__(self, rig: Rig, first: int, count: int, n_gauss: int, k_cap: int, device="cuda"):
+    batched=False: the per-kind calls (all sensors of the range are cameras, or all lidars);
+    count == 1 is the plain per-sensor form.  batched=True: the batched calls (any mix of
+    cameras and lidars, one launch per step, persistent queue rasterisers)."""
+
+    def __init__(self, rig: Rig, first: int, count: int, n_gauss: int, k_cap: int, device="cuda",
+                 batched: bool = False):
         self.rig, self.first, self.count = rig, first, count
         self.lib = rig.lib
-        kinds = {rig.kind(s) for s in range(first, first + count)}
-        assert len(kinds) == 1, "a call range holds one sensor kind"
-        self.kind = kinds.pop()
-        self.lidar = self.kind == KIND_LIDAR
+        self.batched = batched
+        kinds = [rig.kind(s) for s in range(first, first + count)]
+        if not batched:
+            assert len(set(kinds)) == 1, "a per-kind call range holds one sensor kind"
+        self.kind = kinds[0] if len(set(kinds)) == 1 else -1
+        self.lidar = (not batched) and self.kind == KIND_LIDAR
+        self.has_lidar = KIND_LIDAR in kinds
         self.device = device
         self.n_gauss = n_gauss
         tb, rb, fb = rig.tile_base, rig.ray_base, rig.feat_base
@@ -199,15 +209,18 @@ class SensorPass:
         self.cn = torch.empty((R, 4), **f32)
         self.box = torch.empty((R, 4), **f32)
         self.dv = torch.empty((R, 2), **f32)
+        self.dkey = torch.empty((R,), dtype=torch.int64, device=device)
         self.rect = torch.empty((R, 4), **i32)
         self.ntiles = torch.empty((R,), **i32)
         self.tile_range = torch.empty((max(1, self.n_tiles), 2), **i32)
-        if self.lidar:
+        if self.has_lidar or batched:
             self.work_cap = self.n_tiles + (self.n_rays + 255) // 256 + 1
-            self.ray_order = torch.empty((max(1, self.n_rays),), **i32)
+            first_lidar = next((k for k in range(count) if rig.kind(first + k) == KIND_LIDAR), count)
+            n_lidar_rays = self.n_rays - int(self.ray_off[first_lidar])
+            self.ray_order = torch.empty((max(1, n_lidar_rays),), **i32)
             self.ray_range = torch.empty((self.n_tiles + 1, 2), **i32)
             self.work = torch.empty((self.work_cap, 2), **i32)
-            self.n_work = torch.zeros((1,), **i32)
+            self.n_work = torch.zeros((2,), **i32)
         else:
             self.work_cap = 0
             self.ray_order = self.ray_range = self.work = self.n_work = None
@@ -216,7 +229,7 @@ class SensorPass:
         self.alpha = torch.empty((max(1, self.n_rays),), **f32)
         self.t_final = torch.empty((max(1, self.n_rays),), **f32)
         self.last = torch.empty((max(1, self.n_rays),), **i32)
-        self.median = torch.empty((max(1, self.n_rays),), **f32) if self.lidar else None
+        self.median = torch.empty((max(1, self.n_rays),), **f32) if self.has_lidar else None
         self.status = _status_tensor(device)
         self.set_capacity(k_cap)
 
@@ -235,6 +248,7 @@ class SensorPass:
         p = st.SplatProjected()
         p.n_records = self.count * self.n_gauss
         p.mv, p.cn, p.box, p.dv = _ptr(self.mv), _ptr(self.cn), _ptr(self.box), _ptr(self.dv)
+        p.dkey = _ptr(self.dkey)
         p.rect, p.n_tiles = _ptr(self.rect), _ptr(self.ntiles)
         return p
 
@@ -255,18 +269,24 @@ class SensorPass:
 
     # ---- the four calls -------------------------------------------------------------------
     def project(self, g: GaussTensors, stream=None):
-        fn = self.lib.splat_project_lidar if self.lidar else self.lib.splat_project_camera
+        fn = (self.lib.splat_project if self.batched else
+              self.lib.splat_project_lidar if self.lidar else self.lib.splat_project_camera)
         check(fn(C.byref(g.struct()), self.rig.handle, self.first, self.count, C.byref(self.proj_struct()),
                  _ptr(self.status), _stream(stream)), "splat_project")
 
     def bin_sort(self, stream=None):
-        fn = self.lib.splat_bin_sort_lidar if self.lidar else self.lib.splat_bin_sort_camera
+        fn = (self.lib.splat_bin_sort if self.batched else
+              self.lib.splat_bin_sort_lidar if self.lidar else self.lib.splat_bin_sort_camera)
         check(fn(self.rig.handle, self.first, self.count, self.n_gauss, C.byref(self.proj_struct()),
                  C.byref(self.lists_struct()), C.c_void_p(self.ws_ptr), self.ws_bytes, _ptr(self.status),
                  _stream(stream)), "splat_bin_sort")
 
     def raster_fwd(self, g: GaussTensors, support=BOX, stream=None):
-        if self.lidar:
+        if self.batched:
+            check(self.lib.splat_rasterize_fwd(C.byref(g.struct()), self.rig.handle, self.first, self.count,
+                                               C.byref(self.proj_struct()), C.byref(self.lists_struct()), support,
+                                               C.byref(self.out_struct()), _stream(stream)), "splat_rasterize_fwd")
+        elif self.lidar:
             check(self.lib.splat_rasterize_fwd_lidar(C.byref(g.struct()), self.rig.handle, self.first, self.count,
                                                      C.byref(self.proj_struct()), C.byref(self.lists_struct()),
                                                      support, C.byref(self.out_struct()), _ptr(self.status),
@@ -281,7 +301,8 @@ class SensorPass:
         gr = st.SplatGrads()
         gr.means, gr.log_scales, gr.quats = _ptr(grads.means), _ptr(grads.log_scales), _ptr(grads.quats)
         gr.opacities, gr.velocities, gr.features = _ptr(grads.opacities), _ptr(grads.velocities), _ptr(grads.features)
-        fn = self.lib.splat_rasterize_bwd_lidar if self.lidar else self.lib.splat_rasterize_bwd_camera
+        fn = (self.lib.splat_rasterize_bwd if self.batched else
+              self.lib.splat_rasterize_bwd_lidar if self.lidar else self.lib.splat_rasterize_bwd_camera)
         check(fn(C.byref(g.struct()), self.rig.handle, self.first, self.count, C.byref(self.proj_struct()),
                  C.byref(self.lists_struct()), support, C.byref(self.out_struct()), _ptr(dF), _ptr(dD), _ptr(dA),
                  C.byref(gr), C.c_void_p(self.ws_ptr), self.ws_bytes, _stream(stream)), "splat_rasterize_bwd")

@@ -17,6 +17,7 @@ struct SplatRig {
   hipEvent_t uploaded = nullptr;
   bool upload_pending = false;
   bool is_set = false;
+  int n_cu = 0;                     // compute units of the rig's device (persistent grids)
   SplatRigLayout layout;
 };
 
@@ -71,6 +72,10 @@ int splat_rig_create(int32_t n_cameras, int32_t n_lidars, SplatRig** out) {
     return SPLAT_ERR_DEVICE;
   }
   memset(&r->layout, 0, sizeof(r->layout));
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&r->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    r->n_cu = 0;
   *out = r;
   return SPLAT_OK;
 }
@@ -128,6 +133,7 @@ int splat_rig_layout(const SplatRig* r, SplatRigLayout* out) {
 }  // extern "C"
 
 // ---------------------------------------------------------------------------------------------
+// kind: kCamera / kLidar for the plain per-kind calls, -1 for the batched form (any mix)
 static int make_view(const SplatRig* r, int32_t first, int32_t count, int kind, int64_t n_gauss, CallView& v) {
   if (!r || !r->is_set || count <= 0 || first < 0 || first + count > r->n_cam + r->n_lid || n_gauss < 0)
     return SPLAT_ERR_INVALID_ARG;
@@ -138,14 +144,23 @@ static int make_view(const SplatRig* r, int32_t first, int32_t count, int kind, 
   v.n_tiles = 0;
   v.n_rays = 0;
   v.c_max = 0;
+  v.has_lidar = false;
+  v.lidar_ray0 = -1;
   for (int i = 0; i < count; ++i) {
     const DevSensor& d = v.host[i];
     if (kind >= 0 && d.kind != kind) return SPLAT_ERR_INVALID_ARG;
+    if (d.kind == kLidar && !v.has_lidar) {
+      v.has_lidar = true;
+      v.lidar_ray0 = v.n_rays;
+    }
     v.n_tiles += d.n_tiles;
     v.n_rays += d.n_rays;
     v.c_max = d.n_ch > v.c_max ? d.n_ch : v.c_max;
   }
+  if (!v.has_lidar) v.lidar_ray0 = v.n_rays;
   v.lidar = (kind == kLidar);
+  v.queue = (kind < 0);
+  v.n_cu = r->n_cu;
   if ((int64_t)count * n_gauss >= ((int64_t)1 << 32)) return SPLAT_ERR_UNSUPPORTED;
   return SPLAT_OK;
 }
@@ -164,9 +179,10 @@ static int check_gaussians(const SplatGaussians* g, const CallView& v) {
 
 static int check_proj(const SplatProjected* p, const CallView& v) {
   if (!p || p->n_records != (int64_t)v.count * v.n_gauss) return SPLAT_ERR_INVALID_ARG;
-  if (p->n_records > 0 && (!p->mv || !p->cn || !p->box || !p->dv || !p->rect || !p->n_tiles)) return SPLAT_ERR_INVALID_ARG;
+  if (p->n_records > 0 && (!p->mv || !p->cn || !p->box || !p->dv || !p->dkey || !p->rect || !p->n_tiles))
+    return SPLAT_ERR_INVALID_ARG;
   if ((((uintptr_t)p->mv | (uintptr_t)p->cn | (uintptr_t)p->box | (uintptr_t)p->rect) & 15) != 0 ||
-      ((uintptr_t)p->dv & 7) != 0)
+      (((uintptr_t)p->dv | (uintptr_t)p->dkey) & 7) != 0)
     return SPLAT_ERR_INVALID_ARG;
   return SPLAT_OK;
 }
@@ -175,11 +191,10 @@ static int check_lists(const SplatTileLists* L, const CallView& v) {
   if (!L || L->k_cap < 0 || L->k_cap >= ((int64_t)1 << 31)) return SPLAT_ERR_INVALID_ARG;
   if ((L->k_cap > 0 && !L->gauss) || !L->tile_range) return SPLAT_ERR_INVALID_ARG;
   if (((uintptr_t)L->tile_range & 7) != 0) return SPLAT_ERR_INVALID_ARG;
-  if (v.lidar) {
-    if (!L->ray_order || !L->ray_range || !L->work || !L->n_work) return SPLAT_ERR_INVALID_ARG;
+  if (v.has_lidar || v.queue) {
+    if ((v.has_lidar && !L->ray_order) || !L->ray_range || !L->work || !L->n_work) return SPLAT_ERR_INVALID_ARG;
     if ((((uintptr_t)L->ray_range | (uintptr_t)L->work) & 7) != 0) return SPLAT_ERR_INVALID_ARG;
-    int64_t need = v.n_tiles + (v.n_rays + SPLAT_RAYS_PER_ITEM - 1) / SPLAT_RAYS_PER_ITEM + 1;
-    if (L->work_cap < need) return SPLAT_ERR_INVALID_ARG;
+    if (L->work_cap < work_capacity(v.n_tiles, v.n_rays)) return SPLAT_ERR_INVALID_ARG;
   }
   return SPLAT_OK;
 }
@@ -255,6 +270,27 @@ size_t splat_workspace_bytes(const SplatRig* r, int32_t first, int32_t count, in
   CallView v;
   if (make_view(r, first, count, -1, n_gaussians, v) != SPLAT_OK || k_cap < 0) return 0;
   return carve_workspace(nullptr, (int64_t)count * n_gaussians, k_cap, v.n_tiles, v.n_rays).bytes;
+}
+
+int splat_project(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count, const SplatProjected* out,
+                  SplatStatus* st, void* stream) {
+  return project_impl(g, r, first, count, -1, out, st, stream);
+}
+int splat_bin_sort(const SplatRig* r, int32_t first, int32_t count, int64_t n_gaussians, const SplatProjected* proj,
+                   const SplatTileLists* lists, void* ws, size_t ws_bytes, SplatStatus* st, void* stream) {
+  return bin_sort_impl(r, first, count, -1, n_gaussians, proj, lists, ws, ws_bytes, st, stream);
+}
+int splat_rasterize_fwd(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,
+                        const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                        const SplatRenderOut* out, void* stream) {
+  return raster_fwd_impl(g, r, first, count, -1, proj, lists, support, out, stream);
+}
+int splat_rasterize_bwd(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,
+                        const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
+                        const SplatRenderOut* saved, const float* d_feat, const float* d_depth, const float* d_alpha,
+                        const SplatGrads* grads, void* ws, size_t ws_bytes, void* stream) {
+  return raster_bwd_impl(g, r, first, count, -1, proj, lists, support, saved, d_feat, d_depth, d_alpha, grads, ws,
+                         ws_bytes, stream);
 }
 
 int splat_project_camera(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,

@@ -38,6 +38,9 @@ hipError_t fill(T* p, int64_t n, T v, hipStream_t s) {
 }
 
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) { return fill<float>(p, n, v, s); }
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) { return fill<int32_t>(p, n, v, s); }
+
+__global__ void k_copy_i64(const int64_t* __restrict__ src, int64_t* __restrict__ dst) { *dst = *src; }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   int lane = threadIdx.x & 63;
@@ -83,10 +86,11 @@ struct LoadU32 {
   const uint32_t* p;
   __device__ uint32_t operator()(int64_t i) const { return p[i]; }
 };
-struct LoadTilesByOrder {   // n_tiles of the i-th record in depth order
+struct LoadTilesByOrder {   // n_tiles of the i-th visible record in depth order
   const int32_t* n_tiles;
   const uint32_t* order;
-  __device__ int64_t operator()(int64_t i) const { return (int64_t)n_tiles[order[i]]; }
+  const int64_t* n_vis;
+  __device__ int64_t operator()(int64_t i) const { return i < *n_vis ? (int64_t)n_tiles[order[i]] : 0; }
 };
 struct LoadI64 {
   const int64_t* p;
@@ -188,7 +192,8 @@ __device__ __forceinline__ int64_t sort_count(const int64_t* n_ptr, int64_t n_ca
   return n < n_cap ? n : n_cap;
 }
 
-__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap,
+template <typename K>
+__global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap,
                                                     int shift, int bits, uint32_t* __restrict__ hist, int64_t nb) {
   __shared__ uint32_t cnt[kRadixBins];
   const int tid = threadIdx.x;
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
       int64_t i = base + (int64_t)r * kScanThreads + tid;
       if (base + (int64_t)r * kScanThreads >= n) break;
       bool valid = i < n;
-      uint32_t d = valid ? ((keys[i] >> shift) & mask) : 0u;
+      uint32_t d = valid ? ((uint32_t)(keys[i] >> shift) & mask) : 0u;
       uint64_t m = match_digit(d, valid, bits);
       if (valid && (m & lt) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(m));
     }
@@ -212,8 +217,9 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
   hist[(int64_t)tid * nb + blockIdx.x] = cnt[tid];
 }
 
-__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                       uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+template <typename K>
+__global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                       K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                        const int64_t* n_ptr, int64_t n_cap, int shift, int bits,
                                                        const uint32_t* __restrict__ hist, int64_t nb) {
   __shared__ uint32_t run[kRadixBins];
@@ -231,9 +237,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     if (base + (int64_t)r * kScanThreads >= n) break;   // uniform
     int64_t i = base + (int64_t)r * kScanThreads + tid;
     bool valid = i < n;
-    uint32_t key = valid ? kin[i] : 0u;
+    K key = valid ? kin[i] : (K)0;
     uint32_t val = valid ? vin[i] : 0u;
-    uint32_t d = (key >> shift) & mask;
+    uint32_t d = (uint32_t)(key >> shift) & mask;
     uint64_t m = match_digit(d, valid, bits);
     uint32_t rank = (uint32_t)__popcll(m & lt);
     if (valid && rank == 0) wc[wid][d] = (uint32_t)__popcll(m);
@@ -251,24 +257,25 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
   }
 }
 
-// Sorts (k[cur], v[cur]) by the low `total_bits` bits of the key.  On return `cur` indexes the
-// sorted keys; the sorted values are in v[cur], or in `final_vals` when it is non-null.
-static hipError_t radix_sort(uint32_t* k[2], uint32_t* v[2], int& cur, const int64_t* n_ptr, int64_t n_cap,
-                             int total_bits, uint32_t* hist, uint32_t* hist_part, uint32_t* final_vals,
-                             hipStream_t s) {
+// Sorts (k[cur], v[cur]) stably by key bits [lo_bit, lo_bit + total_bits).  On return `cur`
+// indexes the sorted keys; the sorted values are in v[cur], or in `final_vals` when it is
+// non-null.  n_ptr (device) gives the element count when non-null, capped by n_cap.
+template <typename K>
+static hipError_t radix_sort(K* k[2], uint32_t* v[2], int& cur, const int64_t* n_ptr, int64_t n_cap, int lo_bit,
+                             int total_bits, uint32_t* hist, uint32_t* hist_part, uint32_t* final_vals, hipStream_t s) {
   if (total_bits < 1) total_bits = 1;
   const int passes = (total_bits + kRadixBits - 1) / kRadixBits;
   const int64_t nb = div_up(n_cap, kScanTile);
   if (nb == 0) return hipSuccess;
   for (int p = 0; p < passes; ++p) {
-    const int shift = p * kRadixBits;
-    const int bits = (total_bits - shift) < kRadixBits ? (total_bits - shift) : kRadixBits;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(256), 0, s, (const uint32_t*)k[cur], n_ptr, n_cap, shift,
+    const int shift = lo_bit + p * kRadixBits;
+    const int bits = (total_bits - p * kRadixBits) < kRadixBits ? (total_bits - p * kRadixBits) : kRadixBits;
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(256), 0, s, (const K*)k[cur], n_ptr, n_cap, shift,
                        bits, hist, nb);
     hipError_t e = device_scan<uint32_t>(LoadU32{hist}, (int64_t)kRadixBins * nb, hist, hist_part, s);
     if (e != hipSuccess) return e;
     uint32_t* vdst = (p == passes - 1 && final_vals) ? final_vals : v[1 - cur];
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(256), 0, s, (const uint32_t*)k[cur],
+    hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)nb), dim3(256), 0, s, (const K*)k[cur],
                        (const uint32_t*)v[cur], k[1 - cur], vdst, n_ptr, n_cap, shift, bits, (const uint32_t*)hist, nb);
     cur = 1 - cur;
   }
@@ -288,14 +295,23 @@ __device__ __forceinline__ int64_t local_tile_base(const DevSensor* sens, int s)
   return sens[s].tile_base - sens[0].tile_base;
 }
 
-// depth keys: float32 bits of a positive depth sort like the numbers; culled -> 0xFFFFFFFF
-__global__ void k_depth_keys(const int32_t* __restrict__ n_tiles, const float2* __restrict__ dv, int64_t n_rec,
-                             uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+// compaction of the visible records with their float64 depth keys (upper 48 bits)
+struct LoadVisible {
+  const int32_t* n_tiles;
+  __device__ int64_t operator()(int64_t i) const { return n_tiles[i] > 0 ? 1 : 0; }
+};
+
+constexpr int kDepthKeyShift = 16;   // drop the 16 lowest mantissa bits: 2^-36 relative resolution
+constexpr int kDepthKeyBits = 48;
+
+__global__ void k_compact_visible(const int32_t* __restrict__ n_tiles, const unsigned long long* __restrict__ dkey,
+                                  const int64_t* __restrict__ pos, int64_t n_rec, uint64_t* __restrict__ keys,
+                                  uint32_t* __restrict__ vals) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_rec) return;
-  bool vis = n_tiles[i] > 0;
-  keys[i] = vis ? __float_as_uint(dv[i].x) : 0xFFFFFFFFu;   // dv of culled records is not written
-  vals[i] = (uint32_t)i;
+  if (i >= n_rec || n_tiles[i] <= 0) return;
+  int64_t p = pos[i];
+  keys[p] = (uint64_t)dkey[i];
+  vals[p] = (uint32_t)i;
 }
 
 __global__ void k_finalize_count(const int64_t* __restrict__ total, int64_t k_cap, int64_t* __restrict__ n_sort,
@@ -322,10 +338,10 @@ constexpr int kBigRecord = 32;   // records touching more tiles are emitted by a
 
 __global__ void k_emit(const DevSensor* __restrict__ sens, int64_t N, const int32_t* __restrict__ n_tiles,
                        const int4* __restrict__ rect, const uint32_t* __restrict__ order, const int64_t* __restrict__ offs,
-                       int64_t n_rec, int64_t k_cap, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                       int32_t* __restrict__ big, int32_t* __restrict__ n_big) {
+                       const int64_t* __restrict__ n_vis, int64_t k_cap, uint32_t* __restrict__ keys,
+                       uint32_t* __restrict__ vals, int32_t* __restrict__ big, int32_t* __restrict__ n_big) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_rec) return;
+  if (i >= *n_vis) return;
   uint32_t rec = order[i];
   int n = n_tiles[rec];
   if (n <= 0) return;
@@ -397,10 +413,12 @@ __device__ __forceinline__ int sensor_of_ray(const DevSensor* sens, int count, i
   return lo;
 }
 
-__global__ void k_ray_keys(const DevSensor* __restrict__ sens, int count, int64_t n_rays, int64_t n_tiles,
+// lidar rays [r0, r0 + n) of the call -> (tile, ray id) pairs at [0, n)
+__global__ void k_ray_keys(const DevSensor* __restrict__ sens, int count, int64_t r0, int64_t n, int64_t n_tiles,
                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, SplatStatus* st) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_rays) return;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int64_t r = r0 + q;
   int s = sensor_of_ray(sens, count, r);
   const DevSensor& S = sens[s];
   int64_t j = r - (S.ray_base - sens[0].ray_base);
@@ -415,32 +433,77 @@ __global__ void k_ray_keys(const DevSensor* __restrict__ sens, int count, int64_
     atomicAdd(&st->n_rays_invalid, 1u);
   }
   if (ok && st && fabsf(t) > 0.5f * S.t_rs * (1.0f + 1e-6f) + 1e-9f) atomicAdd(&st->n_rays_time, 1u);
-  keys[r] = tile;
-  vals[r] = (uint32_t)r;
+  keys[q] = tile;
+  vals[q] = (uint32_t)r;
 }
 
-__global__ void k_work_count(const int2* __restrict__ range, int64_t n_bins, int64_t* __restrict__ cnt) {
+__device__ __forceinline__ bool camera_tile(const DevSensor* sens, int count, int64_t t, int64_t n_tiles) {
+  if (t >= n_tiles) return false;
+  int lo = 0, hi = count - 1;
+  const int64_t b0 = sens[0].tile_base;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sens[mid].tile_base - b0 <= t) lo = mid; else hi = mid - 1;
+  }
+  return sens[lo].kind == kCamera;
+}
+
+// work items per bin: one per camera tile, ceil(rays / 256) per lidar tile and for the bin of
+// rays outside every tile (bin n_tiles)
+__global__ void k_work_count(const DevSensor* __restrict__ sens, int count, const int2* __restrict__ range,
+                             int64_t n_tiles, int64_t* __restrict__ cnt) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_bins) return;
+  if (t > n_tiles) return;
+  if (camera_tile(sens, count, t, n_tiles)) {
+    cnt[t] = 1;
+    return;
+  }
   int2 r = range[t];
   int64_t c = r.y - r.x;
   cnt[t] = c > 0 ? (c + SPLAT_RAYS_PER_ITEM - 1) / SPLAT_RAYS_PER_ITEM : 0;
 }
 
-__global__ void k_copy_i64(const int64_t* __restrict__ src, int64_t* __restrict__ dst) { *dst = *src; }
-
-__global__ void k_work_emit(const int2* __restrict__ range, int64_t n_bins, const int64_t* __restrict__ woff,
-                            int64_t work_cap, int2* __restrict__ work, int32_t* __restrict__ n_work) {
+__global__ void k_work_emit(const DevSensor* __restrict__ sens, int count, const int2* __restrict__ range,
+                            int64_t n_tiles, const int64_t* __restrict__ woff, int64_t work_cap,
+                            int2* __restrict__ work, int32_t* __restrict__ n_work) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
-    int64_t tot = woff[n_bins];
+    int64_t tot = woff[n_tiles + 1];
     *n_work = (int32_t)(tot < work_cap ? tot : work_cap);
   }
-  if (t >= n_bins) return;
-  int2 r = range[t];
+  if (t > n_tiles) return;
   int64_t o = woff[t];
+  if (camera_tile(sens, count, t, n_tiles)) {
+    if (o < work_cap) work[o] = make_int2((int)t, 0);
+    return;
+  }
+  int2 r = range[t];
   for (int p = r.x; p < r.y; p += SPLAT_RAYS_PER_ITEM, ++o)
     if (o < work_cap) work[o] = make_int2((int)t, p);
+}
+
+// Longest-processing-time order of the persistent queue: items sorted by descending length of
+// their tile's Gaussian list (key = 0xFFFF - min(length, 0xFFFF), stable).
+__global__ void k_queue_keys(const int2* __restrict__ work, const int32_t* __restrict__ n_work,
+                             const int2* __restrict__ tile_range, int64_t n_tiles, uint32_t* __restrict__ keys,
+                             uint32_t* __restrict__ vals) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *n_work) return;
+  int64_t t = work[i].x;
+  int64_t len = 0;
+  if (t < n_tiles) {
+    int2 r = tile_range[t];
+    len = r.y - r.x;
+  }
+  keys[i] = 0xFFFFu - (uint32_t)(len < 0xFFFF ? len : 0xFFFF);
+  vals[i] = (uint32_t)i;
+}
+
+__global__ void k_queue_gather(const int2* __restrict__ src, const uint32_t* __restrict__ order,
+                               const int32_t* __restrict__ n_work, int2* __restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *n_work) return;
+  dst[i] = src[order[i]];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -463,7 +526,7 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   int64_t max_n = nrec > kc ? nrec : kc;
   max_n = max_n > nr ? max_n : nr;
   int64_t max_blocks = div_up(max_n, kScanTile);
-  for (int i = 0; i < 2; ++i) w.dkeys[i] = (uint32_t*)take(nrec * 4);
+  for (int i = 0; i < 2; ++i) w.dkeys[i] = (uint64_t*)take(nrec * 8);
   for (int i = 0; i < 2; ++i) w.dvals[i] = (uint32_t*)take(nrec * 4);
   w.offs = (int64_t*)take((nrec + 1) * 8);
   w.scan_part = (int64_t*)take((div_up(nrec > n_tiles + 2 ? nrec : n_tiles + 2, kScanTile) + 2) * 8);
@@ -473,10 +536,14 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   w.hist_part = (uint32_t*)take((div_up((int64_t)kRadixBins * max_blocks, kScanTile) + 2) * 4);
   for (int i = 0; i < 2; ++i) w.rkeys[i] = (uint32_t*)take(nr * 4);
   for (int i = 0; i < 2; ++i) w.rvals[i] = (uint32_t*)take(nr * 4);
+  const int64_t wcap = work_capacity(n_tiles, nr) + 1;
+  for (int i = 0; i < 2; ++i) w.qkeys[i] = (uint32_t*)take(wcap * 4);
+  for (int i = 0; i < 2; ++i) w.qvals[i] = (uint32_t*)take(wcap * 4);
+  w.qtmp = (int2*)take(wcap * 8);
   w.wcount = (int64_t*)take((n_tiles + 2) * 8);
   w.wpart = (int64_t*)take((div_up(n_tiles + 2, kScanTile) + 2) * 8);
   w.big = (int32_t*)take(nrec * 4);
-  w.n_big = (int32_t*)take(8 * 4);
+  w.n_big = (int32_t*)take(64);   // n_big, then int64 n_sort at +16 B and n_vis at +24 B
   w.g2d = (float*)take(nrec * 10 * 4);
   w.bytes = off;
   return w;
@@ -487,18 +554,24 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   const int64_t n_rec = (int64_t)v.count * v.n_gauss;
   hipError_t e;
   int64_t* n_sort = (int64_t*)(w.n_big + 4);   // spare slots next to the big-record counter
-  // 1. depth order of the records
-  if (n_rec > 0) {
-    hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, (const int32_t*)p.n_tiles,
-                       (const float2*)p.dv, n_rec, w.dkeys[0], w.dvals[0]);
-  }
-  uint32_t* dk[2] = {w.dkeys[0], w.dkeys[1]};
+  // 1. visible records, compacted in record order, then stably sorted by float64 depth
+  int64_t* n_vis = n_sort + 1;
+  if ((e = device_scan<int64_t>(LoadVisible{p.n_tiles}, n_rec, w.offs, w.scan_part, s)) != hipSuccess) return e;
+  const int64_t nb0 = div_up(n_rec, kScanTile);
+  hipLaunchKernelGGL(k_copy_i64, dim3(1), dim3(1), 0, s, (const int64_t*)(w.scan_part + nb0), n_vis);
+  if (n_rec > 0)
+    hipLaunchKernelGGL(k_compact_visible, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, (const int32_t*)p.n_tiles,
+                       (const unsigned long long*)p.dkey, (const int64_t*)w.offs, n_rec, w.dkeys[0], w.dvals[0]);
+  uint64_t* dk[2] = {w.dkeys[0], w.dkeys[1]};
   uint32_t* dvv[2] = {w.dvals[0], w.dvals[1]};
   int cur = 0;
-  if ((e = radix_sort(dk, dvv, cur, nullptr, n_rec, 32, w.hist, w.hist_part, nullptr, s)) != hipSuccess) return e;
+  if ((e = radix_sort<uint64_t>(dk, dvv, cur, n_vis, n_rec, kDepthKeyShift, kDepthKeyBits, w.hist, w.hist_part,
+                                nullptr, s)) != hipSuccess)
+    return e;
   const uint32_t* order = dvv[cur];
   // 2. slot ranges
-  if ((e = device_scan<int64_t>(LoadTilesByOrder{p.n_tiles, order}, n_rec, w.offs, w.scan_part, s)) != hipSuccess) return e;
+  if ((e = device_scan<int64_t>(LoadTilesByOrder{p.n_tiles, order, n_vis}, n_rec, w.offs, w.scan_part, s)) != hipSuccess)
+    return e;
   int64_t nb = div_up(n_rec, kScanTile);
   hipLaunchKernelGGL(k_finalize_count, dim3(1), dim3(1), 0, s, (const int64_t*)(w.scan_part + nb), L.k_cap, n_sort, st);
   // 3. emit: the final tile-sort pass must land its values in lists->gauss
@@ -510,8 +583,8 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   if ((e = fill<int32_t>(w.n_big, 1, 0, s)) != hipSuccess) return e;
   if (n_rec > 0) {
     hipLaunchKernelGGL(k_emit, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, v.sens, v.n_gauss,
-                       (const int32_t*)p.n_tiles, (const int4*)p.rect, order, (const int64_t*)w.offs, n_rec, L.k_cap,
-                       w.tkeys[0], tv[0], w.big, w.n_big);
+                       (const int32_t*)p.n_tiles, (const int4*)p.rect, order, (const int64_t*)w.offs,
+                       (const int64_t*)n_vis, L.k_cap, w.tkeys[0], tv[0], w.big, w.n_big);
     hipLaunchKernelGGL(k_emit_big, dim3(1024), dim3(256), 0, s, v.sens, v.n_gauss, (const int32_t*)p.n_tiles,
                        (const int4*)p.rect, order, (const int64_t*)w.offs, L.k_cap, w.tkeys[0], tv[0],
                        (const int32_t*)w.big, (const int32_t*)w.n_big);
@@ -519,37 +592,54 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   // 4. stable sort by tile
   uint32_t* tk[2] = {w.tkeys[0], w.tkeys[1]};
   int tcur = 0;
-  if ((e = radix_sort(tk, tv, tcur, n_sort, L.k_cap, tbits, w.hist, w.hist_part, nullptr, s)) != hipSuccess) return e;
+  if ((e = radix_sort<uint32_t>(tk, tv, tcur, n_sort, L.k_cap, 0, tbits, w.hist, w.hist_part, nullptr, s)) != hipSuccess)
+    return e;
   // 5. ranges
   if ((e = fill<int32_t>(L.tile_range, 2 * v.n_tiles, 0, s)) != hipSuccess) return e;
   if (L.k_cap > 0)
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(L.k_cap, 256)), dim3(256), 0, s, (const uint32_t*)tk[tcur],
                        (const int64_t*)n_sort, L.k_cap, (int2*)L.tile_range);
-  // 6. lidar rays and work items
-  if (v.lidar) {
-    const int64_t nr = v.n_rays;
+  // 6. lidar rays -> tiles; work items (lidar chunks, and camera tiles in the batched form)
+  if (v.has_lidar || v.queue) {
     const int64_t bins = v.n_tiles + 1;
+    const int64_t r0 = v.lidar_ray0;
+    const int64_t nr = v.n_rays - r0;
     if ((e = fill<int32_t>(L.ray_range, 2 * bins, 0, s)) != hipSuccess) return e;
     if (nr > 0) {
-      hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)div_up(nr, 256)), dim3(256), 0, s, v.sens, v.count, nr, v.n_tiles,
-                         w.rkeys[0], w.rvals[0], st);
+      hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)div_up(nr, 256)), dim3(256), 0, s, v.sens, v.count, r0, nr,
+                         v.n_tiles, w.rkeys[0], w.rvals[0], st);
       uint32_t* rk[2] = {w.rkeys[0], w.rkeys[1]};
       uint32_t* rv[2] = {w.rvals[0], w.rvals[1]};
       int rcur = 0;
-      if ((e = radix_sort(rk, rv, rcur, nullptr, nr, bits_for(bins), w.hist, w.hist_part, (uint32_t*)L.ray_order, s)) !=
-          hipSuccess)
+      if ((e = radix_sort<uint32_t>(rk, rv, rcur, nullptr, nr, 0, bits_for(bins), w.hist, w.hist_part,
+                                    (uint32_t*)L.ray_order, s)) != hipSuccess)
         return e;
       hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(nr, 256)), dim3(256), 0, s, (const uint32_t*)rk[rcur],
                          (const int64_t*)nullptr, nr, (int2*)L.ray_range);
     }
-    hipLaunchKernelGGL(k_work_count, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, (const int2*)L.ray_range, bins,
-                       w.wcount);
+    hipLaunchKernelGGL(k_work_count, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, v.sens, v.count,
+                       (const int2*)L.ray_range, v.n_tiles, w.wcount);
     if ((e = device_scan<int64_t>(LoadI64{w.wcount}, bins, w.wcount, w.wpart, s)) != hipSuccess) return e;
     // the total lands in wpart[nb]; copy it behind the per-bin offsets for k_work_emit
-    int64_t wnb = div_up(bins, kScanTile);
+    const int64_t wnb = div_up(bins, kScanTile);
     hipLaunchKernelGGL(k_copy_i64, dim3(1), dim3(1), 0, s, (const int64_t*)(w.wpart + wnb), w.wcount + bins);
-    hipLaunchKernelGGL(k_work_emit, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, (const int2*)L.ray_range, bins,
-                       (const int64_t*)w.wcount, L.work_cap, (int2*)L.work, L.n_work);
+    int2* wdst = v.queue ? w.qtmp : (int2*)L.work;
+    hipLaunchKernelGGL(k_work_emit, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, v.sens, v.count,
+                       (const int2*)L.ray_range, v.n_tiles, (const int64_t*)w.wcount, L.work_cap, wdst, L.n_work);
+    if (v.queue) {
+      const int64_t wcap = L.work_cap;
+      hipLaunchKernelGGL(k_queue_keys, dim3((unsigned)div_up(wcap, 256)), dim3(256), 0, s, (const int2*)w.qtmp,
+                         (const int32_t*)L.n_work, (const int2*)L.tile_range, v.n_tiles, w.qkeys[0], w.qvals[0]);
+      uint32_t* qk[2] = {w.qkeys[0], w.qkeys[1]};
+      uint32_t* qv[2] = {w.qvals[0], w.qvals[1]};
+      int qcur = 0;
+      // item count: the scan total (clamped to the capacity by the sort)
+      if ((e = radix_sort<uint32_t>(qk, qv, qcur, w.wcount + bins, wcap, 0, 16, w.hist, w.hist_part, nullptr, s)) !=
+          hipSuccess)
+        return e;
+      hipLaunchKernelGGL(k_queue_gather, dim3((unsigned)div_up(wcap, 256)), dim3(256), 0, s, (const int2*)w.qtmp,
+                         (const uint32_t*)qv[qcur], (const int32_t*)L.n_work, (int2*)L.work);
+    }
   }
   return hipGetLastError();
 }

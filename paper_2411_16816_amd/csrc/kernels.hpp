@@ -25,14 +25,22 @@ struct CallView {
   int64_t n_gauss;
   int64_t n_tiles;         // tiles of the call
   int64_t n_rays;          // rays of the call
-  bool lidar;              // all sensors are lidars (false: all cameras)
+  bool lidar;              // plain lidar call (all sensors are lidars)
+  bool queue;              // batched form: any mix of sensors, persistent queue rasterisers
+  bool has_lidar;          // at least one lidar in the call
+  int64_t lidar_ray0;      // local id of the first lidar ray (cameras precede lidars in a rig)
   int c_max;               // max n_channels over the call
+  int n_cu;                // compute units of the device (persistent grid)
 };
+
+inline int64_t work_capacity(int64_t n_tiles, int64_t n_rays) {
+  return n_tiles + (n_rays + SPLAT_RAYS_PER_ITEM - 1) / SPLAT_RAYS_PER_ITEM + 1;
+}
 
 // ---- workspace carving (sizes in bytes, 256-aligned) ----------------------------------------
 struct Workspace {
   // bin/sort
-  uint32_t* dkeys[2];
+  uint64_t* dkeys[2];     // [n_rec] float64 depth keys of the visible records
   uint32_t* dvals[2];
   int64_t* offs;          // [n_rec + 1] exclusive scan of n_tiles in depth order
   int64_t* scan_part;     // block partials of the int64 scan
@@ -44,6 +52,9 @@ struct Workspace {
   uint32_t* rvals[2];
   int64_t* wcount;        // [n_tiles + 2]
   int64_t* wpart;
+  uint32_t* qkeys[2];     // [work_cap] queue cost keys
+  uint32_t* qvals[2];
+  int2* qtmp;             // [work_cap] unordered work items
   int32_t* big;           // [n_rec] records with many tiles, emitted one wavefront each
   int32_t* n_big;
   // adjoint
@@ -66,5 +77,6 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
                              const SplatTileLists& L, int support, const SplatRenderOut& saved, const float* dF,
                              const float* dD, const float* dA, float* g2d, float* dfeat, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
 }  // namespace splat

@@ -27,9 +27,25 @@ __device__ __forceinline__ void load_gaussian(const SplatGaussians& g, int64_t i
   }
 }
 
+// Depth used to ORDER Gaussians (Sec. 3.2: z of the camera-frame mean; Sec. 3.3: range of the
+// lidar-frame mean), evaluated in float64 from the float32 inputs.  The float32 depth that is
+// blended is unchanged; only the ordering key is exact enough that Gaussians whose float32
+// depths coincide still sort by their true depth.  Positive doubles order like their bits.
+__device__ __forceinline__ unsigned long long depth_key(const DevSensor& S, const float mu[3]) {
+  double m[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    m[i] = (double)S.R[3 * i + 0] * mu[0] + (double)S.R[3 * i + 1] * mu[1] + (double)S.R[3 * i + 2] * mu[2] +
+           (double)S.t[i];
+  double d = (S.kind == kCamera) ? m[2] : sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+  d = d > 0.0 ? d : 0.0;
+  return (unsigned long long)__double_as_longlong(d);
+}
+
 __global__ __launch_bounds__(256) void k_project(const DevSensor* __restrict__ sens, int count, SplatGaussians g,
                                                  float4* __restrict__ mv, float4* __restrict__ cn,
                                                  float4* __restrict__ box, float2* __restrict__ dv,
+                                                 unsigned long long* __restrict__ dkey,
                                                  int4* __restrict__ rect, int32_t* __restrict__ n_tiles,
                                                  SplatStatus* st) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -52,6 +68,7 @@ __global__ __launch_bounds__(256) void k_project(const DevSensor* __restrict__ s
       cn[r] = make_float4(o.conic[0], o.conic[1], o.conic[2], o.o_eff);
       box[r] = make_float4(o.box[0], o.box[1], o.box[2], o.box[3]);
       dv[r] = make_float2(o.depth, o.v_r);
+      dkey[r] = depth_key(sens[k], G.mu);
       rect[r] = make_int4(o.rect[0], o.rect[1], o.rect[2], o.rect[3]);
     }
   }
@@ -102,7 +119,7 @@ hipError_t launch_project(const CallView& v, const SplatGaussians& g, const Spla
                           hipStream_t s) {
   if (g.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_project, dim3((unsigned)div_up(g.n, 256)), dim3(256), 0, s, v.sens, v.count, g, (float4*)p.mv,
-                     (float4*)p.cn, (float4*)p.box, (float2*)p.dv, (int4*)p.rect, p.n_tiles, st);
+                     (float4*)p.cn, (float4*)p.box, (float2*)p.dv, p.dkey, (int4*)p.rect, p.n_tiles, st);
   return hipGetLastError();
 }
 

@@ -89,12 +89,12 @@ struct RayCtx {
   bool invalid_bin;   // lidar work item of rays outside every tile
 };
 
+// Lane setup for one work item: a camera tile (all its pixels) or a chunk of <= 256 rays of a
+// lidar tile starting at position `pos` of ray_order (tile == n_tiles: rays outside every tile).
 template <bool LIDAR>
-__device__ __forceinline__ bool setup_item(const RasterArgs& a, RayCtx& c) {
+__device__ __forceinline__ void setup_ray(const RasterArgs& a, int64_t tile, int pos, RayCtx& c) {
   const int tid = threadIdx.x;
-  int64_t tile;
   if (!LIDAR) {
-    tile = blockIdx.x;
     c.s = sensor_of_tile(a.sens, a.count, tile);
     const DevSensor& S = a.sens[c.s];
     int64_t tl = tile - (S.tile_base - a.sens[0].tile_base);
@@ -111,14 +111,12 @@ __device__ __forceinline__ bool setup_item(const RasterArgs& a, RayCtx& c) {
     c.C = S.n_ch;
     c.invalid_bin = false;
   } else {
-    if ((int64_t)blockIdx.x >= (int64_t)*a.n_work) return false;
-    int2 w = a.work[blockIdx.x];
-    tile = w.x;
     int2 rr = a.ray_range[tile];
-    int64_t p = (int64_t)w.y + tid;
+    int64_t p = (int64_t)pos + tid;
     c.valid = p < rr.y;
     c.invalid_bin = (tile == a.n_tiles);
     int64_t r = c.valid ? (int64_t)a.ray_order[p] : 0;
+    if (!c.valid) r = a.ray_order[pos];   // any ray of the item: keeps the sensor uniform
     c.ray = r;
     c.s = c.invalid_bin ? sensor_of_ray_r(a.sens, a.count, r) : sensor_of_tile(a.sens, a.count, tile);
     const DevSensor& S = a.sens[c.s];
@@ -137,7 +135,6 @@ __device__ __forceinline__ bool setup_item(const RasterArgs& a, RayCtx& c) {
   const int2 tr = a.tile_range[(LIDAR && c.invalid_bin) ? 0 : tile];
   c.start = (LIDAR && c.invalid_bin) ? 0 : tr.x;
   c.end = (LIDAR && c.invalid_bin) ? 0 : tr.y;
-  return true;
 }
 
 template <int CMAX>
@@ -169,13 +166,17 @@ __device__ __forceinline__ void stage_batch(const RasterArgs& a, const RayCtx& c
 // ------------------------------------------------------------------------------------------
 // forward
 // ------------------------------------------------------------------------------------------
+template <int CMAX>
+struct FwdSmem {
+  float4 mv[kBlock], cn[kBlock], box[kBlock];
+  float2 dv[kBlock];
+  float4 f[kBlock * (CMAX / 4)];
+};
+
 template <int CMAX, bool LIDAR, bool TILE>
-__global__ __launch_bounds__(kBlock) void k_raster_fwd(RasterArgs a, FwdOut o) {
-  __shared__ float4 s_mv[kBlock], s_cn[kBlock], s_box[kBlock];
-  __shared__ float2 s_dv[kBlock];
-  __shared__ float4 s_f[kBlock * (CMAX / 4)];
+__device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, int64_t tile, int pos, FwdSmem<CMAX>& sm) {
   RayCtx c;
-  if (!setup_item<LIDAR>(a, c)) return;   // uniform over the workgroup
+  setup_ray<LIDAR>(a, tile, pos, c);
   float T = 1.f, D = 0.f, med = 0.f;
   float F[CMAX];
 #pragma unroll
@@ -186,16 +187,16 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(RasterArgs a, FwdOut o) {
   for (int64_t b0 = c.start; b0 < c.end; b0 += kBlock) {
     if (__syncthreads_count(!done) == 0) break;
     const int64_t b1 = (b0 + kBlock < c.end) ? b0 + kBlock : c.end;
-    stage_batch<CMAX>(a, c, b0, b1, s_mv, s_cn, s_box, s_dv, s_f);
+    stage_batch<CMAX>(a, c, b0, b1, sm.mv, sm.cn, sm.box, sm.dv, sm.f);
     __syncthreads();
     const int nb = (int)(b1 - b0);
     for (int j = 0; j < nb; ++j) {
       if (__ballot(!done) == 0) break;
       if (done) continue;
-      const float4 bx = s_box[j];
+      const float4 bx = sm.box[j];
       const float bxa[4] = {bx.x, bx.y, bx.z, bx.w};
       if (!TILE && !box_contains(LIDAR, c.px, c.py, bxa)) continue;
-      const float4 m = s_mv[j], q = s_cn[j];
+      const float4 m = sm.mv[j], q = sm.cn[j];
       const float mva[4] = {m.x, m.y, m.z, m.w}, cna[4] = {q.x, q.y, q.z, q.w};
       PairEval e;
       eval_pair(LIDAR, c.px, c.py, c.t, mva, cna, e);
@@ -206,11 +207,11 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(RasterArgs a, FwdOut o) {
         continue;
       }
       const float w = e.alpha * T;
-      const float2 d = s_dv[j];
+      const float2 d = sm.dv[j];
       const float gv = LIDAR ? SPLAT_FMA(d.y, c.t, d.x) : d.x;
 #pragma unroll
       for (int c4 = 0; c4 < CMAX / 4; ++c4) {
-        const float4 f = s_f[j * (CMAX / 4) + c4];
+        const float4 f = sm.f[j * (CMAX / 4) + c4];
         F[4 * c4 + 0] = SPLAT_FMA(w, f.x, F[4 * c4 + 0]);
         F[4 * c4 + 1] = SPLAT_FMA(w, f.y, F[4 * c4 + 1]);
         F[4 * c4 + 2] = SPLAT_FMA(w, f.z, F[4 * c4 + 2]);
@@ -225,6 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(RasterArgs a, FwdOut o) {
       last = (int)(b0 + j - c.start) + 1;
     }
   }
+  __syncthreads();   // LDS is reused by the next item of a persistent workgroup
   if (!c.valid) return;
   float* fo = o.feat + c.feat_off;
 #pragma unroll
@@ -237,35 +239,133 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(RasterArgs a, FwdOut o) {
   if (LIDAR && o.median) o.median[c.ray] = med;
 }
 
+// plain form: one workgroup per work item (camera: tile = block; lidar: work[block])
+template <int CMAX, bool LIDAR, bool TILE>
+__global__ __launch_bounds__(kBlock) void k_raster_fwd(RasterArgs a, FwdOut o) {
+  __shared__ FwdSmem<CMAX> sm;
+  if (!LIDAR) {
+    fwd_item<CMAX, false, TILE>(a, o, blockIdx.x, 0, sm);
+  } else {
+    if ((int64_t)blockIdx.x >= (int64_t)a.n_work[0]) return;
+    const int2 w = a.work[blockIdx.x];
+    fwd_item<CMAX, true, TILE>(a, o, w.x, w.y, sm);
+  }
+}
+
+// Fetch the next queue entry for the whole workgroup (persistent kernels).
+__device__ __forceinline__ int next_item(int32_t* counter, int* s_slot) {
+  if (threadIdx.x == 0) *s_slot = atomicAdd(counter, 1);
+  __syncthreads();
+  const int it = *s_slot;
+  __syncthreads();
+  return it;
+}
+
+__device__ __forceinline__ bool item_is_lidar(const RasterArgs& a, int64_t tile) {
+  return tile >= a.n_tiles || a.sens[sensor_of_tile(a.sens, a.count, tile)].kind == kLidar;
+}
+
+// persistent form: workgroups drain the cost-ordered queue of camera tiles and lidar chunks
+template <int CMAX, bool TILE>
+__global__ __launch_bounds__(kBlock) void k_raster_fwd_queue(RasterArgs a, FwdOut o, int32_t* counter) {
+  __shared__ FwdSmem<CMAX> sm;
+  __shared__ int s_slot;
+  const int n_items = a.n_work[0];
+  for (;;) {
+    const int it = next_item(counter, &s_slot);
+    if (it >= n_items) break;
+    const int2 w = a.work[it];
+    if (item_is_lidar(a, w.x)) fwd_item<CMAX, true, TILE>(a, o, w.x, w.y, sm);
+    else fwd_item<CMAX, false, TILE>(a, o, w.x, 0, sm);
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // adjoint
 // ------------------------------------------------------------------------------------------
-template <int CTRL, int ROW_MASK>
+template <int CTRL>
 __device__ __forceinline__ float dpp_f(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
 
-// sum over the 64 lanes; the total is valid in lane 63
-__device__ __forceinline__ float wave_sum_to_63(float v) {
-  v += dpp_f<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
-  v += dpp_f<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
-  v += dpp_f<0x141, 0xf>(v);   // row_half_mirror
-  v += dpp_f<0x140, 0xf>(v);   // row_mirror
-  v += dpp_f<0x142, 0xa>(v);   // row_bcast:15 -> rows 1, 3
-  v += dpp_f<0x143, 0xc>(v);   // row_bcast:31 -> rows 2, 3
-  return v;
+// One level of the in-row butterfly: lanes whose `bit` is 0 keep value i, the others value
+// i + H; each adds its partner's copy, read through a DPP lane permutation that flips `bit`.
+template <int CTRL, int H, int N>
+__device__ __forceinline__ void dpp_level(float (&v)[N], bool bit) {
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const float keep = bit ? v[i + H] : v[i];
+    const float send = bit ? v[i] : v[i + H];
+    v[i] = keep + dpp_f<CTRL>(send);
+  }
 }
+
+// Wavefront reduce-scatter of N values per lane (N = 16, 32 or 64).  On return v[0] of lane l
+// holds the sum over all 64 lanes of value index (l >> (6 - log2 N)).  Levels: lane bit 5 by
+// v_permlane32_swap, bit 4 by v_permlane16_swap, bits 3..0 by DPP row_mirror, row_half_mirror
+// and quad permutations.  About 2.2 N instructions instead of 6 N for N separate reductions.
+template <int N>
+__device__ __forceinline__ float wave_reduce_scatter(float (&v)[N]) {
+  static_assert(N == 16 || N == 32 || N == 64, "N");
+  const int lane = threadIdx.x & 63;
+  constexpr int H1 = N / 2;
+#pragma unroll
+  for (int i = 0; i < H1; ++i) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + H1]), false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  constexpr int H2 = H1 / 2;
+#pragma unroll
+  for (int i = 0; i < H2; ++i) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + H2]), false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  constexpr int H3 = H2 / 2;
+  dpp_level<0x140, H3>(v, (lane >> 3) & 1);   // row_mirror: lane i <-> 15 - i
+  constexpr int H4 = H3 / 2;
+  if constexpr (H4 >= 1) dpp_level<0x141, H4>(v, (lane >> 2) & 1);   // row_half_mirror: i <-> 7 - i
+  else v[0] += dpp_f<0x141>(v[0]);
+  constexpr int H5 = H4 / 2;
+  if constexpr (H5 >= 1) dpp_level<0x4E, H5>(v, (lane >> 1) & 1);    // quad_perm [2,3,0,1]
+  else v[0] += dpp_f<0x4E>(v[0]);
+  constexpr int H6 = H5 / 2;
+  if constexpr (H6 >= 1) dpp_level<0xB1, H6>(v, lane & 1);           // quad_perm [1,0,3,2]
+  else v[0] += dpp_f<0xB1>(v[0]);
+  return v[0];
+}
+
+template <int CMAX>
+struct BwdShape {
+  static constexpr int V = kNV + CMAX;                         // values per (ray, Gaussian)
+  static constexpr int N = V <= 16 ? 16 : (V <= 32 ? 32 : 64); // padded for the reduce-scatter
+  static constexpr int SHIFT = N == 16 ? 2 : (N == 32 ? 1 : 0);
+};
+
+constexpr int kBwdBatch = 128;
+
+template <int CMAX>
+struct BwdSmem {
+  float4 mv[kBwdBatch], cn[kBwdBatch], box[kBwdBatch];
+  float2 dv[kBwdBatch];
+  float4 f[kBwdBatch * (CMAX / 4)];
+  float acc[BwdShape<CMAX>::V][kBwdBatch];
+  int used[kBwdBatch];
+  int maxlast;
+};
 
 template <int CMAX, bool LIDAR, bool TILE>
-__global__ __launch_bounds__(kBlock) void k_raster_bwd(RasterArgs a, BwdIn b) {
-  __shared__ float4 s_mv[kBlock], s_cn[kBlock], s_box[kBlock];
-  __shared__ float2 s_dv[kBlock];
-  __shared__ float4 s_f[kBlock * (CMAX / 4)];
-  __shared__ float s_acc[kNV + CMAX][kBlock];
-  __shared__ int s_used[kBlock];
-  __shared__ int s_maxlast;
+__device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, int64_t tile, int pos, BwdSmem<CMAX>& sm) {
+  using SH = BwdShape<CMAX>;
+  static_assert(SH::V <= 64, "channels");
+  float4* s_mv = sm.mv;
+  float4* s_cn = sm.cn;
+  float4* s_box = sm.box;
+  float2* s_dv = sm.dv;
+  float4* s_f = sm.f;
+  auto& s_acc = sm.acc;
+  int* s_used = sm.used;
   RayCtx c;
-  if (!setup_item<LIDAR>(a, c)) return;
+  setup_ray<LIDAR>(a, tile, pos, c);
   if (LIDAR && c.invalid_bin) return;    // uniform over the workgroup
   const int tid = threadIdx.x, lane = tid & 63;
   float T = 1.f, Tf = 1.f, dD = 0.f, dA = 0.f, bufD = 0.f;
@@ -286,19 +386,21 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(RasterArgs a, BwdIn b) {
     for (int k = 0; k < CMAX; ++k)
       if (k < c.C) dF[k] = g[k];
   }
-  if (tid == 0) s_maxlast = 0;
-#pragma unroll
-  for (int k = 0; k < kNV + CMAX; ++k) s_acc[k][tid] = 0.f;
-  s_used[tid] = 0;
+  if (tid == 0) sm.maxlast = 0;
+  for (int k = tid; k < SH::V * kBwdBatch; k += kBlock) (&s_acc[0][0])[k] = 0.f;
+  if (tid < kBwdBatch) s_used[tid] = 0;
   __syncthreads();
-  if (last_l > 0) atomicMax(&s_maxlast, last_l);
+  if (last_l > 0) atomicMax(&sm.maxlast, last_l);
   __syncthreads();
-  const int64_t n_proc = s_maxlast;
+  const int64_t n_proc = sm.maxlast;
+  __syncthreads();           // everyone has read maxlast before it can be reset by the next item
   if (n_proc == 0) return;   // uniform
   const DevSensor& S = a.sens[c.s];
-  for (int64_t b0 = c.start + ((n_proc - 1) / kBlock) * kBlock; b0 >= c.start; b0 -= kBlock) {
-    const int64_t b1 = (b0 + kBlock < c.start + n_proc) ? b0 + kBlock : c.start + n_proc;
-    stage_batch<CMAX>(a, c, b0, b1, s_mv, s_cn, s_box, s_dv, s_f);
+  const int my_idx = lane >> SH::SHIFT;                        // value this lane holds after the scatter
+  const bool my_store = ((lane & ((1 << SH::SHIFT) - 1)) == 0) && my_idx < SH::V;
+  for (int64_t b0 = c.start + ((n_proc - 1) / kBwdBatch) * kBwdBatch; b0 >= c.start; b0 -= kBwdBatch) {
+    const int64_t b1 = (b0 + kBwdBatch < c.start + n_proc) ? b0 + kBwdBatch : c.start + n_proc;
+    if (tid < kBwdBatch) stage_batch<CMAX>(a, c, b0, b1, s_mv, s_cn, s_box, s_dv, s_f);
     __syncthreads();
     const int nb = (int)(b1 - b0);
     for (int j = nb - 1; j >= 0; --j) {
@@ -316,12 +418,9 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(RasterArgs a, BwdIn b) {
         act = e.alpha >= kAlphaMin;
       }
       if (__ballot(act) == 0) continue;   // uniform over the wavefront
-      float v[kNV];
-      float fg[CMAX];
+      float v[SH::N];
 #pragma unroll
-      for (int k = 0; k < kNV; ++k) v[k] = 0.f;
-#pragma unroll
-      for (int k = 0; k < CMAX; ++k) fg[k] = 0.f;
+      for (int k = 0; k < SH::N; ++k) v[k] = 0.f;
       if (act) {
         const float ra = 1.f / (1.f - e.alpha);
         T = T * ra;                       // transmittance in front of this Gaussian
@@ -334,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(RasterArgs a, BwdIn b) {
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int k = 4 * c4 + u;
-            fg[k] = w * dF[k];
+            v[kNV + k] = w * dF[k];
             acc += (fa[u] - buf[k]) * dF[k];
             buf[k] += e.alpha * (fa[u] - buf[k]);
           }
@@ -360,19 +459,9 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(RasterArgs a, BwdIn b) {
         v[8] = dg;
         v[9] = LIDAR ? dg * c.t : 0.f;
       }
-#pragma unroll
-      for (int k = 0; k < kNV; ++k) {
-        const float r = wave_sum_to_63(v[k]);
-        if (lane == 63) atomicAdd(&s_acc[k][j], r);
-      }
-#pragma unroll
-      for (int k = 0; k < CMAX; ++k) {
-        if (k < c.C) {
-          const float r = wave_sum_to_63(fg[k]);
-          if (lane == 63) atomicAdd(&s_acc[kNV + k][j], r);
-        }
-      }
-      if (lane == 63) s_used[j] = 1;
+      const float r = wave_reduce_scatter<SH::N>(v);
+      if (my_store) atomicAdd(&s_acc[my_idx][j], r);
+      if (lane == 0) s_used[j] = 1;
     }
     __syncthreads();
     if (tid < nb && s_used[tid]) {
@@ -393,6 +482,32 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(RasterArgs a, BwdIn b) {
       s_used[tid] = 0;
     }
     __syncthreads();
+  }
+}
+
+template <int CMAX, bool LIDAR, bool TILE>
+__global__ __launch_bounds__(kBlock) void k_raster_bwd(RasterArgs a, BwdIn b) {
+  __shared__ BwdSmem<CMAX> sm;
+  if (!LIDAR) {
+    bwd_item<CMAX, false, TILE>(a, b, blockIdx.x, 0, sm);
+  } else {
+    if ((int64_t)blockIdx.x >= (int64_t)a.n_work[0]) return;
+    const int2 w = a.work[blockIdx.x];
+    bwd_item<CMAX, true, TILE>(a, b, w.x, w.y, sm);
+  }
+}
+
+template <int CMAX, bool TILE>
+__global__ __launch_bounds__(kBlock) void k_raster_bwd_queue(RasterArgs a, BwdIn b, int32_t* counter) {
+  __shared__ BwdSmem<CMAX> sm;
+  __shared__ int s_slot;
+  const int n_items = a.n_work[0];
+  for (;;) {
+    const int it = next_item(counter, &s_slot);
+    if (it >= n_items) break;
+    const int2 w = a.work[it];
+    if (item_is_lidar(a, w.x)) bwd_item<CMAX, true, TILE>(a, b, w.x, w.y, sm);
+    else bwd_item<CMAX, false, TILE>(a, b, w.x, 0, sm);
   }
 }
 
@@ -436,16 +551,62 @@ static void bwd_dispatch(dim3 grid, hipStream_t s, int support, const RasterArgs
     hipLaunchKernelGGL((k_raster_bwd<CMAX, LIDAR, false>), grid, dim3(kBlock), 0, s, a, b);
 }
 
-static int cmax_bucket(int c) { return c <= 4 ? 4 : c <= 8 ? 8 : c <= 16 ? 16 : c <= 32 ? 32 : 64; }
+// persistent grid: as many workgroups as can be resident at once, capped by the item capacity
+template <typename K>
+static unsigned persistent_grid(K kernel, const CallView& v, int64_t items) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  int64_t g = (int64_t)per_cu * (v.n_cu > 0 ? v.n_cu : 256);
+  if (g > items) g = items;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+template <int CMAX, bool TILE>
+static void fwd_queue_launch(const CallView& v, int64_t items, hipStream_t s, const RasterArgs& a, const FwdOut& o,
+                             int32_t* counter) {
+  auto k = k_raster_fwd_queue<CMAX, TILE>;
+  hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items)), dim3(kBlock), 0, s, a, o, counter);
+}
+
+template <int CMAX, bool TILE>
+static void bwd_queue_launch(const CallView& v, int64_t items, hipStream_t s, const RasterArgs& a, const BwdIn& b,
+                             int32_t* counter) {
+  auto k = k_raster_bwd_queue<CMAX, TILE>;
+  hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items)), dim3(kBlock), 0, s, a, b, counter);
+}
+
+static int cmax_bucket(int c) { return c <= 4 ? 4 : c <= 8 ? 8 : c <= 16 ? 16 : c <= 32 ? 32 : 48; }
 
 hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
                              const SplatTileLists& L, int support, const SplatRenderOut& out, hipStream_t s) {
   RasterArgs a = make_args(v, g, p, L);
   FwdOut o{out.feat, out.depth, out.alpha, out.t_final, out.last, out.median};
+  const int cm = cmax_bucket(v.c_max);
+  if (v.queue) {
+    const int64_t items = L.work_cap;
+    if (items <= 0) return hipSuccess;
+    int32_t* counter = L.n_work + 1;
+    hipError_t e = launch_fill_i32(counter, 1, 0, s);
+    if (e != hipSuccess) return e;
+    const bool tile = support == SPLAT_SUPPORT_TILE;
+#define FWDQ_CASE(CM)                                                         \
+  case CM:                                                                    \
+    if (tile) fwd_queue_launch<CM, true>(v, items, s, a, o, counter);         \
+    else fwd_queue_launch<CM, false>(v, items, s, a, o, counter);             \
+    break;
+    switch (cm) {
+      FWDQ_CASE(4)
+      FWDQ_CASE(8)
+      FWDQ_CASE(16)
+      FWDQ_CASE(32)
+      FWDQ_CASE(48)
+    }
+#undef FWDQ_CASE
+    return hipGetLastError();
+  }
   const int64_t items = v.lidar ? L.work_cap : v.n_tiles;
   if (items <= 0) return hipSuccess;
   dim3 grid((unsigned)items);
-  const int cm = cmax_bucket(v.c_max);
 #define FWD_CASE(CM)                                           \
   case CM:                                                     \
     if (v.lidar) fwd_dispatch<CM, true>(grid, s, support, a, o); \
@@ -456,7 +617,7 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
     FWD_CASE(8)
     FWD_CASE(16)
     FWD_CASE(32)
-    FWD_CASE(64)
+    FWD_CASE(48)
   }
 #undef FWD_CASE
   return hipGetLastError();
@@ -467,10 +628,32 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
                              const float* dD, const float* dA, float* g2d, float* dfeat, hipStream_t s) {
   RasterArgs a = make_args(v, g, p, L);
   BwdIn b{saved.t_final, saved.last, dF, dD, dA, g2d, dfeat};
+  const int cm = cmax_bucket(v.c_max);
+  if (v.queue) {
+    const int64_t items = L.work_cap;
+    if (items <= 0) return hipSuccess;
+    int32_t* counter = L.n_work + 1;
+    hipError_t e = launch_fill_i32(counter, 1, 0, s);
+    if (e != hipSuccess) return e;
+    const bool tile = support == SPLAT_SUPPORT_TILE;
+#define BWDQ_CASE(CM)                                                         \
+  case CM:                                                                    \
+    if (tile) bwd_queue_launch<CM, true>(v, items, s, a, b, counter);         \
+    else bwd_queue_launch<CM, false>(v, items, s, a, b, counter);             \
+    break;
+    switch (cm) {
+      BWDQ_CASE(4)
+      BWDQ_CASE(8)
+      BWDQ_CASE(16)
+      BWDQ_CASE(32)
+      BWDQ_CASE(48)
+    }
+#undef BWDQ_CASE
+    return hipGetLastError();
+  }
   const int64_t items = v.lidar ? L.work_cap : v.n_tiles;
   if (items <= 0) return hipSuccess;
   dim3 grid((unsigned)items);
-  const int cm = cmax_bucket(v.c_max);
 #define BWD_CASE(CM)                                           \
   case CM:                                                     \
     if (v.lidar) bwd_dispatch<CM, true>(grid, s, support, a, b); \
@@ -481,7 +664,7 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
     BWD_CASE(8)
     BWD_CASE(16)
     BWD_CASE(32)
-    BWD_CASE(64)
+    BWD_CASE(48)
   }
 #undef BWD_CASE
   return hipGetLastError();

@@ -15,6 +15,7 @@ namespace splat {
 
 constexpr float kTwoPi = 6.28318530717958647692f;   // float32 nearest to 2 pi (0x40C90FDB)
 constexpr float kPi = 3.14159265358979323846f;
+constexpr float kInvTwoPi = 0.159154943091895335769f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTStop = 1e-4f;
@@ -528,8 +529,10 @@ HD void eval_pair(bool lidar, float px, float py, float t, const float mv[4], co
   float dx = px - mx;
   float dy = py - my;
   if (lidar) {
-    if (dx >= kPi) dx -= kTwoPi;
-    else if (dx < -kPi) dx += kTwoPi;
+    // azimuth difference reduced to [-pi, pi): the rolling-shutter shift v t of a Gaussian close
+    // to the sensor can span several turns, so the reduction is modular, not a single wrap
+    const float k = floorf((dx + kPi) * kInvTwoPi);
+    dx = SPLAT_FMA(-k, kTwoPi, dx);
   }
   float q = SPLAT_FMA(cn[0] * dx, dx, cn[2] * dy * dy);
   float sigma = SPLAT_FMA(cn[1] * dx, dy, 0.5f * q);

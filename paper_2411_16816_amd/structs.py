@@ -50,7 +50,7 @@ class SplatRigLayout(C.Structure):
 
 class SplatProjected(C.Structure):
     _fields_ = [("n_records", C.c_int64), ("mv", C.c_void_p), ("cn", C.c_void_p), ("box", C.c_void_p),
-                ("dv", C.c_void_p), ("rect", C.c_void_p), ("n_tiles", C.c_void_p)]
+                ("dv", C.c_void_p), ("dkey", C.c_void_p), ("rect", C.c_void_p), ("n_tiles", C.c_void_p)]
 
 
 class SplatTileLists(C.Structure):
