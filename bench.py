@@ -6,8 +6,14 @@ Workload (default): a 128-beam x 2048-azimuth spinning lidar (100 ms rolling-shu
 synthetic Gaussians in a 300 x 300 x 6 m box; forward + backward (projection, binning, depth
 sort, compositing, adjoint) every step.  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line.  `value` is rays (pixels + lidar rays) per second of whole fwd+bwd steps
-in Mrays/s.  A step = for every sensor: project -> bin/sort -> rasterize_fwd -> rasterize_bwd.
+Two forms of the same step are timed:
+  plain   -- per-sensor calls (project -> bin/sort -> rasterize_fwd -> rasterize_bwd per sensor);
+  batched -- one call per stage for both sensors (one projection launch, one bin/sort building
+             a cost-ordered work queue, persistent forward and adjoint rasterisers).
+Both are checked against the FP64 oracle on sampled rays before timing.
+
+Prints one JSON line.  `value` is the batched form's rays (pixels + lidar rays) per second of
+whole fwd+bwd steps, in Mrays/s; the plain form is reported beside it.
 """
 from __future__ import annotations
 
@@ -27,9 +33,13 @@ METRIC = "Mrays/s fwd+bwd, 128x2048 lidar + 1080p camera; batched vs plain at 1e
 
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3            # packed FMA datasheet figure
-CU, LANES_PER_CU_CLK, CLOCK_GHZ = 256, 64, 2.4
-PEAK_VALU_TLANEOPS = CU * LANES_PER_CU_CLK * CLOCK_GHZ / 1e3   # 39.3 T lane-instructions / s
+PEAK_FP32_TFLOPS = 157.3            # vector FP32, datasheet (packed FMA)
+# algorithmic FP32 work per evaluated (ray, Gaussian) pair of the forward compositing loop:
+# Delta (6), sigma (9), exp (1), alpha (1), transmittance (2), weight (1), feature and depth
+# blends (2 C + 2), plus the lidar range correction (2) and azimuth reduction (3);
+# the adjoint recomputes the pair and back-propagates through it: about 3x the forward.
+FLOP_PER_PAIR = {"camera": 22 + 2 * 16, "lidar": 22 + 2 * 8 + 5}
+BWD_FACTOR = 3.0
 
 
 def parse():
@@ -38,7 +48,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=2_000_000, help="Gaussians")
-    ap.add_argument("--mode", default="plain", choices=["plain"])
+    ap.add_argument("--modes", default="plain,batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=64, help="rays per sensor in the CPU oracle sample")
@@ -68,131 +78,148 @@ def main():
     dev = "cuda"
     G = B.GaussTensors.from_numpy(g, dev)
     rig = B.Rig([cam], [lid], dev)
-    passes = [B.SensorPass(rig, 0, 1, g.n, 1, dev), B.SensorPass(rig, 1, 1, g.n, 1, dev)]
-    Ks = [sp.fit_capacity(G, 1.15) for sp in passes]
-    log(f"intersections: camera {Ks[0]}, lidar {Ks[1]}")
-    # upstream gradients (seeded), resident on the device
-    ups = []
-    for k, sp in enumerate(passes):
-        dF, dD, dA = S.upstream_grads(1000 + k, sp.n_rays, rig.sensors[k].n_channels)
-        ups.append(tuple(torch.from_numpy(a.reshape(-1)).to(dev) for a in (dF, dD, dA)))
-    grads = B.zeros_like_grads(G)
     stream = torch.cuda.current_stream()
     stages = ["project", "bin_sort", "raster_fwd", "raster_bwd"]
-
-    def step(events=None):
+    results = {}
+    for mode in args.modes.split(","):
+        if mode == "plain":
+            passes = [B.SensorPass(rig, 0, 1, g.n, 1, dev), B.SensorPass(rig, 1, 1, g.n, 1, dev)]
+        else:
+            passes = [B.SensorPass(rig, 0, 2, g.n, 1, dev, batched=True)]
+        Ks = [sp.fit_capacity(G, 1.15) for sp in passes]
+        ups = []
         for k, sp in enumerate(passes):
-            ev = events[k] if events is not None else None
-            if ev: ev["project"][0].record(stream)
-            sp.project(G)
-            if ev: ev["project"][1].record(stream); ev["bin_sort"][0].record(stream)
-            sp.bin_sort()
-            if ev: ev["bin_sort"][1].record(stream); ev["raster_fwd"][0].record(stream)
-            sp.raster_fwd(G)
-            if ev: ev["raster_fwd"][1].record(stream); ev["raster_bwd"][0].record(stream)
-            sp.raster_bwd(G, *ups[k], grads)
-            if ev: ev["raster_bwd"][1].record(stream)
+            dF, dD, dA = S.upstream_grads(1000 + k, sp.n_rays, 1)
+            dF = np.random.default_rng(1100 + k).normal(size=sp.n_feat).astype(np.float32)
+            ups.append(tuple(torch.from_numpy(a.reshape(-1)).to(dev) for a in (dF, dD, dA)))
+        grads = B.zeros_like_grads(G)
 
-    for sp in passes:
-        sp.status.zero_()
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    for k, sp in enumerate(passes):
-        st = B.read_status(sp.status)
-        if st.overflow:
-            raise SystemExit(f"intersection overflow on sensor {k}: need {st.n_isect}, have {st.k_cap}")
+        def step(events=None):
+            for k, sp in enumerate(passes):
+                ev = events[k] if events is not None else None
+                if ev: ev["project"][0].record(stream)
+                sp.project(G)
+                if ev: ev["project"][1].record(stream); ev["bin_sort"][0].record(stream)
+                sp.bin_sort()
+                if ev: ev["bin_sort"][1].record(stream); ev["raster_fwd"][0].record(stream)
+                sp.raster_fwd(G)
+                if ev: ev["raster_fwd"][1].record(stream); ev["raster_bwd"][0].record(stream)
+                sp.raster_bwd(G, *ups[k], grads)
+                if ev: ev["raster_bwd"][1].record(stream)
 
-    # ---- parity on sampled rays, same launch configuration as the timed steps -------------
-    parity = None
-    if not (args.no_parity or args.profile_steps):
-        parity = check_parity(passes, rig, g, torch)
-        log(f"parity: {parity}")
+        for sp in passes:
+            sp.status.zero_()
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        for k, sp in enumerate(passes):
+            st = B.read_status(sp.status)
+            if st.overflow:
+                raise SystemExit(f"{mode}: intersection overflow on pass {k}: need {st.n_isect}, have {st.k_cap}")
+        parity = None
+        if not (args.no_parity or args.profile_steps):
+            parity = check_parity(passes, rig, g)
+            log(f"{mode} parity: {parity}")
+        mk = lambda: torch.cuda.Event(enable_timing=True)
+        evs = [[{s: (mk(), mk()) for s in stages} for _ in passes] for _ in range(args.steps)]
+        start, end = mk(), mk()
+        torch.cuda.synchronize()
+        start.record(stream)
+        for i in range(args.steps):
+            step(evs[i])
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end) / args.steps
+        rays = sum(sp.n_rays for sp in passes)
+        names = ["camera", "lidar"] if mode == "plain" else ["both"]
+        stage_ms = {f"{s}_{names[k]}": float(np.mean([e[k][s][0].elapsed_time(e[k][s][1]) for e in evs]))
+                    for k in range(len(passes)) for s in stages}
+        # evaluated pairs (one extra forward with the counter on, outside the timed region)
+        pairs = []
+        for sp in passes:
+            sp.status.zero_()
+            sp.raster_fwd(G, count_pairs=True)
+        torch.cuda.synchronize()
+        pairs = [int(B.read_status(sp.status).n_pairs) for sp in passes]
+        results[mode] = dict(ms=ms, value=rays / (ms * 1e-3) / 1e6, stage_ms=stage_ms, parity=parity, K=Ks,
+                             pairs=pairs, rays=rays)
+        log(f"{mode}: {ms:.3f} ms/step, {results[mode]['value']:.1f} Mrays/s; stages "
+            + json.dumps({k: round(v, 4) for k, v in stage_ms.items()}) + f"; pairs {pairs}")
+        del passes, grads
 
-    # ---- timed region ----------------------------------------------------------------------
-    mk = lambda: torch.cuda.Event(enable_timing=True)
-    evs = [[{s: (mk(), mk()) for s in stages} for _ in passes] for _ in range(args.steps)]
-    start, end = mk(), mk()
-    torch.cuda.synchronize()
-    start.record(stream)
-    for i in range(args.steps):
-        step(evs[i])
-    end.record(stream)
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(end)
-    ms = total_ms / args.steps
-    rays = sum(sp.n_rays for sp in passes)
-    value = rays / (ms * 1e-3) / 1e6
-    stage_ms = {f"{s}_{['camera', 'lidar'][k]}": float(np.mean([e[k][s][0].elapsed_time(e[k][s][1]) for e in evs]))
-                for k in range(len(passes)) for s in stages}
-    log("stage ms:", json.dumps({k: round(v, 4) for k, v in stage_ms.items()}))
-
-    # ---- roofline of the dominant stage ----------------------------------------------------
-    roof = roofline(stage_ms, passes, rig, Ks)
-
+    main_mode = "batched" if "batched" in results else "plain"
+    R = results[main_mode]
+    roof = roofline(results)
     cpu = None
     if not (args.no_cpu_baseline or args.profile_steps):
         cpu = cpu_baseline(g, cam, lid, args.cpu_rays)
-
     out = {
-        "metric": METRIC, "value": round(value, 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": round(R["value"], 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(R["ms"], 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "lidar 128x2048 (100 ms RS, 15 m/s ego) + 1920x1080 RS camera, 2M Gaussians, fwd+bwd",
-                   "mode": args.mode, "gaussians": g.n, "rays_per_step": rays,
-                   "intersections": {"camera": Ks[0], "lidar": Ks[1]}},
-        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+                   "mode": main_mode, "gaussians": g.n, "rays_per_step": R["rays"]},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "parity": parity,
+        "modes": {m: {"value": round(r["value"], 3), "ms_per_step": round(r["ms"], 4),
+                      "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
+                      "intersections": r["K"], "evaluated_pairs": r["pairs"], "parity": r["parity"]}
+                  for m, r in results.items()},
     }
+    if "plain" in results and "batched" in results:
+        out["batched_over_plain"] = round(results["batched"]["value"] / results["plain"]["value"], 4)
     print(json.dumps(out), flush=True)
 
 
-def check_parity(passes, rig, g, torch):
+def check_parity(passes, rig, g):
     """Sampled-ray parity of the timed configuration against the FP64 oracle (1e-4 rel, 1e-5 abs)."""
     from oracle import render as rd
     res = {}
     rng = np.random.default_rng(7)
-    for k, sp in enumerate(passes):
-        sensor = rig.sensors[k]
-        idx = np.sort(rng.choice(sp.n_rays, size=48, replace=False))
-        o = sp.outputs()
-        C = sensor.n_channels
-        F = o["feat"].reshape(-1, C)[idx].cpu().numpy()
-        D = o["depth"][idx].cpu().numpy()
-        A = o["alpha"][idx].cpu().numpy()
-        ref = rd.render_sensor(g, sensor, idx)
-        ok = ~ref["near"]
-        worst = 0.0
-        for a, r in ((F, ref["F"].numpy()), (D, ref["D"].numpy()), (A, ref["A"].numpy())):
-            a, r = a[ok], r[ok]
-            err = np.abs(a - r) / (1e-5 + 1e-4 * np.abs(r))
-            worst = max(worst, float(err.max()) if err.size else 0.0)
-        res[["camera", "lidar"][k]] = {"rays": int(len(idx)), "near_excluded": int((~ok).sum()),
-                                       "max_err_over_tol": round(worst, 4), "pass": worst <= 1.0}
+    for sp in passes:
+        for k in range(sp.count):
+            sensor = rig.sensors[sp.first + k]
+            rs, fs, C = sp.sensor_slices(k)
+            n = rs.stop - rs.start
+            idx = np.sort(rng.choice(n, size=48, replace=False))
+            o = sp.outputs()
+            F = o["feat"][fs].reshape(-1, C)[idx].cpu().numpy()
+            D = o["depth"][rs][idx].cpu().numpy()
+            A = o["alpha"][rs][idx].cpu().numpy()
+            ref = rd.render_sensor(g, sensor, idx)
+            ok = ~ref["near"]
+            worst = 0.0
+            for a, r in ((F, ref["F"].numpy()), (D, ref["D"].numpy()), (A, ref["A"].numpy())):
+                a, r = a[ok], r[ok]
+                err = np.abs(a - r) / (1e-5 + 1e-4 * np.abs(r))
+                worst = max(worst, float(err.max()) if err.size else 0.0)
+            kind = "camera" if hasattr(sensor, "fx") else "lidar"
+            res[kind] = {"rays": int(len(idx)), "near_excluded": int((~ok).sum()),
+                         "max_err_over_tol": round(worst, 4), "pass": bool(worst <= 1.0)}
     return res
 
 
-def roofline(stage_ms, passes, rig, Ks):
-    """HBM roofline of the bin/sort stage (integer, bandwidth-bound work).  Algorithmic bytes:
-    per record 8 B (depth key + id) read and written for each of 4 depth-sort passes; per
-    intersection 8 B emitted, 2 x 16 B for each of the tile-sort passes, 8 B for ranges."""
-    best = None
-    for k, sp in enumerate(passes):
-        n_rec = sp.count * sp.n_gauss
-        K = Ks[k]
-        tile_bits = max(1, int(math.ceil(math.log2(max(2, sp.n_tiles)))))
-        passes_t = (tile_bits + 7) // 8
-        algo = n_rec * (4 * 16 + 8 + 4) + K * (8 + passes_t * 16 + 8)
-        t = stage_ms[f"bin_sort_{['camera', 'lidar'][k]}"] * 1e-3
-        gbs = algo / t / 1e9
-        if best is None or t > best[1]:
-            best = (k, t, gbs, algo)
-    k, t, gbs, algo = best
-    return {"bound": "hbm", "kernel": f"bin_sort_{['camera', 'lidar'][k]}", "achieved": round(gbs, 2),
-            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
-            "algorithmic_bytes": int(algo)}
+def roofline(results):
+    """VALU roofline of the dominant stage, the adjoint call (raster adjoint + the projection
+    adjoint and a zero fill in the same call, so the achieved rate is a lower bound for the
+    raster adjoint kernel).  Algorithmic FLOP = evaluated pairs x FLOP per pair x 3."""
+    mode = "batched" if "batched" in results else "plain"
+    r = results[mode]
+    plain = results.get("plain", r)
+    pc = plain["pairs"]
+    if len(pc) == 2:
+        flop_fwd = pc[0] * FLOP_PER_PAIR["camera"] + pc[1] * FLOP_PER_PAIR["lidar"]
+    else:
+        flop_fwd = pc[0] * 0.5 * (FLOP_PER_PAIR["camera"] + FLOP_PER_PAIR["lidar"])
+    flop_bwd = BWD_FACTOR * flop_fwd
+    t_bwd = sum(v for k, v in r["stage_ms"].items() if k.startswith("raster_bwd")) * 1e-3
+    t_fwd = sum(v for k, v in r["stage_ms"].items() if k.startswith("raster_fwd")) * 1e-3
+    ach = flop_bwd / t_bwd / 1e12
+    return {"bound": "alu", "kernel": f"rasterize_bwd ({mode})", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "algorithmic_flop": int(flop_bwd), "evaluated_pairs": int(sum(pc)),
+            "forward": {"kernel": f"rasterize_fwd ({mode})", "achieved": round(flop_fwd / t_fwd / 1e12, 3),
+                        "frac": round(flop_fwd / t_fwd / 1e12 / PEAK_FP32_TFLOPS, 4)}}
 
 
 def cpu_baseline(g, cam, lid, n_rays):

@@ -64,6 +64,9 @@ typedef struct SplatStatus {
   unsigned int n_nonfinite;       /* projections culled because of non-finite values           */
   unsigned int n_rays_invalid;    /* lidar rays outside [0, 2pi) x [b_0, b_M): output zeros    */
   unsigned int n_rays_time;       /* lidar rays with |t| > t_rs / 2 (still rendered)           */
+  unsigned long long n_pairs;     /* (ray, Gaussian) pairs the forward rasterisers evaluated
+                                     (box test passed, alpha computed); counted when the
+                                     forward call is given a status                          */
 } SplatStatus;
 
 /* Gaussians (Sec. 3.1).  Device arrays. */
@@ -238,7 +241,7 @@ int splat_bin_sort_lidar(const SplatRig* rig, int32_t first, int32_t count, int6
  * 1/255 is skipped; blending stops before a Gaussian that would take T below 1e-4. */
 int splat_rasterize_fwd_camera(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
                                const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
-                               const SplatRenderOut* out, void* stream);
+                               const SplatRenderOut* out, SplatStatus* status, void* stream);
 int splat_rasterize_fwd_lidar(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
                               const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
                               const SplatRenderOut* out, SplatStatus* status, void* stream);
@@ -257,7 +260,7 @@ int splat_bin_sort(const SplatRig* rig, int32_t first, int32_t count, int64_t n_
                    SplatStatus* status, void* stream);
 int splat_rasterize_fwd(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
                         const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
-                        const SplatRenderOut* out, void* stream);
+                        const SplatRenderOut* out, SplatStatus* status, void* stream);
 int splat_rasterize_bwd(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
                         const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
                         const SplatRenderOut* saved, const float* d_feat, const float* d_depth,

@@ -46,13 +46,13 @@ def _declare(lib):
         "splat_project_lidar": (C.c_int, [vp, vp, i32, i32, vp, vp, vp]),
         "splat_bin_sort_camera": (C.c_int, [vp, i32, i32, i64, vp, vp, vp, C.c_size_t, vp, vp]),
         "splat_bin_sort_lidar": (C.c_int, [vp, i32, i32, i64, vp, vp, vp, C.c_size_t, vp, vp]),
-        "splat_rasterize_fwd_camera": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp]),
+        "splat_rasterize_fwd_camera": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp]),
         "splat_rasterize_fwd_lidar": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp]),
         "splat_rasterize_bwd_camera": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
         "splat_rasterize_bwd_lidar": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
         "splat_project": (C.c_int, [vp, vp, i32, i32, vp, vp, vp]),
         "splat_bin_sort": (C.c_int, [vp, i32, i32, i64, vp, vp, vp, C.c_size_t, vp, vp]),
-        "splat_rasterize_fwd": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp]),
+        "splat_rasterize_fwd": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp]),
         "splat_rasterize_bwd": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
@@ -281,20 +281,22 @@ class SensorPass:
                  C.byref(self.lists_struct()), C.c_void_p(self.ws_ptr), self.ws_bytes, _ptr(self.status),
                  _stream(stream)), "splat_bin_sort")
 
-    def raster_fwd(self, g: GaussTensors, support=BOX, stream=None):
+    def raster_fwd(self, g: GaussTensors, support=BOX, stream=None, count_pairs: bool = False):
+        st_ = _ptr(self.status) if count_pairs else None
         if self.batched:
             check(self.lib.splat_rasterize_fwd(C.byref(g.struct()), self.rig.handle, self.first, self.count,
                                                C.byref(self.proj_struct()), C.byref(self.lists_struct()), support,
-                                               C.byref(self.out_struct()), _stream(stream)), "splat_rasterize_fwd")
+                                               C.byref(self.out_struct()), st_, _stream(stream)),
+                  "splat_rasterize_fwd")
         elif self.lidar:
             check(self.lib.splat_rasterize_fwd_lidar(C.byref(g.struct()), self.rig.handle, self.first, self.count,
                                                      C.byref(self.proj_struct()), C.byref(self.lists_struct()),
-                                                     support, C.byref(self.out_struct()), _ptr(self.status),
+                                                     support, C.byref(self.out_struct()), st_,
                                                      _stream(stream)), "splat_rasterize_fwd_lidar")
         else:
             check(self.lib.splat_rasterize_fwd_camera(C.byref(g.struct()), self.rig.handle, self.first, self.count,
                                                       C.byref(self.proj_struct()), C.byref(self.lists_struct()),
-                                                      support, C.byref(self.out_struct()), _stream(stream)),
+                                                      support, C.byref(self.out_struct()), st_, _stream(stream)),
                   "splat_rasterize_fwd_camera")
 
     def raster_bwd(self, g: GaussTensors, dF, dD, dA, grads: GaussTensors, support=BOX, stream=None):

@@ -231,7 +231,7 @@ static int bin_sort_impl(const SplatRig* r, int32_t first, int32_t count, int ki
 
 static int raster_fwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count, int kind,
                            const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
-                           const SplatRenderOut* out, void* stream) {
+                           const SplatRenderOut* out, SplatStatus* st, void* stream) {
   CallView v;
   int rc = make_view(r, first, count, kind, g ? g->n : -1, v);
   if (rc) return rc;
@@ -239,7 +239,7 @@ static int raster_fwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t f
   if ((rc = check_gaussians(g, v)) || (rc = check_proj(proj, v)) || (rc = check_lists(lists, v)) ||
       (rc = check_out(out, v)))
     return rc;
-  return dev_err(launch_raster_fwd(v, *g, *proj, *lists, support, *out, (hipStream_t)stream));
+  return dev_err(launch_raster_fwd(v, *g, *proj, *lists, support, *out, st, (hipStream_t)stream));
 }
 
 static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count, int kind,
@@ -282,8 +282,8 @@ int splat_bin_sort(const SplatRig* r, int32_t first, int32_t count, int64_t n_ga
 }
 int splat_rasterize_fwd(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,
                         const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
-                        const SplatRenderOut* out, void* stream) {
-  return raster_fwd_impl(g, r, first, count, -1, proj, lists, support, out, stream);
+                        const SplatRenderOut* out, SplatStatus* st, void* stream) {
+  return raster_fwd_impl(g, r, first, count, -1, proj, lists, support, out, st, stream);
 }
 int splat_rasterize_bwd(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,
                         const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
@@ -313,14 +313,13 @@ int splat_bin_sort_lidar(const SplatRig* r, int32_t first, int32_t count, int64_
 }
 int splat_rasterize_fwd_camera(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,
                                const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
-                               const SplatRenderOut* out, void* stream) {
-  return raster_fwd_impl(g, r, first, count, kCamera, proj, lists, support, out, stream);
+                               const SplatRenderOut* out, SplatStatus* st, void* stream) {
+  return raster_fwd_impl(g, r, first, count, kCamera, proj, lists, support, out, st, stream);
 }
 int splat_rasterize_fwd_lidar(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,
                               const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
                               const SplatRenderOut* out, SplatStatus* st, void* stream) {
-  (void)st;
-  return raster_fwd_impl(g, r, first, count, kLidar, proj, lists, support, out, stream);
+  return raster_fwd_impl(g, r, first, count, kLidar, proj, lists, support, out, st, stream);
 }
 int splat_rasterize_bwd_camera(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count,
                                const SplatProjected* proj, const SplatTileLists* lists, int32_t support,

@@ -72,7 +72,8 @@ hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const 
 hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const SplatTileLists& L, const Workspace& w,
                            SplatStatus* st, hipStream_t s);
 hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
-                             const SplatTileLists& L, int support, const SplatRenderOut& o, hipStream_t s);
+                             const SplatTileLists& L, int support, const SplatRenderOut& o, SplatStatus* st,
+                             hipStream_t s);
 hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
                              const SplatTileLists& L, int support, const SplatRenderOut& saved, const float* dF,
                              const float* dD, const float* dA, float* g2d, float* dfeat, hipStream_t s);

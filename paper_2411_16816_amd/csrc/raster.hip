@@ -45,6 +45,7 @@ struct FwdOut {
   float* t_final;
   int32_t* last;
   float* median;
+  unsigned long long* n_pairs;   // evaluated-pair counter, or null
 };
 
 struct BwdIn {
@@ -182,6 +183,7 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
 #pragma unroll
   for (int k = 0; k < CMAX; ++k) F[k] = 0.f;
   int last = 0;
+  unsigned pairs = 0;
   bool done = !c.valid;
   bool med_set = false;
   for (int64_t b0 = c.start; b0 < c.end; b0 += kBlock) {
@@ -200,6 +202,7 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
       const float mva[4] = {m.x, m.y, m.z, m.w}, cna[4] = {q.x, q.y, q.z, q.w};
       PairEval e;
       eval_pair(LIDAR, c.px, c.py, c.t, mva, cna, e);
+      ++pairs;
       if (e.alpha < kAlphaMin) continue;
       const float Tn = T * (1.f - e.alpha);
       if (Tn < kTStop) {
@@ -227,6 +230,12 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
     }
   }
   __syncthreads();   // LDS is reused by the next item of a persistent workgroup
+  if (o.n_pairs) {
+    unsigned long long wp = pairs;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) wp += __shfl_xor(wp, d, 64);
+    if ((threadIdx.x & 63) == 0 && wp) atomicAdd(o.n_pairs, wp);
+  }
   if (!c.valid) return;
   float* fo = o.feat + c.feat_off;
 #pragma unroll
@@ -578,9 +587,10 @@ static void bwd_queue_launch(const CallView& v, int64_t items, hipStream_t s, co
 static int cmax_bucket(int c) { return c <= 4 ? 4 : c <= 8 ? 8 : c <= 16 ? 16 : c <= 32 ? 32 : 48; }
 
 hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
-                             const SplatTileLists& L, int support, const SplatRenderOut& out, hipStream_t s) {
+                             const SplatTileLists& L, int support, const SplatRenderOut& out, SplatStatus* st,
+                             hipStream_t s) {
   RasterArgs a = make_args(v, g, p, L);
-  FwdOut o{out.feat, out.depth, out.alpha, out.t_final, out.last, out.median};
+  FwdOut o{out.feat, out.depth, out.alpha, out.t_final, out.last, out.median, st ? &st->n_pairs : nullptr};
   const int cm = cmax_bucket(v.c_max);
   if (v.queue) {
     const int64_t items = L.work_cap;
