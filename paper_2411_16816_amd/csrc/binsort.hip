@@ -217,43 +217,82 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
   hist[(int64_t)tid * nb + blockIdx.x] = cnt[tid];
 }
 
+// Stable scatter of one block tile (4096 keys).  Every key is ranked inside the block by
+// digit (64-lane ballot matching, per-wave counts, running counts per digit), staged in LDS in
+// digit order, and written out so that consecutive lanes write consecutive addresses of a
+// digit's output run (coalesced), at the block's global digit offsets from the scanned
+// histogram.
 template <typename K>
 __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                        K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                        const int64_t* n_ptr, int64_t n_cap, int shift, int bits,
                                                        const uint32_t* __restrict__ hist, int64_t nb) {
+  __shared__ K s_k[kScanTile];
+  __shared__ uint32_t s_v[kScanTile];
+  __shared__ uint32_t gbase[kRadixBins];
+  __shared__ uint32_t lcum[kRadixBins];
   __shared__ uint32_t run[kRadixBins];
   __shared__ uint32_t wc[4][kRadixBins];
+  __shared__ uint32_t tmp[4];
   const int tid = threadIdx.x, wid = tid >> 6;
   const int64_t n = sort_count(n_ptr, n_cap);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   if (base >= n) return;   // uniform over the block
-  run[tid] = hist[(int64_t)tid * nb + blockIdx.x];
-  wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
-  __syncthreads();
+  const int cnt = (int)((n - base) < kScanTile ? (n - base) : kScanTile);
   const uint32_t mask = (1u << bits) - 1u;
   const uint64_t lt = lanemask_lt();
+  gbase[tid] = hist[(int64_t)tid * nb + blockIdx.x];
+  run[tid] = 0u;
+  wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
+  K key[kScanItems];
+  uint32_t val[kScanItems];
+#pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
-    if (base + (int64_t)r * kScanThreads >= n) break;   // uniform
-    int64_t i = base + (int64_t)r * kScanThreads + tid;
-    bool valid = i < n;
-    K key = valid ? kin[i] : (K)0;
-    uint32_t val = valid ? vin[i] : 0u;
-    uint32_t d = (uint32_t)(key >> shift) & mask;
-    uint64_t m = match_digit(d, valid, bits);
-    uint32_t rank = (uint32_t)__popcll(m & lt);
+    const int li = r * kScanThreads + tid;
+    key[r] = li < cnt ? kin[base + li] : (K)0;
+    val[r] = li < cnt ? vin[base + li] : 0u;
+  }
+  __syncthreads();
+  // block-local digit counts
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const bool valid = r * kScanThreads + tid < cnt;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
+    const uint64_t m = match_digit(d, valid, bits);
+    if (valid && (m & lt) == 0) atomicAdd(&run[d], (uint32_t)__popcll(m));
+  }
+  __syncthreads();
+  uint32_t total;
+  lcum[tid] = block_exclusive_scan<uint32_t>(run[tid], tmp, total);
+  run[tid] = 0u;
+  __syncthreads();
+  // stable ranks -> LDS in digit order
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const bool valid = r * kScanThreads + tid < cnt;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
+    const uint64_t m = match_digit(d, valid, bits);
+    const uint32_t rank = (uint32_t)__popcll(m & lt);
     if (valid && rank == 0) wc[wid][d] = (uint32_t)__popcll(m);
     __syncthreads();
     if (valid) {
-      uint32_t pos = run[d] + rank;
-      for (int w = 0; w < wid; ++w) pos += wc[w][d];
-      kout[pos] = key;
-      vout[pos] = val;
+      uint32_t li = lcum[d] + run[d] + rank;
+      for (int w = 0; w < wid; ++w) li += wc[w][d];
+      s_k[li] = key[r];
+      s_v[li] = val[r];
     }
     __syncthreads();
     run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
     wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
     __syncthreads();
+  }
+  // coalesced write-out
+  for (int i = tid; i < cnt; i += kScanThreads) {
+    const K k = s_k[i];
+    const uint32_t d = (uint32_t)(k >> shift) & mask;
+    const uint32_t pos = gbase[d] + (uint32_t)i - lcum[d];
+    kout[pos] = k;
+    vout[pos] = s_v[i];
   }
 }
 
@@ -334,62 +373,53 @@ __device__ __forceinline__ uint32_t tile_of(const DevSensor& S, int64_t base, co
   return (uint32_t)(base + (int64_t)e * S.m_az + a);
 }
 
-constexpr int kBigRecord = 32;   // records touching more tiles are emitted by a whole wavefront
+constexpr int kEmitTile = 2048;   // output slots per workgroup of the emit kernel
 
-__global__ void k_emit(const DevSensor* __restrict__ sens, int64_t N, const int32_t* __restrict__ n_tiles,
-                       const int4* __restrict__ rect, const uint32_t* __restrict__ order, const int64_t* __restrict__ offs,
-                       const int64_t* __restrict__ n_vis, int64_t k_cap, uint32_t* __restrict__ keys,
-                       uint32_t* __restrict__ vals, int32_t* __restrict__ big, int32_t* __restrict__ n_big) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= *n_vis) return;
-  uint32_t rec = order[i];
-  int n = n_tiles[rec];
-  if (n <= 0) return;
-  if (n > kBigRecord) {
-    int slot = atomicAdd(n_big, 1);
-    big[slot] = (int32_t)i;
-    return;
-  }
-  int64_t off = offs[i];
-  int s = (int)(rec / (uint64_t)N);
-  uint32_t g = (uint32_t)(rec - (uint64_t)s * N);
-  const DevSensor& S = sens[s];
-  int64_t base = local_tile_base(sens, s);
-  int4 r = rect[rec];
-  for (int j = 0; j < n; ++j) {
-    int64_t k = off + j;
-    if (k >= k_cap) break;
-    keys[k] = tile_of(S, base, r, j);
-    vals[k] = g;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_emit_big(const DevSensor* __restrict__ sens, int64_t N,
-                                                  const int32_t* __restrict__ n_tiles, const int4* __restrict__ rect,
-                                                  const uint32_t* __restrict__ order, const int64_t* __restrict__ offs,
-                                                  int64_t k_cap, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                  const int32_t* __restrict__ big, const int32_t* __restrict__ n_big) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const int64_t nb = *n_big;
-  for (int64_t b = wave; b < nb; b += n_waves) {
-    int64_t i = big[b];
-    uint32_t rec = order[i];
-    int n = n_tiles[rec];
-    int64_t off = offs[i];
-    int s = (int)(rec / (uint64_t)N);
-    uint32_t g = (uint32_t)(rec - (uint64_t)s * N);
-    const DevSensor& S = sens[s];
-    int64_t base = local_tile_base(sens, s);
-    int4 r = rect[rec];
-    for (int j = lane; j < n; j += 64) {
-      int64_t k = off + j;
-      if (k < k_cap) {
-        keys[k] = tile_of(S, base, r, j);
-        vals[k] = g;
-      }
+// One thread per output slot: slot k belongs to the visible record r (depth order) with
+// offs[r] <= k < offs[r + 1], found by a binary search over the offsets of the records that
+// overlap the workgroup's slots (staged in LDS); the slot's tile is the (k - offs[r])-th tile
+// of that record's rectangle.  Writes are contiguous across lanes.
+__global__ __launch_bounds__(256) void k_emit(const DevSensor* __restrict__ sens, int count, int64_t N,
+                                              const int4* __restrict__ rect, const uint32_t* __restrict__ order,
+                                              const int64_t* __restrict__ offs, const int64_t* __restrict__ n_vis,
+                                              const int64_t* __restrict__ n_slots, uint32_t* __restrict__ keys,
+                                              uint32_t* __restrict__ vals) {
+  __shared__ int64_t s_off[kEmitTile + 1];
+  __shared__ int64_t s_r0;
+  const int tid = threadIdx.x;
+  const int64_t K = *n_slots;
+  const int64_t k0 = (int64_t)blockIdx.x * kEmitTile;
+  if (k0 >= K) return;   // uniform
+  const int64_t nv = *n_vis;
+  if (tid == 0) {
+    int64_t lo = 0, hi = nv - 1;   // last record with offs[r] <= k0 (every visible record has >= 1 slot)
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (offs[mid] <= k0) lo = mid; else hi = mid - 1;
     }
+    s_r0 = lo;
+  }
+  __syncthreads();
+  const int64_t r0 = s_r0;
+  for (int i = tid; i <= kEmitTile; i += 256) {
+    const int64_t r = r0 + i;
+    s_off[i] = r < nv ? offs[r] : INT64_MAX;
+  }
+  __syncthreads();
+  for (int j = 0; j < kEmitTile / 256; ++j) {
+    const int64_t k = k0 + j * 256 + tid;
+    if (k >= K) break;
+    int lo = 0, hi = kEmitTile;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t rec = order[r0 + lo];
+    const int jj = (int)(k - s_off[lo]);
+    const int s = count == 1 ? 0 : (int)(rec / (uint32_t)N);
+    const uint32_t g = rec - (uint32_t)s * (uint32_t)N;
+    keys[k] = tile_of(sens[s], local_tile_base(sens, s), rect[rec], jj);
+    vals[k] = g;
   }
 }
 
@@ -542,8 +572,7 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   w.qtmp = (int2*)take(wcap * 8);
   w.wcount = (int64_t*)take((n_tiles + 2) * 8);
   w.wpart = (int64_t*)take((div_up(n_tiles + 2, kScanTile) + 2) * 8);
-  w.big = (int32_t*)take(nrec * 4);
-  w.n_big = (int32_t*)take(64);   // n_big, then int64 n_sort at +16 B and n_vis at +24 B
+  w.scalars = (int64_t*)take(4 * 8);
   w.g2d = (float*)take(nrec * 10 * 4);
   w.bytes = off;
   return w;
@@ -553,7 +582,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
                            SplatStatus* st, hipStream_t s) {
   const int64_t n_rec = (int64_t)v.count * v.n_gauss;
   hipError_t e;
-  int64_t* n_sort = (int64_t*)(w.n_big + 4);   // spare slots next to the big-record counter
+  int64_t* n_sort = w.scalars;   // min(K, k_cap)
   // 1. visible records, compacted in record order, then stably sorted by float64 depth
   int64_t* n_vis = n_sort + 1;
   if ((e = device_scan<int64_t>(LoadVisible{p.n_tiles}, n_rec, w.offs, w.scan_part, s)) != hipSuccess) return e;
@@ -580,15 +609,10 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   uint32_t* tv[2];
   if (passes % 2 == 0) { tv[0] = (uint32_t*)L.gauss; tv[1] = w.tvals; }
   else { tv[0] = w.tvals; tv[1] = (uint32_t*)L.gauss; }
-  if ((e = fill<int32_t>(w.n_big, 1, 0, s)) != hipSuccess) return e;
-  if (n_rec > 0) {
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, v.sens, v.n_gauss,
-                       (const int32_t*)p.n_tiles, (const int4*)p.rect, order, (const int64_t*)w.offs,
-                       (const int64_t*)n_vis, L.k_cap, w.tkeys[0], tv[0], w.big, w.n_big);
-    hipLaunchKernelGGL(k_emit_big, dim3(1024), dim3(256), 0, s, v.sens, v.n_gauss, (const int32_t*)p.n_tiles,
-                       (const int4*)p.rect, order, (const int64_t*)w.offs, L.k_cap, w.tkeys[0], tv[0],
-                       (const int32_t*)w.big, (const int32_t*)w.n_big);
-  }
+  if (n_rec > 0 && L.k_cap > 0)
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)div_up(L.k_cap, kEmitTile)), dim3(256), 0, s, v.sens, v.count, v.n_gauss,
+                       (const int4*)p.rect, order, (const int64_t*)w.offs, (const int64_t*)n_vis,
+                       (const int64_t*)n_sort, w.tkeys[0], tv[0]);
   // 4. stable sort by tile
   uint32_t* tk[2] = {w.tkeys[0], w.tkeys[1]};
   int tcur = 0;

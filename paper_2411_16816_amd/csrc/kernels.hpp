@@ -55,8 +55,7 @@ struct Workspace {
   uint32_t* qkeys[2];     // [work_cap] queue cost keys
   uint32_t* qvals[2];
   int2* qtmp;             // [work_cap] unordered work items
-  int32_t* big;           // [n_rec] records with many tiles, emitted one wavefront each
-  int32_t* n_big;
+  int64_t* scalars;       // [4] device scalars: clamped intersection count, visible records
   // adjoint
   float* g2d;             // [n_rec, 10]
   size_t bytes;

@@ -100,9 +100,22 @@ __device__ __forceinline__ void setup_ray(const RasterArgs& a, int64_t tile, int
     const DevSensor& S = a.sens[c.s];
     int64_t tl = tile - (S.tile_base - a.sens[0].tile_base);
     int tx = (int)(tl % S.tiles_x), ty = (int)(tl / S.tiles_x);
-    int lx = tid % S.tile_w, ly = tid / S.tile_w;
+    // tiles made of 8x8 blocks give each wavefront an 8x8 pixel block (a compact footprint, so
+    // fewer wavefronts are partly covered by a Gaussian); other tiles are row-major
+    int lx, ly;
+    bool in_tile;
+    if ((S.tile_w & 7) == 0 && (S.tile_h & 7) == 0) {
+      const int blk = tid >> 6, l = tid & 63, bpr = S.tile_w >> 3;
+      lx = (blk % bpr) * 8 + (l & 7);
+      ly = (blk / bpr) * 8 + (l >> 3);
+      in_tile = blk < bpr * (S.tile_h >> 3);
+    } else {
+      lx = tid % S.tile_w;
+      ly = tid / S.tile_w;
+      in_tile = tid < S.tile_w * S.tile_h;
+    }
     int x = tx * S.tile_w + lx, y = ty * S.tile_h + ly;
-    c.valid = (tid < S.tile_w * S.tile_h) && x < S.width && y < S.height;
+    c.valid = in_tile && x < S.width && y < S.height;
     c.px = (float)x + 0.5f;
     c.py = (float)y + 0.5f;
     c.t = (c.py / (float)S.height - 0.5f) * S.t_rs;   // Eq. t_pix at the pixel centre
@@ -297,57 +310,92 @@ __device__ __forceinline__ float dpp_f(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
 
-// One level of the in-row butterfly: lanes whose `bit` is 0 keep value i, the others value
-// i + H; each adds its partner's copy, read through a DPP lane permutation that flips `bit`.
-template <int CTRL, int H, int N>
-__device__ __forceinline__ void dpp_level(float (&v)[N], bool bit) {
+// Wavefront reduce-scatter of V values per lane (V <= 64).  Six levels, one per lane-index bit
+// (5 down to 0): at a level with M values per lane, the lanes whose bit is 0 keep positions
+// [0, H) and the others positions [H, M), H = ceil(M / 2) (a missing upper partner is a zero),
+// each adding its partner lane's copy.  Bit 5 moves data with v_permlane32_swap, bit 4 with
+// v_permlane16_swap, bits 3..0 with DPP row_mirror, row_half_mirror and quad permutations.
+// Once one value is left the remaining levels are plain sums.  About 2 V instructions in all,
+// against 6 V for V separate wavefront reductions; scatter_slot() tells each lane which value
+// it ends up holding.
+constexpr int rs_half(int m) { return m > 1 ? (m + 1) / 2 : 1; }
+
+template <int M, int N>
+__device__ __forceinline__ void rs_swap32(float (&v)[N]) {
+  constexpr int H = rs_half(M);
 #pragma unroll
   for (int i = 0; i < H; ++i) {
-    const float keep = bit ? v[i + H] : v[i];
-    const float send = bit ? v[i] : v[i + H];
-    v[i] = keep + dpp_f<CTRL>(send);
+    const float hi = (M == 1) ? v[0] : ((i + H < M) ? v[i + H] : 0.f);
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(hi), false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
 }
 
-// Wavefront reduce-scatter of N values per lane (N = 16, 32 or 64).  On return v[0] of lane l
-// holds the sum over all 64 lanes of value index (l >> (6 - log2 N)).  Levels: lane bit 5 by
-// v_permlane32_swap, bit 4 by v_permlane16_swap, bits 3..0 by DPP row_mirror, row_half_mirror
-// and quad permutations.  About 2.2 N instructions instead of 6 N for N separate reductions.
-template <int N>
+template <int M, int N>
+__device__ __forceinline__ void rs_swap16(float (&v)[N]) {
+  constexpr int H = rs_half(M);
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const float hi = (M == 1) ? v[0] : ((i + H < M) ? v[i + H] : 0.f);
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(hi), false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+}
+
+template <int CTRL, int M, int N>
+__device__ __forceinline__ void rs_dpp(float (&v)[N], bool bit) {
+  if constexpr (M == 1) {
+    v[0] += dpp_f<CTRL>(v[0]);
+  } else {
+    constexpr int H = rs_half(M);
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const float a = v[i];
+      const float b = (i + H < M) ? v[i + H] : 0.f;
+      const float keep = bit ? b : a;
+      const float send = bit ? a : b;
+      v[i] = keep + dpp_f<CTRL>(send);
+    }
+  }
+}
+
+template <int V, int N>
 __device__ __forceinline__ float wave_reduce_scatter(float (&v)[N]) {
-  static_assert(N == 16 || N == 32 || N == 64, "N");
+  static_assert(V >= 1 && V <= 64 && N >= V, "V");
   const int lane = threadIdx.x & 63;
-  constexpr int H1 = N / 2;
-#pragma unroll
-  for (int i = 0; i < H1; ++i) {
-    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + H1]), false, false);
-    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
-  constexpr int H2 = H1 / 2;
-#pragma unroll
-  for (int i = 0; i < H2; ++i) {
-    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + H2]), false, false);
-    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
-  constexpr int H3 = H2 / 2;
-  dpp_level<0x140, H3>(v, (lane >> 3) & 1);   // row_mirror: lane i <-> 15 - i
-  constexpr int H4 = H3 / 2;
-  if constexpr (H4 >= 1) dpp_level<0x141, H4>(v, (lane >> 2) & 1);   // row_half_mirror: i <-> 7 - i
-  else v[0] += dpp_f<0x141>(v[0]);
-  constexpr int H5 = H4 / 2;
-  if constexpr (H5 >= 1) dpp_level<0x4E, H5>(v, (lane >> 1) & 1);    // quad_perm [2,3,0,1]
-  else v[0] += dpp_f<0x4E>(v[0]);
-  constexpr int H6 = H5 / 2;
-  if constexpr (H6 >= 1) dpp_level<0xB1, H6>(v, lane & 1);           // quad_perm [1,0,3,2]
-  else v[0] += dpp_f<0xB1>(v[0]);
+  constexpr int M1 = rs_half(V), M2 = rs_half(M1), M3 = rs_half(M2), M4 = rs_half(M3), M5 = rs_half(M4);
+  rs_swap32<V>(v);                                  // bit 5
+  rs_swap16<M1>(v);                                 // bit 4
+  rs_dpp<0x140, M2>(v, (lane >> 3) & 1);            // bit 3: row_mirror (i <-> 15 - i)
+  rs_dpp<0x141, M3>(v, (lane >> 2) & 1);            // bit 2: row_half_mirror (i <-> 7 - i)
+  rs_dpp<0x4E, M4>(v, (lane >> 1) & 1);             // bit 1: quad_perm [2,3,0,1]
+  rs_dpp<0xB1, M5>(v, lane & 1);                    // bit 0: quad_perm [1,0,3,2]
   return v[0];
+}
+
+// Which value lane `lane` holds after wave_reduce_scatter<V>, and whether it should store it
+// (one lane per value).
+template <int V>
+__device__ __forceinline__ int scatter_slot(int lane, bool& store) {
+  int m = V, real = V, pos = 0;
+  bool first = true;   // first lane of a group that holds the same value after plain levels
+  for (int b = 5; b >= 0; --b) {
+    const bool bit = (lane >> b) & 1;
+    if (m > 1) {
+      const int h = (m + 1) / 2;
+      if (bit) { pos += h; real -= h; } else { real = real < h ? real : h; }
+      m = h;
+    } else {
+      first = first && !bit;
+    }
+  }
+  store = first && real >= 1;
+  return pos;
 }
 
 template <int CMAX>
 struct BwdShape {
-  static constexpr int V = kNV + CMAX;                         // values per (ray, Gaussian)
-  static constexpr int N = V <= 16 ? 16 : (V <= 32 ? 32 : 64); // padded for the reduce-scatter
-  static constexpr int SHIFT = N == 16 ? 2 : (N == 32 ? 1 : 0);
+  static constexpr int V = kNV + CMAX;   // values reduced per (ray, Gaussian)
 };
 
 constexpr int kBwdBatch = 128;
@@ -378,13 +426,10 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
   if (LIDAR && c.invalid_bin) return;    // uniform over the workgroup
   const int tid = threadIdx.x, lane = tid & 63;
   float T = 1.f, Tf = 1.f, dD = 0.f, dA = 0.f, bufD = 0.f;
-  float dF[CMAX], buf[CMAX];
+  float dF[CMAX];
   int last_l = 0;
 #pragma unroll
-  for (int k = 0; k < CMAX; ++k) {
-    dF[k] = 0.f;
-    buf[k] = 0.f;
-  }
+  for (int k = 0; k < CMAX; ++k) dF[k] = 0.f;
   if (c.valid) {
     T = Tf = b.t_final[c.ray];
     last_l = b.last[c.ray];
@@ -405,8 +450,9 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
   __syncthreads();           // everyone has read maxlast before it can be reset by the next item
   if (n_proc == 0) return;   // uniform
   const DevSensor& S = a.sens[c.s];
-  const int my_idx = lane >> SH::SHIFT;                        // value this lane holds after the scatter
-  const bool my_store = ((lane & ((1 << SH::SHIFT) - 1)) == 0) && my_idx < SH::V;
+  bool my_store;
+  const int my_idx = scatter_slot<SH::V>(lane, my_store);
+  float S_dot = 0.f;   // sum_c buf_c dF_c, the feature part of the colour behind this Gaussian
   for (int64_t b0 = c.start + ((n_proc - 1) / kBwdBatch) * kBwdBatch; b0 >= c.start; b0 -= kBwdBatch) {
     const int64_t b1 = (b0 + kBwdBatch < c.start + n_proc) ? b0 + kBwdBatch : c.start + n_proc;
     if (tid < kBwdBatch) stage_batch<CMAX>(a, c, b0, b1, s_mv, s_cn, s_box, s_dv, s_f);
@@ -418,57 +464,52 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
       const float4 bx = s_box[j];
       const float bxa[4] = {bx.x, bx.y, bx.z, bx.w};
       if (!TILE) act = act && box_contains(LIDAR, c.px, c.py, bxa);
+      if (__ballot(act) == 0) continue;   // uniform over the wavefront
       const float4 m = s_mv[j], q = s_cn[j];
       const float mva[4] = {m.x, m.y, m.z, m.w}, cna[4] = {q.x, q.y, q.z, q.w};
       PairEval e;
-      e.alpha = 0.f;
-      if (act) {
-        eval_pair(LIDAR, c.px, c.py, c.t, mva, cna, e);
-        act = e.alpha >= kAlphaMin;
-      }
+      eval_pair(LIDAR, c.px, c.py, c.t, mva, cna, e);
+      act = act && e.alpha >= kAlphaMin;
       if (__ballot(act) == 0) continue;   // uniform over the wavefront
-      float v[SH::N];
+      // branch-free: inactive lanes use alpha_eff = 0 and contribute exact zeros
+      const float a_eff = act ? e.alpha : 0.f;
+      const float ra = act ? __builtin_amdgcn_rcpf(1.f - e.alpha) : 1.f;
+      T = T * ra;                         // transmittance in front of this Gaussian
+      const float w = a_eff * T;
+      float v[SH::V];
+      float fd = 0.f;
 #pragma unroll
-      for (int k = 0; k < SH::N; ++k) v[k] = 0.f;
-      if (act) {
-        const float ra = 1.f / (1.f - e.alpha);
-        T = T * ra;                       // transmittance in front of this Gaussian
-        const float w = e.alpha * T;
-        float acc = 0.f;
-#pragma unroll
-        for (int c4 = 0; c4 < CMAX / 4; ++c4) {
-          const float4 f = s_f[j * (CMAX / 4) + c4];
-          const float fa[4] = {f.x, f.y, f.z, f.w};
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int k = 4 * c4 + u;
-            v[kNV + k] = w * dF[k];
-            acc += (fa[u] - buf[k]) * dF[k];
-            buf[k] += e.alpha * (fa[u] - buf[k]);
-          }
-        }
-        const float2 d = s_dv[j];
-        const float gv = LIDAR ? SPLAT_FMA(d.y, c.t, d.x) : d.x;
-        acc += (gv - bufD) * dD;
-        bufD += e.alpha * (gv - bufD);
-        const float dalpha = T * acc + dA * Tf * ra;
-        const float dg = w * dD;
-        const float d_oeff = e.clamped ? 0.f : dalpha * e.G;
-        const float dsig = e.clamped ? 0.f : -dalpha * e.alpha;
-        const float ddx = (q.x * e.dx + q.y * e.dy) * dsig;
-        const float ddy = (q.y * e.dx + q.z * e.dy) * dsig;
-        v[0] = -ddx;
-        v[1] = -ddy;
-        v[2] = -ddx * c.t;
-        v[3] = -ddy * c.t;
-        v[4] = 0.5f * e.dx * e.dx * dsig;
-        v[5] = e.dx * e.dy * dsig;
-        v[6] = 0.5f * e.dy * e.dy * dsig;
-        v[7] = d_oeff;
-        v[8] = dg;
-        v[9] = LIDAR ? dg * c.t : 0.f;
+      for (int c4 = 0; c4 < CMAX / 4; ++c4) {
+        const float4 f = s_f[j * (CMAX / 4) + c4];
+        fd = SPLAT_FMA(f.x, dF[4 * c4 + 0], fd);
+        fd = SPLAT_FMA(f.y, dF[4 * c4 + 1], fd);
+        fd = SPLAT_FMA(f.z, dF[4 * c4 + 2], fd);
+        fd = SPLAT_FMA(f.w, dF[4 * c4 + 3], fd);
       }
-      const float r = wave_reduce_scatter<SH::N>(v);
+#pragma unroll
+      for (int k = 0; k < CMAX; ++k) v[kNV + k] = w * dF[k];
+      const float2 d = s_dv[j];
+      const float gv = LIDAR ? SPLAT_FMA(d.y, c.t, d.x) : d.x;
+      const float acc = (fd - S_dot) + (gv - bufD) * dD;
+      S_dot = SPLAT_FMA(a_eff, fd - S_dot, S_dot);
+      bufD = SPLAT_FMA(a_eff, gv - bufD, bufD);
+      const float dalpha = act ? (T * acc + dA * Tf * ra) : 0.f;
+      const float dg = w * dD;
+      const float d_oeff = e.clamped ? 0.f : dalpha * e.G;
+      const float dsig = e.clamped ? 0.f : -dalpha * e.alpha;
+      const float ddx = (q.x * e.dx + q.y * e.dy) * dsig;
+      const float ddy = (q.y * e.dx + q.z * e.dy) * dsig;
+      v[0] = -ddx;
+      v[1] = -ddy;
+      v[2] = -ddx * c.t;
+      v[3] = -ddy * c.t;
+      v[4] = 0.5f * e.dx * e.dx * dsig;
+      v[5] = e.dx * e.dy * dsig;
+      v[6] = 0.5f * e.dy * e.dy * dsig;
+      v[7] = d_oeff;
+      v[8] = dg;
+      v[9] = LIDAR ? dg * c.t : 0.f;
+      const float r = wave_reduce_scatter<SH::V>(v);
       if (my_store) atomicAdd(&s_acc[my_idx][j], r);
       if (lane == 0) s_used[j] = 1;
     }

@@ -7,7 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/splat.h"
+#include "splat.h"
 
 #define HD __host__ __device__ __forceinline__
 
