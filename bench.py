@@ -6,14 +6,16 @@ Workload (default): a 128-beam x 2048-azimuth spinning lidar (100 ms rolling-shu
 synthetic Gaussians in a 300 x 300 x 6 m box; forward + backward (projection, binning, depth
 sort, compositing, adjoint) every step.  Inputs are resident in HBM before timing starts.
 
-Two forms of the same step are timed:
+Three forms of the same step are timed:
   plain   -- per-sensor calls (project -> bin/sort -> rasterize_fwd -> rasterize_bwd per sensor);
   batched -- one call per stage for both sensors (one projection launch, one bin/sort building
-             a cost-ordered work queue, persistent forward and adjoint rasterisers).
-Both are checked against the FP64 oracle on sampled rays before timing.
+             a cost-ordered work queue, persistent forward and adjoint rasterisers);
+  graph   -- the batched step captured once as a hipGraph (splat_pipeline_*) and replayed.
+Each is checked against the FP64 oracle on sampled rays before timing, and also timed
+forward-only (project -> bin/sort -> rasterize_fwd).
 
-Prints one JSON line.  `value` is the batched form's rays (pixels + lidar rays) per second of
-whole fwd+bwd steps, in Mrays/s; the plain form is reported beside it.
+Prints one JSON line.  `value` is the graph-replayed batched form's rays (pixels + lidar rays) per
+second of whole fwd+bwd steps, in Mrays/s; the other forms are reported beside it.
 """
 from __future__ import annotations
 
@@ -48,11 +50,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=2_000_000, help="Gaussians")
-    ap.add_argument("--modes", default="plain,batched")
+    ap.add_argument("--modes", default="plain,batched,graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=64, help="rays per sensor in the CPU oracle sample")
     ap.add_argument("--profile-steps", action="store_true", help="skip parity and CPU legs (for rocprofv3)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the scene's tile shapes")
+    ap.add_argument("--camera-tile", default=None, help="WxH: fixed camera tile (skips autotuning)")
+    ap.add_argument("--lidar-tile", default=None,
+                    help="AZxM: fixed lidar tiles of AZ azimuth steps, elevation tiles merged by M (skips autotuning)")
     return ap.parse_args()
 
 
@@ -77,6 +83,30 @@ def main():
     log(f"scene {sc.name}: {g.n} Gaussians, {sc.n_rays} rays/step, generated in {time.time() - t0:.1f}s")
     dev = "cuda"
     G = B.GaussTensors.from_numpy(g, dev)
+    tiles = {"camera": [int(cam.tile_w), int(cam.tile_h)], "lidar_az_tiles": int(lid.n_az_tiles),
+             "lidar_el_tiles": int(lid.n_el_tiles)}
+    tune_report = None
+    if args.camera_tile or args.lidar_tile:
+        from paper_2411_16816_amd import autotune
+        if args.camera_tile:
+            tw, th = (int(x) for x in args.camera_tile.lower().split("x"))
+            cam = next(c for c in autotune.camera_candidates(cam) if (c.tile_w, c.tile_h) == (tw, th))
+        if args.lidar_tile:
+            taz, m = (int(x) for x in args.lidar_tile.lower().split("x"))
+            n_el = (lid.n_el_tiles + m - 1) // m
+            lid = next(l for l in autotune.lidar_candidates(lid) if autotune._shape(l, False) == (taz, n_el))
+        tiles = {"camera": [int(cam.tile_w), int(cam.tile_h)], "lidar_az_tiles": int(lid.n_az_tiles),
+                 "lidar_el_tiles": int(lid.n_el_tiles)}
+    elif not args.no_autotune:
+        from paper_2411_16816_amd import autotune
+        t1 = time.time()
+        cams, lids, rep = autotune.tune_rig([cam], [lid], G, log=log)
+        cam, lid = cams[0], lids[0]
+        tiles = {"camera": [int(cam.tile_w), int(cam.tile_h)], "lidar_az_tiles": int(lid.n_az_tiles),
+                 "lidar_el_tiles": int(lid.n_el_tiles)}
+        tune_report = {("camera" if k == 0 else "lidar"): [[list(sh), round(ms, 4)] for sh, ms in v[1]]
+                       for k, v in rep.items()}
+        log(f"autotuned tiles {tiles} in {time.time() - t1:.1f}s")
     rig = B.Rig([cam], [lid], dev)
     stream = torch.cuda.current_stream()
     stages = ["project", "bin_sort", "raster_fwd", "raster_bwd"]
@@ -93,8 +123,15 @@ def main():
             dF = np.random.default_rng(1100 + k).normal(size=sp.n_feat).astype(np.float32)
             ups.append(tuple(torch.from_numpy(a.reshape(-1)).to(dev) for a in (dF, dD, dA)))
         grads = B.zeros_like_grads(G)
+        pipe = pipe_fwd = None
+        if mode == "graph":
+            pipe = B.Pipeline(passes[0], G, B.BOX, grads, *ups[0], zero_grads=False)
+            pipe_fwd = B.Pipeline(passes[0], G, B.BOX)
 
         def step(events=None):
+            if pipe is not None:
+                pipe.run()
+                return
             for k, sp in enumerate(passes):
                 ev = events[k] if events is not None else None
                 if ev: ev["project"][0].record(stream)
@@ -132,8 +169,29 @@ def main():
         ms = start.elapsed_time(end) / args.steps
         rays = sum(sp.n_rays for sp in passes)
         names = ["camera", "lidar"] if mode == "plain" else ["both"]
-        stage_ms = {f"{s}_{names[k]}": float(np.mean([e[k][s][0].elapsed_time(e[k][s][1]) for e in evs]))
-                    for k in range(len(passes)) for s in stages}
+        stage_ms = {} if pipe is not None else {
+            f"{s}_{names[k]}": float(np.mean([e[k][s][0].elapsed_time(e[k][s][1]) for e in evs]))
+            for k in range(len(passes)) for s in stages}
+
+        # forward only (project -> bin/sort -> rasterize_fwd), same step count
+        def fwd_step():
+            if pipe_fwd is not None:
+                pipe_fwd.run()
+                return
+            for sp in passes:
+                sp.project(G)
+                sp.bin_sort()
+                sp.raster_fwd(G)
+
+        for _ in range(max(1, args.warmup)):
+            fwd_step()
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(args.steps):
+            fwd_step()
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms_fwd = start.elapsed_time(end) / args.steps
         # evaluated pairs (one extra forward with the counter on, outside the timed region)
         pairs = []
         for sp in passes:
@@ -142,12 +200,16 @@ def main():
         torch.cuda.synchronize()
         pairs = [int(B.read_status(sp.status).n_pairs) for sp in passes]
         results[mode] = dict(ms=ms, value=rays / (ms * 1e-3) / 1e6, stage_ms=stage_ms, parity=parity, K=Ks,
-                             pairs=pairs, rays=rays)
-        log(f"{mode}: {ms:.3f} ms/step, {results[mode]['value']:.1f} Mrays/s; stages "
+                             pairs=pairs, rays=rays, ms_fwd=ms_fwd, value_fwd=rays / (ms_fwd * 1e-3) / 1e6)
+        log(f"{mode}: {ms:.3f} ms/step, {results[mode]['value']:.1f} Mrays/s (forward only {ms_fwd:.3f} ms, "
+            f"{results[mode]['value_fwd']:.1f} Mrays/s); stages "
             + json.dumps({k: round(v, 4) for k, v in stage_ms.items()}) + f"; pairs {pairs}")
-        del passes, grads
+        if pipe is not None:
+            pipe.close()
+            pipe_fwd.close()
+        del passes, grads, pipe, pipe_fwd
 
-    main_mode = "batched" if "batched" in results else "plain"
+    main_mode = next(m for m in ("graph", "batched", "plain") if m in results)
     R = results[main_mode]
     roof = roofline(results)
     cpu = None
@@ -158,16 +220,22 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(R["ms"], 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "lidar 128x2048 (100 ms RS, 15 m/s ego) + 1920x1080 RS camera, 2M Gaussians, fwd+bwd",
-                   "mode": main_mode, "gaussians": g.n, "rays_per_step": R["rays"]},
+                   "mode": main_mode, "gaussians": g.n, "rays_per_step": R["rays"], "tiles": tiles},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "forward_only": {"value": round(R["value_fwd"], 3), "unit": "Mrays/s", "ms_per_step": round(R["ms_fwd"], 4)},
         "modes": {m: {"value": round(r["value"], 3), "ms_per_step": round(r["ms"], 4),
+                      "forward_only_value": round(r["value_fwd"], 3), "forward_only_ms": round(r["ms_fwd"], 4),
                       "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
                       "intersections": r["K"], "evaluated_pairs": r["pairs"], "parity": r["parity"]}
                   for m, r in results.items()},
     }
-    if "plain" in results and "batched" in results:
-        out["batched_over_plain"] = round(results["batched"]["value"] / results["plain"]["value"], 4)
+    if tune_report is not None:
+        out["autotune_ms"] = tune_report
+    if "plain" in results:
+        for m in ("batched", "graph"):
+            if m in results:
+                out[f"{m}_over_plain"] = round(results[m]["value"] / results["plain"]["value"], 4)
     print(json.dumps(out), flush=True)
 
 

@@ -156,6 +156,13 @@ typedef struct SplatTileLists {
   int64_t k_cap;          /* capacity of gauss[]                                             */
   int32_t* gauss;         /* [k_cap] Gaussian ids, grouped by tile, by (depth, id) inside      */
   int32_t* tile_range;    /* [n_tiles, 2] [start, end) into gauss                             */
+  int64_t* entry_base;    /* [count * N] written by bin_sort for records with n_tiles > 0:
+                             the emission position of the record's first (tile, Gaussian) entry.
+                             Entries are emitted record by record in depth order, each record's
+                             tiles in the row-major order of its rectangle, so record r owns the
+                             positions [entry_base[r], entry_base[r] + n_tiles[r]); positions at
+                             or beyond k_cap were dropped (overflow).  The adjoint keeps one
+                             gradient row per position in its workspace.                      */
   /* lidar only (NULL for camera calls): */
   int32_t* ray_order;     /* [n_rays] local ray ids grouped by tile (invalid rays last)         */
   int32_t* ray_range;     /* [n_tiles + 1, 2] [start, end) into ray_order; entry n_tiles =
@@ -173,7 +180,7 @@ typedef struct SplatRenderOut {
   float* alpha;     /* [n_rays] 1 - T_final                                                   */
   float* t_final;   /* [n_rays] final transmittance (saved for the adjoint)                   */
   int32_t* last;    /* [n_rays] 1 + position in the tile list of the last blended Gaussian    */
-  float* median;    /* [n_rays] median range (lidar) or NULL                                  */
+  float* median;    /* [n_rays] median range of lidar rays (camera rays: not written) or NULL */
 } SplatRenderOut;
 
 /* Gradient accumulators (+=), device arrays shaped like SplatGaussians. */
@@ -205,7 +212,10 @@ int splat_rig_layout(const SplatRig* rig, SplatRigLayout* out);
 void splat_rig_destroy(SplatRig* rig);
 
 /* Workspace bytes needed by any call on sensors [first, first+count) of `rig` with
- * `n_gaussians` Gaussians and list capacity k_cap. */
+ * `n_gaussians` Gaussians and list capacity k_cap.  The bin/sort buffers and the adjoint's
+ * buffers overlay each other; the adjoint's part is one gradient row per list entry
+ * (k_cap x (10 + channel bucket) floats, channel buckets 4/8/16/32/48, rows padded to 16 bytes),
+ * k_cap flag bytes and 10 floats per record.  Nothing in it outlives a call. */
 size_t splat_workspace_bytes(const SplatRig* rig, int32_t first, int32_t count, int64_t n_gaussians,
                              int64_t k_cap);
 
@@ -252,7 +262,8 @@ int splat_rasterize_fwd_lidar(const SplatGaussians* g, const SplatRig* rig, int3
  * camera tiles and lidar ray chunks ordered by descending list length; and persistent
  * rasterisers (forward and adjoint) whose workgroups drain that queue.  Lists need ray_order
  * (if any lidar), ray_range, work and n_work.  Results are bit-identical to the per-sensor
- * calls (BOX support); the adjoint accumulates in a different order (float atomics). */
+ * calls (BOX support).  Gradients agree with the per-sensor calls to float rounding: a
+ * workgroup adds its four wavefronts' partial sums in LDS in scheduling order. */
 int splat_project(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
                   const SplatProjected* out, SplatStatus* status, void* stream);
 int splat_bin_sort(const SplatRig* rig, int32_t first, int32_t count, int64_t n_gaussians,
@@ -267,10 +278,14 @@ int splat_rasterize_bwd(const SplatGaussians* g, const SplatRig* rig, int32_t fi
                         const float* d_alpha, const SplatGrads* grads, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- a7: rasterisation backward + projection adjoint.  Walks each ray's list back to front
- * from `last`, recovering T_i = T_{i+1} / (1 - alpha_i) from the saved T_final, reduces
- * per-Gaussian gradients across a wavefront before global atomics, then chains the 2-D
- * gradients to means, log-scales, quaternions, opacities, velocities and features.
- * d_feat / d_depth / d_alpha are the upstream gradients of SplatRenderOut feat/depth/alpha. */
+ * from `last`, recovering T_i = T_{i+1} / (1 - alpha_i) from the saved T_final.  A work item
+ * sums each Gaussian's gradient over its rays (wavefront, then workgroup) and stores it as one
+ * row per (tile, Gaussian) entry at the entry's emission position (see entry_base); work items
+ * of a lidar tile with more than SPLAT_RAYS_PER_ITEM rays share the tile and add atomically
+ * instead.  Each record's rows are then summed in a fixed order and chained to means,
+ * log-scales, quaternions, opacities, velocities and features.  Needs the lists written by
+ * bin_sort for the same projection.  d_feat / d_depth / d_alpha are the upstream gradients of
+ * SplatRenderOut feat/depth/alpha. */
 int splat_rasterize_bwd_camera(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
                                const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
                                const SplatRenderOut* saved, const float* d_feat, const float* d_depth,
@@ -281,6 +296,47 @@ int splat_rasterize_bwd_lidar(const SplatGaussians* g, const SplatRig* rig, int3
                               const SplatRenderOut* saved, const float* d_feat, const float* d_depth,
                               const float* d_alpha, const SplatGrads* grads, void* ws, size_t ws_bytes,
                               void* stream);
+
+/* ---- a8: one step captured as a hipGraph.  A pipeline records, for the sensors
+ * [first, first + count) of a rig, the launches of one step of the batched form: zero *status
+ * (fill kernel), zero the gradients (if SPLAT_STEP_ZERO_GRADS), splat_project, splat_bin_sort,
+ * splat_rasterize_fwd and, with SPLAT_STEP_BACKWARD, splat_rasterize_bwd, all on the buffers of
+ * `step` (validated at creation exactly as those calls validate them).  splat_pipeline_run
+ * launches the graph on `stream`: one host call per step instead of one per kernel.
+ *   - Graph kernels read the sensor table at run time, so poses, velocities, shutter times and
+ *     ray arrays may change between runs through splat_rig_set on the same stream.  A change of
+ *     any sensor's kind, tile count, ray count, channel count or feature offset invalidates the
+ *     pipeline: splat_pipeline_run then returns SPLAT_ERR_INVALID_ARG and launches nothing.
+ *   - The buffers of `step` are captured by address: they must stay allocated, and their
+ *     contents are read/written by every run (inputs may change between runs).
+ *   - The graph holds no memset node (zeroing uses fill kernels) and allocates nothing.
+ *   - Creating a pipeline captures on an internal stream and instantiates the graph; it is not a
+ *     hot-path call.  Runs of one pipeline on different streams must not overlap. */
+#define SPLAT_STEP_BACKWARD 1    /* include the adjoint                                   */
+#define SPLAT_STEP_ZERO_GRADS 2  /* zero every gradient array first (else they accumulate) */
+
+typedef struct SplatStep {
+  SplatGaussians gaussians;
+  SplatProjected proj;
+  SplatTileLists lists;
+  SplatRenderOut out;        /* forward outputs; the saved state of the adjoint              */
+  int32_t support;           /* SPLAT_SUPPORT_BOX or SPLAT_SUPPORT_TILE                      */
+  int32_t flags;             /* SPLAT_STEP_*                                                 */
+  const float* d_feat;       /* upstream gradients (backward only)                           */
+  const float* d_depth;
+  const float* d_alpha;
+  SplatGrads grads;          /* accumulated (backward only)                                  */
+  void* ws;                  /* workspace of splat_workspace_bytes(rig, first, count, n, k_cap) */
+  size_t ws_bytes;
+  SplatStatus* status;       /* zeroed at the start of every run; may be NULL                */
+} SplatStep;
+
+typedef struct SplatPipeline SplatPipeline;
+
+int splat_pipeline_create(const SplatRig* rig, int32_t first, int32_t count, const SplatStep* step,
+                          SplatPipeline** out);
+int splat_pipeline_run(SplatPipeline* pipeline, void* stream);
+void splat_pipeline_destroy(SplatPipeline* pipeline);
 
 #ifdef __cplusplus
 }

@@ -54,6 +54,9 @@ def _declare(lib):
         "splat_bin_sort": (C.c_int, [vp, i32, i32, i64, vp, vp, vp, C.c_size_t, vp, vp]),
         "splat_rasterize_fwd": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp]),
         "splat_rasterize_bwd": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+        "splat_pipeline_create": (C.c_int, [vp, i32, i32, vp, C.POINTER(vp)]),
+        "splat_pipeline_run": (C.c_int, [vp, vp]),
+        "splat_pipeline_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -131,27 +134,52 @@ class Rig:
         h = C.c_void_p()
         check(lib.splat_rig_create(self.n_cam, self.n_lid, C.byref(h)), "splat_rig_create")
         self.handle = h
-        self._keep = []
+        self.device = device
         self.ray_tensors = []
-        cams = (st.SplatCamera * max(1, self.n_cam))()
-        for i, c in enumerate(self.cameras):
-            cams[i] = st.camera_struct(c)
-        lids = (st.SplatLidar * max(1, self.n_lid))()
-        for i, l in enumerate(self.lidars):
-            az = torch.from_numpy(np.ascontiguousarray(l.ray_az, np.float32)).to(device)
-            el = torch.from_numpy(np.ascontiguousarray(l.ray_el, np.float32)).to(device)
-            tt = torch.from_numpy(np.ascontiguousarray(l.ray_t, np.float32)).to(device)
-            self.ray_tensors.append((az, el, tt))
-            lids[i] = st.lidar_struct(l, (az.data_ptr(), el.data_ptr(), tt.data_ptr()), self._keep)
-        self._cams, self._lids = cams, lids
-        check(lib.splat_rig_set(h, cams if self.n_cam else None, lids if self.n_lid else None, _stream()),
-              "splat_rig_set")
+        self._upload()
         lay = st.SplatRigLayout()
         check(lib.splat_rig_layout(h, C.byref(lay)), "splat_rig_layout")
         n = self.n_cam + self.n_lid
         self.tile_base = np.array(lay.tile_base[:n + 1], np.int64)
         self.ray_base = np.array(lay.ray_base[:n + 1], np.int64)
         self.feat_base = np.array(lay.feat_base[:n + 1], np.int64)
+        self.sensors = self.cameras + self.lidars
+
+    def _upload(self):
+        """Sensor structs -> splat_rig_set on the current stream.  Lidar ray arrays of unchanged
+        length are copied into the existing device tensors (their addresses stay valid)."""
+        keep = []
+        cams = (st.SplatCamera * max(1, self.n_cam))()
+        for i, c in enumerate(self.cameras):
+            cams[i] = st.camera_struct(c)
+        lids = (st.SplatLidar * max(1, self.n_lid))()
+        for i, l in enumerate(self.lidars):
+            host = [torch.from_numpy(np.ascontiguousarray(a, np.float32)) for a in (l.ray_az, l.ray_el, l.ray_t)]
+            if i < len(self.ray_tensors) and all(d.numel() == h.numel() for d, h in zip(self.ray_tensors[i], host)):
+                for d, h in zip(self.ray_tensors[i], host):
+                    d.copy_(h)
+            else:
+                dev = tuple(h.to(self.device) for h in host)
+                if i < len(self.ray_tensors):
+                    self.ray_tensors[i] = dev
+                else:
+                    self.ray_tensors.append(dev)
+            az, el, tt = self.ray_tensors[i]
+            lids[i] = st.lidar_struct(l, (az.data_ptr(), el.data_ptr(), tt.data_ptr()), keep)
+        self._cams, self._lids, self._keep = cams, lids, keep
+        check(self.lib.splat_rig_set(self.handle, cams if self.n_cam else None, lids if self.n_lid else None,
+                                     _stream()), "splat_rig_set")
+
+    def update(self, cameras: Optional[Sequence] = None, lidars: Optional[Sequence] = None):
+        """New sensor parameters (poses, motion, rays) for the same sensors; uploaded on the current
+        stream.  Pipelines stay valid while tile, ray and channel counts are unchanged."""
+        if cameras is not None:
+            assert len(cameras) == self.n_cam
+            self.cameras = list(cameras)
+        if lidars is not None:
+            assert len(lidars) == self.n_lid
+            self.lidars = list(lidars)
+        self._upload()
         self.sensors = self.cameras + self.lidars
 
     def kind(self, s: int) -> int:
@@ -213,6 +241,7 @@ class SensorPass:
         self.rect = torch.empty((R, 4), **i32)
         self.ntiles = torch.empty((R,), **i32)
         self.tile_range = torch.empty((max(1, self.n_tiles), 2), **i32)
+        self.entry_base = torch.empty((max(1, R),), dtype=torch.int64, device=device)
         if self.has_lidar or batched:
             self.work_cap = self.n_tiles + (self.n_rays + 255) // 256 + 1
             first_lidar = next((k for k in range(count) if rig.kind(first + k) == KIND_LIDAR), count)
@@ -255,7 +284,7 @@ class SensorPass:
     def lists_struct(self):
         L = st.SplatTileLists()
         L.k_cap = self.k_cap
-        L.gauss, L.tile_range = _ptr(self.gauss), _ptr(self.tile_range)
+        L.gauss, L.tile_range, L.entry_base = _ptr(self.gauss), _ptr(self.tile_range), _ptr(self.entry_base)
         L.ray_order, L.ray_range, L.work, L.n_work = (_ptr(self.ray_order), _ptr(self.ray_range),
                                                       _ptr(self.work), _ptr(self.n_work))
         L.work_cap = self.work_cap
@@ -300,9 +329,7 @@ class SensorPass:
                   "splat_rasterize_fwd_camera")
 
     def raster_bwd(self, g: GaussTensors, dF, dD, dA, grads: GaussTensors, support=BOX, stream=None):
-        gr = st.SplatGrads()
-        gr.means, gr.log_scales, gr.quats = _ptr(grads.means), _ptr(grads.log_scales), _ptr(grads.quats)
-        gr.opacities, gr.velocities, gr.features = _ptr(grads.opacities), _ptr(grads.velocities), _ptr(grads.features)
+        gr = _grads_struct(grads)
         fn = (self.lib.splat_rasterize_bwd if self.batched else
               self.lib.splat_rasterize_bwd_lidar if self.lidar else self.lib.splat_rasterize_bwd_camera)
         check(fn(C.byref(g.struct()), self.rig.handle, self.first, self.count, C.byref(self.proj_struct()),
@@ -342,6 +369,53 @@ class SensorPass:
         s = self.rig.sensors[self.first + k]
         return (slice(int(self.ray_off[k]), int(self.ray_off[k + 1])),
                 slice(int(self.feat_off[k]), int(self.feat_off[k + 1])), s.n_channels)
+
+
+def _grads_struct(grads: GaussTensors) -> st.SplatGrads:
+    gr = st.SplatGrads()
+    gr.means, gr.log_scales, gr.quats = _ptr(grads.means), _ptr(grads.log_scales), _ptr(grads.quats)
+    gr.opacities, gr.velocities, gr.features = _ptr(grads.opacities), _ptr(grads.velocities), _ptr(grads.features)
+    return gr
+
+
+class Pipeline:
+    """One step of a batched SensorPass captured as a hipGraph (splat_pipeline_*).  The tensors
+    named here are captured by address and kept alive by this object; `run` replays the step."""
+
+    def __init__(self, sp: SensorPass, g: GaussTensors, support=BOX, grads: Optional[GaussTensors] = None,
+                 dF=None, dD=None, dA=None, zero_grads: bool = True):
+        if not sp.batched:
+            raise ValueError("pipelines run the batched form")
+        self.lib, self.sp, self.g = sp.lib, sp, g
+        self.keep = (grads, dF, dD, dA)
+        step = st.SplatStep()
+        step.gaussians = g.struct()
+        step.proj, step.lists, step.out = sp.proj_struct(), sp.lists_struct(), sp.out_struct()
+        step.support = support
+        step.flags = 0
+        if grads is not None:
+            step.flags |= st.SPLAT_STEP_BACKWARD | (st.SPLAT_STEP_ZERO_GRADS if zero_grads else 0)
+            step.d_feat, step.d_depth, step.d_alpha = _ptr(dF), _ptr(dD), _ptr(dA)
+            step.grads = _grads_struct(grads)
+        step.ws, step.ws_bytes = C.c_void_p(sp.ws_ptr), sp.ws_bytes
+        step.status = _ptr(sp.status)
+        self.handle = C.c_void_p()
+        check(self.lib.splat_pipeline_create(sp.rig.handle, sp.first, sp.count, C.byref(step), C.byref(self.handle)),
+              "splat_pipeline_create")
+
+    def run(self, stream=None):
+        check(self.lib.splat_pipeline_run(self.handle, _stream(stream)), "splat_pipeline_run")
+
+    def close(self):
+        if self.handle:
+            self.lib.splat_pipeline_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def zeros_like_grads(g: GaussTensors) -> GaussTensors:

@@ -18,8 +18,16 @@ struct SplatRig {
   bool upload_pending = false;
   bool is_set = false;
   int n_cu = 0;                     // compute units of the rig's device (persistent grids)
+  uint64_t layout_gen = 0;          // bumped when a launch-shaping field of any sensor changes
   SplatRigLayout layout;
 };
+
+// Fields that shape launches (grid sizes, buffer extents, validation); everything else a kernel
+// reads from the device table at run time.
+static bool same_layout(const DevSensor& a, const DevSensor& b) {
+  return a.kind == b.kind && a.n_tiles == b.n_tiles && a.n_rays == b.n_rays && a.n_ch == b.n_ch &&
+         a.feat_off == b.feat_off;
+}
 
 extern "C" {
 
@@ -118,6 +126,9 @@ int splat_rig_set(SplatRig* r, const SplatCamera* cams, const SplatLidar* lidars
     return SPLAT_ERR_DEVICE;
   if (hipEventRecord(r->uploaded, s) != hipSuccess) return SPLAT_ERR_DEVICE;
   r->upload_pending = true;
+  bool same = r->is_set;
+  for (int i = 0; same && i < n; ++i) same = same_layout(r->host[i], tab[i]);
+  if (!same) ++r->layout_gen;
   r->host = tab;
   r->layout = L;
   r->is_set = true;
@@ -189,8 +200,8 @@ static int check_proj(const SplatProjected* p, const CallView& v) {
 
 static int check_lists(const SplatTileLists* L, const CallView& v) {
   if (!L || L->k_cap < 0 || L->k_cap >= ((int64_t)1 << 31)) return SPLAT_ERR_INVALID_ARG;
-  if ((L->k_cap > 0 && !L->gauss) || !L->tile_range) return SPLAT_ERR_INVALID_ARG;
-  if (((uintptr_t)L->tile_range & 7) != 0) return SPLAT_ERR_INVALID_ARG;
+  if ((L->k_cap > 0 && !L->gauss) || !L->tile_range || !L->entry_base) return SPLAT_ERR_INVALID_ARG;
+  if ((((uintptr_t)L->tile_range | (uintptr_t)L->entry_base) & 7) != 0) return SPLAT_ERR_INVALID_ARG;
   if (v.has_lidar || v.queue) {
     if ((v.has_lidar && !L->ray_order) || !L->ray_range || !L->work || !L->n_work) return SPLAT_ERR_INVALID_ARG;
     if ((((uintptr_t)L->ray_range | (uintptr_t)L->work) & 7) != 0) return SPLAT_ERR_INVALID_ARG;
@@ -223,9 +234,9 @@ static int bin_sort_impl(const SplatRig* r, int32_t first, int32_t count, int ki
   int rc = make_view(r, first, count, kind, n_gaussians, v);
   if (rc) return rc;
   if ((rc = check_proj(proj, v)) || (rc = check_lists(lists, v))) return rc;
-  Workspace w = carve_workspace(nullptr, (int64_t)count * n_gaussians, lists->k_cap, v.n_tiles, v.n_rays);
+  Workspace w = carve_workspace(nullptr, (int64_t)count * n_gaussians, lists->k_cap, v.n_tiles, v.n_rays, v.c_max);
   if (!ws || ws_bytes < w.bytes || ((uintptr_t)ws & 255) != 0) return SPLAT_ERR_INVALID_ARG;
-  w = carve_workspace(ws, (int64_t)count * n_gaussians, lists->k_cap, v.n_tiles, v.n_rays);
+  w = carve_workspace(ws, (int64_t)count * n_gaussians, lists->k_cap, v.n_tiles, v.n_rays, v.c_max);
   return dev_err(launch_bin_sort(v, *proj, *lists, w, st, (hipStream_t)stream));
 }
 
@@ -254,13 +265,15 @@ static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t f
   if (!saved || !saved->t_final || !saved->last || !dD || !dA || (v.c_max > 0 && !dF)) return SPLAT_ERR_INVALID_ARG;
   if (!gr || !gr->means || !gr->log_scales || !gr->quats || !gr->opacities || (v.c_max > 0 && !gr->features))
     return SPLAT_ERR_INVALID_ARG;
-  Workspace w = carve_workspace(nullptr, (int64_t)count * g->n, lists->k_cap, v.n_tiles, v.n_rays);
+  Workspace w = carve_workspace(nullptr, (int64_t)count * g->n, lists->k_cap, v.n_tiles, v.n_rays, v.c_max);
   if (!ws || ws_bytes < w.bytes || ((uintptr_t)ws & 255) != 0) return SPLAT_ERR_INVALID_ARG;
-  w = carve_workspace(ws, (int64_t)count * g->n, lists->k_cap, v.n_tiles, v.n_rays);
+  w = carve_workspace(ws, (int64_t)count * g->n, lists->k_cap, v.n_tiles, v.n_rays, v.c_max);
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_fill_f32(w.g2d, (int64_t)count * g->n * 10, 0.f, s);
-  if (e == hipSuccess) e = launch_raster_bwd(v, *g, *proj, *lists, support, *saved, dF, dD, dA, w.g2d, gr->features, s);
-  if (e == hipSuccess) e = launch_project_bwd(v, *g, *proj, w.g2d, *gr, s);
+  // slot flags start cleared; the atomic part only exists where lidar tiles can be split
+  hipError_t e = launch_fill_i32((int32_t*)w.flags, div_up(lists->k_cap, 4), 0, s);
+  if (e == hipSuccess && v.has_lidar) e = launch_fill_f32(w.g2d, (int64_t)count * g->n * kNV, 0.f, s);
+  if (e == hipSuccess) e = launch_raster_bwd(v, *g, *proj, *lists, support, *saved, dF, dD, dA, w, gr->features, s);
+  if (e == hipSuccess) e = launch_project_bwd(v, *g, *proj, *lists, w, *gr, s);
   return dev_err(e);
 }
 
@@ -269,7 +282,7 @@ extern "C" {
 size_t splat_workspace_bytes(const SplatRig* r, int32_t first, int32_t count, int64_t n_gaussians, int64_t k_cap) {
   CallView v;
   if (make_view(r, first, count, -1, n_gaussians, v) != SPLAT_OK || k_cap < 0) return 0;
-  return carve_workspace(nullptr, (int64_t)count * n_gaussians, k_cap, v.n_tiles, v.n_rays).bytes;
+  return carve_workspace(nullptr, (int64_t)count * n_gaussians, k_cap, v.n_tiles, v.n_rays, v.c_max).bytes;
 }
 
 int splat_project(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count, const SplatProjected* out,
@@ -335,5 +348,99 @@ int splat_rasterize_bwd_lidar(const SplatGaussians* g, const SplatRig* r, int32_
   return raster_bwd_impl(g, r, first, count, kLidar, proj, lists, support, saved, d_feat, d_depth, d_alpha, grads,
                          ws, ws_bytes, stream);
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// Pipelines: one step captured into a hipGraph.
+// ---------------------------------------------------------------------------------------------
+struct SplatPipeline {
+  const SplatRig* rig = nullptr;
+  uint64_t layout_gen = 0;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void pipeline_free(SplatPipeline* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  delete p;
+}
+
+// The step's launches, in order, on `s` (validation included).
+static int step_launches(const SplatRig* r, int32_t first, int32_t count, const SplatStep* st, hipStream_t s) {
+  const bool bwd = (st->flags & SPLAT_STEP_BACKWARD) != 0;
+  const SplatGaussians* g = &st->gaussians;
+  if (st->status) {
+    hipError_t e = launch_fill_i32((int32_t*)st->status, sizeof(SplatStatus) / 4, 0, s);
+    if (e != hipSuccess) return dev_err(e);
+  }
+  if (bwd && (st->flags & SPLAT_STEP_ZERO_GRADS)) {
+    const SplatGrads& gr = st->grads;
+    const int64_t n = g->n;
+    if (!gr.means || !gr.log_scales || !gr.quats || !gr.opacities) return SPLAT_ERR_INVALID_ARG;
+    hipError_t e = launch_fill_f32(gr.means, 3 * n, 0.f, s);
+    if (e == hipSuccess) e = launch_fill_f32(gr.log_scales, 3 * n, 0.f, s);
+    if (e == hipSuccess) e = launch_fill_f32(gr.quats, 4 * n, 0.f, s);
+    if (e == hipSuccess) e = launch_fill_f32(gr.opacities, n, 0.f, s);
+    if (e == hipSuccess && gr.velocities) e = launch_fill_f32(gr.velocities, 3 * n, 0.f, s);
+    if (e == hipSuccess && gr.features) e = launch_fill_f32(gr.features, n * g->c_total, 0.f, s);
+    if (e != hipSuccess) return dev_err(e);
+  }
+  int rc = project_impl(g, r, first, count, -1, &st->proj, st->status, s);
+  if (!rc) rc = bin_sort_impl(r, first, count, -1, g->n, &st->proj, &st->lists, st->ws, st->ws_bytes, st->status, s);
+  if (!rc) rc = raster_fwd_impl(g, r, first, count, -1, &st->proj, &st->lists, st->support, &st->out, st->status, s);
+  if (!rc && bwd)
+    rc = raster_bwd_impl(g, r, first, count, -1, &st->proj, &st->lists, st->support, &st->out, st->d_feat,
+                         st->d_depth, st->d_alpha, &st->grads, st->ws, st->ws_bytes, s);
+  return rc;
+}
+
+extern "C" {
+
+int splat_pipeline_create(const SplatRig* r, int32_t first, int32_t count, const SplatStep* step,
+                          SplatPipeline** out) {
+  if (!out || !step) return SPLAT_ERR_INVALID_ARG;
+  *out = nullptr;
+  CallView v;
+  int rc = make_view(r, first, count, -1, step->gaussians.n, v);
+  if (rc) return rc;
+  SplatPipeline* p = new (std::nothrow) SplatPipeline();
+  if (!p) return SPLAT_ERR_DEVICE;
+  p->rig = r;
+  p->layout_gen = r->layout_gen;
+  if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+    pipeline_free(p);
+    return SPLAT_ERR_DEVICE;
+  }
+  if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    pipeline_free(p);
+    return SPLAT_ERR_DEVICE;
+  }
+  rc = step_launches(r, first, count, step, p->cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(p->cap, &graph);
+  p->graph = graph;
+  if (rc == SPLAT_OK && ec != hipSuccess) rc = SPLAT_ERR_DEVICE;
+  if (rc == SPLAT_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+    rc = SPLAT_ERR_DEVICE;
+  if (rc != SPLAT_OK) {
+    pipeline_free(p);
+    return rc;
+  }
+  *out = p;
+  return SPLAT_OK;
+}
+
+int splat_pipeline_run(SplatPipeline* p, void* stream) {
+  if (!p) return SPLAT_ERR_INVALID_ARG;
+  if (p->rig->layout_gen != p->layout_gen) return SPLAT_ERR_INVALID_ARG;
+  return dev_err(hipGraphLaunch(p->exec, (hipStream_t)stream));
+}
+
+void splat_pipeline_destroy(SplatPipeline* p) { pipeline_free(p); }
 
 }  // extern "C"

@@ -364,15 +364,6 @@ __global__ void k_finalize_count(const int64_t* __restrict__ total, int64_t k_ca
   }
 }
 
-__device__ __forceinline__ uint32_t tile_of(const DevSensor& S, int64_t base, const int4 r, int j) {
-  if (S.kind == kCamera) {
-    int tx = r.x + j % r.z, ty = r.y + j / r.z;
-    return (uint32_t)(base + (int64_t)ty * S.tiles_x + tx);
-  }
-  int a = (r.x + j % r.z) % S.m_az, e = r.y + j / r.z;
-  return (uint32_t)(base + (int64_t)e * S.m_az + a);
-}
-
 constexpr int kEmitTile = 2048;   // output slots per workgroup of the emit kernel
 
 // One thread per output slot: slot k belongs to the visible record r (depth order) with
@@ -418,9 +409,17 @@ __global__ __launch_bounds__(256) void k_emit(const DevSensor* __restrict__ sens
     const int jj = (int)(k - s_off[lo]);
     const int s = count == 1 ? 0 : (int)(rec / (uint32_t)N);
     const uint32_t g = rec - (uint32_t)s * (uint32_t)N;
-    keys[k] = tile_of(sens[s], local_tile_base(sens, s), rect[rec], jj);
+    keys[k] = (uint32_t)(local_tile_base(sens, s) + rect_tile(sens[s], rect[rec], jj));
     vals[k] = g;
   }
+}
+
+// entry_base[rec] = emission position of the record's first entry (depth order i -> record)
+__global__ void k_entry_base(const uint32_t* __restrict__ order, const int64_t* __restrict__ offs,
+                             const int64_t* __restrict__ n_vis, int64_t* __restrict__ entry_base) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *n_vis) return;
+  entry_base[order[i]] = offs[i];
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap, int2* __restrict__ range) {
@@ -541,7 +540,7 @@ __global__ void k_queue_gather(const int2* __restrict__ src, const uint32_t* __r
 // ------------------------------------------------------------------------------------------
 static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_tiles, int64_t n_rays) {
+Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_tiles, int64_t n_rays, int c_max) {
   Workspace w;
   char* p = (char*)base;
   size_t off = 0;
@@ -573,8 +572,14 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   w.wcount = (int64_t*)take((n_tiles + 2) * 8);
   w.wpart = (int64_t*)take((div_up(n_tiles + 2, kScanTile) + 2) * 8);
   w.scalars = (int64_t*)take(4 * 8);
-  w.g2d = (float*)take(nrec * 10 * 4);
-  w.bytes = off;
+  const size_t sort_bytes = off;
+  // adjoint buffers start over at the base
+  off = 0;
+  w.stride = slot_stride(cmax_bucket(c_max));
+  w.slots = (float*)take((size_t)kc * w.stride * 4);
+  w.flags = (uint8_t*)take((size_t)div_up(kc, 4) * 4);
+  w.g2d = (float*)take((size_t)nrec * kNV * 4);
+  w.bytes = off > sort_bytes ? off : sort_bytes;
   return w;
 }
 
@@ -603,6 +608,9 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
     return e;
   int64_t nb = div_up(n_rec, kScanTile);
   hipLaunchKernelGGL(k_finalize_count, dim3(1), dim3(1), 0, s, (const int64_t*)(w.scan_part + nb), L.k_cap, n_sort, st);
+  if (n_rec > 0)
+    hipLaunchKernelGGL(k_entry_base, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, order,
+                       (const int64_t*)w.offs, (const int64_t*)n_vis, L.entry_base);
   // 3. emit: the final tile-sort pass must land its values in lists->gauss
   const int tbits = bits_for(v.n_tiles);
   const int passes = (tbits + kRadixBits - 1) / kRadixBits;

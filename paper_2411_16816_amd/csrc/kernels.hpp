@@ -17,6 +17,17 @@ constexpr int kRadixBins = 1 << kRadixBits;
 
 inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Gradient values of one record read by the projection adjoint: mean.x, mean.y, vel.x, vel.y,
+// conic a, b, c, o_eff, depth (z | r), v_r.
+constexpr int kNV = 10;
+
+// channel counts are compiled in buckets
+inline int cmax_bucket(int c) { return c <= 4 ? 4 : c <= 8 ? 8 : c <= 16 ? 16 : c <= 32 ? 32 : 48; }
+
+// Floats per adjoint slot row: kNV geometric values then the bucket's channels, padded to a
+// float4 multiple.
+constexpr int slot_stride(int cmax_b) { return (kNV + cmax_b + 3) & ~3; }
+
 // Views of the device buffers of one call (local numbering), shared by the launchers.
 struct CallView {
   const DevSensor* sens;   // device table entries [first, first + count)
@@ -56,18 +67,21 @@ struct Workspace {
   uint32_t* qvals[2];
   int2* qtmp;             // [work_cap] unordered work items
   int64_t* scalars;       // [4] device scalars: clamped intersection count, visible records
-  // adjoint
-  float* g2d;             // [n_rec, 10]
+  // adjoint (overlays the bin/sort buffers: the two are never live in one call)
+  float* slots;           // [k_cap, slot_stride] per-entry gradient rows, indexed by emission position
+  uint8_t* flags;         // [k_cap] 1 = slot row written by this adjoint call
+  float* g2d;             // [n_rec, kNV] atomically accumulated part (lidar tiles split over items)
+  int stride;             // slot_stride(cmax_bucket(c_max))
   size_t bytes;
 };
 
-Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_tiles, int64_t n_rays);
+Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_tiles, int64_t n_rays, int c_max);
 
 // ---- launchers ------------------------------------------------------------------------------
 hipError_t launch_project(const CallView& v, const SplatGaussians& g, const SplatProjected& p, SplatStatus* st,
                           hipStream_t s);
-hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p, const float* g2d,
-                              const SplatGrads& gr, hipStream_t s);
+hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
+                              const SplatTileLists& L, const Workspace& w, const SplatGrads& gr, hipStream_t s);
 hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const SplatTileLists& L, const Workspace& w,
                            SplatStatus* st, hipStream_t s);
 hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
@@ -75,7 +89,7 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
                              hipStream_t s);
 hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
                              const SplatTileLists& L, int support, const SplatRenderOut& saved, const float* dF,
-                             const float* dD, const float* dA, float* g2d, float* dfeat, hipStream_t s);
+                             const float* dD, const float* dA, const Workspace& w, float* dfeat, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 

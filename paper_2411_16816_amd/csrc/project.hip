@@ -7,6 +7,7 @@
 // sensors reads the Gaussian arrays once instead of S times.  Records are written SoA
 // (record = sensor * N + gaussian); culled records only write n_tiles = 0.
 #include "kernels.hpp"
+#include "wave_ops.hpp"
 
 namespace splat {
 
@@ -75,7 +76,107 @@ __global__ __launch_bounds__(256) void k_project(const DevSensor* __restrict__ s
   if (nonfin && st) atomicAdd(&st->n_nonfinite, nonfin);
 }
 
-// g2d: per record (mean.x, mean.y, vel.x, vel.y, conic a, b, c, o_eff, depth (z | r), v_r)
+// Records with more entries than this are summed by the whole wavefront, shorter ones by their
+// own lane.
+constexpr int kCoopEntries = 32;
+
+template <int SW, int V>
+__device__ __forceinline__ void add_row(const float* __restrict__ row, float (&acc)[V]) {
+  const float4* q = reinterpret_cast<const float4*>(row);
+#pragma unroll
+  for (int u = 0; u < SW / 4; ++u) {
+    const float4 x = q[u];
+    if (4 * u + 0 < V) acc[4 * u + 0] += x.x;
+    if (4 * u + 1 < V) acc[4 * u + 1] += x.y;
+    if (4 * u + 2 < V) acc[4 * u + 2] += x.z;
+    if (4 * u + 3 < V) acc[4 * u + 3] += x.w;
+  }
+}
+
+// Wavefront-scope ordering of LDS accesses between lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Gradient of every record, one thread per Gaussian and sensor loop: the sum of the
+// rasteriser's rows over the record's entries (positions [entry_base, entry_base + n_tiles) of
+// the slot array, rows whose flag is set), taken in a fixed order so that the result does not
+// depend on scheduling.  The geometric part (kNV values) goes to g2d[rec] (added to the atomic
+// part of split lidar tiles when `accumulate`), the channel part to the features gradient.
+template <int CMAX>
+__global__ __launch_bounds__(256) void k_slot_reduce(const DevSensor* __restrict__ sens, int count, int64_t N,
+                                                     int c_total, const int32_t* __restrict__ n_tiles,
+                                                     const int64_t* __restrict__ entry_base,
+                                                     const float* __restrict__ slots,
+                                                     const uint8_t* __restrict__ flags, int64_t k_cap,
+                                                     bool accumulate, float* __restrict__ g2d,
+                                                     float* __restrict__ dfeat) {
+  constexpr int V = kNV + CMAX;
+  constexpr int SW = slot_stride(CMAX);
+  __shared__ float s_red[4][V];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < N;
+  if (__ballot(live) == 0) return;   // uniform over the wavefront
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  bool store;
+  const int my_idx = scatter_slot<V>(lane, store);
+  for (int k = 0; k < count; ++k) {
+    const int64_t r = (int64_t)k * N + i;
+    const int nt = live ? n_tiles[r] : 0;
+    int64_t base = 0;
+    int n = 0;
+    if (nt > 0) {
+      base = entry_base[r];
+      const int64_t room = k_cap - base;   // entries at or beyond k_cap were never listed
+      n = room <= 0 ? 0 : (nt < room ? nt : (int)room);
+    }
+    float acc[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = 0.f;
+    const bool coop = n > kCoopEntries;
+    if (!coop) {
+      for (int j = 0; j < n; ++j)
+        if (flags[base + j]) add_row<SW>(slots + (base + j) * SW, acc);
+    }
+    uint64_t m = __ballot(coop);
+    while (m) {
+      const int L = __builtin_ctzll(m);
+      m &= m - 1;
+      const int64_t bL = ((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)base, L)) |
+                         ((int64_t)__builtin_amdgcn_readlane((int)(base >> 32), L) << 32);
+      const int nL = __builtin_amdgcn_readlane(n, L);
+      float part[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) part[v] = 0.f;
+      for (int j = lane; j < nL; j += 64)
+        if (flags[bL + j]) add_row<SW>(slots + (bL + j) * SW, part);
+      const float sum = wave_reduce_scatter<V>(part);
+      if (store) s_red[wv][my_idx] = sum;
+      wave_sync();
+      if (lane == L) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = s_red[wv][v];
+      }
+      wave_sync();
+    }
+    if (nt <= 0) continue;
+    float* q = g2d + r * kNV;
+#pragma unroll
+    for (int v = 0; v < kNV; ++v) q[v] = accumulate ? q[v] + acc[v] : acc[v];
+    if (dfeat) {
+      const DevSensor& S = sens[k];
+      float* fp = dfeat + i * c_total + S.feat_off;
+#pragma unroll
+      for (int c = 0; c < CMAX; ++c)
+        if (c < S.n_ch) fp[c] += acc[kNV + c];
+    }
+  }
+}
+
+// Projection adjoint, one thread per Gaussian: chains every record's g2d gradient (mean.x,
+// mean.y, vel.x, vel.y, conic a, b, c, o_eff, depth (z | r), v_r) through the projection.
 __global__ __launch_bounds__(256) void k_project_bwd(const DevSensor* __restrict__ sens, int count, SplatGaussians g,
                                                      const int32_t* __restrict__ n_tiles, const float* __restrict__ g2d,
                                                      SplatGrads gr) {
@@ -92,7 +193,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const DevSensor* __restrict
   for (int k = 0; k < count; ++k) {
     const int64_t r = (int64_t)k * g.n + i;
     if (n_tiles[r] <= 0) continue;
-    const float* q = g2d + r * 10;
+    const float* q = g2d + r * kNV;
     RecGrad rg;
     rg.mean[0] = q[0]; rg.mean[1] = q[1]; rg.vel[0] = q[2]; rg.vel[1] = q[3];
     rg.conic[0] = q[4]; rg.conic[1] = q[5]; rg.conic[2] = q[6]; rg.o_eff = q[7];
@@ -123,11 +224,29 @@ hipError_t launch_project(const CallView& v, const SplatGaussians& g, const Spla
   return hipGetLastError();
 }
 
-hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p, const float* g2d,
-                              const SplatGrads& gr, hipStream_t s) {
+hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
+                              const SplatTileLists& L, const Workspace& w, const SplatGrads& gr, hipStream_t s) {
   if (g.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)div_up(g.n, 256)), dim3(256), 0, s, v.sens, v.count, g,
-                     (const int32_t*)p.n_tiles, g2d, gr);
+  const int cm = cmax_bucket(v.c_max);
+  if (w.stride != slot_stride(cm)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)div_up(g.n, 256));
+  float* dfeat = v.c_max > 0 ? gr.features : nullptr;
+#define SR_CASE(CM)                                                                                               \
+  case CM:                                                                                                        \
+    hipLaunchKernelGGL(k_slot_reduce<CM>, grid, dim3(256), 0, s, v.sens, v.count, g.n, g.c_total,                 \
+                       (const int32_t*)p.n_tiles, (const int64_t*)L.entry_base, (const float*)w.slots,            \
+                       (const uint8_t*)w.flags, L.k_cap, v.has_lidar, w.g2d, dfeat);                              \
+    break;
+  switch (cm) {
+    SR_CASE(4)
+    SR_CASE(8)
+    SR_CASE(16)
+    SR_CASE(32)
+    SR_CASE(48)
+  }
+#undef SR_CASE
+  hipLaunchKernelGGL(k_project_bwd, grid, dim3(256), 0, s, v.sens, v.count, g, (const int32_t*)p.n_tiles,
+                     (const float*)w.g2d, gr);
   return hipGetLastError();
 }
 

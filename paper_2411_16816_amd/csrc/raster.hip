@@ -11,13 +11,14 @@
 //
 // The adjoint walks the same list back to front from each ray's `last`, recovering
 // T_i = T_{i+1} / (1 - alpha_i) from the saved final transmittance.  Per-Gaussian gradients
-// are summed across the wavefront with DPP row operations, across the workgroup in LDS, and
-// reach global memory with one atomic per (Gaussian, tile, value).
+// are summed across the wavefront (reduce-scatter over permlane swaps and DPP), across the
+// workgroup in LDS, and stored as one row per (tile, Gaussian) entry at the entry's emission
+// position, where the projection adjoint sums each record's rows in a fixed order.  Only work
+// items of lidar tiles split over several items add their rows with global atomics.
 #include "kernels.hpp"
+#include "wave_ops.hpp"
 
 namespace splat {
-
-constexpr int kNV = 10;   // geometric gradient values per record (see k_project_bwd)
 
 struct RasterArgs {
   const DevSensor* sens;
@@ -30,6 +31,8 @@ struct RasterArgs {
   const float2* dv;
   const int32_t* gauss;
   const int2* tile_range;
+  const int4* rect;
+  const int64_t* entry_base;
   const float* features;
   int c_total;
   const int32_t* ray_order;
@@ -54,8 +57,10 @@ struct BwdIn {
   const float* dF;
   const float* dD;
   const float* dA;
-  float* g2d;
-  float* dfeat;
+  float* slots;      // [k_cap, slot_stride] rows written by work items that own their tile
+  uint8_t* flags;    // [k_cap] set for every row written
+  float* g2d;        // [n_rec, kNV] atomic part from work items of split lidar tiles
+  float* dfeat;      // features gradient (atomic part, split lidar tiles)
 };
 
 __device__ __forceinline__ int sensor_of_tile(const DevSensor* sens, int count, int64_t t) {
@@ -305,93 +310,6 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd_queue(RasterArgs a, FwdOu
 // ------------------------------------------------------------------------------------------
 // adjoint
 // ------------------------------------------------------------------------------------------
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
-}
-
-// Wavefront reduce-scatter of V values per lane (V <= 64).  Six levels, one per lane-index bit
-// (5 down to 0): at a level with M values per lane, the lanes whose bit is 0 keep positions
-// [0, H) and the others positions [H, M), H = ceil(M / 2) (a missing upper partner is a zero),
-// each adding its partner lane's copy.  Bit 5 moves data with v_permlane32_swap, bit 4 with
-// v_permlane16_swap, bits 3..0 with DPP row_mirror, row_half_mirror and quad permutations.
-// Once one value is left the remaining levels are plain sums.  About 2 V instructions in all,
-// against 6 V for V separate wavefront reductions; scatter_slot() tells each lane which value
-// it ends up holding.
-constexpr int rs_half(int m) { return m > 1 ? (m + 1) / 2 : 1; }
-
-template <int M, int N>
-__device__ __forceinline__ void rs_swap32(float (&v)[N]) {
-  constexpr int H = rs_half(M);
-#pragma unroll
-  for (int i = 0; i < H; ++i) {
-    const float hi = (M == 1) ? v[0] : ((i + H < M) ? v[i + H] : 0.f);
-    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(hi), false, false);
-    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
-}
-
-template <int M, int N>
-__device__ __forceinline__ void rs_swap16(float (&v)[N]) {
-  constexpr int H = rs_half(M);
-#pragma unroll
-  for (int i = 0; i < H; ++i) {
-    const float hi = (M == 1) ? v[0] : ((i + H < M) ? v[i + H] : 0.f);
-    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(hi), false, false);
-    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
-}
-
-template <int CTRL, int M, int N>
-__device__ __forceinline__ void rs_dpp(float (&v)[N], bool bit) {
-  if constexpr (M == 1) {
-    v[0] += dpp_f<CTRL>(v[0]);
-  } else {
-    constexpr int H = rs_half(M);
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-      const float a = v[i];
-      const float b = (i + H < M) ? v[i + H] : 0.f;
-      const float keep = bit ? b : a;
-      const float send = bit ? a : b;
-      v[i] = keep + dpp_f<CTRL>(send);
-    }
-  }
-}
-
-template <int V, int N>
-__device__ __forceinline__ float wave_reduce_scatter(float (&v)[N]) {
-  static_assert(V >= 1 && V <= 64 && N >= V, "V");
-  const int lane = threadIdx.x & 63;
-  constexpr int M1 = rs_half(V), M2 = rs_half(M1), M3 = rs_half(M2), M4 = rs_half(M3), M5 = rs_half(M4);
-  rs_swap32<V>(v);                                  // bit 5
-  rs_swap16<M1>(v);                                 // bit 4
-  rs_dpp<0x140, M2>(v, (lane >> 3) & 1);            // bit 3: row_mirror (i <-> 15 - i)
-  rs_dpp<0x141, M3>(v, (lane >> 2) & 1);            // bit 2: row_half_mirror (i <-> 7 - i)
-  rs_dpp<0x4E, M4>(v, (lane >> 1) & 1);             // bit 1: quad_perm [2,3,0,1]
-  rs_dpp<0xB1, M5>(v, lane & 1);                    // bit 0: quad_perm [1,0,3,2]
-  return v[0];
-}
-
-// Which value lane `lane` holds after wave_reduce_scatter<V>, and whether it should store it
-// (one lane per value).
-template <int V>
-__device__ __forceinline__ int scatter_slot(int lane, bool& store) {
-  int m = V, real = V, pos = 0;
-  bool first = true;   // first lane of a group that holds the same value after plain levels
-  for (int b = 5; b >= 0; --b) {
-    const bool bit = (lane >> b) & 1;
-    if (m > 1) {
-      const int h = (m + 1) / 2;
-      if (bit) { pos += h; real -= h; } else { real = real < h ? real : h; }
-      m = h;
-    } else {
-      first = first && !bit;
-    }
-  }
-  store = first && real >= 1;
-  return pos;
-}
 
 template <int CMAX>
 struct BwdShape {
@@ -450,6 +368,10 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
   __syncthreads();           // everyone has read maxlast before it can be reset by the next item
   if (n_proc == 0) return;   // uniform
   const DevSensor& S = a.sens[c.s];
+  const int64_t tile_local = tile - (S.tile_base - a.sens[0].tile_base);
+  // a lidar tile with more rays than one item holds is shared by several items
+  const bool split = LIDAR && (a.ray_range[tile].y - a.ray_range[tile].x > SPLAT_RAYS_PER_ITEM);
+  constexpr int SW = slot_stride(CMAX);
   bool my_store;
   const int my_idx = scatter_slot<SH::V>(lane, my_store);
   float S_dot = 0.f;   // sum_c buf_c dF_c, the feature part of the colour behind this Gaussian
@@ -517,18 +439,29 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
     if (tid < nb && s_used[tid]) {
       const int64_t g = a.gauss[b0 + tid];
       const int64_t rec = (int64_t)c.s * a.N + g;
-      float* gp = b.g2d + rec * kNV;
+      if (!split) {
+        // this item is the only one of its tile: the entry's row is complete, store it
+        const int64_t p = a.entry_base[rec] + rect_entry(S, a.rect[rec], tile_local);
+        float4* row = reinterpret_cast<float4*>(b.slots + p * SW);
 #pragma unroll
-      for (int k = 0; k < kNV; ++k) {
-        atomicAdd(gp + k, s_acc[k][tid]);
-        s_acc[k][tid] = 0.f;
-      }
-      float* fp = b.dfeat + g * a.c_total + S.feat_off;
+        for (int q = 0; q < SW / 4; ++q) {
+          float x[4];
 #pragma unroll
-      for (int k = 0; k < CMAX; ++k) {
-        if (k < c.C) atomicAdd(fp + k, s_acc[kNV + k][tid]);
-        s_acc[kNV + k][tid] = 0.f;
+          for (int u = 0; u < 4; ++u) x[u] = (4 * q + u < SH::V) ? s_acc[4 * q + u][tid] : 0.f;
+          row[q] = make_float4(x[0], x[1], x[2], x[3]);
+        }
+        b.flags[p] = 1;
+      } else {
+        float* gp = b.g2d + rec * kNV;
+#pragma unroll
+        for (int k = 0; k < kNV; ++k) atomicAdd(gp + k, s_acc[k][tid]);
+        float* fp = b.dfeat + g * a.c_total + S.feat_off;
+#pragma unroll
+        for (int k = 0; k < CMAX; ++k)
+          if (k < c.C) atomicAdd(fp + k, s_acc[kNV + k][tid]);
       }
+#pragma unroll
+      for (int k = 0; k < SH::V; ++k) s_acc[k][tid] = 0.f;
       s_used[tid] = 0;
     }
     __syncthreads();
@@ -576,6 +509,8 @@ static RasterArgs make_args(const CallView& v, const SplatGaussians& g, const Sp
   a.dv = (const float2*)p.dv;
   a.gauss = L.gauss;
   a.tile_range = (const int2*)L.tile_range;
+  a.rect = (const int4*)p.rect;
+  a.entry_base = L.entry_base;
   a.features = g.features;
   a.c_total = g.c_total;
   a.ray_order = L.ray_order;
@@ -624,8 +559,6 @@ static void bwd_queue_launch(const CallView& v, int64_t items, hipStream_t s, co
   auto k = k_raster_bwd_queue<CMAX, TILE>;
   hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items)), dim3(kBlock), 0, s, a, b, counter);
 }
-
-static int cmax_bucket(int c) { return c <= 4 ? 4 : c <= 8 ? 8 : c <= 16 ? 16 : c <= 32 ? 32 : 48; }
 
 hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
                              const SplatTileLists& L, int support, const SplatRenderOut& out, SplatStatus* st,
@@ -676,10 +609,11 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
 
 hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
                              const SplatTileLists& L, int support, const SplatRenderOut& saved, const float* dF,
-                             const float* dD, const float* dA, float* g2d, float* dfeat, hipStream_t s) {
+                             const float* dD, const float* dA, const Workspace& w, float* dfeat, hipStream_t s) {
   RasterArgs a = make_args(v, g, p, L);
-  BwdIn b{saved.t_final, saved.last, dF, dD, dA, g2d, dfeat};
+  BwdIn b{saved.t_final, saved.last, dF, dD, dA, w.slots, w.flags, w.g2d, dfeat};
   const int cm = cmax_bucket(v.c_max);
+  if (w.stride != slot_stride(cm)) return hipErrorInvalidValue;
   if (v.queue) {
     const int64_t items = L.work_cap;
     if (items <= 0) return hipSuccess;

@@ -308,6 +308,29 @@ HD void lidar_rect(const DevSensor& S, ProjOut& o) {
   o.n_tiles = n * ne;
 }
 
+// Tile (sensor-local id) of the j-th entry of a record's rectangle r = (x0, y0, w, h): entries
+// are numbered row-major, and lidar azimuth tiles wrap modulo M_phi.
+HD int64_t rect_tile(const DevSensor& S, const int4 r, int j) {
+  if (S.kind == kCamera) {
+    const int tx = r.x + j % r.z, ty = r.y + j / r.z;
+    return (int64_t)ty * S.tiles_x + tx;
+  }
+  const int a = (r.x + j % r.z) % S.m_az, e = r.y + j / r.z;
+  return (int64_t)e * S.m_az + a;
+}
+
+// Inverse of rect_tile: the entry number of sensor-local tile t inside rectangle r.
+HD int rect_entry(const DevSensor& S, const int4 r, int64_t t) {
+  if (S.kind == kCamera) {
+    const int tx = (int)(t % S.tiles_x), ty = (int)(t / S.tiles_x);
+    return (ty - r.y) * r.z + (tx - r.x);
+  }
+  const int a = (int)(t % S.m_az), e = (int)(t / S.m_az);
+  int da = a - r.x;
+  if (da < 0) da += S.m_az;
+  return (e - r.y) * r.z + da;
+}
+
 // Full forward projection of Gaussian (mu_w, M, vg, opac) into sensor S.  n_tiles = 0 = culled.
 HD void project_one(const DevSensor& S, const float mu_w[3], const float M[9], const float vg[3], float opac,
                     ProjInter& I, ProjOut& o) {

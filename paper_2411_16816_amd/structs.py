@@ -56,7 +56,7 @@ class SplatProjected(C.Structure):
 
 class SplatTileLists(C.Structure):
     _fields_ = [("k_cap", C.c_int64), ("gauss", C.c_void_p), ("tile_range", C.c_void_p),
-                ("ray_order", C.c_void_p), ("ray_range", C.c_void_p), ("work", C.c_void_p),
+                ("entry_base", C.c_void_p), ("ray_order", C.c_void_p), ("ray_range", C.c_void_p), ("work", C.c_void_p),
                 ("n_work", C.c_void_p), ("work_cap", C.c_int64)]
 
 
@@ -108,3 +108,14 @@ def lidar_struct(lid, ray_ptrs=(None, None, None), bounds_keepalive=None) -> Spl
     s.ray_az, s.ray_el, s.ray_t = ray_ptrs
     s.feat_offset, s.n_channels = int(lid.feat_offset), int(lid.n_channels)
     return s
+
+
+SPLAT_STEP_BACKWARD = 1
+SPLAT_STEP_ZERO_GRADS = 2
+
+
+class SplatStep(C.Structure):
+    _fields_ = [("gaussians", SplatGaussians), ("proj", SplatProjected), ("lists", SplatTileLists),
+                ("out", SplatRenderOut), ("support", C.c_int32), ("flags", C.c_int32),
+                ("d_feat", C.c_void_p), ("d_depth", C.c_void_p), ("d_alpha", C.c_void_p),
+                ("grads", SplatGrads), ("ws", C.c_void_p), ("ws_bytes", C.c_size_t), ("status", C.c_void_p)]

@@ -77,3 +77,34 @@ def test_rig_create_rejects_bad_counts_without_device():
     assert lib.splat_rig_create(-1, 2, C.byref(h)) == 1
     assert lib.splat_rig_create(2000, 0, C.byref(h)) == 1
     assert lib.splat_workspace_bytes(None, 0, 1, 10, 10) == 0
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """sizeof / offsetof of every public struct, compiled from include/splat.h with gcc, against
+    the ctypes mirrors the binding passes across the ABI."""
+    from paper_2411_16816_amd import structs as st
+    mirrors = [st.SplatStatus, st.SplatGaussians, st.SplatCamera, st.SplatLidar, st.SplatRigLayout,
+               st.SplatProjected, st.SplatTileLists, st.SplatRenderOut, st.SplatGrads, st.SplatStep]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "splat.h"', "int main(void) {"]
+    for m in mirrors:
+        n = m.__name__
+        lines.append(f'  printf("{n} size %zu\\n", sizeof({n}));')
+        for f in m._fields_:
+            lines.append(f'  printf("{n} {f[0]} %zu\\n", offsetof({n}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, v = line.split()
+            got[(a, b)] = int(v)
+    for m in mirrors:
+        n = m.__name__
+        assert got[(n, "size")] == C.sizeof(m), n
+        for f in m._fields_:
+            assert got[(n, f[0])] == getattr(m, f[0]).offset, (n, f[0])

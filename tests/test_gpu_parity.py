@@ -395,7 +395,7 @@ def test_batched_queue_equals_plain():
 # ------------------------------------------------------------------------------------------
 # a7: adjoint
 # ------------------------------------------------------------------------------------------
-def _grad_check(kind, seed):
+def _grad_check(kind, seed, lidar_tile_az=16):
     b = _binding()
     rng = np.random.default_rng(seed)
     if kind == "camera":
@@ -405,7 +405,7 @@ def _grad_check(kind, seed):
         mu = np.stack([rng.uniform(2, 12, n), rng.uniform(-5, 5, n), rng.uniform(-3.5, 3.5, n)], 1)
         rig = b.Rig([sensor], [])
     else:
-        sensor = S.make_lidar((0, 0, 0), 0.0, 16, -15.0, 15.0, 256, tile_az=16, tile_el=8, t_sweep=0.1,
+        sensor = S.make_lidar((0, 0, 0), 0.0, 16, -15.0, 15.0, 256, tile_az=lidar_tile_az, tile_el=8, t_sweep=0.1,
                               ego_vel_world=(10.0, 1.0, 0), feat_offset=3, n_channels=8)
         n = 300
         mu = np.stack([rng.uniform(-10, 10, n), rng.uniform(-10, 10, n), rng.uniform(-1.5, 1.5, n)], 1)
@@ -455,6 +455,11 @@ def test_backward_camera():
 
 def test_backward_lidar():
     _grad_check("lidar", 8)
+
+
+def test_backward_lidar_split_tiles():
+    """64 x 8 = 512 rays per tile: every tile is two work items, whose gradients add atomically."""
+    _grad_check("lidar", 9, lidar_tile_az=64)
 
 
 def test_autograd_function_camera():
