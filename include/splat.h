@@ -144,9 +144,11 @@ typedef struct SplatProjected {
   float* cn;        /* [n_records,4] conic (a,b,c) of (Sigma + sI)^-1 = [[a,b],[b,c]], o_eff    */
   float* box;       /* [n_records,4] lo_u, lo_v, hi_u, hi_v of the 3-sigma + RS box          */
   float* dv;        /* [n_records,2] depth (z | range) and range velocity (lidar; 0 camera)    */
-  unsigned long long* dkey; /* [n_records] depth sort key: IEEE bits of the depth (z | range)
-                       evaluated in float64 from the float32 inputs; Gaussians are ordered by
-                       its upper 48 bits (2^-36 relative), ties by Gaussian id               */
+  unsigned long long* dkey; /* [n_records] IEEE bits of the depth (z | range) evaluated in
+                       float64 from the float32 inputs.  Gaussians are ordered by the 40-bit
+                       key (e << 35) | (mantissa >> 17), e = binary exponent + 16 clamped to
+                       [0, 31] (key 0 below 2^-16, all ones from 2^16 on): 2^-35 relative
+                       resolution; equal keys keep Gaussian-id order                        */
   int32_t* rect;    /* [n_records,4] tiles: camera (x0, y0, nx, ny); lidar (az0, el0, naz, nel) */
   int32_t* n_tiles; /* [n_records] tiles touched (0 = culled)                                 */
 } SplatProjected;

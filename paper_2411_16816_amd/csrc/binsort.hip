@@ -204,37 +204,45 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
   const uint32_t mask = (1u << bits) - 1u;
   const uint64_t lt = lanemask_lt();
   if (base < n) {
+    // all loads first (independent), then the ranking
+    uint32_t d[kScanItems];
+#pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
-      int64_t i = base + (int64_t)r * kScanThreads + tid;
-      if (base + (int64_t)r * kScanThreads >= n) break;
-      bool valid = i < n;
-      uint32_t d = valid ? ((uint32_t)(keys[i] >> shift) & mask) : 0u;
-      uint64_t m = match_digit(d, valid, bits);
-      if (valid && (m & lt) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(m));
+      const int64_t i = base + (int64_t)r * kScanThreads + tid;
+      d[r] = i < n ? ((uint32_t)(keys[i] >> shift) & mask) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+      if (base + (int64_t)r * kScanThreads >= n) break;   // uniform over the block
+      const bool valid = base + (int64_t)r * kScanThreads + tid < n;
+      const uint64_t m = match_digit(d[r], valid, bits);
+      if (valid && (m & lt) == 0) atomicAdd(&cnt[d[r]], (uint32_t)__popcll(m));
     }
   }
   __syncthreads();
   hist[(int64_t)tid * nb + blockIdx.x] = cnt[tid];
 }
 
-// Stable scatter of one block tile (4096 keys).  Every key is ranked inside the block by
-// digit (64-lane ballot matching, per-wave counts, running counts per digit), staged in LDS in
-// digit order, and written out so that consecutive lanes write consecutive addresses of a
-// digit's output run (coalesced), at the block's global digit offsets from the scanned
-// histogram.
+// Stable scatter of one block tile (4096 keys).  Wavefront w owns the contiguous quarter
+// [1024 w, 1024 w + 1024) of the tile and walks it in 16 rounds of 64 keys: ballot matching of
+// the digit gives each key its rank among the round's equal digits, and a wave-private running
+// count per digit (LDS, touched only by that wavefront) carries the rank across rounds.  One
+// block scan then turns (digit, wavefront) counts into offsets, keys are staged in LDS in digit
+// order and written out so that consecutive lanes write consecutive addresses of a digit's
+// output run (coalesced), at the block's global digit offsets from the scanned histogram.
 template <typename K>
 __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                        K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                        const int64_t* n_ptr, int64_t n_cap, int shift, int bits,
                                                        const uint32_t* __restrict__ hist, int64_t nb) {
+  constexpr int kPerWave = kScanTile / 4;
   __shared__ K s_k[kScanTile];
   __shared__ uint32_t s_v[kScanTile];
   __shared__ uint32_t gbase[kRadixBins];
   __shared__ uint32_t lcum[kRadixBins];
-  __shared__ uint32_t run[kRadixBins];
-  __shared__ uint32_t wc[4][kRadixBins];
+  __shared__ uint32_t wc[4][kRadixBins];   // per-wavefront running counts, then offsets
   __shared__ uint32_t tmp[4];
-  const int tid = threadIdx.x, wid = tid >> 6;
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
   const int64_t n = sort_count(n_ptr, n_cap);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   if (base >= n) return;   // uniform over the block
@@ -242,50 +250,53 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   const uint32_t mask = (1u << bits) - 1u;
   const uint64_t lt = lanemask_lt();
   gbase[tid] = hist[(int64_t)tid * nb + blockIdx.x];
-  run[tid] = 0u;
   wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
   K key[kScanItems];
-  uint32_t val[kScanItems];
+  uint32_t val[kScanItems], rank[kScanItems];
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
-    const int li = r * kScanThreads + tid;
+    const int li = wid * kPerWave + r * 64 + lane;
     key[r] = li < cnt ? kin[base + li] : (K)0;
     val[r] = li < cnt ? vin[base + li] : 0u;
   }
   __syncthreads();
-  // block-local digit counts
+  uint32_t* run = wc[wid];
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
-    const bool valid = r * kScanThreads + tid < cnt;
+    const bool valid = wid * kPerWave + r * 64 + lane < cnt;
     const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
     const uint64_t m = match_digit(d, valid, bits);
-    if (valid && (m & lt) == 0) atomicAdd(&run[d], (uint32_t)__popcll(m));
+    const uint32_t before = valid ? run[d] : 0u;
+    rank[r] = before + (uint32_t)__popcll(m & lt);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (valid && (m & lt) == 0) run[d] = before + (uint32_t)__popcll(m);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   __syncthreads();
+  // digit totals -> block offsets; per-wavefront offsets inside each digit
+  const uint32_t c0 = wc[0][tid], c1 = wc[1][tid], c2 = wc[2][tid], c3 = wc[3][tid];
   uint32_t total;
-  lcum[tid] = block_exclusive_scan<uint32_t>(run[tid], tmp, total);
-  run[tid] = 0u;
+  const uint32_t dcum = block_exclusive_scan<uint32_t>(c0 + c1 + c2 + c3, tmp, total);
+  lcum[tid] = dcum;
+  wc[0][tid] = dcum;
+  wc[1][tid] = dcum + c0;
+  wc[2][tid] = dcum + c0 + c1;
+  wc[3][tid] = dcum + c0 + c1 + c2;
   __syncthreads();
-  // stable ranks -> LDS in digit order
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
-    const bool valid = r * kScanThreads + tid < cnt;
-    const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
-    const uint64_t m = match_digit(d, valid, bits);
-    const uint32_t rank = (uint32_t)__popcll(m & lt);
-    if (valid && rank == 0) wc[wid][d] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (valid) {
-      uint32_t li = lcum[d] + run[d] + rank;
-      for (int w = 0; w < wid; ++w) li += wc[w][d];
+    if (wid * kPerWave + r * 64 + lane < cnt) {
+      const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
+      const uint32_t li = wc[wid][d] + rank[r];
       s_k[li] = key[r];
       s_v[li] = val[r];
     }
-    __syncthreads();
-    run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
-    wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
-    __syncthreads();
   }
+  __syncthreads();
   // coalesced write-out
   for (int i = tid; i < cnt; i += kScanThreads) {
     const K k = s_k[i];
@@ -340,8 +351,17 @@ struct LoadVisible {
   __device__ int64_t operator()(int64_t i) const { return n_tiles[i] > 0 ? 1 : 0; }
 };
 
-constexpr int kDepthKeyShift = 16;   // drop the 16 lowest mantissa bits: 2^-36 relative resolution
-constexpr int kDepthKeyBits = 48;
+// 40-bit sort key of a positive float64 depth: 5 bits of binary exponent over [2^-16, 2^16)
+// and the top 35 mantissa bits (2^-35 relative resolution), monotone in the depth; depths
+// outside that range clamp to the first / last key (ties then keep Gaussian-id order).
+constexpr int kDepthKeyBits = 40;
+
+__device__ __forceinline__ uint64_t depth_sort_key(unsigned long long bits) {
+  const int e = (int)((bits >> 52) & 0x7FF) - (1023 - 16);
+  if (e < 0) return 0ull;
+  if (e > 31) return (1ull << kDepthKeyBits) - 1ull;
+  return ((uint64_t)e << 35) | ((bits & 0xFFFFFFFFFFFFFull) >> 17);
+}
 
 __global__ void k_compact_visible(const int32_t* __restrict__ n_tiles, const unsigned long long* __restrict__ dkey,
                                   const int64_t* __restrict__ pos, int64_t n_rec, uint64_t* __restrict__ keys,
@@ -349,7 +369,7 @@ __global__ void k_compact_visible(const int32_t* __restrict__ n_tiles, const uns
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_rec || n_tiles[i] <= 0) return;
   int64_t p = pos[i];
-  keys[p] = (uint64_t)dkey[i];
+  keys[p] = depth_sort_key(dkey[i]);
   vals[p] = (uint32_t)i;
 }
 
@@ -368,30 +388,22 @@ constexpr int kEmitTile = 2048;   // output slots per workgroup of the emit kern
 
 // One thread per output slot: slot k belongs to the visible record r (depth order) with
 // offs[r] <= k < offs[r + 1], found by a binary search over the offsets of the records that
-// overlap the workgroup's slots (staged in LDS); the slot's tile is the (k - offs[r])-th tile
-// of that record's rectangle.  Writes are contiguous across lanes.
+// overlap the workgroup's slots (staged in LDS, starting at the block's first record bstart);
+// the slot's tile is the (k - offs[r])-th tile of that record's rectangle.  Writes are
+// contiguous across lanes.
 __global__ __launch_bounds__(256) void k_emit(const DevSensor* __restrict__ sens, int count, int64_t N,
                                               const int4* __restrict__ rect, const uint32_t* __restrict__ order,
                                               const int64_t* __restrict__ offs, const int64_t* __restrict__ n_vis,
-                                              const int64_t* __restrict__ n_slots, uint32_t* __restrict__ keys,
+                                              const int64_t* __restrict__ n_slots,
+                                              const int64_t* __restrict__ bstart, uint32_t* __restrict__ keys,
                                               uint32_t* __restrict__ vals) {
   __shared__ int64_t s_off[kEmitTile + 1];
-  __shared__ int64_t s_r0;
   const int tid = threadIdx.x;
   const int64_t K = *n_slots;
   const int64_t k0 = (int64_t)blockIdx.x * kEmitTile;
   if (k0 >= K) return;   // uniform
   const int64_t nv = *n_vis;
-  if (tid == 0) {
-    int64_t lo = 0, hi = nv - 1;   // last record with offs[r] <= k0 (every visible record has >= 1 slot)
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (offs[mid] <= k0) lo = mid; else hi = mid - 1;
-    }
-    s_r0 = lo;
-  }
-  __syncthreads();
-  const int64_t r0 = s_r0;
+  const int64_t r0 = bstart[blockIdx.x];   // last record with offs[r] <= k0
   for (int i = tid; i <= kEmitTile; i += 256) {
     const int64_t r = r0 + i;
     s_off[i] = r < nv ? offs[r] : INT64_MAX;
@@ -415,20 +427,40 @@ __global__ __launch_bounds__(256) void k_emit(const DevSensor* __restrict__ sens
 }
 
 // entry_base[rec] = emission position of the record's first entry (depth order i -> record)
+// Per visible record (depth order i): entry_base[record] = offs[i], and the first record of
+// every emit block whose first slot falls in the record's range [offs[i], offs[i + 1]).
 __global__ void k_entry_base(const uint32_t* __restrict__ order, const int64_t* __restrict__ offs,
-                             const int64_t* __restrict__ n_vis, int64_t* __restrict__ entry_base) {
+                             const int64_t* __restrict__ n_vis, const int64_t* __restrict__ total, int64_t n_rec,
+                             int64_t n_blocks, int64_t* __restrict__ entry_base, int64_t* __restrict__ bstart) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= *n_vis) return;
-  entry_base[order[i]] = offs[i];
+  const int64_t a = offs[i];
+  const int64_t b = i + 1 < n_rec ? offs[i + 1] : *total;
+  entry_base[order[i]] = a;
+  for (int64_t kb = (a + kEmitTile - 1) / kEmitTile; kb < n_blocks && kb * kEmitTile < b; ++kb) bstart[kb] = i;
 }
 
+constexpr int kRangeItems = 8;   // sorted keys per thread of k_ranges
+
+// [start, end) of every key's run in a sorted key array; keys that do not occur keep the range
+// the caller filled in.
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap, int2* __restrict__ range) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t n = sort_count(n_ptr, n_cap);
-  if (i >= n) return;
-  uint32_t t = keys[i];
-  if (i == 0 || keys[i - 1] != t) range[t].x = (int)i;
-  if (i == n - 1 || keys[i + 1] != t) range[t].y = (int)(i + 1);
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeItems;
+  const int64_t n = sort_count(n_ptr, n_cap);
+  if (i0 >= n) return;
+  uint32_t k[kRangeItems + 2];
+#pragma unroll
+  for (int j = 0; j < kRangeItems + 2; ++j) {
+    const int64_t i = i0 - 1 + j;
+    k[j] = (i >= 0 && i < n) ? keys[i] : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int j = 1; j <= kRangeItems; ++j) {
+    const int64_t i = i0 - 1 + j;
+    if (i >= n) break;
+    if (k[j - 1] != k[j]) range[k[j]].x = (int)i;
+    if (k[j + 1] != k[j]) range[k[j]].y = (int)(i + 1);
+  }
 }
 
 // ---- lidar rays ------------------------------------------------------------------------------
@@ -572,6 +604,7 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   w.wcount = (int64_t*)take((n_tiles + 2) * 8);
   w.wpart = (int64_t*)take((div_up(n_tiles + 2, kScanTile) + 2) * 8);
   w.scalars = (int64_t*)take(4 * 8);
+  w.bstart = (int64_t*)take((size_t)(div_up(kc, kEmitTile) + 1) * 8);
   const size_t sort_bytes = off;
   // adjoint buffers start over at the base
   off = 0;
@@ -579,6 +612,10 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   w.slots = (float*)take((size_t)kc * w.stride * 4);
   w.flags = (uint8_t*)take((size_t)div_up(kc, 4) * 4);
   w.g2d = (float*)take((size_t)nrec * kNV * 4);
+  w.rflag = (uint8_t*)take((size_t)div_up(nrec, 4) * 4);
+  w.long_cap = long_part_cap(nrec, kc);
+  w.long_list = (uint32_t*)take((size_t)kLongParts * w.long_cap * 8);
+  w.n_long = (int32_t*)take(kLongParts * 4);
   w.bytes = off > sort_bytes ? off : sort_bytes;
   return w;
 }
@@ -588,7 +625,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   const int64_t n_rec = (int64_t)v.count * v.n_gauss;
   hipError_t e;
   int64_t* n_sort = w.scalars;   // min(K, k_cap)
-  // 1. visible records, compacted in record order, then stably sorted by float64 depth
+  // 1. visible records, compacted in record order, then stably sorted by the 40-bit depth key
   int64_t* n_vis = n_sort + 1;
   if ((e = device_scan<int64_t>(LoadVisible{p.n_tiles}, n_rec, w.offs, w.scan_part, s)) != hipSuccess) return e;
   const int64_t nb0 = div_up(n_rec, kScanTile);
@@ -599,7 +636,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   uint64_t* dk[2] = {w.dkeys[0], w.dkeys[1]};
   uint32_t* dvv[2] = {w.dvals[0], w.dvals[1]};
   int cur = 0;
-  if ((e = radix_sort<uint64_t>(dk, dvv, cur, n_vis, n_rec, kDepthKeyShift, kDepthKeyBits, w.hist, w.hist_part,
+  if ((e = radix_sort<uint64_t>(dk, dvv, cur, n_vis, n_rec, 0, kDepthKeyBits, w.hist, w.hist_part,
                                 nullptr, s)) != hipSuccess)
     return e;
   const uint32_t* order = dvv[cur];
@@ -608,9 +645,11 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
     return e;
   int64_t nb = div_up(n_rec, kScanTile);
   hipLaunchKernelGGL(k_finalize_count, dim3(1), dim3(1), 0, s, (const int64_t*)(w.scan_part + nb), L.k_cap, n_sort, st);
+  const int64_t emit_blocks = div_up(L.k_cap, kEmitTile);
   if (n_rec > 0)
     hipLaunchKernelGGL(k_entry_base, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, order,
-                       (const int64_t*)w.offs, (const int64_t*)n_vis, L.entry_base);
+                       (const int64_t*)w.offs, (const int64_t*)n_vis, (const int64_t*)(w.scan_part + nb), n_rec,
+                       emit_blocks, L.entry_base, w.bstart);
   // 3. emit: the final tile-sort pass must land its values in lists->gauss
   const int tbits = bits_for(v.n_tiles);
   const int passes = (tbits + kRadixBits - 1) / kRadixBits;
@@ -618,9 +657,9 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   if (passes % 2 == 0) { tv[0] = (uint32_t*)L.gauss; tv[1] = w.tvals; }
   else { tv[0] = w.tvals; tv[1] = (uint32_t*)L.gauss; }
   if (n_rec > 0 && L.k_cap > 0)
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)div_up(L.k_cap, kEmitTile)), dim3(256), 0, s, v.sens, v.count, v.n_gauss,
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks), dim3(256), 0, s, v.sens, v.count, v.n_gauss,
                        (const int4*)p.rect, order, (const int64_t*)w.offs, (const int64_t*)n_vis,
-                       (const int64_t*)n_sort, w.tkeys[0], tv[0]);
+                       (const int64_t*)n_sort, (const int64_t*)w.bstart, w.tkeys[0], tv[0]);
   // 4. stable sort by tile
   uint32_t* tk[2] = {w.tkeys[0], w.tkeys[1]};
   int tcur = 0;
@@ -629,7 +668,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   // 5. ranges
   if ((e = fill<int32_t>(L.tile_range, 2 * v.n_tiles, 0, s)) != hipSuccess) return e;
   if (L.k_cap > 0)
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(L.k_cap, 256)), dim3(256), 0, s, (const uint32_t*)tk[tcur],
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(L.k_cap, 256 * kRangeItems)), dim3(256), 0, s, (const uint32_t*)tk[tcur],
                        (const int64_t*)n_sort, L.k_cap, (int2*)L.tile_range);
   // 6. lidar rays -> tiles; work items (lidar chunks, and camera tiles in the batched form)
   if (v.has_lidar || v.queue) {
@@ -646,7 +685,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
       if ((e = radix_sort<uint32_t>(rk, rv, rcur, nullptr, nr, 0, bits_for(bins), w.hist, w.hist_part,
                                     (uint32_t*)L.ray_order, s)) != hipSuccess)
         return e;
-      hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(nr, 256)), dim3(256), 0, s, (const uint32_t*)rk[rcur],
+      hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(nr, 256 * kRangeItems)), dim3(256), 0, s, (const uint32_t*)rk[rcur],
                          (const int64_t*)nullptr, nr, (int2*)L.ray_range);
     }
     hipLaunchKernelGGL(k_work_count, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, v.sens, v.count,

@@ -28,6 +28,15 @@ inline int cmax_bucket(int c) { return c <= 4 ? 4 : c <= 8 ? 8 : c <= 16 ? 16 : 
 // float4 multiple.
 constexpr int slot_stride(int cmax_b) { return (kNV + cmax_b + 3) & ~3; }
 
+// The list of long-record chunks is appended through this many counters (wavefront w uses
+// counter w % kLongParts), so that no single counter takes every wavefront's atomic.  A
+// partition holds at most one chunk per record of its wavefronts plus one per 1024 listed
+// entries of all records.
+constexpr int kLongParts = 64;
+inline int64_t long_part_cap(int64_t n_rec, int64_t k_cap) {
+  return div_up(div_up(n_rec, 64), kLongParts) * 64 + div_up(k_cap, 1024) + 1;
+}
+
 // Views of the device buffers of one call (local numbering), shared by the launchers.
 struct CallView {
   const DevSensor* sens;   // device table entries [first, first + count)
@@ -67,10 +76,15 @@ struct Workspace {
   uint32_t* qvals[2];
   int2* qtmp;             // [work_cap] unordered work items
   int64_t* scalars;       // [4] device scalars: clamped intersection count, visible records
+  int64_t* bstart;        // [emit blocks + 1] first record (depth order) of every emit block
   // adjoint (overlays the bin/sort buffers: the two are never live in one call)
   float* slots;           // [k_cap, slot_stride] per-entry gradient rows, indexed by emission position
   uint8_t* flags;         // [k_cap] 1 = slot row written by this adjoint call
   float* g2d;             // [n_rec, kNV] atomically accumulated part (lidar tiles split over items)
+  uint8_t* rflag;         // [n_rec] 1 = the adjoint produced a gradient for the record
+  uint32_t* long_list;    // [kLongParts * long_cap] (record, chunk) pairs of long touched records
+  int32_t* n_long;        // [kLongParts] partition counts
+  int64_t long_cap;       // records per partition
   int stride;             // slot_stride(cmax_bucket(c_max))
   size_t bytes;
 };

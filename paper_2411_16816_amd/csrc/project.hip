@@ -80,6 +80,26 @@ __global__ __launch_bounds__(256) void k_project(const DevSensor* __restrict__ s
 // own lane.
 constexpr int kCoopEntries = 32;
 
+// Bit j of the result is the flag of position base + j, for j < n <= kCoopEntries.  Reads the
+// aligned 32-bit words that cover [base, base + n) all at once (independent loads, no branch per
+// position); the flag array is padded to a multiple of 4 bytes and base + n <= its length.
+__device__ __forceinline__ uint32_t flag_mask(const uint8_t* __restrict__ flags, int64_t base, int n) {
+  constexpr int kWords = (kCoopEntries + 3) / 4 + 1;
+  const int64_t a0 = base & ~(int64_t)3;
+  const int off = (int)(base - a0);
+  const int nw = (off + n + 3) >> 2;
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(flags + a0);
+  uint64_t m = 0;
+#pragma unroll
+  for (int k = 0; k < kWords; ++k) {
+    const uint32_t x = w[k < nw ? k : nw - 1];   // in bounds: re-reads the last word past nw
+    const uint32_t nib = (x & 1u) | ((x >> 7) & 2u) | ((x >> 14) & 4u) | ((x >> 21) & 8u);
+    m |= (k < nw ? (uint64_t)nib : 0ull) << (4 * k);
+  }
+  m >>= off;
+  return (uint32_t)(m & ((1ull << n) - 1ull));
+}
+
 template <int SW, int V>
 __device__ __forceinline__ void add_row(const float* __restrict__ row, float (&acc)[V]) {
   const float4* q = reinterpret_cast<const float4*>(row);
@@ -100,14 +120,118 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Gradient of every record, one thread per Gaussian and sensor loop: the sum of the
+// Long records are summed in chunks of kChunk positions, one wavefront per chunk and
+// kChunk / 64 positions per lane.
+constexpr int kChunk = 1024;
+constexpr int kLanePositions = kChunk / 64;
+
+__device__ __forceinline__ int listed_entries(int nt, int64_t base, int64_t k_cap) {
+  const int64_t room = k_cap - base;   // entries at or beyond k_cap were never listed
+  return room <= 0 ? 0 : (nt < room ? nt : (int)room);
+}
+
+// Work items (record, chunk) for every record that the adjoint touched and that has more than
+// kCoopEntries listed entries, appended to partition (wavefront index % kLongParts) of `list`:
+// one atomic per wavefront, spread over kLongParts counters.  The list order varies from run
+// to run; the sums do not.
+__global__ __launch_bounds__(256) void k_long_records(const int32_t* __restrict__ n_tiles,
+                                                      const uint8_t* __restrict__ rflag,
+                                                      const int64_t* __restrict__ entry_base, int64_t n_rec,
+                                                      int64_t k_cap, uint2* __restrict__ list, int64_t cap,
+                                                      int32_t* __restrict__ n_list) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int chunks = 0;
+  if (r < n_rec && n_tiles[r] > kCoopEntries && rflag[r] != 0)
+    chunks = (listed_entries(n_tiles[r], entry_base[r], k_cap) + kChunk - 1) / kChunk;
+  if (__ballot(chunks > 0) == 0) return;   // uniform over the wavefront
+  const int lane = threadIdx.x & 63;
+  int incl = chunks;   // inclusive prefix over the wavefront
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const int part = (int)((r >> 6) % kLongParts);
+  int first = 0;
+  if (lane == 63) first = atomicAdd(n_list + part, incl);
+  first = __shfl(first, 63, 64);
+  uint2* dst = list + part * cap + first + (incl - chunks);
+  for (int c = 0; c < chunks; ++c) dst[c] = make_uint2((uint32_t)r, (uint32_t)c);
+}
+
+// One wavefront per (record, chunk): every lane sums the flagged rows of its kLanePositions
+// positions, the wavefront reduces, and the chunk's total is stored into the row of the
+// chunk's first position, flagged 2 (zeros if no row was written).  Only this wavefront
+// touches the chunk's rows.  Items are numbered partition by partition.
+template <int CMAX>
+__global__ __launch_bounds__(256) void k_slot_reduce_long(const uint2* __restrict__ list, int64_t cap,
+                                                          const int32_t* __restrict__ n_list,
+                                                          const int32_t* __restrict__ n_tiles,
+                                                          const int64_t* __restrict__ entry_base, float* slots,
+                                                          uint8_t* flags, int64_t k_cap) {
+  constexpr int V = kNV + CMAX;
+  constexpr int SW = slot_stride(CMAX);
+  static_assert(kLongParts == 64, "one partition count per lane");
+  static_assert(kLanePositions <= kCoopEntries, "flag_mask range");
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  // inclusive prefix of the partition counts, one per lane
+  int incl = n_list[lane];
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const int64_t total = __shfl(incl, 63, 64);
+  bool store;
+  const int idx = scatter_slot<V>(lane, store);
+  for (int64_t it = wave; it < total; it += n_waves) {
+    const int part = (int)__popcll(__ballot(incl <= it));   // partitions that end at or before it
+    const int before = part == 0 ? 0 : __shfl(incl, part - 1, 64);
+    const uint2 item = list[part * cap + (it - before)];
+    const uint32_t r = item.x;
+    const int64_t base = entry_base[r];
+    const int n = listed_entries(n_tiles[r], base, k_cap);
+    const int64_t c0 = (int64_t)item.y * kChunk;             // chunk start (record-relative)
+    const int64_t l0 = c0 + lane * kLanePositions;           // this lane's first position
+    int cnt = (int)(n - l0);
+    cnt = cnt < 0 ? 0 : (cnt > kLanePositions ? kLanePositions : cnt);
+    float sum_v[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) sum_v[v] = 0.f;
+    uint32_t fm = cnt > 0 ? flag_mask(flags, base + l0, cnt) : 0u;
+    while (fm) {   // two rows in flight per iteration
+      const int j0 = __builtin_ctz(fm);
+      fm &= fm - 1;
+      const bool two = fm != 0;
+      const int j1 = two ? __builtin_ctz(fm) : j0;
+      if (two) fm &= fm - 1;
+      float r0[V], r1[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) r0[v] = r1[v] = 0.f;
+      add_row<SW>(slots + (base + l0 + j0) * SW, r0);
+      add_row<SW>(slots + (base + l0 + j1) * SW, r1);
+#pragma unroll
+      for (int v = 0; v < V; ++v) sum_v[v] += two ? r0[v] + r1[v] : r0[v];
+    }
+    const float sum = wave_reduce_scatter<V>(sum_v);
+    if (store) slots[(base + c0) * SW + idx] = sum;
+    if (lane == 0) flags[base + c0] = 2;
+  }
+}
+
+// Gradient of every touched record, one thread per Gaussian and sensor loop: the sum of the
 // rasteriser's rows over the record's entries (positions [entry_base, entry_base + n_tiles) of
-// the slot array, rows whose flag is set), taken in a fixed order so that the result does not
-// depend on scheduling.  The geometric part (kNV values) goes to g2d[rec] (added to the atomic
-// part of split lidar tiles when `accumulate`), the channel part to the features gradient.
+// the slot array, rows whose flag is set; a long record's total sits in its first row), taken
+// in a fixed order so that the result does not depend on scheduling.  The geometric part (kNV
+// values) goes to g2d[rec] (added to the atomic part of split lidar tiles when `accumulate`),
+// the channel part to the features gradient.  Untouched records have no gradient and are
+// skipped here and in the projection adjoint.
 template <int CMAX>
 __global__ __launch_bounds__(256) void k_slot_reduce(const DevSensor* __restrict__ sens, int count, int64_t N,
                                                      int c_total, const int32_t* __restrict__ n_tiles,
+                                                     const uint8_t* __restrict__ rflag,
                                                      const int64_t* __restrict__ entry_base,
                                                      const float* __restrict__ slots,
                                                      const uint8_t* __restrict__ flags, int64_t k_cap,
@@ -115,53 +239,38 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const DevSensor* __restrict
                                                      float* __restrict__ dfeat) {
   constexpr int V = kNV + CMAX;
   constexpr int SW = slot_stride(CMAX);
-  __shared__ float s_red[4][V];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = i < N;
-  if (__ballot(live) == 0) return;   // uniform over the wavefront
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  bool store;
-  const int my_idx = scatter_slot<V>(lane, store);
+  if (i >= N) return;
   for (int k = 0; k < count; ++k) {
     const int64_t r = (int64_t)k * N + i;
-    const int nt = live ? n_tiles[r] : 0;
-    int64_t base = 0;
-    int n = 0;
-    if (nt > 0) {
-      base = entry_base[r];
-      const int64_t room = k_cap - base;   // entries at or beyond k_cap were never listed
-      n = room <= 0 ? 0 : (nt < room ? nt : (int)room);
-    }
+    if (rflag[r] == 0) continue;
+    const int nt = n_tiles[r];
+    const int64_t base = entry_base[r];
+    const int n = listed_entries(nt, base, k_cap);
     float acc[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[v] = 0.f;
-    const bool coop = n > kCoopEntries;
-    if (!coop) {
-      for (int j = 0; j < n; ++j)
-        if (flags[base + j]) add_row<SW>(slots + (base + j) * SW, acc);
-    }
-    uint64_t m = __ballot(coop);
-    while (m) {
-      const int L = __builtin_ctzll(m);
-      m &= m - 1;
-      const int64_t bL = ((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)base, L)) |
-                         ((int64_t)__builtin_amdgcn_readlane((int)(base >> 32), L) << 32);
-      const int nL = __builtin_amdgcn_readlane(n, L);
-      float part[V];
+    if (nt > kCoopEntries) {
+      // chunk totals from k_slot_reduce_long, in chunk order
+      const int nc = (n + kChunk - 1) / kChunk;
+      for (int c = 0; c < nc; ++c) add_row<SW>(slots + (base + (int64_t)c * kChunk) * SW, acc);
+    } else if (n > 0) {
+      uint32_t fm = flag_mask(flags, base, n);
+      while (fm) {   // two rows in flight per iteration
+        const int j0 = __builtin_ctz(fm);
+        fm &= fm - 1;
+        const bool two = fm != 0;
+        const int j1 = two ? __builtin_ctz(fm) : j0;
+        if (two) fm &= fm - 1;
+        float r0[V], r1[V];
 #pragma unroll
-      for (int v = 0; v < V; ++v) part[v] = 0.f;
-      for (int j = lane; j < nL; j += 64)
-        if (flags[bL + j]) add_row<SW>(slots + (bL + j) * SW, part);
-      const float sum = wave_reduce_scatter<V>(part);
-      if (store) s_red[wv][my_idx] = sum;
-      wave_sync();
-      if (lane == L) {
+        for (int v = 0; v < V; ++v) r0[v] = r1[v] = 0.f;
+        add_row<SW>(slots + (base + j0) * SW, r0);
+        add_row<SW>(slots + (base + j1) * SW, r1);
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc[v] = s_red[wv][v];
+        for (int v = 0; v < V; ++v) acc[v] += two ? r0[v] + r1[v] : r0[v];
       }
-      wave_sync();
     }
-    if (nt <= 0) continue;
     float* q = g2d + r * kNV;
 #pragma unroll
     for (int v = 0; v < kNV; ++v) q[v] = accumulate ? q[v] + acc[v] : acc[v];
@@ -178,10 +287,13 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const DevSensor* __restrict
 // Projection adjoint, one thread per Gaussian: chains every record's g2d gradient (mean.x,
 // mean.y, vel.x, vel.y, conic a, b, c, o_eff, depth (z | r), v_r) through the projection.
 __global__ __launch_bounds__(256) void k_project_bwd(const DevSensor* __restrict__ sens, int count, SplatGaussians g,
-                                                     const int32_t* __restrict__ n_tiles, const float* __restrict__ g2d,
+                                                     const uint8_t* __restrict__ rflag, const float* __restrict__ g2d,
                                                      SplatGrads gr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.n) return;
+  bool touched = false;
+  for (int k = 0; k < count && !touched; ++k) touched = rflag[(int64_t)k * g.n + i] != 0;
+  if (!touched) return;
   GaussLoad G;
   load_gaussian(g, i, G);
   QuatRot qr;
@@ -192,7 +304,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const DevSensor* __restrict
   bool any = false;
   for (int k = 0; k < count; ++k) {
     const int64_t r = (int64_t)k * g.n + i;
-    if (n_tiles[r] <= 0) continue;
+    if (rflag[r] == 0) continue;   // no gradient reached this record
     const float* q = g2d + r * kNV;
     RecGrad rg;
     rg.mean[0] = q[0]; rg.mean[1] = q[1]; rg.vel[0] = q[2]; rg.vel[1] = q[3];
@@ -231,11 +343,22 @@ hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const 
   if (w.stride != slot_stride(cm)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)div_up(g.n, 256));
   float* dfeat = v.c_max > 0 ? gr.features : nullptr;
+  const int64_t n_rec = (int64_t)v.count * g.n;
+  if (w.long_cap != long_part_cap(n_rec, L.k_cap)) return hipErrorInvalidValue;
+  hipError_t e = launch_fill_i32(w.n_long, kLongParts, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_long_records, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, (const int32_t*)p.n_tiles,
+                     (const uint8_t*)w.rflag, (const int64_t*)L.entry_base, n_rec, L.k_cap, (uint2*)w.long_list,
+                     w.long_cap, w.n_long);
+  const int64_t long_blocks = div_up(n_rec, 4) < 4096 ? div_up(n_rec, 4) : 4096;
 #define SR_CASE(CM)                                                                                               \
   case CM:                                                                                                        \
+    hipLaunchKernelGGL(k_slot_reduce_long<CM>, dim3((unsigned)long_blocks), dim3(256), 0, s,                      \
+                       (const uint2*)w.long_list, w.long_cap, (const int32_t*)w.n_long,                           \
+                       (const int32_t*)p.n_tiles, (const int64_t*)L.entry_base, w.slots, w.flags, L.k_cap);       \
     hipLaunchKernelGGL(k_slot_reduce<CM>, grid, dim3(256), 0, s, v.sens, v.count, g.n, g.c_total,                 \
-                       (const int32_t*)p.n_tiles, (const int64_t*)L.entry_base, (const float*)w.slots,            \
-                       (const uint8_t*)w.flags, L.k_cap, v.has_lidar, w.g2d, dfeat);                              \
+                       (const int32_t*)p.n_tiles, (const uint8_t*)w.rflag, (const int64_t*)L.entry_base,          \
+                       (const float*)w.slots, (const uint8_t*)w.flags, L.k_cap, v.has_lidar, w.g2d, dfeat);      \
     break;
   switch (cm) {
     SR_CASE(4)
@@ -245,7 +368,7 @@ hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const 
     SR_CASE(48)
   }
 #undef SR_CASE
-  hipLaunchKernelGGL(k_project_bwd, grid, dim3(256), 0, s, v.sens, v.count, g, (const int32_t*)p.n_tiles,
+  hipLaunchKernelGGL(k_project_bwd, grid, dim3(256), 0, s, v.sens, v.count, g, (const uint8_t*)w.rflag,
                      (const float*)w.g2d, gr);
   return hipGetLastError();
 }

@@ -59,6 +59,7 @@ struct BwdIn {
   const float* dA;
   float* slots;      // [k_cap, slot_stride] rows written by work items that own their tile
   uint8_t* flags;    // [k_cap] set for every row written
+  uint8_t* rflag;    // [n_rec] set for every record given a gradient (row or atomic)
   float* g2d;        // [n_rec, kNV] atomic part from work items of split lidar tiles
   float* dfeat;      // features gradient (atomic part, split lidar tiles)
 };
@@ -439,6 +440,7 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
     if (tid < nb && s_used[tid]) {
       const int64_t g = a.gauss[b0 + tid];
       const int64_t rec = (int64_t)c.s * a.N + g;
+      b.rflag[rec] = 1;   // idempotent: every writer stores the same byte
       if (!split) {
         // this item is the only one of its tile: the entry's row is complete, store it
         const int64_t p = a.entry_base[rec] + rect_entry(S, a.rect[rec], tile_local);
@@ -611,7 +613,7 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
                              const SplatTileLists& L, int support, const SplatRenderOut& saved, const float* dF,
                              const float* dD, const float* dA, const Workspace& w, float* dfeat, hipStream_t s) {
   RasterArgs a = make_args(v, g, p, L);
-  BwdIn b{saved.t_final, saved.last, dF, dD, dA, w.slots, w.flags, w.g2d, dfeat};
+  BwdIn b{saved.t_final, saved.last, dF, dD, dA, w.slots, w.flags, w.rflag, w.g2d, dfeat};
   const int cm = cmax_bucket(v.c_max);
   if (w.stride != slot_stride(cm)) return hipErrorInvalidValue;
   if (v.queue) {

@@ -124,12 +124,20 @@ def test_project_lidar():
 # ------------------------------------------------------------------------------------------
 # a3 / a4: binning and sorting, bit-exact against the stage check
 # ------------------------------------------------------------------------------------------
+def depth_sort_key(bits):
+    """The library's documented 40-bit ordering key of float64 depth bits (splat.h, dkey)."""
+    bits = np.asarray(bits, np.uint64)
+    e = ((bits >> np.uint64(52)) & np.uint64(0x7FF)).astype(np.int64) - (1023 - 16)
+    key = (np.clip(e, 0, 31).astype(np.uint64) << np.uint64(35)) | ((bits & np.uint64(0xFFFFFFFFFFFFF)) >> np.uint64(17))
+    key = np.where(e < 0, np.uint64(0), key)
+    return np.where(e > 31, np.uint64((1 << 40) - 1), key)
+
+
 def _expected_lists(sp, sensor, g_n):
     nt = sp.ntiles.cpu().numpy()[:g_n]
     keep = nt > 0
     box = sp.box.cpu().numpy()[:g_n]
-    # the library orders by the upper 48 bits of the float64 depth (documented in splat.h)
-    depth = sp.dkey.cpu().numpy()[:g_n].view(np.uint64) >> np.uint64(16)
+    depth = depth_sort_key(sp.dkey.cpu().numpy()[:g_n].view(np.uint64))
     if hasattr(sensor, "ray_az"):
         rect = tl.lidar_tile_rect_f32(box[:, :2], box[:, 2:], sensor)
         per = tl.lidar_tiles_of(rect, sensor)
