@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--cpu-rays", type=int, default=64, help="rays per sensor in the CPU oracle sample")
     ap.add_argument("--profile-steps", action="store_true", help="skip parity and CPU legs (for rocprofv3)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the scene's tile shapes")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with two 1 GiB device copies (reference kernel for rocprofv3 byte counters)")
     ap.add_argument("--camera-tile", default=None, help="WxH: fixed camera tile (skips autotuning)")
     ap.add_argument("--lidar-tile", default=None,
                     help="AZxM: fixed lidar tiles of AZ azimuth steps, elevation tiles merged by M (skips autotuning)")
@@ -139,9 +141,9 @@ def main():
                 if ev: ev["project"][1].record(stream); ev["bin_sort"][0].record(stream)
                 sp.bin_sort()
                 if ev: ev["bin_sort"][1].record(stream); ev["raster_fwd"][0].record(stream)
-                sp.raster_fwd(G)
+                sp.raster_fwd(G, timer=ev["k_fwd"] if ev else None)
                 if ev: ev["raster_fwd"][1].record(stream); ev["raster_bwd"][0].record(stream)
-                sp.raster_bwd(G, *ups[k], grads)
+                sp.raster_bwd(G, *ups[k], grads, timer=ev["k_bwd"] if ev else None)
                 if ev: ev["raster_bwd"][1].record(stream)
 
         for sp in passes:
@@ -158,7 +160,12 @@ def main():
             parity = check_parity(passes, rig, g)
             log(f"{mode} parity: {parity}")
         mk = lambda: torch.cuda.Event(enable_timing=True)
-        evs = [[{s: (mk(), mk()) for s in stages} for _ in passes] for _ in range(args.steps)]
+        evs = [[{s: (mk(), mk()) for s in stages + ["k_fwd", "k_bwd"]} for _ in passes] for _ in range(args.steps)]
+        for e in evs:          # the library records these events: create them on this stream first
+            for d in e:
+                for a, b in d.values():
+                    a.record(stream)
+                    b.record(stream)
         start, end = mk(), mk()
         torch.cuda.synchronize()
         start.record(stream)
@@ -172,6 +179,10 @@ def main():
         stage_ms = {} if pipe is not None else {
             f"{s}_{names[k]}": float(np.mean([e[k][s][0].elapsed_time(e[k][s][1]) for e in evs]))
             for k in range(len(passes)) for s in stages}
+        # the rasteriser kernels alone (events recorded by the library around the kernel launch)
+        kernel_ms = {} if pipe is not None else {
+            f"{s}_{names[k]}": float(np.mean([e[k][s][0].elapsed_time(e[k][s][1]) for e in evs]))
+            for k in range(len(passes)) for s in ("k_fwd", "k_bwd")}
 
         # forward only (project -> bin/sort -> rasterize_fwd), same step count
         def fwd_step():
@@ -199,7 +210,8 @@ def main():
             sp.raster_fwd(G, count_pairs=True)
         torch.cuda.synchronize()
         pairs = [int(B.read_status(sp.status).n_pairs) for sp in passes]
-        results[mode] = dict(ms=ms, value=rays / (ms * 1e-3) / 1e6, stage_ms=stage_ms, parity=parity, K=Ks,
+        results[mode] = dict(ms=ms, value=rays / (ms * 1e-3) / 1e6, stage_ms=stage_ms, kernel_ms=kernel_ms,
+                             parity=parity, K=Ks,
                              pairs=pairs, rays=rays, ms_fwd=ms_fwd, value_fwd=rays / (ms_fwd * 1e-3) / 1e6)
         log(f"{mode}: {ms:.3f} ms/step, {results[mode]['value']:.1f} Mrays/s (forward only {ms_fwd:.3f} ms, "
             f"{results[mode]['value_fwd']:.1f} Mrays/s); stages "
@@ -211,7 +223,7 @@ def main():
 
     main_mode = next(m for m in ("graph", "batched", "plain") if m in results)
     R = results[main_mode]
-    roof = roofline(results)
+    roof = roofline(results) if "batched" in results else None
     cpu = None
     if not (args.no_cpu_baseline or args.profile_steps):
         cpu = cpu_baseline(g, cam, lid, args.cpu_rays)
@@ -237,6 +249,13 @@ def main():
             if m in results:
                 out[f"{m}_over_plain"] = round(results[m]["value"] / results["plain"]["value"], 4)
     print(json.dumps(out), flush=True)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration: 2 copies of 1 GiB")
 
 
 def check_parity(passes, rig, g):
@@ -267,12 +286,44 @@ def check_parity(passes, rig, g):
     return res
 
 
+# kernel whose roofline is reported: the batched adjoint rasteriser, the longest kernel of the step
+ROOF_KERNEL = "k_raster_bwd_queue<16, false>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_raster_bwd_queue_headline.md")
+KERNEL_SOURCES = ["paper_2411_16816_amd/csrc/raster.hip", "paper_2411_16816_amd/csrc/splat_common.hpp",
+                  "paper_2411_16816_amd/csrc/wave_ops.hpp", "paper_2411_16816_amd/csrc/kernels.hpp",
+                  "include/splat.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of ROOF_KERNEL from the committed rocprofv3 --pmc summary, or None
+    when the summary is missing or was taken on other kernel sources."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = dict(line[2:].split(": ", 1) for line in txt.splitlines() if line.startswith("- ") and ": " in line)
+    if vals.get("source_hash", "").strip() != kernel_source_hash():
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch"].strip())
+    except (KeyError, ValueError):
+        return None
+
+
 def roofline(results):
-    """VALU roofline of the dominant stage, the adjoint call (raster adjoint + the projection
-    adjoint and a zero fill in the same call, so the achieved rate is a lower bound for the
-    raster adjoint kernel).  Algorithmic FLOP = evaluated pairs x FLOP per pair x 3."""
-    mode = "batched" if "batched" in results else "plain"
-    r = results[mode]
+    """VALU roofline of the batched adjoint rasteriser kernel.  Time: the kernel alone, from
+    events the library records around its launch (splat_time_next_raster), averaged over the
+    timed steps.  Algorithmic FLOP = evaluated pairs x FLOP per pair x 3."""
+    r = results["batched"]
     plain = results.get("plain", r)
     pc = plain["pairs"]
     if len(pc) == 2:
@@ -280,13 +331,16 @@ def roofline(results):
     else:
         flop_fwd = pc[0] * 0.5 * (FLOP_PER_PAIR["camera"] + FLOP_PER_PAIR["lidar"])
     flop_bwd = BWD_FACTOR * flop_fwd
-    t_bwd = sum(v for k, v in r["stage_ms"].items() if k.startswith("raster_bwd")) * 1e-3
-    t_fwd = sum(v for k, v in r["stage_ms"].items() if k.startswith("raster_fwd")) * 1e-3
+    t_bwd = r["kernel_ms"]["k_bwd_both"] * 1e-3
+    t_fwd = r["kernel_ms"]["k_fwd_both"] * 1e-3
     ach = flop_bwd / t_bwd / 1e12
-    return {"bound": "alu", "kernel": f"rasterize_bwd ({mode})", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
-            "algorithmic_flop": int(flop_bwd), "evaluated_pairs": int(sum(pc)),
-            "forward": {"kernel": f"rasterize_fwd ({mode})", "achieved": round(flop_fwd / t_fwd / 1e12, 3),
+    traffic = measured_traffic()
+    return {"bound": "alu", "kernel": ROOF_KERNEL, "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+            "kernel_ms": round(t_bwd * 1e3, 4), "algorithmic_flop": int(flop_bwd), "evaluated_pairs": int(sum(pc)),
+            "hbm_gbs": None if traffic is None else round(traffic / t_bwd / 1e9, 1),
+            "forward": {"kernel": "k_raster_fwd_queue<16, false>", "kernel_ms": round(t_fwd * 1e3, 4),
+                        "achieved": round(flop_fwd / t_fwd / 1e12, 3),
                         "frac": round(flop_fwd / t_fwd / 1e12 / PEAK_FP32_TFLOPS, 4)}}
 
 

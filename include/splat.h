@@ -314,6 +314,15 @@ int splat_rasterize_bwd_lidar(const SplatGaussians* g, const SplatRig* rig, int3
  *   - The graph holds no memset node (zeroing uses fill kernels) and allocates nothing.
  *   - Creating a pipeline captures on an internal stream and instantiates the graph; it is not a
  *     hot-path call.  Runs of one pipeline on different streams must not overlap. */
+/* ---- measurement hook.  The next splat_rasterize_fwd* or splat_rasterize_bwd* call made by
+ * the calling host thread records hipEvent_t `start_event` on its stream right before its
+ * rasteriser kernel and `stop_event` right after it (not around the zero fills or, in the
+ * adjoint, the gradient sums and the projection adjoint), then forgets them.  Both NULL
+ * clears a pending request; exactly one NULL is SPLAT_ERR_INVALID_ARG.  Creating a pipeline
+ * clears it too (graphs hold no event records).  For benchmarks: per-kernel time without a
+ * profiler. */
+int splat_time_next_raster(void* start_event, void* stop_event);
+
 #define SPLAT_STEP_BACKWARD 1    /* include the adjoint                                   */
 #define SPLAT_STEP_ZERO_GRADS 2  /* zero every gradient array first (else they accumulate) */
 

@@ -54,6 +54,7 @@ def _declare(lib):
         "splat_bin_sort": (C.c_int, [vp, i32, i32, i64, vp, vp, vp, C.c_size_t, vp, vp]),
         "splat_rasterize_fwd": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp]),
         "splat_rasterize_bwd": (C.c_int, [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+        "splat_time_next_raster": (C.c_int, [vp, vp]),
         "splat_pipeline_create": (C.c_int, [vp, i32, i32, vp, C.POINTER(vp)]),
         "splat_pipeline_run": (C.c_int, [vp, vp]),
         "splat_pipeline_destroy": (None, [vp]),
@@ -310,8 +311,17 @@ class SensorPass:
                  C.byref(self.lists_struct()), C.c_void_p(self.ws_ptr), self.ws_bytes, _ptr(self.status),
                  _stream(stream)), "splat_bin_sort")
 
-    def raster_fwd(self, g: GaussTensors, support=BOX, stream=None, count_pairs: bool = False):
+    def _time(self, timer):
+        """Ask the library to record timer = (start, stop) torch events around the next
+        rasteriser kernel (splat_time_next_raster)."""
+        if timer is not None:
+            a, b = timer
+            check(self.lib.splat_time_next_raster(C.c_void_p(a.cuda_event), C.c_void_p(b.cuda_event)),
+                  "splat_time_next_raster")
+
+    def raster_fwd(self, g: GaussTensors, support=BOX, stream=None, count_pairs: bool = False, timer=None):
         st_ = _ptr(self.status) if count_pairs else None
+        self._time(timer)
         if self.batched:
             check(self.lib.splat_rasterize_fwd(C.byref(g.struct()), self.rig.handle, self.first, self.count,
                                                C.byref(self.proj_struct()), C.byref(self.lists_struct()), support,
@@ -328,8 +338,9 @@ class SensorPass:
                                                       support, C.byref(self.out_struct()), st_, _stream(stream)),
                   "splat_rasterize_fwd_camera")
 
-    def raster_bwd(self, g: GaussTensors, dF, dD, dA, grads: GaussTensors, support=BOX, stream=None):
+    def raster_bwd(self, g: GaussTensors, dF, dD, dA, grads: GaussTensors, support=BOX, stream=None, timer=None):
         gr = _grads_struct(grads)
+        self._time(timer)
         fn = (self.lib.splat_rasterize_bwd if self.batched else
               self.lib.splat_rasterize_bwd_lidar if self.lidar else self.lib.splat_rasterize_bwd_camera)
         check(fn(C.byref(g.struct()), self.rig.handle, self.first, self.count, C.byref(self.proj_struct()),

@@ -240,6 +240,15 @@ static int bin_sort_impl(const SplatRig* r, int32_t first, int32_t count, int ki
   return dev_err(launch_bin_sort(v, *proj, *lists, w, st, (hipStream_t)stream));
 }
 
+// Measurement hook (splat_time_next_raster): consumed by the next rasterise call of this thread.
+static thread_local KernelTimer t_next_timer;
+
+static KernelTimer take_timer() {
+  KernelTimer t = t_next_timer;
+  t_next_timer = KernelTimer();
+  return t;
+}
+
 static int raster_fwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count, int kind,
                            const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
                            const SplatRenderOut* out, SplatStatus* st, void* stream) {
@@ -250,7 +259,7 @@ static int raster_fwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t f
   if ((rc = check_gaussians(g, v)) || (rc = check_proj(proj, v)) || (rc = check_lists(lists, v)) ||
       (rc = check_out(out, v)))
     return rc;
-  return dev_err(launch_raster_fwd(v, *g, *proj, *lists, support, *out, st, (hipStream_t)stream));
+  return dev_err(launch_raster_fwd(v, *g, *proj, *lists, support, *out, st, (hipStream_t)stream, take_timer()));
 }
 
 static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count, int kind,
@@ -273,7 +282,8 @@ static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t f
   hipError_t e = launch_fill_i32((int32_t*)w.flags, div_up(lists->k_cap, 4), 0, s);
   if (e == hipSuccess) e = launch_fill_i32((int32_t*)w.rflag, div_up((int64_t)count * g->n, 4), 0, s);
   if (e == hipSuccess && v.has_lidar) e = launch_fill_f32(w.g2d, (int64_t)count * g->n * kNV, 0.f, s);
-  if (e == hipSuccess) e = launch_raster_bwd(v, *g, *proj, *lists, support, *saved, dF, dD, dA, w, gr->features, s);
+  if (e == hipSuccess)
+    e = launch_raster_bwd(v, *g, *proj, *lists, support, *saved, dF, dD, dA, w, gr->features, s, take_timer());
   if (e == hipSuccess) e = launch_project_bwd(v, *g, *proj, *lists, w, *gr, s);
   return dev_err(e);
 }
@@ -402,9 +412,17 @@ static int step_launches(const SplatRig* r, int32_t first, int32_t count, const 
 
 extern "C" {
 
+int splat_time_next_raster(void* start_event, void* stop_event) {
+  if ((start_event == nullptr) != (stop_event == nullptr)) return SPLAT_ERR_INVALID_ARG;
+  t_next_timer.start = (hipEvent_t)start_event;
+  t_next_timer.stop = (hipEvent_t)stop_event;
+  return SPLAT_OK;
+}
+
 int splat_pipeline_create(const SplatRig* r, int32_t first, int32_t count, const SplatStep* step,
                           SplatPipeline** out) {
   if (!out || !step) return SPLAT_ERR_INVALID_ARG;
+  t_next_timer = KernelTimer();   // no event records inside a captured graph
   *out = nullptr;
   CallView v;
   int rc = make_view(r, first, count, -1, step->gaussians.n, v);

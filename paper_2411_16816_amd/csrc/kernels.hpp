@@ -98,12 +98,18 @@ hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const 
                               const SplatTileLists& L, const Workspace& w, const SplatGrads& gr, hipStream_t s);
 hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const SplatTileLists& L, const Workspace& w,
                            SplatStatus* st, hipStream_t s);
+// Optional events recorded on the launch stream right before and after the rasteriser kernel.
+struct KernelTimer {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
                              const SplatTileLists& L, int support, const SplatRenderOut& o, SplatStatus* st,
-                             hipStream_t s);
+                             hipStream_t s, const KernelTimer& timer);
 hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
                              const SplatTileLists& L, int support, const SplatRenderOut& saved, const float* dF,
-                             const float* dD, const float* dA, const Workspace& w, float* dfeat, hipStream_t s);
+                             const float* dD, const float* dA, const Workspace& w, float* dfeat, hipStream_t s,
+                             const KernelTimer& timer);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 

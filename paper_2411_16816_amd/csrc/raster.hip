@@ -564,7 +564,7 @@ static void bwd_queue_launch(const CallView& v, int64_t items, hipStream_t s, co
 
 hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
                              const SplatTileLists& L, int support, const SplatRenderOut& out, SplatStatus* st,
-                             hipStream_t s) {
+                             hipStream_t s, const KernelTimer& timer) {
   RasterArgs a = make_args(v, g, p, L);
   FwdOut o{out.feat, out.depth, out.alpha, out.t_final, out.last, out.median, st ? &st->n_pairs : nullptr};
   const int cm = cmax_bucket(v.c_max);
@@ -580,6 +580,7 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
     if (tile) fwd_queue_launch<CM, true>(v, items, s, a, o, counter);         \
     else fwd_queue_launch<CM, false>(v, items, s, a, o, counter);             \
     break;
+    if (timer.start) (void)hipEventRecord(timer.start, s);
     switch (cm) {
       FWDQ_CASE(4)
       FWDQ_CASE(8)
@@ -588,6 +589,7 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
       FWDQ_CASE(48)
     }
 #undef FWDQ_CASE
+    if (timer.stop) (void)hipEventRecord(timer.stop, s);
     return hipGetLastError();
   }
   const int64_t items = v.lidar ? L.work_cap : v.n_tiles;
@@ -598,6 +600,7 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
     if (v.lidar) fwd_dispatch<CM, true>(grid, s, support, a, o); \
     else fwd_dispatch<CM, false>(grid, s, support, a, o);      \
     break;
+  if (timer.start) (void)hipEventRecord(timer.start, s);
   switch (cm) {
     FWD_CASE(4)
     FWD_CASE(8)
@@ -606,12 +609,14 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
     FWD_CASE(48)
   }
 #undef FWD_CASE
+  if (timer.stop) (void)hipEventRecord(timer.stop, s);
   return hipGetLastError();
 }
 
 hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
                              const SplatTileLists& L, int support, const SplatRenderOut& saved, const float* dF,
-                             const float* dD, const float* dA, const Workspace& w, float* dfeat, hipStream_t s) {
+                             const float* dD, const float* dA, const Workspace& w, float* dfeat, hipStream_t s,
+                             const KernelTimer& timer) {
   RasterArgs a = make_args(v, g, p, L);
   BwdIn b{saved.t_final, saved.last, dF, dD, dA, w.slots, w.flags, w.rflag, w.g2d, dfeat};
   const int cm = cmax_bucket(v.c_max);
@@ -628,6 +633,7 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
     if (tile) bwd_queue_launch<CM, true>(v, items, s, a, b, counter);         \
     else bwd_queue_launch<CM, false>(v, items, s, a, b, counter);             \
     break;
+    if (timer.start) (void)hipEventRecord(timer.start, s);
     switch (cm) {
       BWDQ_CASE(4)
       BWDQ_CASE(8)
@@ -636,6 +642,7 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
       BWDQ_CASE(48)
     }
 #undef BWDQ_CASE
+    if (timer.stop) (void)hipEventRecord(timer.stop, s);
     return hipGetLastError();
   }
   const int64_t items = v.lidar ? L.work_cap : v.n_tiles;
@@ -646,6 +653,7 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
     if (v.lidar) bwd_dispatch<CM, true>(grid, s, support, a, b); \
     else bwd_dispatch<CM, false>(grid, s, support, a, b);      \
     break;
+  if (timer.start) (void)hipEventRecord(timer.start, s);
   switch (cm) {
     BWD_CASE(4)
     BWD_CASE(8)
@@ -654,6 +662,7 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
     BWD_CASE(48)
   }
 #undef BWD_CASE
+  if (timer.stop) (void)hipEventRecord(timer.stop, s);
   return hipGetLastError();
 }
 
