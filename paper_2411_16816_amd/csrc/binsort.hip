@@ -112,27 +112,18 @@ __global__ __launch_bounds__(256) void k_scan_reduce(Load ld, int64_t n, T* __re
   if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
-// single block: exclusive scan of part[0..nb) in place, part[nb] = total
-template <typename T>
-__global__ __launch_bounds__(256) void k_scan_partials(T* __restrict__ part, int64_t nb) {
-  __shared__ T tmp[4];
-  T carry = 0;
-  for (int64_t b0 = 0; b0 < nb; b0 += 256) {
-    int64_t i = b0 + threadIdx.x;
-    T v = i < nb ? part[i] : (T)0;
-    T total;
-    T ex = block_exclusive_scan<T>(v, tmp, total);
-    if (i < nb) part[i] = carry + ex;
-    carry += total;
-  }
-  if (threadIdx.x == 0) part[nb] = carry;
-}
-
+// Block b: exclusive scan of its tile, offset by the sum of the block totals part[0..b) (read
+// by the block itself); the last block writes the grand total to part[nb].
 template <typename T, typename Load>
-__global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, const T* __restrict__ part, T* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, T* __restrict__ part, int64_t nb,
+                                                   T* __restrict__ out) {
   __shared__ T tile[kScanTile];
   __shared__ T tmp[4];
   int64_t base = (int64_t)blockIdx.x * kScanTile;
+  T pb = 0;
+  for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) pb += part[i];
+  T before;
+  block_exclusive_scan<T>(pb, tmp, before);
 #pragma unroll 4
   for (int r = 0; r < kScanItems; ++r) {
     int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
@@ -147,7 +138,8 @@ __global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, const T* 
     acc += tile[threadIdx.x * kScanItems + k];
   }
   T total;
-  T pre = block_exclusive_scan<T>(acc, tmp, total) + part[blockIdx.x];
+  T pre = block_exclusive_scan<T>(acc, tmp, total) + before;
+  if (blockIdx.x == nb - 1 && threadIdx.x == 0) part[nb] = before + total;
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) tile[threadIdx.x * kScanItems + k] = pre + loc[k];
@@ -159,7 +151,8 @@ __global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, const T* 
   }
 }
 
-// exclusive scan of n elements into out[0..n); part[nb] receives the total
+// exclusive scan of n elements into out[0..n) (out may alias the loaded array: each block
+// reads its tile before writing it); part[0..nb) receives block totals, part[nb] the total
 template <typename T, typename Load>
 hipError_t device_scan(Load ld, int64_t n, T* out, T* part, hipStream_t s) {
   int64_t nb = div_up(n, kScanTile);
@@ -168,8 +161,7 @@ hipError_t device_scan(Load ld, int64_t n, T* out, T* part, hipStream_t s) {
     return hipGetLastError();
   }
   hipLaunchKernelGGL((k_scan_reduce<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, part);
-  hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(256), 0, s, part, nb);
-  hipLaunchKernelGGL((k_scan_down<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, (const T*)part, out);
+  hipLaunchKernelGGL((k_scan_down<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, part, nb, out);
   return hipGetLastError();
 }
 
@@ -409,19 +401,33 @@ __global__ __launch_bounds__(256) void k_emit(const DevSensor* __restrict__ sens
     s_off[i] = r < nv ? offs[r] : INT64_MAX;
   }
   __syncthreads();
-  for (int j = 0; j < kEmitTile / 256; ++j) {
+  // the thread's kPer slots go through each step together, so that their global loads overlap
+  constexpr int kPer = kEmitTile / 256;
+  int rl[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
     const int64_t k = k0 + j * 256 + tid;
-    if (k >= K) break;
     int lo = 0, hi = kEmitTile;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (s_off[mid] <= k) lo = mid; else hi = mid - 1;
     }
-    const uint32_t rec = order[r0 + lo];
-    const int jj = (int)(k - s_off[lo]);
-    const int s = count == 1 ? 0 : (int)(rec / (uint32_t)N);
-    const uint32_t g = rec - (uint32_t)s * (uint32_t)N;
-    keys[k] = (uint32_t)(local_tile_base(sens, s) + rect_tile(sens[s], rect[rec], jj));
+    rl[j] = lo;
+  }
+  uint32_t rec[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) rec[j] = (k0 + j * 256 + tid < K) ? order[r0 + rl[j]] : 0u;
+  int4 rc[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) rc[j] = (k0 + j * 256 + tid < K) ? rect[rec[j]] : make_int4(0, 0, 1, 1);
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int64_t k = k0 + j * 256 + tid;
+    if (k >= K) break;
+    const int jj = (int)(k - s_off[rl[j]]);
+    const int s = count == 1 ? 0 : (int)(rec[j] / (uint32_t)N);
+    const uint32_t g = rec[j] - (uint32_t)s * (uint32_t)N;
+    keys[k] = (uint32_t)(local_tile_base(sens, s) + rect_tile(sens[s], rc[j], jj));
     vals[k] = g;
   }
 }
@@ -443,23 +449,24 @@ __global__ void k_entry_base(const uint32_t* __restrict__ order, const int64_t* 
 constexpr int kRangeItems = 8;   // sorted keys per thread of k_ranges
 
 // [start, end) of every key's run in a sorted key array; keys that do not occur keep the range
-// the caller filled in.
+// the caller filled in.  Thread t of a block handles elements base + j * 256 + t (coalesced).
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap, int2* __restrict__ range) {
-  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeItems;
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * kRangeItems + threadIdx.x;
   const int64_t n = sort_count(n_ptr, n_cap);
-  if (i0 >= n) return;
-  uint32_t k[kRangeItems + 2];
+  uint32_t cur[kRangeItems], prev[kRangeItems], next[kRangeItems];
 #pragma unroll
-  for (int j = 0; j < kRangeItems + 2; ++j) {
-    const int64_t i = i0 - 1 + j;
-    k[j] = (i >= 0 && i < n) ? keys[i] : 0xFFFFFFFFu;
+  for (int j = 0; j < kRangeItems; ++j) {
+    const int64_t i = base + (int64_t)j * blockDim.x;
+    cur[j] = i < n ? keys[i] : 0xFFFFFFFFu;
+    prev[j] = (i > 0 && i <= n) ? keys[i - 1] : 0xFFFFFFFFu;
+    next[j] = i + 1 < n ? keys[i + 1] : 0xFFFFFFFFu;
   }
 #pragma unroll
-  for (int j = 1; j <= kRangeItems; ++j) {
-    const int64_t i = i0 - 1 + j;
+  for (int j = 0; j < kRangeItems; ++j) {
+    const int64_t i = base + (int64_t)j * blockDim.x;
     if (i >= n) break;
-    if (k[j - 1] != k[j]) range[k[j]].x = (int)i;
-    if (k[j + 1] != k[j]) range[k[j]].y = (int)(i + 1);
+    if (prev[j] != cur[j]) range[cur[j]].x = (int)i;
+    if (next[j] != cur[j]) range[cur[j]].y = (int)(i + 1);
   }
 }
 
@@ -543,8 +550,17 @@ __global__ void k_work_emit(const DevSensor* __restrict__ sens, int count, const
     if (o < work_cap) work[o] = make_int2((int)t, p);
 }
 
-// Longest-processing-time order of the persistent queue: items sorted by descending length of
-// their tile's Gaussian list (key = 0xFFFF - min(length, 0xFFFF), stable).
+// Longest-processing-time order of the persistent queue: items sorted (stably) by descending
+// length of their tile's Gaussian list, in buckets of about 6 %: the key is 255 minus an 8-bit
+// log-scale code of the length (4 bits of exponent, 4 bits of mantissa).
+__device__ __forceinline__ uint32_t length_code(int64_t len) {
+  const uint32_t x = (uint32_t)(len < 0xFFFFF ? len : 0xFFFFF) + 1u;   // >= 1
+  const int e = 31 - __clz(x);                                       // 0..20
+  const uint32_t m = e >= 4 ? (x >> (e - 4)) & 15u : (x << (4 - e)) & 15u;
+  const uint32_t c = ((uint32_t)e << 4) | m;
+  return c < 255u ? c : 255u;
+}
+
 __global__ void k_queue_keys(const int2* __restrict__ work, const int32_t* __restrict__ n_work,
                              const int2* __restrict__ tile_range, int64_t n_tiles, uint32_t* __restrict__ keys,
                              uint32_t* __restrict__ vals) {
@@ -556,7 +572,7 @@ __global__ void k_queue_keys(const int2* __restrict__ work, const int32_t* __res
     int2 r = tile_range[t];
     len = r.y - r.x;
   }
-  keys[i] = 0xFFFFu - (uint32_t)(len < 0xFFFF ? len : 0xFFFF);
+  keys[i] = 255u - length_code(len);
   vals[i] = (uint32_t)i;
 }
 
@@ -705,7 +721,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
       uint32_t* qv[2] = {w.qvals[0], w.qvals[1]};
       int qcur = 0;
       // item count: the scan total (clamped to the capacity by the sort)
-      if ((e = radix_sort<uint32_t>(qk, qv, qcur, w.wcount + bins, wcap, 0, 16, w.hist, w.hist_part, nullptr, s)) !=
+      if ((e = radix_sort<uint32_t>(qk, qv, qcur, w.wcount + bins, wcap, 0, 8, w.hist, w.hist_part, nullptr, s)) !=
           hipSuccess)
         return e;
       hipLaunchKernelGGL(k_queue_gather, dim3((unsigned)div_up(wcap, 256)), dim3(256), 0, s, (const int2*)w.qtmp,

@@ -349,6 +349,15 @@ def test_batched_equals_plain():
             np.testing.assert_array_equal(a[key], p[key])
 
 
+def queue_length_code(lens):
+    """The library's documented queue bucket of a list length (binsort.hip, length_code):
+    4 bits of binary exponent and 4 bits of mantissa of min(len, 2^20 - 1) + 1."""
+    x = np.minimum(np.asarray(lens, np.int64), 0xFFFFF) + 1
+    e = np.floor(np.log2(x)).astype(np.int64)
+    m = np.where(e >= 4, (x >> np.maximum(e - 4, 0)) & 15, (x << np.maximum(4 - e, 0)) & 15)
+    return np.minimum((e << 4) | m, 255)
+
+
 def test_batched_queue_equals_plain():
     """Batched form (cameras and lidars in one call, persistent queue) against per-sensor calls:
     forward bit-identical, adjoint equal up to float atomic order."""
@@ -370,7 +379,7 @@ def test_batched_queue_equals_plain():
     work = bat.work.cpu().numpy()[:nw]
     tr = bat.tile_range.cpu().numpy()
     lens = np.array([tr[t, 1] - tr[t, 0] if t < bat.n_tiles else 0 for t in work[:, 0]])
-    assert np.all(np.diff(np.minimum(lens, 0xFFFF)) <= 0)
+    assert np.all(np.diff(queue_length_code(lens)) <= 0)
     n_cam_tiles = int(rig.tile_base[2])
     assert sorted(work[work[:, 0] < n_cam_tiles, 0].tolist()) == list(range(n_cam_tiles))
     R = bat.n_rays
