@@ -168,11 +168,14 @@ hipError_t device_scan(Load ld, int64_t n, T* out, T* part, hipStream_t s) {
 // ------------------------------------------------------------------------------------------
 // radix sort: stable, 8-bit digits, keys and values uint32
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int bits) {
+// Lanes of the wavefront whose (valid) digit equals this lane's: one ballot per digit bit.
+// Always 8 bits, unrolled; a narrower digit has zero high bits, whose ballots change nothing.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
   uint64_t m = __ballot(valid);
-  for (int b = 0; b < bits; ++b) {
-    bool bit = (d >> b) & 1u;
-    uint64_t bb = __ballot(valid && bit);
+#pragma unroll
+  for (int b = 0; b < kRadixBits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = __ballot(valid && bit);
     m &= bit ? bb : ~bb;
   }
   return m;
@@ -184,35 +187,31 @@ __device__ __forceinline__ int64_t sort_count(const int64_t* n_ptr, int64_t n_ca
   return n < n_cap ? n : n_cap;
 }
 
+// Per-block digit counts of one 4096-key tile, counted with LDS atomics into one histogram per
+// wavefront (order does not matter for counting), written digit-major: hist[d * nb + block].
 template <typename K>
 __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap,
                                                     int shift, int bits, uint32_t* __restrict__ hist, int64_t nb) {
-  __shared__ uint32_t cnt[kRadixBins];
-  const int tid = threadIdx.x;
-  cnt[tid] = 0;
+  __shared__ uint32_t cnt[4][kRadixBins];
+  const int tid = threadIdx.x, wid = tid >> 6;
+  cnt[0][tid] = cnt[1][tid] = cnt[2][tid] = cnt[3][tid] = 0;
   __syncthreads();
   const int64_t n = sort_count(n_ptr, n_cap);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   const uint32_t mask = (1u << bits) - 1u;
-  const uint64_t lt = lanemask_lt();
   if (base < n) {
-    // all loads first (independent), then the ranking
     uint32_t d[kScanItems];
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
       const int64_t i = base + (int64_t)r * kScanThreads + tid;
-      d[r] = i < n ? ((uint32_t)(keys[i] >> shift) & mask) : 0u;
+      d[r] = i < n ? ((uint32_t)(keys[i] >> shift) & mask) : 0xFFFFFFFFu;
     }
 #pragma unroll
-    for (int r = 0; r < kScanItems; ++r) {
-      if (base + (int64_t)r * kScanThreads >= n) break;   // uniform over the block
-      const bool valid = base + (int64_t)r * kScanThreads + tid < n;
-      const uint64_t m = match_digit(d[r], valid, bits);
-      if (valid && (m & lt) == 0) atomicAdd(&cnt[d[r]], (uint32_t)__popcll(m));
-    }
+    for (int r = 0; r < kScanItems; ++r)
+      if (d[r] != 0xFFFFFFFFu) atomicAdd(&cnt[wid][d[r]], 1u);
   }
   __syncthreads();
-  hist[(int64_t)tid * nb + blockIdx.x] = cnt[tid];
+  hist[(int64_t)tid * nb + blockIdx.x] = cnt[0][tid] + cnt[1][tid] + cnt[2][tid] + cnt[3][tid];
 }
 
 // Stable scatter of one block tile (4096 keys).  Wavefront w owns the contiguous quarter
@@ -257,7 +256,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   for (int r = 0; r < kScanItems; ++r) {
     const bool valid = wid * kPerWave + r * 64 + lane < cnt;
     const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
-    const uint64_t m = match_digit(d, valid, bits);
+    const uint64_t m = match_digit(d, valid);
     const uint32_t before = valid ? run[d] : 0u;
     rank[r] = before + (uint32_t)__popcll(m & lt);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -377,58 +376,86 @@ __global__ void k_finalize_count(const int64_t* __restrict__ total, int64_t k_ca
 }
 
 constexpr int kEmitTile = 2048;   // output slots per workgroup of the emit kernel
+constexpr int kEmitPer = kEmitTile / 256;   // consecutive slots per thread
 
-// One thread per output slot: slot k belongs to the visible record r (depth order) with
-// offs[r] <= k < offs[r + 1], found by a binary search over the offsets of the records that
-// overlap the workgroup's slots (staged in LDS, starting at the block's first record bstart);
-// the slot's tile is the (k - offs[r])-th tile of that record's rectangle.  Writes are
-// contiguous across lanes.
+// q = floor(a / b) for 0 <= a < 2^24, b >= 1, from a float reciprocal with an exact correction.
+__device__ __forceinline__ int div_small(int a, int b) {
+  int q = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
+  q -= (q * b > a) ? 1 : 0;
+  q += ((q + 1) * b <= a) ? 1 : 0;
+  return q;
+}
+
+// Thread t emits the kEmitPer consecutive slots k0 + t kEmitPer + j.  Slot k belongs to the
+// visible record r (depth order) with offs[r] <= k < offs[r + 1]: one binary search over the
+// offsets of the records overlapping the workgroup's slots (staged in LDS relative to k0,
+// starting at the block's first record bstart) finds the first slot's record, and the walk
+// advances at most one record per slot (every visible record has >= 1 slot).  The slot's tile
+// is the (k - offs[r])-th tile of the record's rectangle.  Results are staged in LDS and written
+// out coalesced.
 __global__ __launch_bounds__(256) void k_emit(const DevSensor* __restrict__ sens, int count, int64_t N,
                                               const int4* __restrict__ rect, const uint32_t* __restrict__ order,
                                               const int64_t* __restrict__ offs, const int64_t* __restrict__ n_vis,
                                               const int64_t* __restrict__ n_slots,
                                               const int64_t* __restrict__ bstart, uint32_t* __restrict__ keys,
                                               uint32_t* __restrict__ vals) {
-  __shared__ int64_t s_off[kEmitTile + 1];
+  __shared__ int s_off[kEmitTile + 2];   // offs[r0 + i] - k0, capped at kEmitTile + 1
+  __shared__ uint32_t s_key[kEmitTile], s_val[kEmitTile];
   const int tid = threadIdx.x;
   const int64_t K = *n_slots;
   const int64_t k0 = (int64_t)blockIdx.x * kEmitTile;
   if (k0 >= K) return;   // uniform
   const int64_t nv = *n_vis;
   const int64_t r0 = bstart[blockIdx.x];   // last record with offs[r] <= k0
-  for (int i = tid; i <= kEmitTile; i += 256) {
+  for (int i = tid; i < kEmitTile + 2; i += 256) {
     const int64_t r = r0 + i;
-    s_off[i] = r < nv ? offs[r] : INT64_MAX;
+    // a record starting before k0 keeps its exact (negative) offset: one record's slots fit int32
+    int64_t rel = r < nv ? offs[r] - k0 : (int64_t)kEmitTile + 1;
+    s_off[i] = (int)(rel > kEmitTile + 1 ? kEmitTile + 1 : rel);
   }
   __syncthreads();
-  // the thread's kPer slots go through each step together, so that their global loads overlap
-  constexpr int kPer = kEmitTile / 256;
-  int rl[kPer];
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    const int64_t k = k0 + j * 256 + tid;
-    int lo = 0, hi = kEmitTile;
+  const int nk = (int)((K - k0) < kEmitTile ? (K - k0) : kEmitTile);
+  const int j0 = tid * kEmitPer;
+  if (j0 < nk) {
+    int lo = 0, hi = kEmitTile;   // last i with s_off[i] <= j0
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= k) lo = mid; else hi = mid - 1;
+      if (s_off[mid] <= j0) lo = mid; else hi = mid - 1;
     }
-    rl[j] = lo;
+    int cur = -1;
+    uint32_t g = 0;
+    int4 rc = make_int4(0, 0, 1, 1);
+    int64_t tbase = 0;
+    const DevSensor* S = sens;
+#pragma unroll
+    for (int j = 0; j < kEmitPer; ++j) {
+      const int q = j0 + j;
+      if (q >= nk) break;
+      if (s_off[lo + 1] <= q) ++lo;
+      if (lo != cur) {
+        cur = lo;
+        const uint32_t rec = order[r0 + lo];
+        int s = 0;
+        if (count > 1) {
+          s = (int)((float)rec * __builtin_amdgcn_rcpf((float)N));
+          s -= ((int64_t)s * N > (int64_t)rec) ? 1 : 0;
+          s += ((int64_t)(s + 1) * N <= (int64_t)rec) ? 1 : 0;
+        }
+        g = rec - (uint32_t)s * (uint32_t)N;
+        rc = rect[rec];
+        S = sens + s;
+        tbase = local_tile_base(sens, s);
+      }
+      const int jj = q - s_off[lo];
+      const int row = div_small(jj, rc.z);
+      s_key[q] = (uint32_t)(tbase + rect_tile_rc(*S, rc, row, jj - row * rc.z));
+      s_val[q] = g;
+    }
   }
-  uint32_t rec[kPer];
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) rec[j] = (k0 + j * 256 + tid < K) ? order[r0 + rl[j]] : 0u;
-  int4 rc[kPer];
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) rc[j] = (k0 + j * 256 + tid < K) ? rect[rec[j]] : make_int4(0, 0, 1, 1);
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    const int64_t k = k0 + j * 256 + tid;
-    if (k >= K) break;
-    const int jj = (int)(k - s_off[rl[j]]);
-    const int s = count == 1 ? 0 : (int)(rec[j] / (uint32_t)N);
-    const uint32_t g = rec[j] - (uint32_t)s * (uint32_t)N;
-    keys[k] = (uint32_t)(local_tile_base(sens, s) + rect_tile(sens[s], rc[j], jj));
-    vals[k] = g;
+  __syncthreads();
+  for (int q = tid; q < nk; q += 256) {
+    keys[k0 + q] = s_key[q];
+    vals[k0 + q] = s_val[q];
   }
 }
 

@@ -308,16 +308,17 @@ HD void lidar_rect(const DevSensor& S, ProjOut& o) {
   o.n_tiles = n * ne;
 }
 
-// Tile (sensor-local id) of the j-th entry of a record's rectangle r = (x0, y0, w, h): entries
-// are numbered row-major, and lidar azimuth tiles wrap modulo M_phi.
-HD int64_t rect_tile(const DevSensor& S, const int4 r, int j) {
-  if (S.kind == kCamera) {
-    const int tx = r.x + j % r.z, ty = r.y + j / r.z;
-    return (int64_t)ty * S.tiles_x + tx;
-  }
-  const int a = (r.x + j % r.z) % S.m_az, e = r.y + j / r.z;
-  return (int64_t)e * S.m_az + a;
+// Tile (sensor-local id) at (row, col) of a record's rectangle r = (x0, y0, w, h); lidar
+// azimuth tiles wrap modulo M_phi (x0 < M_phi and w <= M_phi, so one subtraction suffices).
+HD int64_t rect_tile_rc(const DevSensor& S, const int4 r, int row, int col) {
+  if (S.kind == kCamera) return (int64_t)(r.y + row) * S.tiles_x + (r.x + col);
+  int a = r.x + col;
+  a -= a >= S.m_az ? S.m_az : 0;
+  return (int64_t)(r.y + row) * S.m_az + a;
 }
+
+// Tile of the j-th entry of rectangle r: entries are numbered row-major.
+HD int64_t rect_tile(const DevSensor& S, const int4 r, int j) { return rect_tile_rc(S, r, j / r.z, j % r.z); }
 
 // Inverse of rect_tile: the entry number of sensor-local tile t inside rectangle r.
 HD int rect_entry(const DevSensor& S, const int4 r, int64_t t) {
