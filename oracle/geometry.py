@@ -205,8 +205,10 @@ def project_lidar(p: Params, lid) -> Projection:
     r = torch.sqrt(x * x + y * y + z * z)
     with torch.no_grad():
         in_range = (r >= lid.r_min) & (r <= lid.r_max) & (rho >= 1e-4 * r)
-    # keep culled entries finite: substitute a harmless point
-    safe = in_range[:, None]
+        # the spherical map is singular on the z axis and at the origin: substitute a harmless
+        # point there only, so that range-culled entries keep their true (finite) box
+        regular = (rho >= 1e-4 * r) & (r > 0)
+    safe = regular[:, None]
     mu_s = torch.where(safe, mu, torch.tensor([1.0, 0.0, 0.0], dtype=D).expand_as(mu))
     xs, ys, zs = mu_s.unbind(-1)
     rs = torch.sqrt(xs * xs + ys * ys + zs * zs)

@@ -118,9 +118,26 @@ def _tile_mask(proj, sensor, cols, rays_tile):
     return torch.from_numpy(m)
 
 
-def _composite(proj, feats, rays_p, rays_t, idx, cand):
+def _alpha_at(proj, ids, rays_p, rays_t):
+    """alpha of Gaussians `ids` at the rays (as if they were candidates), [r, len(ids)]."""
+    mean = proj.mean2d[ids].detach()
+    vel = proj.vel2d[ids].detach()
+    con = proj.conic[ids].detach()
+    o = proj.o_eff[ids].detach()
+    delta = rays_p[:, None, :] - (mean[None] + vel[None] * rays_t[:, None, None])
+    if proj.kind == "lidar":
+        d_az = torch.remainder(delta[..., 0] + math.pi, TWO_PI) - math.pi
+        delta = torch.stack([d_az, delta[..., 1]], -1)
+    dx, dy = delta[..., 0], delta[..., 1]
+    sigma = 0.5 * (con[None, :, 0] * dx * dx + con[None, :, 2] * dy * dy) + con[None, :, 1] * dx * dy
+    return torch.clamp(o[None] * torch.exp(-sigma), max=ALPHA_MAX)
+
+
+def _composite(proj, feats, rays_p, rays_t, idx, cand, amb=None):
     """Front-to-back compositing of the Gaussians `idx` (already in (depth, id) order) for a
-    chunk of rays; `cand` [r,K] marks candidacy.  Returns differentiable F, D, A and
+    chunk of rays; `cand` [r,K] marks candidacy.  `amb` [r,K] marks Gaussians whose candidacy
+    is a near-edge decision: the ray is near-decision if one of them would pass the alpha skip
+    rule at or before the point where the ray stops.  Returns differentiable F, D, A and
     diagnostics."""
     mean = proj.mean2d[idx]
     vel = proj.vel2d[idx]
@@ -168,17 +185,24 @@ def _composite(proj, feats, rays_p, rays_t, idx, cand):
         clamped = cand & (alpha_raw > ALPHA_MAX)
         sig = torch.stack([(keep * ids1).sum(1), (keep * ids1 * ids1).sum(1),
                            (clamped * ids1).sum(1)], -1)
-        # near-decision diagnostics
-        near = (cand & (torch.abs(alpha * 255.0 - 1.0) <= NEAR_ALPHA)).any(1)
-        near |= (cand & (torch.abs(alpha_raw / ALPHA_MAX - 1.0) <= NEAR_ALPHA)).any(1)
+        # near-decision diagnostics: decisions at or before the point where the ray stops
+        reached = cand & (torch.arange(K)[None, :] <= first[:, None])
+        near = (reached & (torch.abs(alpha * 255.0 - 1.0) <= NEAR_ALPHA)).any(1)
+        near |= (reached & (torch.abs(alpha_raw / ALPHA_MAX - 1.0) <= NEAR_ALPHA)).any(1)
         upto = keep1 & (torch.arange(K)[None, :] <= first[:, None])
         near |= (upto & (torch.abs(t_try / T_STOP - 1.0) <= NEAR_T)).any(1)
         near |= (keep & (torch.abs(ta / 0.5 - 1.0) <= NEAR_T)).any(1)
-        # depth near-ties among Gaussians that pass the skip rule
+        if amb is not None:
+            matters = amb & (alpha >= ALPHA_MIN * (1.0 - NEAR_ALPHA)) & (torch.arange(K)[None, :] <= first[:, None])
+            near |= matters.any(1)
+        # depth near-ties among Gaussians that pass the skip rule up to the stop: distinct depths
+        # closer than the ordering key resolves may be ordered differently; exactly equal depths
+        # are ordered by id on both sides
         dep = proj.depth[idx].detach()
         if K > 1:
-            close = torch.abs(dep[1:] - dep[:-1]) <= NEAR_DEPTH * dep[1:]
-            both = keep1[:, 1:] & keep1[:, :-1]
+            gap = torch.abs(dep[1:] - dep[:-1])
+            close = (gap <= NEAR_DEPTH * dep[1:]) & (gap > 0)
+            both = upto[:, 1:] & upto[:, :-1]
             near |= (both & close[None, :]).any(1)
     return F, Dv, A, T_final, median, last_id, n_kept, near, sig
 
@@ -208,17 +232,21 @@ def render(proj, sensor, feats_all, rays: Rays, mode: str = "box", chunk: int = 
             cand_all = _box_mask(proj, order, p) & rv[:, None]
             wide = _box_mask(proj, order, p, NEAR_BOX) & rv[:, None]
             narrow = _box_mask(proj, order, p, -NEAR_BOX) & rv[:, None]
-            near_box = (wide != narrow).any(1)
+            amb_all = wide != narrow   # candidacy decided within the float32 ambiguity band
+            near_box = torch.zeros(e - s, dtype=torch.bool)
         else:
             cand_all = _tile_mask(proj, sensor, order, rays.tile[s:e])
             near_box = torch.zeros(e - s, dtype=torch.bool)
             wide = cand_all
-        # culled-but-near-threshold Gaussians whose box reaches the ray also make it near
-        all_ids = np.nonzero(near_cull & ~valid)[0]
-        if all_ids.shape[0] > 0:
-            near_box |= _box_mask(proj, all_ids, p, NEAR_BOX).any(1)
-        near_box |= (wide & torch.from_numpy(near_cull[order])[None, :]).any(1)
-        cols = cand_all.any(0).numpy()
+            amb_all = None
+        # Gaussians whose culling is a near-threshold decision make the ray near if their box
+        # reaches it and they would pass the alpha skip rule there
+        nc_ids = np.nonzero(near_cull)[0]
+        if nc_ids.shape[0] > 0:
+            reach = _box_mask(proj, nc_ids, p, NEAR_BOX) & rv[:, None]
+            blends = _alpha_at(proj, nc_ids, p, t) >= ALPHA_MIN * (1.0 - NEAR_ALPHA)
+            near_box |= (reach & blends).any(1)
+        cols = (cand_all | (amb_all if amb_all is not None else cand_all)).any(0).numpy()
         idx = order[cols]
         if idx.shape[0] == 0:
             r = e - s
@@ -233,7 +261,8 @@ def render(proj, sensor, feats_all, rays: Rays, mode: str = "box", chunk: int = 
             outNear.append(near_box)
             outS.append(torch.zeros(r, 3, dtype=D))
             continue
-        F, Dv, A, T, M, L, N, near, S = _composite(proj, feats, p, t, idx, cand_all[:, cols])
+        F, Dv, A, T, M, L, N, near, S = _composite(proj, feats, p, t, idx, cand_all[:, cols],
+                                                   None if amb_all is None else amb_all[:, cols])
         outS.append(S)
         outF.append(F)
         outD.append(Dv)

@@ -112,18 +112,43 @@ __global__ __launch_bounds__(256) void k_scan_reduce(Load ld, int64_t n, T* __re
   if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
-// Block b: exclusive scan of its tile, offset by the sum of the block totals part[0..b) (read
-// by the block itself); the last block writes the grand total to part[nb].
+// Up to this many blocks every down-sweep block sums the block totals before it itself (one
+// launch fewer); beyond it a single block scans the totals first.
+constexpr int64_t kScanFusedBlocks = 1024;
+
+// single block: exclusive scan of part[0..nb) in place, part[nb] = total
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan_partials(T* __restrict__ part, int64_t nb) {
+  __shared__ T tmp[4];
+  T carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+    int64_t i = b0 + threadIdx.x;
+    T v = i < nb ? part[i] : (T)0;
+    T total;
+    T ex = block_exclusive_scan<T>(v, tmp, total);
+    if (i < nb) part[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) part[nb] = carry;
+}
+
+// Block b: exclusive scan of its tile, offset by the total of the blocks before it: with
+// `fused`, the sum of the block totals part[0..b) (read by the block itself; the last block
+// writes the grand total to part[nb]), otherwise part[b] as scanned by k_scan_partials.
 template <typename T, typename Load>
-__global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, T* __restrict__ part, int64_t nb,
+__global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, T* __restrict__ part, int64_t nb, bool fused,
                                                    T* __restrict__ out) {
   __shared__ T tile[kScanTile];
   __shared__ T tmp[4];
   int64_t base = (int64_t)blockIdx.x * kScanTile;
-  T pb = 0;
-  for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) pb += part[i];
   T before;
-  block_exclusive_scan<T>(pb, tmp, before);
+  if (fused) {
+    T pb = 0;
+    for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) pb += part[i];
+    block_exclusive_scan<T>(pb, tmp, before);
+  } else {
+    before = part[blockIdx.x];
+  }
 #pragma unroll 4
   for (int r = 0; r < kScanItems; ++r) {
     int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
@@ -139,7 +164,7 @@ __global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, T* __rest
   }
   T total;
   T pre = block_exclusive_scan<T>(acc, tmp, total) + before;
-  if (blockIdx.x == nb - 1 && threadIdx.x == 0) part[nb] = before + total;
+  if (fused && blockIdx.x == nb - 1 && threadIdx.x == 0) part[nb] = before + total;
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) tile[threadIdx.x * kScanItems + k] = pre + loc[k];
@@ -152,7 +177,7 @@ __global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, T* __rest
 }
 
 // exclusive scan of n elements into out[0..n) (out may alias the loaded array: each block
-// reads its tile before writing it); part[0..nb) receives block totals, part[nb] the total
+// reads its tile before writing it); part[nb] receives the total
 template <typename T, typename Load>
 hipError_t device_scan(Load ld, int64_t n, T* out, T* part, hipStream_t s) {
   int64_t nb = div_up(n, kScanTile);
@@ -161,7 +186,10 @@ hipError_t device_scan(Load ld, int64_t n, T* out, T* part, hipStream_t s) {
     return hipGetLastError();
   }
   hipLaunchKernelGGL((k_scan_reduce<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, part);
-  hipLaunchKernelGGL((k_scan_down<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, part, nb, out);
+  const bool fused = nb <= kScanFusedBlocks;
+  if (!fused) hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(256), 0, s, part, nb);
+  hipLaunchKernelGGL((k_scan_down<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, part, nb, fused,
+                     out);
   return hipGetLastError();
 }
 
@@ -407,17 +435,27 @@ __global__ __launch_bounds__(256) void k_emit(const DevSensor* __restrict__ sens
   if (k0 >= K) return;   // uniform
   const int64_t nv = *n_vis;
   const int64_t r0 = bstart[blockIdx.x];   // last record with offs[r] <= k0
-  for (int i = tid; i < kEmitTile + 2; i += 256) {
-    const int64_t r = r0 + i;
-    // a record starting before k0 keeps its exact (negative) offset: one record's slots fit int32
-    int64_t rel = r < nv ? offs[r] - k0 : (int64_t)kEmitTile + 1;
-    s_off[i] = (int)(rel > kEmitTile + 1 ? kEmitTile + 1 : rel);
+  // stage offsets in rounds of 256 records until they pass the block's last slot (a block
+  // usually overlaps far fewer than kEmitTile records)
+  int n_loaded = 0;
+  for (int i0 = 0; i0 < kEmitTile + 2; i0 += 256) {
+    const int i = i0 + tid;
+    int v = kEmitTile + 1;
+    if (i < kEmitTile + 2) {
+      const int64_t r = r0 + i;
+      // a record starting before k0 keeps its exact (negative) offset: one record's slots fit int32
+      const int64_t rel = r < nv ? offs[r] - k0 : (int64_t)kEmitTile + 1;
+      v = (int)(rel > kEmitTile + 1 ? kEmitTile + 1 : rel);
+      s_off[i] = v;
+    }
+    n_loaded = i0 + 256;
+    if (__syncthreads_count(v <= kEmitTile) < 256) break;   // uniform: some record starts past the block
   }
-  __syncthreads();
+  if (n_loaded > kEmitTile + 2) n_loaded = kEmitTile + 2;
   const int nk = (int)((K - k0) < kEmitTile ? (K - k0) : kEmitTile);
   const int j0 = tid * kEmitPer;
   if (j0 < nk) {
-    int lo = 0, hi = kEmitTile;   // last i with s_off[i] <= j0
+    int lo = 0, hi = n_loaded - 2;   // last i with s_off[i] <= j0 (s_off[n_loaded - 1] > j0)
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (s_off[mid] <= j0) lo = mid; else hi = mid - 1;

@@ -1,0 +1,155 @@
+"""Full-size configurations in the batched launch form that bench.py times (one call per stage
+for all sensors of the scene, persistent queue rasterisers), against the FP64 oracle on
+sampled rays:
+
+* C2 (500k Gaussians, 1080p rolling-shutter camera), C3 (2M Gaussians, 128 x 2048 lidar sweep),
+  C4 (1.5M Gaussians, 6 cameras of uneven sizes + a 64 x 1800 lidar): forward values of sampled
+  rays of every sensor, and gradients.  For the gradients the upstream gradient is nonzero only
+  on the sampled rays, so the exact gradient is a sum over those rays that the oracle evaluates
+  over all Gaussians, element by element.
+* C5 (3M Gaussians, 48 lidar sweeps of 32 / 64 / 128 beams and 12 cameras): forward values of
+  sampled rays, rendered as batched calls over sensor groups.
+
+Bars as in test_gpu_parity: 1e-5 + 1e-4 |ref| per rendered element on rays without a
+near-threshold decision; gradients within 1e-3 relative per tensor and per element."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import geometry as geo
+from oracle import grad as ogr
+from oracle import render as rd
+from scenes import synthetic as S
+from tests.gpu_helpers import gpu_outputs, rtol_check
+
+pytestmark = pytest.mark.gpu
+
+
+def _binding():
+    from paper_2411_16816_amd import binding
+    binding.load()
+    return binding
+
+
+def _render(sc):
+    b = _binding()
+    rig = b.Rig(sc.cameras, sc.lidars)
+    G = b.GaussTensors.from_numpy(sc.gaussians)
+    n_s = len(rig.sensors)
+    sp = b.SensorPass(rig, 0, n_s, sc.gaussians.n, 1, batched=True)
+    sp.fit_capacity(G, 1.1)
+    sp.status.zero_()
+    sp.render(G)
+    torch.cuda.synchronize()
+    st = b.read_status(sp.status)
+    assert st.overflow == 0 and st.n_nonfinite == 0
+    return b, rig, G, sp
+
+
+def _check_forward(sp, rig, g, k, idx):
+    return _check_forward_at(sp, rig, g, 0, k, idx)
+
+
+def _check_forward_at(sp, rig, g, first, k, idx):
+    """Sampled rays of sensor k of a call starting at rig sensor `first`, against the oracle;
+    returns the oracle's near mask."""
+    sensor = rig.sensors[first + k]
+    out = gpu_outputs(sp, k)
+    ref = rd.render_sensor(g, sensor, idx)
+    ok = ~ref["near"]
+    # a sanity bound: the exclusion must leave most sampled rays to compare
+    assert ref["near"].sum() <= max(2, 0.15 * len(idx)), (first + k, int(ref["near"].sum()), len(idx))
+    for key, refv in (("F", ref["F"]), ("D", ref["D"]), ("A", ref["A"])):
+        got = out[key][idx]
+        bad = rtol_check(got, refv.numpy(), mask=ok)
+        assert not bad.any(), (k, key, int(bad.sum()))
+    if "median" in out and hasattr(sensor, "ray_az"):
+        bad = rtol_check(out["median"][idx], ref["median"].numpy(), mask=ok)
+        assert not bad.any(), (k, "median", int(bad.sum()))
+    return ref["near"]
+
+
+def _config(name):
+    return {"c2": S.config_2, "c3": S.config_3, "c4": S.config_4, "c5": S.config_5}[name]()
+
+
+@pytest.mark.parametrize("cfg,rays", [("c2", 24), ("c3", 24), ("c4", 6)])
+def test_full_size_forward_and_gradients(cfg, rays):
+    sc = _config(cfg)
+    print(f"[configs] {sc.name}: {sc.gaussians.n} Gaussians, {len(sc.cameras)} cameras, {len(sc.lidars)} lidars",
+          flush=True)
+    b, rig, G, sp = _render(sc)
+    g = sc.gaussians
+    rng = np.random.default_rng(404)
+    up = np.random.default_rng(405)
+    dF = np.zeros(sp.n_feat, np.float32)
+    dD = np.zeros(sp.n_rays, np.float32)
+    dA = np.zeros(sp.n_rays, np.float32)
+    picks = []
+    for k, sensor in enumerate(rig.sensors):
+        idx = np.sort(rng.choice(sensor.n_rays, size=rays, replace=False))
+        near = _check_forward(sp, rig, g, k, idx)
+        keep = idx[~near]                       # near-threshold rays get no upstream gradient
+        rs, fs, C = sp.sensor_slices(k)
+        dFk = up.normal(size=(len(keep), C)).astype(np.float32)
+        dDk = (0.1 * up.normal(size=len(keep))).astype(np.float32)
+        dAk = up.normal(size=len(keep)).astype(np.float32)
+        dF[fs.start:fs.stop].reshape(-1, C)[keep] = dFk
+        dD[rs.start + keep] = dDk
+        dA[rs.start + keep] = dAk
+        picks.append((sensor, keep, dFk, dDk, dAk))
+    grads = b.zeros_like_grads(G)
+    t = lambda a: torch.from_numpy(a).cuda()
+    sp.raster_bwd(G, t(dF), t(dD), t(dA), grads)
+    torch.cuda.synchronize()
+    ref = None
+    for sensor, keep, dFk, dDk, dAk in picks:
+        r, _ = ogr.reference_grads(g, sensor, keep, dFk, dDk, dAk)
+        ref = r if ref is None else {n: ref[n] + r[n] for n in ref}
+    got = dict(means=grads.means, log_scales=grads.log_scales, quats=grads.quats, opacities=grads.opacities,
+               velocities=grads.velocities, features=grads.features)
+    for name in geo.Params.names:
+        gg = got[name].cpu().numpy().astype(np.float64)
+        rr = ref[name]
+        nrm = np.linalg.norm(rr)
+        assert nrm > 0, name
+        assert np.linalg.norm(gg - rr) / nrm <= 1e-3, (cfg, name, np.linalg.norm(gg - rr) / nrm)
+        bad = np.abs(gg - rr) > 1e-3 * np.abs(rr) + 1e-5 * np.abs(rr).max()
+        nz = int(((rr != 0) | (gg != 0)).sum())   # elements that a sampled ray reaches
+        assert bad.sum() <= max(2, 2e-3 * nz), (cfg, name, int(bad.sum()), nz)
+
+
+def test_full_size_c5_forward():
+    """C5's 60 sensors hold more (tile, Gaussian) entries than one call's lists address (int32
+    positions), so the sweep renders as several batched calls over sensor groups: 6 cameras,
+    8 sweeps of 128 beams, and a mixed group of a camera with 32-beam sweeps."""
+    b = _binding()
+    sc = _config("c5")
+    n_cam, n_lid = len(sc.cameras), len(sc.lidars)
+    print(f"[configs] {sc.name}: {sc.gaussians.n} Gaussians, {n_cam} cameras, {n_lid} lidars", flush=True)
+    rig = b.Rig(sc.cameras, sc.lidars)
+    G = b.GaussTensors.from_numpy(sc.gaussians)
+    rng = np.random.default_rng(505)
+    groups = [(0, 6), (n_cam + 32, 8), (n_cam - 1, 9)]
+    for first, count in groups:
+        sp = b.SensorPass(rig, first, count, sc.gaussians.n, 1, batched=True)
+        K = sp.fit_capacity(G, 1.1)
+        print(f"[configs] group [{first}, {first + count}): {K} entries", flush=True)
+        sp.status.zero_()
+        sp.render(G)
+        torch.cuda.synchronize()
+        st = b.read_status(sp.status)
+        assert st.overflow == 0 and st.n_nonfinite == 0
+        for k in (0, count - 1):
+            idx = np.sort(rng.choice(rig.sensors[first + k].n_rays, size=6, replace=False))
+            _check_forward_at(sp, rig, sc.gaussians, first, k, idx)
+        # the group's last sensor rendered by a per-sensor call: bit-identical
+        one = b.SensorPass(rig, first + count - 1, 1, sc.gaussians.n, 1)
+        one.fit_capacity(G, 1.1)
+        one.render(G)
+        torch.cuda.synchronize()
+        a_, p_ = gpu_outputs(sp, count - 1), gpu_outputs(one, 0)
+        for key in ("F", "D", "A", "T"):
+            np.testing.assert_array_equal(a_[key], p_[key], err_msg=f"group {first} {key}")
+        del sp, one
+        torch.cuda.empty_cache()
