@@ -446,6 +446,9 @@ int splat_pipeline_create(const SplatRig* r, int32_t first, int32_t count, const
   if (rc == SPLAT_OK && ec != hipSuccess) rc = SPLAT_ERR_DEVICE;
   if (rc == SPLAT_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
     rc = SPLAT_ERR_DEVICE;
+  // move the graph's launch setup to creation time instead of the first run
+  if (rc == SPLAT_OK && (hipGraphUpload(p->exec, p->cap) != hipSuccess || hipStreamSynchronize(p->cap) != hipSuccess))
+    rc = SPLAT_ERR_DEVICE;
   if (rc != SPLAT_OK) {
     pipeline_free(p);
     return rc;

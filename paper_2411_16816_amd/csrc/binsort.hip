@@ -329,9 +329,11 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
 // Sorts (k[cur], v[cur]) stably by key bits [lo_bit, lo_bit + total_bits).  On return `cur`
 // indexes the sorted keys; the sorted values are in v[cur], or in `final_vals` when it is
 // non-null.  n_ptr (device) gives the element count when non-null, capped by n_cap.
+// `first_hist_ready`: the caller already wrote the first pass's digit counts into `hist`.
 template <typename K>
 static hipError_t radix_sort(K* k[2], uint32_t* v[2], int& cur, const int64_t* n_ptr, int64_t n_cap, int lo_bit,
-                             int total_bits, uint32_t* hist, uint32_t* hist_part, uint32_t* final_vals, hipStream_t s) {
+                             int total_bits, uint32_t* hist, uint32_t* hist_part, uint32_t* final_vals, hipStream_t s,
+                             bool first_hist_ready = false) {
   if (total_bits < 1) total_bits = 1;
   const int passes = (total_bits + kRadixBits - 1) / kRadixBits;
   const int64_t nb = div_up(n_cap, kScanTile);
@@ -339,8 +341,9 @@ static hipError_t radix_sort(K* k[2], uint32_t* v[2], int& cur, const int64_t* n
   for (int p = 0; p < passes; ++p) {
     const int shift = lo_bit + p * kRadixBits;
     const int bits = (total_bits - p * kRadixBits) < kRadixBits ? (total_bits - p * kRadixBits) : kRadixBits;
-    hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(256), 0, s, (const K*)k[cur], n_ptr, n_cap, shift,
-                       bits, hist, nb);
+    if (!(p == 0 && first_hist_ready))
+      hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(256), 0, s, (const K*)k[cur], n_ptr, n_cap, shift,
+                         bits, hist, nb);
     hipError_t e = device_scan<uint32_t>(LoadU32{hist}, (int64_t)kRadixBins * nb, hist, hist_part, s);
     if (e != hipSuccess) return e;
     uint32_t* vdst = (p == passes - 1 && final_vals) ? final_vals : v[1 - cur];
@@ -403,8 +406,9 @@ __global__ void k_finalize_count(const int64_t* __restrict__ total, int64_t k_ca
   }
 }
 
-constexpr int kEmitTile = 2048;   // output slots per workgroup of the emit kernel
-constexpr int kEmitPer = kEmitTile / 256;   // consecutive slots per thread
+constexpr int kEmitTile = kScanTile;   // output slots per workgroup of the emit kernel = one radix tile
+constexpr int kEmitThreads = 512;
+constexpr int kEmitPer = kEmitTile / kEmitThreads;   // consecutive slots per thread
 
 // q = floor(a / b) for 0 <= a < 2^24, b >= 1, from a float reciprocal with an exact correction.
 __device__ __forceinline__ int div_small(int a, int b) {
@@ -420,25 +424,35 @@ __device__ __forceinline__ int div_small(int a, int b) {
 // starting at the block's first record bstart) finds the first slot's record, and the walk
 // advances at most one record per slot (every visible record has >= 1 slot).  The slot's tile
 // is the (k - offs[r])-th tile of the record's rectangle.  Results are staged in LDS and written
-// out coalesced.
-__global__ __launch_bounds__(256) void k_emit(const DevSensor* __restrict__ sens, int count, int64_t N,
-                                              const int4* __restrict__ rect, const uint32_t* __restrict__ order,
-                                              const int64_t* __restrict__ offs, const int64_t* __restrict__ n_vis,
-                                              const int64_t* __restrict__ n_slots,
-                                              const int64_t* __restrict__ bstart, uint32_t* __restrict__ keys,
-                                              uint32_t* __restrict__ vals) {
+// out coalesced.  A workgroup's slots are exactly one tile of the radix sort that follows, so it
+// also writes that tile's counts of the low key digit (the first pass's histogram,
+// hist[d * nb + block], zero for blocks past the last slot).
+__global__ __launch_bounds__(kEmitThreads) void k_emit(const DevSensor* __restrict__ sens, int count, int64_t N,
+                                                       const int4* __restrict__ rect,
+                                                       const uint32_t* __restrict__ order,
+                                                       const int64_t* __restrict__ offs,
+                                                       const int64_t* __restrict__ n_vis,
+                                                       const int64_t* __restrict__ n_slots,
+                                                       const int64_t* __restrict__ bstart, uint32_t* __restrict__ keys,
+                                                       uint32_t* __restrict__ vals, uint32_t* __restrict__ hist,
+                                                       int64_t nb) {
   __shared__ int s_off[kEmitTile + 2];   // offs[r0 + i] - k0, capped at kEmitTile + 1
   __shared__ uint32_t s_key[kEmitTile], s_val[kEmitTile];
+  __shared__ uint32_t s_cnt[kRadixBins];
   const int tid = threadIdx.x;
   const int64_t K = *n_slots;
   const int64_t k0 = (int64_t)blockIdx.x * kEmitTile;
-  if (k0 >= K) return;   // uniform
+  if (tid < kRadixBins) s_cnt[tid] = 0;
+  if (k0 >= K) {   // uniform
+    if (tid < kRadixBins) hist[(int64_t)tid * nb + blockIdx.x] = 0;
+    return;
+  }
   const int64_t nv = *n_vis;
   const int64_t r0 = bstart[blockIdx.x];   // last record with offs[r] <= k0
   // stage offsets in rounds of 256 records until they pass the block's last slot (a block
   // usually overlaps far fewer than kEmitTile records)
   int n_loaded = 0;
-  for (int i0 = 0; i0 < kEmitTile + 2; i0 += 256) {
+  for (int i0 = 0; i0 < kEmitTile + 2; i0 += kEmitThreads) {
     const int i = i0 + tid;
     int v = kEmitTile + 1;
     if (i < kEmitTile + 2) {
@@ -448,8 +462,8 @@ __global__ __launch_bounds__(256) void k_emit(const DevSensor* __restrict__ sens
       v = (int)(rel > kEmitTile + 1 ? kEmitTile + 1 : rel);
       s_off[i] = v;
     }
-    n_loaded = i0 + 256;
-    if (__syncthreads_count(v <= kEmitTile) < 256) break;   // uniform: some record starts past the block
+    n_loaded = i0 + kEmitThreads;
+    if (__syncthreads_count(v <= kEmitTile) < kEmitThreads) break;   // uniform: a record starts past the block
   }
   if (n_loaded > kEmitTile + 2) n_loaded = kEmitTile + 2;
   const int nk = (int)((K - k0) < kEmitTile ? (K - k0) : kEmitTile);
@@ -486,15 +500,18 @@ __global__ __launch_bounds__(256) void k_emit(const DevSensor* __restrict__ sens
       }
       const int jj = q - s_off[lo];
       const int row = div_small(jj, rc.z);
-      s_key[q] = (uint32_t)(tbase + rect_tile_rc(*S, rc, row, jj - row * rc.z));
+      const uint32_t key = (uint32_t)(tbase + rect_tile_rc(*S, rc, row, jj - row * rc.z));
+      s_key[q] = key;
       s_val[q] = g;
+      atomicAdd(&s_cnt[key & (kRadixBins - 1)], 1u);
     }
   }
   __syncthreads();
-  for (int q = tid; q < nk; q += 256) {
+  for (int q = tid; q < nk; q += kEmitThreads) {
     keys[k0 + q] = s_key[q];
     vals[k0 + q] = s_val[q];
   }
+  if (tid < kRadixBins) hist[(int64_t)tid * nb + blockIdx.x] = s_cnt[tid];
 }
 
 // entry_base[rec] = emission position of the record's first entry (depth order i -> record)
@@ -738,13 +755,15 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   if (passes % 2 == 0) { tv[0] = (uint32_t*)L.gauss; tv[1] = w.tvals; }
   else { tv[0] = w.tvals; tv[1] = (uint32_t*)L.gauss; }
   if (n_rec > 0 && L.k_cap > 0)
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks), dim3(256), 0, s, v.sens, v.count, v.n_gauss,
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks), dim3(kEmitThreads), 0, s, v.sens, v.count, v.n_gauss,
                        (const int4*)p.rect, order, (const int64_t*)w.offs, (const int64_t*)n_vis,
-                       (const int64_t*)n_sort, (const int64_t*)w.bstart, w.tkeys[0], tv[0]);
+                       (const int64_t*)n_sort, (const int64_t*)w.bstart, w.tkeys[0], tv[0], w.hist,
+                       div_up(L.k_cap, kScanTile));
   // 4. stable sort by tile
   uint32_t* tk[2] = {w.tkeys[0], w.tkeys[1]};
   int tcur = 0;
-  if ((e = radix_sort<uint32_t>(tk, tv, tcur, n_sort, L.k_cap, 0, tbits, w.hist, w.hist_part, nullptr, s)) != hipSuccess)
+  if ((e = radix_sort<uint32_t>(tk, tv, tcur, n_sort, L.k_cap, 0, tbits, w.hist, w.hist_part, nullptr, s,
+                                n_rec > 0 && L.k_cap > 0)) != hipSuccess)
     return e;
   // 5. ranges
   if ((e = fill<int32_t>(L.tile_range, 2 * v.n_tiles, 0, s)) != hipSuccess) return e;

@@ -211,24 +211,26 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
     stage_batch<CMAX>(a, c, b0, b1, sm.mv, sm.cn, sm.box, sm.dv, sm.f);
     __syncthreads();
     const int nb = (int)(b1 - b0);
+    // Branch-free over the lanes: a lane's decisions (box, skip, stop) become selects, and a
+    // lane that does not blend the Gaussian adds exact zeros.  Only wavefront-uniform branches
+    // remain: stop when every lane has stopped, skip a Gaussian that misses every live lane.
     for (int j = 0; j < nb; ++j) {
       if (__ballot(!done) == 0) break;
-      if (done) continue;
       const float4 bx = sm.box[j];
       const float bxa[4] = {bx.x, bx.y, bx.z, bx.w};
-      if (!TILE && !box_contains(LIDAR, c.px, c.py, bxa)) continue;
+      bool act = !done && (TILE || box_contains(LIDAR, c.px, c.py, bxa));
+      if (__ballot(act) == 0) continue;
       const float4 m = sm.mv[j], q = sm.cn[j];
       const float mva[4] = {m.x, m.y, m.z, m.w}, cna[4] = {q.x, q.y, q.z, q.w};
       PairEval e;
       eval_pair(LIDAR, c.px, c.py, c.t, mva, cna, e);
-      ++pairs;
-      if (e.alpha < kAlphaMin) continue;
+      pairs += act ? 1u : 0u;
+      act = act && e.alpha >= kAlphaMin;
       const float Tn = T * (1.f - e.alpha);
-      if (Tn < kTStop) {
-        done = true;
-        continue;
-      }
-      const float w = e.alpha * T;
+      const bool stop = act && Tn < kTStop;
+      done = done || stop;
+      act = act && !stop;
+      const float w = act ? e.alpha * T : 0.f;
       const float2 d = sm.dv[j];
       const float gv = LIDAR ? SPLAT_FMA(d.y, c.t, d.x) : d.x;
 #pragma unroll
@@ -240,12 +242,13 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
         F[4 * c4 + 3] = SPLAT_FMA(w, f.w, F[4 * c4 + 3]);
       }
       D = SPLAT_FMA(w, gv, D);
-      if (LIDAR && !med_set && Tn < 0.5f) {
-        med = gv;
-        med_set = true;
+      if (LIDAR) {
+        const bool hit = act && !med_set && Tn < 0.5f;
+        med = hit ? gv : med;
+        med_set = med_set || hit;
       }
-      T = Tn;
-      last = (int)(b0 + j - c.start) + 1;
+      T = act ? Tn : T;
+      last = act ? (int)(b0 + j - c.start) + 1 : last;
     }
   }
   __syncthreads();   // LDS is reused by the next item of a persistent workgroup
