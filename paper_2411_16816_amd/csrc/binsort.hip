@@ -135,9 +135,15 @@ __global__ __launch_bounds__(256) void k_scan_partials(T* __restrict__ part, int
 // Block b: exclusive scan of its tile, offset by the total of the blocks before it: with
 // `fused`, the sum of the block totals part[0..b) (read by the block itself; the last block
 // writes the grand total to part[nb]), otherwise part[b] as scanned by k_scan_partials.
-template <typename T, typename Load>
+// no per-element work besides the scan
+struct NoVisit {
+  template <typename T>
+  __device__ void operator()(int64_t, T, T) const {}
+};
+
+template <typename T, typename Load, typename Visit>
 __global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, T* __restrict__ part, int64_t nb, bool fused,
-                                                   T* __restrict__ out) {
+                                                   T* __restrict__ out, Visit vis) {
   __shared__ T tile[kScanTile];
   __shared__ T tmp[4];
   int64_t base = (int64_t)blockIdx.x * kScanTile;
@@ -169,17 +175,23 @@ __global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, T* __rest
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) tile[threadIdx.x * kScanItems + k] = pre + loc[k];
   __syncthreads();
+  const T end = before + total;   // exclusive prefix after the block
 #pragma unroll 4
   for (int r = 0; r < kScanItems; ++r) {
-    int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
-    if (i < n) out[i] = tile[r * kScanThreads + threadIdx.x];
+    const int li = r * kScanThreads + threadIdx.x;
+    const int64_t i = base + li;
+    if (i < n) {
+      const T p = tile[li];
+      out[i] = p;
+      vis(i, p, (li + 1 < kScanTile ? tile[li + 1] : end) - p);   // element i's value is the gap
+    }
   }
 }
 
 // exclusive scan of n elements into out[0..n) (out may alias the loaded array: each block
 // reads its tile before writing it); part[nb] receives the total
-template <typename T, typename Load>
-hipError_t device_scan(Load ld, int64_t n, T* out, T* part, hipStream_t s) {
+template <typename T, typename Load, typename Visit = NoVisit>
+hipError_t device_scan(Load ld, int64_t n, T* out, T* part, hipStream_t s, Visit vis = Visit()) {
   int64_t nb = div_up(n, kScanTile);
   if (nb == 0) {
     hipLaunchKernelGGL((k_fill<T>), dim3(1), dim3(64), 0, s, part, (int64_t)1, (T)0);
@@ -188,8 +200,8 @@ hipError_t device_scan(Load ld, int64_t n, T* out, T* part, hipStream_t s) {
   hipLaunchKernelGGL((k_scan_reduce<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, part);
   const bool fused = nb <= kScanFusedBlocks;
   if (!fused) hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(256), 0, s, part, nb);
-  hipLaunchKernelGGL((k_scan_down<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, part, nb, fused,
-                     out);
+  hipLaunchKernelGGL((k_scan_down<T, Load, Visit>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, part, nb,
+                     fused, out, vis);
   return hipGetLastError();
 }
 
@@ -514,19 +526,21 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const DevSensor* __restri
   if (tid < kRadixBins) hist[(int64_t)tid * nb + blockIdx.x] = s_cnt[tid];
 }
 
-// entry_base[rec] = emission position of the record's first entry (depth order i -> record)
-// Per visible record (depth order i): entry_base[record] = offs[i], and the first record of
-// every emit block whose first slot falls in the record's range [offs[i], offs[i + 1]).
-__global__ void k_entry_base(const uint32_t* __restrict__ order, const int64_t* __restrict__ offs,
-                             const int64_t* __restrict__ n_vis, const int64_t* __restrict__ total, int64_t n_rec,
-                             int64_t n_blocks, int64_t* __restrict__ entry_base, int64_t* __restrict__ bstart) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= *n_vis) return;
-  const int64_t a = offs[i];
-  const int64_t b = i + 1 < n_rec ? offs[i + 1] : *total;
-  entry_base[order[i]] = a;
-  for (int64_t kb = (a + kEmitTile - 1) / kEmitTile; kb < n_blocks && kb * kEmitTile < b; ++kb) bstart[kb] = i;
-}
+// Visitor of the offsets scan over the visible records in depth order: record i (value = its
+// tile count, exclusive prefix a) owns slots [a, a + count); writes entry_base[record] = a and
+// the first record of every emit block whose first slot falls in that range.
+struct EntryVisit {
+  const uint32_t* order;
+  const int64_t* n_vis;
+  int64_t* entry_base;
+  int64_t* bstart;
+  int64_t n_blocks;
+  __device__ void operator()(int64_t i, int64_t a, int64_t cnt) const {
+    if (i >= *n_vis) return;
+    entry_base[order[i]] = a;
+    for (int64_t kb = (a + kEmitTile - 1) / kEmitTile; kb < n_blocks && kb * kEmitTile < a + cnt; ++kb) bstart[kb] = i;
+  }
+};
 
 constexpr int kRangeItems = 8;   // sorted keys per thread of k_ranges
 
@@ -739,15 +753,12 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
     return e;
   const uint32_t* order = dvv[cur];
   // 2. slot ranges
-  if ((e = device_scan<int64_t>(LoadTilesByOrder{p.n_tiles, order, n_vis}, n_rec, w.offs, w.scan_part, s)) != hipSuccess)
+  const int64_t emit_blocks = div_up(L.k_cap, kEmitTile);
+  if ((e = device_scan<int64_t>(LoadTilesByOrder{p.n_tiles, order, n_vis}, n_rec, w.offs, w.scan_part, s,
+                                EntryVisit{order, n_vis, L.entry_base, w.bstart, emit_blocks})) != hipSuccess)
     return e;
   int64_t nb = div_up(n_rec, kScanTile);
   hipLaunchKernelGGL(k_finalize_count, dim3(1), dim3(1), 0, s, (const int64_t*)(w.scan_part + nb), L.k_cap, n_sort, st);
-  const int64_t emit_blocks = div_up(L.k_cap, kEmitTile);
-  if (n_rec > 0)
-    hipLaunchKernelGGL(k_entry_base, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, order,
-                       (const int64_t*)w.offs, (const int64_t*)n_vis, (const int64_t*)(w.scan_part + nb), n_rec,
-                       emit_blocks, L.entry_base, w.bstart);
   // 3. emit: the final tile-sort pass must land its values in lists->gauss
   const int tbits = bits_for(v.n_tiles);
   const int passes = (tbits + kRadixBits - 1) / kRadixBits;
