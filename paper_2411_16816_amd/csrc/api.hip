@@ -157,18 +157,23 @@ static int make_view(const SplatRig* r, int32_t first, int32_t count, int kind, 
   v.c_max = 0;
   v.has_lidar = false;
   v.lidar_ray0 = -1;
+  v.lidar_tile0 = 0;
   for (int i = 0; i < count; ++i) {
     const DevSensor& d = v.host[i];
     if (kind >= 0 && d.kind != kind) return SPLAT_ERR_INVALID_ARG;
     if (d.kind == kLidar && !v.has_lidar) {
       v.has_lidar = true;
       v.lidar_ray0 = v.n_rays;
+      v.lidar_tile0 = v.n_tiles;
     }
     v.n_tiles += d.n_tiles;
     v.n_rays += d.n_rays;
     v.c_max = d.n_ch > v.c_max ? d.n_ch : v.c_max;
   }
-  if (!v.has_lidar) v.lidar_ray0 = v.n_rays;
+  if (!v.has_lidar) {
+    v.lidar_ray0 = v.n_rays;
+    v.lidar_tile0 = v.n_tiles;
+  }
   v.lidar = (kind == kLidar);
   v.queue = (kind < 0);
   v.n_cu = r->n_cu;

@@ -372,6 +372,12 @@ static int bits_for(int64_t n_values) {   // bits needed for values 0..n_values-
   return b < 1 ? 1 : b;
 }
 
+// bits of a ray's cell code: the rest of the bin's last radix digit (none when the bin fills it)
+static int ray_cell_bits(int bin_bits) {
+  const int c = (kRadixBits - bin_bits % kRadixBits) % kRadixBits;
+  return bin_bits + c <= 32 ? c : 0;
+}
+
 // ------------------------------------------------------------------------------------------
 // binning kernels
 // ------------------------------------------------------------------------------------------
@@ -546,23 +552,25 @@ constexpr int kRangeItems = 8;   // sorted keys per thread of k_ranges
 
 // [start, end) of every key's run in a sorted key array; keys that do not occur keep the range
 // the caller filled in.  Thread t of a block handles elements base + j * 256 + t (coalesced).
-__global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap, int2* __restrict__ range) {
+// The run of key k is range[(k >> shift) + offset].
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap, int2* __restrict__ range,
+                         int shift, int64_t offset) {
   const int64_t base = (int64_t)blockIdx.x * blockDim.x * kRangeItems + threadIdx.x;
   const int64_t n = sort_count(n_ptr, n_cap);
   uint32_t cur[kRangeItems], prev[kRangeItems], next[kRangeItems];
 #pragma unroll
   for (int j = 0; j < kRangeItems; ++j) {
     const int64_t i = base + (int64_t)j * blockDim.x;
-    cur[j] = i < n ? keys[i] : 0xFFFFFFFFu;
-    prev[j] = (i > 0 && i <= n) ? keys[i - 1] : 0xFFFFFFFFu;
-    next[j] = i + 1 < n ? keys[i + 1] : 0xFFFFFFFFu;
+    cur[j] = i < n ? keys[i] >> shift : 0xFFFFFFFFu;
+    prev[j] = (i > 0 && i <= n) ? keys[i - 1] >> shift : 0xFFFFFFFFu;
+    next[j] = i + 1 < n ? keys[i + 1] >> shift : 0xFFFFFFFFu;
   }
 #pragma unroll
   for (int j = 0; j < kRangeItems; ++j) {
     const int64_t i = base + (int64_t)j * blockDim.x;
     if (i >= n) break;
-    if (prev[j] != cur[j]) range[cur[j]].x = (int)i;
-    if (next[j] != cur[j]) range[cur[j]].y = (int)(i + 1);
+    if (prev[j] != cur[j]) range[cur[j] + offset].x = (int)i;
+    if (next[j] != cur[j]) range[cur[j] + offset].y = (int)(i + 1);
   }
 }
 
@@ -577,9 +585,12 @@ __device__ __forceinline__ int sensor_of_ray(const DevSensor* sens, int count, i
   return lo;
 }
 
-// lidar rays [r0, r0 + n) of the call -> (tile, ray id) pairs at [0, n)
+// lidar rays [r0, r0 + n) of the call -> (key, ray id) pairs at [0, n); key = ((bin - t0) <<
+// cell_bits) | cell, bin = the ray's tile (n_tiles: outside every tile), t0 = the call's first
+// lidar tile, cell = ray_cell_code inside the tile (0 outside)
 __global__ void k_ray_keys(const DevSensor* __restrict__ sens, int count, int64_t r0, int64_t n, int64_t n_tiles,
-                           uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, SplatStatus* st) {
+                           int64_t t0, int cell_bits, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                           SplatStatus* st) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const int64_t r = r0 + q;
@@ -588,16 +599,18 @@ __global__ void k_ray_keys(const DevSensor* __restrict__ sens, int count, int64_
   int64_t j = r - (S.ray_base - sens[0].ray_base);
   float az = S.ray_az[j], el = S.ray_el[j], t = S.ray_t[j];
   bool ok = (az >= 0.f) && (az < kTwoPi) && (el >= S.bounds[0]) && (el < S.bounds[S.m_el]) && finite_f(t);
-  uint32_t tile = (uint32_t)n_tiles;
+  uint32_t tile = (uint32_t)n_tiles, cell = 0;
   if (ok) {
+    const float u = div_rn(az, S.az_w);
     int a = floor_div_clamped(az, S.az_w) % S.m_az;
     int e = count_le(S, el) - 1;
     tile = (uint32_t)(local_tile_base(sens, s) + (int64_t)e * S.m_az + a);
+    cell = ray_cell_code(u, el, S.bounds[e], S.bounds[e + 1], cell_bits);
   } else if (st) {
     atomicAdd(&st->n_rays_invalid, 1u);
   }
   if (ok && st && fabsf(t) > 0.5f * S.t_rs * (1.0f + 1e-6f) + 1e-9f) atomicAdd(&st->n_rays_time, 1u);
-  keys[q] = tile;
+  keys[q] = ((tile - (uint32_t)t0) << cell_bits) | cell;
   vals[q] = (uint32_t)r;
 }
 
@@ -780,7 +793,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   if ((e = fill<int32_t>(L.tile_range, 2 * v.n_tiles, 0, s)) != hipSuccess) return e;
   if (L.k_cap > 0)
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(L.k_cap, 256 * kRangeItems)), dim3(256), 0, s, (const uint32_t*)tk[tcur],
-                       (const int64_t*)n_sort, L.k_cap, (int2*)L.tile_range);
+                       (const int64_t*)n_sort, L.k_cap, (int2*)L.tile_range, 0, (int64_t)0);
   // 6. lidar rays -> tiles; work items (lidar chunks, and camera tiles in the batched form)
   if (v.has_lidar || v.queue) {
     const int64_t bins = v.n_tiles + 1;
@@ -788,16 +801,21 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
     const int64_t nr = v.n_rays - r0;
     if ((e = fill<int32_t>(L.ray_range, 2 * bins, 0, s)) != hipSuccess) return e;
     if (nr > 0) {
+      // rays grouped by tile, and inside a tile in Z-order of their cells (compact work items);
+      // the cell code fills the unused bits of the bin's last radix digit, so it adds no pass
+      const int64_t t0 = v.lidar_tile0;
+      const int bin_bits = bits_for(bins - t0);
+      const int cell_bits = ray_cell_bits(bin_bits);
       hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)div_up(nr, 256)), dim3(256), 0, s, v.sens, v.count, r0, nr,
-                         v.n_tiles, w.rkeys[0], w.rvals[0], st);
+                         v.n_tiles, t0, cell_bits, w.rkeys[0], w.rvals[0], st);
       uint32_t* rk[2] = {w.rkeys[0], w.rkeys[1]};
       uint32_t* rv[2] = {w.rvals[0], w.rvals[1]};
       int rcur = 0;
-      if ((e = radix_sort<uint32_t>(rk, rv, rcur, nullptr, nr, 0, bits_for(bins), w.hist, w.hist_part,
+      if ((e = radix_sort<uint32_t>(rk, rv, rcur, nullptr, nr, 0, bin_bits + cell_bits, w.hist, w.hist_part,
                                     (uint32_t*)L.ray_order, s)) != hipSuccess)
         return e;
       hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(nr, 256 * kRangeItems)), dim3(256), 0, s, (const uint32_t*)rk[rcur],
-                         (const int64_t*)nullptr, nr, (int2*)L.ray_range);
+                         (const int64_t*)nullptr, nr, (int2*)L.ray_range, cell_bits, t0);
     }
     hipLaunchKernelGGL(k_work_count, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, v.sens, v.count,
                        (const int2*)L.ray_range, v.n_tiles, w.wcount);

@@ -49,6 +49,7 @@ struct CallView {
   bool queue;              // batched form: any mix of sensors, persistent queue rasterisers
   bool has_lidar;          // at least one lidar in the call
   int64_t lidar_ray0;      // local id of the first lidar ray (cameras precede lidars in a rig)
+  int64_t lidar_tile0;     // local id of the first lidar tile
   int c_max;               // max n_channels over the call
   int n_cu;                // compute units of the device (persistent grid)
 };

@@ -59,6 +59,25 @@ HD float div_rn(float a, float b) {
 #endif
 }
 
+// Z-order cell of a lidar ray inside its tile, on `cell_bits` bits: the tile is cut into
+// 2^ab x 2^eb cells (ab = ceil(cell_bits / 2) azimuth bits, eb = floor(cell_bits / 2) elevation
+// bits; azimuth from the fractional part of az / w, elevation from (el - b_e) / (b_{e+1} - b_e),
+// float32 with correctly rounded divisions) and the cell's coordinates are interleaved: azimuth
+// bit i at 2i, elevation bit i at 2i + 1 (the last azimuth bit on top when ab > eb).  Rays in
+// consecutive codes are close together.
+HD uint32_t ray_cell_code(float az_over_w, float el, float b_lo, float b_hi, int cell_bits) {
+  const int ab = (cell_bits + 1) >> 1, eb = cell_bits >> 1;
+  const float fa = az_over_w - floorf(az_over_w);
+  const float fe = div_rn(el - b_lo, b_hi - b_lo);
+  int qa = (int)(fa * (float)(1 << ab)), qe = (int)(fe * (float)(1 << eb));
+  qa = qa < 0 ? 0 : (qa > (1 << ab) - 1 ? (1 << ab) - 1 : qa);
+  qe = qe < 0 ? 0 : (qe > (1 << eb) - 1 ? (1 << eb) - 1 : qe);
+  uint32_t z = 0;
+  for (int i = 0; i < ab; ++i) z |= (((uint32_t)qa >> i) & 1u) << (2 * i);
+  for (int i = 0; i < eb; ++i) z |= (((uint32_t)qe >> i) & 1u) << (2 * i + 1);
+  return z;
+}
+
 HD int32_t floor_div_clamped(float x, float w) {
   float q = floorf(div_rn(x, w));
   const float lim = 16777216.0f;

@@ -133,6 +133,31 @@ def depth_sort_key(bits):
     return np.where(e > 31, np.uint64((1 << 40) - 1), key)
 
 
+def ray_cell_codes_f32(lid, n_bins):
+    """The library's documented order of rays inside a lidar tile (splat_common.hpp,
+    ray_cell_code; binsort.hip, ray_cell_bits): the rest of the bin's last 8-bit radix digit holds
+    a Z-order cell code of the ray inside its tile, computed in float32."""
+    F = np.float32
+    bin_bits = max(1, int(np.ceil(np.log2(n_bins))))
+    c = (8 - bin_bits % 8) % 8
+    ab, eb = (c + 1) // 2, c // 2
+    az = np.asarray(lid.ray_az, F)
+    el = np.asarray(lid.ray_el, F)
+    u = (az / tl.lidar_tile_width_f32(lid)).astype(F)
+    fa = (u - np.floor(u)).astype(F)
+    b = np.asarray(lid.elev_bounds, F)
+    e = np.clip(np.searchsorted(b, el, side="right") - 1, 0, b.shape[0] - 2)
+    fe = ((el - b[e]).astype(F) / (b[e + 1] - b[e]).astype(F)).astype(F)
+    qa = np.clip(np.trunc((fa * F(1 << ab)).astype(F)).astype(np.int64), 0, (1 << ab) - 1)
+    qe = np.clip(np.trunc((fe * F(1 << eb)).astype(F)).astype(np.int64), 0, (1 << eb) - 1)
+    z = np.zeros_like(qa)
+    for i in range(ab):
+        z |= ((qa >> i) & 1) << (2 * i)
+    for i in range(eb):
+        z |= ((qe >> i) & 1) << (2 * i + 1)
+    return z
+
+
 def _expected_lists(sp, sensor, g_n):
     nt = sp.ntiles.cpu().numpy()[:g_n]
     keep = nt > 0
@@ -171,9 +196,12 @@ def test_bin_sort_bit_exact(kind):
         tiles = np.where(v, e * sensor.n_az_tiles + a, sensor.n_az_tiles * sensor.n_el_tiles)
         order = sp.ray_order.cpu().numpy()[:sensor.n_rays]
         rr = sp.ray_range.cpu().numpy()
+        code = ray_cell_codes_f32(sensor, sensor.n_az_tiles * sensor.n_el_tiles + 1)
         for t in range(rr.shape[0]):
             ids = order[rr[t, 0]:rr[t, 1]]
-            np.testing.assert_array_equal(ids, np.nonzero(tiles == t)[0])
+            want_ids = np.nonzero(tiles == t)[0]
+            c = np.where(t < sensor.n_az_tiles * sensor.n_el_tiles, code[want_ids], 0)
+            np.testing.assert_array_equal(ids, want_ids[np.lexsort((want_ids, c))])
         nw = int(sp.n_work.cpu()[0])
         work = sp.work.cpu().numpy()[:nw]
         counts = rr[:, 1] - rr[:, 0]
