@@ -198,8 +198,10 @@ typedef struct SplatGrads {
 const char* splat_status_string(int code);
 int splat_version(void);
 
-/* Host-only validation of one sensor description (no device call): SPLAT_OK or
- * SPLAT_ERR_INVALID_ARG.  splat_rig_set applies the same checks. */
+/* Host-only validation of one sensor description (no device call): SPLAT_OK,
+ * SPLAT_ERR_INVALID_ARG, or SPLAT_ERR_UNSUPPORTED for a valid sensor beyond the kernels'
+ * limits: more than 65535 tiles across a row (camera tiles_x, lidar n_az_tiles) or 2^24 tiles
+ * or more in total.  splat_rig_set applies the same checks and returns the same codes. */
 int splat_check_camera(const SplatCamera* cam);
 int splat_check_lidar(const SplatLidar* lidar);
 

@@ -103,9 +103,9 @@ int splat_rig_set(SplatRig* r, const SplatCamera* cams, const SplatLidar* lidars
   const int n = r->n_cam + r->n_lid;
   std::vector<DevSensor> tab(n);
   for (int i = 0; i < r->n_cam; ++i)
-    if (build_camera(cams[i], tab[i]) != SPLAT_OK) return SPLAT_ERR_INVALID_ARG;
+    if (int rc = build_camera(cams[i], tab[i])) return rc;
   for (int i = 0; i < r->n_lid; ++i)
-    if (build_lidar(lidars[i], tab[r->n_cam + i]) != SPLAT_OK) return SPLAT_ERR_INVALID_ARG;
+    if (int rc = build_lidar(lidars[i], tab[r->n_cam + i])) return rc;
   SplatRigLayout L;
   memset(&L, 0, sizeof(L));
   L.n_sensors = n;

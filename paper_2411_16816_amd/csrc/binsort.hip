@@ -2,8 +2,8 @@
 // "Projection, tiling, and sorting"; Sec. 3.3 "Tiling and sorting"; App. A).
 //
 // Pipeline of one call (all on the stream, no host synchronisation):
-//   1. records are stably sorted by depth (float32 bits; culled records get the largest key),
-//      so equal depths keep record (= Gaussian id) order;
+//   1. the visible records are compacted and stably sorted by a 40-bit key of their float64
+//      depth, so equal keys keep record (= Gaussian id) order;
 //   2. an exclusive scan of n_tiles in that order gives every record its slot range;
 //   3. every record emits (local tile id, Gaussian id) pairs into its slots;
 //   4. a stable LSD radix sort on the tile id groups the pairs by tile; inside a tile they stay in
@@ -86,12 +86,6 @@ struct LoadU32 {
   const uint32_t* p;
   __device__ uint32_t operator()(int64_t i) const { return p[i]; }
 };
-struct LoadTilesByOrder {   // n_tiles of the i-th visible record in depth order
-  const int32_t* n_tiles;
-  const uint32_t* order;
-  const int64_t* n_vis;
-  __device__ int64_t operator()(int64_t i) const { return i < *n_vis ? (int64_t)n_tiles[order[i]] : 0; }
-};
 struct LoadI64 {
   const int64_t* p;
   __device__ int64_t operator()(int64_t i) const { return p[i]; }
@@ -100,12 +94,14 @@ struct LoadI64 {
 template <typename T, typename Load>
 __global__ __launch_bounds__(256) void k_scan_reduce(Load ld, int64_t n, T* __restrict__ part) {
   __shared__ T tmp[4];
-  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int64_t base = (int64_t)blockIdx.x * kScanTile;   // < n: the grid has div_up(n, kScanTile) blocks
   T acc = 0;
+  // indices clamped into [0, n): every load is issued unconditionally, back to back
 #pragma unroll 4
   for (int r = 0; r < kScanItems; ++r) {
-    int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
-    if (i < n) acc += ld(i);
+    const int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
+    const T x = ld(i < n ? i : n - 1);
+    acc += i < n ? x : (T)0;
   }
   T total;
   block_exclusive_scan<T>(acc, tmp, total);
@@ -144,8 +140,11 @@ struct NoVisit {
 template <typename T, typename Load, typename Visit>
 __global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, T* __restrict__ part, int64_t nb, bool fused,
                                                    T* __restrict__ out, Visit vis) {
-  __shared__ T tile[kScanTile];
+  // element li of the tile lives at pad(li) = li + li / 16: a thread's 16 consecutive
+  // elements then start 17 apart, which spreads the per-thread pass over the LDS banks
+  __shared__ T tile[kScanTile + kScanTile / kScanItems];
   __shared__ T tmp[4];
+  auto pad = [](int li) { return li + (li >> 4); };
   int64_t base = (int64_t)blockIdx.x * kScanTile;
   T before;
   if (fused) {
@@ -157,8 +156,9 @@ __global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, T* __rest
   }
 #pragma unroll 4
   for (int r = 0; r < kScanItems; ++r) {
-    int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
-    tile[r * kScanThreads + threadIdx.x] = i < n ? ld(i) : (T)0;
+    const int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
+    const T x = ld(i < n ? i : n - 1);
+    tile[pad(r * kScanThreads + threadIdx.x)] = i < n ? x : (T)0;
   }
   __syncthreads();
   T loc[kScanItems];
@@ -166,14 +166,14 @@ __global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, T* __rest
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     loc[k] = acc;
-    acc += tile[threadIdx.x * kScanItems + k];
+    acc += tile[pad(threadIdx.x * kScanItems + k)];
   }
   T total;
   T pre = block_exclusive_scan<T>(acc, tmp, total) + before;
   if (fused && blockIdx.x == nb - 1 && threadIdx.x == 0) part[nb] = before + total;
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) tile[threadIdx.x * kScanItems + k] = pre + loc[k];
+  for (int k = 0; k < kScanItems; ++k) tile[pad(threadIdx.x * kScanItems + k)] = pre + loc[k];
   __syncthreads();
   const T end = before + total;   // exclusive prefix after the block
 #pragma unroll 4
@@ -181,9 +181,9 @@ __global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, T* __rest
     const int li = r * kScanThreads + threadIdx.x;
     const int64_t i = base + li;
     if (i < n) {
-      const T p = tile[li];
+      const T p = tile[pad(li)];
       out[i] = p;
-      vis(i, p, (li + 1 < kScanTile ? tile[li + 1] : end) - p);   // element i's value is the gap
+      vis(i, p, (li + 1 < kScanTile ? tile[pad(li + 1)] : end) - p);   // element i's value is the gap
     }
   }
 }
@@ -244,7 +244,8 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
       const int64_t i = base + (int64_t)r * kScanThreads + tid;
-      d[r] = i < n ? ((uint32_t)(keys[i] >> shift) & mask) : 0xFFFFFFFFu;
+      const uint32_t x = (uint32_t)(keys[i < n ? i : n - 1] >> shift) & mask;   // unconditional load
+      d[r] = i < n ? x : 0xFFFFFFFFu;
     }
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r)
@@ -287,8 +288,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
     const int li = wid * kPerWave + r * 64 + lane;
-    key[r] = li < cnt ? kin[base + li] : (K)0;
-    val[r] = li < cnt ? vin[base + li] : 0u;
+    const int lc = li < cnt ? li : cnt - 1;   // unconditional loads; lanes past cnt are invalid below
+    key[r] = kin[base + lc];
+    val[r] = vin[base + lc];
   }
   __syncthreads();
   uint32_t* run = wc[wid];
@@ -403,15 +405,31 @@ __device__ __forceinline__ uint64_t depth_sort_key(unsigned long long bits) {
   return ((uint64_t)e << 35) | ((bits & 0xFFFFFFFFFFFFFull) >> 17);
 }
 
+// The record's tile count rides in the key's top 24 bits (the sort looks only at the low
+// kDepthKeyBits), so that the scan of the counts in depth order reads the sorted keys
+// contiguously instead of gathering by record.  A sensor has fewer than 2^24 tiles.
 __global__ void k_compact_visible(const int32_t* __restrict__ n_tiles, const unsigned long long* __restrict__ dkey,
                                   const int64_t* __restrict__ pos, int64_t n_rec, uint64_t* __restrict__ keys,
                                   uint32_t* __restrict__ vals) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_rec || n_tiles[i] <= 0) return;
+  if (i >= n_rec) return;
+  const int32_t nt = n_tiles[i];
+  if (nt <= 0) return;
   int64_t p = pos[i];
-  keys[p] = depth_sort_key(dkey[i]);
+  keys[p] = ((uint64_t)nt << kDepthKeyBits) | depth_sort_key(dkey[i]);
   vals[p] = (uint32_t)i;
 }
+
+// tile count of the i-th visible record in depth order, from its sorted packed key (entries
+// past the visible count hold stale keys and count zero)
+struct LoadPackedTiles {
+  const uint64_t* keys;
+  const int64_t* n_vis;
+  __device__ int64_t operator()(int64_t i) const {
+    const uint64_t k = keys[i];
+    return i < *n_vis ? (int64_t)(k >> kDepthKeyBits) : 0;
+  }
+};
 
 __global__ void k_finalize_count(const int64_t* __restrict__ total, int64_t k_cap, int64_t* __restrict__ n_sort,
                                  SplatStatus* st) {
@@ -427,6 +445,8 @@ __global__ void k_finalize_count(const int64_t* __restrict__ total, int64_t k_ca
 constexpr int kEmitTile = kScanTile;   // output slots per workgroup of the emit kernel = one radix tile
 constexpr int kEmitThreads = 512;
 constexpr int kEmitPer = kEmitTile / kEmitThreads;   // consecutive slots per thread
+constexpr int kEmitRecs = kEmitTile + 1;             // records that can meet one workgroup's slots
+static_assert(kEmitPer == 8, "k_emit stores a thread's slots as two 16-byte vectors");
 
 // q = floor(a / b) for 0 <= a < 2^24, b >= 1, from a float reciprocal with an exact correction.
 __device__ __forceinline__ int div_small(int a, int b) {
@@ -437,14 +457,18 @@ __device__ __forceinline__ int div_small(int a, int b) {
 }
 
 // Thread t emits the kEmitPer consecutive slots k0 + t kEmitPer + j.  Slot k belongs to the
-// visible record r (depth order) with offs[r] <= k < offs[r + 1]: one binary search over the
-// offsets of the records overlapping the workgroup's slots (staged in LDS relative to k0,
-// starting at the block's first record bstart) finds the first slot's record, and the walk
-// advances at most one record per slot (every visible record has >= 1 slot).  The slot's tile
-// is the (k - offs[r])-th tile of the record's rectangle.  Results are staged in LDS and written
-// out coalesced.  A workgroup's slots are exactly one tile of the radix sort that follows, so it
-// also writes that tile's counts of the low key digit (the first pass's histogram,
-// hist[d * nb + block], zero for blocks past the last slot).
+// visible record r (depth order) with offs[r] <= k < offs[r + 1]; the records that can own a
+// slot of the workgroup are bstart[b] .. bstart[b + 1] (at most kEmitRecs).  They are staged
+// first, all in parallel: every record's first slot relative to k0 and a descriptor
+//   {Gaussian id, key of the rectangle's first tile, width | wrap column << 16, row stride},
+// where the key of entry (row, col) of the rectangle is first + row * stride + col, minus the
+// stride once col reaches the wrap column (lidar azimuth wrap; cameras never wrap).  A thread
+// then finds its first slot's record by binary search and walks its slots through LDS only
+// (every visible record has >= 1 slot, so the walk advances at most one record per slot).
+// Keys and ids are stored straight from registers (each thread's slots are contiguous).  A
+// workgroup's slots are exactly one tile of the radix sort that follows, so it also writes that
+// tile's counts of the low key digit (the first pass's histogram, hist[d * nb + block], zero
+// for blocks past the last slot).
 __global__ __launch_bounds__(kEmitThreads) void k_emit(const DevSensor* __restrict__ sens, int count, int64_t N,
                                                        const int4* __restrict__ rect,
                                                        const uint32_t* __restrict__ order,
@@ -454,9 +478,10 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const DevSensor* __restri
                                                        const int64_t* __restrict__ bstart, uint32_t* __restrict__ keys,
                                                        uint32_t* __restrict__ vals, uint32_t* __restrict__ hist,
                                                        int64_t nb) {
-  __shared__ int s_off[kEmitTile + 2];   // offs[r0 + i] - k0, capped at kEmitTile + 1
-  __shared__ uint32_t s_key[kEmitTile], s_val[kEmitTile];
+  __shared__ uint4 s_desc[kEmitRecs];
+  __shared__ int16_t s_off[kEmitRecs + 1];   // first slot - k0, clamped to [0, kEmitTile + 1]
   __shared__ uint32_t s_cnt[kRadixBins];
+  __shared__ int s_off0;                     // first slot - k0 of record 0 (<= 0), unclamped
   const int tid = threadIdx.x;
   const int64_t K = *n_slots;
   const int64_t k0 = (int64_t)blockIdx.x * kEmitTile;
@@ -465,70 +490,100 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const DevSensor* __restri
     if (tid < kRadixBins) hist[(int64_t)tid * nb + blockIdx.x] = 0;
     return;
   }
-  const int64_t nv = *n_vis;
-  const int64_t r0 = bstart[blockIdx.x];   // last record with offs[r] <= k0
-  // stage offsets in rounds of 256 records until they pass the block's last slot (a block
-  // usually overlaps far fewer than kEmitTile records)
-  int n_loaded = 0;
-  for (int i0 = 0; i0 < kEmitTile + 2; i0 += kEmitThreads) {
-    const int i = i0 + tid;
-    int v = kEmitTile + 1;
-    if (i < kEmitTile + 2) {
-      const int64_t r = r0 + i;
-      // a record starting before k0 keeps its exact (negative) offset: one record's slots fit int32
-      const int64_t rel = r < nv ? offs[r] - k0 : (int64_t)kEmitTile + 1;
-      v = (int)(rel > kEmitTile + 1 ? kEmitTile + 1 : rel);
-      s_off[i] = v;
+  const int64_t r0 = bstart[blockIdx.x];
+  const int64_t used = (K + kEmitTile - 1) / kEmitTile;   // workgroups with slots; bstart is set for each
+  const int64_t r_last = blockIdx.x + 1 < used ? bstart[blockIdx.x + 1] : *n_vis - 1;
+  const int nrec = (int)(r_last - r0 + 1 < kEmitRecs ? r_last - r0 + 1 : kEmitRecs);
+  // stage the records, three rounds per iteration with clamped (always valid) indices so that
+  // their loads are issued together
+  constexpr int kU = 3;
+  for (int i0 = 0; i0 < nrec; i0 += kU * kEmitThreads) {
+    int64_t rel[kU];
+    uint32_t rec[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * kEmitThreads + tid;
+      const int64_t r = r0 + (i < nrec ? i : nrec - 1);
+      rel[u] = offs[r] - k0;
+      rec[u] = order[r];
     }
-    n_loaded = i0 + kEmitThreads;
-    if (__syncthreads_count(v <= kEmitTile) < kEmitThreads) break;   // uniform: a record starts past the block
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * kEmitThreads + tid;
+      int s = 0;
+      if (count > 1) {
+        s = (int)((float)rec[u] * __builtin_amdgcn_rcpf((float)N));
+        s -= ((int64_t)s * N > (int64_t)rec[u]) ? 1 : 0;
+        s += ((int64_t)(s + 1) * N <= (int64_t)rec[u]) ? 1 : 0;
+      }
+      const DevSensor& S = sens[s];
+      const int4 rc = rect[rec[u]];
+      const bool cam = S.kind == kCamera;
+      const uint32_t stride = (uint32_t)(cam ? S.tiles_x : S.m_az);
+      const uint32_t first = (uint32_t)(S.tile_base - sens[0].tile_base) + (uint32_t)rc.y * stride + (uint32_t)rc.x;
+      const uint32_t wrap = (uint32_t)(cam ? rc.z : S.m_az - rc.x);
+      if (i < nrec) {
+        s_desc[i] = make_uint4(rec[u] - (uint32_t)s * (uint32_t)N, first, (uint32_t)rc.z | (wrap << 16), stride);
+        const int64_t v = rel[u] < 0 ? 0 : (rel[u] > kEmitTile + 1 ? kEmitTile + 1 : rel[u]);
+        s_off[i] = (int16_t)v;
+        if (i == 0) s_off0 = (int)rel[u];
+      }
+    }
   }
-  if (n_loaded > kEmitTile + 2) n_loaded = kEmitTile + 2;
+  if (tid == 0) s_off[nrec] = (int16_t)(kEmitTile + 1);
+  __syncthreads();
   const int nk = (int)((K - k0) < kEmitTile ? (K - k0) : kEmitTile);
   const int j0 = tid * kEmitPer;
+  uint32_t kk[kEmitPer], gg[kEmitPer];
   if (j0 < nk) {
-    int lo = 0, hi = n_loaded - 2;   // last i with s_off[i] <= j0 (s_off[n_loaded - 1] > j0)
+    int lo = 0, hi = nrec - 1;   // last record with s_off[lo] <= j0 (s_off[0] = 0)
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (s_off[mid] <= j0) lo = mid; else hi = mid - 1;
     }
-    int cur = -1;
-    uint32_t g = 0;
-    int4 rc = make_int4(0, 0, 1, 1);
-    int64_t tbase = 0;
-    const DevSensor* S = sens;
+    uint4 d = s_desc[lo];
+    int nxt = s_off[lo + 1];
+    int w = (int)(d.z & 0xFFFFu), wrap = (int)(d.z >> 16);
+    const int jj = j0 - (lo == 0 ? s_off0 : (int)s_off[lo]);
+    int row = div_small(jj, w), col = jj - row * w;
 #pragma unroll
     for (int j = 0; j < kEmitPer; ++j) {
       const int q = j0 + j;
-      if (q >= nk) break;
-      if (s_off[lo + 1] <= q) ++lo;
-      if (lo != cur) {
-        cur = lo;
-        const uint32_t rec = order[r0 + lo];
-        int s = 0;
-        if (count > 1) {
-          s = (int)((float)rec * __builtin_amdgcn_rcpf((float)N));
-          s -= ((int64_t)s * N > (int64_t)rec) ? 1 : 0;
-          s += ((int64_t)(s + 1) * N <= (int64_t)rec) ? 1 : 0;
-        }
-        g = rec - (uint32_t)s * (uint32_t)N;
-        rc = rect[rec];
-        S = sens + s;
-        tbase = local_tile_base(sens, s);
+      if (q < nk && q >= nxt) {   // the next record starts here (it is staged: its first slot < nk)
+        ++lo;
+        d = s_desc[lo];
+        nxt = s_off[lo + 1];
+        w = (int)(d.z & 0xFFFFu);
+        wrap = (int)(d.z >> 16);
+        row = 0;
+        col = 0;
       }
-      const int jj = q - s_off[lo];
-      const int row = div_small(jj, rc.z);
-      const uint32_t key = (uint32_t)(tbase + rect_tile_rc(*S, rc, row, jj - row * rc.z));
-      s_key[q] = key;
-      s_val[q] = g;
-      atomicAdd(&s_cnt[key & (kRadixBins - 1)], 1u);
+      const uint32_t key = d.y + (uint32_t)row * d.w + (uint32_t)col - (col >= wrap ? d.w : 0u);
+      kk[j] = key;
+      gg[j] = d.x;
+      if (q < nk) atomicAdd(&s_cnt[key & (kRadixBins - 1)], 1u);
+      if (++col == w) {
+        col = 0;
+        ++row;
+      }
+    }
+    uint32_t* kp = keys + k0 + j0;
+    uint32_t* vp = vals + k0 + j0;
+    if (j0 + kEmitPer <= nk && ((((uintptr_t)kp) | ((uintptr_t)vp)) & 15) == 0) {
+      reinterpret_cast<uint4*>(kp)[0] = make_uint4(kk[0], kk[1], kk[2], kk[3]);
+      reinterpret_cast<uint4*>(kp)[1] = make_uint4(kk[4], kk[5], kk[6], kk[7]);
+      reinterpret_cast<uint4*>(vp)[0] = make_uint4(gg[0], gg[1], gg[2], gg[3]);
+      reinterpret_cast<uint4*>(vp)[1] = make_uint4(gg[4], gg[5], gg[6], gg[7]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kEmitPer; ++j)
+        if (j0 + j < nk) {
+          kp[j] = kk[j];
+          vp[j] = gg[j];
+        }
     }
   }
   __syncthreads();
-  for (int q = tid; q < nk; q += kEmitThreads) {
-    keys[k0 + q] = s_key[q];
-    vals[k0 + q] = s_val[q];
-  }
   if (tid < kRadixBins) hist[(int64_t)tid * nb + blockIdx.x] = s_cnt[tid];
 }
 
@@ -557,13 +612,16 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ptr
                          int shift, int64_t offset) {
   const int64_t base = (int64_t)blockIdx.x * blockDim.x * kRangeItems + threadIdx.x;
   const int64_t n = sort_count(n_ptr, n_cap);
+  if ((int64_t)blockIdx.x * blockDim.x * kRangeItems >= n) return;   // uniform; n >= 1 below
+  auto at = [&](int64_t i) { return keys[i < 0 ? 0 : (i < n ? i : n - 1)] >> shift; };   // clamped: no branch per load
   uint32_t cur[kRangeItems], prev[kRangeItems], next[kRangeItems];
 #pragma unroll
   for (int j = 0; j < kRangeItems; ++j) {
     const int64_t i = base + (int64_t)j * blockDim.x;
-    cur[j] = i < n ? keys[i] >> shift : 0xFFFFFFFFu;
-    prev[j] = (i > 0 && i <= n) ? keys[i - 1] >> shift : 0xFFFFFFFFu;
-    next[j] = i + 1 < n ? keys[i + 1] >> shift : 0xFFFFFFFFu;
+    const uint32_t c = at(i), p = at(i - 1), x = at(i + 1);
+    cur[j] = i < n ? c : 0xFFFFFFFFu;
+    prev[j] = (i > 0 && i <= n) ? p : 0xFFFFFFFFu;
+    next[j] = i + 1 < n ? x : 0xFFFFFFFFu;
   }
 #pragma unroll
   for (int j = 0; j < kRangeItems; ++j) {
@@ -767,7 +825,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   const uint32_t* order = dvv[cur];
   // 2. slot ranges
   const int64_t emit_blocks = div_up(L.k_cap, kEmitTile);
-  if ((e = device_scan<int64_t>(LoadTilesByOrder{p.n_tiles, order, n_vis}, n_rec, w.offs, w.scan_part, s,
+  if ((e = device_scan<int64_t>(LoadPackedTiles{dk[cur], n_vis}, n_rec, w.offs, w.scan_part, s,
                                 EntryVisit{order, n_vis, L.entry_base, w.bstart, emit_blocks})) != hipSuccess)
     return e;
   int64_t nb = div_up(n_rec, kScanTile);

@@ -15,7 +15,12 @@ inline bool finite_all(const float* v, int n) {
   return true;
 }
 
-// returns SPLAT_OK or SPLAT_ERR_INVALID_ARG
+// Limits of the binning kernels: a rectangle's width and wrap column are packed into 16 bits
+// each, and a record's tile count into the top 24 bits of its 64-bit depth key.
+constexpr int64_t kMaxRowTiles = 65535;
+constexpr int64_t kMaxSensorTiles = ((int64_t)1 << 24) - 1;
+
+// returns SPLAT_OK, SPLAT_ERR_INVALID_ARG, or SPLAT_ERR_UNSUPPORTED (beyond the limits above)
 inline int build_camera(const SplatCamera& c, DevSensor& d) {
   memset(&d, 0, sizeof(d));
   if (c.width <= 0 || c.height <= 0 || c.tile_w <= 0 || c.tile_h <= 0) return SPLAT_ERR_INVALID_ARG;
@@ -45,8 +50,10 @@ inline int build_camera(const SplatCamera& c, DevSensor& d) {
   }
   d.width = c.width; d.height = c.height;
   d.tile_w = c.tile_w; d.tile_h = c.tile_h;
-  d.tiles_x = (c.width + c.tile_w - 1) / c.tile_w;
-  d.tiles_y = (c.height + c.tile_h - 1) / c.tile_h;
+  const int64_t tx = ((int64_t)c.width + c.tile_w - 1) / c.tile_w, ty = ((int64_t)c.height + c.tile_h - 1) / c.tile_h;
+  if (tx > kMaxRowTiles || tx * ty > kMaxSensorTiles) return SPLAT_ERR_UNSUPPORTED;
+  d.tiles_x = (int32_t)tx;
+  d.tiles_y = (int32_t)ty;
   d.n_tiles = d.tiles_x * d.tiles_y;
   d.n_rays = (int64_t)c.width * c.height;
   return SPLAT_OK;
@@ -66,6 +73,7 @@ inline int build_lidar(const SplatLidar& l, DevSensor& d) {
     if (!isfinite(l.elev_bounds[k])) return SPLAT_ERR_INVALID_ARG;
     if (k > 0 && !(l.elev_bounds[k] > l.elev_bounds[k - 1])) return SPLAT_ERR_INVALID_ARG;
   }
+  if (l.n_az_tiles > kMaxRowTiles || (int64_t)l.n_az_tiles * l.n_el_tiles > kMaxSensorTiles) return SPLAT_ERR_UNSUPPORTED;
   float az_w = (float)l.tile_az * l.az_res;
   // the azimuth tiles must cover a full turn: M_phi * N_phi * res >= 2 pi (up to rounding)
   if ((double)l.n_az_tiles * (double)az_w < 2.0 * M_PI * (1.0 - 1e-6)) return SPLAT_ERR_INVALID_ARG;

@@ -49,6 +49,14 @@ def test_camera_validation_on_host():
     big = S.make_camera((0, 0, 1.5), 0.0, 1920, 1080, 1500.0, tile=(32, 16))   # 512 px per tile
     assert lib.splat_check_camera(C.byref(st.camera_struct(big))) == 1
     assert lib.splat_check_camera(None) == 1
+    # valid but beyond the binning kernels' limits (unsupported, code 4): 65536 tiles across a
+    # row, and 2^24 tiles in total
+    wide = S.make_camera((0, 0, 1.5), 0.0, 65536, 4, 1500.0, tile=(1, 1))
+    assert lib.splat_check_camera(C.byref(st.camera_struct(wide))) == 4
+    many = S.make_camera((0, 0, 1.5), 0.0, 4096, 4096, 1500.0, tile=(1, 1))
+    assert lib.splat_check_camera(C.byref(st.camera_struct(many))) == 4
+    edge = S.make_camera((0, 0, 1.5), 0.0, 65535, 4, 1500.0, tile=(1, 1))
+    assert lib.splat_check_camera(C.byref(st.camera_struct(edge))) == 0
 
 
 def test_lidar_validation_on_host():
