@@ -340,6 +340,14 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   }
 }
 
+// Digit width of every pass but possibly the last for a sort over total_bits: the fewest
+// passes of at most kRadixBits, with the bits spread evenly (14 bits: 7 + 7 rather than 8 + 6),
+// so that no pass scatters into many more digit runs than it needs.
+static inline int radix_pass_bits(int total_bits) {
+  const int passes = (total_bits + kRadixBits - 1) / kRadixBits;
+  return (total_bits + passes - 1) / passes;
+}
+
 // Sorts (k[cur], v[cur]) stably by key bits [lo_bit, lo_bit + total_bits).  On return `cur`
 // indexes the sorted keys; the sorted values are in v[cur], or in `final_vals` when it is
 // non-null.  n_ptr (device) gives the element count when non-null, capped by n_cap.
@@ -350,11 +358,12 @@ static hipError_t radix_sort(K* k[2], uint32_t* v[2], int& cur, const int64_t* n
                              bool first_hist_ready = false) {
   if (total_bits < 1) total_bits = 1;
   const int passes = (total_bits + kRadixBits - 1) / kRadixBits;
+  const int per = radix_pass_bits(total_bits);   // bits spread evenly over the passes
   const int64_t nb = div_up(n_cap, kScanTile);
   if (nb == 0) return hipSuccess;
   for (int p = 0; p < passes; ++p) {
-    const int shift = lo_bit + p * kRadixBits;
-    const int bits = (total_bits - p * kRadixBits) < kRadixBits ? (total_bits - p * kRadixBits) : kRadixBits;
+    const int shift = lo_bit + p * per;
+    const int bits = (total_bits - p * per) < per ? (total_bits - p * per) : per;
     if (!(p == 0 && first_hist_ready))
       hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(256), 0, s, (const K*)k[cur], n_ptr, n_cap, shift,
                          bits, hist, nb);
@@ -467,7 +476,7 @@ __device__ __forceinline__ int div_small(int a, int b) {
 // (every visible record has >= 1 slot, so the walk advances at most one record per slot).
 // Keys and ids are stored straight from registers (each thread's slots are contiguous).  A
 // workgroup's slots are exactly one tile of the radix sort that follows, so it also writes that
-// tile's counts of the low key digit (the first pass's histogram, hist[d * nb + block], zero
+// tile's counts of the first pass's digit (key & digit_mask: hist[d * nb + block], zero
 // for blocks past the last slot).
 __global__ __launch_bounds__(kEmitThreads) void k_emit(const DevSensor* __restrict__ sens, int count, int64_t N,
                                                        const int4* __restrict__ rect,
@@ -477,7 +486,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const DevSensor* __restri
                                                        const int64_t* __restrict__ n_slots,
                                                        const int64_t* __restrict__ bstart, uint32_t* __restrict__ keys,
                                                        uint32_t* __restrict__ vals, uint32_t* __restrict__ hist,
-                                                       int64_t nb) {
+                                                       int64_t nb, uint32_t digit_mask) {
   __shared__ uint4 s_desc[kEmitRecs];
   __shared__ int16_t s_off[kEmitRecs + 1];   // first slot - k0, clamped to [0, kEmitTile + 1]
   __shared__ uint32_t s_cnt[kRadixBins];
@@ -561,7 +570,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const DevSensor* __restri
       const uint32_t key = d.y + (uint32_t)row * d.w + (uint32_t)col - (col >= wrap ? d.w : 0u);
       kk[j] = key;
       gg[j] = d.x;
-      if (q < nk) atomicAdd(&s_cnt[key & (kRadixBins - 1)], 1u);
+      if (q < nk) atomicAdd(&s_cnt[key & digit_mask], 1u);
       if (++col == w) {
         col = 0;
         ++row;
@@ -840,7 +849,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
     hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks), dim3(kEmitThreads), 0, s, v.sens, v.count, v.n_gauss,
                        (const int4*)p.rect, order, (const int64_t*)w.offs, (const int64_t*)n_vis,
                        (const int64_t*)n_sort, (const int64_t*)w.bstart, w.tkeys[0], tv[0], w.hist,
-                       div_up(L.k_cap, kScanTile));
+                       div_up(L.k_cap, kScanTile), (1u << radix_pass_bits(tbits)) - 1u);
   // 4. stable sort by tile
   uint32_t* tk[2] = {w.tkeys[0], w.tkeys[1]};
   int tcur = 0;
