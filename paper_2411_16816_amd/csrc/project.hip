@@ -113,13 +113,6 @@ __device__ __forceinline__ void add_row(const float* __restrict__ row, float (&a
   }
 }
 
-// Wavefront-scope ordering of LDS accesses between lanes of one wavefront.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Long records are summed in chunks of kChunk positions, one wavefront per chunk and
 // kChunk / 64 positions per lane.
 constexpr int kChunk = 1024;
