@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--modes", default="plain,batched,graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=64, help="rays per sensor in the CPU oracle sample")
+    ap.add_argument("--cpu-rays", type=int, default=160, help="rays per sensor in the CPU oracle sample")
     ap.add_argument("--profile-steps", action="store_true", help="skip parity and CPU legs (for rocprofv3)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the scene's tile shapes")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -120,11 +120,20 @@ def main():
         else:
             passes = [B.SensorPass(rig, 0, 2, g.n, 1, dev, batched=True)]
         Ks = [sp.fit_capacity(G, 1.15) for sp in passes]
-        ups = []
-        for k, sp in enumerate(passes):
-            dF, dD, dA = S.upstream_grads(1000 + k, sp.n_rays, 1)
-            dF = np.random.default_rng(1100 + k).normal(size=sp.n_feat).astype(np.float32)
-            ups.append(tuple(torch.from_numpy(a.reshape(-1)).to(dev) for a in (dF, dD, dA)))
+        # upstream gradients drawn per sensor; the batched form takes their concatenation, so that
+        # every form differentiates the same loss
+        per_sensor = []
+        for k, sensor in enumerate((cam, lid)):
+            _, dD, dA = S.upstream_grads(1000 + k, sensor.n_rays, 1)
+            dF = np.random.default_rng(1100 + k).normal(size=sensor.n_rays * sensor.n_channels).astype(np.float32)
+            per_sensor.append((dF, dD.reshape(-1), dA.reshape(-1)))
+        if mode == "plain":
+            host_ups = per_sensor
+        else:
+            host_ups = [tuple(np.concatenate([per_sensor[0][i], per_sensor[1][i]]) for i in range(3))]
+        ups = [tuple(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev) for a in u) for u in host_ups]
+        for sp, u in zip(passes, ups):
+            assert u[0].numel() == sp.n_feat and u[1].numel() == sp.n_rays, "upstream gradient shapes"
         grads = B.zeros_like_grads(G)
         pipe = pipe_fwd = None
         if mode == "graph":
@@ -168,13 +177,31 @@ def main():
                     a.record(stream)
                     b.record(stream)
         start, end = mk(), mk()
+        marks = [mk() for _ in range(args.steps - 1)]   # step boundaries inside the timed region
         torch.cuda.synchronize()
         start.record(stream)
         for i in range(args.steps):
             step(evs[i])
+            if i < args.steps - 1:
+                marks[i].record(stream)
         end.record(stream)
         torch.cuda.synchronize()
         ms = start.elapsed_time(end) / args.steps
+        bounds = [start] + marks + [end]
+        per_step = np.array([bounds[i].elapsed_time(bounds[i + 1]) for i in range(args.steps)])
+        step_ms = {"median": round(float(np.median(per_step)), 4), "p99": round(float(np.percentile(per_step, 99)), 4),
+                   "min": round(float(per_step.min()), 4), "max": round(float(per_step.max()), 4)}
+        # state after the warm-up and timed steps, for the agreement check between the forms
+        snap_out = {}
+        for k, sp in enumerate(passes):
+            o = sp.outputs()
+            for key in ("feat", "depth", "alpha", "t_final", "last"):
+                snap_out.setdefault(key, []).append(o[key].clone())
+        snap_out = {key: torch.cat(v) for key, v in snap_out.items()}
+        # the median is written for lidar rays only
+        snap_out["median_lidar"] = (passes[1].outputs()["median"].clone() if mode == "plain" else
+                                    passes[0].outputs()["median"][passes[0].sensor_slices(1)[0]].clone())
+        snap_grad = {name: getattr(grads, name).clone() for name in GRAD_FIELDS}
         rays = sum(sp.n_rays for sp in passes)
         names = ["camera", "lidar"] if mode == "plain" else ["both"]
         stage_ms = {} if pipe is not None else {
@@ -210,10 +237,12 @@ def main():
             sp.status.zero_()
             sp.raster_fwd(G, count_pairs=True)
         torch.cuda.synchronize()
-        pairs = [int(B.read_status(sp.status).n_pairs) for sp in passes]
+        sts = [B.read_status(sp.status) for sp in passes]
+        pairs = [int(x.n_pairs) for x in sts]
+        stopped = [int(x.n_stopped) for x in sts]
         results[mode] = dict(ms=ms, value=rays / (ms * 1e-3) / 1e6, stage_ms=stage_ms, kernel_ms=kernel_ms,
-                             parity=parity, K=Ks,
-                             pairs=pairs, rays=rays, ms_fwd=ms_fwd, value_fwd=rays / (ms_fwd * 1e-3) / 1e6)
+                             parity=parity, K=Ks, step_ms=step_ms, snap_out=snap_out, snap_grad=snap_grad,
+                             pairs=pairs, stopped=stopped, rays=rays, ms_fwd=ms_fwd, value_fwd=rays / (ms_fwd * 1e-3) / 1e6)
         log(f"{mode}: {ms:.3f} ms/step, {results[mode]['value']:.1f} Mrays/s (forward only {ms_fwd:.3f} ms, "
             f"{results[mode]['value_fwd']:.1f} Mrays/s); stages "
             + json.dumps({k: round(v, 4) for k, v in stage_ms.items()}) + f"; pairs {pairs}")
@@ -245,9 +274,16 @@ def main():
         "modes": {m: {"value": round(r["value"], 3), "ms_per_step": round(r["ms"], 4),
                       "forward_only_value": round(r["value_fwd"], 3), "forward_only_ms": round(r["ms_fwd"], 4),
                       "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
-                      "intersections": r["K"], "evaluated_pairs": r["pairs"], "parity": r["parity"]}
+                      "intersections": r["K"], "evaluated_pairs": r["pairs"],
+                      "pairs_per_ray": round(sum(r["pairs"]) / r["rays"], 2),
+                      "early_stop_rate": round(sum(r["stopped"]) / r["rays"], 4), "parity": r["parity"]}
                   for m, r in results.items()},
     }
+    for m, r in results.items():
+        out["modes"][m]["step_ms"] = r["step_ms"]
+    agree = mode_agreement(results)
+    if agree:
+        out["agreement"] = agree
     if tune_report is not None:
         out["autotune_ms"] = tune_report
     if "plain" in results:
@@ -262,6 +298,44 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("calibration: 2 copies of 1 GiB")
+
+
+GRAD_FIELDS = ("means", "log_scales", "quats", "opacities", "velocities", "features")
+
+
+def mode_agreement(results):
+    """Each form against the plain per-sensor calls on the same inputs, after the same warm-up +
+    timed steps: forward outputs must be bit-identical (the median of lidar rays only); the
+    accumulated gradients must agree within 1e-4 (relative norm per field)."""
+    if "plain" not in results:
+        return None
+    ref = results["plain"]
+    out = {}
+    for m, r in results.items():
+        if m == "plain":
+            continue
+        fwd_equal = True
+        for key, x in r["snap_out"].items():
+            y = ref["snap_out"][key]
+            fwd_equal = fwd_equal and x.shape == y.shape and bool(torch_equal(x, y))
+        worst = 0.0
+        for name in GRAD_FIELDS:
+            x = r["snap_grad"][name].double()
+            y = ref["snap_grad"][name].double()
+            ny = float(y.norm())
+            if ny > 0:
+                worst = max(worst, float((x - y).norm()) / ny)
+        out[f"{m}_vs_plain"] = {"forward_bit_equal": fwd_equal, "grad_rel_err": float(f"{worst:.3g}"),
+                                "pass": bool(fwd_equal and worst <= 1e-4)}
+    for r in results.values():
+        r.pop("snap_out", None)
+        r.pop("snap_grad", None)
+    return out
+
+
+def torch_equal(x, y):
+    import torch
+    return torch.equal(x, y)
 
 
 def check_parity(passes, rig, g):

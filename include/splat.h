@@ -67,6 +67,8 @@ typedef struct SplatStatus {
   unsigned long long n_pairs;     /* (ray, Gaussian) pairs the forward rasterisers evaluated
                                      (box test passed, alpha computed); counted when the
                                      forward call is given a status                          */
+  unsigned long long n_stopped;   /* rays whose walk ended early because the next blend would
+                                     take the transmittance below 1e-4; counted with n_pairs */
 } SplatStatus;
 
 /* Gaussians (Sec. 3.1).  Device arrays. */

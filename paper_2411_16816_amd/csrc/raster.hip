@@ -49,6 +49,7 @@ struct FwdOut {
   int32_t* last;
   float* median;
   unsigned long long* n_pairs;   // evaluated-pair counter, or null
+  unsigned long long* n_stopped; // early-stopped ray counter (with n_pairs)
 };
 
 struct BwdIn {
@@ -204,6 +205,7 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
   int last = 0;
   unsigned pairs = 0;
   bool done = !c.valid;
+  bool stopped = false;
   bool med_set = false;
   for (int64_t b0 = c.start; b0 < c.end; b0 += kBlock) {
     if (__syncthreads_count(!done) == 0) break;
@@ -229,6 +231,7 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
       const float Tn = T * (1.f - e.alpha);
       const bool stop = act && Tn < kTStop;
       done = done || stop;
+      stopped = stopped || stop;
       act = act && !stop;
       const float w = act ? e.alpha * T : 0.f;
       const float2 d = sm.dv[j];
@@ -257,6 +260,8 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) wp += __shfl_xor(wp, d, 64);
     if ((threadIdx.x & 63) == 0 && wp) atomicAdd(o.n_pairs, wp);
+    const unsigned long long ns = (unsigned long long)__popcll(__ballot(stopped));
+    if ((threadIdx.x & 63) == 0 && ns) atomicAdd(o.n_stopped, ns);
   }
   if (!c.valid) return;
   float* fo = o.feat + c.feat_off;
@@ -569,7 +574,8 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
                              const SplatTileLists& L, int support, const SplatRenderOut& out, SplatStatus* st,
                              hipStream_t s, const KernelTimer& timer) {
   RasterArgs a = make_args(v, g, p, L);
-  FwdOut o{out.feat, out.depth, out.alpha, out.t_final, out.last, out.median, st ? &st->n_pairs : nullptr};
+  FwdOut o{out.feat, out.depth, out.alpha, out.t_final, out.last, out.median, st ? &st->n_pairs : nullptr,
+           st ? &st->n_stopped : nullptr};
   const int cm = cmax_bucket(v.c_max);
   if (v.queue) {
     const int64_t items = L.work_cap;

@@ -15,7 +15,7 @@ SUPPORT_TILE = 1
 class SplatStatus(C.Structure):
     _fields_ = [("n_isect", C.c_ulonglong), ("k_cap", C.c_ulonglong), ("overflow", C.c_uint),
                 ("n_nonfinite", C.c_uint), ("n_rays_invalid", C.c_uint), ("n_rays_time", C.c_uint),
-                ("n_pairs", C.c_ulonglong)]
+                ("n_pairs", C.c_ulonglong), ("n_stopped", C.c_ulonglong)]
 
 
 class SplatGaussians(C.Structure):
