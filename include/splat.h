@@ -353,6 +353,58 @@ int splat_pipeline_create(const SplatRig* rig, int32_t first, int32_t count, con
 int splat_pipeline_run(SplatPipeline* pipeline, void* stream);
 void splat_pipeline_destroy(SplatPipeline* pipeline);
 
+/* ---- scene-graph composition at a capture time (Sec. 3.1 "Scene representation"; the actor
+ * velocity term of Eq. pixel_velocity, Sec. 3.2, and App. D "Rolling shutter details").
+ * The scene is a static background plus rigid actors.  Gaussian i with actor_id[i] = a in
+ * [0, n) holds its mean and rotation in the frame of actor a's box; composing writes the
+ * world-frame arrays that the projection calls read (SplatGaussians.means / quats / velocities):
+ *     mu_w = R_a mu + t_a,     q_w = q_a (x) q,     v_w = R_a (w_a x mu + v_a)
+ * with q_a = q_b (x) dq / |dq| (q_b normalised; the rotation offset acts in the actor frame),
+ * R_a = R(q_a), t_a = t_b + dt (world frame), v_a = v_b + dv and w_a in the actor frame, and
+ * (x) the Hamilton product (R(a (x) b) = R(a) R(b)).  Gaussians with a negative id, or an id
+ * >= n, are static background: mean and rotation are copied, and the world velocity is the
+ * input velocity (zero when `velocities` is NULL).  All arrays are device arrays; quaternion
+ * arrays must be 16-byte aligned (SPLAT_ERR_INVALID_ARG otherwise). */
+typedef struct SplatActors {
+  int32_t n;                    /* actors                                                     */
+  const float* rot;             /* [n,4] base rotation q_b (w,x,y,z), actor -> world         */
+  const float* trans;           /* [n,3] base translation t_b, world frame                   */
+  const float* rot_offset;      /* [n,4] learnable rotation offset dq (w,x,y,z) or NULL      */
+  const float* trans_offset;    /* [n,3] learnable translation offset dt or NULL             */
+  const float* lin_vel;         /* [n,3] linear velocity v_b, actor frame, or NULL (zero)    */
+  const float* lin_vel_offset;  /* [n,3] learnable velocity offset dv or NULL                */
+  const float* ang_vel;         /* [n,3] angular velocity w_a, actor frame, or NULL (zero)   */
+} SplatActors;
+
+/* Gradient accumulators (+=) of the learnable actor arrays, device arrays shaped like them;
+ * a NULL member is skipped (rot_offset also when SplatActors.rot_offset is NULL). */
+typedef struct SplatActorGrads {
+  float* rot_offset;      /* [n,4] */
+  float* trans_offset;    /* [n,3] */
+  float* lin_vel_offset;  /* [n,3] */
+  float* ang_vel;         /* [n,3] */
+} SplatActorGrads;
+
+/* Composes n Gaussians: means [n,3], quats [n,4], velocities [n,3] or NULL, actor_id [n]
+ * (int32) -> means_w [n,3], quats_w [n,4], vel_w [n,3].  Outputs must not overlap the inputs.
+ * n = 0 is a no-op.  Stream-ordered, allocates nothing. */
+int splat_compose(int64_t n, const float* means, const float* quats, const float* velocities,
+                  const int32_t* actor_id, const SplatActors* actors, float* means_w, float* quats_w,
+                  float* vel_w, void* stream);
+/* Workspace of splat_compose_bwd: one 24-float accumulator per actor. */
+size_t splat_compose_workspace_bytes(int32_t n_actors);
+/* Adjoint of splat_compose.  Upstream gradients d_means_w [n,3], d_quats_w [n,4], d_vel_w [n,3]
+ * (e.g. the projection adjoint's SplatGrads means / quats / velocities); accumulates (+=)
+ * d_means [n,3] and d_quats [n,4] of the local arrays, d_velocities [n,3] of static Gaussians
+ * (skipped when NULL), and the actor gradients.  ws must hold
+ * splat_compose_workspace_bytes(actors->n) bytes (SPLAT_ERR_CAPACITY otherwise); its contents
+ * are overwritten.  Calls sharing a workspace must not overlap.  Per-actor sums use float
+ * atomics, so their rounding depends on scheduling. */
+int splat_compose_bwd(int64_t n, const float* means, const float* quats, const int32_t* actor_id,
+                      const SplatActors* actors, const float* d_means_w, const float* d_quats_w,
+                      const float* d_vel_w, float* d_means, float* d_quats, float* d_velocities,
+                      const SplatActorGrads* d_actors, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,9 @@ def _declare(lib):
         "splat_pipeline_create": (C.c_int, [vp, i32, i32, vp, C.POINTER(vp)]),
         "splat_pipeline_run": (C.c_int, [vp, vp]),
         "splat_pipeline_destroy": (None, [vp]),
+        "splat_compose": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "splat_compose_workspace_bytes": (C.c_size_t, [i32]),
+        "splat_compose_bwd": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -465,3 +468,100 @@ class SplatRenderFn(torch.autograd.Function):
         sp.raster_bwd(g, f32(dF, sp.n_feat), f32(dD, sp.n_rays), f32(dA, sp.n_rays), grads, ctx.support)
         return (None, None, grads.means, grads.log_scales, grads.quats, grads.opacities,
                 grads.velocities if ctx.has_vel else None, grads.features)
+
+
+# ----------------------------------------------------------------------------------------
+# scene-graph composition (splat_compose / splat_compose_bwd)
+# ----------------------------------------------------------------------------------------
+ACTOR_FIELDS = ("rot", "trans", "rot_offset", "trans_offset", "lin_vel", "lin_vel_offset", "ang_vel")
+ACTOR_GRAD_FIELDS = ("rot_offset", "trans_offset", "lin_vel_offset", "ang_vel")
+
+
+@dataclass
+class ActorTensors:
+    """Actor poses and motions at a capture time (device float32; None = identity / zero)."""
+    rot: torch.Tensor                               # [A,4] (w,x,y,z)
+    trans: torch.Tensor                             # [A,3]
+    rot_offset: Optional[torch.Tensor] = None       # [A,4]
+    trans_offset: Optional[torch.Tensor] = None     # [A,3]
+    lin_vel: Optional[torch.Tensor] = None          # [A,3]
+    lin_vel_offset: Optional[torch.Tensor] = None   # [A,3]
+    ang_vel: Optional[torch.Tensor] = None          # [A,3]
+
+    @property
+    def n(self) -> int:
+        return int(self.rot.shape[0])
+
+    def struct(self) -> st.SplatActors:
+        a = st.SplatActors()
+        a.n = self.n
+        for f in ACTOR_FIELDS:
+            setattr(a, f, _ptr(getattr(self, f)))
+        return a
+
+
+def _f32(t: torch.Tensor, cols: int, name: str) -> torch.Tensor:
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.dim() != 2 or t.shape[1] != cols:
+        raise SplatError(f"{name}: expected a contiguous float32 [*, {cols}] tensor")
+    return t
+
+
+def compose(means: torch.Tensor, quats: torch.Tensor, actor_id: torch.Tensor, actors: ActorTensors,
+            velocities: Optional[torch.Tensor] = None, stream=None):
+    """World means, rotations and velocities of the scene composed at the actors' poses."""
+    lib = load()
+    n = int(means.shape[0])
+    _f32(means, 3, "means"), _f32(quats, 4, "quats")
+    if actor_id.dtype != torch.int32 or actor_id.numel() != n:
+        raise SplatError("actor_id: expected int32 [n]")
+    mw, qw, vw = torch.empty_like(means), torch.empty_like(quats), torch.empty_like(means)
+    A = actors.struct()
+    check(lib.splat_compose(n, _ptr(means), _ptr(quats), _ptr(velocities), _ptr(actor_id), C.byref(A), _ptr(mw),
+                            _ptr(qw), _ptr(vw), _stream(stream)), "splat_compose")
+    return mw, qw, vw
+
+
+def compose_bwd(means, quats, actor_id, actors: ActorTensors, d_means_w, d_quats_w, d_vel_w, d_means, d_quats,
+                d_velocities=None, d_actors: Optional[dict] = None, ws: Optional[torch.Tensor] = None, stream=None):
+    """Accumulates (+=) the gradients of the local arrays and of the learnable actor arrays."""
+    lib = load()
+    n = int(means.shape[0])
+    need = int(lib.splat_compose_workspace_bytes(actors.n))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=means.device)
+    G = st.SplatActorGrads()
+    for f in ACTOR_GRAD_FIELDS:
+        setattr(G, f, _ptr((d_actors or {}).get(f)))
+    A = actors.struct()
+    check(lib.splat_compose_bwd(n, _ptr(means), _ptr(quats), _ptr(actor_id), C.byref(A), _ptr(d_means_w),
+                                _ptr(d_quats_w), _ptr(d_vel_w), _ptr(d_means), _ptr(d_quats), _ptr(d_velocities),
+                                C.byref(G), _ptr(ws), ws.numel(), _stream(stream)), "splat_compose_bwd")
+    return ws
+
+
+class ComposeFn(torch.autograd.Function):
+    """Differentiable composition: (means, quats, velocities, rot_offset, trans_offset,
+    lin_vel_offset, ang_vel) -> (world means, world quats, world velocities).  The base rotation,
+    translation and linear velocity of the actors are constants."""
+
+    @staticmethod
+    def forward(ctx, actor_id, rot, trans, lin_vel, means, quats, velocities, rot_offset, trans_offset,
+                lin_vel_offset, ang_vel):
+        actors = ActorTensors(rot, trans, rot_offset, trans_offset, lin_vel, lin_vel_offset, ang_vel)
+        mw, qw, vw = compose(means, quats, actor_id, actors, velocities)
+        ctx.actors = actors
+        ctx.save_for_backward(actor_id, means, quats)
+        ctx.has_vel = velocities is not None
+        return mw, qw, vw
+
+    @staticmethod
+    def backward(ctx, gm, gq, gv):
+        actor_id, means, quats = ctx.saved_tensors
+        A = ctx.actors
+        z = lambda t: None if t is None else torch.zeros_like(t)
+        dm, dq = torch.zeros_like(means), torch.zeros_like(quats)
+        dv = torch.zeros_like(means) if ctx.has_vel else None
+        da = {f: z(getattr(A, f)) for f in ACTOR_GRAD_FIELDS}
+        compose_bwd(means, quats, actor_id, A, gm.contiguous(), gq.contiguous(), gv.contiguous(), dm, dq, dv, da)
+        return (None, None, None, None, dm, dq, dv, da["rot_offset"], da["trans_offset"], da["lin_vel_offset"],
+                da["ang_vel"])

@@ -119,3 +119,14 @@ class SplatStep(C.Structure):
                 ("out", SplatRenderOut), ("support", C.c_int32), ("flags", C.c_int32),
                 ("d_feat", C.c_void_p), ("d_depth", C.c_void_p), ("d_alpha", C.c_void_p),
                 ("grads", SplatGrads), ("ws", C.c_void_p), ("ws_bytes", C.c_size_t), ("status", C.c_void_p)]
+
+
+class SplatActors(C.Structure):
+    _fields_ = [("n", C.c_int32), ("rot", C.c_void_p), ("trans", C.c_void_p), ("rot_offset", C.c_void_p),
+                ("trans_offset", C.c_void_p), ("lin_vel", C.c_void_p), ("lin_vel_offset", C.c_void_p),
+                ("ang_vel", C.c_void_p)]
+
+
+class SplatActorGrads(C.Structure):
+    _fields_ = [("rot_offset", C.c_void_p), ("trans_offset", C.c_void_p), ("lin_vel_offset", C.c_void_p),
+                ("ang_vel", C.c_void_p)]

@@ -365,6 +365,64 @@ def make_config(k: int, **kw) -> Scene:
     return {1: config_1, 2: config_2, 3: config_3, 4: config_4, 5: config_5}[k](**kw)
 
 
+# ----------------------------------------------------------------------------------------
+# scene graph: static background + rigid actors (cars on the road)
+# ----------------------------------------------------------------------------------------
+@dataclass
+class ActorScene:
+    gaussians: Gaussians        # means / quats in the actor frame for actor Gaussians
+    actor_id: np.ndarray        # [N] int32, -1 = static background
+    rot: np.ndarray             # [A,4] f32 base rotation (w,x,y,z), actor -> world
+    trans: np.ndarray           # [A,3] f32 base translation (box centre), world
+    rot_offset: np.ndarray      # [A,4] f32 learnable rotation offset (near identity)
+    trans_offset: np.ndarray    # [A,3] f32
+    lin_vel: np.ndarray         # [A,3] f32 actor frame
+    lin_vel_offset: np.ndarray  # [A,3] f32
+    ang_vel: np.ndarray         # [A,3] f32 actor frame
+
+
+def actor_scene(seed: int, n: int, n_actors: int, actor_frac: float = 0.3, contiguous: bool = True,
+                n_feat: int = 16, tumbling: bool = False) -> ActorScene:
+    """A road slab (static, world frame) plus n_actors car-sized boxes (4.5 x 2 x 1.6 m) holding
+    actor_frac of the Gaussians in their own frame.  Cars sit on the road (x in [5, 100] m,
+    y in [-12, 12] m) with uniform yaw and small roll / pitch, drive forward at N(10, 3) m/s along
+    their own x axis with yaw rates N(0, 0.2) rad/s; pose and velocity offsets are small (as
+    after a few optimisation steps).  Gaussians of one actor are stored together when
+    `contiguous`, otherwise the order is shuffled.  `tumbling` draws actor rotations uniformly
+    (any roll and pitch) and angular velocities on every axis: a harder case than cars."""
+    rng = _rng(seed)
+    n_act = int(round(n * actor_frac)) if n_actors > 0 else 0
+    n_static = n - n_act
+    static_means = road_slab(rng, n_static, (0.5, 100.0), (-15.0, 15.0), 6.0)
+    half = np.array([2.25, 1.0, 0.8])
+    aid_act = rng.integers(0, max(n_actors, 1), size=n_act)
+    aid_act.sort()
+    local_means = rng.uniform(-1.0, 1.0, size=(n_act, 3)) * half
+    means = np.concatenate([static_means, local_means])
+    g = random_gaussians(rng, means, n_feat, rgb=True, moving_frac=0.2)
+    aid = np.concatenate([np.full(n_static, -1, np.int64), aid_act]).astype(np.int32)
+    if not contiguous:
+        perm = rng.permutation(n)
+        g = g.subset(perm)
+        aid = aid[perm]
+    g.velocities[aid >= 0] = 0.0
+    A = max(n_actors, 0)
+    yaw = rng.uniform(-math.pi, math.pi, size=A)
+    tilt = rng.normal(0.0, 0.02, size=(A, 2))
+    rot = np.stack([np.cos(yaw / 2), np.sin(tilt[:, 0] / 2), np.sin(tilt[:, 1] / 2), np.sin(yaw / 2)], 1)
+    if tumbling:
+        rot = rng.normal(size=(A, 4))
+    rot /= np.linalg.norm(rot, axis=1, keepdims=True)
+    trans = np.stack([rng.uniform(5.0, 100.0, A), rng.uniform(-12.0, 12.0, A), np.full(A, 0.8)], 1)
+    rot_off = np.concatenate([np.ones((A, 1)), rng.normal(0.0, 0.01, size=(A, 3))], 1)
+    f = lambda x: np.ascontiguousarray(x, dtype=F32)
+    return ActorScene(g, aid, f(rot), f(trans), f(rot_off), f(rng.normal(0.0, 0.05, (A, 3))),
+                      f(np.stack([rng.normal(10.0, 3.0, A), np.zeros(A), np.zeros(A)], 1)),
+                      f(rng.normal(0.0, 0.1, (A, 3))),
+                      f(rng.normal(0.0, 0.5, (A, 3)) if tumbling else
+                        np.stack([np.zeros(A), np.zeros(A), rng.normal(0.0, 0.2, A)], 1)))
+
+
 def upstream_grads(seed: int, n_rays: int, n_channels: int):
     """Seeded upstream gradients dL/dF [R,C], dL/dD [R], dL/dA [R] (float32)."""
     rng = _rng(seed)
