@@ -37,6 +37,8 @@ METRIC = "Mrays/s fwd+bwd, 128x2048 lidar + 1080p camera; batched vs plain at 1e
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3            # vector FP32, datasheet (packed FMA)
+PEAK_HBM_GBS = 8000.0               # HBM3E, datasheet
+SEED_COMPOSE = 16816 + 11           # seed of the composition workload
 # algorithmic FP32 work per evaluated (ray, Gaussian) pair of the forward compositing loop:
 # Delta (6), sigma (9), exp (1), alpha (1), transmittance (2), weight (1), feature and depth
 # blends (2 C + 2), plus the lidar range correction (2) and azimuth reduction (3);
@@ -53,6 +55,10 @@ def parse():
     ap.add_argument("--n", type=int, default=2_000_000, help="Gaussians")
     ap.add_argument("--modes", default="plain,batched,graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compose", action="store_true", help="skip the scene-graph composition measurement")
+    ap.add_argument("--c5", action="store_true",
+                    help="instead of the headline step: the 60-sensor sweep workload (3M Gaussians, 48 lidar sweeps "
+                         "+ 12 cameras) with per-sensor latency p50/p99 from in-kernel clocks")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=160, help="rays per sensor in the CPU oracle sample")
     ap.add_argument("--profile-steps", action="store_true", help="skip parity and CPU legs (for rocprofv3)")
@@ -79,6 +85,9 @@ def main():
     from paper_2411_16816_amd import binding as B
     from scenes import synthetic as S
 
+    if args.c5:
+        print(json.dumps(c5_latency(args, "cuda")), flush=True)
+        return
     t0 = time.time()
     sc = S.headline(n=args.n)
     cam, lid = sc.cameras[0], sc.lidars[0]
@@ -281,6 +290,8 @@ def main():
     }
     for m, r in results.items():
         out["modes"][m]["step_ms"] = r["step_ms"]
+    if not args.no_compose:
+        out["compose"] = compose_bench(args, dev)
     agree = mode_agreement(results)
     if agree:
         out["agreement"] = agree
@@ -422,6 +433,145 @@ def roofline(results):
             "forward": {"kernel": "k_raster_fwd_queue<16, false>", "kernel_ms": round(t_fwd * 1e3, 4),
                         "achieved": round(flop_fwd / t_fwd / 1e12, 3),
                         "frac": round(flop_fwd / t_fwd / 1e12 / PEAK_FP32_TFLOPS, 4)}}
+
+
+def c5_latency(args, dev):
+    """The sweep workload: 3M Gaussians, 48 lidar sweeps (16 each of 32, 64 and 128 beams,
+    1024-2048 azimuth steps) and 12 1080p cameras.  Its lists exceed one call's int32 positions,
+    so a step is one batched call (persistent rasteriser) per sensor group.  Per-sensor latency =
+    (device clock when the sensor's last work item finished) - (device clock stamped on the
+    stream when the group's step started), fwd-only and fwd+bwd; p50 / p99 over the sensors and
+    the timed steps."""
+    import torch
+    from paper_2411_16816_amd import binding as B
+    from scenes import synthetic as S
+    t0 = time.time()
+    sc = S.config_5()
+    n_cam = len(sc.cameras)
+    log(f"C5: {sc.gaussians.n} Gaussians, {n_cam} cameras, {len(sc.lidars)} lidars, built in {time.time() - t0:.1f}s")
+    rig = B.Rig(sc.cameras, sc.lidars, dev)
+    G = B.GaussTensors.from_numpy(sc.gaussians, dev)
+    hz = B.device_clock_hz()
+    groups = [(0, 6), (6, 6), (n_cam, 16), (n_cam + 16, 16), (n_cam + 32, 8), (n_cam + 40, 8)]
+    stream = torch.cuda.current_stream()
+    lat = {"fwd": {"camera": [], "lidar": []}, "fwd_bwd": {"camera": [], "lidar": []}}
+    ms = {"fwd": 0.0, "fwd_bwd": 0.0}
+    rays_total = 0
+    mk = lambda: torch.cuda.Event(enable_timing=True)
+    for first, count in groups:
+        sp = B.SensorPass(rig, first, count, sc.gaussians.n, 1, dev, batched=True)
+        K = sp.fit_capacity(G, 1.1)
+        rng = np.random.default_rng(700 + first)
+        dF = torch.from_numpy(rng.normal(size=sp.n_feat).astype(np.float32)).to(dev)
+        dD = torch.from_numpy((0.01 * rng.normal(size=sp.n_rays)).astype(np.float32)).to(dev)
+        dA = torch.from_numpy(rng.normal(size=sp.n_rays).astype(np.float32)).to(dev)
+        grads = B.zeros_like_grads(G)
+        clk = torch.zeros(args.steps + 1, dtype=torch.int64, device=dev)
+        kinds = ["camera" if first + k < n_cam else "lidar" for k in range(count)]
+        for phase in ("fwd", "fwd_bwd"):
+            done = torch.zeros(args.steps + 1, count, dtype=torch.int64, device=dev)
+
+            def step(i):
+                B.device_clock(clk, i)
+                sp.project(G)
+                sp.bin_sort()
+                sp.raster_fwd(G, sensor_done=done[i] if phase == "fwd" else None)
+                if phase == "fwd_bwd":
+                    sp.raster_bwd(G, dF, dD, dA, grads, sensor_done=done[i])
+
+            step(args.steps)   # warm-up (slot `steps`, discarded)
+            torch.cuda.synchronize()
+            a, b = mk(), mk()
+            a.record(stream)
+            for i in range(args.steps):
+                step(i)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms[phase] += a.elapsed_time(b) / args.steps
+            d = done[:args.steps].cpu().numpy().astype(np.float64)
+            c = clk[:args.steps].cpu().numpy().astype(np.float64)
+            for k in range(count):
+                lat[phase][kinds[k]].extend(((d[:, k] - c) / hz * 1e3).tolist())
+        st_ = B.read_status(sp.status)
+        if st_.overflow:
+            raise SystemExit(f"C5 group {first}: overflow")
+        rays_total += sp.n_rays
+        log(f"C5 group [{first}, {first + count}): {K} entries, {sp.n_rays} rays")
+        del sp, grads
+        torch.cuda.empty_cache()
+    pct = lambda v, q: round(float(np.percentile(np.asarray(v), q)), 4)
+    out = {"metric": "C5 sweep: per-sensor latency p50/p99 and Mrays/s, fwd and fwd+bwd", "n_gpus": 1,
+           "steps": args.steps, "data": "synthetic", "dtype": "f32",
+           "config": {"workload": "3M Gaussians, 48 lidar sweeps (16 x 32 / 64 / 128 beams, 1024-2048 az) + "
+                                  "12 RS cameras 1920x1080", "calls_per_step": len(groups),
+                      "groups": [list(g_) for g_ in groups], "rays_per_step": rays_total}}
+    for phase in ("fwd", "fwd_bwd"):
+        out[phase] = {"ms_per_step": round(ms[phase], 4), "Mrays_per_s": round(rays_total / (ms[phase] * 1e-3) / 1e6, 3),
+                      "latency_ms": {k: {"p50": pct(v, 50), "p99": pct(v, 99), "n": len(v)}
+                                     for k, v in lat[phase].items()}}
+        log(f"C5 {phase}: {ms[phase]:.3f} ms/step; latency {out[phase]['latency_ms']}")
+    return out
+
+
+def compose_bench(args, dev):
+    """Scene-graph composition (splat_compose, splat_compose_bwd) on 2M Gaussians of which 30 %
+    belong to 64 car-sized actors, timed with HIP events around each call over the timed steps,
+    against the HBM roofline (algorithmic bytes: every array read or written once)."""
+    import torch
+    from oracle import compose as oc
+    from paper_2411_16816_amd import binding as B
+    from scenes import synthetic as S
+    sc = S.actor_scene(SEED_COMPOSE, 2_000_000, 64)
+    g = sc.gaussians
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
+    mu, q, v, aid = f(g.means), f(g.quats), f(g.velocities), torch.from_numpy(sc.actor_id).to(dev)
+    A = B.ActorTensors(f(sc.rot), f(sc.trans), f(sc.rot_offset), f(sc.trans_offset), f(sc.lin_vel),
+                       f(sc.lin_vel_offset), f(sc.ang_vel))
+    r = np.random.default_rng(9)
+    gm, gq, gv = (f(r.normal(size=s_)) for s_ in ((g.n, 3), (g.n, 4), (g.n, 3)))
+    dm, dq, dv = torch.zeros_like(mu), torch.zeros_like(q), torch.zeros_like(v)
+    da = {k: torch.zeros_like(getattr(A, k)) for k in B.ACTOR_GRAD_FIELDS}
+    ws = torch.empty(int(B.load().splat_compose_workspace_bytes(A.n)), dtype=torch.uint8, device=dev)
+    for _ in range(args.warmup):
+        mw, qw, vw = B.compose(mu, q, aid, A, v)
+        B.compose_bwd(mu, q, aid, A, gm, gq, gv, dm, dq, dv, da, ws)
+    stream = torch.cuda.current_stream()
+    mk = lambda: torch.cuda.Event(enable_timing=True)
+    ev = [(mk(), mk(), mk()) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for e0, e1, e2 in ev:
+        e0.record(stream)
+        mw, qw, vw = B.compose(mu, q, aid, A, v)
+        e1.record(stream)
+        B.compose_bwd(mu, q, aid, A, gm, gq, gv, dm, dq, dv, da, ws)
+        e2.record(stream)
+    torch.cuda.synchronize()
+    t_f = float(np.median([a.elapsed_time(b) for a, b, _ in ev])) * 1e-3
+    t_b = float(np.median([b.elapsed_time(c) for _, b, c in ev])) * 1e-3
+    n, n_static = g.n, int((sc.actor_id < 0).sum())
+    bytes_f = n * (12 + 16 + 4 + 12 + 16 + 12) + n_static * 12
+    bytes_b = n * (12 + 16 + 12 + 4 + 12 + 16 + 24 + 32) + n_static * 24
+    # sampled parity of the world arrays against the oracle
+    idx = np.sort(np.random.default_rng(3).choice(n, 4096, replace=False))
+    t = lambda a: torch.from_numpy(np.asarray(a, np.float64))
+    sub_id = sc.actor_id[idx]
+    ref = oc.compose(t(g.means[idx]), t(g.quats[idx]), sub_id, t(sc.rot), t(sc.trans), t(sc.rot_offset),
+                     t(sc.trans_offset), t(sc.lin_vel), t(sc.lin_vel_offset), t(sc.ang_vel), t(g.velocities[idx]))
+    worst = 0.0
+    for got, want in zip((mw, qw, vw), ref):
+        a_ = got[torch.from_numpy(idx).to(dev)].double().cpu().numpy()
+        w_ = want.numpy()
+        worst = max(worst, float((np.abs(a_ - w_) / (1e-5 + 1e-4 * np.abs(w_))).max()))
+    ach_f, ach_b = bytes_f / t_f / 1e9, bytes_b / t_b / 1e9
+    log(f"compose: fwd {t_f * 1e3:.4f} ms ({ach_f:.0f} GB/s), bwd {t_b * 1e3:.4f} ms ({ach_b:.0f} GB/s)")
+    return {"workload": "2M Gaussians, 30 % in 64 rigid actors (cars), world means / rotations / velocities",
+            "fwd_ms": round(t_f * 1e3, 4), "bwd_ms": round(t_b * 1e3, 4),
+            "roofline": {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
+                         "fwd": {"achieved": round(ach_f, 1), "frac": round(ach_f / PEAK_HBM_GBS, 4),
+                                 "bytes_per_launch": int(bytes_f)},
+                         "bwd": {"achieved": round(ach_b, 1), "frac": round(ach_b / PEAK_HBM_GBS, 4),
+                                 "bytes_per_launch": int(bytes_b)}},
+            "parity": {"gaussians": 4096, "max_err_over_tol": round(worst, 4), "pass": bool(worst <= 1.0)}}
 
 
 def cpu_baseline(g, cam, lid, n_rays):

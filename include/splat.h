@@ -185,6 +185,11 @@ typedef struct SplatRenderOut {
   float* t_final;   /* [n_rays] final transmittance (saved for the adjoint)                   */
   int32_t* last;    /* [n_rays] 1 + position in the tile list of the last blended Gaussian    */
   float* median;    /* [n_rays] median range of lidar rays (camera rays: not written) or NULL */
+  unsigned long long* sensor_done;  /* [count] or NULL: for latency measurement, each sensor's
+                       entry is raised (atomic max) to the device wall clock (splat_device_clock
+                       ticks) when a work item of that sensor finishes in a rasteriser call
+                       given this struct (the forward's `out`, or the adjoint's `saved`); the
+                       caller zeroes it.  Items of lidar rays outside every tile are not timed. */
 } SplatRenderOut;
 
 /* Gradient accumulators (+=), device arrays shaped like SplatGaussians. */
@@ -352,6 +357,12 @@ int splat_pipeline_create(const SplatRig* rig, int32_t first, int32_t count, con
                           SplatPipeline** out);
 int splat_pipeline_run(SplatPipeline* pipeline, void* stream);
 void splat_pipeline_destroy(SplatPipeline* pipeline);
+
+/* ---- device clock, for latency measurement: splat_device_clock writes the device's
+ * constant-rate wall clock to *dst (device memory) when the stream reaches the call (one tiny
+ * kernel); splat_device_clock_hz gives its rate in ticks per second for the current device. */
+int splat_device_clock(unsigned long long* dst, void* stream);
+int splat_device_clock_hz(int64_t* hz);
 
 /* ---- scene-graph composition at a capture time (Sec. 3.1 "Scene representation"; the actor
  * velocity term of Eq. pixel_velocity, Sec. 3.2, and App. D "Rolling shutter details").

@@ -58,6 +58,8 @@ def _declare(lib):
         "splat_pipeline_create": (C.c_int, [vp, i32, i32, vp, C.POINTER(vp)]),
         "splat_pipeline_run": (C.c_int, [vp, vp]),
         "splat_pipeline_destroy": (None, [vp]),
+        "splat_device_clock": (C.c_int, [vp, vp]),
+        "splat_device_clock_hz": (C.c_int, [C.POINTER(C.c_int64)]),
         "splat_compose": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "splat_compose_workspace_bytes": (C.c_size_t, [i32]),
         "splat_compose_bwd": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
@@ -294,10 +296,11 @@ class SensorPass:
         L.work_cap = self.work_cap
         return L
 
-    def out_struct(self):
+    def out_struct(self, sensor_done: Optional[torch.Tensor] = None):
         o = st.SplatRenderOut()
         o.feat, o.depth, o.alpha = _ptr(self.feat), _ptr(self.depth), _ptr(self.alpha)
         o.t_final, o.last, o.median = _ptr(self.t_final), _ptr(self.last), _ptr(self.median)
+        o.sensor_done = _ptr(sensor_done)
         return o
 
     # ---- the four calls -------------------------------------------------------------------
@@ -322,32 +325,37 @@ class SensorPass:
             check(self.lib.splat_time_next_raster(C.c_void_p(a.cuda_event), C.c_void_p(b.cuda_event)),
                   "splat_time_next_raster")
 
-    def raster_fwd(self, g: GaussTensors, support=BOX, stream=None, count_pairs: bool = False, timer=None):
+    def raster_fwd(self, g: GaussTensors, support=BOX, stream=None, count_pairs: bool = False, timer=None,
+                   sensor_done: Optional[torch.Tensor] = None):
+        """sensor_done: optional int64 [count] device tensor of per-sensor completion clocks."""
         st_ = _ptr(self.status) if count_pairs else None
         self._time(timer)
+        out = self.out_struct(sensor_done)
         if self.batched:
             check(self.lib.splat_rasterize_fwd(C.byref(g.struct()), self.rig.handle, self.first, self.count,
                                                C.byref(self.proj_struct()), C.byref(self.lists_struct()), support,
-                                               C.byref(self.out_struct()), st_, _stream(stream)),
+                                               C.byref(out), st_, _stream(stream)),
                   "splat_rasterize_fwd")
         elif self.lidar:
             check(self.lib.splat_rasterize_fwd_lidar(C.byref(g.struct()), self.rig.handle, self.first, self.count,
                                                      C.byref(self.proj_struct()), C.byref(self.lists_struct()),
-                                                     support, C.byref(self.out_struct()), st_,
+                                                     support, C.byref(out), st_,
                                                      _stream(stream)), "splat_rasterize_fwd_lidar")
         else:
             check(self.lib.splat_rasterize_fwd_camera(C.byref(g.struct()), self.rig.handle, self.first, self.count,
                                                       C.byref(self.proj_struct()), C.byref(self.lists_struct()),
-                                                      support, C.byref(self.out_struct()), st_, _stream(stream)),
+                                                      support, C.byref(out), st_, _stream(stream)),
                   "splat_rasterize_fwd_camera")
 
-    def raster_bwd(self, g: GaussTensors, dF, dD, dA, grads: GaussTensors, support=BOX, stream=None, timer=None):
+    def raster_bwd(self, g: GaussTensors, dF, dD, dA, grads: GaussTensors, support=BOX, stream=None, timer=None,
+                   sensor_done: Optional[torch.Tensor] = None):
         gr = _grads_struct(grads)
         self._time(timer)
         fn = (self.lib.splat_rasterize_bwd if self.batched else
               self.lib.splat_rasterize_bwd_lidar if self.lidar else self.lib.splat_rasterize_bwd_camera)
         check(fn(C.byref(g.struct()), self.rig.handle, self.first, self.count, C.byref(self.proj_struct()),
-                 C.byref(self.lists_struct()), support, C.byref(self.out_struct()), _ptr(dF), _ptr(dD), _ptr(dA),
+                 C.byref(self.lists_struct()), support, C.byref(self.out_struct(sensor_done)), _ptr(dF), _ptr(dD),
+                 _ptr(dA),
                  C.byref(gr), C.c_void_p(self.ws_ptr), self.ws_bytes, _stream(stream)), "splat_rasterize_bwd")
 
     # ---- conveniences ---------------------------------------------------------------------
@@ -565,3 +573,17 @@ class ComposeFn(torch.autograd.Function):
         compose_bwd(means, quats, actor_id, A, gm.contiguous(), gq.contiguous(), gv.contiguous(), dm, dq, dv, da)
         return (None, None, None, None, dm, dq, dv, da["rot_offset"], da["trans_offset"], da["lin_vel_offset"],
                 da["ang_vel"])
+
+
+# ----------------------------------------------------------------------------------------
+# device clock (latency measurement)
+# ----------------------------------------------------------------------------------------
+def device_clock(dst: torch.Tensor, index: int = 0, stream=None):
+    """Writes the device wall clock into dst[index] (int64 device tensor) in stream order."""
+    check(load().splat_device_clock(C.c_void_p(dst.data_ptr() + 8 * index), _stream(stream)), "splat_device_clock")
+
+
+def device_clock_hz() -> int:
+    hz = C.c_int64()
+    check(load().splat_device_clock_hz(C.byref(hz)), "splat_device_clock_hz")
+    return int(hz.value)

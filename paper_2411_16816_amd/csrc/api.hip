@@ -29,7 +29,26 @@ static bool same_layout(const DevSensor& a, const DevSensor& b) {
          a.feat_off == b.feat_off;
 }
 
+// one thread: the device's constant-rate wall clock at the point the stream reaches the launch
+__global__ void k_device_clock(unsigned long long* dst) { *dst = (unsigned long long)wall_clock64(); }
+
 extern "C" {
+
+int splat_device_clock(unsigned long long* dst, void* stream) {
+  if (!dst) return SPLAT_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(k_device_clock, dim3(1), dim3(1), 0, (hipStream_t)stream, dst);
+  return hipGetLastError() == hipSuccess ? SPLAT_OK : SPLAT_ERR_DEVICE;
+}
+
+int splat_device_clock_hz(int64_t* hz) {
+  if (!hz) return SPLAT_ERR_INVALID_ARG;
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SPLAT_ERR_DEVICE;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    return SPLAT_ERR_DEVICE;
+  *hz = (int64_t)khz * 1000;
+  return SPLAT_OK;
+}
 
 const char* splat_status_string(int code) {
   switch (code) {

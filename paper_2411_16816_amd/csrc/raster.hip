@@ -50,6 +50,7 @@ struct FwdOut {
   float* median;
   unsigned long long* n_pairs;   // evaluated-pair counter, or null
   unsigned long long* n_stopped; // early-stopped ray counter (with n_pairs)
+  unsigned long long* sensor_done;  // per-sensor completion clock (atomic max), or null
 };
 
 struct BwdIn {
@@ -63,7 +64,13 @@ struct BwdIn {
   uint8_t* rflag;    // [n_rec] set for every record given a gradient (row or atomic)
   float* g2d;        // [n_rec, kNV] atomic part from work items of split lidar tiles
   float* dfeat;      // features gradient (atomic part, split lidar tiles)
+  unsigned long long* sensor_done;  // per-sensor completion clock (atomic max), or null
 };
+
+// Latency stamp of a finished work item: the sensor's entry rises to the device wall clock.
+__device__ __forceinline__ void stamp_done(unsigned long long* done, int s) {
+  if (done && threadIdx.x == 0) atomicMax(done + s, (unsigned long long)wall_clock64());
+}
 
 __device__ __forceinline__ int sensor_of_tile(const DevSensor* sens, int count, int64_t t) {
   int lo = 0, hi = count - 1;
@@ -263,6 +270,7 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
     const unsigned long long ns = (unsigned long long)__popcll(__ballot(stopped));
     if ((threadIdx.x & 63) == 0 && ns) atomicAdd(o.n_stopped, ns);
   }
+  if (!(LIDAR && c.invalid_bin)) stamp_done(o.sensor_done, c.s);
   if (!c.valid) return;
   float* fo = o.feat + c.feat_off;
 #pragma unroll
@@ -350,7 +358,7 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
   int* s_used = sm.used;
   RayCtx c;
   setup_ray<LIDAR>(a, tile, pos, c);
-  if (LIDAR && c.invalid_bin) return;    // uniform over the workgroup
+  if (LIDAR && c.invalid_bin) return;    // uniform over the workgroup (not timed)
   const int tid = threadIdx.x, lane = tid & 63;
   float T = 1.f, Tf = 1.f, dD = 0.f, dA = 0.f, bufD = 0.f;
   float dF[CMAX];
@@ -375,7 +383,10 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
   __syncthreads();
   const int64_t n_proc = sm.maxlast;
   __syncthreads();           // everyone has read maxlast before it can be reset by the next item
-  if (n_proc == 0) return;   // uniform
+  if (n_proc == 0) {         // uniform
+    stamp_done(b.sensor_done, c.s);
+    return;
+  }
   const DevSensor& S = a.sens[c.s];
   const int64_t tile_local = tile - (S.tile_base - a.sens[0].tile_base);
   // a lidar tile with more rays than one item holds is shared by several items
@@ -476,6 +487,7 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
     }
     __syncthreads();
   }
+  stamp_done(b.sensor_done, c.s);
 }
 
 template <int CMAX, bool LIDAR, bool TILE>
@@ -575,7 +587,7 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
                              hipStream_t s, const KernelTimer& timer) {
   RasterArgs a = make_args(v, g, p, L);
   FwdOut o{out.feat, out.depth, out.alpha, out.t_final, out.last, out.median, st ? &st->n_pairs : nullptr,
-           st ? &st->n_stopped : nullptr};
+           st ? &st->n_stopped : nullptr, out.sensor_done};
   const int cm = cmax_bucket(v.c_max);
   if (v.queue) {
     const int64_t items = L.work_cap;
@@ -627,7 +639,7 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
                              const float* dD, const float* dA, const Workspace& w, float* dfeat, hipStream_t s,
                              const KernelTimer& timer) {
   RasterArgs a = make_args(v, g, p, L);
-  BwdIn b{saved.t_final, saved.last, dF, dD, dA, w.slots, w.flags, w.rflag, w.g2d, dfeat};
+  BwdIn b{saved.t_final, saved.last, dF, dD, dA, w.slots, w.flags, w.rflag, w.g2d, dfeat, saved.sensor_done};
   const int cm = cmax_bucket(v.c_max);
   if (w.stride != slot_stride(cm)) return hipErrorInvalidValue;
   if (v.queue) {

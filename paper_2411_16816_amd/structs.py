@@ -62,7 +62,7 @@ class SplatTileLists(C.Structure):
 
 class SplatRenderOut(C.Structure):
     _fields_ = [("feat", C.c_void_p), ("depth", C.c_void_p), ("alpha", C.c_void_p), ("t_final", C.c_void_p),
-                ("last", C.c_void_p), ("median", C.c_void_p)]
+                ("last", C.c_void_p), ("median", C.c_void_p), ("sensor_done", C.c_void_p)]
 
 
 class SplatGrads(C.Structure):
