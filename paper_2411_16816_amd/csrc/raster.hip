@@ -201,8 +201,28 @@ struct FwdSmem {
   float4 f[kBlock * (CMAX / 4)];
 };
 
+// Counters of a workgroup's forward items, per lane, summed over every item the workgroup
+// renders and added to the status once per wavefront at the end of the kernel (a persistent
+// workgroup renders many items; per-item global atomics on two addresses would contend).
+struct FwdCount {
+  unsigned long long pairs = 0, stopped = 0;
+  __device__ void flush(const FwdOut& o) {
+    if (!o.n_pairs) return;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      pairs += __shfl_xor(pairs, d, 64);
+      stopped += __shfl_xor(stopped, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      if (pairs) atomicAdd(o.n_pairs, pairs);
+      if (stopped) atomicAdd(o.n_stopped, stopped);
+    }
+  }
+};
+
 template <int CMAX, bool LIDAR, bool TILE>
-__device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, int64_t tile, int pos, FwdSmem<CMAX>& sm) {
+__device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, int64_t tile, int pos, FwdSmem<CMAX>& sm,
+                                         FwdCount& cnt) {
   RayCtx c;
   setup_ray<LIDAR>(a, tile, pos, c);
   float T = 1.f, D = 0.f, med = 0.f;
@@ -262,14 +282,8 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
     }
   }
   __syncthreads();   // LDS is reused by the next item of a persistent workgroup
-  if (o.n_pairs) {
-    unsigned long long wp = pairs;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) wp += __shfl_xor(wp, d, 64);
-    if ((threadIdx.x & 63) == 0 && wp) atomicAdd(o.n_pairs, wp);
-    const unsigned long long ns = (unsigned long long)__popcll(__ballot(stopped));
-    if ((threadIdx.x & 63) == 0 && ns) atomicAdd(o.n_stopped, ns);
-  }
+  cnt.pairs += pairs;
+  cnt.stopped += stopped ? 1u : 0u;
   if (!(LIDAR && c.invalid_bin)) stamp_done(o.sensor_done, c.s);
   if (!c.valid) return;
   float* fo = o.feat + c.feat_off;
@@ -287,13 +301,15 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
 template <int CMAX, bool LIDAR, bool TILE>
 __global__ __launch_bounds__(kBlock) void k_raster_fwd(RasterArgs a, FwdOut o) {
   __shared__ FwdSmem<CMAX> sm;
+  FwdCount cnt;
   if (!LIDAR) {
-    fwd_item<CMAX, false, TILE>(a, o, blockIdx.x, 0, sm);
+    fwd_item<CMAX, false, TILE>(a, o, blockIdx.x, 0, sm, cnt);
   } else {
     if ((int64_t)blockIdx.x >= (int64_t)a.n_work[0]) return;
     const int2 w = a.work[blockIdx.x];
-    fwd_item<CMAX, true, TILE>(a, o, w.x, w.y, sm);
+    fwd_item<CMAX, true, TILE>(a, o, w.x, w.y, sm, cnt);
   }
+  cnt.flush(o);
 }
 
 // Fetch the next queue entry for the whole workgroup (persistent kernels).
@@ -314,14 +330,16 @@ template <int CMAX, bool TILE>
 __global__ __launch_bounds__(kBlock) void k_raster_fwd_queue(RasterArgs a, FwdOut o, int32_t* counter) {
   __shared__ FwdSmem<CMAX> sm;
   __shared__ int s_slot;
+  FwdCount cnt;
   const int n_items = a.n_work[0];
   for (;;) {
     const int it = next_item(counter, &s_slot);
     if (it >= n_items) break;
     const int2 w = a.work[it];
-    if (item_is_lidar(a, w.x)) fwd_item<CMAX, true, TILE>(a, o, w.x, w.y, sm);
-    else fwd_item<CMAX, false, TILE>(a, o, w.x, 0, sm);
+    if (item_is_lidar(a, w.x)) fwd_item<CMAX, true, TILE>(a, o, w.x, w.y, sm, cnt);
+    else fwd_item<CMAX, false, TILE>(a, o, w.x, 0, sm, cnt);
   }
+  cnt.flush(o);
 }
 
 // ------------------------------------------------------------------------------------------
