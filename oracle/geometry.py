@@ -29,6 +29,9 @@ TWO_PI = 2.0 * math.pi
 
 
 def t64(x) -> torch.Tensor:
+    """FP64 tensor of x; a tensor passes through (keeping its autograd graph)."""
+    if isinstance(x, torch.Tensor):
+        return x.to(D)
     return torch.as_tensor(np.asarray(x, dtype=np.float64), dtype=D)
 
 
@@ -108,7 +111,10 @@ def relative_velocity(mu_s, p: Params, R, lin_vel, ang_vel):
 # --------------------------------------------------------------------------------------
 # common tail: EWA dilation, conic, compensated opacity, rectangular box (Eq. alpha, Sec. 3.2)
 # --------------------------------------------------------------------------------------
-def _dilate_and_box(mean2d, cov2, vel2, opac, eps2d, t_rs):
+def _dilate_and_box(mean2d, cov2, vel2, opac, eps2d, t_rs, t_off=0.0):
+    """t_off: capture-time offset of the sensor (cameras): the rows are exposed over
+    [t_off - t_rs/2, t_off + t_rs/2], so the box is centred on the mean at t_off (a candidacy
+    decision, not differentiated)."""
     a = cov2[:, 0, 0] + eps2d
     b = cov2[:, 0, 1]
     c = cov2[:, 1, 1] + eps2d
@@ -119,8 +125,9 @@ def _dilate_and_box(mean2d, cov2, vel2, opac, eps2d, t_rs):
     o_eff = opac * torch.sqrt(torch.clamp(ratio, min=1e-300))
     o_eff = torch.where(det2 > 0, o_eff, torch.zeros_like(o_eff))
     ext = 3.0 * torch.sqrt(torch.stack([a, c], -1)) + torch.abs(vel2) * (0.5 * t_rs)
-    lo = mean2d - ext
-    hi = mean2d + ext
+    centre = mean2d + vel2.detach() * float(t_off)
+    lo = centre - ext
+    hi = centre + ext
     return conic, o_eff, ext, lo, hi
 
 
@@ -168,7 +175,9 @@ def project_camera(p: Params, cam) -> Projection:
     vrel = relative_velocity(mu, p, cam.R, cam.lin_vel, cam.ang_vel)
     vel2 = (J @ vrel[..., None])[..., 0]
     mean2d = torch.stack([u, v], -1)
-    conic, o_eff, ext, lo, hi = _dilate_and_box(mean2d, cov2, vel2, p.opacities, cam.eps2d, cam.t_rs)
+    t_off = getattr(cam, "time_offset", 0.0)
+    t_off = float(t_off.detach()) if isinstance(t_off, torch.Tensor) else float(t_off)
+    conic, o_eff, ext, lo, hi = _dilate_and_box(mean2d, cov2, vel2, p.opacities, cam.eps2d, cam.t_rs, t_off)
     with torch.no_grad():
         valid = in_depth.clone()
         valid &= (lo[:, 0] < cam.width) & (hi[:, 0] > 0) & (lo[:, 1] < cam.height) & (hi[:, 1] > 0)

@@ -39,6 +39,45 @@ def reference_grads(g, sensor, ray_idx, dF, dD, dA, mode="box"):
     return res, out
 
 
+def reference_sensor_grads(g, sensor, ray_idx, dF, dD, dA, mode="box"):
+    """Gradients of the weighted loss with respect to the sensor's linear and angular velocity
+    (sensor frame) and, for a camera, its time offset: {name: float64 numpy}, by FP64 autograd
+    with the sensor parameters as leaves (candidacy decisions do not depend on them
+    differentiably)."""
+    import dataclasses
+    leaves = {"lin_vel": geo.t64(sensor.lin_vel).clone().requires_grad_(True),
+              "ang_vel": geo.t64(sensor.ang_vel).clone().requires_grad_(True)}
+    if not hasattr(sensor, "ray_az"):
+        leaves["time_offset"] = geo.t64(getattr(sensor, "time_offset", 0.0)).clone().requires_grad_(True)
+    s2 = dataclasses.replace(sensor, **leaves)
+    p = geo.Params.from_gaussians(g)
+    out = rd.render_sensor(p, s2, ray_idx, mode)
+    L = weighted_loss(out, geo.t64(dF), geo.t64(dD), geo.t64(dA))
+    grads = torch.autograd.grad(L, list(leaves.values()), allow_unused=True)
+    return {k: (np.zeros(tuple(v.shape)) if gr is None else gr.detach().numpy())
+            for (k, v), gr in zip(leaves.items(), grads)}, out
+
+
+def sensor_finite_diff(g, sensor, ray_idx, dF, dD, dA, name, index=None, h=1e-6, mode="box"):
+    """Central difference of the weighted loss in one sensor parameter (FP64 forward)."""
+    import dataclasses
+    base = np.asarray(getattr(sensor, name), dtype=np.float64)
+    dF, dD, dA = geo.t64(dF), geo.t64(dD), geo.t64(dA)
+    p = geo.Params.from_gaussians(g)
+    vals = []
+    for sgn in (1.0, -1.0):
+        x = base.copy()
+        if index is None:
+            x = x + sgn * h
+        else:
+            x[index] += sgn * h
+        s2 = dataclasses.replace(sensor, **{name: x if x.ndim else float(x)})
+        with torch.no_grad():
+            out = rd.render_sensor(p, s2, ray_idx, mode)
+            vals.append(float(weighted_loss(out, dF, dD, dA)))
+    return (vals[0] - vals[1]) / (2 * h)
+
+
 def _forward_value(p, sensor, ray_idx, dF, dD, dA, mode):
     with torch.no_grad():
         out = rd.render_sensor(p, sensor, ray_idx, mode)

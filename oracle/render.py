@@ -63,7 +63,9 @@ def camera_rays(cam, pixel_idx=None) -> Rays:
     row = idx // cam.width
     col = idx % cam.width
     p = torch.stack([geo.t64(col + 0.5), geo.t64(row + 0.5)], -1)
-    t = geo.t64(((row + 0.5) / cam.height - 0.5) * cam.t_rs)
+    # capture time of the row relative to the sensor timestamp (Eq. t_pix), plus the camera's
+    # time offset between its timestamp and the middle of the exposure (Sec. 3.2)
+    t = geo.t64(((row + 0.5) / cam.height - 0.5) * cam.t_rs) + geo.t64(getattr(cam, "time_offset", 0.0))
     tx = -(-cam.width // cam.tile_w)
     tile = (row // cam.tile_h) * tx + col // cam.tile_w
     return Rays(p, t, tile, np.ones(idx.shape[0], bool))

@@ -85,6 +85,7 @@ class Camera:
     n_channels: int = 0
     tile_w: int = 16
     tile_h: int = 16
+    time_offset: float = 0.0   # sensor timestamp minus middle of the exposure [s]
 
     @property
     def n_rays(self) -> int:
