@@ -100,6 +100,9 @@ typedef struct SplatCamera {
   float jac_clamp;   /* x/z, y/z clamped to +-jac_clamp * (size/2)/f inside J (0 = off)        */
   int32_t feat_offset, n_channels;  /* blended feature columns [offset, offset + n_channels)   */
   int32_t tile_w, tile_h;           /* pixels per tile; tile_w * tile_h <= 256, both >= 1      */
+  float time_offset; /* [s] camera timestamp minus the middle of the exposure (Sec. 3.2): pixel
+                        row times are (p_v / H - 1/2) t_rs + time_offset, and the rolling-shutter
+                        box is centred on the mean at time_offset.  0 = centred exposure.    */
 } SplatCamera;
 
 /* Spinning lidar (Sec. 3.3, App. A).  x_l = R x_w + t with x forward, y left, z up.
@@ -200,6 +203,11 @@ typedef struct SplatGrads {
   float* opacities;   /* [n]   */
   float* velocities;  /* [n,3] or NULL */
   float* features;    /* [n,c_total] */
+  /* Sensor parameters of the call's sensors [first, first + count) (index k = sensor - first),
+   * accumulated (+=) when non-NULL: */
+  float* sensor_lin_vel;      /* [count,3] dL/d lin_vel (sensor frame)                          */
+  float* sensor_ang_vel;      /* [count,3] dL/d ang_vel (sensor frame)                          */
+  float* sensor_time_offset;  /* [count] dL/d time_offset of cameras (lidar entries untouched)  */
 } SplatGrads;
 
 const char* splat_status_string(int code);

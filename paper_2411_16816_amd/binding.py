@@ -348,8 +348,8 @@ class SensorPass:
                   "splat_rasterize_fwd_camera")
 
     def raster_bwd(self, g: GaussTensors, dF, dD, dA, grads: GaussTensors, support=BOX, stream=None, timer=None,
-                   sensor_done: Optional[torch.Tensor] = None):
-        gr = _grads_struct(grads)
+                   sensor_done: Optional[torch.Tensor] = None, sensor_grads: Optional[dict] = None):
+        gr = _grads_struct(grads, sensor_grads)
         self._time(timer)
         fn = (self.lib.splat_rasterize_bwd if self.batched else
               self.lib.splat_rasterize_bwd_lidar if self.lidar else self.lib.splat_rasterize_bwd_camera)
@@ -393,10 +393,17 @@ class SensorPass:
                 slice(int(self.feat_off[k]), int(self.feat_off[k + 1])), s.n_channels)
 
 
-def _grads_struct(grads: GaussTensors) -> st.SplatGrads:
+SENSOR_GRAD_FIELDS = ("sensor_lin_vel", "sensor_ang_vel", "sensor_time_offset")
+
+
+def _grads_struct(grads: GaussTensors, sensor_grads: Optional[dict] = None) -> st.SplatGrads:
+    """sensor_grads: optional {"sensor_lin_vel": [count,3], "sensor_ang_vel": [count,3],
+    "sensor_time_offset": [count]} float32 device accumulators of the call's sensors."""
     gr = st.SplatGrads()
     gr.means, gr.log_scales, gr.quats = _ptr(grads.means), _ptr(grads.log_scales), _ptr(grads.quats)
     gr.opacities, gr.velocities, gr.features = _ptr(grads.opacities), _ptr(grads.velocities), _ptr(grads.features)
+    for f in SENSOR_GRAD_FIELDS:
+        setattr(gr, f, _ptr((sensor_grads or {}).get(f)))
     return gr
 
 

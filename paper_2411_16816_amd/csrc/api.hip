@@ -307,7 +307,8 @@ static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t f
   if (e == hipSuccess) e = launch_fill_i32((int32_t*)w.rflag, div_up((int64_t)count * g->n, 4), 0, s);
   if (e == hipSuccess && v.has_lidar) e = launch_fill_f32(w.g2d, (int64_t)count * g->n * kNV, 0.f, s);
   if (e == hipSuccess)
-    e = launch_raster_bwd(v, *g, *proj, *lists, support, *saved, dF, dD, dA, w, gr->features, s, take_timer());
+    e = launch_raster_bwd(v, *g, *proj, *lists, support, *saved, dF, dD, dA, w, gr->features, gr->sensor_time_offset, s,
+                          take_timer());
   if (e == hipSuccess) e = launch_project_bwd(v, *g, *proj, *lists, w, *gr, s);
   return dev_err(e);
 }

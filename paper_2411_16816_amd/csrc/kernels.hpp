@@ -109,8 +109,8 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
                              hipStream_t s, const KernelTimer& timer);
 hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
                              const SplatTileLists& L, int support, const SplatRenderOut& saved, const float* dF,
-                             const float* dD, const float* dA, const Workspace& w, float* dfeat, hipStream_t s,
-                             const KernelTimer& timer);
+                             const float* dD, const float* dA, const Workspace& w, float* dfeat, float* d_toff,
+                             hipStream_t s, const KernelTimer& timer);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 

@@ -279,37 +279,69 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const DevSensor* __restrict
 
 // Projection adjoint, one thread per Gaussian: chains every record's g2d gradient (mean.x,
 // mean.y, vel.x, vel.y, conic a, b, c, o_eff, depth (z | r), v_r) through the projection.
+// Projection adjoint, one thread per Gaussian over the call's sensors.  With sensor-velocity
+// gradients requested, every touched record also contributes dL/dlin = -g and dL/dang = g x mu_s
+// (g = dL/dvrel, mu_s the sensor-frame mean), summed per sensor over the wavefront with a
+// reduce-scatter and one atomic per value.
 __global__ __launch_bounds__(256) void k_project_bwd(const DevSensor* __restrict__ sens, int count, SplatGaussians g,
                                                      const uint8_t* __restrict__ rflag, const float* __restrict__ g2d,
                                                      SplatGrads gr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.n) return;
+  const bool in = i < g.n;
+  const bool want_s = gr.sensor_lin_vel || gr.sensor_ang_vel;   // uniform
   bool touched = false;
-  for (int k = 0; k < count && !touched; ++k) touched = rflag[(int64_t)k * g.n + i] != 0;
-  if (!touched) return;
+  if (in)
+    for (int k = 0; k < count && !touched; ++k) touched = rflag[(int64_t)k * g.n + i] != 0;
+  if (!want_s) {
+    if (!in || !touched) return;
+  } else if (__ballot(in && touched) == 0) {
+    return;   // uniform over the wavefront: nothing to add
+  }
+  const bool live = in && touched;
   GaussLoad G;
-  load_gaussian(g, i, G);
   QuatRot qr;
   float s[3], M[9];
-  gaussian_M(G.q, G.ls, qr, s, M);
+  if (live) {
+    load_gaussian(g, i, G);
+    gaussian_M(G.q, G.ls, qr, s, M);
+  }
   float dmu[3] = {0.f, 0.f, 0.f}, dM[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, dvg[3] = {0.f, 0.f, 0.f};
   float dop = 0.f;
   bool any = false;
+  bool store = false;
+  const int slot = want_s ? scatter_slot<6>(threadIdx.x & 63, store) : 0;
   for (int k = 0; k < count; ++k) {
     const int64_t r = (int64_t)k * g.n + i;
-    if (rflag[r] == 0) continue;   // no gradient reached this record
-    const float* q = g2d + r * kNV;
-    RecGrad rg;
-    rg.mean[0] = q[0]; rg.mean[1] = q[1]; rg.vel[0] = q[2]; rg.vel[1] = q[3];
-    rg.conic[0] = q[4]; rg.conic[1] = q[5]; rg.conic[2] = q[6]; rg.o_eff = q[7];
-    rg.depth = q[8]; rg.v_r = q[9];
-    ProjInter I;
-    ProjOut o;
-    project_one(sens[k], G.mu, M, G.vg, G.op, I, o);
-    project_one_vjp(sens[k], M, G.op, I, o, rg, dmu, dM, dvg, &dop);
-    any = true;
+    const bool hit = live && rflag[r] != 0;   // a gradient reached this record
+    float sv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (hit) {
+      const float* q = g2d + r * kNV;
+      RecGrad rg;
+      rg.mean[0] = q[0]; rg.mean[1] = q[1]; rg.vel[0] = q[2]; rg.vel[1] = q[3];
+      rg.conic[0] = q[4]; rg.conic[1] = q[5]; rg.conic[2] = q[6]; rg.o_eff = q[7];
+      rg.depth = q[8]; rg.v_r = q[9];
+      ProjInter I;
+      ProjOut o;
+      project_one(sens[k], G.mu, M, G.vg, G.op, I, o);
+      float dv[3];
+      project_one_vjp(sens[k], M, G.op, I, o, rg, dmu, dM, dvg, &dop, dv);
+      any = true;
+      if (want_s) {
+        float c3[3];
+        cross3(dv, I.mu, c3);
+        sv[0] = -dv[0]; sv[1] = -dv[1]; sv[2] = -dv[2];
+        sv[3] = c3[0]; sv[4] = c3[1]; sv[5] = c3[2];
+      }
+    }
+    if (want_s && __ballot(hit) != 0) {   // uniform
+      const float x = wave_reduce_scatter<6>(sv);
+      if (store) {
+        float* dst = slot < 3 ? gr.sensor_lin_vel : gr.sensor_ang_vel;
+        if (dst) atomicAdd(dst + 3 * k + (slot % 3), x);
+      }
+    }
   }
-  if (!any) return;
+  if (!live || !any) return;
   float dq[4], dls[3];
   gaussian_M_vjp(qr, s, dM, dq, dls);
   gr.means[3 * i + 0] += dmu[0]; gr.means[3 * i + 1] += dmu[1]; gr.means[3 * i + 2] += dmu[2];

@@ -65,6 +65,7 @@ struct BwdIn {
   float* g2d;        // [n_rec, kNV] atomic part from work items of split lidar tiles
   float* dfeat;      // features gradient (atomic part, split lidar tiles)
   unsigned long long* sensor_done;  // per-sensor completion clock (atomic max), or null
+  float* d_toff;     // [count] camera time-offset gradients (+=), or null
 };
 
 // Latency stamp of a finished work item: the sensor's entry rises to the device wall clock.
@@ -132,7 +133,8 @@ __device__ __forceinline__ void setup_ray(const RasterArgs& a, int64_t tile, int
     c.valid = in_tile && x < S.width && y < S.height;
     c.px = (float)x + 0.5f;
     c.py = (float)y + 0.5f;
-    c.t = (c.py / (float)S.height - 0.5f) * S.t_rs;   // Eq. t_pix at the pixel centre
+    // Eq. t_pix at the pixel centre, plus the camera's time offset (timestamp - mid-exposure)
+    c.t = (c.py / (float)S.height - 0.5f) * S.t_rs + S.t_off;
     int64_t pix = (int64_t)y * S.width + x;
     c.ray = (S.ray_base - a.sens[0].ray_base) + pix;
     c.feat_off = (S.feat_base - a.sens[0].feat_base) + pix * S.n_ch;
@@ -361,6 +363,7 @@ struct BwdSmem {
   float acc[BwdShape<CMAX>::V][kBwdBatch];
   int used[kBwdBatch];
   int maxlast;
+  float toff;   // the item's time-offset gradient, summed over its wavefronts
 };
 
 template <int CMAX, bool LIDAR, bool TILE>
@@ -393,7 +396,10 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
     for (int k = 0; k < CMAX; ++k)
       if (k < c.C) dF[k] = g[k];
   }
-  if (tid == 0) sm.maxlast = 0;
+  if (tid == 0) {
+    sm.maxlast = 0;
+    sm.toff = 0.f;
+  }
   for (int k = tid; k < SH::V * kBwdBatch; k += kBlock) (&s_acc[0][0])[k] = 0.f;
   if (tid < kBwdBatch) s_used[tid] = 0;
   __syncthreads();
@@ -413,6 +419,7 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
   bool my_store;
   const int my_idx = scatter_slot<SH::V>(lane, my_store);
   float S_dot = 0.f;   // sum_c buf_c dF_c, the feature part of the colour behind this Gaussian
+  float tacc = 0.f;    // camera: dL/dt of this ray's pairs (mean at time t moves with the velocity)
   for (int64_t b0 = c.start + ((n_proc - 1) / kBwdBatch) * kBwdBatch; b0 >= c.start; b0 -= kBwdBatch) {
     const int64_t b1 = (b0 + kBwdBatch < c.start + n_proc) ? b0 + kBwdBatch : c.start + n_proc;
     if (tid < kBwdBatch) stage_batch<CMAX>(a, c, b0, b1, s_mv, s_cn, s_box, s_dv, s_f);
@@ -459,6 +466,7 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
       const float dsig = e.clamped ? 0.f : -dalpha * e.alpha;
       const float ddx = (q.x * e.dx + q.y * e.dy) * dsig;
       const float ddy = (q.y * e.dx + q.z * e.dy) * dsig;
+      if (!LIDAR) tacc = SPLAT_FMA(-ddx, m.z, SPLAT_FMA(-ddy, m.w, tacc));
       v[0] = -ddx;
       v[1] = -ddy;
       v[2] = -ddx * c.t;
@@ -504,6 +512,13 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
       s_used[tid] = 0;
     }
     __syncthreads();
+  }
+  if (!LIDAR && b.d_toff) {   // uniform: the item's time-offset gradient, one global add
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) tacc += __shfl_xor(tacc, d, 64);
+    if (lane == 0) atomicAdd(&sm.toff, tacc);
+    __syncthreads();
+    if (tid == 0) atomicAdd(b.d_toff + c.s, sm.toff);
   }
   stamp_done(b.sensor_done, c.s);
 }
@@ -654,10 +669,10 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
 
 hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
                              const SplatTileLists& L, int support, const SplatRenderOut& saved, const float* dF,
-                             const float* dD, const float* dA, const Workspace& w, float* dfeat, hipStream_t s,
-                             const KernelTimer& timer) {
+                             const float* dD, const float* dA, const Workspace& w, float* dfeat, float* d_toff,
+                             hipStream_t s, const KernelTimer& timer) {
   RasterArgs a = make_args(v, g, p, L);
-  BwdIn b{saved.t_final, saved.last, dF, dD, dA, w.slots, w.flags, w.rflag, w.g2d, dfeat, saved.sensor_done};
+  BwdIn b{saved.t_final, saved.last, dF, dD, dA, w.slots, w.flags, w.rflag, w.g2d, dfeat, saved.sensor_done, d_toff};
   const int cm = cmax_bucket(v.c_max);
   if (w.stride != slot_stride(cm)) return hipErrorInvalidValue;
   if (v.queue) {

@@ -30,7 +30,7 @@ inline int build_camera(const SplatCamera& c, DevSensor& d) {
   if (c.n_channels < 0 || c.n_channels > SPLAT_MAX_CHANNELS || c.feat_offset < 0) return SPLAT_ERR_INVALID_ARG;
   if (!finite_all(c.R, 9) || !finite_all(c.t, 3) || !finite_all(c.lin_vel, 3) || !finite_all(c.ang_vel, 3))
     return SPLAT_ERR_INVALID_ARG;
-  if (!isfinite(c.cx) || !isfinite(c.cy)) return SPLAT_ERR_INVALID_ARG;
+  if (!isfinite(c.cx) || !isfinite(c.cy) || !isfinite(c.time_offset)) return SPLAT_ERR_INVALID_ARG;
   d.kind = kCamera;
   d.feat_off = c.feat_offset;
   d.n_ch = c.n_channels;
@@ -40,6 +40,7 @@ inline int build_camera(const SplatCamera& c, DevSensor& d) {
   memcpy(d.ang, c.ang_vel, sizeof(d.ang));
   d.t_rs = c.t_rs;
   d.eps2d = c.eps2d;
+  d.t_off = c.time_offset;
   d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
   d.near_p = c.near_plane; d.far_p = c.far_plane;
   if (c.jac_clamp > 0.f) {

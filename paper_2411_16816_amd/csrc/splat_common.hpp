@@ -34,6 +34,7 @@ struct alignas(16) DevSensor {
   int64_t n_rays;
   float R[9], t[3], lin[3], ang[3];
   float t_rs, eps2d;
+  float t_off;                 // camera time offset (0 for lidars)
   // camera
   float fx, fy, cx, cy, near_p, far_p, limx, limy;   // limx/limy <= 0: no Jacobian clamp
   int32_t width, height, tile_w, tile_h, tiles_x, tiles_y;
@@ -195,10 +196,12 @@ HD void dilate_and_box(const DevSensor& S, float opac, ProjInter& I, ProjOut& o)
   float hr = 0.5f * S.t_rs;
   float ex = 3.0f * sqrtf(a) + fabsf(o.vel[0]) * hr;
   float ey = 3.0f * sqrtf(c) + fabsf(o.vel[1]) * hr;
-  o.box[0] = o.mean[0] - ex;
-  o.box[1] = o.mean[1] - ey;
-  o.box[2] = o.mean[0] + ex;
-  o.box[3] = o.mean[1] + ey;
+  // centred on the mean at the sensor's time offset (the middle of the exposure; 0 for lidars)
+  const float cx = fmaf(o.vel[0], S.t_off, o.mean[0]), cy = fmaf(o.vel[1], S.t_off, o.mean[1]);
+  o.box[0] = cx - ex;
+  o.box[1] = cy - ey;
+  o.box[2] = cx + ex;
+  o.box[3] = cy + ey;
 }
 
 HD void sensor_frame(const DevSensor& S, const float mu_w[3], const float M[9], const float vg[3], ProjInter& I) {
@@ -394,8 +397,11 @@ struct RecGrad {
   float mean[2], vel[2], conic[3], o_eff, depth, v_r;
 };
 
+// dvrel_out (optional): the gradient with respect to the sensor-frame relative velocity, from
+// which the sensor's own velocity gradients follow (vrel = -ang x mu - lin + R vg).
 HD void project_one_vjp(const DevSensor& S, const float M[9], float opac, const ProjInter& I, const ProjOut& o,
-                        const RecGrad& g, float dmu_w[3], float dM[9], float dvg[3], float* dopac) {
+                        const RecGrad& g, float dmu_w[3], float dM[9], float dvg[3], float* dopac,
+                        float* dvrel_out = nullptr) {
   const float s = S.eps2d;
   // --- o_eff = opac * sqrt(ratio), ratio = det2 / detp
   float sq = sqrtf(I.ratio);
@@ -444,6 +450,11 @@ HD void project_one_vjp(const DevSensor& S, const float M[9], float opac, const 
     for (int k = 0; k < 3; ++k) dJ[i * 3 + k] += gv[i] * I.vrel[k];
   float dvrel[3];
   mat3t_vec(I.J, gv, dvrel);
+  if (dvrel_out) {
+    dvrel_out[0] = dvrel[0];
+    dvrel_out[1] = dvrel[1];
+    dvrel_out[2] = dvrel[2];
+  }
   // --- sensor-frame mean gradient
   float dmu[3] = {0, 0, 0};
   if (S.kind == kCamera) {

@@ -30,7 +30,7 @@ class SplatCamera(C.Structure):
                 ("lin_vel", C.c_float * 3), ("ang_vel", C.c_float * 3), ("t_rs", C.c_float),
                 ("eps2d", C.c_float), ("near_plane", C.c_float), ("far_plane", C.c_float),
                 ("jac_clamp", C.c_float), ("feat_offset", C.c_int32), ("n_channels", C.c_int32),
-                ("tile_w", C.c_int32), ("tile_h", C.c_int32)]
+                ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("time_offset", C.c_float)]
 
 
 class SplatLidar(C.Structure):
@@ -67,7 +67,8 @@ class SplatRenderOut(C.Structure):
 
 class SplatGrads(C.Structure):
     _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
-                ("opacities", C.c_void_p), ("velocities", C.c_void_p), ("features", C.c_void_p)]
+                ("opacities", C.c_void_p), ("velocities", C.c_void_p), ("features", C.c_void_p),
+                ("sensor_lin_vel", C.c_void_p), ("sensor_ang_vel", C.c_void_p), ("sensor_time_offset", C.c_void_p)]
 
 
 def _arr(ctype, n, values):
@@ -87,6 +88,7 @@ def camera_struct(cam) -> SplatCamera:
     s.near_plane, s.far_plane, s.jac_clamp = float(cam.near), float(cam.far), float(cam.jac_clamp)
     s.feat_offset, s.n_channels = int(cam.feat_offset), int(cam.n_channels)
     s.tile_w, s.tile_h = int(cam.tile_w), int(cam.tile_h)
+    s.time_offset = float(getattr(cam, "time_offset", 0.0))
     return s
 
 
