@@ -12,7 +12,9 @@ them by (depth, Gaussian id) and alpha-composites front to back:
   * F = sum_i f_i alpha_i prod_{j<i}(1 - alpha_j) (Eq. alpha_blend); the depth output blends
     the camera z, or the rolling-shutter corrected lidar range r + v_r t (Sec. 3.3);
   * median range = corrected range of the first Gaussian after which the transmittance is
-    below 1/2 (Sec. 3.3), 0 if there is none.
+    below 1/2 (Sec. 3.3), 0 if there is none;
+  * line-of-sight sum (the loss term L_los of the training-details appendix): for a lidar ray with a measured range r_p,
+    the sum of the alphas of the blended Gaussians whose corrected range is below r_p - eps.
 
 Candidate rule:
   BOX  (default) -- Gaussians whose 3-sigma + rolling-shutter box contains the sample point
@@ -55,6 +57,7 @@ class Rays:
     t: torch.Tensor      # [R] time relative to the sensor's mid-exposure
     tile: np.ndarray     # [R] tile id (for the TILE rule), -1 if the ray is outside all tiles
     valid: np.ndarray    # [R] bool
+    los_thr: torch.Tensor = None   # [R] lidar: measured range minus the line-of-sight margin
 
 
 def camera_rays(cam, pixel_idx=None) -> Rays:
@@ -78,7 +81,9 @@ def lidar_rays(lid, ray_idx=None) -> Rays:
     p = torch.stack([geo.t64(az), geo.t64(el)], -1)
     a, e, valid = tl.lidar_ray_tiles(az, el, lid)
     tile = np.where(valid, e * lid.n_az_tiles + a, -1)
-    return Rays(p, geo.t64(lid.ray_t[idx]), tile, valid)
+    rng_ = getattr(lid, "ray_range", None)
+    thr = None if rng_ is None else geo.t64(np.asarray(rng_, np.float64)[idx]) - float(lid.los_eps)
+    return Rays(p, geo.t64(lid.ray_t[idx]), tile, valid, thr)
 
 
 def _box_mask(proj, cols, p, lo_pad=0.0):
@@ -135,12 +140,13 @@ def _alpha_at(proj, ids, rays_p, rays_t):
     return torch.clamp(o[None] * torch.exp(-sigma), max=ALPHA_MAX)
 
 
-def _composite(proj, feats, rays_p, rays_t, idx, cand, amb=None):
+def _composite(proj, feats, rays_p, rays_t, idx, cand, amb=None, los_thr=None):
     """Front-to-back compositing of the Gaussians `idx` (already in (depth, id) order) for a
     chunk of rays; `cand` [r,K] marks candidacy.  `amb` [r,K] marks Gaussians whose candidacy
     is a near-edge decision: the ray is near-decision if one of them would pass the alpha skip
-    rule at or before the point where the ray stops.  Returns differentiable F, D, A and
-    diagnostics."""
+    rule at or before the point where the ray stops.  `los_thr` [r] (lidar): the line-of-sight
+    sum adds the alpha of every blended Gaussian whose corrected range is below it (the line-of-sight
+    loss term of the training-details appendix).  Returns differentiable F, D, A, los and diagnostics."""
     mean = proj.mean2d[idx]
     vel = proj.vel2d[idx]
     con = proj.conic[idx]
@@ -171,6 +177,11 @@ def _composite(proj, feats, rays_p, rays_t, idx, cand, amb=None):
         g = proj.blend[idx][None].expand_as(w)
     F = w @ feats[idx]
     Dv = (w * g).sum(1)
+    if los_thr is not None:
+        front = keep & (g.detach() < los_thr[:, None])
+        los = torch.where(front, alpha, torch.zeros_like(alpha)).sum(1)
+    else:
+        los = torch.zeros_like(Dv)
     T_final = t_after[:, -1]
     A = 1.0 - T_final
     with torch.no_grad():
@@ -197,6 +208,9 @@ def _composite(proj, feats, rays_p, rays_t, idx, cand, amb=None):
         if amb is not None:
             matters = amb & (alpha >= ALPHA_MIN * (1.0 - NEAR_ALPHA)) & (torch.arange(K)[None, :] <= first[:, None])
             near |= matters.any(1)
+        if los_thr is not None:   # a corrected range within float32 reach of the threshold
+            gd = g.detach()
+            near |= (keep & (torch.abs(gd - los_thr[:, None]) <= NEAR_BOX * (torch.abs(gd) + 1.0))).any(1)
         # depth near-ties among Gaussians that pass the skip rule up to the stop: distinct depths
         # closer than the ordering key resolves may be ordered differently; exactly equal depths
         # are ordered by id on both sides
@@ -206,7 +220,7 @@ def _composite(proj, feats, rays_p, rays_t, idx, cand, amb=None):
             close = (gap <= NEAR_DEPTH * dep[1:]) & (gap > 0)
             both = upto[:, 1:] & upto[:, :-1]
             near |= (both & close[None, :]).any(1)
-    return F, Dv, A, T_final, median, last_id, n_kept, near, sig
+    return F, Dv, A, T_final, median, last_id, n_kept, near, sig, los
 
 
 def render(proj, sensor, feats_all, rays: Rays, mode: str = "box", chunk: int = None):
@@ -223,7 +237,7 @@ def render(proj, sensor, feats_all, rays: Rays, mode: str = "box", chunk: int = 
     n_rays = rays.p.shape[0]
     if chunk is None:
         chunk = int(max(1, min(256, 4_000_000 // max(1, order.shape[0]))))
-    outF, outD, outA, outT, outM, outL, outN, outNear, outS = [], [], [], [], [], [], [], [], []
+    outF, outD, outA, outT, outM, outL, outN, outNear, outS, outLos = [], [], [], [], [], [], [], [], [], []
     near_cull = proj.near_cull.numpy()
     for s in range(0, n_rays, chunk):
         e = min(n_rays, s + chunk)
@@ -262,9 +276,12 @@ def render(proj, sensor, feats_all, rays: Rays, mode: str = "box", chunk: int = 
             outN.append(torch.zeros(r, dtype=torch.int64))
             outNear.append(near_box)
             outS.append(torch.zeros(r, 3, dtype=D))
+            outLos.append(z + 0.0 * proj.o_eff.sum())
             continue
-        F, Dv, A, T, M, L, N, near, S = _composite(proj, feats, p, t, idx, cand_all[:, cols],
-                                                   None if amb_all is None else amb_all[:, cols])
+        thr = None if rays.los_thr is None else rays.los_thr[s:e]
+        F, Dv, A, T, M, L, N, near, S, LOS = _composite(proj, feats, p, t, idx, cand_all[:, cols],
+                                                        None if amb_all is None else amb_all[:, cols], thr)
+        outLos.append(LOS)
         outS.append(S)
         outF.append(F)
         outD.append(Dv)
@@ -275,7 +292,7 @@ def render(proj, sensor, feats_all, rays: Rays, mode: str = "box", chunk: int = 
         outN.append(N)
         outNear.append(near | near_box)
     return dict(F=torch.cat(outF), D=torch.cat(outD), A=torch.cat(outA), T=torch.cat(outT),
-                median=torch.cat(outM), last_id=torch.cat(outL), n_kept=torch.cat(outN),
+                median=torch.cat(outM), last_id=torch.cat(outL), n_kept=torch.cat(outN), los=torch.cat(outLos),
                 near=torch.cat(outNear).numpy(), sig=torch.cat(outS))
 
 

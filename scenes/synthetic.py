@@ -115,6 +115,8 @@ class Lidar:
     ray_t: np.ndarray         # [R] f32, seconds relative to the middle of the sweep
     feat_offset: int = 0
     n_channels: int = 0
+    ray_range: Optional[np.ndarray] = None   # [R] f32 measured range of each ray, or None
+    los_eps: float = 0.8      # line-of-sight margin [m]
 
     @property
     def n_rays(self) -> int:
