@@ -127,6 +127,9 @@ typedef struct SplatLidar {
   const float* ray_el;       /* device [n_rays] */
   const float* ray_t;        /* device [n_rays] */
   int32_t feat_offset, n_channels;
+  const float* ray_range;    /* device [n_rays] measured range of each ray, or NULL: enables the
+                                line-of-sight sum (training-details appendix, loss term L_los)  */
+  float los_eps;             /* line-of-sight margin [m] (0.8 in the paper), >= 0               */
 } SplatLidar;
 
 /* Opaque rig: a device-resident table of sensors (cameras first, then lidars). */
@@ -193,6 +196,11 @@ typedef struct SplatRenderOut {
                        ticks) when a work item of that sensor finishes in a rasteriser call
                        given this struct (the forward's `out`, or the adjoint's `saved`); the
                        caller zeroes it.  Items of lidar rays outside every tile are not timed. */
+  float* los;       /* [n_rays] or NULL: lidar rays' line-of-sight sum, the alphas of the Gaussians
+                       the ray blends whose corrected range r + v_r t is below ray_range - los_eps
+                       (0 without ray_range; camera rays: not written)                         */
+  const float* d_los;  /* [n_rays] or NULL: upstream gradient of `los`, read by the adjoint from
+                       its `saved` struct (NULL = zero)                                          */
 } SplatRenderOut;
 
 /* Gradient accumulators (+=), device arrays shaped like SplatGaussians. */

@@ -23,15 +23,20 @@ from . import geometry as geo
 from . import render as rd
 
 
-def weighted_loss(out, dF, dD, dA):
-    return (out["F"] * dF).sum() + (out["D"] * dD).sum() + (out["A"] * dA).sum()
+def weighted_loss(out, dF, dD, dA, dlos=None):
+    """Sum of the outputs weighted by upstream gradients; `dlos` weights the lidar line-of-sight
+    sum (the loss term L_los of the training-details appendix)."""
+    L = (out["F"] * dF).sum() + (out["D"] * dD).sum() + (out["A"] * dA).sum()
+    if dlos is not None:
+        L = L + (out["los"] * dlos).sum()
+    return L
 
 
-def reference_grads(g, sensor, ray_idx, dF, dD, dA, mode="box"):
+def reference_grads(g, sensor, ray_idx, dF, dD, dA, mode="box", dlos=None):
     """Returns ({name: grad [N,...] float64 numpy}, forward dict)."""
     p = geo.Params.from_gaussians(g, requires_grad=True)
     out = rd.render_sensor(p, sensor, ray_idx, mode)
-    L = weighted_loss(out, geo.t64(dF), geo.t64(dD), geo.t64(dA))
+    L = weighted_loss(out, geo.t64(dF), geo.t64(dD), geo.t64(dA), None if dlos is None else geo.t64(dlos))
     grads = torch.autograd.grad(L, p.tensors(), allow_unused=True)
     res = {}
     for name, gr, ten in zip(geo.Params.names, grads, p.tensors()):

@@ -160,8 +160,12 @@ class Rig:
             cams[i] = st.camera_struct(c)
         lids = (st.SplatLidar * max(1, self.n_lid))()
         for i, l in enumerate(self.lidars):
-            host = [torch.from_numpy(np.ascontiguousarray(a, np.float32)) for a in (l.ray_az, l.ray_el, l.ray_t)]
-            if i < len(self.ray_tensors) and all(d.numel() == h.numel() for d, h in zip(self.ray_tensors[i], host)):
+            arrs = (l.ray_az, l.ray_el, l.ray_t)
+            if getattr(l, "ray_range", None) is not None:   # measured ranges: the line-of-sight sum
+                arrs = arrs + (l.ray_range,)
+            host = [torch.from_numpy(np.ascontiguousarray(a, np.float32)) for a in arrs]
+            if (i < len(self.ray_tensors) and len(self.ray_tensors[i]) == len(host)
+                    and all(d.numel() == h.numel() for d, h in zip(self.ray_tensors[i], host))):
                 for d, h in zip(self.ray_tensors[i], host):
                     d.copy_(h)
             else:
@@ -170,8 +174,7 @@ class Rig:
                     self.ray_tensors[i] = dev
                 else:
                     self.ray_tensors.append(dev)
-            az, el, tt = self.ray_tensors[i]
-            lids[i] = st.lidar_struct(l, (az.data_ptr(), el.data_ptr(), tt.data_ptr()), keep)
+            lids[i] = st.lidar_struct(l, tuple(d.data_ptr() for d in self.ray_tensors[i]), keep)
         self._cams, self._lids, self._keep = cams, lids, keep
         check(self.lib.splat_rig_set(self.handle, cams if self.n_cam else None, lids if self.n_lid else None,
                                      _stream()), "splat_rig_set")
@@ -265,6 +268,7 @@ class SensorPass:
         self.t_final = torch.empty((max(1, self.n_rays),), **f32)
         self.last = torch.empty((max(1, self.n_rays),), **i32)
         self.median = torch.empty((max(1, self.n_rays),), **f32) if self.has_lidar else None
+        self.los = torch.empty((max(1, self.n_rays),), **f32) if self.has_lidar else None
         self.status = _status_tensor(device)
         self.set_capacity(k_cap)
 
@@ -296,11 +300,12 @@ class SensorPass:
         L.work_cap = self.work_cap
         return L
 
-    def out_struct(self, sensor_done: Optional[torch.Tensor] = None):
+    def out_struct(self, sensor_done: Optional[torch.Tensor] = None, d_los: Optional[torch.Tensor] = None):
         o = st.SplatRenderOut()
         o.feat, o.depth, o.alpha = _ptr(self.feat), _ptr(self.depth), _ptr(self.alpha)
         o.t_final, o.last, o.median = _ptr(self.t_final), _ptr(self.last), _ptr(self.median)
         o.sensor_done = _ptr(sensor_done)
+        o.los, o.d_los = _ptr(self.los), _ptr(d_los)
         return o
 
     # ---- the four calls -------------------------------------------------------------------
@@ -348,13 +353,15 @@ class SensorPass:
                   "splat_rasterize_fwd_camera")
 
     def raster_bwd(self, g: GaussTensors, dF, dD, dA, grads: GaussTensors, support=BOX, stream=None, timer=None,
-                   sensor_done: Optional[torch.Tensor] = None, sensor_grads: Optional[dict] = None):
+                   sensor_done: Optional[torch.Tensor] = None, sensor_grads: Optional[dict] = None,
+                   d_los: Optional[torch.Tensor] = None):
+        """d_los: optional [n_rays] upstream gradient of the lidar line-of-sight sums."""
         gr = _grads_struct(grads, sensor_grads)
         self._time(timer)
         fn = (self.lib.splat_rasterize_bwd if self.batched else
               self.lib.splat_rasterize_bwd_lidar if self.lidar else self.lib.splat_rasterize_bwd_camera)
         check(fn(C.byref(g.struct()), self.rig.handle, self.first, self.count, C.byref(self.proj_struct()),
-                 C.byref(self.lists_struct()), support, C.byref(self.out_struct(sensor_done)), _ptr(dF), _ptr(dD),
+                 C.byref(self.lists_struct()), support, C.byref(self.out_struct(sensor_done, d_los)), _ptr(dF), _ptr(dD),
                  _ptr(dA),
                  C.byref(gr), C.c_void_p(self.ws_ptr), self.ws_bytes, _stream(stream)), "splat_rasterize_bwd")
 
@@ -384,7 +391,8 @@ class SensorPass:
         n = self.n_rays
         return dict(feat=self.feat[:self.n_feat], depth=self.depth[:n], alpha=self.alpha[:n],
                     t_final=self.t_final[:n], last=self.last[:n],
-                    median=None if self.median is None else self.median[:n])
+                    median=None if self.median is None else self.median[:n],
+                    los=None if self.los is None else self.los[:n])
 
     def sensor_slices(self, k: int):
         """(ray slice, feature slice, channels) of the k-th sensor of the call."""

@@ -51,6 +51,7 @@ struct FwdOut {
   unsigned long long* n_pairs;   // evaluated-pair counter, or null
   unsigned long long* n_stopped; // early-stopped ray counter (with n_pairs)
   unsigned long long* sensor_done;  // per-sensor completion clock (atomic max), or null
+  float* los;                       // lidar line-of-sight sums, or null
 };
 
 struct BwdIn {
@@ -66,6 +67,7 @@ struct BwdIn {
   float* dfeat;      // features gradient (atomic part, split lidar tiles)
   unsigned long long* sensor_done;  // per-sensor completion clock (atomic max), or null
   float* d_toff;     // [count] camera time-offset gradients (+=), or null
+  const float* d_los;  // upstream gradient of the lidar line-of-sight sums, or null
 };
 
 // Latency stamp of a finished work item: the sensor's entry rises to the device wall clock.
@@ -103,6 +105,7 @@ struct RayCtx {
   int C;              // channels
   int64_t start, end; // the tile's list range
   bool invalid_bin;   // lidar work item of rays outside every tile
+  float los_thr;      // lidar line-of-sight threshold: measured range - margin (-inf: none)
 };
 
 // Lane setup for one work item: a camera tile (all its pixels) or a chunk of <= 256 rays of a
@@ -140,6 +143,7 @@ __device__ __forceinline__ void setup_ray(const RasterArgs& a, int64_t tile, int
     c.feat_off = (S.feat_base - a.sens[0].feat_base) + pix * S.n_ch;
     c.C = S.n_ch;
     c.invalid_bin = false;
+    c.los_thr = -INFINITY;
   } else {
     int2 rr = a.ray_range[tile];
     int64_t p = (int64_t)pos + tid;
@@ -160,6 +164,7 @@ __device__ __forceinline__ void setup_ray(const RasterArgs& a, int64_t tile, int
     } else {
       c.px = c.py = c.t = 0.f;
     }
+    c.los_thr = (c.valid && S.ray_range) ? S.ray_range[j] - S.los_eps : -INFINITY;
   }
   // the invalid-ray bin (tile == n_tiles) has no Gaussian list: read an in-bounds entry and drop it
   const int2 tr = a.tile_range[(LIDAR && c.invalid_bin) ? 0 : tile];
@@ -227,7 +232,7 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
                                          FwdCount& cnt) {
   RayCtx c;
   setup_ray<LIDAR>(a, tile, pos, c);
-  float T = 1.f, D = 0.f, med = 0.f;
+  float T = 1.f, D = 0.f, med = 0.f, los = 0.f;
   float F[CMAX];
 #pragma unroll
   for (int k = 0; k < CMAX; ++k) F[k] = 0.f;
@@ -274,6 +279,7 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
         F[4 * c4 + 3] = SPLAT_FMA(w, f.w, F[4 * c4 + 3]);
       }
       D = SPLAT_FMA(w, gv, D);
+      if (LIDAR) los += (act && gv < c.los_thr) ? e.alpha : 0.f;   // line-of-sight sum
       if (LIDAR) {
         const bool hit = act && !med_set && Tn < 0.5f;
         med = hit ? gv : med;
@@ -297,6 +303,7 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
   o.t_final[c.ray] = T;
   o.last[c.ray] = last;
   if (LIDAR && o.median) o.median[c.ray] = med;
+  if (LIDAR && o.los) o.los[c.ray] = los;
 }
 
 // plain form: one workgroup per work item (camera: tile = block; lidar: work[block])
@@ -381,7 +388,7 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
   setup_ray<LIDAR>(a, tile, pos, c);
   if (LIDAR && c.invalid_bin) return;    // uniform over the workgroup (not timed)
   const int tid = threadIdx.x, lane = tid & 63;
-  float T = 1.f, Tf = 1.f, dD = 0.f, dA = 0.f, bufD = 0.f;
+  float T = 1.f, Tf = 1.f, dD = 0.f, dA = 0.f, bufD = 0.f, dlos = 0.f;
   float dF[CMAX];
   int last_l = 0;
 #pragma unroll
@@ -391,6 +398,7 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
     last_l = b.last[c.ray];
     dD = b.dD[c.ray];
     dA = b.dA[c.ray];
+    if (LIDAR && b.d_los) dlos = b.d_los[c.ray];
     const float* g = b.dF + c.feat_off;
 #pragma unroll
     for (int k = 0; k < CMAX; ++k)
@@ -460,7 +468,9 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
       const float acc = (fd - S_dot) + (gv - bufD) * dD;
       S_dot = SPLAT_FMA(a_eff, fd - S_dot, S_dot);
       bufD = SPLAT_FMA(a_eff, gv - bufD, bufD);
-      const float dalpha = act ? (T * acc + dA * Tf * ra) : 0.f;
+      // line-of-sight sum: its upstream gradient adds directly to the alpha of Gaussians in front
+      const float dlos_a = (LIDAR && gv < c.los_thr) ? dlos : 0.f;
+      const float dalpha = act ? (T * acc + dA * Tf * ra + dlos_a) : 0.f;
       const float dg = w * dD;
       const float d_oeff = e.clamped ? 0.f : dalpha * e.G;
       const float dsig = e.clamped ? 0.f : -dalpha * e.alpha;
@@ -620,7 +630,7 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
                              hipStream_t s, const KernelTimer& timer) {
   RasterArgs a = make_args(v, g, p, L);
   FwdOut o{out.feat, out.depth, out.alpha, out.t_final, out.last, out.median, st ? &st->n_pairs : nullptr,
-           st ? &st->n_stopped : nullptr, out.sensor_done};
+           st ? &st->n_stopped : nullptr, out.sensor_done, out.los};
   const int cm = cmax_bucket(v.c_max);
   if (v.queue) {
     const int64_t items = L.work_cap;
@@ -672,7 +682,8 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
                              const float* dD, const float* dA, const Workspace& w, float* dfeat, float* d_toff,
                              hipStream_t s, const KernelTimer& timer) {
   RasterArgs a = make_args(v, g, p, L);
-  BwdIn b{saved.t_final, saved.last, dF, dD, dA, w.slots, w.flags, w.rflag, w.g2d, dfeat, saved.sensor_done, d_toff};
+  BwdIn b{saved.t_final, saved.last, dF, dD, dA, w.slots, w.flags, w.rflag, w.g2d, dfeat, saved.sensor_done, d_toff,
+          saved.d_los};
   const int cm = cmax_bucket(v.c_max);
   if (w.stride != slot_stride(cm)) return hipErrorInvalidValue;
   if (v.queue) {

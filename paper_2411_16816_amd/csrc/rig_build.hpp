@@ -66,6 +66,7 @@ inline int build_lidar(const SplatLidar& l, DevSensor& d) {
   if (!(l.az_res > 0.f) || !(l.r_min >= 0.f) || !(l.r_max > l.r_min) || !(l.eps2d >= 0.f) || !(l.t_rs >= 0.f))
     return SPLAT_ERR_INVALID_ARG;
   if (l.elev_bounds == nullptr || l.n_rays < 0) return SPLAT_ERR_INVALID_ARG;
+  if (!(l.los_eps >= 0.f) || !isfinite(l.los_eps)) return SPLAT_ERR_INVALID_ARG;
   if (l.n_rays > 0 && (l.ray_az == nullptr || l.ray_el == nullptr || l.ray_t == nullptr)) return SPLAT_ERR_INVALID_ARG;
   if (l.n_channels < 0 || l.n_channels > SPLAT_MAX_CHANNELS || l.feat_offset < 0) return SPLAT_ERR_INVALID_ARG;
   if (!finite_all(l.R, 9) || !finite_all(l.t, 3) || !finite_all(l.lin_vel, 3) || !finite_all(l.ang_vel, 3))
@@ -97,6 +98,8 @@ inline int build_lidar(const SplatLidar& l, DevSensor& d) {
   d.ray_az = l.ray_az;
   d.ray_el = l.ray_el;
   d.ray_t = l.ray_t;
+  d.ray_range = l.ray_range;
+  d.los_eps = l.los_eps;
   d.n_tiles = l.n_az_tiles * l.n_el_tiles;
   d.n_rays = l.n_rays;
   return SPLAT_OK;

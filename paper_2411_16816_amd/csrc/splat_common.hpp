@@ -44,6 +44,8 @@ struct alignas(16) DevSensor {
   const float* ray_az;
   const float* ray_el;
   const float* ray_t;
+  const float* ray_range;      // measured ranges (line-of-sight sum) or null
+  float los_eps;
   float bounds[SPLAT_MAX_EL_TILES + 1];
 };
 

@@ -39,7 +39,8 @@ class SplatLidar(C.Structure):
                 ("r_max", C.c_float), ("az_res", C.c_float), ("tile_az", C.c_int32),
                 ("n_az_tiles", C.c_int32), ("n_el_tiles", C.c_int32), ("elev_bounds", C.c_void_p),
                 ("n_rays", C.c_int64), ("ray_az", C.c_void_p), ("ray_el", C.c_void_p), ("ray_t", C.c_void_p),
-                ("feat_offset", C.c_int32), ("n_channels", C.c_int32)]
+                ("feat_offset", C.c_int32), ("n_channels", C.c_int32), ("ray_range", C.c_void_p),
+                ("los_eps", C.c_float)]
 
 
 class SplatRigLayout(C.Structure):
@@ -62,7 +63,8 @@ class SplatTileLists(C.Structure):
 
 class SplatRenderOut(C.Structure):
     _fields_ = [("feat", C.c_void_p), ("depth", C.c_void_p), ("alpha", C.c_void_p), ("t_final", C.c_void_p),
-                ("last", C.c_void_p), ("median", C.c_void_p), ("sensor_done", C.c_void_p)]
+                ("last", C.c_void_p), ("median", C.c_void_p), ("sensor_done", C.c_void_p), ("los", C.c_void_p),
+                ("d_los", C.c_void_p)]
 
 
 class SplatGrads(C.Structure):
@@ -107,8 +109,10 @@ def lidar_struct(lid, ray_ptrs=(None, None, None), bounds_keepalive=None) -> Spl
         bounds_keepalive.append(b)
     s.elev_bounds = b.ctypes.data
     s.n_rays = int(lid.n_rays)
-    s.ray_az, s.ray_el, s.ray_t = ray_ptrs
+    s.ray_az, s.ray_el, s.ray_t = ray_ptrs[:3]
     s.feat_offset, s.n_channels = int(lid.feat_offset), int(lid.n_channels)
+    s.ray_range = ray_ptrs[3] if len(ray_ptrs) > 3 else None
+    s.los_eps = float(getattr(lid, "los_eps", 0.8))
     return s
 
 
