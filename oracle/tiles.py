@@ -15,6 +15,10 @@ Lidar (App. A, lidar tiling): N_phi azimuth steps by N_omega channels per tile.
     Omega_high = (the last boundary <= the upper edge) + 1 (clamped to <= M_omega); this is
     our reading of the garbled sentence at the end of App. A's tiling paragraph.
 
+Training-time cap (App. A): `lidar_training_dropped` picks the rays a crowded tile drops, from
+per-ray priorities (the shuffle, an input); pinned by a worked example and by invariants (kept
+count per tile, priorities on either side of the cut, ties by ray index).
+
 `*_f32` functions evaluate the same ranges in IEEE float32 in the exact order the GPU library
 documents (include/splat.h), from the library's own float32 boxes: they are the bit-exact stage
 check, not an independent derivation.  The FP64 functions follow the paper's formulas and are
@@ -181,3 +185,24 @@ def tile_lists(tiles_per_gaussian, depth, valid, n_tiles):
         for t in tiles_per_gaussian[g]:
             lists[t].append(int(g))
     return lists
+
+
+# --------------------------------------------------------------------------------------
+# training-time cap on the rays of a lidar tile (App. A, lidar points to rasterisation points)
+# --------------------------------------------------------------------------------------
+def lidar_training_dropped(az_tile, el_tile, valid, priority, n_az_tiles, cap=256):
+    """During training a tile that receives more than `cap` lidar rays renders a random `cap` of
+    them (the paper shuffles the points each iteration and discards those beyond 256).  The
+    shuffle is an input: one priority per ray; a tile keeps its `cap` rays of smallest
+    (priority, ray index) and drops the rest.  Returns `dropped` [R] bool (False for rays
+    outside every tile).  Plain per-tile loop."""
+    priority = np.asarray(priority)
+    tile = np.asarray(el_tile, np.int64) * int(n_az_tiles) + np.asarray(az_tile, np.int64)
+    valid = np.asarray(valid, bool)
+    dropped = np.zeros(len(priority), bool)
+    for t in np.unique(tile[valid]):
+        members = np.nonzero(valid & (tile == t))[0]
+        order = sorted(members.tolist(), key=lambda r: (int(priority[r]), r))
+        for r in order[cap:]:
+            dropped[r] = True
+    return dropped
