@@ -4,7 +4,9 @@
 Workload (default): a 128-beam x 2048-azimuth spinning lidar (100 ms rolling-shutter sweep,
 15 m/s ego velocity) plus one 1920x1080 rolling-shutter camera at the lidar origin, over 2M
 synthetic Gaussians in a 300 x 300 x 6 m box; forward + backward (projection, binning, depth
-sort, compositing, adjoint) every step.  Inputs are resident in HBM before timing starts.
+sort, compositing, adjoint) every step.  The lidar carries measured ranges, so each step also
+sums the line-of-sight opacities of its rays and back-propagates their upstream gradient.
+Inputs are resident in HBM before timing starts.
 
 Three forms of the same step are timed:
   plain   -- per-sensor calls (project -> bin/sort -> rasterize_fwd -> rasterize_bwd per sensor);
@@ -39,6 +41,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3            # vector FP32, datasheet (packed FMA)
 PEAK_HBM_GBS = 8000.0               # HBM3E, datasheet
 SEED_COMPOSE = 16816 + 11           # seed of the composition workload
+SEED_POINTS = 16816 + 12            # seed of the lidar points-to-rays workload
 # algorithmic FP32 work per evaluated (ray, Gaussian) pair of the forward compositing loop:
 # Delta (6), sigma (9), exp (1), alpha (1), transmittance (2), weight (1), feature and depth
 # blends (2 C + 2), plus the lidar range correction (2) and azimuth reduction (3);
@@ -55,7 +58,7 @@ def parse():
     ap.add_argument("--n", type=int, default=2_000_000, help="Gaussians")
     ap.add_argument("--modes", default="plain,batched,graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compose", action="store_true", help="skip the scene-graph composition measurement")
+    ap.add_argument("--no-compose", action="store_true", help="skip the scene-graph composition and lidar points-to-rays measurements")
     ap.add_argument("--c5", action="store_true",
                     help="instead of the headline step: the 60-sensor sweep workload (3M Gaussians, 48 lidar sweeps "
                          "+ 12 cameras) with per-sensor latency p50/p99 from in-kernel clocks")
@@ -131,22 +134,26 @@ def main():
         Ks = [sp.fit_capacity(G, 1.15) for sp in passes]
         # upstream gradients drawn per sensor; the batched form takes their concatenation, so that
         # every form differentiates the same loss
+        # (dF, dD, dA, d_los): the line-of-sight weight is drawn for lidar rays, zero for pixels
         per_sensor = []
         for k, sensor in enumerate((cam, lid)):
             _, dD, dA = S.upstream_grads(1000 + k, sensor.n_rays, 1)
             dF = np.random.default_rng(1100 + k).normal(size=sensor.n_rays * sensor.n_channels).astype(np.float32)
-            per_sensor.append((dF, dD.reshape(-1), dA.reshape(-1)))
+            dl = (np.random.default_rng(1200 + k).normal(size=sensor.n_rays).astype(np.float32) if k == 1 else
+                  np.zeros(sensor.n_rays, np.float32))
+            per_sensor.append((dF, dD.reshape(-1), dA.reshape(-1), dl))
         if mode == "plain":
             host_ups = per_sensor
         else:
-            host_ups = [tuple(np.concatenate([per_sensor[0][i], per_sensor[1][i]]) for i in range(3))]
+            host_ups = [tuple(np.concatenate([per_sensor[0][i], per_sensor[1][i]]) for i in range(4))]
         ups = [tuple(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev) for a in u) for u in host_ups]
         for sp, u in zip(passes, ups):
-            assert u[0].numel() == sp.n_feat and u[1].numel() == sp.n_rays, "upstream gradient shapes"
+            assert u[0].numel() == sp.n_feat and u[1].numel() == sp.n_rays and u[3].numel() == sp.n_rays, \
+                "upstream gradient shapes"
         grads = B.zeros_like_grads(G)
         pipe = pipe_fwd = None
         if mode == "graph":
-            pipe = B.Pipeline(passes[0], G, B.BOX, grads, *ups[0], zero_grads=False)
+            pipe = B.Pipeline(passes[0], G, B.BOX, grads, *ups[0][:3], zero_grads=False, d_los=ups[0][3])
             pipe_fwd = B.Pipeline(passes[0], G, B.BOX)
 
         def step(events=None):
@@ -162,7 +169,7 @@ def main():
                 if ev: ev["bin_sort"][1].record(stream); ev["raster_fwd"][0].record(stream)
                 sp.raster_fwd(G, timer=ev["k_fwd"] if ev else None)
                 if ev: ev["raster_fwd"][1].record(stream); ev["raster_bwd"][0].record(stream)
-                sp.raster_bwd(G, *ups[k], grads, timer=ev["k_bwd"] if ev else None)
+                sp.raster_bwd(G, *ups[k][:3], grads, timer=ev["k_bwd"] if ev else None, d_los=ups[k][3])
                 if ev: ev["raster_bwd"][1].record(stream)
 
         for sp in passes:
@@ -207,9 +214,10 @@ def main():
             for key in ("feat", "depth", "alpha", "t_final", "last"):
                 snap_out.setdefault(key, []).append(o[key].clone())
         snap_out = {key: torch.cat(v) for key, v in snap_out.items()}
-        # the median is written for lidar rays only
-        snap_out["median_lidar"] = (passes[1].outputs()["median"].clone() if mode == "plain" else
-                                    passes[0].outputs()["median"][passes[0].sensor_slices(1)[0]].clone())
+        # the median and the line-of-sight sum are written for lidar rays only
+        for key in ("median", "los"):
+            snap_out[f"{key}_lidar"] = (passes[1].outputs()[key].clone() if mode == "plain" else
+                                        passes[0].outputs()[key][passes[0].sensor_slices(1)[0]].clone())
         snap_grad = {name: getattr(grads, name).clone() for name in GRAD_FIELDS}
         rays = sum(sp.n_rays for sp in passes)
         names = ["camera", "lidar"] if mode == "plain" else ["both"]
@@ -273,7 +281,8 @@ def main():
         "metric": METRIC, "value": round(R["value"], 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(R["ms"], 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "lidar 128x2048 (100 ms RS, 15 m/s ego) + 1920x1080 RS camera, 2M Gaussians, fwd+bwd",
+        "config": {"workload": "lidar 128x2048 (100 ms RS, 15 m/s ego, line-of-sight sum) + 1920x1080 RS camera, "
+                               "2M Gaussians, fwd+bwd",
                    "mode": "batched" if main_mode != "plain" else "plain",
                    "launch": "hipGraph replay" if main_mode == "graph" else "stream",
                    "gaussians": g.n, "rays_per_step": R["rays"], "tiles": tiles},
@@ -292,6 +301,7 @@ def main():
         out["modes"][m]["step_ms"] = r["step_ms"]
     if not args.no_compose:
         out["compose"] = compose_bench(args, dev)
+        out["points_to_rays"] = points_bench(args, dev, lid)
     agree = mode_agreement(results)
     if agree:
         out["agreement"] = agree
@@ -316,8 +326,8 @@ GRAD_FIELDS = ("means", "log_scales", "quats", "opacities", "velocities", "featu
 
 def mode_agreement(results):
     """Each form against the plain per-sensor calls on the same inputs, after the same warm-up +
-    timed steps: forward outputs must be bit-identical (the median of lidar rays only); the
-    accumulated gradients must agree within 1e-4 (relative norm per field)."""
+    timed steps: forward outputs must be bit-identical (median and line-of-sight sum: lidar rays
+    only); the accumulated gradients must agree within 1e-4 (relative norm per field)."""
     if "plain" not in results:
         return None
     ref = results["plain"]
@@ -367,7 +377,10 @@ def check_parity(passes, rig, g):
             ref = rd.render_sensor(g, sensor, idx)
             ok = ~ref["near"]
             worst = 0.0
-            for a, r in ((F, ref["F"].numpy()), (D, ref["D"].numpy()), (A, ref["A"].numpy())):
+            checks = [(F, ref["F"].numpy()), (D, ref["D"].numpy()), (A, ref["A"].numpy())]
+            if o["los"] is not None and not hasattr(sensor, "fx"):
+                checks.append((o["los"][rs][idx].cpu().numpy(), ref["los"].numpy()))
+            for a, r in checks:
                 a, r = a[ok], r[ok]
                 err = np.abs(a - r) / (1e-5 + 1e-4 * np.abs(r))
                 worst = max(worst, float(err.max()) if err.size else 0.0)
@@ -574,6 +587,51 @@ def compose_bench(args, dev):
             "parity": {"gaussians": 4096, "max_err_over_tol": round(worst, 4), "pass": bool(worst <= 1.0)}}
 
 
+def points_bench(args, dev, lid):
+    """Lidar points to rasterisation rays (splat_lidar_points_to_rays) for one 128 x 2048 sweep and
+    for 64 sweeps in one launch, timed with HIP events around each call on the launching stream,
+    against the HBM roofline (28 B per point: point and time read, azimuth, elevation and range
+    written once)."""
+    import torch
+    from oracle import points as op
+    from paper_2411_16816_amd import binding as B
+    from scenes import synthetic as S
+    out = {"workload": "ego-motion-compensated world points of a 128 x 2048 sweep (100 ms, 15 m/s) -> "
+                       "azimuth / elevation / measured range", "bytes_per_point": 28, "sizes": {}}
+    stream = torch.cuda.current_stream()
+    mk = lambda: torch.cuda.Event(enable_timing=True)
+    worst = 0.0
+    for label, n in (("one_sweep", lid.n_rays), ("64_sweeps", 64 * lid.n_rays)):
+        pts, t = S.lidar_points(SEED_POINTS, n)
+        P, T = torch.from_numpy(pts).to(dev), torch.from_numpy(t).to(dev)
+        o = tuple(torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3))
+        for _ in range(max(1, args.warmup)):
+            B.points_to_rays(P, T, lid.R, lid.t, lid.lin_vel, lid.ang_vel, out=o)
+        ev = [(mk(), mk()) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        for e0, e1 in ev:
+            e0.record(stream)
+            B.points_to_rays(P, T, lid.R, lid.t, lid.lin_vel, lid.ang_vel, out=o)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        sec = float(np.median([a.elapsed_time(b) for a, b in ev])) * 1e-3
+        ach = 28.0 * n / sec / 1e9
+        idx = np.sort(np.random.default_rng(5).choice(n, 4096, replace=False))
+        ref = op.points_to_rays(pts[idx], t[idx], lid.R, lid.t, lid.lin_vel, lid.ang_vel)
+        ii = torch.from_numpy(idx).to(dev)
+        for k, (got, want) in enumerate(zip(o, ref)):
+            a_ = got[ii].double().cpu().numpy()
+            d = np.abs(((a_ - want + np.pi) % (2 * np.pi)) - np.pi) if k == 0 else np.abs(a_ - want)
+            worst = max(worst, float((d / (1e-5 + 1e-4 * np.abs(want))).max()))
+        out["sizes"][label] = {"points": n, "ms": round(sec * 1e3, 4), "achieved_GBs": round(ach, 1),
+                               "frac": round(ach / PEAK_HBM_GBS, 4)}
+        log(f"points_to_rays {label}: {n} points, {sec * 1e3:.4f} ms ({ach:.0f} GB/s)")
+        del P, T, o
+    out["roofline"] = {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS}
+    out["parity"] = {"points": 2 * 4096, "max_err_over_tol": round(worst, 4), "pass": bool(worst <= 1.0)}
+    return out
+
+
 def cpu_baseline(g, cam, lid, n_rays):
     """The FP64 oracle, fwd + bwd (autograd), on a bounded seeded sample of rays per sensor."""
     import torch
@@ -585,7 +643,8 @@ def cpu_baseline(g, cam, lid, n_rays):
     for k, sensor in enumerate((cam, lid)):
         idx = np.sort(rng.choice(sensor.n_rays, size=n_rays, replace=False))
         dF, dD, dA = S.upstream_grads(2000 + k, n_rays, sensor.n_channels)
-        ogr.reference_grads(g, sensor, idx, dF, dD, dA)
+        dlos = np.random.default_rng(2100 + k).normal(size=n_rays) if k == 1 else None
+        ogr.reference_grads(g, sensor, idx, dF, dD, dA, dlos=dlos)
         total_rays += n_rays
     dt = time.time() - t0
     return {"value": round(total_rays / dt / 1e6, 8), "unit": "Mrays/s", "cores": torch.get_num_threads(),

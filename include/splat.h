@@ -130,6 +130,15 @@ typedef struct SplatLidar {
   const float* ray_range;    /* device [n_rays] measured range of each ray, or NULL: enables the
                                 line-of-sight sum (training-details appendix, loss term L_los)  */
   float los_eps;             /* line-of-sight margin [m] (0.8 in the paper), >= 0               */
+  const uint16_t* ray_priority;  /* device [n_rays] or NULL.  Non-NULL selects the training-time
+                                cap of App. A: a tile renders at most SPLAT_RAYS_PER_ITEM rays,
+                                those of smallest priority (ties: smaller ray index); its other
+                                rays are dropped (SplatRenderOut.dropped): they get the outputs of
+                                a ray that meets no Gaussian and their upstream gradients are
+                                ignored.  Fresh uniform priorities each step shuffle the rays.
+                                NULL: every ray is rendered (a crowded tile takes several work
+                                items).  A call with any such lidar supports at most 65535 lidar
+                                tiles (SPLAT_ERR_UNSUPPORTED otherwise).                        */
 } SplatLidar;
 
 /* Opaque rig: a device-resident table of sensors (cameras first, then lidars). */
@@ -201,6 +210,9 @@ typedef struct SplatRenderOut {
                        (0 without ray_range; camera rays: not written)                         */
   const float* d_los;  /* [n_rays] or NULL: upstream gradient of `los`, read by the adjoint from
                        its `saved` struct (NULL = zero)                                          */
+  uint8_t* dropped; /* [n_rays] or NULL: 1 for lidar rays dropped by the training-time cap
+                       (SplatLidar.ray_priority), else 0; written by the forward for lidar rays
+                       (camera rays: not written)                                              */
 } SplatRenderOut;
 
 /* Gradient accumulators (+=), device arrays shaped like SplatGaussians. */
@@ -431,6 +443,25 @@ int splat_compose_bwd(int64_t n, const float* means, const float* quats, const i
                       const SplatActors* actors, const float* d_means_w, const float* d_quats_w,
                       const float* d_vel_w, float* d_means, float* d_quats, float* d_velocities,
                       const SplatActorGrads* d_actors, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- lidar points to rasterisation rays (App. A, "Lidar points to rasterization points") ----
+ * A sweep's n points arrive with the ego motion compensated: world coordinates as if the whole
+ * sweep were captured at its reference time (the middle of the sweep), with each point's capture
+ * time relative to it in `times`.  Each point is expressed in the sensor frame at the reference
+ * time, x_l = R x_w + t (R row-major, as in SplatLidar), moved back to the sensor at its own
+ * capture time under the sensor's constant linear and angular velocity (sensor frame, as in
+ * SplatLidar): x_cap = x_l + time (-ang_vel x x_l - lin_vel), and converted to spherical
+ * coordinates: ray_az = atan2(y, x) in [0, 2 pi), ray_el = asin(z / r), ray_range = r = |x_cap|.
+ * With `times` as the ray times, the outputs are a SplatLidar's ray_az / ray_el / ray_range.
+ * A point at the sensor origin gets azimuth and elevation 0; a non-finite point gets NaN
+ * outputs (rays outside every tile, counted in SplatStatus.n_rays_invalid).
+ * points: device [n,3]; times, ray_az, ray_el: device [n]; ray_range: device [n] or NULL;
+ * R [9], t [3]: HOST arrays (required); lin_vel, ang_vel: HOST [3] or NULL (zero).  Outputs
+ * must not overlap the inputs.  n = 0 is a no-op; n < 0 or a missing required pointer gives
+ * SPLAT_ERR_INVALID_ARG.  Stream-ordered, allocates nothing. */
+int splat_lidar_points_to_rays(int64_t n, const float* points, const float* times, const float* R,
+                               const float* t, const float* lin_vel, const float* ang_vel, float* ray_az,
+                               float* ray_el, float* ray_range, void* stream);
 
 #ifdef __cplusplus
 }

@@ -63,6 +63,7 @@ def _declare(lib):
         "splat_compose": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "splat_compose_workspace_bytes": (C.c_size_t, [i32]),
         "splat_compose_bwd": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+        "splat_lidar_points_to_rays": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -160,21 +161,25 @@ class Rig:
             cams[i] = st.camera_struct(c)
         lids = (st.SplatLidar * max(1, self.n_lid))()
         for i, l in enumerate(self.lidars):
-            arrs = (l.ray_az, l.ray_el, l.ray_t)
+            f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32))
+            host = {"az": f32(l.ray_az), "el": f32(l.ray_el), "t": f32(l.ray_t)}
             if getattr(l, "ray_range", None) is not None:   # measured ranges: the line-of-sight sum
-                arrs = arrs + (l.ray_range,)
-            host = [torch.from_numpy(np.ascontiguousarray(a, np.float32)) for a in arrs]
-            if (i < len(self.ray_tensors) and len(self.ray_tensors[i]) == len(host)
-                    and all(d.numel() == h.numel() for d, h in zip(self.ray_tensors[i], host))):
-                for d, h in zip(self.ray_tensors[i], host):
-                    d.copy_(h)
+                host["range"] = f32(l.ray_range)
+            if getattr(l, "ray_priority", None) is not None:   # the training-time cap
+                # uint16 priorities travel as int16 bit patterns (torch has no uint16 copies)
+                host["priority"] = torch.from_numpy(np.ascontiguousarray(l.ray_priority, np.uint16).view(np.int16))
+            old = self.ray_tensors[i] if i < len(self.ray_tensors) else None
+            if (old is not None and old.keys() == host.keys()
+                    and all(old[k].numel() == h.numel() for k, h in host.items())):
+                for k, h in host.items():
+                    old[k].copy_(h)
             else:
-                dev = tuple(h.to(self.device) for h in host)
-                if i < len(self.ray_tensors):
+                dev = {k: h.to(self.device) for k, h in host.items()}
+                if old is not None:
                     self.ray_tensors[i] = dev
                 else:
                     self.ray_tensors.append(dev)
-            lids[i] = st.lidar_struct(l, tuple(d.data_ptr() for d in self.ray_tensors[i]), keep)
+            lids[i] = st.lidar_struct(l, {k: d.data_ptr() for k, d in self.ray_tensors[i].items()}, keep)
         self._cams, self._lids, self._keep = cams, lids, keep
         check(self.lib.splat_rig_set(self.handle, cams if self.n_cam else None, lids if self.n_lid else None,
                                      _stream()), "splat_rig_set")
@@ -269,6 +274,8 @@ class SensorPass:
         self.last = torch.empty((max(1, self.n_rays),), **i32)
         self.median = torch.empty((max(1, self.n_rays),), **f32) if self.has_lidar else None
         self.los = torch.empty((max(1, self.n_rays),), **f32) if self.has_lidar else None
+        self.dropped = torch.empty((max(1, self.n_rays),), dtype=torch.uint8, device=device) if self.has_lidar \
+            else None
         self.status = _status_tensor(device)
         self.set_capacity(k_cap)
 
@@ -306,6 +313,7 @@ class SensorPass:
         o.t_final, o.last, o.median = _ptr(self.t_final), _ptr(self.last), _ptr(self.median)
         o.sensor_done = _ptr(sensor_done)
         o.los, o.d_los = _ptr(self.los), _ptr(d_los)
+        o.dropped = _ptr(self.dropped)
         return o
 
     # ---- the four calls -------------------------------------------------------------------
@@ -392,7 +400,8 @@ class SensorPass:
         return dict(feat=self.feat[:self.n_feat], depth=self.depth[:n], alpha=self.alpha[:n],
                     t_final=self.t_final[:n], last=self.last[:n],
                     median=None if self.median is None else self.median[:n],
-                    los=None if self.los is None else self.los[:n])
+                    los=None if self.los is None else self.los[:n],
+                    dropped=None if self.dropped is None else self.dropped[:n])
 
     def sensor_slices(self, k: int):
         """(ray slice, feature slice, channels) of the k-th sensor of the call."""
@@ -420,14 +429,14 @@ class Pipeline:
     named here are captured by address and kept alive by this object; `run` replays the step."""
 
     def __init__(self, sp: SensorPass, g: GaussTensors, support=BOX, grads: Optional[GaussTensors] = None,
-                 dF=None, dD=None, dA=None, zero_grads: bool = True):
+                 dF=None, dD=None, dA=None, zero_grads: bool = True, d_los=None):
         if not sp.batched:
             raise ValueError("pipelines run the batched form")
         self.lib, self.sp, self.g = sp.lib, sp, g
-        self.keep = (grads, dF, dD, dA)
+        self.keep = (grads, dF, dD, dA, d_los)
         step = st.SplatStep()
         step.gaussians = g.struct()
-        step.proj, step.lists, step.out = sp.proj_struct(), sp.lists_struct(), sp.out_struct()
+        step.proj, step.lists, step.out = sp.proj_struct(), sp.lists_struct(), sp.out_struct(d_los=d_los)
         step.support = support
         step.flags = 0
         if grads is not None:
@@ -602,3 +611,32 @@ def device_clock_hz() -> int:
     hz = C.c_int64()
     check(load().splat_device_clock_hz(C.byref(hz)), "splat_device_clock_hz")
     return int(hz.value)
+
+
+# ----------------------------------------------------------------------------------------
+# lidar points to rasterisation rays (splat_lidar_points_to_rays)
+# ----------------------------------------------------------------------------------------
+def points_to_rays(points: torch.Tensor, times: torch.Tensor, R, t, lin_vel=None, ang_vel=None,
+                   with_range: bool = True, out=None, stream=None):
+    """World points [n,3] (ego motion compensated) and capture times [n] -> (ray_az, ray_el,
+    ray_range or None), float32 device tensors.  R (3x3 or 9), t, lin_vel, ang_vel: host arrays of
+    the lidar (x_l = R x_w + t; velocities in the sensor frame).  `out` = (az, el, range) writes
+    into existing tensors."""
+    lib = load()
+    n = int(points.shape[0])
+    if points.dtype != torch.float32 or times.dtype != torch.float32 or not points.is_contiguous() \
+            or not times.is_contiguous() or tuple(points.shape) != (n, 3) or times.numel() != n:
+        raise ValueError("points [n,3] and times [n] must be contiguous float32")
+    if out is None:
+        az, el = torch.empty(n, dtype=torch.float32, device=points.device), torch.empty(n, dtype=torch.float32,
+                                                                                       device=points.device)
+        rg = torch.empty(n, dtype=torch.float32, device=points.device) if with_range else None
+    else:
+        az, el, rg = out
+    h = lambda a, k: None if a is None else (C.c_float * k)(*np.asarray(a, np.float32).reshape(-1)[:k])
+    Rh, th, vh, wh = h(R, 9), h(t, 3), h(lin_vel, 3), h(ang_vel, 3)
+    check(lib.splat_lidar_points_to_rays(n, _ptr(points), _ptr(times), C.cast(Rh, C.c_void_p), C.cast(th, C.c_void_p),
+                                         None if vh is None else C.cast(vh, C.c_void_p),
+                                         None if wh is None else C.cast(wh, C.c_void_p), _ptr(az), _ptr(el), _ptr(rg),
+                                         _stream(stream)), "splat_lidar_points_to_rays")
+    return az, el, rg

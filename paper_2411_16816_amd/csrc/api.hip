@@ -175,6 +175,7 @@ static int make_view(const SplatRig* r, int32_t first, int32_t count, int kind, 
   v.n_rays = 0;
   v.c_max = 0;
   v.has_lidar = false;
+  v.ray_cap = false;
   v.lidar_ray0 = -1;
   v.lidar_tile0 = 0;
   for (int i = 0; i < count; ++i) {
@@ -185,6 +186,7 @@ static int make_view(const SplatRig* r, int32_t first, int32_t count, int kind, 
       v.lidar_ray0 = v.n_rays;
       v.lidar_tile0 = v.n_tiles;
     }
+    v.ray_cap = v.ray_cap || (d.kind == kLidar && d.ray_prio != nullptr);
     v.n_tiles += d.n_tiles;
     v.n_rays += d.n_rays;
     v.c_max = d.n_ch > v.c_max ? d.n_ch : v.c_max;
@@ -197,6 +199,8 @@ static int make_view(const SplatRig* r, int32_t first, int32_t count, int kind, 
   v.queue = (kind < 0);
   v.n_cu = r->n_cu;
   if ((int64_t)count * n_gauss >= ((int64_t)1 << 32)) return SPLAT_ERR_UNSUPPORTED;
+  // the capped ray sort keys are (lidar bin, 16-bit priority) in 32 bits
+  if (v.ray_cap && v.n_tiles + 1 - v.lidar_tile0 > 65536) return SPLAT_ERR_UNSUPPORTED;
   return SPLAT_OK;
 }
 

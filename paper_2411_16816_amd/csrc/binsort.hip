@@ -654,7 +654,8 @@ __device__ __forceinline__ int sensor_of_ray(const DevSensor* sens, int count, i
 
 // lidar rays [r0, r0 + n) of the call -> (key, ray id) pairs at [0, n); key = ((bin - t0) <<
 // cell_bits) | cell, bin = the ray's tile (n_tiles: outside every tile), t0 = the call's first
-// lidar tile, cell = ray_cell_code inside the tile (0 outside)
+// lidar tile, cell = ray_cell_code inside the tile (0 outside), or the ray's 16-bit priority
+// when its lidar caps the rays per tile (training time)
 __global__ void k_ray_keys(const DevSensor* __restrict__ sens, int count, int64_t r0, int64_t n, int64_t n_tiles,
                            int64_t t0, int cell_bits, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                            SplatStatus* st) {
@@ -672,7 +673,8 @@ __global__ void k_ray_keys(const DevSensor* __restrict__ sens, int count, int64_
     int a = floor_div_clamped(az, S.az_w) % S.m_az;
     int e = count_le(S, el) - 1;
     tile = (uint32_t)(local_tile_base(sens, s) + (int64_t)e * S.m_az + a);
-    cell = ray_cell_code(u, el, S.bounds[e], S.bounds[e + 1], cell_bits);
+    // training-time cap: the ray's priority orders the tile (its first rays are the ones kept)
+    cell = S.ray_prio ? (uint32_t)S.ray_prio[j] : ray_cell_code(u, el, S.bounds[e], S.bounds[e + 1], cell_bits);
   } else if (st) {
     atomicAdd(&st->n_rays_invalid, 1u);
   }
@@ -870,9 +872,10 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
     if (nr > 0) {
       // rays grouped by tile, and inside a tile in Z-order of their cells (compact work items);
       // the cell code fills the unused bits of the bin's last radix digit, so it adds no pass
+      // (under the training-time cap 16 bits of priority take its place, and add passes)
       const int64_t t0 = v.lidar_tile0;
       const int bin_bits = bits_for(bins - t0);
-      const int cell_bits = ray_cell_bits(bin_bits);
+      const int cell_bits = v.ray_cap ? 16 : ray_cell_bits(bin_bits);   // make_view keeps bin_bits <= 16
       hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)div_up(nr, 256)), dim3(256), 0, s, v.sens, v.count, r0, nr,
                          v.n_tiles, t0, cell_bits, w.rkeys[0], w.rvals[0], st);
       uint32_t* rk[2] = {w.rkeys[0], w.rkeys[1]};

@@ -48,6 +48,7 @@ struct CallView {
   bool lidar;              // plain lidar call (all sensors are lidars)
   bool queue;              // batched form: any mix of sensors, persistent queue rasterisers
   bool has_lidar;          // at least one lidar in the call
+  bool ray_cap;            // a lidar of the call renders at most SPLAT_RAYS_PER_ITEM rays per tile
   int64_t lidar_ray0;      // local id of the first lidar ray (cameras precede lidars in a rig)
   int64_t lidar_tile0;     // local id of the first lidar tile
   int c_max;               // max n_channels over the call

@@ -52,6 +52,7 @@ struct FwdOut {
   unsigned long long* n_stopped; // early-stopped ray counter (with n_pairs)
   unsigned long long* sensor_done;  // per-sensor completion clock (atomic max), or null
   float* los;                       // lidar line-of-sight sums, or null
+  uint8_t* dropped;                 // lidar rays dropped by the training-time cap, or null
 };
 
 struct BwdIn {
@@ -106,6 +107,7 @@ struct RayCtx {
   int64_t start, end; // the tile's list range
   bool invalid_bin;   // lidar work item of rays outside every tile
   float los_thr;      // lidar line-of-sight threshold: measured range - margin (-inf: none)
+  bool dropped;       // lidar ray dropped by the training-time cap (renders nothing)
 };
 
 // Lane setup for one work item: a camera tile (all its pixels) or a chunk of <= 256 rays of a
@@ -144,6 +146,7 @@ __device__ __forceinline__ void setup_ray(const RasterArgs& a, int64_t tile, int
     c.C = S.n_ch;
     c.invalid_bin = false;
     c.los_thr = -INFINITY;
+    c.dropped = false;
   } else {
     int2 rr = a.ray_range[tile];
     int64_t p = (int64_t)pos + tid;
@@ -165,11 +168,16 @@ __device__ __forceinline__ void setup_ray(const RasterArgs& a, int64_t tile, int
       c.px = c.py = c.t = 0.f;
     }
     c.los_thr = (c.valid && S.ray_range) ? S.ray_range[j] - S.los_eps : -INFINITY;
+    // training-time cap (App. A): a tile's rays past the first work item (its first
+    // SPLAT_RAYS_PER_ITEM rays in priority order) are dropped; uniform over the work item
+    c.dropped = S.ray_prio != nullptr && !c.invalid_bin && (int64_t)pos - rr.x >= SPLAT_RAYS_PER_ITEM;
   }
-  // the invalid-ray bin (tile == n_tiles) has no Gaussian list: read an in-bounds entry and drop it
+  // the invalid-ray bin (tile == n_tiles) has no Gaussian list: read an in-bounds entry and drop
+  // it; a work item of dropped rays renders an empty list
+  const bool empty = LIDAR && (c.invalid_bin || c.dropped);
   const int2 tr = a.tile_range[(LIDAR && c.invalid_bin) ? 0 : tile];
-  c.start = (LIDAR && c.invalid_bin) ? 0 : tr.x;
-  c.end = (LIDAR && c.invalid_bin) ? 0 : tr.y;
+  c.start = empty ? 0 : tr.x;
+  c.end = empty ? 0 : tr.y;
 }
 
 template <int CMAX>
@@ -304,6 +312,7 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
   o.last[c.ray] = last;
   if (LIDAR && o.median) o.median[c.ray] = med;
   if (LIDAR && o.los) o.los[c.ray] = los;
+  if (LIDAR && o.dropped) o.dropped[c.ray] = c.dropped ? 1 : 0;
 }
 
 // plain form: one workgroup per work item (camera: tile = block; lidar: work[block])
@@ -545,8 +554,11 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(RasterArgs a, BwdIn b) {
   }
 }
 
+// at least 4 waves per SIMD (at most 128 VGPRs): the register allocator otherwise drifts above
+// that bound as the item code grows, and the lost occupancy costs more than it saves
 template <int CMAX, bool TILE>
-__global__ __launch_bounds__(kBlock) void k_raster_bwd_queue(RasterArgs a, BwdIn b, int32_t* counter) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void k_raster_bwd_queue(RasterArgs a, BwdIn b, int32_t* counter) {
   __shared__ BwdSmem<CMAX> sm;
   __shared__ int s_slot;
   const int n_items = a.n_work[0];
@@ -630,7 +642,8 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
                              hipStream_t s, const KernelTimer& timer) {
   RasterArgs a = make_args(v, g, p, L);
   FwdOut o{out.feat, out.depth, out.alpha, out.t_final, out.last, out.median, st ? &st->n_pairs : nullptr,
-           st ? &st->n_stopped : nullptr, out.sensor_done, out.los};
+           st ? &st->n_stopped : nullptr, out.sensor_done, out.los,
+           out.dropped};
   const int cm = cmax_bucket(v.c_max);
   if (v.queue) {
     const int64_t items = L.work_cap;

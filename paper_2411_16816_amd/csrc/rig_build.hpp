@@ -100,6 +100,7 @@ inline int build_lidar(const SplatLidar& l, DevSensor& d) {
   d.ray_t = l.ray_t;
   d.ray_range = l.ray_range;
   d.los_eps = l.los_eps;
+  d.ray_prio = l.ray_priority;
   d.n_tiles = l.n_az_tiles * l.n_el_tiles;
   d.n_rays = l.n_rays;
   return SPLAT_OK;

@@ -45,6 +45,7 @@ struct alignas(16) DevSensor {
   const float* ray_el;
   const float* ray_t;
   const float* ray_range;      // measured ranges (line-of-sight sum) or null
+  const uint16_t* ray_prio;    // training-time cap: per-ray priorities, or null (render every ray)
   float los_eps;
   float bounds[SPLAT_MAX_EL_TILES + 1];
 };

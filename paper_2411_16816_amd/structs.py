@@ -40,7 +40,7 @@ class SplatLidar(C.Structure):
                 ("n_az_tiles", C.c_int32), ("n_el_tiles", C.c_int32), ("elev_bounds", C.c_void_p),
                 ("n_rays", C.c_int64), ("ray_az", C.c_void_p), ("ray_el", C.c_void_p), ("ray_t", C.c_void_p),
                 ("feat_offset", C.c_int32), ("n_channels", C.c_int32), ("ray_range", C.c_void_p),
-                ("los_eps", C.c_float)]
+                ("los_eps", C.c_float), ("ray_priority", C.c_void_p)]
 
 
 class SplatRigLayout(C.Structure):
@@ -64,7 +64,7 @@ class SplatTileLists(C.Structure):
 class SplatRenderOut(C.Structure):
     _fields_ = [("feat", C.c_void_p), ("depth", C.c_void_p), ("alpha", C.c_void_p), ("t_final", C.c_void_p),
                 ("last", C.c_void_p), ("median", C.c_void_p), ("sensor_done", C.c_void_p), ("los", C.c_void_p),
-                ("d_los", C.c_void_p)]
+                ("d_los", C.c_void_p), ("dropped", C.c_void_p)]
 
 
 class SplatGrads(C.Structure):
@@ -95,7 +95,9 @@ def camera_struct(cam) -> SplatCamera:
 
 
 def lidar_struct(lid, ray_ptrs=(None, None, None), bounds_keepalive=None) -> SplatLidar:
-    """`ray_ptrs` are device pointers (ints) of the azimuth, elevation and time arrays."""
+    """`ray_ptrs` are device pointers (ints) of the azimuth, elevation and time arrays, optionally
+    followed by the measured ranges; or a dict with keys az, el, t and optionally range and
+    priority (the training-time cap)."""
     s = SplatLidar()
     s.R = _arr(C.c_float, 9, lid.R)
     s.t = _arr(C.c_float, 3, lid.t)
@@ -109,9 +111,13 @@ def lidar_struct(lid, ray_ptrs=(None, None, None), bounds_keepalive=None) -> Spl
         bounds_keepalive.append(b)
     s.elev_bounds = b.ctypes.data
     s.n_rays = int(lid.n_rays)
-    s.ray_az, s.ray_el, s.ray_t = ray_ptrs[:3]
+    if isinstance(ray_ptrs, dict):
+        s.ray_az, s.ray_el, s.ray_t = ray_ptrs["az"], ray_ptrs["el"], ray_ptrs["t"]
+        s.ray_range, s.ray_priority = ray_ptrs.get("range"), ray_ptrs.get("priority")
+    else:
+        s.ray_az, s.ray_el, s.ray_t = ray_ptrs[:3]
+        s.ray_range = ray_ptrs[3] if len(ray_ptrs) > 3 else None
     s.feat_offset, s.n_channels = int(lid.feat_offset), int(lid.n_channels)
-    s.ray_range = ray_ptrs[3] if len(ray_ptrs) > 3 else None
     s.los_eps = float(getattr(lid, "los_eps", 0.8))
     return s
 

@@ -117,6 +117,7 @@ class Lidar:
     n_channels: int = 0
     ray_range: Optional[np.ndarray] = None   # [R] f32 measured range of each ray, or None
     los_eps: float = 0.8      # line-of-sight margin [m]
+    ray_priority: Optional[np.ndarray] = None   # [R] uint16 training-time cap priorities, or None
 
     @property
     def n_rays(self) -> int:
@@ -353,12 +354,30 @@ def config_5(seed: int = SEED_BASE + 5, n: int = 3_000_000) -> Scene:
     return Scene("C5_batched_sweep", g, cams, lidars, seed)
 
 
+def measured_ranges(rng, n_rays: int, lo: float = 2.0, hi: float = 100.0) -> np.ndarray:
+    """Stand-in for the ranges a lidar sweep measures: log-uniform in [lo, hi] m (returns are
+    denser near the sensor), one per ray, float32."""
+    return np.exp(rng.uniform(math.log(lo), math.log(hi), n_rays)).astype(np.float32)
+
+
+def lidar_points(seed: int, n: int, t_sweep: float = 0.1):
+    """Stand-in for a sweep's ego-motion-compensated points: world positions uniform in config 3's
+    300 x 300 x 6 m box and capture times uniform over the sweep, relative to its middle
+    (float32 [n,3], [n])."""
+    rng = _rng(seed)
+    pts = uniform_box(rng, n, (-150, -150, -3), (150, 150, 3)).astype(np.float32)
+    t = rng.uniform(-0.5 * t_sweep, 0.5 * t_sweep, n).astype(np.float32)
+    return pts, t
+
+
 def headline(seed: int = SEED_BASE + 3, n: int = 2_000_000) -> Scene:
     """Headline workload: the 128-beam x 2048-azimuth lidar of config 3 plus one 1920x1080
     rolling-shutter camera at the lidar origin looking +x, over config 3's 2M Gaussians.
-    The camera blends all 16 feature columns, the lidar columns 3..10."""
+    The camera blends all 16 feature columns, the lidar columns 3..10; the lidar carries
+    measured ranges (`measured_ranges`), so a training step includes the line-of-sight sum."""
     sc = config_3(seed, n)
     lid = sc.lidars[0]
+    lid = replace(lid, ray_range=measured_ranges(_rng(seed + 100), lid.n_rays))
     cam = make_camera((0, 0, 0), 0.0, 1920, 1080, 1500.0, t_rs=0.03,
                       ego_vel_world=(15.0, 0.0, 0.0), feat_offset=0, n_channels=16)
     return Scene("H_lidar128x2048_cam1080p", sc.gaussians, [cam], [lid], seed)

@@ -1,0 +1,171 @@
+"""Training-time lidar ray cap (SplatLidar.ray_priority; App. A: a tile that receives more than
+256 rays renders a random 256 of them during training) through the C ABI against the oracle:
+the dropped set bit-exact (oracle/tiles.py on the library's float32 ray tiles), kept rays within
+1e-4 relative / 1e-5 absolute of the FP64 rendering, dropped rays with the outputs of a ray that
+meets nothing, and gradients within 1e-3 relative of the oracle's over the kept rays only;
+per-sensor and batched with a camera and an uncapped lidar."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import geometry as geo
+from oracle import grad as ogr
+from oracle import render as rd
+from oracle import tiles as ot
+from scenes import synthetic as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _binding():
+    from paper_2411_16816_amd import binding
+    binding.load()
+    return binding
+
+
+def _scene(seed):
+    rng = np.random.default_rng(seed)
+    n = 500
+    mu = np.stack([rng.uniform(-14, 14, n), rng.uniform(-14, 14, n), rng.uniform(-1.5, 1.5, n)], 1)
+    return S.random_gaussians(rng, mu, 8, moving_frac=0.4, log_scale_mean=-0.6)
+
+
+def _lidar(seed, capped=True, tile_az=64):
+    """16 beams x 1024 azimuths in tiles of 64 x 8 rays: 512 rays per tile, so a capped tile
+    drops half of them."""
+    lid = S.make_lidar((0, 0, 0), 0.0, 16, -15.0, 15.0, 1024, tile_az=tile_az, tile_el=8, t_sweep=0.1,
+                       ego_vel_world=(10.0, 1.0, 0), ego_yaw_rate=0.2, n_channels=8)
+    rng = np.random.default_rng(seed)
+    lid.ray_range = rng.uniform(0.5, 16.0, lid.n_rays).astype(np.float32)
+    if capped:
+        lid.ray_priority = rng.integers(0, 1 << 16, lid.n_rays).astype(np.uint16)
+    return lid
+
+
+def _dropped_oracle(lid):
+    a, e, v = ot.lidar_ray_tiles_f32(lid.ray_az, lid.ray_el, lid)
+    return ot.lidar_training_dropped(a, e, v, lid.ray_priority, lid.n_az_tiles, cap=256)
+
+
+def _check_forward(o, rs, lid, g):
+    got_drop = o["dropped"][rs].cpu().numpy().astype(bool)
+    want = _dropped_oracle(lid) if lid.ray_priority is not None else np.zeros(lid.n_rays, bool)
+    np.testing.assert_array_equal(got_drop, want)
+    kept = np.nonzero(~want)[0]
+    ref = rd.render_sensor(g, lid, kept)
+    ok = ~ref["near"]
+    assert ok.mean() > 0.9
+    for key, rkey in (("alpha", "A"), ("depth", "D"), ("los", "los")):
+        a = o[key][rs].cpu().numpy().astype(np.float64)[kept]
+        r = ref[rkey].numpy()
+        err = np.abs(a[ok] - r[ok]) / (1e-5 + 1e-4 * np.abs(r[ok]))
+        assert err.max() <= 1.0, (key, float(err.max()))
+    d = np.nonzero(want)[0]
+    if len(d):
+        for key, val in (("alpha", 0.0), ("depth", 0.0), ("los", 0.0), ("t_final", 1.0), ("last", 0)):
+            assert np.all(o[key][rs].cpu().numpy()[d] == val), key
+    return want, ref
+
+
+def test_cap_forward_single_lidar():
+    b = _binding()
+    g = _scene(31)
+    lid = _lidar(3)
+    print("[cap] forward single lidar", flush=True)
+    rig = b.Rig([], [lid])
+    G = b.GaussTensors.from_numpy(g)
+    sp = b.SensorPass(rig, 0, 1, g.n, 1)
+    sp.fit_capacity(G)
+    sp.render(G)
+    torch.cuda.synchronize()
+    want, _ = _check_forward(sp.outputs(), slice(0, lid.n_rays), lid, g)
+    assert 0.3 < want.mean() < 0.6
+    # new priorities (a new shuffle) pick a different subset of the same size
+    lid2 = dataclasses.replace(lid, ray_priority=np.random.default_rng(99).integers(0, 1 << 16, lid.n_rays)
+                               .astype(np.uint16))
+    rig.update(lidars=[lid2])
+    sp.render(G)
+    torch.cuda.synchronize()
+    want2, _ = _check_forward(sp.outputs(), slice(0, lid.n_rays), lid2, g)
+    assert want2.sum() == want.sum() and (want2 != want).any()
+    # without priorities every ray is rendered
+    rig.update(lidars=[dataclasses.replace(lid, ray_priority=None)])
+    sp.render(G)
+    torch.cuda.synchronize()
+    assert int(sp.outputs()["dropped"].sum()) == 0
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_cap_gradients_mixed_rig(batched):
+    """A camera, a capped lidar and an uncapped one: forward per sensor and the Gaussian
+    gradients of a loss over every ray (line-of-sight term included) against the oracle's
+    gradients over the rays each sensor actually renders."""
+    b = _binding()
+    g = _scene(32)
+    cam = S.make_camera((0, 0, 0), 0.0, 64, 48, 60.0, t_rs=0.04, ego_vel_world=(6.0, 0.5, 0), n_channels=8)
+    lids = [_lidar(4, capped=True), _lidar(5, capped=False, tile_az=32)]
+    print(f"[cap] gradients batched={batched}", flush=True)
+    G = b.GaussTensors.from_numpy(g)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32).reshape(-1)).cuda()
+    sensors = [cam] + lids
+    rig = b.Rig([cam], lids)
+    if batched:
+        passes = [(b.SensorPass(rig, 0, 3, g.n, 1, batched=True), [0, 1, 2])]
+    else:
+        passes = [(b.SensorPass(rig, k, 1, g.n, 1), [k]) for k in range(3)]
+    # upstream gradients; rays whose oracle decisions are within float32 reach carry none
+    ups, refs = [], []
+    for k, s in enumerate(sensors):
+        up = np.random.default_rng(70 + k)
+        R, C = s.n_rays, s.n_channels
+        dF, dD, dA = up.normal(size=(R, C)), 0.1 * up.normal(size=R), up.normal(size=R)
+        dl = up.normal(size=R) if k > 0 else np.zeros(R)
+        drop = _dropped_oracle(s) if getattr(s, "ray_priority", None) is not None else np.zeros(R, bool)
+        rendered = np.nonzero(~drop)[0]
+        _, out = ogr.reference_grads(g, s, rendered, dF[rendered], dD[rendered], dA[rendered],
+                                     dlos=dl[rendered] if k > 0 else None)
+        keep = np.zeros(R, bool)
+        keep[rendered[~out["near"]]] = True
+        # dropped rays keep their (ignored) upstream gradient: the library must not use it
+        mask = keep | drop
+        dF, dD, dA, dl = dF * mask[:, None], dD * mask, dA * mask, dl * mask
+        ref, _ = ogr.reference_grads(g, s, rendered, dF[rendered], dD[rendered], dA[rendered],
+                                     dlos=dl[rendered] if k > 0 else None)
+        ups.append((dF, dD, dA, dl))
+        refs.append(ref)
+    got = []
+    for sp, ks in passes:
+        sp.fit_capacity(G)
+        sp.render(G)
+        torch.cuda.synchronize()
+        o = sp.outputs()
+        for j, k in enumerate(ks):
+            if k > 0:
+                _check_forward(o, sp.sensor_slices(j)[0], sensors[k], g)
+        cat = lambda i: np.concatenate([ups[k][i].reshape(-1) for k in ks])
+        grads = b.zeros_like_grads(G)
+        sp.raster_bwd(G, t(cat(0)), t(cat(1)), t(cat(2)), grads, d_los=t(cat(3)))
+        torch.cuda.synchronize()
+        got.append(grads)
+    for name in geo.Params.names:
+        gg = sum(getattr(gr, name).cpu().numpy().astype(np.float64) for gr in got)
+        rr = sum(r[name] for r in refs)
+        nrm = np.linalg.norm(rr)
+        assert nrm > 0, name
+        assert np.linalg.norm(gg - rr) / nrm <= 1e-3, (name, np.linalg.norm(gg - rr) / nrm)
+
+
+def test_cap_rejects_too_many_tiles():
+    """Capped ray keys hold the lidar bin in 16 bits: a call with more than 65535 lidar tiles is
+    refused (workspace query 0, every call SPLAT_ERR_UNSUPPORTED) before any launch."""
+    b = _binding()
+    g = _scene(33)
+    lid = S.make_lidar((0, 0, 0), 0.0, 128, -25.0, 15.0, 2048, tile_az=1, tile_el=2, n_channels=8)
+    assert lid.n_az_tiles * lid.n_el_tiles > 65535
+    lid.ray_priority = np.zeros(lid.n_rays, np.uint16)
+    rig = b.Rig([], [lid])
+    assert int(rig.lib.splat_workspace_bytes(rig.handle, 0, 1, g.n, 1)) == 0   # the call is refused
+    with pytest.raises(b.SplatError):
+        b.SensorPass(rig, 0, 1, g.n, 1)
