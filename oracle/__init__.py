@@ -16,9 +16,10 @@ Layout:
                rotations and rigid-body velocities (Sec. 3.1, Eq. pixel_velocity, App. D)
   points    -- lidar points to rasterisation rays: ego-motion compensation removed, spherical
                coordinates (App. A)
+  mcmc      -- the MCMC opacity and scale regulariser of the training-details appendix
 
 Parity status of every function is listed in each module header.  "Parity unpinned" items:
 the value of the lidar dilation s_L and the Jacobian clamp constant are conventions passed in
 as inputs (the paper prints no worked values for them).
 """
-from . import geometry, tiles, render, grad, compose, points  # noqa: F401
+from . import geometry, tiles, render, grad, compose, points, mcmc  # noqa: F401
