@@ -17,9 +17,10 @@ Layout:
   points    -- lidar points to rasterisation rays: ego-motion compensation removed, spherical
                coordinates (App. A)
   mcmc      -- the MCMC opacity and scale regulariser of the training-details appendix
+  decoders  -- the lidar MLP decoding rendered features to intensity and ray-drop probability
 
 Parity status of every function is listed in each module header.  "Parity unpinned" items:
 the value of the lidar dilation s_L and the Jacobian clamp constant are conventions passed in
 as inputs (the paper prints no worked values for them).
 """
-from . import geometry, tiles, render, grad, compose, points, mcmc  # noqa: F401
+from . import geometry, tiles, render, grad, compose, points, mcmc, decoders  # noqa: F401
