@@ -42,6 +42,7 @@ PEAK_FP32_TFLOPS = 157.3            # vector FP32, datasheet (packed FMA)
 PEAK_HBM_GBS = 8000.0               # HBM3E, datasheet
 SEED_COMPOSE = 16816 + 11           # seed of the composition workload
 SEED_POINTS = 16816 + 12            # seed of the lidar points-to-rays workload
+SEED_DECODER = 16816 + 13           # seed of the lidar decoder workload (weights, features)
 # algorithmic FP32 work per evaluated (ray, Gaussian) pair of the forward compositing loop:
 # Delta (6), sigma (9), exp (1), alpha (1), transmittance (2), weight (1), feature and depth
 # blends (2 C + 2), plus the lidar range correction (2) and azimuth reduction (3);
@@ -58,7 +59,7 @@ def parse():
     ap.add_argument("--n", type=int, default=2_000_000, help="Gaussians")
     ap.add_argument("--modes", default="plain,batched,graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compose", action="store_true", help="skip the scene-graph composition and lidar points-to-rays measurements")
+    ap.add_argument("--no-compose", action="store_true", help="skip the composition, points-to-rays, MCMC regulariser and decoder measurements")
     ap.add_argument("--c5", action="store_true",
                     help="instead of the headline step: the 60-sensor sweep workload (3M Gaussians, 48 lidar sweeps "
                          "+ 12 cameras) with per-sensor latency p50/p99 from in-kernel clocks")
@@ -302,6 +303,8 @@ def main():
     if not args.no_compose:
         out["compose"] = compose_bench(args, dev)
         out["points_to_rays"] = points_bench(args, dev, lid)
+        out["mcmc_regularizer"] = mcmc_bench(args, dev, G, g)
+        out["lidar_decoder"] = decoder_bench(args, dev, lid)
     agree = mode_agreement(results)
     if agree:
         out["agreement"] = agree
@@ -629,6 +632,101 @@ def points_bench(args, dev, lid):
         del P, T, o
     out["roofline"] = {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS}
     out["parity"] = {"points": 2 * 4096, "max_err_over_tol": round(worst, 4), "pass": bool(worst <= 1.0)}
+    return out
+
+
+def mcmc_bench(args, dev, G, g):
+    """MCMC regulariser (splat_mcmc_regularizer) over the step's 2M Gaussians: value and
+    opacity / log-scale gradients, timed with HIP events around each call on the launching
+    stream, against the HBM roofline (48 B per Gaussian: opacity and log-scales read, their
+    gradients read and written)."""
+    import torch
+    from oracle import mcmc
+    from paper_2411_16816_amd import binding as B
+    val = torch.zeros(1, device=dev)
+    gr = B.zeros_like_grads(G)
+    for _ in range(max(1, args.warmup)):
+        B.mcmc_regularizer(G, val, gr)
+    stream = torch.cuda.current_stream()
+    mk = lambda: torch.cuda.Event(enable_timing=True)
+    ev = [(mk(), mk()) for _ in range(args.steps)]
+    val.zero_()
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record(stream)
+        B.mcmc_regularizer(G, val, gr)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    sec = float(np.median([a.elapsed_time(b_) for a, b_ in ev])) * 1e-3
+    ach = 48.0 * g.n / sec / 1e9
+    with torch.no_grad():
+        L = float(mcmc.regulariser(g.opacities, g.log_scales, g.quats))
+    err = abs(float(val) / args.steps - L) / L
+    log(f"mcmc_regularizer: {g.n} Gaussians, {sec * 1e3:.4f} ms ({ach:.0f} GB/s), value rel err {err:.2e}")
+    return {"workload": f"{g.n} Gaussians of the step, value + opacity / log-scale gradients",
+            "ms": round(sec * 1e3, 4), "bytes_per_gaussian": 48,
+            "roofline": {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS, "achieved": round(ach, 1),
+                         "frac": round(ach / PEAK_HBM_GBS, 4)},
+            "parity": {"value_rel_err": float(f"{err:.3g}"), "pass": bool(err <= 1e-4)}}
+
+
+def decoder_bench(args, dev, lid):
+    """Lidar decoder (splat_lidar_decode / _bwd, 8 feature channels, hidden width 32) on one
+    128 x 2048 sweep and on 64 sweeps in one launch, timed with HIP events around each call;
+    forward against the HBM roofline (48 B per ray: feature row, angles, two outputs) and its
+    FLOP (2 x (32 x 11 + 64) per ray) against the FP32 peak."""
+    import torch
+    from oracle import decoders as dec
+    from paper_2411_16816_amd import binding as B
+    rng = np.random.default_rng(SEED_DECODER)
+    C = 8
+    W = [rng.normal(0, 0.5, (32, C + 3)), rng.normal(0, 0.2, 32), rng.normal(0, 0.5, (2, 32)), rng.normal(0, 0.2, 2)]
+    W = [w.astype(np.float32) for w in W]
+    mlp = B.LidarMLP(*(torch.from_numpy(w).to(dev) for w in W))
+    stream = torch.cuda.current_stream()
+    mk = lambda: torch.cuda.Event(enable_timing=True)
+    out = {"workload": "lidar decoder, 8 feature channels + ray direction -> intensity, ray drop (hidden 32)",
+           "bytes_per_ray_fwd": 48, "flop_per_ray_fwd": 2 * (32 * (C + 3) + 64), "sizes": {}}
+    worst = 0.0
+    for label, reps in (("one_sweep", 1), ("64_sweeps", 64)):
+        n = lid.n_rays * reps
+        F = torch.from_numpy(rng.normal(size=(n, C)).astype(np.float32)).to(dev)
+        az = torch.from_numpy(np.tile(lid.ray_az.astype(np.float32), reps)).to(dev)
+        el = torch.from_numpy(np.tile(lid.ray_el.astype(np.float32), reps)).to(dev)
+        dI = torch.from_numpy(rng.normal(size=n).astype(np.float32)).to(dev)
+        dP = torch.from_numpy(rng.normal(size=n).astype(np.float32)).to(dev)
+        dF = torch.zeros_like(F)
+        dm = {f: torch.zeros_like(getattr(mlp, f)) for f in B.MLP_FIELDS}
+        ws = torch.empty(int(B.load().splat_lidar_decode_workspace_bytes(n, C)), dtype=torch.uint8, device=dev)
+        for _ in range(max(1, args.warmup)):
+            I, P = B.lidar_decode(F, az, el, mlp)
+            B.lidar_decode_bwd(F, az, el, mlp, dI, dP, dF, dm, ws)
+        ev = [(mk(), mk(), mk()) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        for e0, e1, e2 in ev:
+            e0.record(stream)
+            I, P = B.lidar_decode(F, az, el, mlp)
+            e1.record(stream)
+            B.lidar_decode_bwd(F, az, el, mlp, dI, dP, dF, dm, ws)
+            e2.record(stream)
+        torch.cuda.synchronize()
+        t_f = float(np.median([a.elapsed_time(b_) for a, b_, _ in ev])) * 1e-3
+        t_b = float(np.median([b_.elapsed_time(c) for _, b_, c in ev])) * 1e-3
+        idx = np.sort(np.random.default_rng(5).choice(n, 4096, replace=False))
+        ii = torch.from_numpy(idx).to(dev)
+        with torch.no_grad():
+            rI, rP = dec.lidar_mlp(F[ii].double().cpu(), az[ii].cpu().numpy(), el[ii].cpu().numpy(), *W)
+        for got, want in ((I[ii], rI), (P[ii], rP)):
+            a_, w_ = got.double().cpu().numpy(), want.numpy()
+            worst = max(worst, float((np.abs(a_ - w_) / (1e-5 + 1e-4 * np.abs(w_))).max()))
+        gbs = 48.0 * n / t_f / 1e9
+        out["sizes"][label] = {"rays": n, "fwd_ms": round(t_f * 1e3, 4), "bwd_ms": round(t_b * 1e3, 4),
+                               "fwd_GBs": round(gbs, 1), "fwd_hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
+                               "fwd_TFLOPs": round(out["flop_per_ray_fwd"] * n / t_f / 1e12, 2)}
+        log(f"lidar decoder {label}: {n} rays, fwd {t_f * 1e3:.4f} ms ({gbs:.0f} GB/s), bwd {t_b * 1e3:.4f} ms")
+        del F, az, el, dI, dP, dF, ws
+    out["roofline"] = {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS}
+    out["parity"] = {"rays": 2 * 4096, "max_err_over_tol": round(worst, 4), "pass": bool(worst <= 1.0)}
     return out
 
 

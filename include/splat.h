@@ -463,6 +463,59 @@ int splat_lidar_points_to_rays(int64_t n, const float* points, const float* time
                                const float* t, const float* lin_vel, const float* ang_vel, float* ray_az,
                                float* ray_el, float* ray_range, void* stream);
 
+/* ---- lidar decoder (Sec. 3.3; the training-details appendix: two layers, hidden width 32) ----
+ * Per lidar ray, the rendered feature row F (n_feat channels, rows of n_feat floats as the lidar
+ * rasteriser writes them) and the ray's unit direction in the sensor frame,
+ * d = (cos el cos az, cos el sin az, sin el), are decoded by a two-layer MLP:
+ *   h = ReLU(W1 [F, d] + b1),  z = W2 h + b2,  intensity = sigmoid(z0),  drop = sigmoid(z1).
+ * The weights are device arrays (row-major); trained values are not needed to define the op. */
+typedef struct SplatLidarMLP {
+  int32_t n_feat;     /* C, 0..32                                                               */
+  const float* w1;    /* [32, C + 3]: columns 0..C-1 multiply F, C..C+2 multiply d             */
+  const float* b1;    /* [32]                                                                   */
+  const float* w2;    /* [2, 32]: row 0 intensity, row 1 ray drop                               */
+  const float* b2;    /* [2]                                                                    */
+} SplatLidarMLP;
+
+/* Weight-gradient accumulators (+=), device arrays shaped like SplatLidarMLP's; NULL skips one. */
+typedef struct SplatLidarMLPGrads {
+  float* w1;
+  float* b1;
+  float* w2;
+  float* b2;
+} SplatLidarMLPGrads;
+
+/* Decodes n_rays rays: feat [n_rays, C], ray_az / ray_el [n_rays] (the rays the features were
+ * rendered for) -> intensity [n_rays], drop_prob [n_rays] (either may be NULL).  n_rays = 0 is a
+ * no-op; C outside 0..32 or a missing weight array gives SPLAT_ERR_INVALID_ARG.  Stream-ordered,
+ * allocates nothing. */
+int splat_lidar_decode(int64_t n_rays, const float* feat, const float* ray_az, const float* ray_el,
+                       const SplatLidarMLP* mlp, float* intensity, float* drop_prob, void* stream);
+/* Workspace of splat_lidar_decode_bwd (per-workgroup partial weight gradients); 0 = invalid. */
+size_t splat_lidar_decode_workspace_bytes(int64_t n_rays, int32_t n_feat);
+/* Adjoint of splat_lidar_decode.  Upstream gradients d_intensity, d_drop_prob [n_rays] (either
+ * NULL = zero) -> d_feat [n_rays, C] (+=, or NULL) and the weight gradients (+=).  The weight
+ * gradients are sums over rays, added in a fixed order (deterministic).  Workspace: caller-owned,
+ * at least splat_lidar_decode_workspace_bytes bytes (SPLAT_ERR_CAPACITY otherwise).
+ * Stream-ordered, allocates nothing. */
+int splat_lidar_decode_bwd(int64_t n_rays, const float* feat, const float* ray_az, const float* ray_el,
+                           const SplatLidarMLP* mlp, const float* d_intensity, const float* d_drop_prob,
+                           float* d_feat, const SplatLidarMLPGrads* d_mlp, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* ---- MCMC regulariser (training-details appendix) -------------------------------------------
+ * The opacity and scale regularisation of the MCMC densification strategy:
+ *   L = lambda_o sum_i |o_i| + lambda_s sum_i sum_j |sqrt(eig_j(Sigma_i))|
+ * (the paper: lambda_o = 0.005, lambda_s = 0.001).  With Sigma = R diag(exp(2 l)) R^T the square
+ * roots of the eigenvalues are exp(l_j) whatever the rotation.  Adds L to *value (device float,
+ * or NULL) and dL/do = lambda_o sign(o), dL/dl = lambda_s exp(l) to grads->opacities and
+ * grads->log_scales (each may be NULL, as may `grads`; other members are not touched).  The
+ * value is summed in float32, per workgroup and then atomically (its last bits depend on the
+ * order); the gradients are exact elementwise.  n = 0 is a no-op; non-finite lambdas give
+ * SPLAT_ERR_INVALID_ARG.  Stream-ordered, allocates nothing. */
+int splat_mcmc_regularizer(const SplatGaussians* g, float lambda_o, float lambda_s, float* value,
+                           const SplatGrads* grads, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

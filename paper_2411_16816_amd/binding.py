@@ -64,6 +64,10 @@ def _declare(lib):
         "splat_compose_workspace_bytes": (C.c_size_t, [i32]),
         "splat_compose_bwd": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
         "splat_lidar_points_to_rays": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "splat_mcmc_regularizer": (C.c_int, [vp, C.c_float, C.c_float, vp, vp, vp]),
+        "splat_lidar_decode": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp]),
+        "splat_lidar_decode_workspace_bytes": (C.c_size_t, [i64, i32]),
+        "splat_lidar_decode_bwd": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -640,3 +644,76 @@ def points_to_rays(points: torch.Tensor, times: torch.Tensor, R, t, lin_vel=None
                                          None if wh is None else C.cast(wh, C.c_void_p), _ptr(az), _ptr(el), _ptr(rg),
                                          _stream(stream)), "splat_lidar_points_to_rays")
     return az, el, rg
+
+
+# ----------------------------------------------------------------------------------------
+# MCMC regulariser (splat_mcmc_regularizer)
+# ----------------------------------------------------------------------------------------
+MCMC_LAMBDA_O = 0.005
+MCMC_LAMBDA_S = 0.001
+
+
+def mcmc_regularizer(g: GaussTensors, value: Optional[torch.Tensor] = None, grads: Optional[GaussTensors] = None,
+                     lambda_o: float = MCMC_LAMBDA_O, lambda_s: float = MCMC_LAMBDA_S, stream=None):
+    """Adds the regulariser's value to `value` (float32 device scalar tensor) and its gradients to
+    grads.opacities / grads.log_scales."""
+    gr = None
+    if grads is not None:
+        gr = st.SplatGrads()
+        gr.opacities, gr.log_scales = _ptr(grads.opacities), _ptr(grads.log_scales)
+    check(load().splat_mcmc_regularizer(C.byref(g.struct()), float(lambda_o), float(lambda_s), _ptr(value),
+                                        None if gr is None else C.byref(gr), _stream(stream)),
+          "splat_mcmc_regularizer")
+
+
+# ----------------------------------------------------------------------------------------
+# lidar decoder (splat_lidar_decode / splat_lidar_decode_bwd)
+# ----------------------------------------------------------------------------------------
+MLP_FIELDS = ("w1", "b1", "w2", "b2")
+
+
+@dataclass
+class LidarMLP:
+    """Weights of the lidar decoder: w1 [32, C+3], b1 [32], w2 [2, 32], b2 [2] (float32 device)."""
+    w1: torch.Tensor
+    b1: torch.Tensor
+    w2: torch.Tensor
+    b2: torch.Tensor
+
+    @property
+    def n_feat(self) -> int:
+        return int(self.w1.shape[1]) - 3
+
+    def struct(self) -> st.SplatLidarMLP:
+        m = st.SplatLidarMLP()
+        m.n_feat = self.n_feat
+        m.w1, m.b1, m.w2, m.b2 = (_ptr(getattr(self, f)) for f in MLP_FIELDS)
+        return m
+
+
+def lidar_decode(feat: torch.Tensor, az: torch.Tensor, el: torch.Tensor, mlp: LidarMLP, stream=None):
+    """(intensity [R], drop probability [R]) of feature rows feat [R, C]."""
+    n = int(az.numel())
+    if feat.numel() != n * mlp.n_feat:
+        raise ValueError("feat must hold n_rays rows of n_feat channels")
+    I = torch.empty(n, dtype=torch.float32, device=az.device)
+    P = torch.empty(n, dtype=torch.float32, device=az.device)
+    check(load().splat_lidar_decode(n, _ptr(feat), _ptr(az), _ptr(el), C.byref(mlp.struct()), _ptr(I), _ptr(P),
+                                    _stream(stream)), "splat_lidar_decode")
+    return I, P
+
+
+def lidar_decode_bwd(feat, az, el, mlp: LidarMLP, d_int, d_drop, d_feat=None, d_mlp: Optional[dict] = None,
+                     ws: Optional[torch.Tensor] = None, stream=None):
+    """Adds dL/dfeat to d_feat and the weight gradients to d_mlp[field] (float32 device tensors)."""
+    lib = load()
+    n = int(az.numel())
+    nb = int(lib.splat_lidar_decode_workspace_bytes(n, mlp.n_feat))
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=az.device)
+    g = st.SplatLidarMLPGrads()
+    d_mlp = d_mlp or {}
+    g.w1, g.b1, g.w2, g.b2 = (_ptr(d_mlp.get(f)) for f in MLP_FIELDS)
+    check(lib.splat_lidar_decode_bwd(n, _ptr(feat), _ptr(az), _ptr(el), C.byref(mlp.struct()), _ptr(d_int),
+                                     _ptr(d_drop), _ptr(d_feat), C.byref(g), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                     _stream(stream)), "splat_lidar_decode_bwd")

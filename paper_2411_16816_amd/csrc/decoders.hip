@@ -1,0 +1,275 @@
+// decoders.hip -- the lidar decoder of the rendered features (SplatAD, arXiv 2411.16816, Sec. 3.3;
+// the training-details appendix gives its size: two layers, hidden width 32).
+//
+// Per lidar ray, the rendered feature row F (C channels) and the ray's unit direction
+// d = (cos el cos az, cos el sin az, sin el) in the sensor frame are decoded:
+//   h = ReLU(W1 [F, d] + b1),  z = W2 h + b2,  intensity = sigmoid(z0),  drop = sigmoid(z1).
+//
+// Forward: one thread per ray, the weights staged in LDS (every lane reads the same weight: LDS
+// broadcasts), about 32 (C + 5) FMAs per ray; HBM moves the feature row, the angles and the
+// two outputs.  Adjoint: one thread per ray recomputes the forward, writes dL/dF (+=) and stages
+// its input x, hidden pre-activation gradient, hidden output and output gradient in LDS; the
+// weight gradients are contractions over rays, so each thread then sums its share of the
+// (W1, b1, W2, b2) entries over the workgroup's 128 rays from LDS into registers, across the
+// chunks a persistent workgroup takes.  Every workgroup stores its partial sums, and a second
+// kernel adds them in workgroup order: deterministic, no atomics.
+#include "kernels.hpp"
+
+namespace splat {
+
+constexpr int kDecHidden = 32;
+constexpr int kDecBlock = 128;
+constexpr int kDecMaxC = 32;
+
+inline int dec_outputs(int C) { return kDecHidden * (C + 3) + kDecHidden + 2 * kDecHidden + 2; }
+
+template <int CM>
+struct DecWeights {
+  float w1f[kDecHidden][CM];   // feature columns of W1 (zero beyond C)
+  float w1d[kDecHidden][3];    // direction columns of W1
+  float b1[kDecHidden];
+  float w2[2][kDecHidden];
+  float b2[2];
+};
+
+template <int CM>
+__device__ void stage_weights(DecWeights<CM>& W, const SplatLidarMLP& m) {
+  const int C = m.n_feat;
+  for (int i = threadIdx.x; i < kDecHidden * CM; i += blockDim.x) {
+    const int j = i / CM, k = i % CM;
+    W.w1f[j][k] = k < C ? m.w1[j * (C + 3) + k] : 0.f;
+  }
+  for (int i = threadIdx.x; i < kDecHidden * 3; i += blockDim.x) W.w1d[i / 3][i % 3] = m.w1[(i / 3) * (C + 3) + C + i % 3];
+  for (int i = threadIdx.x; i < kDecHidden; i += blockDim.x) W.b1[i] = m.b1[i];
+  for (int i = threadIdx.x; i < 2 * kDecHidden; i += blockDim.x) W.w2[i / kDecHidden][i % kDecHidden] = m.w2[i];
+  if (threadIdx.x < 2) W.b2[threadIdx.x] = m.b2[threadIdx.x];
+}
+
+__device__ __forceinline__ float sigmoid_f(float z) { return 1.f / (1.f + expf(-z)); }
+
+template <int CM>
+__device__ __forceinline__ void load_ray(const float* feat, const float* az, const float* el, int64_t r, int C,
+                                         float (&F)[CM], float (&d)[3]) {
+  const float* row = feat + r * C;
+#pragma unroll
+  for (int k = 0; k < CM; ++k) F[k] = k < C ? row[k] : 0.f;
+  float sa, ca, se, ce;
+  sincosf(az[r], &sa, &ca);
+  sincosf(el[r], &se, &ce);
+  d[0] = ce * ca;
+  d[1] = ce * sa;
+  d[2] = se;
+}
+
+template <int CM>
+__device__ __forceinline__ float hidden_pre(const DecWeights<CM>& W, int j, const float (&F)[CM], const float (&d)[3]) {
+  float p = W.b1[j];
+#pragma unroll
+  for (int k = 0; k < CM; ++k) p = fmaf(W.w1f[j][k], F[k], p);
+  p = fmaf(W.w1d[j][0], d[0], p);
+  p = fmaf(W.w1d[j][1], d[1], p);
+  return fmaf(W.w1d[j][2], d[2], p);
+}
+
+template <int CM>
+__global__ __launch_bounds__(kDecBlock) void k_lidar_decode(int64_t n, const float* __restrict__ feat,
+                                                            const float* __restrict__ az, const float* __restrict__ el,
+                                                            SplatLidarMLP m, float* __restrict__ intensity,
+                                                            float* __restrict__ drop) {
+  __shared__ DecWeights<CM> W;
+  stage_weights<CM>(W, m);
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    float F[CM], d[3];
+    load_ray<CM>(feat, az, el, r, m.n_feat, F, d);
+    float z0 = W.b2[0], z1 = W.b2[1];
+#pragma unroll 4
+    for (int j = 0; j < kDecHidden; ++j) {
+      const float h = fmaxf(hidden_pre<CM>(W, j, F, d), 0.f);
+      z0 = fmaf(W.w2[0][j], h, z0);
+      z1 = fmaf(W.w2[1][j], h, z1);
+    }
+    if (intensity) intensity[r] = sigmoid_f(z0);
+    if (drop) drop[r] = sigmoid_f(z1);
+  }
+}
+
+// LDS rows of one chunk of rays for the weight-gradient contraction
+template <int CM>
+struct DecStage {
+  float x[kDecBlock][CM + 4];            // [F, d] (padded)
+  float dpre[kDecBlock][kDecHidden + 1];
+  float h[kDecBlock][kDecHidden + 1];
+  float dz[kDecBlock][2];
+};
+
+template <int CM>
+__global__ __launch_bounds__(kDecBlock) void k_lidar_decode_bwd(int64_t n, const float* __restrict__ feat,
+                                                                const float* __restrict__ az,
+                                                                const float* __restrict__ el, SplatLidarMLP m,
+                                                                const float* __restrict__ d_int,
+                                                                const float* __restrict__ d_drop,
+                                                                float* __restrict__ d_feat, float* __restrict__ partial,
+                                                                int n_out) {
+  constexpr int NPT = (kDecHidden * (CM + 3) + 3 * kDecHidden + 2 + kDecBlock - 1) / kDecBlock;
+  __shared__ DecWeights<CM> W;
+  __shared__ DecStage<CM> S;
+  stage_weights<CM>(W, m);
+  const int C = m.n_feat, XC = C + 3;
+  const int nw1 = kDecHidden * XC, nb1 = nw1 + kDecHidden, nw2 = nb1 + 2 * kDecHidden;
+  float acc[NPT];
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) acc[i] = 0.f;
+  const int t = threadIdx.x;
+  for (int64_t base = (int64_t)blockIdx.x * kDecBlock; base < n; base += (int64_t)gridDim.x * kDecBlock) {
+    __syncthreads();   // weights staged / the previous chunk's rows consumed
+    const int64_t r = base + t;
+    if (r < n) {
+      float F[CM], d[3];
+      load_ray<CM>(feat, az, el, r, C, F, d);
+      float z0 = W.b2[0], z1 = W.b2[1];
+      // forward again; the pre-activations wait in this ray's LDS row (the lane's own row)
+#pragma unroll 2
+      for (int j = 0; j < kDecHidden; ++j) {
+        const float p = hidden_pre<CM>(W, j, F, d);
+        const float h = fmaxf(p, 0.f);
+        S.dpre[t][j] = p;
+        S.h[t][j] = h;
+        z0 = fmaf(W.w2[0][j], h, z0);
+        z1 = fmaf(W.w2[1][j], h, z1);
+      }
+      const float s0 = sigmoid_f(z0), s1 = sigmoid_f(z1);
+      const float g0 = d_int ? d_int[r] * s0 * (1.f - s0) : 0.f;
+      const float g1 = d_drop ? d_drop[r] * s1 * (1.f - s1) : 0.f;
+      S.dz[t][0] = g0;
+      S.dz[t][1] = g1;
+#pragma unroll
+      for (int k = 0; k < CM; ++k) S.x[t][k] = F[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) S.x[t][CM + k] = d[k];   // x = [F, d]: direction after the features
+      float dF[CM];
+#pragma unroll
+      for (int k = 0; k < CM; ++k) dF[k] = 0.f;
+#pragma unroll 2
+      for (int j = 0; j < kDecHidden; ++j) {
+        const float dp = S.dpre[t][j] > 0.f ? fmaf(W.w2[0][j], g0, W.w2[1][j] * g1) : 0.f;
+        S.dpre[t][j] = dp;
+#pragma unroll
+        for (int k = 0; k < CM; ++k) dF[k] = fmaf(W.w1f[j][k], dp, dF[k]);
+      }
+      if (d_feat) {
+        float* row = d_feat + r * C;
+#pragma unroll
+        for (int k = 0; k < CM; ++k)
+          if (k < C) row[k] += dF[k];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kDecHidden; ++j) S.dpre[t][j] = S.h[t][j] = 0.f;
+      S.dz[t][0] = S.dz[t][1] = 0.f;
+#pragma unroll
+      for (int k = 0; k < CM + 3; ++k) S.x[t][k] = 0.f;
+    }
+    __syncthreads();
+    const int rows = (n - base) < kDecBlock ? (int)(n - base) : kDecBlock;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int o = t + i * kDecBlock;
+      if (o >= n_out) break;
+      float s = 0.f;
+      if (o < nw1) {                      // dW1[j][k] = sum dpre_j x_k
+        const int j = o / XC, k = o % XC;
+        const int kx = k < C ? k : CM + (k - C);
+        for (int q = 0; q < rows; ++q) s = fmaf(S.dpre[q][j], S.x[q][kx], s);
+      } else if (o < nb1) {               // db1[j] = sum dpre_j
+        const int j = o - nw1;
+        for (int q = 0; q < rows; ++q) s += S.dpre[q][j];
+      } else if (o < nw2) {               // dW2[c][j] = sum dz_c h_j
+        const int c = (o - nb1) / kDecHidden, j = (o - nb1) % kDecHidden;
+        for (int q = 0; q < rows; ++q) s = fmaf(S.dz[q][c], S.h[q][j], s);
+      } else {                            // db2[c] = sum dz_c
+        const int c = o - nw2;
+        for (int q = 0; q < rows; ++q) s += S.dz[q][c];
+      }
+      acc[i] += s;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) {
+    const int o = t + i * kDecBlock;
+    if (o < n_out) partial[(int64_t)blockIdx.x * n_out + o] = acc[i];
+  }
+}
+
+// weight gradients (+=): the workgroups' partial sums added in workgroup order
+__global__ void k_lidar_decode_wsum(const float* __restrict__ partial, int n_blocks, int n_out, int C,
+                                    SplatLidarMLPGrads g) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_out) return;
+  float s = 0.f;
+  for (int b = 0; b < n_blocks; ++b) s += partial[(int64_t)b * n_out + o];
+  const int nw1 = kDecHidden * (C + 3), nb1 = nw1 + kDecHidden, nw2 = nb1 + 2 * kDecHidden;
+  if (o < nw1) { if (g.w1) g.w1[o] += s; }
+  else if (o < nb1) { if (g.b1) g.b1[o - nw1] += s; }
+  else if (o < nw2) { if (g.w2) g.w2[o - nb1] += s; }
+  else if (g.b2) g.b2[o - nw2] += s;
+}
+
+static int bwd_blocks(int64_t n) {
+  int64_t b = div_up(n, kDecBlock);
+  return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+}
+
+static bool mlp_ok(const SplatLidarMLP* m) {
+  return m && m->n_feat >= 0 && m->n_feat <= kDecMaxC && m->w1 && m->b1 && m->w2 && m->b2;
+}
+
+}  // namespace splat
+
+using namespace splat;
+
+#define SPLAT_DEC_DISPATCH(C, KERNEL, ...)                                                             \
+  do {                                                                                                 \
+    if ((C) <= 8) hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__);                                          \
+    else if ((C) <= 16) hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__);                                   \
+    else hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__);                                                  \
+  } while (0)
+
+extern "C" {
+
+int splat_lidar_decode(int64_t n_rays, const float* feat, const float* ray_az, const float* ray_el,
+                       const SplatLidarMLP* mlp, float* intensity, float* drop_prob, void* stream) {
+  if (n_rays < 0 || !mlp_ok(mlp)) return SPLAT_ERR_INVALID_ARG;
+  if (n_rays == 0 || (!intensity && !drop_prob)) return SPLAT_OK;
+  if ((mlp->n_feat > 0 && !feat) || !ray_az || !ray_el) return SPLAT_ERR_INVALID_ARG;
+  int64_t blocks = div_up(n_rays, kDecBlock);
+  if (blocks > 4096) blocks = 4096;
+  SPLAT_DEC_DISPATCH(mlp->n_feat, k_lidar_decode, dim3((unsigned)blocks), dim3(kDecBlock), 0, (hipStream_t)stream,
+                     n_rays, feat, ray_az, ray_el, *mlp, intensity, drop_prob);
+  return hipGetLastError() == hipSuccess ? SPLAT_OK : SPLAT_ERR_DEVICE;
+}
+
+size_t splat_lidar_decode_workspace_bytes(int64_t n_rays, int32_t n_feat) {
+  if (n_rays < 0 || n_feat < 0 || n_feat > kDecMaxC) return 0;
+  return (size_t)bwd_blocks(n_rays) * dec_outputs(n_feat) * sizeof(float);
+}
+
+int splat_lidar_decode_bwd(int64_t n_rays, const float* feat, const float* ray_az, const float* ray_el,
+                           const SplatLidarMLP* mlp, const float* d_intensity, const float* d_drop_prob,
+                           float* d_feat, const SplatLidarMLPGrads* d_mlp, void* ws, size_t ws_bytes, void* stream) {
+  if (n_rays < 0 || !mlp_ok(mlp) || !d_mlp) return SPLAT_ERR_INVALID_ARG;
+  if (n_rays == 0) return SPLAT_OK;
+  if ((mlp->n_feat > 0 && !feat) || !ray_az || !ray_el) return SPLAT_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < splat_lidar_decode_workspace_bytes(n_rays, mlp->n_feat)) return SPLAT_ERR_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  const int nb = bwd_blocks(n_rays), n_out = dec_outputs(mlp->n_feat);
+  float* partial = (float*)ws;
+  SPLAT_DEC_DISPATCH(mlp->n_feat, k_lidar_decode_bwd, dim3((unsigned)nb), dim3(kDecBlock), 0, s, n_rays, feat,
+                     ray_az, ray_el, *mlp, d_intensity, d_drop_prob, d_feat, partial, n_out);
+  hipLaunchKernelGGL(k_lidar_decode_wsum, dim3((unsigned)div_up(n_out, 256)), dim3(256), 0, s, (const float*)partial, nb,
+                     n_out, mlp->n_feat, *d_mlp);
+  return hipGetLastError() == hipSuccess ? SPLAT_OK : SPLAT_ERR_DEVICE;
+}
+
+}  // extern "C"

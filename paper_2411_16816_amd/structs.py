@@ -142,3 +142,11 @@ class SplatActors(C.Structure):
 class SplatActorGrads(C.Structure):
     _fields_ = [("rot_offset", C.c_void_p), ("trans_offset", C.c_void_p), ("lin_vel_offset", C.c_void_p),
                 ("ang_vel", C.c_void_p)]
+
+
+class SplatLidarMLP(C.Structure):
+    _fields_ = [("n_feat", C.c_int32), ("w1", C.c_void_p), ("b1", C.c_void_p), ("w2", C.c_void_p), ("b2", C.c_void_p)]
+
+
+class SplatLidarMLPGrads(C.Structure):
+    _fields_ = [("w1", C.c_void_p), ("b1", C.c_void_p), ("w2", C.c_void_p), ("b2", C.c_void_p)]

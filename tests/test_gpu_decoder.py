@@ -1,0 +1,170 @@
+"""Lidar decoder (splat_lidar_decode / splat_lidar_decode_bwd; Sec. 3.3, training-details
+appendix) through the C ABI against the FP64 oracle (oracle/decoders.py) on the same float32
+inputs: intensity and drop probability within 1e-4 relative / 1e-5 absolute, dL/dF element by
+element and the weight gradients (sums over every ray) within 1e-4 relative of their norm;
+feature widths 0 to 32 with ragged ray counts, the headline sweep, edge cases, and the decoder
+chained to the lidar rasteriser against FP64 autograd through the oracle's render and decoder."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import decoders as dec
+from oracle import geometry as geo
+from oracle import render as rd
+from scenes import synthetic as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _binding():
+    from paper_2411_16816_amd import binding
+    binding.load()
+    return binding
+
+
+def _weights(rng, C):
+    return [rng.normal(0, 0.5, (32, C + 3)).astype(np.float32), rng.normal(0, 0.2, 32).astype(np.float32),
+            rng.normal(0, 0.5, (2, 32)).astype(np.float32), rng.normal(0, 0.2, 2).astype(np.float32)]
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _close(a, r, what):
+    err = np.abs(a.astype(np.float64) - r) / (1e-5 + 1e-4 * np.abs(r))
+    assert float(err.max(initial=0.0)) <= 1.0, (what, float(err.max()))
+
+
+def _rel(a, r, what, tol=1e-4):
+    nr = np.linalg.norm(r)
+    assert np.linalg.norm(a.astype(np.float64) - r) <= tol * max(nr, 1e-30), (what, np.linalg.norm(a - r) / nr)
+
+
+def _run(b, F, az, el, W, dI, dP):
+    mlp = b.LidarMLP(*(_dev(w) for w in W))
+    Fd, azd, eld = _dev(F), _dev(az), _dev(el)
+    I, P = b.lidar_decode(Fd, azd, eld, mlp)
+    dF = torch.ones_like(Fd)   # accumulates
+    dm = {f: torch.zeros_like(getattr(mlp, f)) for f in b.MLP_FIELDS}
+    b.lidar_decode_bwd(Fd, azd, eld, mlp, _dev(dI), _dev(dP), dF, dm)
+    torch.cuda.synchronize()
+    return I.cpu().numpy(), P.cpu().numpy(), dF.cpu().numpy() - 1.0, {k: v.cpu().numpy() for k, v in dm.items()}
+
+
+def _oracle(F, az, el, W, dI, dP):
+    leaves = [torch.tensor(x, dtype=torch.float64, requires_grad=True) for x in [F] + W]
+    I, P = dec.lidar_mlp(leaves[0], az, el, *leaves[1:])
+    ((I * torch.from_numpy(dI.astype(np.float64))).sum() + (P * torch.from_numpy(dP.astype(np.float64))).sum()).backward()
+    return I.detach().numpy(), P.detach().numpy(), leaves[0].grad.numpy(), {f: l.grad.numpy() for f, l in
+                                                                             zip(("w1", "b1", "w2", "b2"), leaves[1:])}
+
+
+@pytest.mark.parametrize("n,C", [(70001, 8), (70001, 16), (4099, 3), (4099, 32), (129, 0), (1, 8)])
+def test_decoder_matches_oracle(n, C):
+    b = _binding()
+    rng = np.random.default_rng(100 + n + C)
+    print(f"[decoder] n={n} C={C}", flush=True)
+    F = rng.normal(size=(n, C)).astype(np.float32)
+    az = rng.uniform(0, 2 * np.pi, n).astype(np.float32)
+    el = rng.uniform(-0.45, 0.27, n).astype(np.float32)
+    W = _weights(rng, C)
+    dI, dP = rng.normal(size=n).astype(np.float32), rng.normal(size=n).astype(np.float32)
+    got = _run(b, F, az, el, W, dI, dP)
+    ref = _oracle(F, az, el, W, dI, dP)
+    _close(got[0], ref[0], "intensity")
+    _close(got[1], ref[1], "drop")
+    if C:
+        _close(got[2], ref[2], "d_feat")
+    for f in ("w1", "b1", "w2", "b2"):
+        _rel(got[3][f], ref[3][f], f)
+
+
+def test_decoder_edge_cases():
+    b = _binding()
+    rng = np.random.default_rng(5)
+    W = _weights(rng, 8)
+    mlp = b.LidarMLP(*(_dev(w) for w in W))
+    e = torch.empty(0, device="cuda")
+    I, P = b.lidar_decode(e, e, e, mlp)   # no rays
+    assert I.numel() == 0
+    b.lidar_decode_bwd(e, e, e, mlp, e, e, None, {})
+    # only the drop output's gradient given, no d_feat
+    n = 300
+    F = rng.normal(size=(n, 8)).astype(np.float32)
+    az = rng.uniform(0, 6, n).astype(np.float32)
+    el = rng.uniform(-0.3, 0.2, n).astype(np.float32)
+    dm = {f: torch.zeros_like(getattr(mlp, f)) for f in b.MLP_FIELDS}
+    b.lidar_decode_bwd(_dev(F), _dev(az), _dev(el), mlp, None, _dev(np.ones(n, np.float32)), None, dm)
+    torch.cuda.synchronize()
+    ref = _oracle(F, az, el, W, np.zeros(n, np.float32), np.ones(n, np.float32))
+    for f in ("w1", "b1", "w2", "b2"):
+        _rel(dm[f].cpu().numpy(), ref[3][f], f)
+    assert float(dm["w2"][0].abs().max()) == 0.0   # no intensity gradient
+    with pytest.raises(b.SplatError):   # more than 32 channels
+        wide = b.LidarMLP(_dev(np.zeros((32, 36), np.float32)), *(_dev(w) for w in W[1:]))
+        b.lidar_decode(_dev(np.zeros((4, 33), np.float32)), _dev(az[:4]), _dev(el[:4]), wide)
+
+
+def test_decoder_headline_sweep():
+    b = _binding()
+    lid = S.headline(n=1000).lidars[0]
+    n = lid.n_rays
+    rng = np.random.default_rng(6)
+    print(f"[decoder] headline sweep n={n}", flush=True)
+    F = rng.normal(size=(n, 8)).astype(np.float32)
+    W = _weights(rng, 8)
+    dI, dP = rng.normal(size=n).astype(np.float32), rng.normal(size=n).astype(np.float32)
+    az, el = lid.ray_az.astype(np.float32), lid.ray_el.astype(np.float32)
+    got = _run(b, F, az, el, W, dI, dP)
+    ref = _oracle(F, az, el, W, dI, dP)
+    for k, w in ((0, "intensity"), (1, "drop"), (2, "d_feat")):
+        _close(got[k], ref[k], w)
+    for f in ("w1", "b1", "w2", "b2"):
+        _rel(got[3][f], ref[3][f], f)
+
+
+def test_decoder_chained_to_the_rasteriser():
+    """Rendered lidar features decoded to intensity and drop probability: the Gaussian gradients
+    of a loss on the decoded values (decoder adjoint -> rasteriser adjoint) match FP64 autograd
+    through the oracle's render and decoder within 1e-3 relative."""
+    b = _binding()
+    rng = np.random.default_rng(7)
+    n_g = 400
+    mu = np.stack([rng.uniform(-14, 14, n_g), rng.uniform(-14, 14, n_g), rng.uniform(-1.5, 1.5, n_g)], 1)
+    g = S.random_gaussians(rng, mu, 8, moving_frac=0.3, log_scale_mean=-0.6)
+    lid = S.make_lidar((0, 0, 0), 0.0, 16, -15.0, 15.0, 256, tile_az=16, tile_el=8, t_sweep=0.1,
+                       ego_vel_world=(10.0, 1.0, 0), n_channels=8)
+    W = _weights(rng, 8)
+    R = lid.n_rays
+    wI, wP = rng.normal(size=R), rng.normal(size=R)
+    # oracle: render + decoder in FP64; rays with near decisions carry no upstream gradient
+    out0 = rd.render_sensor(g, lid)
+    keep = (~out0["near"]).astype(np.float64)
+    wI, wP = (wI * keep).astype(np.float32), (wP * keep).astype(np.float32)
+    p = geo.Params.from_gaussians(g, requires_grad=True)
+    out = rd.render_sensor(p, lid)
+    I, P = dec.lidar_mlp(out["F"], lid.ray_az.astype(np.float32), lid.ray_el.astype(np.float32), *W)
+    ((I * torch.from_numpy(wI.astype(np.float64))).sum() + (P * torch.from_numpy(wP.astype(np.float64))).sum()).backward()
+    ref = {name: t.grad.numpy() for name, t in zip(geo.Params.names, p.tensors()) if t.grad is not None}
+    # library: render, decode, decoder adjoint -> dF, rasteriser adjoint
+    rig = b.Rig([], [lid])
+    G = b.GaussTensors.from_numpy(g)
+    sp = b.SensorPass(rig, 0, 1, g.n, 1)
+    sp.fit_capacity(G)
+    sp.render(G)
+    o = sp.outputs()
+    mlp = b.LidarMLP(*(_dev(w) for w in W))
+    azd, eld = _dev(lid.ray_az.astype(np.float32)), _dev(lid.ray_el.astype(np.float32))
+    dF = torch.zeros_like(o["feat"])
+    b.lidar_decode_bwd(o["feat"], azd, eld, mlp, _dev(wI), _dev(wP), dF, {})
+    grads = b.zeros_like_grads(G)
+    zero = torch.zeros(R, device="cuda")
+    sp.raster_bwd(G, dF, zero, zero, grads)
+    torch.cuda.synchronize()
+    for name, r in ref.items():
+        a = getattr(grads, name).cpu().numpy().astype(np.float64)
+        nr = np.linalg.norm(r)
+        if nr == 0:
+            continue
+        assert np.linalg.norm(a - r) / nr <= 1e-3, (name, np.linalg.norm(a - r) / nr)
