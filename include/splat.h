@@ -503,6 +503,57 @@ int splat_lidar_decode_bwd(int64_t n_rays, const float* feat, const float* ray_a
                            float* d_feat, const SplatLidarMLPGrads* d_mlp, void* ws, size_t ws_bytes,
                            void* stream);
 
+/* ---- camera decoder (Sec. 3.2; the training-details appendix: two residual blocks of width 32,
+ * kernel size 3, then a final linear layer) ------------------------------------------------------
+ * Per pixel x = [F, d, e]: the camera's rendered feature row F (its first n_feat channels), the
+ * unit world-frame direction d of the ray through the pixel centre (camera frame
+ * ((u+1/2-cx)/fx, (v+1/2-cy)/fy, 1) normalised, rotated by R^T), and the camera embedding e.
+ *   h0 = ReLU(conv_in(x)),  r_k = ReLU(conv_k1(h_{k-1})),  h_k = ReLU(h_{k-1} + conv_k2(r_k))
+ *   (M, b) = W_out h_2 + b_out,   I = M * F[0:3] + b            (k = 1, 2)
+ * Convolutions: 3x3, stride 1, zero padding, bias, cross-correlation.  Weights are device
+ * arrays in OIHW order; trained values are not needed to define the op.  Arithmetic is FP32
+ * throughout (the 3x3 convolutions on the matrix cores). */
+typedef struct SplatCameraCNN {
+  int32_t n_feat;             /* D_f >= 3 (F[0:3] is the colour); D_f + 3 + n_embed <= 32      */
+  int32_t n_embed;            /* E, 0..8                                                       */
+  const float* embed;         /* [E] this camera's embedding                                   */
+  const float* w_in;          /* [32, D_f + 3 + E, 3, 3]                                       */
+  const float* b_in;          /* [32]                                                          */
+  const float* w_block[4];    /* [32, 32, 3, 3]: block 1 conv 1, conv 2, block 2 conv 1, conv 2 */
+  const float* b_block[4];    /* [32]                                                          */
+  const float* w_out;         /* [6, 32]: rows 0-2 M, rows 3-5 b                               */
+  const float* b_out;         /* [6]                                                           */
+} SplatCameraCNN;
+
+/* Gradient accumulators (+=) shaped like SplatCameraCNN's arrays; NULL skips one. */
+typedef struct SplatCameraCNNGrads {
+  float* embed;
+  float* w_in;
+  float* b_in;
+  float* w_block[4];
+  float* b_block[4];
+  float* w_out;
+  float* b_out;
+} SplatCameraCNNGrads;
+
+/* Workspace of the camera decoder for a width x height camera: the activations (six images of
+ * 32 channels) that the adjoint reads, three gradient images and partial sums.  0 = invalid. */
+size_t splat_camera_decode_workspace_bytes(int32_t width, int32_t height);
+/* Decodes one camera: feat [H*W, C] (C = cam->n_channels, or n_feat when that is 0; rows as the
+ * camera rasteriser writes them) -> image [H*W, 3].  Writes the activations into ws (caller-
+ * owned, 256-byte aligned, >= splat_camera_decode_workspace_bytes, SPLAT_ERR_CAPACITY
+ * otherwise).  Invalid sizes or missing arrays give SPLAT_ERR_INVALID_ARG.  Stream-ordered,
+ * allocates nothing. */
+int splat_camera_decode(const SplatCamera* cam, const float* feat, const SplatCameraCNN* cnn, float* image,
+                        void* ws, size_t ws_bytes, void* stream);
+/* Adjoint of splat_camera_decode.  d_image [H*W, 3] -> d_feat [H*W, C] (+=, or NULL) and the
+ * weight and embedding gradients (+=).  ws must hold what the last splat_camera_decode with the
+ * same camera, features and weights wrote.  Weight gradients are sums over pixels added in a
+ * fixed order (deterministic).  Stream-ordered, allocates nothing. */
+int splat_camera_decode_bwd(const SplatCamera* cam, const float* feat, const SplatCameraCNN* cnn,
+                            const float* d_image, float* d_feat, const SplatCameraCNNGrads* d_cnn, void* ws,
+                            size_t ws_bytes, void* stream);
+
 /* ---- MCMC regulariser (training-details appendix) -------------------------------------------
  * The opacity and scale regularisation of the MCMC densification strategy:
  *   L = lambda_o sum_i |o_i| + lambda_s sum_i sum_j |sqrt(eig_j(Sigma_i))|

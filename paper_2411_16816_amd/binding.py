@@ -68,6 +68,9 @@ def _declare(lib):
         "splat_lidar_decode": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp]),
         "splat_lidar_decode_workspace_bytes": (C.c_size_t, [i64, i32]),
         "splat_lidar_decode_bwd": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+        "splat_camera_decode_workspace_bytes": (C.c_size_t, [i32, i32]),
+        "splat_camera_decode": (C.c_int, [vp, vp, vp, vp, vp, C.c_size_t, vp]),
+        "splat_camera_decode_bwd": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -717,3 +720,67 @@ def lidar_decode_bwd(feat, az, el, mlp: LidarMLP, d_int, d_drop, d_feat=None, d_
     check(lib.splat_lidar_decode_bwd(n, _ptr(feat), _ptr(az), _ptr(el), C.byref(mlp.struct()), _ptr(d_int),
                                      _ptr(d_drop), _ptr(d_feat), C.byref(g), C.c_void_p(ws.data_ptr()), ws.numel(),
                                      _stream(stream)), "splat_lidar_decode_bwd")
+
+
+# ----------------------------------------------------------------------------------------
+# camera decoder (splat_camera_decode / splat_camera_decode_bwd)
+# ----------------------------------------------------------------------------------------
+@dataclass
+class CameraCNN:
+    """Camera decoder weights (float32 device): embed [E], w_in [32, D_f+3+E, 3, 3], b_in [32],
+    w_block / b_block: four [32, 32, 3, 3] / [32], w_out [6, 32], b_out [6]."""
+    embed: torch.Tensor
+    w_in: torch.Tensor
+    b_in: torch.Tensor
+    w_block: list
+    b_block: list
+    w_out: torch.Tensor
+    b_out: torch.Tensor
+
+    @property
+    def n_embed(self) -> int:
+        return int(self.embed.numel())
+
+    @property
+    def n_feat(self) -> int:
+        return int(self.w_in.shape[1]) - 3 - self.n_embed
+
+    def struct(self) -> st.SplatCameraCNN:
+        m = st.SplatCameraCNN()
+        m.n_feat, m.n_embed = self.n_feat, self.n_embed
+        m.embed, m.w_in, m.b_in = _ptr(self.embed), _ptr(self.w_in), _ptr(self.b_in)
+        for k in range(4):
+            m.w_block[k], m.b_block[k] = self.w_block[k].data_ptr(), self.b_block[k].data_ptr()
+        m.w_out, m.b_out = _ptr(self.w_out), _ptr(self.b_out)
+        return m
+
+
+def camera_decode_workspace(cam, device="cuda") -> torch.Tensor:
+    nb = int(load().splat_camera_decode_workspace_bytes(int(cam.width), int(cam.height)))
+    if nb == 0:
+        raise SplatError("splat_camera_decode_workspace_bytes returned 0")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def camera_decode(cam, feat: torch.Tensor, cnn: CameraCNN, ws: torch.Tensor, stream=None) -> torch.Tensor:
+    """Decoded image [H*W, 3] of the camera's feature rows feat [H*W * C]; ws from
+    camera_decode_workspace (keeps the activations for camera_decode_bwd)."""
+    image = torch.empty(int(cam.width) * int(cam.height) * 3, dtype=torch.float32, device=feat.device)
+    check(load().splat_camera_decode(C.byref(st.camera_struct(cam)), _ptr(feat), C.byref(cnn.struct()), _ptr(image),
+                                     C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "splat_camera_decode")
+    return image
+
+
+def camera_decode_bwd(cam, feat, cnn: CameraCNN, d_image, d_feat, d_cnn: dict, ws: torch.Tensor, stream=None):
+    """Adds dL/dfeat to d_feat and the weight / embedding gradients to d_cnn (same keys as
+    CameraCNN's fields; w_block and b_block lists of four)."""
+    g = st.SplatCameraCNNGrads()
+    g.embed, g.w_in, g.b_in = _ptr(d_cnn.get("embed")), _ptr(d_cnn.get("w_in")), _ptr(d_cnn.get("b_in"))
+    for k in range(4):
+        wb, bb = d_cnn.get("w_block"), d_cnn.get("b_block")
+        g.w_block[k] = None if wb is None else wb[k].data_ptr()
+        g.b_block[k] = None if bb is None else bb[k].data_ptr()
+    g.w_out, g.b_out = _ptr(d_cnn.get("w_out")), _ptr(d_cnn.get("b_out"))
+    check(load().splat_camera_decode_bwd(C.byref(st.camera_struct(cam)), _ptr(feat), C.byref(cnn.struct()),
+                                         _ptr(d_image), _ptr(d_feat), C.byref(g), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                         _stream(stream)), "splat_camera_decode_bwd")

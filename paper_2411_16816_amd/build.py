@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsplat.so")
-SOURCES = ["api.hip", "project.hip", "binsort.hip", "raster.hip", "compose.hip", "points.hip", "mcmc.hip", "decoders.hip"]
+SOURCES = ["api.hip", "project.hip", "binsort.hip", "raster.hip", "compose.hip", "points.hip", "mcmc.hip", "decoders.hip", "cnn.hip"]
 ARCH = os.environ.get("SPLAT_OFFLOAD_ARCH", "gfx950")
 
 # packed FP32 instructions are disabled for every HIP translation unit

@@ -150,3 +150,14 @@ class SplatLidarMLP(C.Structure):
 
 class SplatLidarMLPGrads(C.Structure):
     _fields_ = [("w1", C.c_void_p), ("b1", C.c_void_p), ("w2", C.c_void_p), ("b2", C.c_void_p)]
+
+
+class SplatCameraCNN(C.Structure):
+    _fields_ = [("n_feat", C.c_int32), ("n_embed", C.c_int32), ("embed", C.c_void_p), ("w_in", C.c_void_p),
+                ("b_in", C.c_void_p), ("w_block", C.c_void_p * 4), ("b_block", C.c_void_p * 4), ("w_out", C.c_void_p),
+                ("b_out", C.c_void_p)]
+
+
+class SplatCameraCNNGrads(C.Structure):
+    _fields_ = [("embed", C.c_void_p), ("w_in", C.c_void_p), ("b_in", C.c_void_p), ("w_block", C.c_void_p * 4),
+                ("b_block", C.c_void_p * 4), ("w_out", C.c_void_p), ("b_out", C.c_void_p)]

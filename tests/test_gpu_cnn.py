@@ -1,0 +1,149 @@
+"""Camera decoder (splat_camera_decode / splat_camera_decode_bwd; Sec. 3.2, training-details
+appendix) through the C ABI against the FP64 oracle (oracle/decoders.py) on the same float32
+inputs: the decoded image within 1e-4 relative / 1e-5 absolute; dL/dF, the embedding and every
+weight gradient within 1e-4 of their norm.  Images ragged against the 16 x 16 and 16 x 8 tiles,
+without an embedding, a 1080p camera checked on crops (the network's receptive field has
+radius 5, so the oracle on a crop with a 5-pixel margin is exact inside it), edge cases."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import decoders as dec
+from scenes import synthetic as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _binding():
+    from paper_2411_16816_amd import binding
+    binding.load()
+    return binding
+
+
+def _weights(rng, Df, E):
+    cin = Df + 3 + E
+    return {"embed": rng.normal(0, 1.0, E), "w_in": rng.normal(0, np.sqrt(2.0 / (9 * cin)), (32, cin, 3, 3)),
+            "b_in": rng.normal(0, 0.05, 32),
+            "w_block": [rng.normal(0, 0.5 * np.sqrt(2.0 / 288), (32, 32, 3, 3)) for _ in range(4)],
+            "b_block": [rng.normal(0, 0.05, 32) for _ in range(4)],
+            "w_out": rng.normal(0, np.sqrt(1.0 / 32), (6, 32)), "b_out": rng.normal(0, 0.1, 6)}
+
+
+def _f32(x):
+    return np.asarray(x, np.float32)
+
+
+def _dev_cnn(b, W):
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(_f32(a))).cuda()
+    return b.CameraCNN(d(W["embed"]), d(W["w_in"]), d(W["b_in"]), [d(w) for w in W["w_block"]],
+                       [d(x) for x in W["b_block"]], d(W["w_out"]), d(W["b_out"]))
+
+
+def _oracle(F, cam, W, dI=None):
+    t = lambda a: torch.tensor(_f32(a), dtype=torch.float64, requires_grad=dI is not None)
+    leaves = {"F": t(F), "embed": t(W["embed"]), "w_in": t(W["w_in"]), "b_in": t(W["b_in"]),
+              "w_block": [t(w) for w in W["w_block"]], "b_block": [t(x) for x in W["b_block"]],
+              "w_out": t(W["w_out"]), "b_out": t(W["b_out"])}
+    I = dec.camera_cnn(leaves["F"], cam, leaves["embed"], leaves["w_in"], leaves["b_in"], leaves["w_block"],
+                       leaves["b_block"], leaves["w_out"], leaves["b_out"])
+    if dI is None:
+        return I.detach().numpy(), None
+    (I * torch.from_numpy(dI.astype(np.float64))).sum().backward()
+    g = {k: (v.grad.numpy() if not isinstance(v, list) else [x.grad.numpy() for x in v]) for k, v in leaves.items()}
+    return I.detach().numpy(), g
+
+
+def _close(a, r, what):
+    err = np.abs(a.astype(np.float64) - r) / (1e-5 + 1e-4 * np.abs(r))
+    assert float(err.max(initial=0.0)) <= 1.0, (what, float(err.max()))
+
+
+def _rel(a, r, what, tol=1e-4):
+    nr = np.linalg.norm(r)
+    d = np.linalg.norm(a.astype(np.float64) - r)
+    assert d <= tol * max(nr, 1e-30), (what, d / max(nr, 1e-30))
+
+
+def _camera(w, h, yaw=20.0, n_ch=16):
+    return S.make_camera((0, 0, 1.5), yaw, w, h, 0.8 * w, n_channels=n_ch)
+
+
+@pytest.mark.parametrize("w,h,E", [(37, 23, 8), (64, 48, 8), (16, 16, 8), (21, 9, 0), (1, 1, 8)])
+def test_camera_decoder_matches_oracle(w, h, E):
+    b = _binding()
+    rng = np.random.default_rng(w * 100 + h + E)
+    cam = _camera(w, h)
+    Df = 16
+    print(f"[cnn] {w}x{h} E={E}", flush=True)
+    W = _weights(rng, Df, E)
+    F = _f32(rng.normal(size=(h, w, Df)))
+    dI = _f32(rng.normal(size=(h, w, 3)))
+    cnn = _dev_cnn(b, W)
+    ws = b.camera_decode_workspace(cam)
+    Fd = torch.from_numpy(F.reshape(-1)).cuda()
+    I = b.camera_decode(cam, Fd, cnn, ws)
+    dF = torch.zeros_like(Fd)
+    dcnn = {"embed": torch.zeros_like(cnn.embed), "w_in": torch.zeros_like(cnn.w_in), "b_in": torch.zeros_like(cnn.b_in),
+            "w_block": [torch.zeros_like(x) for x in cnn.w_block], "b_block": [torch.zeros_like(x) for x in cnn.b_block],
+            "w_out": torch.zeros_like(cnn.w_out), "b_out": torch.zeros_like(cnn.b_out)}
+    b.camera_decode_bwd(cam, Fd, cnn, torch.from_numpy(dI.reshape(-1)).cuda(), dF, dcnn, ws)
+    torch.cuda.synchronize()
+    ref, g = _oracle(F, cam, W, dI)
+    _close(I.cpu().numpy().reshape(h, w, 3), ref, "image")
+    _rel(dF.cpu().numpy().reshape(h, w, Df), g["F"], "d_feat")
+    for k in ("w_in", "b_in", "w_out", "b_out") + (("embed",) if E else ()):
+        _rel(dcnn[k].cpu().numpy(), g[k], k)
+    for j in range(4):
+        _rel(dcnn["w_block"][j].cpu().numpy(), g["w_block"][j], f"w_block{j}")
+        _rel(dcnn["b_block"][j].cpu().numpy(), g["b_block"][j], f"b_block{j}")
+
+
+def _crop_ref(F, cam, W, x0, y0, cw, chh):
+    m = 5
+    xs, ys = max(0, x0 - m), max(0, y0 - m)
+    xe, ye = min(cam.width, x0 + cw + m), min(cam.height, y0 + chh + m)
+    sub = dataclasses.replace(cam, width=xe - xs, height=ye - ys, cx=cam.cx - xs, cy=cam.cy - ys)
+    I, _ = _oracle(F[ys:ye, xs:xe], sub, W)
+    return I[y0 - ys:y0 - ys + chh, x0 - xs:x0 - xs + cw]
+
+
+def test_camera_decoder_1080p_on_crops():
+    b = _binding()
+    rng = np.random.default_rng(11)
+    cam = S.headline(n=1000).cameras[0]
+    Df = cam.n_channels
+    h, w = cam.height, cam.width
+    print(f"[cnn] {w}x{h}", flush=True)
+    W = _weights(rng, Df, 8)
+    F = _f32(rng.normal(size=(h, w, Df)))
+    cnn = _dev_cnn(b, W)
+    ws = b.camera_decode_workspace(cam)
+    I = b.camera_decode(cam, torch.from_numpy(F.reshape(-1)).cuda(), cnn, ws)
+    torch.cuda.synchronize()
+    I = I.cpu().numpy().reshape(h, w, 3)
+    crops = [(0, 0), (w - 24, h - 24), (w - 24, 0), (0, h - 24)] + \
+        [(int(rng.integers(5, w - 30)), int(rng.integers(5, h - 30))) for _ in range(4)]
+    for x0, y0 in crops:
+        _close(I[y0:y0 + 24, x0:x0 + 24], _crop_ref(F, cam, W, x0, y0, 24, 24), f"crop {x0},{y0}")
+
+
+def test_camera_decoder_edge_cases():
+    b = _binding()
+    rng = np.random.default_rng(12)
+    cam = _camera(8, 8)
+    W = _weights(rng, 16, 8)
+    cnn = _dev_cnn(b, W)
+    ws = b.camera_decode_workspace(cam)
+    F = torch.zeros(8 * 8 * 16, device="cuda")
+    with pytest.raises(b.SplatError):      # workspace too small
+        b.camera_decode(cam, F, cnn, ws[:1024])
+    wide = _dev_cnn(b, _weights(rng, 16, 14))   # 16 + 3 + 14 > 32 input channels
+    with pytest.raises(b.SplatError):
+        b.camera_decode(cam, F, wide, ws)
+    # zero features: I = b of the head at every pixel depends only on directions and embedding
+    I = b.camera_decode(cam, F, cnn, ws)
+    torch.cuda.synchronize()
+    ref, _ = _oracle(np.zeros((8, 8, 16), np.float32), cam, W)
+    _close(I.cpu().numpy().reshape(8, 8, 3), ref, "zero features")
