@@ -37,12 +37,12 @@ sys.path.insert(0, ROOT)
 METRIC = "Mrays/s fwd+bwd, 128x2048 lidar + 1080p camera; batched vs plain at 1e-4 err"
 
 # MI355X published peaks
-PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3            # vector FP32, datasheet (packed FMA)
+PEAK_FP32_TFLOPS = 157.3            # FP32, datasheet (vector packed FMA; also the dense FP32 matrix-core rate)
 PEAK_HBM_GBS = 8000.0               # HBM3E, datasheet
 SEED_COMPOSE = 16816 + 11           # seed of the composition workload
 SEED_POINTS = 16816 + 12            # seed of the lidar points-to-rays workload
 SEED_DECODER = 16816 + 13           # seed of the lidar decoder workload (weights, features)
+SEED_CNN = 16816 + 14               # seed of the camera decoder workload
 # algorithmic FP32 work per evaluated (ray, Gaussian) pair of the forward compositing loop:
 # Delta (6), sigma (9), exp (1), alpha (1), transmittance (2), weight (1), feature and depth
 # blends (2 C + 2), plus the lidar range correction (2) and azimuth reduction (3);
@@ -305,6 +305,7 @@ def main():
         out["points_to_rays"] = points_bench(args, dev, lid)
         out["mcmc_regularizer"] = mcmc_bench(args, dev, G, g)
         out["lidar_decoder"] = decoder_bench(args, dev, lid)
+        out["camera_decoder"] = cnn_bench(args, dev, cam)
     agree = mode_agreement(results)
     if agree:
         out["agreement"] = agree
@@ -728,6 +729,76 @@ def decoder_bench(args, dev, lid):
     out["roofline"] = {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS}
     out["parity"] = {"rays": 2 * 4096, "max_err_over_tol": round(worst, 4), "pass": bool(worst <= 1.0)}
     return out
+
+
+def cnn_bench(args, dev, cam):
+    """Camera decoder (splat_camera_decode / _bwd) on the 1920 x 1080 camera, 16 feature channels
+    + direction + 8-float embedding, timed with HIP events around each call.  Algorithmic FLOP:
+    the five 3x3 convolutions (2 x 9 x C_in x 32 per pixel each, C_in = 27 for the stem) and the
+    1x1 head; the adjoint counts the input- and weight-gradient convolutions (twice the forward)
+    plus the head.  Against the FP32 matrix-core peak."""
+    import torch
+    from oracle import decoders as dec
+    from paper_2411_16816_amd import binding as B
+    rng = np.random.default_rng(SEED_CNN)
+    Df, E = cam.n_channels, 8
+    cin = Df + 3 + E
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
+    Wn = {"embed": rng.normal(0, 1, E), "w_in": rng.normal(0, np.sqrt(2 / (9 * cin)), (32, cin, 3, 3)),
+          "b_in": rng.normal(0, 0.05, 32), "w_block": [rng.normal(0, 0.5 * np.sqrt(2 / 288), (32, 32, 3, 3)) for _ in range(4)],
+          "b_block": [rng.normal(0, 0.05, 32) for _ in range(4)], "w_out": rng.normal(0, np.sqrt(1 / 32), (6, 32)),
+          "b_out": rng.normal(0, 0.1, 6)}
+    cnn = B.CameraCNN(d(Wn["embed"]), d(Wn["w_in"]), d(Wn["b_in"]), [d(w) for w in Wn["w_block"]],
+                      [d(x) for x in Wn["b_block"]], d(Wn["w_out"]), d(Wn["b_out"]))
+    H, W = cam.height, cam.width
+    n = H * W
+    F = d(rng.normal(size=n * Df))
+    dI = d(rng.normal(size=n * 3))
+    dF = torch.zeros_like(F)
+    dc = {"embed": torch.zeros_like(cnn.embed), "w_in": torch.zeros_like(cnn.w_in), "b_in": torch.zeros_like(cnn.b_in),
+          "w_block": [torch.zeros_like(x) for x in cnn.w_block], "b_block": [torch.zeros_like(x) for x in cnn.b_block],
+          "w_out": torch.zeros_like(cnn.w_out), "b_out": torch.zeros_like(cnn.b_out)}
+    ws = B.camera_decode_workspace(cam, dev)
+    for _ in range(max(1, args.warmup)):
+        I = B.camera_decode(cam, F, cnn, ws)
+        B.camera_decode_bwd(cam, F, cnn, dI, dF, dc, ws)
+    stream = torch.cuda.current_stream()
+    mk = lambda: torch.cuda.Event(enable_timing=True)
+    ev = [(mk(), mk(), mk()) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for e0, e1, e2 in ev:
+        e0.record(stream)
+        I = B.camera_decode(cam, F, cnn, ws)
+        e1.record(stream)
+        B.camera_decode_bwd(cam, F, cnn, dI, dF, dc, ws)
+        e2.record(stream)
+    torch.cuda.synchronize()
+    t_f = float(np.median([a.elapsed_time(b_) for a, b_, _ in ev])) * 1e-3
+    t_b = float(np.median([b_.elapsed_time(c) for _, b_, c in ev])) * 1e-3
+    conv_px = 2 * 9 * cin * 32 + 4 * 2 * 9 * 32 * 32
+    flop_f = n * (conv_px + 2 * 6 * 32 + 3 * 2)
+    flop_b = n * (2 * conv_px + 2 * 2 * 6 * 32)
+    # parity: a 24 x 24 crop (5-pixel margin: the receptive field) against the FP64 oracle
+    import dataclasses
+    x0, y0, m = 700, 500, 5
+    Fh = F.view(H, W, Df)[y0 - m:y0 + 24 + m, x0 - m:x0 + 24 + m].double().cpu()
+    sub = dataclasses.replace(cam, width=34, height=34, cx=cam.cx - (x0 - m), cy=cam.cy - (y0 - m))
+    with torch.no_grad():
+        ref = dec.camera_cnn(Fh, sub, Wn["embed"].astype(np.float32), Wn["w_in"].astype(np.float32),
+                             Wn["b_in"].astype(np.float32), [w.astype(np.float32) for w in Wn["w_block"]],
+                             [x.astype(np.float32) for x in Wn["b_block"]], Wn["w_out"].astype(np.float32),
+                             Wn["b_out"].astype(np.float32))[m:m + 24, m:m + 24].numpy()
+    got = I.view(H, W, 3)[y0:y0 + 24, x0:x0 + 24].double().cpu().numpy()
+    worst = float((np.abs(got - ref) / (1e-5 + 1e-4 * np.abs(ref))).max())
+    tf, tb = flop_f / t_f / 1e12, flop_b / t_b / 1e12
+    log(f"camera decoder 1080p: fwd {t_f * 1e3:.3f} ms ({tf:.1f} TFLOP/s), bwd {t_b * 1e3:.3f} ms ({tb:.1f} TFLOP/s)")
+    return {"workload": f"camera decoder on {W}x{H}: {Df} feature channels + direction + {E}-float embedding, "
+                        "3x3 stem, two residual blocks of width 32, 1x1 head",
+            "fwd_ms": round(t_f * 1e3, 4), "bwd_ms": round(t_b * 1e3, 4),
+            "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_FP32_TFLOPS,
+                         "fwd": {"achieved": round(tf, 2), "frac": round(tf / PEAK_FP32_TFLOPS, 4), "flop": int(flop_f)},
+                         "bwd": {"achieved": round(tb, 2), "frac": round(tb / PEAK_FP32_TFLOPS, 4), "flop": int(flop_b)}},
+            "parity": {"pixels": 576, "max_err_over_tol": round(worst, 4), "pass": bool(worst <= 1.0)}}
 
 
 def cpu_baseline(g, cam, lid, n_rays):

@@ -23,6 +23,7 @@
 //     registers, and a second kernel adds the workgroups' partial sums in a fixed order.
 //   * the stem input, the 1x1 head and their adjoints are per-pixel kernels.
 #include "kernels.hpp"
+#include "reduce.hpp"
 
 namespace splat {
 
@@ -36,6 +37,31 @@ constexpr int kHeadOut = 6 * kCC + 6;        // dW_out [6][32], db_out [6]
 constexpr int kCnnBlock = 128;               // per-pixel kernels with LDS contractions
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Stages an R x Cw pixel window of a 32-channel NHWC image whose top-left pixel is (y0, x0) into
+// LDS rows of kLS floats (zeros outside the image).  Every load of a thread is issued before its
+// first LDS store, so the window's global loads are all in flight at once.
+template <int R, int Cw>
+__device__ __forceinline__ void stage_window(const float* __restrict__ img, int H, int W, int y0, int x0, float* dst) {
+  constexpr int kVec = R * Cw * 8;
+  constexpr int kPer = (kVec + 255) / 256;
+  float4 v[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int i = threadIdx.x + 256 * j;
+    v[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i < kVec) {
+      const int pix = i >> 3, q = i & 7;
+      const int y = y0 + pix / Cw, x = x0 + pix % Cw;
+      if (y >= 0 && y < H && x >= 0 && x < W) v[j] = reinterpret_cast<const float4*>(img + ((int64_t)y * W + x) * 32)[q];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int i = threadIdx.x + 256 * j;
+    if (i < kVec) *reinterpret_cast<float4*>(&dst[(i >> 3) * kLS + (i & 7) * 4]) = v[j];
+  }
+}
 
 __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -66,17 +92,23 @@ __device__ __forceinline__ float conv_w(const ConvArgs& a, int cin, int cout, in
   return a.w[((cin * a.ci_n + cout) * 3 + (2 - ky)) * 3 + (2 - kx)];
 }
 
-__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
+constexpr int kFrag = 9 * 8 * 2 * 64;   // B fragments of one convolution: [tap][step][half][lane]
+
+// The B operands of every MFMA of k_conv3x3 in lane order, so that the convolution loads each
+// tap's fragments as coalesced rows (and flips / transposes the weights for the input gradient
+// here, once per launch, instead of per load).
+__global__ void k_conv_frag(ConvArgs a, float* __restrict__ frag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kFrag) return;
+  const int lane = i & 63, h = (i >> 6) & 1, s = (i >> 7) & 7, tap = i >> 10;
+  frag[i] = conv_w(a, 8 * (lane >> 4) + s, 16 * h + (lane & 15), tap / 3, tap % 3);
+}
+
+__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a, const float* __restrict__ frag) {
   __shared__ __align__(16) float s_in[kHalo * kHalo * kLS];
   const int tiles_x = (a.W + kTS - 1) / kTS;
   const int tx0 = (int)(blockIdx.x % tiles_x) * kTS, ty0 = (int)(blockIdx.x / tiles_x) * kTS;
-  for (int i = threadIdx.x; i < kHalo * kHalo * 8; i += 256) {
-    const int pix = i >> 3, q = i & 7;
-    const int y = ty0 + pix / kHalo - 1, x = tx0 + pix % kHalo - 1;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (y >= 0 && y < a.H && x >= 0 && x < a.W) v = reinterpret_cast<const float4*>(a.in + ((int64_t)y * a.W + x) * kCC)[q];
-    *reinterpret_cast<float4*>(&s_in[pix * kLS + q * 4]) = v;
-  }
+  stage_window<kHalo, kHalo>(a.in, a.H, a.W, ty0 - 1, tx0 - 1, s_in);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
@@ -85,26 +117,42 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int h = 0; h < 2; ++h) acc[r][h] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float bf[8][2], bn[8][2];
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) bf[s][h] = frag[(s * 2 + h) * 64 + lane];
+#pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
     const int ky = tap / 3, kx = tap % 3;
-    float bf[8][2];
+    // the next tap's fragments are in flight while this tap's MFMAs run
+    const int tn = tap < 8 ? tap + 1 : tap;
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
-      for (int h = 0; h < 2; ++h) bf[s][h] = conv_w(a, 8 * lk + s, 16 * h + li, ky, kx);
+      for (int h = 0; h < 2; ++h) bn[s][h] = frag[((tn * 8 + s) * 2 + h) * 64 + lane];
+    float av[4][8];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int py = wave * 4 + r;
       const float* src = &s_in[((py + ky) * kHalo + li + kx) * kLS + 8 * lk];
       const float4 a0 = *reinterpret_cast<const float4*>(src);
       const float4 a1 = *reinterpret_cast<const float4*>(src + 4);
-      const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        acc[r][0] = mfma4(av[s], bf[s][0], acc[r][0]);
-        acc[r][1] = mfma4(av[s], bf[s][1], acc[r][1]);
-      }
+      av[r][0] = a0.x; av[r][1] = a0.y; av[r][2] = a0.z; av[r][3] = a0.w;
+      av[r][4] = a1.x; av[r][5] = a1.y; av[r][6] = a1.z; av[r][7] = a1.w;
     }
+    // eight independent accumulators between two MFMAs on the same one
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        acc[r][0] = mfma4(av[r][s], bf[s][0], acc[r][0]);
+        acc[r][1] = mfma4(av[r][s], bf[s][1], acc[r][1]);
+      }
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) bf[s][h] = bn[s][h];
   }
   // D[i][j]: pixel column 4 lk + e of the row, output channel 16 h + li
 #pragma unroll
@@ -147,34 +195,24 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const float* __restrict__
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int tx0 = (tile % tiles_x) * kTS, ty0 = (tile / tiles_x) * kWTH;
     __syncthreads();   // the previous tile's LDS reads are done
-    for (int i = threadIdx.x; i < (kWTH + 2) * kHalo * 8; i += 256) {
-      const int pix = i >> 3, q = i & 7;
-      const int yy = ty0 + pix / kHalo - 1, xx = tx0 + pix % kHalo - 1;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = reinterpret_cast<const float4*>(x + ((int64_t)yy * W + xx) * kCC)[q];
-      *reinterpret_cast<float4*>(&s_x[pix * kLS + q * 4]) = v;
-    }
-    for (int i = threadIdx.x; i < kWTH * kTS * 8; i += 256) {
-      const int pix = i >> 3, q = i & 7;
-      const int yy = ty0 + pix / kTS, xx = tx0 + pix % kTS;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (yy < H && xx < W) v = reinterpret_cast<const float4*>(dy + ((int64_t)yy * W + xx) * kCC)[q];
-      *reinterpret_cast<float4*>(&s_dy[pix * kLS + q * 4]) = v;
-    }
+    stage_window<kWTH + 2, kHalo>(x, H, W, ty0 - 1, tx0 - 1, s_x);
+    stage_window<kWTH, kTS>(dy, H, W, ty0, tx0, s_dy);
     __syncthreads();
     for (int q = bg; q < kWTH * kTS; q += 8) accb += s_dy[q * kLS + bco];
+    // nine independent accumulators (output blocks: tap, input-channel half, output half)
+    // between two MFMAs on the same one
+#pragma unroll 2
+    for (int s = 0; s < kWTH * kTS / 4; ++s) {
+      const int pix = 4 * s + lk;
+      const int py = pix >> 4, px = pix & 15;
+      const float bv0 = s_dy[pix * kLS + li], bv1 = s_dy[pix * kLS + 16 + li];
 #pragma unroll
-    for (int m = 0; m < 9; ++m) {
-      const int t = wave + 4 * m;             // output block: tap, input-channel half, output half
-      const int tap = t >> 2, ch = (t >> 1) & 1, oh = t & 1;
-      const int ky = tap / 3, kx = tap % 3;
-#pragma unroll 4
-      for (int s = 0; s < kWTH * kTS / 4; ++s) {
-        const int pix = 4 * s + lk;
-        const int py = pix >> 4, px = pix & 15;
+      for (int m = 0; m < 9; ++m) {
+        const int t = wave + 4 * m;
+        const int tap = t >> 2, ch = (t >> 1) & 1, oh = t & 1;
+        const int ky = tap / 3, kx = tap % 3;
         const float av = s_x[((py + ky) * kHalo + px + kx) * kLS + 16 * ch + li];
-        const float bv = s_dy[pix * kLS + 16 * oh + li];
-        acc[m] = mfma4(av, bv, acc[m]);
+        acc[m] = mfma4(av, oh ? bv1 : bv0, acc[m]);
       }
     }
   }
@@ -198,29 +236,21 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const float* __restrict__
   }
 }
 
-// dW (OIHW, +=) and db (+=) of one convolution from the workgroups' partials, in workgroup order
-__global__ void k_conv_wsum(const float* __restrict__ partial, int n_blocks, int ci_n, int co_n, float* dw, float* db) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= kWOut) return;
-  float s = 0.f;
-  for (int b = 0; b < n_blocks; ++b) s += partial[(int64_t)b * kWOut + o];
-  if (o < 9 * kCC * kCC) {
-    const int tap = o / (kCC * kCC), ci = (o / kCC) % kCC, co = o % kCC;
-    if (dw && ci < ci_n && co < co_n) dw[(co * ci_n + ci) * 9 + tap] += s;
-  } else {
-    const int co = o - 9 * kCC * kCC;
-    if (db && co < co_n) db[co] += s;
+// dW (OIHW, +=) and db (+=) of one convolution from the column sums of the partials
+struct ConvGradStore {
+  float* dw;
+  float* db;
+  int ci_n, co_n;
+  __device__ void operator()(int o, float s) const {
+    if (o < 9 * kCC * kCC) {
+      const int tap = o / (kCC * kCC), ci = (o / kCC) % kCC, co = o % kCC;
+      if (dw && ci < ci_n && co < co_n) dw[(co * ci_n + ci) * 9 + tap] += s;
+    } else {
+      const int co = o - 9 * kCC * kCC;
+      if (db && co < co_n) db[co] += s;
+    }
   }
-}
-
-// dst[o] += sum over blocks of partial[b * stride + o], o < n_out, in block order
-__global__ void k_sum_partials(const float* __restrict__ partial, int stride, int n_blocks, int n_out, float* dst) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= n_out || !dst) return;
-  float s = 0.f;
-  for (int b = 0; b < n_blocks; ++b) s += partial[(int64_t)b * stride + o];
-  dst[o] += s;
-}
+};
 
 struct CnnGeo {
   float R[9];         // world -> camera rotation
@@ -263,26 +293,60 @@ __global__ void k_cnn_input(const float* __restrict__ feat, int C, int Df, int E
 __global__ __launch_bounds__(256) void k_cnn_input_bwd(const float* __restrict__ dx0, int64_t n, int C, int Df, int E,
                                                         float* __restrict__ d_feat, float* __restrict__ partial_e) {
   __shared__ float s_e[256][9];
+  __shared__ float s_p[8][9];
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   float e[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) e[k] = 0.f;
   if (p < n) {
     const float* src = dx0 + p * kCC;
+    float v[kCC];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {   // every load issued before any store
+      const float4 x = reinterpret_cast<const float4*>(src)[q];
+      v[4 * q] = x.x;
+      v[4 * q + 1] = x.y;
+      v[4 * q + 2] = x.z;
+      v[4 * q + 3] = x.w;
+    }
     if (d_feat) {
       float* row = d_feat + p * C;
-      for (int k = 0; k < Df; ++k) row[k] += src[k];
+      if (((C | Df) & 3) == 0) {   // uniform: 16-byte rows
+        float4 old[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (4 * q < Df) old[q] = reinterpret_cast<const float4*>(row)[q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (4 * q < Df)
+            reinterpret_cast<float4*>(row)[q] =
+                make_float4(old[q].x + v[4 * q], old[q].y + v[4 * q + 1], old[q].z + v[4 * q + 2], old[q].w + v[4 * q + 3]);
+      } else {
+        float old[kCC];
+#pragma unroll
+        for (int k = 0; k < kCC; ++k) old[k] = k < Df ? row[k] : 0.f;
+#pragma unroll
+        for (int k = 0; k < kCC; ++k)
+          if (k < Df) row[k] = old[k] + v[k];
+      }
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < E) e[k] = src[Df + 3 + k];
+    for (int j = 0; j < 8; ++j)
+      if (j < E) e[j] = src[Df + 3 + j];
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) s_e[threadIdx.x][k] = e[k];
   __syncthreads();
+  if (threadIdx.x < 64) {   // 8 slices of 32 rows per embedding entry, then the 8 slices in order
+    const int k = threadIdx.x & 7, part = threadIdx.x >> 3;
+    float s = 0.f;
+    for (int t = 32 * part; t < 32 * part + 32; ++t) s += s_e[t][k];
+    s_p[part][k] = s;
+  }
+  __syncthreads();
   if (threadIdx.x < 8) {
     float s = 0.f;
-    for (int t = 0; t < 256; ++t) s += s_e[t][threadIdx.x];
+    for (int part = 0; part < 8; ++part) s += s_p[part][threadIdx.x];
     partial_e[(int64_t)blockIdx.x * 8 + threadIdx.x] = s;
   }
 }
@@ -424,6 +488,7 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_head_bwd(const float* __restr
 struct CnnWs {
   float* act[6];   // x0, h0, r1, h1, r2, h2
   float* g[3];     // gradient buffers
+  float* frag;     // B fragments of the convolution being launched
   float* partial;  // partial sums
   size_t bytes;
 };
@@ -446,6 +511,8 @@ inline CnnWs carve_cnn(void* base, int W, int H) {
   char* b = (char*)base;
   for (int i = 0; i < 6; ++i, off += act) w.act[i] = (float*)(b + off);
   for (int i = 0; i < 3; ++i, off += act) w.g[i] = (float*)(b + off);
+  w.frag = (float*)(b + off);
+  off += (size_t)kFrag * sizeof(float);
   size_t part = (size_t)wgrad_blocks(W, H) * kWOut;
   const size_t hp = (size_t)head_blocks(n) * kHeadOut;
   const size_t ep = (size_t)input_bwd_blocks(n) * 8;
@@ -479,10 +546,12 @@ static CnnGeo cnn_geo(const SplatCamera* cam) {
 }
 
 static hipError_t conv(const float* in, float* out, const float* w, int ci_n, int co_n, int transpose,
-                       const float* bias, const float* addend, const float* mask, int relu, int W, int H, hipStream_t s) {
+                       const float* bias, const float* addend, const float* mask, int relu, int W, int H, float* frag,
+                       hipStream_t s) {
   ConvArgs a{in, out, w, ci_n, co_n, transpose, bias, addend, mask, relu, H, W};
   const int tiles = ((W + kTS - 1) / kTS) * ((H + kTS - 1) / kTS);
-  hipLaunchKernelGGL(k_conv3x3, dim3((unsigned)tiles), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_conv_frag, dim3((unsigned)(kFrag / 256)), dim3(256), 0, s, a, frag);
+  hipLaunchKernelGGL(k_conv3x3, dim3((unsigned)tiles), dim3(256), 0, s, a, (const float*)frag);
   return hipGetLastError();
 }
 
@@ -490,8 +559,7 @@ static hipError_t wgrad(const float* x, const float* dy, int ci_n, int co_n, flo
                         int H, hipStream_t s) {
   const int nb = wgrad_blocks(W, H);
   hipLaunchKernelGGL(k_conv3x3_wgrad, dim3((unsigned)nb), dim3(256), 0, s, x, dy, H, W, partial);
-  hipLaunchKernelGGL(k_conv_wsum, dim3((unsigned)((kWOut + 255) / 256)), dim3(256), 0, s, (const float*)partial, nb, ci_n,
-                     co_n, dw, db);
+  launch_column_sums((const float*)partial, kWOut, nb, kWOut, ConvGradStore{dw, db, ci_n, co_n}, s);
   return hipGetLastError();
 }
 
@@ -519,13 +587,14 @@ int splat_camera_decode(const SplatCamera* cam, const float* feat, const SplatCa
   const int cin = cnn->n_feat + 3 + cnn->n_embed;
   hipLaunchKernelGGL(k_cnn_input, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, feat, C, cnn->n_feat, cnn->n_embed,
                      cnn->embed, cnn_geo(cam), w.act[0]);
-  hipError_t e = conv(w.act[0], w.act[1], cnn->w_in, cin, kCC, 0, cnn->b_in, nullptr, nullptr, 1, W, H, s);
+  hipError_t e = conv(w.act[0], w.act[1], cnn->w_in, cin, kCC, 0, cnn->b_in, nullptr, nullptr, 1, W, H, w.frag, s);
   for (int k = 0; k < 2 && e == hipSuccess; ++k) {
     float* hin = w.act[1 + 2 * k];
-    e = conv(hin, w.act[2 + 2 * k], cnn->w_block[2 * k], kCC, kCC, 0, cnn->b_block[2 * k], nullptr, nullptr, 1, W, H, s);
+    e = conv(hin, w.act[2 + 2 * k], cnn->w_block[2 * k], kCC, kCC, 0, cnn->b_block[2 * k], nullptr, nullptr, 1, W, H,
+             w.frag, s);
     if (e == hipSuccess)
       e = conv(w.act[2 + 2 * k], w.act[3 + 2 * k], cnn->w_block[2 * k + 1], kCC, kCC, 0, cnn->b_block[2 * k + 1], hin,
-               nullptr, 1, W, H, s);
+               nullptr, 1, W, H, w.frag, s);
   }
   if (e != hipSuccess) return SPLAT_ERR_DEVICE;
   hipLaunchKernelGGL(k_cnn_head, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, (const float*)w.act[5], feat, C,
@@ -550,9 +619,8 @@ int splat_camera_decode_bwd(const SplatCamera* cam, const float* feat, const Spl
   const int hb = head_blocks(n);
   hipLaunchKernelGGL(k_cnn_head_bwd, dim3((unsigned)hb), dim3(kCnnBlock), 0, s, (const float*)h2, feat, C, cnn->w_out,
                      cnn->b_out, n, d_image, d_feat, ga, w.partial);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, (const float*)w.partial, kHeadOut, hb, 6 * kCC, d_cnn->w_out);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, (const float*)(w.partial + 6 * kCC), kHeadOut, hb, 6,
-                     d_cnn->b_out);
+  launch_column_sums((const float*)w.partial, kHeadOut, hb, 6 * kCC, AddTo{d_cnn->w_out}, s);
+  launch_column_sums((const float*)(w.partial + 6 * kCC), kHeadOut, hb, 6, AddTo{d_cnn->b_out}, s);
   hipError_t e = hipGetLastError();
   // blocks, last first: dpre_k in `dp`, h_{k-1}, r_k the saved activations
   float* dp = ga;
@@ -565,11 +633,11 @@ int splat_camera_decode_bwd(const SplatCamera* cam, const float* feat, const Spl
     // conv_k2: its input r_k, output gradient dpre_k
     e = wgrad(r, dp, kCC, kCC, d_cnn->w_block[2 * k + 1], d_cnn->b_block[2 * k + 1], w.partial, W, H, s);
     if (e == hipSuccess)   // du_k = conv_k2^T(dpre_k) * [r_k > 0]
-      e = conv(dp, du, cnn->w_block[2 * k + 1], kCC, kCC, 1, nullptr, nullptr, r, 0, W, H, s);
+      e = conv(dp, du, cnn->w_block[2 * k + 1], kCC, kCC, 1, nullptr, nullptr, r, 0, W, H, w.frag, s);
     if (e == hipSuccess)   // conv_k1: input h_{k-1}, output gradient du_k
       e = wgrad(hin, du, kCC, kCC, d_cnn->w_block[2 * k], d_cnn->b_block[2 * k], w.partial, W, H, s);
     if (e == hipSuccess)   // dpre_{k-1} = (dpre_k + conv_k1^T(du_k)) * [h_{k-1} > 0]
-      e = conv(du, dnext, cnn->w_block[2 * k], kCC, kCC, 1, nullptr, dp, hin, 0, W, H, s);
+      e = conv(du, dnext, cnn->w_block[2 * k], kCC, kCC, 1, nullptr, dp, hin, 0, W, H, w.frag, s);
     spare[0] = dp;
     spare[1] = du;
     dp = dnext;
@@ -581,14 +649,12 @@ int splat_camera_decode_bwd(const SplatCamera* cam, const float* feat, const Spl
   // stem: dW_in, db_in; dx0 = conv_in^T(dpre0)
   if (e == hipSuccess) e = wgrad(x0, dp, cin, kCC, d_cnn->w_in, d_cnn->b_in, w.partial, W, H, s);
   float* dx0 = spare[0];
-  if (e == hipSuccess) e = conv(dp, dx0, cnn->w_in, cin, kCC, 1, nullptr, nullptr, nullptr, 0, W, H, s);
+  if (e == hipSuccess) e = conv(dp, dx0, cnn->w_in, cin, kCC, 1, nullptr, nullptr, nullptr, 0, W, H, w.frag, s);
   if (e != hipSuccess) return SPLAT_ERR_DEVICE;
   const int64_t eb = input_bwd_blocks(n);
   hipLaunchKernelGGL(k_cnn_input_bwd, dim3((unsigned)eb), dim3(256), 0, s, (const float*)dx0, n, C, cnn->n_feat,
                      cnn->n_embed, d_feat, w.partial);
-  if (cnn->n_embed > 0)
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, (const float*)w.partial, 8, (int)eb, cnn->n_embed,
-                       d_cnn->embed);
+  if (cnn->n_embed > 0) launch_column_sums((const float*)w.partial, 8, (int)eb, cnn->n_embed, AddTo{d_cnn->embed}, s);
   return hipGetLastError() == hipSuccess ? SPLAT_OK : SPLAT_ERR_DEVICE;
 }
 

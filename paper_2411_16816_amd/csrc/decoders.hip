@@ -14,6 +14,7 @@
 // chunks a persistent workgroup takes.  Every workgroup stores its partial sums, and a second
 // kernel adds them in workgroup order: deterministic, no atomics.
 #include "kernels.hpp"
+#include "reduce.hpp"
 
 namespace splat {
 
@@ -96,13 +97,19 @@ __global__ __launch_bounds__(kDecBlock) void k_lidar_decode(int64_t n, const flo
 }
 
 // LDS rows of one chunk of rays for the weight-gradient contraction
+// N-tiles of 16 columns of the x rows: [F (CM), d (3), 1] padded with zeros
+template <int CM>
+constexpr int dec_xtiles() { return (CM + 4 + 15) / 16; }
+
 template <int CM>
 struct DecStage {
-  float x[kDecBlock][CM + 4];            // [F, d] (padded)
+  float x[kDecBlock][16 * dec_xtiles<CM>() + 1];   // [F (zero beyond C), d, 1, 0...]
   float dpre[kDecBlock][kDecHidden + 1];
-  float h[kDecBlock][kDecHidden + 1];
+  float h[kDecBlock][3 * 16 + 1];                   // [h (32), 1, 0...]
   float dz[kDecBlock][2];
 };
+
+typedef float decx4 __attribute__((ext_vector_type(4)));
 
 template <int CM>
 __global__ __launch_bounds__(kDecBlock) void k_lidar_decode_bwd(int64_t n, const float* __restrict__ feat,
@@ -112,16 +119,19 @@ __global__ __launch_bounds__(kDecBlock) void k_lidar_decode_bwd(int64_t n, const
                                                                 const float* __restrict__ d_drop,
                                                                 float* __restrict__ d_feat, float* __restrict__ partial,
                                                                 int n_out) {
-  constexpr int NPT = (kDecHidden * (CM + 3) + 3 * kDecHidden + 2 + kDecBlock - 1) / kDecBlock;
+  constexpr int NXT = dec_xtiles<CM>();
+  constexpr int NTILE = 2 * NXT + 3;             // dW1|db1: 2 x NXT blocks; dW2|db2: 3 blocks
+  constexpr int NPW = (NTILE + 1) / 2;           // blocks per wavefront (two wavefronts)
   __shared__ DecWeights<CM> W;
   __shared__ DecStage<CM> S;
   stage_weights<CM>(W, m);
   const int C = m.n_feat, XC = C + 3;
   const int nw1 = kDecHidden * XC, nb1 = nw1 + kDecHidden, nw2 = nb1 + 2 * kDecHidden;
-  float acc[NPT];
+  decx4 acc[NPW];
 #pragma unroll
-  for (int i = 0; i < NPT; ++i) acc[i] = 0.f;
+  for (int i = 0; i < NPW; ++i) acc[i] = decx4{0.f, 0.f, 0.f, 0.f};
   const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
   for (int64_t base = (int64_t)blockIdx.x * kDecBlock; base < n; base += (int64_t)gridDim.x * kDecBlock) {
     __syncthreads();   // weights staged / the previous chunk's rows consumed
     const int64_t r = base + t;
@@ -148,6 +158,10 @@ __global__ __launch_bounds__(kDecBlock) void k_lidar_decode_bwd(int64_t n, const
       for (int k = 0; k < CM; ++k) S.x[t][k] = F[k];
 #pragma unroll
       for (int k = 0; k < 3; ++k) S.x[t][CM + k] = d[k];   // x = [F, d]: direction after the features
+#pragma unroll
+      for (int k = CM + 3; k < 16 * NXT; ++k) S.x[t][k] = k == CM + 3 ? 1.f : 0.f;   // ones: the bias
+#pragma unroll
+      for (int k = kDecHidden; k < 48; ++k) S.h[t][k] = k == kDecHidden ? 1.f : 0.f;
       float dF[CM];
 #pragma unroll
       for (int k = 0; k < CM; ++k) dF[k] = 0.f;
@@ -166,55 +180,79 @@ __global__ __launch_bounds__(kDecBlock) void k_lidar_decode_bwd(int64_t n, const
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < kDecHidden; ++j) S.dpre[t][j] = S.h[t][j] = 0.f;
+      for (int j = 0; j < kDecHidden; ++j) S.dpre[t][j] = 0.f;
+#pragma unroll
+      for (int j = 0; j < 48; ++j) S.h[t][j] = 0.f;
       S.dz[t][0] = S.dz[t][1] = 0.f;
 #pragma unroll
-      for (int k = 0; k < CM + 3; ++k) S.x[t][k] = 0.f;
+      for (int k = 0; k < 16 * NXT; ++k) S.x[t][k] = 0.f;
     }
     __syncthreads();
-    const int rows = (n - base) < kDecBlock ? (int)(n - base) : kDecBlock;
+    // Weight gradients: contractions over the chunk's rays on the matrix cores (16x16x4 FP32),
+    // K = 128 rays in 32 steps (rows 4 s + lk).  Blocks 0 .. 2 NXT - 1: [dW1 | db1] =
+    // dpre^T [x, 1] (M: hidden 16 jh .. +15, N: x columns 16 nt .. +15); blocks 2 NXT .. +2:
+    // [dW2 | db2] = dz^T [h, 1] (M: the two outputs padded to 16, N: h columns 16 nt .. +15).
 #pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-      const int o = t + i * kDecBlock;
-      if (o >= n_out) break;
-      float s = 0.f;
-      if (o < nw1) {                      // dW1[j][k] = sum dpre_j x_k
-        const int j = o / XC, k = o % XC;
-        const int kx = k < C ? k : CM + (k - C);
-        for (int q = 0; q < rows; ++q) s = fmaf(S.dpre[q][j], S.x[q][kx], s);
-      } else if (o < nb1) {               // db1[j] = sum dpre_j
-        const int j = o - nw1;
-        for (int q = 0; q < rows; ++q) s += S.dpre[q][j];
-      } else if (o < nw2) {               // dW2[c][j] = sum dz_c h_j
-        const int c = (o - nb1) / kDecHidden, j = (o - nb1) % kDecHidden;
-        for (int q = 0; q < rows; ++q) s = fmaf(S.dz[q][c], S.h[q][j], s);
-      } else {                            // db2[c] = sum dz_c
-        const int c = o - nw2;
-        for (int q = 0; q < rows; ++q) s += S.dz[q][c];
+    for (int i = 0; i < NPW; ++i) {
+      const int b = wave + 2 * i;
+      if (b >= NTILE) break;
+#pragma unroll 4
+      for (int s = 0; s < kDecBlock / 4; ++s) {
+        const int q = 4 * s + lk;
+        float av, bv;
+        if (b < 2 * NXT) {
+          const int jh = b / NXT, nt = b % NXT;
+          av = S.dpre[q][16 * jh + li];
+          bv = S.x[q][16 * nt + li];
+        } else {
+          const int nt = b - 2 * NXT;
+          av = li < 2 ? S.dz[q][li] : 0.f;
+          bv = S.h[q][16 * nt + li];
+        }
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i], 0, 0, 0);
       }
-      acc[i] += s;
     }
   }
+  // D[i][j] of a block: lane j + 16 (i / 4), element i % 4
+  float* dst = partial + (int64_t)blockIdx.x * n_out;
 #pragma unroll
-  for (int i = 0; i < NPT; ++i) {
-    const int o = t + i * kDecBlock;
-    if (o < n_out) partial[(int64_t)blockIdx.x * n_out + o] = acc[i];
+  for (int i = 0; i < NPW; ++i) {
+    const int b = wave + 2 * i;
+    if (b >= NTILE) break;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 4 * lk + e;
+      const float v = acc[i][e];
+      if (b < 2 * NXT) {
+        const int jh = b / NXT, nt = b % NXT;
+        const int j = 16 * jh + row, col = 16 * nt + li;
+        if (col < C) dst[j * XC + col] = v;                                 // feature columns of W1
+        else if (col >= CM && col < CM + 3) dst[j * XC + C + (col - CM)] = v;   // direction columns
+        else if (col == CM + 3) dst[nw1 + j] = v;                         // b1
+      } else {
+        const int nt = b - 2 * NXT;
+        const int c = row, col = 16 * nt + li;
+        if (c < 2) {
+          if (col < kDecHidden) dst[nb1 + c * kDecHidden + col] = v;      // W2
+          else if (col == kDecHidden) dst[nw2 + c] = v;                   // b2
+        }
+      }
+    }
   }
 }
 
-// weight gradients (+=): the workgroups' partial sums added in workgroup order
-__global__ void k_lidar_decode_wsum(const float* __restrict__ partial, int n_blocks, int n_out, int C,
-                                    SplatLidarMLPGrads g) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= n_out) return;
-  float s = 0.f;
-  for (int b = 0; b < n_blocks; ++b) s += partial[(int64_t)b * n_out + o];
-  const int nw1 = kDecHidden * (C + 3), nb1 = nw1 + kDecHidden, nw2 = nb1 + 2 * kDecHidden;
-  if (o < nw1) { if (g.w1) g.w1[o] += s; }
-  else if (o < nb1) { if (g.b1) g.b1[o - nw1] += s; }
-  else if (o < nw2) { if (g.w2) g.w2[o - nb1] += s; }
-  else if (g.b2) g.b2[o - nw2] += s;
-}
+// weight gradients (+=) from the column sums of the workgroups' partials
+struct MlpGradStore {
+  SplatLidarMLPGrads g;
+  int C;
+  __device__ void operator()(int o, float s) const {
+    const int nw1 = kDecHidden * (C + 3), nb1 = nw1 + kDecHidden, nw2 = nb1 + 2 * kDecHidden;
+    if (o < nw1) { if (g.w1) g.w1[o] += s; }
+    else if (o < nb1) { if (g.b1) g.b1[o - nw1] += s; }
+    else if (o < nw2) { if (g.w2) g.w2[o - nb1] += s; }
+    else if (g.b2) g.b2[o - nw2] += s;
+  }
+};
 
 static int bwd_blocks(int64_t n) {
   int64_t b = div_up(n, kDecBlock);
@@ -267,8 +305,7 @@ int splat_lidar_decode_bwd(int64_t n_rays, const float* feat, const float* ray_a
   float* partial = (float*)ws;
   SPLAT_DEC_DISPATCH(mlp->n_feat, k_lidar_decode_bwd, dim3((unsigned)nb), dim3(kDecBlock), 0, s, n_rays, feat,
                      ray_az, ray_el, *mlp, d_intensity, d_drop_prob, d_feat, partial, n_out);
-  hipLaunchKernelGGL(k_lidar_decode_wsum, dim3((unsigned)div_up(n_out, 256)), dim3(256), 0, s, (const float*)partial, nb,
-                     n_out, mlp->n_feat, *d_mlp);
+  launch_column_sums((const float*)partial, n_out, nb, n_out, MlpGradStore{*d_mlp, mlp->n_feat}, s);
   return hipGetLastError() == hipSuccess ? SPLAT_OK : SPLAT_ERR_DEVICE;
 }
 
