@@ -43,6 +43,7 @@ SEED_COMPOSE = 16816 + 11           # seed of the composition workload
 SEED_POINTS = 16816 + 12            # seed of the lidar points-to-rays workload
 SEED_DECODER = 16816 + 13           # seed of the lidar decoder workload (weights, features)
 SEED_CNN = 16816 + 14               # seed of the camera decoder workload
+SEED_RELOC = 16816 + 15             # seed of the relocation workload (dead set, draws)
 # algorithmic FP32 work per evaluated (ray, Gaussian) pair of the forward compositing loop:
 # Delta (6), sigma (9), exp (1), alpha (1), transmittance (2), weight (1), feature and depth
 # blends (2 C + 2), plus the lidar range correction (2) and azimuth reduction (3);
@@ -664,11 +665,38 @@ def mcmc_bench(args, dev, G, g):
         L = float(mcmc.regulariser(g.opacities, g.log_scales, g.quats))
     err = abs(float(val) / args.steps - L) / L
     log(f"mcmc_regularizer: {g.n} Gaussians, {sec * 1e3:.4f} ms ({ach:.0f} GB/s), value rel err {err:.2e}")
-    return {"workload": f"{g.n} Gaussians of the step, value + opacity / log-scale gradients",
-            "ms": round(sec * 1e3, 4), "bytes_per_gaussian": 48,
-            "roofline": {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS, "achieved": round(ach, 1),
-                         "frac": round(ach / PEAK_HBM_GBS, 4)},
-            "parity": {"value_rel_err": float(f"{err:.3g}"), "pass": bool(err <= 1e-4)}}
+    out = {"workload": f"{g.n} Gaussians of the step, value + opacity / log-scale gradients",
+           "ms": round(sec * 1e3, 4), "bytes_per_gaussian": 48,
+           "roofline": {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS, "achieved": round(ach, 1),
+                        "frac": round(ach / PEAK_HBM_GBS, 4)},
+           "parity": {"value_rel_err": float(f"{err:.3g}"), "pass": bool(err <= 1e-4)}}
+    # relocation: 10 % of the Gaussians dead; the arrays are restored before every call (outside
+    # the timed events), since the call relocates in place
+    rng = np.random.default_rng(SEED_RELOC)
+    dead = rng.choice(g.n, g.n // 10, replace=False)
+    o_dead = G.opacities.clone()
+    o_dead[torch.from_numpy(dead).to(dev)] = torch.from_numpy(rng.uniform(0, 0.005, len(dead)).astype(np.float32)).to(dev)
+    fields = ("means", "log_scales", "quats", "opacities", "velocities", "features")
+    pristine = {f: getattr(G, f).clone() for f in fields if getattr(G, f) is not None and f != "opacities"}
+    pristine["opacities"] = o_dead
+    work = B.GaussTensors(*(pristine[f].clone() if f in pristine else None for f in fields))
+    u = torch.from_numpy(rng.integers(0, 1 << 32, g.n, dtype=np.uint64).astype(np.uint32).view(np.int32)).to(dev)
+    ws = torch.empty(int(B.load().splat_mcmc_relocate_workspace_bytes(g.n)), dtype=torch.uint8, device=dev)
+    ev = [(mk(), mk()) for _ in range(args.steps)]
+    for k in range(max(1, args.warmup) + args.steps):
+        for f, t in pristine.items():
+            getattr(work, f).copy_(t)
+        if k >= max(1, args.warmup):
+            ev[k - max(1, args.warmup)][0].record(stream)
+        tgt, moved = B.mcmc_relocate(work, u, ws=ws)
+        if k >= max(1, args.warmup):
+            ev[k - max(1, args.warmup)][1].record(stream)
+    torch.cuda.synchronize()
+    sec_r = float(np.median([a.elapsed_time(b_) for a, b_ in ev])) * 1e-3
+    log(f"mcmc_relocate: {g.n} Gaussians, {len(dead)} dead, {sec_r * 1e3:.4f} ms")
+    out["relocate"] = {"workload": f"{g.n} Gaussians, {len(dead)} dead (opacity <= 0.005), copies capped at 51",
+                       "ms": round(sec_r * 1e3, 4), "relocated": int(moved)}
+    return out
 
 
 def decoder_bench(args, dev, lid):

@@ -567,6 +567,40 @@ int splat_camera_decode_bwd(const SplatCamera* cam, const float* feat, const Spl
 int splat_mcmc_regularizer(const SplatGaussians* g, float lambda_o, float lambda_s, float* value,
                            const SplatGrads* grads, void* stream);
 
+/* ---- MCMC relocation of dead Gaussians (the MCMC densification strategy the paper adopts,
+ * with at most 5M Gaussians) -------------------------------------------------------------------
+ * Gaussian arrays the call updates in place (same layout as SplatGaussians). */
+typedef struct SplatGaussianState {
+  int64_t n;
+  float* means;        /* [n,3] */
+  float* log_scales;   /* [n,3] */
+  float* quats;        /* [n,4] */
+  float* opacities;    /* [n]   */
+  float* velocities;   /* [n,3] or NULL */
+  float* features;     /* [n,c_total] */
+  int32_t c_total;
+} SplatGaussianState;
+
+/* Workspace of splat_mcmc_relocate (weights, their scan, counts, new values); 0 = invalid. */
+size_t splat_mcmc_relocate_workspace_bytes(int64_t n);
+/* A Gaussian with opacity <= dead_opacity (0.005 in the strategy), or a non-finite one, is
+ * dead; each dead Gaussian becomes a copy of an alive target drawn with probability
+ * proportional to opacity, and every target shared by N Gaussians (itself and N - 1 copies,
+ * N capped at n_max, 51 in the strategy) gets
+ *   o' = 1 - (1 - o)^(1/N),   log-scales + log(o / sum_{k=1..N} C(N,k) (-1)^(k+1) o'^k / sqrt(k)),
+ * which keeps the integral of the N copies' composited opacity profile along each axis equal to
+ * the original's.  The copies take the target's mean, rotation, velocity, features and the new
+ * opacity and log-scales.  The draw is exact integer arithmetic from the caller's randoms
+ * u [n] (uint32, one per Gaussian, read for dead ones): weights floor(min(o, 1) 2^24) of alive
+ * Gaussians, r = floor(u * total / 2^32), the target the first Gaussian whose inclusive weight
+ * sum exceeds r.  With no alive Gaussian nothing changes.  target [n] (or NULL): the target of
+ * each relocated Gaussian, -1 otherwise (for resetting optimiser state); n_relocated (device,
+ * or NULL): += the number relocated.  All arrays are device arrays; ws caller-owned, 256-byte
+ * aligned, >= splat_mcmc_relocate_workspace_bytes (SPLAT_ERR_CAPACITY otherwise); n >= 2^31
+ * gives SPLAT_ERR_UNSUPPORTED.  Stream-ordered, allocates nothing. */
+int splat_mcmc_relocate(const SplatGaussianState* g, const uint32_t* u, float dead_opacity, int32_t n_max,
+                        int32_t* target, unsigned long long* n_relocated, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ profile of the N copies, 1 - (1 - o' g')^N along an axis, equal to that of the o
 Readings (listed in the design notes): the draw is an input, one 32-bit integer u per Gaussian;
 the weights are the opacities in fixed point, floor(o * 2^24), so that the draw is exact integer
 arithmetic (r = floor(u * total / 2^32), the target is the first Gaussian whose inclusive weight
-sum exceeds r); the copies take the target's mean, rotation, velocity and features and the new
+sum exceeds r; a Gaussian is alive when o > 0.005 and its weight is at most 2^24); the copies take the target's mean, rotation, velocity and features and the new
 opacity and scales; o' is not clamped; with no alive Gaussian nothing moves.
 
 Relocation pins: a hand-worked draw, the opacity identity 1 - (1 - o')^N = o, the profile
@@ -71,8 +71,8 @@ def relocated_opacity_scale(o, n):
 def draw_targets(opacities, u, dead_opacity=DEAD_OPACITY):
     """Target index of every dead Gaussian (-1 for alive ones, and for all when none is alive)."""
     o = np.asarray(opacities, np.float32)
-    dead = o <= np.float32(dead_opacity)
-    w = np.where(dead, 0, np.floor(o.astype(np.float64) * WEIGHT_ONE)).astype(np.int64)
+    dead = ~(o > np.float32(dead_opacity))
+    w = np.where(dead, 0, np.minimum(np.floor(o.astype(np.float64) * WEIGHT_ONE), WEIGHT_ONE)).astype(np.int64)
     incl = np.cumsum(w)
     total = int(incl[-1]) if len(incl) else 0
     tgt = np.full(len(o), -1, np.int64)

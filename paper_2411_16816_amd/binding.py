@@ -69,6 +69,8 @@ def _declare(lib):
         "splat_lidar_decode_workspace_bytes": (C.c_size_t, [i64, i32]),
         "splat_lidar_decode_bwd": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
         "splat_camera_decode_workspace_bytes": (C.c_size_t, [i32, i32]),
+        "splat_mcmc_relocate_workspace_bytes": (C.c_size_t, [i64]),
+        "splat_mcmc_relocate": (C.c_int, [vp, vp, C.c_float, i32, vp, vp, vp, C.c_size_t, vp]),
         "splat_camera_decode": (C.c_int, [vp, vp, vp, vp, vp, C.c_size_t, vp]),
         "splat_camera_decode_bwd": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
     }
@@ -784,3 +786,31 @@ def camera_decode_bwd(cam, feat, cnn: CameraCNN, d_image, d_feat, d_cnn: dict, w
     check(load().splat_camera_decode_bwd(C.byref(st.camera_struct(cam)), _ptr(feat), C.byref(cnn.struct()),
                                          _ptr(d_image), _ptr(d_feat), C.byref(g), C.c_void_p(ws.data_ptr()), ws.numel(),
                                          _stream(stream)), "splat_camera_decode_bwd")
+
+
+# ----------------------------------------------------------------------------------------
+# MCMC relocation (splat_mcmc_relocate)
+# ----------------------------------------------------------------------------------------
+MCMC_DEAD_OPACITY = 0.005
+MCMC_N_MAX = 51
+
+
+def mcmc_relocate(g: GaussTensors, u: torch.Tensor, dead_opacity: float = MCMC_DEAD_OPACITY,
+                  n_max: int = MCMC_N_MAX, ws: Optional[torch.Tensor] = None, stream=None):
+    """Relocates g's dead Gaussians in place.  u: int32 device tensor [n] holding uint32 random
+    bits.  Returns (target int32 [n], number relocated as an int64 device tensor)."""
+    lib = load()
+    n = int(g.means.shape[0])
+    st_ = st.SplatGaussianState()
+    st_.n = n
+    st_.means, st_.log_scales, st_.quats = _ptr(g.means), _ptr(g.log_scales), _ptr(g.quats)
+    st_.opacities, st_.velocities, st_.features = _ptr(g.opacities), _ptr(g.velocities), _ptr(g.features)
+    st_.c_total = int(g.features.shape[1]) if g.features is not None else 0
+    nb = int(lib.splat_mcmc_relocate_workspace_bytes(n))
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=g.means.device)
+    target = torch.empty(max(n, 1), dtype=torch.int32, device=g.means.device)
+    moved = torch.zeros(1, dtype=torch.int64, device=g.means.device)
+    check(lib.splat_mcmc_relocate(C.byref(st_), _ptr(u), float(dead_opacity), int(n_max), _ptr(target), _ptr(moved),
+                                  C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "splat_mcmc_relocate")
+    return target[:n], moved

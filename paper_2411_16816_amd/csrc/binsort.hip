@@ -914,4 +914,8 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   return hipGetLastError();
 }
 
+hipError_t launch_exclusive_scan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* part, hipStream_t s) {
+  return device_scan<int64_t>(LoadI64{in}, n, out, part, s);
+}
+
 }  // namespace splat

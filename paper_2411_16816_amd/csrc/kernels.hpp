@@ -114,5 +114,8 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
                              hipStream_t s, const KernelTimer& timer);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+// exclusive scan of in[0..n) into out (may alias in); part: div_up(n, kScanTile) + 1 entries,
+// the last of which receives the total
+hipError_t launch_exclusive_scan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* part, hipStream_t s);
 
 }  // namespace splat

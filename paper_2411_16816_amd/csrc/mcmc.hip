@@ -63,3 +63,159 @@ int splat_mcmc_regularizer(const SplatGaussians* g, float lambda_o, float lambda
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// Relocation of dead Gaussians (the MCMC densification strategy the paper adopts): a Gaussian
+// with opacity <= the dead threshold takes the place of an alive one drawn with probability
+// proportional to opacity; a target shared by N Gaussians gets o' = 1 - (1 - o)^(1/N) and its
+// scales times o / sum_{k=1..N} C(N, k) (-1)^(k+1) o'^k / sqrt(k) (the N copies' composited
+// profile integrates to the original's).  The draw is exact integer arithmetic: weights
+// floor(o * 2^24) (alive only), their exclusive scan, r = floor(u * total / 2^32) from the
+// caller's 32-bit random u, the target the first Gaussian whose inclusive sum exceeds r.
+// Four passes over the Gaussians plus a scan: weights, draw (binary search, one atomic count per
+// dead Gaussian), new opacity and scales of each target (FP64), copies.
+// ---------------------------------------------------------------------------------------------
+namespace splat {
+
+constexpr float kWeightOne = 16777216.f;   // 2^24
+
+__global__ void k_reloc_weights(const float* __restrict__ o, int64_t n, float thr, int64_t* __restrict__ w,
+                                int32_t* __restrict__ counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float oi = o[i];
+  w[i] = oi > thr ? (int64_t)fminf(floorf(oi * kWeightOne), kWeightOne) : 0;
+  counts[i] = 0;
+}
+
+__global__ void k_reloc_draw(const float* __restrict__ o, int64_t n, float thr, const uint32_t* __restrict__ u,
+                             const int64_t* __restrict__ excl, const int64_t* __restrict__ total_p,
+                             int32_t* __restrict__ counts, int32_t* __restrict__ target,
+                             unsigned long long* __restrict__ n_moved) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t total = *total_p;
+  int32_t t = -1;
+  if (!(o[i] > thr) && total > 0) {
+    const uint64_t T = (uint64_t)total, ui = u[i];
+    const int64_t r = (int64_t)((T >> 32) * ui + (((T & 0xffffffffull) * ui) >> 32));   // < total
+    int64_t lo = 0, hi = n - 1;   // first j whose inclusive sum (excl[j + 1], or the total) exceeds r
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      const int64_t inc = mid + 1 < n ? excl[mid + 1] : total;
+      if (inc > r) hi = mid;
+      else lo = mid + 1;
+    }
+    t = (int32_t)lo;
+    atomicAdd(&counts[t], 1);
+    if (n_moved) atomicAdd(n_moved, 1ull);
+  }
+  target[i] = t;
+}
+
+__global__ void k_reloc_update(const float* __restrict__ o, const float* __restrict__ ls, int64_t n,
+                               const int32_t* __restrict__ counts, int n_max, float* __restrict__ new_o,
+                               float* __restrict__ new_ls) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || counts[i] == 0) return;
+  int N = counts[i] + 1;
+  N = N < n_max ? N : n_max;
+  const double od = o[i];
+  const double on = 1.0 - pow(1.0 - od, 1.0 / N);
+  double denom = 0.0, c = 1.0, p = 1.0;   // c = C(N, k), p = o'^k
+  for (int k = 1; k <= N; ++k) {
+    c = c * (double)(N - k + 1) / (double)k;
+    p *= on;
+    denom += ((k & 1) ? c : -c) * p / sqrt((double)k);
+  }
+  const double lf = log(od / denom);
+  new_o[i] = (float)on;
+  for (int d = 0; d < 3; ++d) new_ls[3 * i + d] = (float)((double)ls[3 * i + d] + lf);
+}
+
+__global__ void k_reloc_apply(SplatGaussianState g, const int32_t* __restrict__ target,
+                              const int32_t* __restrict__ counts, const float* __restrict__ new_o,
+                              const float* __restrict__ new_ls) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  const int64_t t = target[i];
+  if (t >= 0) {   // a dead Gaussian becomes a copy of its (alive, never written here) target
+    for (int d = 0; d < 3; ++d) g.means[3 * i + d] = g.means[3 * t + d];
+    for (int d = 0; d < 4; ++d) g.quats[4 * i + d] = g.quats[4 * t + d];
+    if (g.velocities)
+      for (int d = 0; d < 3; ++d) g.velocities[3 * i + d] = g.velocities[3 * t + d];
+    if (g.features)
+      for (int d = 0; d < g.c_total; ++d) g.features[i * g.c_total + d] = g.features[t * g.c_total + d];
+    g.opacities[i] = new_o[t];
+    for (int d = 0; d < 3; ++d) g.log_scales[3 * i + d] = new_ls[3 * t + d];
+  } else if (counts[i] > 0) {
+    g.opacities[i] = new_o[i];
+    for (int d = 0; d < 3; ++d) g.log_scales[3 * i + d] = new_ls[3 * i + d];
+  }
+}
+
+struct RelocWs {
+  int64_t* w;
+  int64_t* part;
+  int32_t* counts;
+  int32_t* target;
+  float* new_o;
+  float* new_ls;
+  size_t bytes;
+};
+
+inline RelocWs carve_reloc(void* base, int64_t n) {
+  RelocWs r;
+  char* b = (char*)base;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = b + off;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  r.w = (int64_t*)take(n * sizeof(int64_t));
+  r.part = (int64_t*)take((div_up(n, kScanTile) + 1) * sizeof(int64_t));
+  r.counts = (int32_t*)take(n * sizeof(int32_t));
+  r.target = (int32_t*)take(n * sizeof(int32_t));
+  r.new_o = (float*)take(n * sizeof(float));
+  r.new_ls = (float*)take(3 * n * sizeof(float));
+  r.bytes = off;
+  return r;
+}
+
+}  // namespace splat
+
+extern "C" {
+
+size_t splat_mcmc_relocate_workspace_bytes(int64_t n) {
+  if (n < 0) return 0;
+  return carve_reloc(nullptr, n > 0 ? n : 1).bytes;
+}
+
+int splat_mcmc_relocate(const SplatGaussianState* g, const uint32_t* u, float dead_opacity, int32_t n_max,
+                        int32_t* target, unsigned long long* n_relocated, void* ws, size_t ws_bytes, void* stream) {
+  if (!g || g->n < 0 || n_max < 1 || !std::isfinite(dead_opacity)) return SPLAT_ERR_INVALID_ARG;
+  if (g->n == 0) return SPLAT_OK;
+  if (g->n >= ((int64_t)1 << 31)) return SPLAT_ERR_UNSUPPORTED;
+  if (!u || !g->means || !g->log_scales || !g->quats || !g->opacities || (g->c_total > 0 && !g->features) ||
+      g->c_total < 0)
+    return SPLAT_ERR_INVALID_ARG;
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < splat_mcmc_relocate_workspace_bytes(g->n)) return SPLAT_ERR_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  RelocWs w = carve_reloc(ws, g->n);
+  int32_t* tgt = target ? target : w.target;
+  const unsigned nb = (unsigned)div_up(g->n, 256);
+  hipLaunchKernelGGL(k_reloc_weights, dim3(nb), dim3(256), 0, s, (const float*)g->opacities, g->n, dead_opacity, w.w,
+                     w.counts);
+  if (launch_exclusive_scan_i64(w.w, g->n, w.w, w.part, s) != hipSuccess) return SPLAT_ERR_DEVICE;
+  hipLaunchKernelGGL(k_reloc_draw, dim3(nb), dim3(256), 0, s, (const float*)g->opacities, g->n, dead_opacity, u,
+                     (const int64_t*)w.w, (const int64_t*)(w.part + div_up(g->n, kScanTile)), w.counts, tgt,
+                     n_relocated);
+  hipLaunchKernelGGL(k_reloc_update, dim3(nb), dim3(256), 0, s, (const float*)g->opacities,
+                     (const float*)g->log_scales, g->n, (const int32_t*)w.counts, (int)n_max, w.new_o, w.new_ls);
+  hipLaunchKernelGGL(k_reloc_apply, dim3(nb), dim3(256), 0, s, *g, (const int32_t*)tgt, (const int32_t*)w.counts,
+                     (const float*)w.new_o, (const float*)w.new_ls);
+  return hipGetLastError() == hipSuccess ? SPLAT_OK : SPLAT_ERR_DEVICE;
+}
+
+}  // extern "C"

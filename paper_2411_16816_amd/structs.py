@@ -161,3 +161,8 @@ class SplatCameraCNN(C.Structure):
 class SplatCameraCNNGrads(C.Structure):
     _fields_ = [("embed", C.c_void_p), ("w_in", C.c_void_p), ("b_in", C.c_void_p), ("w_block", C.c_void_p * 4),
                 ("b_block", C.c_void_p * 4), ("w_out", C.c_void_p), ("b_out", C.c_void_p)]
+
+
+class SplatGaussianState(C.Structure):
+    _fields_ = [("n", C.c_int64), ("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacities", C.c_void_p), ("velocities", C.c_void_p), ("features", C.c_void_p), ("c_total", C.c_int32)]
