@@ -83,8 +83,9 @@ def log(*a):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the sharded design is described "
-              f"in DESIGN.md and is not measured.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the path is measured on one GPU's "
+              f"share; its multi-GPU form (replicated Gaussians, sensors split across GPUs, one gradient "
+              f"all-reduce) is a design, not a measured configuration.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2411_16816_amd import binding as B
