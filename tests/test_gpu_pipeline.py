@@ -83,3 +83,57 @@ def test_pipeline_replays_match_eager():
         pipe.run()
     pipe.close()
     torch.cuda.synchronize()
+
+
+def test_pipeline_with_line_of_sight_and_cap():
+    """A lidar with measured ranges (line-of-sight sum, its upstream gradient d_los) and the
+    training-time cap (priorities redrawn between replays, copied into the same device arrays):
+    every replay reproduces the eager batched calls, the sums and dropped flags included."""
+    b = _binding()
+    g = _scene()
+    cam, lid = _sensors(0)
+    lid = S.make_lidar((0.0, 0.0, 1.8), 5.0, 16, -20.0, 10.0, 512, t_sweep=0.1, ego_vel_world=(12.0, 0.0, 0.0),
+                       tile_az=64, feat_offset=3, n_channels=8)   # 64 x 8 = 512 rays per tile: half dropped
+    rng = np.random.default_rng(17)
+    lid.ray_range = rng.uniform(1.0, 40.0, lid.n_rays).astype(np.float32)
+    lid.ray_priority = rng.integers(0, 1 << 16, lid.n_rays).astype(np.uint16)
+    rig = b.Rig([cam], [lid])
+    G = b.GaussTensors.from_numpy(g)
+    sp = b.SensorPass(rig, 0, 2, g.n, 1, batched=True)
+    sp.fit_capacity(G, margin=2.0)
+    ref = b.SensorPass(rig, 0, 2, g.n, sp.k_cap, batched=True)
+    up = np.random.default_rng(6)
+    dF = torch.from_numpy(up.normal(size=sp.n_feat).astype(np.float32)).cuda()
+    dD = torch.from_numpy((0.1 * up.normal(size=sp.n_rays)).astype(np.float32)).cuda()
+    dA = torch.from_numpy(up.normal(size=sp.n_rays).astype(np.float32)).cuda()
+    dl = torch.from_numpy(up.normal(size=sp.n_rays).astype(np.float32)).cuda()
+    gpipe = b.zeros_like_grads(G)
+    pipe = b.Pipeline(sp, G, b.BOX, gpipe, dF, dD, dA, d_los=dl)
+    lid_rays = sp.sensor_slices(1)[0]
+    prev = None
+    for k in range(3):
+        print(f"[pipeline] los + cap replay {k}", flush=True)
+        lid.ray_priority = rng.integers(0, 1 << 16, lid.n_rays).astype(np.uint16)
+        rig.update(lidars=[lid])
+        ref.render(G)
+        gref = b.zeros_like_grads(G)
+        ref.raster_bwd(G, dF, dD, dA, gref, d_los=dl)
+        torch.cuda.synchronize()
+        pipe.run()
+        torch.cuda.synchronize()
+        o_p, o_r = sp.outputs(), ref.outputs()
+        for key in ("feat", "depth", "alpha", "t_final", "last"):
+            np.testing.assert_array_equal(o_p[key].cpu().numpy(), o_r[key].cpu().numpy(), err_msg=key)
+        for key in ("median", "los", "dropped"):
+            np.testing.assert_array_equal(o_p[key][lid_rays].cpu().numpy(), o_r[key][lid_rays].cpu().numpy(),
+                                          err_msg=key)
+        dropped = o_p["dropped"][lid_rays].cpu().numpy()
+        assert 0.3 < dropped.mean() < 0.6 and float(o_p["los"][lid_rays].abs().max()) > 0
+        for name in ("means", "log_scales", "quats", "opacities", "velocities", "features"):
+            x = getattr(gpipe, name).cpu().numpy().astype(np.float64)
+            y = getattr(gref, name).cpu().numpy().astype(np.float64)
+            assert np.linalg.norm(y) > 0, name
+            assert np.linalg.norm(x - y) <= 1e-5 * np.linalg.norm(y), (k, name)
+        if prev is not None:   # a new shuffle drops another set of rays
+            assert (dropped != prev).any()
+        prev = dropped
