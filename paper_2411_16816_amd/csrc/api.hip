@@ -309,7 +309,12 @@ static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t f
   // slot flags start cleared; the atomic part only exists where lidar tiles can be split
   hipError_t e = launch_fill_i32((int32_t*)w.flags, div_up(lists->k_cap, 4), 0, s);
   if (e == hipSuccess) e = launch_fill_i32((int32_t*)w.rflag, div_up((int64_t)count * g->n, 4), 0, s);
-  if (e == hipSuccess && v.has_lidar) e = launch_fill_f32(w.g2d, (int64_t)count * g->n * kNV, 0.f, s);
+  if (e == hipSuccess && v.has_lidar) {
+    // only lidar records (the call's last sensors) receive atomic parts: zero their rows alone
+    int k_lid = 0;
+    while (k_lid < count && v.host[k_lid].kind != kLidar) ++k_lid;
+    e = launch_fill_f32(w.g2d + (int64_t)k_lid * g->n * kNV, (int64_t)(count - k_lid) * g->n * kNV, 0.f, s);
+  }
   if (e == hipSuccess)
     e = launch_raster_bwd(v, *g, *proj, *lists, support, *saved, dF, dD, dA, w, gr->features, gr->sensor_time_offset, s,
                           take_timer());

@@ -264,9 +264,11 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const DevSensor* __restrict
         for (int v = 0; v < V; ++v) acc[v] += two ? r0[v] + r1[v] : r0[v];
       }
     }
+    // lidar records add to the atomic part of split tiles; camera rows are only ever written here
     float* q = g2d + r * kNV;
+    const bool add = accumulate && sens[k].kind == kLidar;
 #pragma unroll
-    for (int v = 0; v < kNV; ++v) q[v] = accumulate ? q[v] + acc[v] : acc[v];
+    for (int v = 0; v < kNV; ++v) q[v] = add ? q[v] + acc[v] : acc[v];
     if (dfeat) {
       const DevSensor& S = sens[k];
       float* fp = dfeat + i * c_total + S.feat_off;
