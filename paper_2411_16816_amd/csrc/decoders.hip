@@ -132,12 +132,45 @@ __global__ __launch_bounds__(kDecBlock) void k_lidar_decode_bwd(int64_t n, const
   for (int i = 0; i < NPW; ++i) acc[i] = decx4{0.f, 0.f, 0.f, 0.f};
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
-  for (int64_t base = (int64_t)blockIdx.x * kDecBlock; base < n; base += (int64_t)gridDim.x * kDecBlock) {
+  // a ray's inputs; those of the next chunk are loaded while the current chunk is computed
+  // (the kernel is latency-bound on these loads otherwise)
+  struct RayIn {
+    float F[CM];
+    float az, el, di, dd;
+  };
+  auto fetch = [&](int64_t rr, RayIn& in) {
+    if (rr >= n) return;
+    const float* row = feat + rr * C;
+#pragma unroll
+    for (int k = 0; k < CM; ++k) in.F[k] = k < C ? row[k] : 0.f;
+    in.az = az[rr];
+    in.el = el[rr];
+    in.di = d_int ? d_int[rr] : 0.f;
+    in.dd = d_drop ? d_drop[rr] : 0.f;
+  };
+  const int64_t step = (int64_t)gridDim.x * kDecBlock;
+  RayIn cur{};
+  fetch((int64_t)blockIdx.x * kDecBlock + t, cur);
+  for (int64_t base = (int64_t)blockIdx.x * kDecBlock; base < n; base += step) {
     __syncthreads();   // weights staged / the previous chunk's rows consumed
     const int64_t r = base + t;
+    RayIn nxt{};   // stays zero past the last chunk
+    fetch(r + step, nxt);
+    float old[CM];   // the feature-gradient row this ray adds to
+#pragma unroll
+    for (int k = 0; k < CM; ++k) old[k] = (d_feat && r < n && k < C) ? d_feat[r * C + k] : 0.f;
     if (r < n) {
       float F[CM], d[3];
-      load_ray<CM>(feat, az, el, r, C, F, d);
+#pragma unroll
+      for (int k = 0; k < CM; ++k) F[k] = cur.F[k];
+      {
+        float sa, ca, se, ce;
+        sincosf(cur.az, &sa, &ca);
+        sincosf(cur.el, &se, &ce);
+        d[0] = ce * ca;
+        d[1] = ce * sa;
+        d[2] = se;
+      }
       float z0 = W.b2[0], z1 = W.b2[1];
       // forward again; the pre-activations wait in this ray's LDS row (the lane's own row)
 #pragma unroll 2
@@ -150,8 +183,8 @@ __global__ __launch_bounds__(kDecBlock) void k_lidar_decode_bwd(int64_t n, const
         z1 = fmaf(W.w2[1][j], h, z1);
       }
       const float s0 = sigmoid_f(z0), s1 = sigmoid_f(z1);
-      const float g0 = d_int ? d_int[r] * s0 * (1.f - s0) : 0.f;
-      const float g1 = d_drop ? d_drop[r] * s1 * (1.f - s1) : 0.f;
+      const float g0 = cur.di * s0 * (1.f - s0);
+      const float g1 = cur.dd * s1 * (1.f - s1);
       S.dz[t][0] = g0;
       S.dz[t][1] = g1;
 #pragma unroll
@@ -176,7 +209,7 @@ __global__ __launch_bounds__(kDecBlock) void k_lidar_decode_bwd(int64_t n, const
         float* row = d_feat + r * C;
 #pragma unroll
         for (int k = 0; k < CM; ++k)
-          if (k < C) row[k] += dF[k];
+          if (k < C) row[k] = old[k] + dF[k];
       }
     } else {
 #pragma unroll
@@ -212,6 +245,7 @@ __global__ __launch_bounds__(kDecBlock) void k_lidar_decode_bwd(int64_t n, const
         acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i], 0, 0, 0);
       }
     }
+    cur = nxt;
   }
   // D[i][j] of a block: lane j + 16 (i / 4), element i % 4
   float* dst = partial + (int64_t)blockIdx.x * n_out;
