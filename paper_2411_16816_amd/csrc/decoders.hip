@@ -24,25 +24,29 @@ constexpr int kDecMaxC = 32;
 
 inline int dec_outputs(int C) { return kDecHidden * (C + 3) + kDecHidden + 2 * kDecHidden + 2; }
 
+// Laid out for 16-byte LDS reads: per hidden unit j its feature-weight row (zero beyond C), its
+// direction weights with its bias, and its two output weights.
 template <int CM>
-struct DecWeights {
-  float w1f[kDecHidden][CM];   // feature columns of W1 (zero beyond C)
-  float w1d[kDecHidden][3];    // direction columns of W1
-  float b1[kDecHidden];
-  float w2[2][kDecHidden];
+struct __align__(16) DecWeights {
+  float4 w1f[kDecHidden][CM / 4];   // feature columns of W1
+  float4 aux[kDecHidden];           // (W1 direction columns 0..2, b1)
+  float2 w2p[kDecHidden];           // (W2[0][j], W2[1][j])
   float b2[2];
 };
 
 template <int CM>
 __device__ void stage_weights(DecWeights<CM>& W, const SplatLidarMLP& m) {
   const int C = m.n_feat;
+  float* w1f = reinterpret_cast<float*>(&W.w1f[0][0]);
   for (int i = threadIdx.x; i < kDecHidden * CM; i += blockDim.x) {
     const int j = i / CM, k = i % CM;
-    W.w1f[j][k] = k < C ? m.w1[j * (C + 3) + k] : 0.f;
+    w1f[i] = k < C ? m.w1[j * (C + 3) + k] : 0.f;
   }
-  for (int i = threadIdx.x; i < kDecHidden * 3; i += blockDim.x) W.w1d[i / 3][i % 3] = m.w1[(i / 3) * (C + 3) + C + i % 3];
-  for (int i = threadIdx.x; i < kDecHidden; i += blockDim.x) W.b1[i] = m.b1[i];
-  for (int i = threadIdx.x; i < 2 * kDecHidden; i += blockDim.x) W.w2[i / kDecHidden][i % kDecHidden] = m.w2[i];
+  for (int j = threadIdx.x; j < kDecHidden; j += blockDim.x) {
+    const float* r = m.w1 + j * (C + 3) + C;
+    W.aux[j] = make_float4(r[0], r[1], r[2], m.b1[j]);
+    W.w2p[j] = make_float2(m.w2[j], m.w2[kDecHidden + j]);
+  }
   if (threadIdx.x < 2) W.b2[threadIdx.x] = m.b2[threadIdx.x];
 }
 
@@ -64,12 +68,19 @@ __device__ __forceinline__ void load_ray(const float* feat, const float* az, con
 
 template <int CM>
 __device__ __forceinline__ float hidden_pre(const DecWeights<CM>& W, int j, const float (&F)[CM], const float (&d)[3]) {
-  float p = W.b1[j];
+  const float4 a = W.aux[j];
+  float p = a.w;
 #pragma unroll
-  for (int k = 0; k < CM; ++k) p = fmaf(W.w1f[j][k], F[k], p);
-  p = fmaf(W.w1d[j][0], d[0], p);
-  p = fmaf(W.w1d[j][1], d[1], p);
-  return fmaf(W.w1d[j][2], d[2], p);
+  for (int q = 0; q < CM / 4; ++q) {
+    const float4 w = W.w1f[j][q];
+    p = fmaf(w.x, F[4 * q], p);
+    p = fmaf(w.y, F[4 * q + 1], p);
+    p = fmaf(w.z, F[4 * q + 2], p);
+    p = fmaf(w.w, F[4 * q + 3], p);
+  }
+  p = fmaf(a.x, d[0], p);
+  p = fmaf(a.y, d[1], p);
+  return fmaf(a.z, d[2], p);
 }
 
 template <int CM>
@@ -88,8 +99,9 @@ __global__ __launch_bounds__(kDecBlock) void k_lidar_decode(int64_t n, const flo
 #pragma unroll 4
     for (int j = 0; j < kDecHidden; ++j) {
       const float h = fmaxf(hidden_pre<CM>(W, j, F, d), 0.f);
-      z0 = fmaf(W.w2[0][j], h, z0);
-      z1 = fmaf(W.w2[1][j], h, z1);
+      const float2 w2 = W.w2p[j];
+      z0 = fmaf(w2.x, h, z0);
+      z1 = fmaf(w2.y, h, z1);
     }
     if (intensity) intensity[r] = sigmoid_f(z0);
     if (drop) drop[r] = sigmoid_f(z1);
@@ -179,8 +191,9 @@ __global__ __launch_bounds__(kDecBlock) void k_lidar_decode_bwd(int64_t n, const
         const float h = fmaxf(p, 0.f);
         S.dpre[t][j] = p;
         S.h[t][j] = h;
-        z0 = fmaf(W.w2[0][j], h, z0);
-        z1 = fmaf(W.w2[1][j], h, z1);
+        const float2 w2 = W.w2p[j];
+        z0 = fmaf(w2.x, h, z0);
+        z1 = fmaf(w2.y, h, z1);
       }
       const float s0 = sigmoid_f(z0), s1 = sigmoid_f(z1);
       const float g0 = cur.di * s0 * (1.f - s0);
@@ -200,10 +213,17 @@ __global__ __launch_bounds__(kDecBlock) void k_lidar_decode_bwd(int64_t n, const
       for (int k = 0; k < CM; ++k) dF[k] = 0.f;
 #pragma unroll 2
       for (int j = 0; j < kDecHidden; ++j) {
-        const float dp = S.dpre[t][j] > 0.f ? fmaf(W.w2[0][j], g0, W.w2[1][j] * g1) : 0.f;
+        const float2 w2 = W.w2p[j];
+        const float dp = S.dpre[t][j] > 0.f ? fmaf(w2.x, g0, w2.y * g1) : 0.f;
         S.dpre[t][j] = dp;
 #pragma unroll
-        for (int k = 0; k < CM; ++k) dF[k] = fmaf(W.w1f[j][k], dp, dF[k]);
+        for (int q = 0; q < CM / 4; ++q) {
+          const float4 w = W.w1f[j][q];
+          dF[4 * q] = fmaf(w.x, dp, dF[4 * q]);
+          dF[4 * q + 1] = fmaf(w.y, dp, dF[4 * q + 1]);
+          dF[4 * q + 2] = fmaf(w.z, dp, dF[4 * q + 2]);
+          dF[4 * q + 3] = fmaf(w.w, dp, dF[4 * q + 3]);
+        }
       }
       if (d_feat) {
         float* row = d_feat + r * C;
