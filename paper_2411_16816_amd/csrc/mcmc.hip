@@ -6,8 +6,9 @@
 // dL/do = lambda_o sign(o).
 //
 // HBM-bound: per Gaussian it reads o and l (16 B) and read-modify-writes their gradients
-// (32 B).  A grid-stride loop; L is summed per wavefront, then per workgroup through LDS, and
-// added to the caller's scalar with one atomic per workgroup.
+// (32 B).  A grid-stride loop over groups of four Gaussians (16-byte accesses); L is summed per
+// wavefront, then per workgroup through LDS, and added to the caller's scalar with one atomic per
+// workgroup.
 #include <cmath>
 
 #include "kernels.hpp"
@@ -15,18 +16,52 @@
 
 namespace splat {
 
+__device__ __forceinline__ float sgnf(float o) { return o > 0.f ? 1.f : (o < 0.f ? -1.f : 0.f); }
+
+// Four Gaussians per thread with 16-byte accesses when every array is 16-byte aligned (their
+// log-scale rows then span three float4), one per thread otherwise and for the tail.
 __global__ __launch_bounds__(256) void k_mcmc_reg(int64_t n, const float* __restrict__ opac,
                                                   const float* __restrict__ log_scales, float lam_o, float lam_s,
                                                   float* __restrict__ value, float* __restrict__ d_opac,
-                                                  float* __restrict__ d_ls) {
+                                                  float* __restrict__ d_ls, int vec) {
   __shared__ float s_part[4];
   float acc = 0.f;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  const int64_t n4 = vec ? n / 4 : 0;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4; q += stride) {
+    const float4 o = reinterpret_cast<const float4*>(opac)[q];
+    const float4* lp = reinterpret_cast<const float4*>(log_scales) + 3 * q;
+    const float4 l0 = lp[0], l1 = lp[1], l2 = lp[2];
+    const float e[12] = {expf(l0.x), expf(l0.y), expf(l0.z), expf(l0.w), expf(l1.x), expf(l1.y),
+                         expf(l1.z), expf(l1.w), expf(l2.x), expf(l2.y), expf(l2.z), expf(l2.w)};
+    float se = 0.f;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) se += e[k];
+    acc += lam_o * (fabsf(o.x) + fabsf(o.y) + fabsf(o.z) + fabsf(o.w)) + lam_s * se;
+    if (d_opac) {
+      float4 g = reinterpret_cast<float4*>(d_opac)[q];
+      g.x += lam_o * sgnf(o.x);
+      g.y += lam_o * sgnf(o.y);
+      g.z += lam_o * sgnf(o.z);
+      g.w += lam_o * sgnf(o.w);
+      reinterpret_cast<float4*>(d_opac)[q] = g;
+    }
+    if (d_ls) {
+      float4* gp = reinterpret_cast<float4*>(d_ls) + 3 * q;
+      float4 g0 = gp[0], g1 = gp[1], g2 = gp[2];
+      g0.x += lam_s * e[0]; g0.y += lam_s * e[1]; g0.z += lam_s * e[2]; g0.w += lam_s * e[3];
+      g1.x += lam_s * e[4]; g1.y += lam_s * e[5]; g1.z += lam_s * e[6]; g1.w += lam_s * e[7];
+      g2.x += lam_s * e[8]; g2.y += lam_s * e[9]; g2.z += lam_s * e[10]; g2.w += lam_s * e[11];
+      gp[0] = g0;
+      gp[1] = g1;
+      gp[2] = g2;
+    }
+  }
+  for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const float o = opac[i];
     const float s0 = expf(log_scales[3 * i]), s1 = expf(log_scales[3 * i + 1]), s2 = expf(log_scales[3 * i + 2]);
     acc += lam_o * fabsf(o) + lam_s * (s0 + s1 + s2);
-    if (d_opac) d_opac[i] += lam_o * (o > 0.f ? 1.f : (o < 0.f ? -1.f : 0.f));
+    if (d_opac) d_opac[i] += lam_o * sgnf(o);
     if (d_ls) {
       d_ls[3 * i] += lam_s * s0;
       d_ls[3 * i + 1] += lam_s * s1;
@@ -55,10 +90,14 @@ int splat_mcmc_regularizer(const SplatGaussians* g, float lambda_o, float lambda
   float* d_o = grads ? grads->opacities : nullptr;
   float* d_l = grads ? grads->log_scales : nullptr;
   if (!value && !d_o && !d_l) return SPLAT_OK;
-  int64_t blocks = div_up(g->n, 256);
-  if (blocks > 2048) blocks = 2048;
+  const uintptr_t al = (uintptr_t)g->opacities | (uintptr_t)g->log_scales | (uintptr_t)d_o | (uintptr_t)d_l;
+  const int vec = (al & 15) == 0;
+  // few workgroups, each striding over many Gaussians: every workgroup adds its part of L with
+  // one atomic on the same address, and those atomics serialise
+  int64_t blocks = div_up(vec ? div_up(g->n, 4) : g->n, 256);
+  if (blocks > 512) blocks = 512;
   hipLaunchKernelGGL(k_mcmc_reg, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, g->n, g->opacities,
-                     g->log_scales, lambda_o, lambda_s, value, d_o, d_l);
+                     g->log_scales, lambda_o, lambda_s, value, d_o, d_l, vec);
   return hipGetLastError() == hipSuccess ? SPLAT_OK : SPLAT_ERR_DEVICE;
 }
 
