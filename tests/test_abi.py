@@ -93,7 +93,8 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_2411_16816_amd import structs as st
     mirrors = [st.SplatStatus, st.SplatGaussians, st.SplatCamera, st.SplatLidar, st.SplatRigLayout,
                st.SplatProjected, st.SplatTileLists, st.SplatRenderOut, st.SplatGrads, st.SplatStep,
-               st.SplatActors, st.SplatActorGrads]
+               st.SplatActors, st.SplatActorGrads, st.SplatLidarMLP, st.SplatLidarMLPGrads, st.SplatCameraCNN,
+               st.SplatCameraCNNGrads, st.SplatGaussianState]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "splat.h"', "int main(void) {"]
     for m in mirrors:
         n = m.__name__
