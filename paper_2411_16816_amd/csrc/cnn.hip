@@ -330,9 +330,12 @@ __global__ __launch_bounds__(256) void k_cnn_input_bwd(const float* __restrict__
           if (k < Df) row[k] = old[k] + v[k];
       }
     }
+    // the embedding's channels Df + 3 .. Df + 3 + E - 1, picked from the registers already loaded
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (j < E) e[j] = src[Df + 3 + j];
+    for (int k = 0; k < kCC; ++k)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < E && k == Df + 3 + j) e[j] = v[k];
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) s_e[threadIdx.x][k] = e[k];
