@@ -581,7 +581,8 @@ typedef struct SplatGaussianState {
   int32_t c_total;
 } SplatGaussianState;
 
-/* Workspace of splat_mcmc_relocate (weights, their scan, counts, new values); 0 = invalid. */
+/* Workspace of splat_mcmc_relocate (weights, their scan, a lookup table of the draw, counts, new
+ * values); 0 = invalid. */
 size_t splat_mcmc_relocate_workspace_bytes(int64_t n);
 /* A Gaussian with opacity <= dead_opacity (0.005 in the strategy), or a non-finite one, is
  * dead; each dead Gaussian becomes a copy of an alive target drawn with probability

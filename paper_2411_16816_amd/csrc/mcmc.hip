@@ -111,8 +111,10 @@ int splat_mcmc_regularizer(const SplatGaussians* g, float lambda_o, float lambda
 // profile integrates to the original's).  The draw is exact integer arithmetic: weights
 // floor(o * 2^24) (alive only), their exclusive scan, r = floor(u * total / 2^32) from the
 // caller's 32-bit random u, the target the first Gaussian whose inclusive sum exceeds r.
-// Four passes over the Gaussians plus a scan: weights, draw (binary search, one atomic count per
-// dead Gaussian), new opacity and scales of each target (FP64), copies.
+// Passes: weights, their scan, a lookup table of the draw (for every 2^s-wide range of r the first
+// Gaussian that can be its target, one entry per four Gaussians), the draw (a short binary search
+// between two table entries, one atomic count per dead Gaussian), new opacity and scales of each
+// target (FP64), copies.
 // ---------------------------------------------------------------------------------------------
 namespace splat {
 
@@ -127,29 +129,71 @@ __global__ void k_reloc_weights(const float* __restrict__ o, int64_t n, float th
   counts[i] = 0;
 }
 
-__global__ void k_reloc_draw(const float* __restrict__ o, int64_t n, float thr, const uint32_t* __restrict__ u,
-                             const int64_t* __restrict__ excl, const int64_t* __restrict__ total_p,
-                             int32_t* __restrict__ counts, int32_t* __restrict__ target,
-                             unsigned long long* __restrict__ n_moved) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t total = *total_p;
-  int32_t t = -1;
-  if (!(o[i] > thr) && total > 0) {
-    const uint64_t T = (uint64_t)total, ui = u[i];
-    const int64_t r = (int64_t)((T >> 32) * ui + (((T & 0xffffffffull) * ui) >> 32));   // < total
-    int64_t lo = 0, hi = n - 1;   // first j whose inclusive sum (excl[j + 1], or the total) exceeds r
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      const int64_t inc = mid + 1 < n ? excl[mid + 1] : total;
-      if (inc > r) hi = mid;
-      else lo = mid + 1;
-    }
-    t = (int32_t)lo;
-    atomicAdd(&counts[t], 1);
-    if (n_moved) atomicAdd(n_moved, 1ull);
+// the first j in [lo, hi] whose inclusive sum (excl[j + 1], or the total) exceeds r; the caller
+// guarantees that it lies in that range
+__device__ inline int64_t first_exceeding(const int64_t* __restrict__ excl, int64_t n, int64_t total, int64_t r,
+                                          int64_t lo, int64_t hi) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const int64_t inc = mid + 1 < n ? excl[mid + 1] : total;
+    if (inc > r) hi = mid;
+    else lo = mid + 1;
   }
-  target[i] = t;
+  return lo;
+}
+
+// bucket width 2^s of the lookup table: the smallest s with (total - 1) >> s < n_lut
+__device__ inline int lut_shift(int64_t total, int64_t n_lut) {
+  int s = 0;
+  while (((total - 1) >> s) >= n_lut) ++s;
+  return s;
+}
+
+inline int64_t reloc_lut_entries(int64_t n) { return n > 4 ? (n + 3) / 4 : 1; }
+
+// lut[b] = the target of r = b << s, for b <= (total - 1) >> s
+__global__ void k_reloc_lut(const int64_t* __restrict__ excl, int64_t n, const int64_t* __restrict__ total_p,
+                            int64_t n_lut, int32_t* __restrict__ lut) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = *total_p;
+  if (total <= 0) return;
+  const int s = lut_shift(total, n_lut);
+  if (b > ((total - 1) >> s)) return;
+  lut[b] = (int32_t)first_exceeding(excl, n, total, b << s, 0, n - 1);
+}
+
+// grid-stride over the Gaussians; targets are nondecreasing in r, so the target of r lies between
+// the table entries of its bucket and of the next one (the last Gaussian for the last bucket)
+__global__ __launch_bounds__(256) void k_reloc_draw(const float* __restrict__ o, int64_t n, float thr,
+                                                    const uint32_t* __restrict__ u, const int64_t* __restrict__ excl,
+                                                    const int64_t* __restrict__ total_p, int64_t n_lut,
+                                                    const int32_t* __restrict__ lut, int32_t* __restrict__ counts,
+                                                    int32_t* __restrict__ target,
+                                                    unsigned long long* __restrict__ n_moved) {
+  __shared__ unsigned int s_moved;
+  if (threadIdx.x == 0) s_moved = 0;
+  __syncthreads();
+  const int64_t total = *total_p;
+  const int s = total > 0 ? lut_shift(total, n_lut) : 0;
+  const int64_t last_b = total > 0 ? (total - 1) >> s : 0;
+  unsigned int moved = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t t = -1;
+    if (!(o[i] > thr) && total > 0) {
+      const uint64_t T = (uint64_t)total, ui = u[i];
+      const int64_t r = (int64_t)((T >> 32) * ui + (((T & 0xffffffffull) * ui) >> 32));   // < total
+      const int64_t b = r >> s;
+      const int64_t lo = lut[b], hi = b < last_b ? (int64_t)lut[b + 1] : n - 1;
+      t = (int32_t)first_exceeding(excl, n, total, r, lo, hi);
+      atomicAdd(&counts[t], 1);
+      ++moved;
+    }
+    target[i] = t;
+  }
+  if (!n_moved) return;   // uniform
+  if (moved) atomicAdd(&s_moved, moved);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_moved) atomicAdd(n_moved, (unsigned long long)s_moved);
 }
 
 __global__ void k_reloc_update(const float* __restrict__ o, const float* __restrict__ ls, int64_t n,
@@ -198,6 +242,7 @@ struct RelocWs {
   int64_t* part;
   int32_t* counts;
   int32_t* target;
+  int32_t* lut;
   float* new_o;
   float* new_ls;
   size_t bytes;
@@ -216,6 +261,7 @@ inline RelocWs carve_reloc(void* base, int64_t n) {
   r.part = (int64_t*)take((div_up(n, kScanTile) + 1) * sizeof(int64_t));
   r.counts = (int32_t*)take(n * sizeof(int32_t));
   r.target = (int32_t*)take(n * sizeof(int32_t));
+  r.lut = (int32_t*)take(reloc_lut_entries(n) * sizeof(int32_t));
   r.new_o = (float*)take(n * sizeof(float));
   r.new_ls = (float*)take(3 * n * sizeof(float));
   r.bytes = off;
@@ -247,9 +293,15 @@ int splat_mcmc_relocate(const SplatGaussianState* g, const uint32_t* u, float de
   hipLaunchKernelGGL(k_reloc_weights, dim3(nb), dim3(256), 0, s, (const float*)g->opacities, g->n, dead_opacity, w.w,
                      w.counts);
   if (launch_exclusive_scan_i64(w.w, g->n, w.w, w.part, s) != hipSuccess) return SPLAT_ERR_DEVICE;
-  hipLaunchKernelGGL(k_reloc_draw, dim3(nb), dim3(256), 0, s, (const float*)g->opacities, g->n, dead_opacity, u,
-                     (const int64_t*)w.w, (const int64_t*)(w.part + div_up(g->n, kScanTile)), w.counts, tgt,
-                     n_relocated);
+  const int64_t* excl = w.w;
+  const int64_t* total = w.part + div_up(g->n, kScanTile);
+  const int64_t n_lut = reloc_lut_entries(g->n);
+  hipLaunchKernelGGL(k_reloc_lut, dim3((unsigned)div_up(n_lut, 256)), dim3(256), 0, s, excl, g->n, total, n_lut,
+                     w.lut);
+  // a bounded grid: one atomic per workgroup on the shared count
+  const unsigned nd = nb < 2048 ? nb : 2048;
+  hipLaunchKernelGGL(k_reloc_draw, dim3(nd), dim3(256), 0, s, (const float*)g->opacities, g->n, dead_opacity, u,
+                     excl, total, n_lut, (const int32_t*)w.lut, w.counts, tgt, n_relocated);
   hipLaunchKernelGGL(k_reloc_update, dim3(nb), dim3(256), 0, s, (const float*)g->opacities,
                      (const float*)g->log_scales, g->n, (const int32_t*)w.counts, (int)n_max, w.new_o, w.new_ls);
   hipLaunchKernelGGL(k_reloc_apply, dim3(nb), dim3(256), 0, s, *g, (const int32_t*)tgt, (const int32_t*)w.counts,
