@@ -79,6 +79,20 @@ def test_relocate_cap_and_degenerate_cases():
     np.testing.assert_array_equal(G.log_scales.cpu().numpy(), g.log_scales)
 
 
+def test_relocate_few_alive_small_total():
+    # total weight below one entry per four Gaussians: every value of r has a lookup-table entry of
+    # its own; and a few alive near the threshold scattered through a large dead set
+    b = _binding()
+    for seed, n, alive in ((11, 500_000, [123_457]), (12, 300_001, [0, 17, 150_000, 300_000])):
+        g, u = _scene(seed, n, 1.0)
+        g.opacities[alive] = np.float32(0.006)
+        print(f"[relocate] few alive n={n} alive={alive}", flush=True)
+        G, tgt, moved = _run(b, g, u, n_max=51)
+        np.testing.assert_array_equal(tgt, mcmc.draw_targets(g.opacities, u))
+        assert moved == n - len(alive)
+        assert set(np.unique(tgt[tgt >= 0])) <= set(alive)
+
+
 def test_relocate_headline_scene():
     b = _binding()
     g = S.headline().gaussians
