@@ -258,35 +258,44 @@ struct CnnGeo {
   int W, H;
 };
 
-// x = [F, d, e, 0...] per pixel
-__global__ void k_cnn_input(const float* __restrict__ feat, int C, int Df, int E, const float* __restrict__ embed,
-                            CnnGeo g, float* __restrict__ x0) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// x = [F, d, e, 0...] per pixel; eight lanes per pixel, lane q writing channels 4q .. 4q + 3, so
+// that a wavefront reads and writes contiguous rows (vec: 16-byte feature rows, C and Df multiples
+// of 4)
+__global__ __launch_bounds__(256) void k_cnn_input(const float* __restrict__ feat, int C, int Df, int E,
+                                                   const float* __restrict__ embed, CnnGeo g, int vec,
+                                                   float* __restrict__ x0) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p = t >> 3;
+  const int k0 = 4 * (int)(t & 7);
   if (p >= (int64_t)g.W * g.H) return;
-  const int u = (int)(p % g.W), v = (int)(p / g.W);
-  float dc0 = ((float)u + 0.5f - g.cx) / g.fx, dc1 = ((float)v + 0.5f - g.cy) / g.fy, dc2 = 1.f;
-  const float inv = rsqrtf(dc0 * dc0 + dc1 * dc1 + 1.f);
-  dc0 *= inv;
-  dc1 *= inv;
-  dc2 *= inv;
-  float v32[kCC];
-#pragma unroll
-  for (int k = 0; k < kCC; ++k) v32[k] = 0.f;
   const float* row = feat + p * C;
+  float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (vec && k0 + 4 <= Df) {
+    out = *reinterpret_cast<const float4*>(row + k0);
+  } else if (k0 < Df + 3 + E) {
+    const int u = (int)(p % g.W), v = (int)(p / g.W);
+    float dc0 = ((float)u + 0.5f - g.cx) / g.fx, dc1 = ((float)v + 0.5f - g.cy) / g.fy, dc2 = 1.f;
+    const float inv = rsqrtf(dc0 * dc0 + dc1 * dc1 + 1.f);
+    dc0 *= inv;
+    dc1 *= inv;
+    dc2 *= inv;
+    // world direction R^T d_c
+    const float dw0 = g.R[0] * dc0 + g.R[3] * dc1 + g.R[6] * dc2, dw1 = g.R[1] * dc0 + g.R[4] * dc1 + g.R[7] * dc2,
+                dw2 = g.R[2] * dc0 + g.R[5] * dc1 + g.R[8] * dc2;
+    float o4[4];
 #pragma unroll
-  for (int k = 0; k < kCC; ++k)
-    if (k < Df) v32[k] = row[k];
-  // world direction R^T d_c
-  const float dw[3] = {g.R[0] * dc0 + g.R[3] * dc1 + g.R[6] * dc2, g.R[1] * dc0 + g.R[4] * dc1 + g.R[7] * dc2,
-                       g.R[2] * dc0 + g.R[5] * dc1 + g.R[8] * dc2};
-#pragma unroll
-  for (int k = 0; k < kCC; ++k) {
-    if (k >= Df && k < Df + 3) v32[k] = dw[k - Df];
-    if (k >= Df + 3 && k < Df + 3 + E) v32[k] = embed[k - Df - 3];
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + j;
+      o4[j] = k < Df            ? row[k]
+              : k == Df         ? dw0
+              : k == Df + 1     ? dw1
+              : k == Df + 2     ? dw2
+              : k < Df + 3 + E  ? embed[k - Df - 3]
+                                : 0.f;
+    }
+    out = make_float4(o4[0], o4[1], o4[2], o4[3]);
   }
-  float4* o = reinterpret_cast<float4*>(x0 + p * kCC);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) o[q] = make_float4(v32[4 * q], v32[4 * q + 1], v32[4 * q + 2], v32[4 * q + 3]);
+  reinterpret_cast<float4*>(x0 + p * kCC)[t & 7] = out;
 }
 
 // the stem's input gradient: d_feat += dx[0:Df]; per-workgroup sums of dx[Df+3 : Df+3+E] (embedding)
@@ -588,8 +597,9 @@ int splat_camera_decode(const SplatCamera* cam, const float* feat, const SplatCa
   const int C = cam->n_channels > 0 ? cam->n_channels : cnn->n_feat;
   if (cnn->n_feat > C) return SPLAT_ERR_INVALID_ARG;
   const int cin = cnn->n_feat + 3 + cnn->n_embed;
-  hipLaunchKernelGGL(k_cnn_input, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, feat, C, cnn->n_feat, cnn->n_embed,
-                     cnn->embed, cnn_geo(cam), w.act[0]);
+  const int vec = (((uintptr_t)feat & 15) == 0 && ((C | cnn->n_feat) & 3) == 0) ? 1 : 0;
+  hipLaunchKernelGGL(k_cnn_input, dim3((unsigned)div_up(8 * n, 256)), dim3(256), 0, s, feat, C, cnn->n_feat,
+                     cnn->n_embed, cnn->embed, cnn_geo(cam), vec, w.act[0]);
   hipError_t e = conv(w.act[0], w.act[1], cnn->w_in, cin, kCC, 0, cnn->b_in, nullptr, nullptr, 1, W, H, w.frag, s);
   for (int k = 0; k < 2 && e == hipSuccess; ++k) {
     float* hin = w.act[1 + 2 * k];

@@ -100,6 +100,37 @@ def test_camera_decoder_matches_oracle(w, h, E):
         _rel(dcnn["b_block"][j].cpu().numpy(), g["b_block"][j], f"b_block{j}")
 
 
+@pytest.mark.parametrize("Df,C,E", [(7, 10, 5), (12, 14, 8), (12, 12, 3), (13, 13, 0)])
+def test_camera_decoder_other_feature_widths(Df, C, E):
+    # feature rows of C floats of which the network reads the first Df (C, Df not multiples of 4:
+    # the element-wise input path); the other channels of d_feat stay untouched
+    b = _binding()
+    w, h = 29, 19
+    rng = np.random.default_rng(100 * Df + C + E)
+    cam = _camera(w, h, n_ch=C)
+    print(f"[cnn] Df={Df} C={C} E={E}", flush=True)
+    W = _weights(rng, Df, E)
+    F = _f32(rng.normal(size=(h, w, C)))
+    dI = _f32(rng.normal(size=(h, w, 3)))
+    cnn = _dev_cnn(b, W)
+    ws = b.camera_decode_workspace(cam)
+    Fd = torch.from_numpy(F.reshape(-1)).cuda()
+    I = b.camera_decode(cam, Fd, cnn, ws)
+    dF = torch.zeros_like(Fd)
+    dcnn = {"embed": torch.zeros_like(cnn.embed), "w_in": torch.zeros_like(cnn.w_in), "b_in": torch.zeros_like(cnn.b_in),
+            "w_block": [torch.zeros_like(x) for x in cnn.w_block], "b_block": [torch.zeros_like(x) for x in cnn.b_block],
+            "w_out": torch.zeros_like(cnn.w_out), "b_out": torch.zeros_like(cnn.b_out)}
+    b.camera_decode_bwd(cam, Fd, cnn, torch.from_numpy(dI.reshape(-1)).cuda(), dF, dcnn, ws)
+    torch.cuda.synchronize()
+    ref, g = _oracle(np.ascontiguousarray(F[..., :Df]), cam, W, dI)
+    _close(I.cpu().numpy().reshape(h, w, 3), ref, "image")
+    dFh = dF.cpu().numpy().reshape(h, w, C)
+    _rel(dFh[..., :Df], g["F"], "d_feat")
+    assert (dFh[..., Df:] == 0).all()
+    for k in ("w_in", "b_in") + (("embed",) if E else ()):
+        _rel(dcnn[k].cpu().numpy(), g[k], k)
+
+
 def _crop_ref(F, cam, W, x0, y0, cw, chh):
     m = 5
     xs, ys = max(0, x0 - m), max(0, y0 - m)
