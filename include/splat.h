@@ -61,7 +61,10 @@ typedef struct SplatStatus {
   unsigned long long n_isect;     /* intersections (tile, Gaussian) of the last bin/sort      */
   unsigned long long k_cap;       /* capacity the last bin/sort was given                      */
   unsigned int overflow;          /* non-zero if n_isect exceeded k_cap (lists truncated)      */
-  unsigned int n_nonfinite;       /* projections culled because of non-finite values           */
+  unsigned int n_nonfinite;       /* (Gaussian, sensor) projections culled because of non-finite
+                                     values: a non-finite sensor-frame mean, or a non-finite
+                                     projected mean, velocity, conic, o_eff, box or depth of a
+                                     Gaussian inside the depth / range limits                   */
   unsigned int n_rays_invalid;    /* lidar rays outside [0, 2pi) x [b_0, b_M): output zeros    */
   unsigned int n_rays_time;       /* lidar rays with |t| > t_rs / 2 (still rendered)           */
   unsigned long long n_pairs;     /* (ray, Gaussian) pairs the forward rasterisers evaluated

@@ -20,6 +20,8 @@ Candidate rule:
   BOX  (default) -- Gaussians whose 3-sigma + rolling-shutter box contains the sample point
                     (lo <= p < hi; the azimuth test is modular: (phi - lo) mod 2pi < hi - lo);
   TILE (literal) -- Gaussians whose tile range contains the ray's tile.
+Under either rule a candidacy decided within the float32 band of a box edge (BOX) or of a tile
+border (TILE) makes the ray near-decision if that Gaussian would pass the alpha skip rule there.
 
 Pins (tests/test_oracle_render.py): single-Gaussian and two-Gaussian closed forms, empty scene,
 monotone transmittance, weights summing to 1 - T, permutation invariance, rolling shutter
@@ -104,9 +106,16 @@ def _box_mask(proj, cols, p, lo_pad=0.0):
     return m_az & m_el
 
 
-def _tile_mask(proj, sensor, cols, rays_tile):
+def _tile_mask(proj, sensor, cols, rays_tile, lo_pad=0.0):
+    """Candidacy of Gaussians `cols` under TILE: the ray's tile lies in the Gaussian's tile
+    range.  `lo_pad` widens (> 0) or narrows (< 0) every box edge by lo_pad * (|mean| + ext)
+    before the ranges are taken, to find tile decisions within the float32 ambiguity band."""
     lo = proj.lo[cols].detach().numpy()
     hi = proj.hi[cols].detach().numpy()
+    if lo_pad != 0.0:
+        pad = lo_pad * (np.abs(proj.mean2d[cols].detach().numpy()) + proj.ext[cols].detach().numpy())
+        lo = lo - pad
+        hi = hi + pad
     if proj.kind == "lidar":
         start, n_az, el0, el1 = tl.lidar_tile_rect(lo, hi, sensor)
         M = sensor.n_az_tiles
@@ -252,9 +261,11 @@ def render(proj, sensor, feats_all, rays: Rays, mode: str = "box", chunk: int = 
             near_box = torch.zeros(e - s, dtype=torch.bool)
         else:
             cand_all = _tile_mask(proj, sensor, order, rays.tile[s:e])
+            # a box edge within the float32 band of a tile border: the tile decision may differ
+            wide = _tile_mask(proj, sensor, order, rays.tile[s:e], NEAR_BOX)
+            narrow = _tile_mask(proj, sensor, order, rays.tile[s:e], -NEAR_BOX)
+            amb_all = wide != narrow
             near_box = torch.zeros(e - s, dtype=torch.bool)
-            wide = cand_all
-            amb_all = None
         # Gaussians whose culling is a near-threshold decision make the ray near if their box
         # reaches it and they would pass the alpha skip rule there
         nc_ids = np.nonzero(near_cull)[0]

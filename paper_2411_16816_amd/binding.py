@@ -286,10 +286,14 @@ class SensorPass:
         self.dropped = torch.empty((max(1, self.n_rays),), dtype=torch.uint8, device=device) if self.has_lidar \
             else None
         self.status = _status_tensor(device)
+        # bumped by every call that rewrites the forward state (records, lists, outputs,
+        # capacity); SplatRenderFn.backward refuses state newer than its forward
+        self.generation = 0
         self.set_capacity(k_cap)
 
     # ---- structs -------------------------------------------------------------------------
     def set_capacity(self, k_cap: int):
+        self.generation += 1
         self.k_cap = int(k_cap)
         self.gauss = torch.empty((max(1, self.k_cap),), dtype=torch.int32, device=self.device)
         nbytes = int(self.lib.splat_workspace_bytes(self.rig.handle, self.first, self.count, self.n_gauss, self.k_cap))
@@ -327,12 +331,14 @@ class SensorPass:
 
     # ---- the four calls -------------------------------------------------------------------
     def project(self, g: GaussTensors, stream=None):
+        self.generation += 1
         fn = (self.lib.splat_project if self.batched else
               self.lib.splat_project_lidar if self.lidar else self.lib.splat_project_camera)
         check(fn(C.byref(g.struct()), self.rig.handle, self.first, self.count, C.byref(self.proj_struct()),
                  _ptr(self.status), _stream(stream)), "splat_project")
 
     def bin_sort(self, stream=None):
+        self.generation += 1
         fn = (self.lib.splat_bin_sort if self.batched else
               self.lib.splat_bin_sort_lidar if self.lidar else self.lib.splat_bin_sort_camera)
         check(fn(self.rig.handle, self.first, self.count, self.n_gauss, C.byref(self.proj_struct()),
@@ -350,6 +356,7 @@ class SensorPass:
     def raster_fwd(self, g: GaussTensors, support=BOX, stream=None, count_pairs: bool = False, timer=None,
                    sensor_done: Optional[torch.Tensor] = None):
         """sensor_done: optional int64 [count] device tensor of per-sensor completion clocks."""
+        self.generation += 1
         st_ = _ptr(self.status) if count_pairs else None
         self._time(timer)
         out = self.out_struct(sensor_done)
@@ -479,10 +486,20 @@ def zeros_like_grads(g: GaussTensors) -> GaussTensors:
                         None if g.velocities is None else z(g.velocities), z(g.features))
 
 
+def check_saved_state(sp, generation: int):
+    """Raise unless `sp` still holds the forward state recorded at `generation`."""
+    if sp.generation != generation:
+        raise SplatError("SplatRenderFn.backward: the SensorPass was used again after this forward "
+                         f"(state {sp.generation}, forward {generation}); run backward before the next "
+                         "render through the same pass, or give each render its own pass")
+
+
 class SplatRenderFn(torch.autograd.Function):
     """Differentiable render of one call range.  Inputs are the Gaussian tensors; outputs are the
     flat feature rows, depth and alpha of the call (see SensorPass.sensor_slices).  The pass's
-    buffers hold the forward state, so backward must run before the pass renders again."""
+    buffers hold the forward state, so backward must run before the pass renders again: a
+    backward whose pass has projected, binned, rendered or been resized since its forward raises
+    SplatError instead of differentiating the newer state."""
 
     @staticmethod
     def forward(ctx, sp: SensorPass, support: int, means, log_scales, quats, opacities, velocities, features):
@@ -497,6 +514,7 @@ class SplatRenderFn(torch.autograd.Function):
             sp.bin_sort()
         sp.raster_fwd(g, support)
         ctx.sp, ctx.support, ctx.g = sp, support, g
+        ctx.generation = sp.generation
         ctx.has_vel = velocities is not None
         o = sp.outputs()
         return o["feat"].clone(), o["depth"].clone(), o["alpha"].clone()
@@ -504,6 +522,7 @@ class SplatRenderFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, dF, dD, dA):
         sp, g = ctx.sp, ctx.g
+        check_saved_state(sp, ctx.generation)
         grads = zeros_like_grads(g)
         f32 = lambda t, n: torch.zeros(n, dtype=torch.float32, device=g.means.device) if t is None else t.contiguous()
         sp.raster_bwd(g, f32(dF, sp.n_feat), f32(dD, sp.n_rays), f32(dA, sp.n_rays), grads, ctx.support)
@@ -795,10 +814,40 @@ MCMC_DEAD_OPACITY = 0.005
 MCMC_N_MAX = 51
 
 
+def check_relocate_args(g: GaussTensors, u: torch.Tensor):
+    """Host-side checks of splat_mcmc_relocate's arrays (the C side sees raw pointers only and
+    cannot tell a short or mistyped array): contiguous float32 Gaussian arrays of n rows with
+    3 / 3 / 4 / 1 / 3 / C columns on one device, and u a contiguous int32 or uint32 array of at
+    least n entries on that device.  Raises SplatError."""
+    if g.means is None or g.means.dim() != 2 or g.means.shape[1] != 3:
+        raise SplatError("mcmc_relocate: means must be [n, 3]")
+    n = int(g.means.shape[0])
+    dev = g.means.device
+    shapes = {"means": (3,), "log_scales": (3,), "quats": (4,), "opacities": (), "velocities": (3,),
+              "features": None}
+    for name, cols in shapes.items():
+        t = getattr(g, name)
+        if t is None:
+            if name == "velocities":
+                continue
+            raise SplatError(f"mcmc_relocate: {name} is required")
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.device != dev:
+            raise SplatError(f"mcmc_relocate: {name} must be a contiguous float32 tensor on {dev}")
+        ok = t.shape[0] == n and (t.dim() == 2 if cols is None else tuple(t.shape[1:]) == cols)
+        if not ok:
+            raise SplatError(f"mcmc_relocate: {name} has shape {tuple(t.shape)}, expected {n} rows"
+                             + ("" if cols is None else f" of shape {cols}"))
+    if u is None or u.dtype not in (torch.int32, torch.uint32) or not u.is_contiguous() or u.device != dev:
+        raise SplatError(f"mcmc_relocate: u must be a contiguous int32 or uint32 tensor on {dev}")
+    if u.numel() < n:
+        raise SplatError(f"mcmc_relocate: u holds {u.numel()} randoms for {n} Gaussians")
+
+
 def mcmc_relocate(g: GaussTensors, u: torch.Tensor, dead_opacity: float = MCMC_DEAD_OPACITY,
                   n_max: int = MCMC_N_MAX, ws: Optional[torch.Tensor] = None, stream=None):
     """Relocates g's dead Gaussians in place.  u: int32 device tensor [n] holding uint32 random
     bits.  Returns (target int32 [n], number relocated as an int64 device tensor)."""
+    check_relocate_args(g, u)
     lib = load()
     n = int(g.means.shape[0])
     st_ = st.SplatGaussianState()

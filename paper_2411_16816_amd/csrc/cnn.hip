@@ -299,8 +299,10 @@ __global__ __launch_bounds__(256) void k_cnn_input(const float* __restrict__ fea
 }
 
 // the stem's input gradient: d_feat += dx[0:Df]; per-workgroup sums of dx[Df+3 : Df+3+E] (embedding)
+// vec: the host found d_feat 16-byte aligned and C, Df multiples of 4 (16-byte rows)
 __global__ __launch_bounds__(256) void k_cnn_input_bwd(const float* __restrict__ dx0, int64_t n, int C, int Df, int E,
-                                                        float* __restrict__ d_feat, float* __restrict__ partial_e) {
+                                                        int vec, float* __restrict__ d_feat,
+                                                        float* __restrict__ partial_e) {
   __shared__ float s_e[256][9];
   __shared__ float s_p[8][9];
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -320,7 +322,7 @@ __global__ __launch_bounds__(256) void k_cnn_input_bwd(const float* __restrict__
     }
     if (d_feat) {
       float* row = d_feat + p * C;
-      if (((C | Df) & 3) == 0) {   // uniform: 16-byte rows
+      if (vec) {   // uniform: 16-byte rows
         float4 old[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q)
@@ -665,8 +667,9 @@ int splat_camera_decode_bwd(const SplatCamera* cam, const float* feat, const Spl
   if (e == hipSuccess) e = conv(dp, dx0, cnn->w_in, cin, kCC, 1, nullptr, nullptr, nullptr, 0, W, H, w.frag, s);
   if (e != hipSuccess) return SPLAT_ERR_DEVICE;
   const int64_t eb = input_bwd_blocks(n);
+  const int vec = (((uintptr_t)d_feat & 15) == 0 && ((C | cnn->n_feat) & 3) == 0) ? 1 : 0;
   hipLaunchKernelGGL(k_cnn_input_bwd, dim3((unsigned)eb), dim3(256), 0, s, (const float*)dx0, n, C, cnn->n_feat,
-                     cnn->n_embed, d_feat, w.partial);
+                     cnn->n_embed, vec, d_feat, w.partial);
   if (cnn->n_embed > 0) launch_column_sums((const float*)w.partial, 8, (int)eb, cnn->n_embed, AddTo{d_cnn->embed}, s);
   return hipGetLastError() == hipSuccess ? SPLAT_OK : SPLAT_ERR_DEVICE;
 }

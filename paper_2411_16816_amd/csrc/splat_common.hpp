@@ -363,6 +363,8 @@ HD void project_one(const DevSensor& S, const float mu_w[3], const float M[9], c
   o.n_tiles = 0;
   o.nonfinite = false;
   sensor_frame(S, mu_w, M, vg, I);
+  // a non-finite mean fails every depth / range comparison: count it rather than cull it silently
+  if (!(finite_f(I.mu[0]) && finite_f(I.mu[1]) && finite_f(I.mu[2]))) { o.nonfinite = true; return; }
   bool ok = (S.kind == kCamera) ? project_camera_core(S, I, o) : project_lidar_core(S, I, o);
   if (!ok) return;
   dilate_and_box(S, opac, I, o);

@@ -59,3 +59,30 @@ def last_ids_gpu(sp, k, sensor, ray_idx, last):
         if t >= 0 and l > 0:
             out[i] = lists[base + t][l - 1]
     return out
+
+
+def grad_mismatch(got, ref, rtol=1e-3, afloor=1e-5):
+    """Elements outside the per-element gradient bar |g - g_ref| <= rtol |g_ref| + afloor max|g_ref|."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return np.abs(got - ref) > rtol * np.abs(ref) + afloor * np.abs(ref).max(initial=0.0)
+
+
+def assert_grad_close(got, ref, what, rtol=1e-3, norm_tol=1e-3, afloor=1e-5, require_nonzero=True):
+    """The gradient bar of the parity tests: ||g - g_ref|| <= norm_tol ||g_ref|| for the array,
+    and |g - g_ref| <= rtol |g_ref| + afloor max|g_ref| for every element.  On failure the
+    message names the worst elements (flat index, GPU value, reference value)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    nrm = float(np.linalg.norm(ref))
+    if require_nonzero:
+        assert nrm > 0, f"{what}: reference gradient is zero"
+    rel = float(np.linalg.norm(got - ref)) / max(nrm, 1e-300)
+    bad = grad_mismatch(got, ref, rtol, afloor)
+    if rel <= norm_tol and not bad.any():
+        return
+    err = (np.abs(got - ref) / (rtol * np.abs(ref) + afloor * np.abs(ref).max(initial=0.0) + 1e-300)).reshape(-1)
+    worst = np.argsort(-err)[:8]
+    rows = ", ".join(f"[{int(i)}] gpu {got.reshape(-1)[i]:.6g} ref {ref.reshape(-1)[i]:.6g}" for i in worst)
+    raise AssertionError(f"{what}: relative norm error {rel:.3g}, {int(bad.sum())} of {bad.size} elements "
+                         f"outside the bar; worst: {rows}")

@@ -61,9 +61,14 @@ def _close(a, r, what):
 
 
 def _rel(a, r, what, tol=1e-4):
+    """Within `tol` of the reference's norm, and element by element within 1e-3 relative with
+    an absolute floor of 1e-5 max |ref| (the gradient bar of the rasteriser tests)."""
+    a = a.astype(np.float64)
     nr = np.linalg.norm(r)
-    d = np.linalg.norm(a.astype(np.float64) - r)
+    d = np.linalg.norm(a - r)
     assert d <= tol * max(nr, 1e-30), (what, d / max(nr, 1e-30))
+    bad = np.abs(a - r) > 1e-3 * np.abs(r) + 1e-5 * np.abs(r).max(initial=0.0)
+    assert not bad.any(), (what, int(bad.sum()), int(bad.size))
 
 
 def _camera(w, h, yaw=20.0, n_ch=16):
@@ -178,3 +183,40 @@ def test_camera_decoder_edge_cases():
     torch.cuda.synchronize()
     ref, _ = _oracle(np.zeros((8, 8, 16), np.float32), cam, W)
     _close(I.cpu().numpy().reshape(8, 8, 3), ref, "zero features")
+
+
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_camera_decoder_unaligned_feature_gradient(shift):
+    """d_feat (and feat) as views at 4-, 8- and 12-byte offsets into a larger buffer, with C and
+    Df multiples of 4: the element-wise path must be taken, and the result must equal the one
+    from aligned buffers exactly (the same sums, added once per element)."""
+    b = _binding()
+    w, h = 23, 17
+    rng = np.random.default_rng(900 + shift)
+    cam = _camera(w, h)
+    W = _weights(rng, 16, 8)
+    F = _f32(rng.normal(size=(h, w, 16)))
+    dI = torch.from_numpy(_f32(rng.normal(size=(h, w, 3))).reshape(-1)).cuda()
+    cnn = _dev_cnn(b, W)
+    ws = b.camera_decode_workspace(cam)
+    n = F.size
+    base = torch.from_numpy(F.reshape(-1)).cuda()
+    big_f = torch.zeros(n + 8, device="cuda")
+    big_f[shift:shift + n] = base
+    f_off = big_f[shift:shift + n]
+    init = torch.from_numpy(_f32(rng.normal(size=n))).cuda()
+    big_d = torch.full((n + 8,), 7.0, device="cuda")
+    big_d[shift:shift + n] = init
+    d_off = big_d[shift:shift + n]
+    assert d_off.data_ptr() % 16 != 0 and f_off.data_ptr() % 16 != 0
+    zeros = lambda: {"embed": torch.zeros_like(cnn.embed), "w_in": torch.zeros_like(cnn.w_in)}
+    I_a = b.camera_decode(cam, base, cnn, ws)
+    d_a = init.clone()
+    b.camera_decode_bwd(cam, base, cnn, dI, d_a, zeros(), ws)
+    I_u = b.camera_decode(cam, f_off, cnn, ws)
+    b.camera_decode_bwd(cam, f_off, cnn, dI, d_off, zeros(), ws)
+    torch.cuda.synchronize()
+    assert torch.equal(I_a, I_u)
+    assert torch.equal(d_a, d_off)
+    # the guard floats on either side of the view are untouched
+    assert (big_d[:shift] == 7.0).all() and (big_d[shift + n:] == 7.0).all()

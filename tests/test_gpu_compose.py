@@ -9,6 +9,7 @@ import torch
 
 from oracle import compose as oc
 from scenes import synthetic as S
+from tests.gpu_helpers import assert_grad_close
 
 pytestmark = pytest.mark.gpu
 
@@ -85,9 +86,9 @@ def test_compose_matches_oracle(n_actors, contiguous, tumbling):
     for a, r, w in zip(out, ref, ("means", "quats", "velocities")):
         _close(a, r, w)
     for name, x in (("means", dm), ("quats", dq), ("vel", dv)):
-        assert _rel(x.cpu().numpy(), rg[name]) <= 1e-3, name
+        assert_grad_close(x.cpu().numpy(), rg[name], name)
     for f, x in da.items():
-        assert _rel(x.cpu().numpy(), rg[f]) <= 1e-3, f
+        assert_grad_close(x.cpu().numpy(), rg[f], f)
 
 
 def test_compose_edge_cases():
@@ -106,7 +107,7 @@ def test_compose_edge_cases():
     for a, r, w in zip(out, ref, ("means", "quats", "velocities")):
         _close(a, r, w)
     for name, x in (("means", dm), ("quats", dq), ("vel", dv)):
-        assert _rel(x.cpu().numpy(), rg[name]) <= 1e-3, name
+        assert_grad_close(x.cpu().numpy(), rg[name], name)
     # an all-static scene copies its inputs exactly
     sc = S.actor_scene(7, 3000, 0)
     mu, q, v, aid, A = _dev(b, sc)
@@ -134,9 +135,9 @@ def test_compose_full_size_sampled():
     for a, r, w in zip(out, ref, ("means", "quats", "velocities")):
         _close(a[idx], r[idx], w)
     for name, x in (("means", dm), ("quats", dq)):
-        assert _rel(x.cpu().numpy()[idx], rg[name][idx]) <= 1e-3, name
+        assert_grad_close(x.cpu().numpy()[idx], rg[name][idx], name)
     for f, x in da.items():
-        assert _rel(x.cpu().numpy(), rg[f]) <= 1e-3, f
+        assert_grad_close(x.cpu().numpy(), rg[f], f)
 
 
 def test_compose_autograd_function_feeds_render():

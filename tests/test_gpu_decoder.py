@@ -37,8 +37,13 @@ def _close(a, r, what):
 
 
 def _rel(a, r, what, tol=1e-4):
+    """Within `tol` of the reference's norm, and element by element within 1e-3 relative with
+    an absolute floor of 1e-5 max |ref| (the gradient bar of the rasteriser tests)."""
+    a = a.astype(np.float64)
     nr = np.linalg.norm(r)
-    assert np.linalg.norm(a.astype(np.float64) - r) <= tol * max(nr, 1e-30), (what, np.linalg.norm(a - r) / nr)
+    assert np.linalg.norm(a - r) <= tol * max(nr, 1e-30), (what, np.linalg.norm(a - r) / max(nr, 1e-30))
+    bad = np.abs(a - r) > 1e-3 * np.abs(r) + 1e-5 * np.abs(r).max(initial=0.0)
+    assert not bad.any(), (what, int(bad.sum()), int(bad.size))
 
 
 def _run(b, F, az, el, W, dI, dP):

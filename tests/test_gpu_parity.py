@@ -16,7 +16,7 @@ from oracle import grad as ogr
 from oracle import render as rd
 from oracle import tiles as tl
 from scenes import synthetic as S
-from tests.gpu_helpers import gpu_outputs, last_ids_gpu, rtol_check, tile_lists_gpu
+from tests.gpu_helpers import assert_grad_close, gpu_outputs, last_ids_gpu, rtol_check, tile_lists_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -92,7 +92,11 @@ def _check_projection(sp, g, sensor):
     for k in ref:
         scale = max(1e-12, float(np.abs(ref[k]).max()))
         bad = rtol_check(got[k], ref[k], rtol=2e-5, atol=2e-6 * scale)
-        assert bad.mean() < 1e-3 and (np.abs(got[k] - ref[k]) <= 1e-4 * scale + 1e-3 * np.abs(ref[k])).all(), k
+        if bad.any():
+            i = np.argwhere(bad)[:6]
+            rows = [(tuple(int(v) for v in ix), float(got[k][tuple(ix)]), float(ref[k][tuple(ix)])) for ix in i]
+            raise AssertionError(f"projection {k}: {int(bad.sum())} of {bad.size} elements beyond 2e-5 relative "
+                                 f"/ 2e-6 of the largest; first: {rows}")
     # stage check: tile rectangles bit-exact with the documented float32 arithmetic
     rect = sp.rect.cpu().numpy()[keep]
     gb = sp.box.cpu().numpy()[keep]
@@ -484,14 +488,7 @@ def _grad_check(kind, seed, lidar_tile_az=16):
     got = dict(means=grads.means, log_scales=grads.log_scales, quats=grads.quats, opacities=grads.opacities,
                velocities=grads.velocities, features=grads.features)
     for name in geo.Params.names:
-        gg = got[name].cpu().numpy().astype(np.float64)
-        rr = ref[name]
-        nrm = np.linalg.norm(rr)
-        assert nrm > 0, name
-        rel = np.linalg.norm(gg - rr) / nrm
-        assert rel <= 1e-3, (name, rel)
-        bad = np.abs(gg - rr) > 1e-3 * np.abs(rr) + 1e-5 * np.abs(rr).max()
-        assert bad.mean() < 2e-3, (name, int(bad.sum()))
+        assert_grad_close(got[name].cpu().numpy(), ref[name], f"{kind} {name}")
 
 
 def test_backward_camera():

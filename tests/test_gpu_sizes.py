@@ -20,7 +20,7 @@ from oracle import geometry as geo
 from oracle import grad as ogr
 from oracle import render as rd
 from scenes import synthetic as S
-from tests.gpu_helpers import gpu_outputs, rtol_check
+from tests.gpu_helpers import assert_grad_close, gpu_outputs, rtol_check
 
 pytestmark = pytest.mark.gpu
 
@@ -109,14 +109,7 @@ def test_full_size_forward_and_gradients(cfg, rays):
     got = dict(means=grads.means, log_scales=grads.log_scales, quats=grads.quats, opacities=grads.opacities,
                velocities=grads.velocities, features=grads.features)
     for name in geo.Params.names:
-        gg = got[name].cpu().numpy().astype(np.float64)
-        rr = ref[name]
-        nrm = np.linalg.norm(rr)
-        assert nrm > 0, name
-        assert np.linalg.norm(gg - rr) / nrm <= 1e-3, (cfg, name, np.linalg.norm(gg - rr) / nrm)
-        bad = np.abs(gg - rr) > 1e-3 * np.abs(rr) + 1e-5 * np.abs(rr).max()
-        nz = int(((rr != 0) | (gg != 0)).sum())   # elements that a sampled ray reaches
-        assert bad.sum() <= max(2, 2e-3 * nz), (cfg, name, int(bad.sum()), nz)
+        assert_grad_close(got[name].cpu().numpy(), ref[name], f"{cfg} {name}")
 
 
 def test_full_size_c5_forward():

@@ -241,3 +241,112 @@ def test_rolling_shutter_box_extension():
     s2 = (100.0 * 0.1 / 5.0) ** 2
     v = 100.0 * 2.0 / 5.0
     np.testing.assert_allclose(pr.ext[0].numpy(), [3 * math.sqrt(s2 + 0.3) + v * 0.02, 3 * math.sqrt(s2 + 0.3)], rtol=1e-6)
+
+
+# ------------------------------------------------------------------------------------------
+# Jacobian clamp off the frustum (the 3DGS projection the paper keeps, Sec. 3.2): J^I is
+# evaluated at x/z and y/z clamped to +-jac_clamp * (size / 2) / f, while the mean is not
+# ------------------------------------------------------------------------------------------
+def _clamp_camera(jac_clamp):
+    # fx != fy and width != height, so a swapped focal length or half-size changes the limits
+    return S.make_camera((0, 0, 0), 0.0, 64, 48, 100.0, fy=80.0, cx=32.0, cy=24.0, t_rs=0.0,
+                         jac_clamp=jac_clamp)
+
+
+def _clamp_closed_form(fx, fy, z, tx, ty, sig, vrel):
+    """Hand-expanded J Sigma J^T for an isotropic Sigma = sig^2 I and J v, with J evaluated at
+    (tx, ty) = (x/z, y/z) after the clamp: J = [[fx/z, 0, -fx tx/z], [0, fy/z, -fy ty/z]]."""
+    s = (sig / z) ** 2
+    cov = s * np.array([[fx * fx * (1 + tx * tx), fx * fy * tx * ty],
+                        [fx * fy * tx * ty, fy * fy * (1 + ty * ty)]])
+    vx, vy, vz = vrel
+    vel = np.array([fx * (vx - tx * vz) / z, fy * (vy - ty * vz) / z])
+    return cov, vel
+
+
+def _clamp_cases(geo_mod):
+    """Yields (got cov, got vel, got mean, expected cov, expected vel, expected mean) for points
+    beyond the clamp on both axes (one of them negative), inside it, and with the clamp off."""
+    sig = 0.25
+    lin = np.array([-1.5, 0.7, -2.0])              # camera frame; the Gaussian is static
+    vrel = -lin                                    # relative velocity of a static point
+    cases = []
+    # (x/z, y/z, z, jac_clamp) -> clamped (tx, ty) by hand
+    for rx, ry, z, jc, tx, ty in [
+        (0.8, -0.6, 10.0, 1.3, 1.3 * 32 / 100, -1.3 * 24 / 80),    # both clamped
+        (-0.5, 0.45, 7.0, 1.3, -1.3 * 32 / 100, 1.3 * 24 / 80),    # both clamped, signs flipped
+        (0.2, 0.1, 12.0, 1.3, 0.2, 0.1),                           # inside: untouched
+        (0.8, -0.6, 10.0, 2.0, 2.0 * 32 / 100, -2.0 * 24 / 80),    # another clamp value
+        (0.8, -0.6, 10.0, 0.0, 0.8, -0.6),                         # clamp off
+    ]:
+        cam = _clamp_camera(jc)
+        cam.lin_vel = lin.astype(np.float32)
+        # camera axes: x_c = -Y_w, y_c = -Z_w, z_c = X_w for this camera at the origin
+        xc, yc = rx * z, ry * z
+        g = _gauss([[z, -xc, -yc]], log_scales=[[math.log(sig)] * 3])
+        pr = geo_mod.project_camera(geo_mod.Params.from_gaussians(g), cam)
+        m = g.means[0].astype(np.float64)
+        zf, xf, yf = m[0], -m[1], -m[2]             # the float32 point actually used
+        t_x = tx if jc > 0 and abs(xf / zf) > jc * 32 / 100 else xf / zf
+        t_y = ty if jc > 0 and abs(yf / zf) > jc * 24 / 80 else yf / zf
+        s_f = float(np.float32(sig))
+        cov, vel = _clamp_closed_form(100.0, 80.0, zf, t_x, t_y, math.exp(math.log(s_f)), vrel.astype(np.float32).astype(np.float64))
+        mean = np.array([100.0 * xf / zf + 32.0, 80.0 * yf / zf + 24.0])   # never clamped
+        cases.append((pr.cov2d[0].detach().numpy(), pr.vel2d[0].detach().numpy(),
+                      pr.mean2d[0].detach().numpy(), cov, vel, mean, (rx, ry, jc)))
+    return cases
+
+
+def _check_clamp(geo_mod):
+    for got_c, got_v, got_m, cov, vel, mean, tag in _clamp_cases(geo_mod):
+        np.testing.assert_allclose(got_c, cov, rtol=1e-6, atol=1e-9, err_msg=str(tag))
+        np.testing.assert_allclose(got_v, vel, rtol=1e-6, atol=1e-9, err_msg=str(tag))
+        np.testing.assert_allclose(got_m, mean, rtol=1e-9, atol=1e-9, err_msg=str(tag))
+
+
+def test_jacobian_clamp_closed_form():
+    _check_clamp(geo)
+
+
+def test_jacobian_clamp_changes_the_projection():
+    """With the clamp on, an off-frustum Gaussian's covariance and velocity differ from the
+    unclamped ones by far more than the pin's tolerance (the pin can tell them apart)."""
+    cases = _clamp_cases(geo)
+    on, off = cases[0], cases[4]
+    assert np.abs(on[0] - off[0]).max() > 0.05 * np.abs(off[0]).max()
+    assert np.abs(on[1] - off[1]).max() > 0.05 * np.abs(off[1]).max()
+    np.testing.assert_allclose(on[2], off[2], rtol=1e-12)          # the mean is the same
+
+
+def _mutant_geometry(old, new):
+    """The oracle's geometry module with one planted mistake (source replaced once), on the CPU."""
+    import inspect
+    import types
+    src = inspect.getsource(geo)
+    assert src.count(old) == 1, old
+    import sys
+    name = "oracle._geometry_mutant"
+    mod = types.ModuleType(name)
+    sys.modules[name] = mod          # dataclasses look their module up while being created
+    try:
+        exec(compile(src.replace(old, new), name, "exec"), mod.__dict__)
+    finally:
+        del sys.modules[name]
+    return mod
+
+
+@pytest.mark.parametrize("old,new", [
+    # full size instead of half size
+    ("limx = cam.jac_clamp * 0.5 * cam.width / cam.fx", "limx = cam.jac_clamp * cam.width / cam.fx"),
+    # x clamped instead of x/z
+    ("tx = torch.clamp(tx, -limx, limx)", "tx = torch.clamp(x, -limx, limx) / zs"),
+    # width and height swapped
+    ("limy = cam.jac_clamp * 0.5 * cam.height / cam.fy", "limy = cam.jac_clamp * 0.5 * cam.width / cam.fy"),
+    # the clamp dropped on y
+    ("ty = torch.clamp(ty, -limy, limy)", "ty = ty"),
+    # the clamped ratio leaking into the mean
+    ("u = cam.fx * x / zs + cam.cx", "u = cam.fx * torch.clamp(x / zs, -1.3 * 0.5 * cam.width / cam.fx, 1.3 * 0.5 * cam.width / cam.fx) + cam.cx"),
+])
+def test_jacobian_clamp_pin_catches_planted_mistakes(old, new):
+    with pytest.raises(AssertionError):
+        _check_clamp(_mutant_geometry(old, new))

@@ -246,3 +246,42 @@ def test_tile_rule_is_superset_of_box_candidates():
     tile = rd._tile_mask(pr, cam, order, rays.tile).numpy()
     assert np.all(tile[box])
     assert tile.sum() > box.sum()
+
+
+def test_tile_rule_hand_worked():
+    """TILE mode (the paper's rule: every Gaussian listed for the pixel's tile, Sec. 3.2, and
+    App. A's lidar tile ranges) on boxes chosen by hand: the candidate set is the union of
+    whole tiles, worked out on paper below, including pixels outside the box."""
+    from types import SimpleNamespace
+    cam = _cam(W=64, H=48)              # 8 x 8 tiles: 8 tiles across, 6 down
+    # box x in [17.5, 40.2) -> tiles x 2..5 (17.5/8 = 2.19, 40.2/8 = 5.03); y in [3, 20) -> 0..2
+    lo = torch.tensor([[17.5, 3.0], [-5.0, 40.1]], dtype=torch.float64)
+    hi = torch.tensor([[40.2, 20.0], [7.9, 47.0]], dtype=torch.float64)
+    # second box: x in [-5, 7.9) -> tile 0 only; y in [40.1, 47) -> tile 5
+    proj = SimpleNamespace(lo=lo, hi=hi, kind="camera")
+    pix = np.array([[16, 0], [17, 3], [40, 23], [47, 23], [48, 0], [20, 24], [0, 40], [7, 47],
+                    [8, 47], [0, 39]])
+    tiles = (pix[:, 1] // 8) * 8 + pix[:, 0] // 8
+    m = rd._tile_mask(proj, cam, np.array([0, 1]), tiles).numpy()
+    want0 = [True, True, True, True, False, False, False, False, False, False]
+    want1 = [False, False, False, False, False, False, True, True, False, False]
+    assert m[:, 0].tolist() == want0
+    assert m[:, 1].tolist() == want1
+    # lidar: 5 azimuth tiles of 2 pi / 5 rad, elevation boundaries (-0.2, 0, 0.2)
+    lid = SimpleNamespace(n_az_tiles=5, tile_az=4, az_res=2 * math.pi / 20,
+                          elev_bounds=np.array([-0.2, 0.0, 0.2]))
+    w = 2 * math.pi / 5
+    # box A: azimuth [-0.3, 0.5) wraps: floor(-0.3 / w) = -1 -> tile 4, floor(0.5 / w) + 1 = 1
+    #   -> tiles {4, 0}; elevation [-0.05, 0.05) -> both rows.  Tiles {4, 0, 9, 5}.
+    # box B: azimuth [2w + 0.1, 2w + 0.2), elevation [0.01, 0.02) -> tile 2 + 5 * 1 = 7.
+    # box C: azimuth [1.0, 1.0 + 2 pi) spans every column; elevation [-0.3, -0.1) -> row 0.
+    lo = torch.tensor([[-0.3, -0.05], [2 * w + 0.1, 0.01], [1.0, -0.3]], dtype=torch.float64)
+    hi = torch.tensor([[0.5, 0.05], [2 * w + 0.2, 0.02], [1.0 + 2 * math.pi, -0.1]], dtype=torch.float64)
+    proj = SimpleNamespace(lo=lo, hi=hi, kind="lidar")
+    tiles = np.arange(10)
+    m = rd._tile_mask(proj, lid, np.array([0, 1, 2]), tiles).numpy()
+    assert np.nonzero(m[:, 0])[0].tolist() == [0, 4, 5, 9]
+    assert np.nonzero(m[:, 1])[0].tolist() == [7]
+    assert np.nonzero(m[:, 2])[0].tolist() == [0, 1, 2, 3, 4]
+    # a ray outside every tile (tile -1) is never a candidate
+    assert not rd._tile_mask(proj, lid, np.array([0, 1, 2]), np.array([-1])).numpy().any()
