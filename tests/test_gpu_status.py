@@ -8,7 +8,7 @@ import torch
 
 from oracle import render as rd
 from scenes import synthetic as S
-from tests.gpu_helpers import gpu_outputs, rtol_check
+from tests.gpu_helpers import gpu_outputs, grad_mismatch, rtol_check
 
 pytestmark = pytest.mark.gpu
 
@@ -99,11 +99,15 @@ def test_nonfinite_gaussians_counted_and_harmless(kind):
     # the finite Gaussians render exactly as without the poisoned ones (same order, same sums)
     for key in ("F", "D", "A", "T", "last"):
         np.testing.assert_array_equal(clean[key], poisoned[key], err_msg=key)
+    # the finite Gaussians' gradients are those of the clean scene; their per-Gaussian sums over
+    # tiles are float atomics whose order follows the schedule, so two runs agree to the
+    # run-to-run bar of the adjoint (1e-4 relative per element, 1e-5 of the largest), not bit for bit
     n = g.n
     for name in ("means", "log_scales", "quats", "opacities", "velocities", "features"):
         a = getattr(grads[0], name).cpu().numpy()
         p = getattr(grads[1], name).cpu().numpy()
-        np.testing.assert_array_equal(p[:n], a, err_msg=name)
+        bad = grad_mismatch(p[:n], a, rtol=1e-4, afloor=1e-5)
+        assert not bad.any(), (name, int(bad.sum()))
         assert (p[n:] == 0).all(), name                      # culled: no gradient at all
 
 
