@@ -447,6 +447,21 @@ int splat_compose_bwd(int64_t n, const float* means, const float* quats, const i
                       const float* d_vel_w, float* d_means, float* d_quats, float* d_velocities,
                       const SplatActorGrads* d_actors, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): splat_compose_bwd with the per-actor accumulators in a
+ * library-owned device array instead of a caller workspace.  The array holds
+ * SPLAT_COMPOSE_NOALLOC_MAX_ACTORS actors (24 floats each, 1.5 MiB); each GPU the call runs on
+ * keeps its own copy until the process ends.  actors->n above the maximum: SPLAT_ERR_CAPACITY,
+ * nothing launched.  Arguments, outputs and the other error codes are those of
+ * splat_compose_bwd.  Allocates nothing.  Every call on one GPU shares that GPU's array: the call
+ * clears what it uses (a fill kernel, stream-ordered), and calls that overlap on one GPU (other
+ * streams or threads) race and give wrong actor gradients. */
+#define SPLAT_COMPOSE_NOALLOC_MAX_ACTORS 16384
+int splat_compose_bwd_noalloc(int64_t n, const float* means, const float* quats, const int32_t* actor_id,
+                              const SplatActors* actors, const float* d_means_w, const float* d_quats_w,
+                              const float* d_vel_w, float* d_means, float* d_quats, float* d_velocities,
+                              const SplatActorGrads* d_actors, void* stream);
+
 /* ---- lidar points to rasterisation rays (App. A, "Lidar points to rasterization points") ----
  * A sweep's n points arrive with the ego motion compensated: world coordinates as if the whole
  * sweep were captured at its reference time (the middle of the sweep), with each point's capture

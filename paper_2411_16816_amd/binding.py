@@ -63,6 +63,7 @@ def _declare(lib):
         "splat_compose": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "splat_compose_workspace_bytes": (C.c_size_t, [i32]),
         "splat_compose_bwd": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+        "splat_compose_bwd_noalloc": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "splat_lidar_points_to_rays": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "splat_mcmc_regularizer": (C.c_int, [vp, C.c_float, C.c_float, vp, vp, vp]),
         "splat_lidar_decode": (C.c_int, [i64, vp, vp, vp, vp, vp, vp, vp]),
@@ -597,6 +598,26 @@ def compose_bwd(means, quats, actor_id, actors: ActorTensors, d_means_w, d_quats
                                 _ptr(d_quats_w), _ptr(d_vel_w), _ptr(d_means), _ptr(d_quats), _ptr(d_velocities),
                                 C.byref(G), _ptr(ws), ws.numel(), _stream(stream)), "splat_compose_bwd")
     return ws
+
+
+COMPOSE_NOALLOC_MAX_ACTORS = 16384   # SPLAT_COMPOSE_NOALLOC_MAX_ACTORS
+
+
+def compose_bwd_noalloc(means, quats, actor_id, actors: ActorTensors, d_means_w, d_quats_w, d_vel_w, d_means,
+                        d_quats, d_velocities=None, d_actors: Optional[dict] = None, stream=None):
+    """compose_bwd through the entry point that allocates nothing: the per-actor accumulators
+    live in the library's own per-GPU array (at most COMPOSE_NOALLOC_MAX_ACTORS actors).  Calls
+    that overlap on one GPU race."""
+    lib = load()
+    n = int(means.shape[0])
+    G = st.SplatActorGrads()
+    for f in ACTOR_GRAD_FIELDS:
+        setattr(G, f, _ptr((d_actors or {}).get(f)))
+    A = actors.struct()
+    check(lib.splat_compose_bwd_noalloc(n, _ptr(means), _ptr(quats), _ptr(actor_id), C.byref(A), _ptr(d_means_w),
+                                        _ptr(d_quats_w), _ptr(d_vel_w), _ptr(d_means), _ptr(d_quats),
+                                        _ptr(d_velocities), C.byref(G), _stream(stream)),
+          "splat_compose_bwd_noalloc")
 
 
 class ComposeFn(torch.autograd.Function):

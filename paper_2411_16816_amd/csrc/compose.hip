@@ -13,6 +13,8 @@
 // rotation quaternion, linear and angular velocity: 22 floats) over each wavefront's lanes of
 // one actor with the reduce-scatter of wave_ops.hpp, one global atomic per value and actor per
 // wavefront; a per-actor pass then chains them to the offsets.
+#include <mutex>
+
 #include "kernels.hpp"
 #include "wave_ops.hpp"
 
@@ -244,6 +246,61 @@ static bool actors_ok(const SplatActors* A) {
   return A && A->n >= 0 && (A->n == 0 || (A->rot && A->trans));
 }
 
+static int compose_bwd_check(int64_t n, const float* means, const float* quats, const int32_t* actor_id,
+                             const SplatActors* actors, const float* d_means_w, const float* d_quats_w,
+                             const float* d_vel_w, const float* d_means, const float* d_quats,
+                             const SplatActorGrads* d_actors) {
+  if (n < 0 || !actors_ok(actors) || !d_actors) return SPLAT_ERR_INVALID_ARG;
+  if (n == 0) return SPLAT_OK;
+  if (!means || !quats || !actor_id || !d_means_w || !d_quats_w || !d_vel_w || !d_means || !d_quats)
+    return SPLAT_ERR_INVALID_ARG;
+  if ((((uintptr_t)quats) | ((uintptr_t)d_quats_w) | ((uintptr_t)d_quats)) & 15) return SPLAT_ERR_INVALID_ARG;
+  return SPLAT_OK;
+}
+
+// The adjoint's launches with the per-actor accumulators in `acc` (actors->n x kActorAcc floats,
+// cleared here by a fill kernel so that the sequence stays capturable).
+static int compose_bwd_launch(int64_t n, const float* means, const float* quats, const int32_t* actor_id,
+                              const SplatActors* actors, const float* d_means_w, const float* d_quats_w,
+                              const float* d_vel_w, float* d_means, float* d_quats, float* d_velocities,
+                              const SplatActorGrads* d_actors, float* acc, hipStream_t s) {
+  if (actors->n > 0 && launch_fill_f32(acc, (int64_t)actors->n * kActorAcc, 0.f, s) != hipSuccess)
+    return SPLAT_ERR_DEVICE;
+  int64_t blocks = div_up(n, 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_compose_bwd, dim3((unsigned)blocks), dim3(256), 0, s, n, means, quats, actor_id, *actors,
+                     d_means_w, d_quats_w, d_vel_w, d_means, d_quats, d_velocities, acc);
+  if (actors->n > 0)
+    hipLaunchKernelGGL(k_actor_finalize, dim3((unsigned)div_up(actors->n, 64)), dim3(64), 0, s, *actors,
+                       (const float*)acc, *d_actors);
+  return hipGetLastError() == hipSuccess ? SPLAT_OK : SPLAT_ERR_DEVICE;
+}
+
+// Library-owned accumulators of splat_compose_bwd_noalloc: SPLAT_COMPOSE_NOALLOC_MAX_ACTORS
+// actors of kActorAcc floats.  Each GPU holds its own copy at its own address for the life of
+// the process.  In host code `scratch` names a host-side stand-in, never the device memory: the
+// device address comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address is handed to kernels.
+static __device__ __align__(256) float scratch[(size_t)SPLAT_COMPOSE_NOALLOC_MAX_ACTORS * kActorAcc];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mutex;
+static float* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's copy of `scratch` (looked up on the first call there).
+static bool scratch_address(float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) return false;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return false;
+    g_scratch_ptr[dev] = (float*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return true;
+}
+
 extern "C" {
 
 int splat_compose(int64_t n, const float* means, const float* quats, const float* velocities, const int32_t* actor_id,
@@ -265,24 +322,26 @@ int splat_compose_bwd(int64_t n, const float* means, const float* quats, const i
                       const SplatActors* actors, const float* d_means_w, const float* d_quats_w, const float* d_vel_w,
                       float* d_means, float* d_quats, float* d_velocities, const SplatActorGrads* d_actors, void* ws,
                       size_t ws_bytes, void* stream) {
-  if (n < 0 || !actors_ok(actors) || !d_actors) return SPLAT_ERR_INVALID_ARG;
-  if (n == 0) return SPLAT_OK;
-  if (!means || !quats || !actor_id || !d_means_w || !d_quats_w || !d_vel_w || !d_means || !d_quats)
-    return SPLAT_ERR_INVALID_ARG;
-  if ((((uintptr_t)quats) | ((uintptr_t)d_quats_w) | ((uintptr_t)d_quats)) & 15) return SPLAT_ERR_INVALID_ARG;
+  const int rc = compose_bwd_check(n, means, quats, actor_id, actors, d_means_w, d_quats_w, d_vel_w, d_means, d_quats,
+                                   d_actors);
+  if (rc != SPLAT_OK || n == 0) return rc;
   if (!ws || ws_bytes < splat_compose_workspace_bytes(actors->n)) return SPLAT_ERR_CAPACITY;
-  hipStream_t s = (hipStream_t)stream;
-  float* acc = (float*)ws;
-  if (actors->n > 0 && launch_fill_f32(acc, (int64_t)actors->n * kActorAcc, 0.f, s) != hipSuccess)
-    return SPLAT_ERR_DEVICE;
-  int64_t blocks = div_up(n, 256);
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_compose_bwd, dim3((unsigned)blocks), dim3(256), 0, s, n, means, quats, actor_id, *actors,
-                     d_means_w, d_quats_w, d_vel_w, d_means, d_quats, d_velocities, acc);
-  if (actors->n > 0)
-    hipLaunchKernelGGL(k_actor_finalize, dim3((unsigned)div_up(actors->n, 64)), dim3(64), 0, s, *actors,
-                       (const float*)acc, *d_actors);
-  return hipGetLastError() == hipSuccess ? SPLAT_OK : SPLAT_ERR_DEVICE;
+  return compose_bwd_launch(n, means, quats, actor_id, actors, d_means_w, d_quats_w, d_vel_w, d_means, d_quats,
+                            d_velocities, d_actors, (float*)ws, (hipStream_t)stream);
+}
+
+int splat_compose_bwd_noalloc(int64_t n, const float* means, const float* quats, const int32_t* actor_id,
+                              const SplatActors* actors, const float* d_means_w, const float* d_quats_w,
+                              const float* d_vel_w, float* d_means, float* d_quats, float* d_velocities,
+                              const SplatActorGrads* d_actors, void* stream) {
+  const int rc = compose_bwd_check(n, means, quats, actor_id, actors, d_means_w, d_quats_w, d_vel_w, d_means, d_quats,
+                                   d_actors);
+  if (rc != SPLAT_OK || n == 0) return rc;
+  if (actors->n > SPLAT_COMPOSE_NOALLOC_MAX_ACTORS) return SPLAT_ERR_CAPACITY;
+  float* acc = nullptr;
+  if (!scratch_address(&acc)) return SPLAT_ERR_DEVICE;
+  return compose_bwd_launch(n, means, quats, actor_id, actors, d_means_w, d_quats_w, d_vel_w, d_means, d_quats,
+                            d_velocities, d_actors, acc, (hipStream_t)stream);
 }
 
 }  // extern "C"
