@@ -60,7 +60,7 @@ extern "C" {
 typedef struct SplatStatus {
   unsigned long long n_isect;     /* intersections (tile, Gaussian) of the last bin/sort      */
   unsigned long long k_cap;       /* capacity the last bin/sort was given                      */
-  unsigned int overflow;          /* non-zero if n_isect exceeded k_cap (lists truncated)      */
+  unsigned int overflow;          /* non-zero if n_isect exceeded k_cap (lists left empty)     */
   unsigned int n_nonfinite;       /* (Gaussian, sensor) projections culled because of non-finite
                                      values: a non-finite sensor-frame mean, or a non-finite
                                      projected mean, velocity, conic, o_eff, box or depth of a
@@ -179,12 +179,11 @@ typedef struct SplatTileLists {
   int32_t* gauss;         /* [k_cap] Gaussian ids, grouped by tile, by (depth, id) inside      */
   int32_t* tile_range;    /* [n_tiles, 2] [start, end) into gauss                             */
   int64_t* entry_base;    /* [count * N] written by bin_sort for records with n_tiles > 0:
-                             the emission position of the record's first (tile, Gaussian) entry.
-                             Entries are emitted record by record in depth order, each record's
-                             tiles in the row-major order of its rectangle, so record r owns the
-                             positions [entry_base[r], entry_base[r] + n_tiles[r]); positions at
-                             or beyond k_cap were dropped (overflow).  The adjoint keeps one
-                             gradient row per position in its workspace.                      */
+                             the number of the record's first (tile, Gaussian) entry.  Entries
+                             are numbered record by record in record order, each record's tiles
+                             in the row-major order of its rectangle, so record r owns the
+                             numbers [entry_base[r], entry_base[r] + n_tiles[r]).  The adjoint
+                             keeps one gradient row per entry number in its workspace.         */
   /* lidar only (NULL for camera calls): */
   int32_t* ray_order;     /* [n_rays] local ray ids grouped by tile (invalid rays last)         */
   int32_t* ray_range;     /* [n_tiles + 1, 2] [start, end) into ray_order; entry n_tiles =
@@ -275,12 +274,14 @@ int splat_project_lidar(const SplatGaussians* g, const SplatRig* rig, int32_t fi
                         const SplatProjected* out, SplatStatus* status, void* stream);
 
 /* ---- a3 / a4: tile binning + depth sort (Sec. 3.2; Sec. 3.3 "Tiling and sorting"; App. A).
- * Orders records by depth (stable, so equal depths keep Gaussian-id order), emits one
- * (tile, Gaussian) pair per touched tile, stably sorts the pairs by tile and writes per-tile
- * ranges.  The lidar variant also bins the supplied rays into their tiles (a ray is a box of
- * zero extent, App. A) and cuts every tile's rays into work items of <= 256 rays.  More than
- * k_cap pairs: the lists are truncated (memory-safe), status->overflow is set and
- * status->n_isect holds the needed capacity. */
+ * Orders records by depth (stable, so equal depths keep Gaussian-id order) and writes, for
+ * every tile, the ids of the Gaussians whose rectangle contains it in that order (the order
+ * of a stable (tile | depth) key sort) with per-tile [start, end) ranges into gauss.  The
+ * lists of different tiles are laid out in an order of the library's choosing (tile_range
+ * says where each is).  The lidar variant also bins the supplied rays into their tiles (a ray
+ * is a box of zero extent, App. A) and cuts every tile's rays into work items of <= 256 rays.
+ * More than k_cap (tile, Gaussian) pairs: every list is left empty (memory-safe),
+ * status->overflow is set and status->n_isect holds the needed capacity. */
 int splat_bin_sort_camera(const SplatRig* rig, int32_t first, int32_t count, int64_t n_gaussians,
                           const SplatProjected* proj, const SplatTileLists* lists, void* ws,
                           size_t ws_bytes, SplatStatus* status, void* stream);
@@ -322,7 +323,7 @@ int splat_rasterize_bwd(const SplatGaussians* g, const SplatRig* rig, int32_t fi
 /* ---- a7: rasterisation backward + projection adjoint.  Walks each ray's list back to front
  * from `last`, recovering T_i = T_{i+1} / (1 - alpha_i) from the saved T_final.  A work item
  * sums each Gaussian's gradient over its rays (wavefront, then workgroup) and stores it as one
- * row per (tile, Gaussian) entry at the entry's emission position (see entry_base); work items
+ * row per (tile, Gaussian) entry at the entry's number (see entry_base); work items
  * of a lidar tile with more than SPLAT_RAYS_PER_ITEM rays share the tile and add atomically
  * instead.  Each record's rows are then summed in a fixed order and chained to means,
  * log-scales, quaternions, opacities, velocities and features.  Needs the lists written by

@@ -26,7 +26,7 @@ struct SplatRig {
 // reads from the device table at run time.
 static bool same_layout(const DevSensor& a, const DevSensor& b) {
   return a.kind == b.kind && a.n_tiles == b.n_tiles && a.n_rays == b.n_rays && a.n_ch == b.n_ch &&
-         a.feat_off == b.feat_off;
+         a.feat_off == b.feat_off && a.st_x == b.st_x && a.st_y == b.st_y;
 }
 
 // one thread: the device's constant-rate wall clock at the point the stream reaches the launch
@@ -129,7 +129,10 @@ int splat_rig_set(SplatRig* r, const SplatCamera* cams, const SplatLidar* lidars
   memset(&L, 0, sizeof(L));
   L.n_sensors = n;
   L.n_cameras = r->n_cam;
+  int64_t st_base = 0;
   for (int i = 0; i < n; ++i) {
+    tab[i].st_base = st_base;
+    st_base += (int64_t)tab[i].st_x * tab[i].st_y;
     tab[i].tile_base = L.tile_base[i];
     tab[i].ray_base = L.ray_base[i];
     tab[i].feat_base = L.feat_base[i];
@@ -172,6 +175,7 @@ static int make_view(const SplatRig* r, int32_t first, int32_t count, int kind, 
   v.count = count;
   v.n_gauss = n_gauss;
   v.n_tiles = 0;
+  v.n_supertiles = 0;
   v.n_rays = 0;
   v.c_max = 0;
   v.has_lidar = false;
@@ -188,6 +192,7 @@ static int make_view(const SplatRig* r, int32_t first, int32_t count, int kind, 
     }
     v.ray_cap = v.ray_cap || (d.kind == kLidar && d.ray_prio != nullptr);
     v.n_tiles += d.n_tiles;
+    v.n_supertiles += (int64_t)d.st_x * d.st_y;
     v.n_rays += d.n_rays;
     v.c_max = d.n_ch > v.c_max ? d.n_ch : v.c_max;
   }

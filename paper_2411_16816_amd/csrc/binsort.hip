@@ -2,13 +2,21 @@
 // "Projection, tiling, and sorting"; Sec. 3.3 "Tiling and sorting"; App. A).
 //
 // Pipeline of one call (all on the stream, no host synchronisation):
-//   1. the visible records are compacted and stably sorted by a 40-bit key of their float64
-//      depth, so equal keys keep record (= Gaussian id) order;
-//   2. an exclusive scan of n_tiles in that order gives every record its slot range;
-//   3. every record emits (local tile id, Gaussian id) pairs into its slots;
-//   4. a stable LSD radix sort on the tile id groups the pairs by tile; inside a tile they stay in
-//      (depth, id) order, which is the ordering the paper obtains from its (tile | depth) keys;
-//   5. per-tile [start, end) ranges;
+//   1. one scan over the records in record order counts the visible records and their
+//      (tile, Gaussian) entries, gives each visible record its entry numbers (the adjoint's
+//      gradient rows) and compacts the visible records with a 40-bit key of their float64 depth;
+//   2. the visible records are stably sorted by that key, so equal keys keep record
+//      (= Gaussian id) order;
+//   3. tiles are grouped into supertiles of 8 x 8 tiles; a scan in depth order gives every
+//      record the place of its (supertile, record) entries, one per supertile its rectangle
+//      meets, and they are written in depth order;
+//   4. a stable radix sort by supertile groups those entries, each supertile's in depth order;
+//   5. each supertile's entries are cut into items of at most 256; per item, the entries
+//      meeting each of the supertile's 64 tiles are counted (wavefront ballots), one scan of the
+//      counts gives every tile its list range and every item its first position in each list,
+//      and the items write the Gaussian ids straight into the lists, ranked by ballot prefix.
+//      Every list holds its tile's Gaussians in (depth, id) order, the ordering the paper gets
+//      from sorting (tile | depth) keys, while only the compact supertile entries are sorted;
 //   6. lidar: rays are binned into their tiles (a ray is a box of zero extent, App. A), invalid
 //      rays go to an extra bin, and every tile's rays are cut into work items of <= 256 rays.
 //
@@ -55,6 +63,22 @@ __device__ __forceinline__ int64_t shfl_up_i64(int64_t v, int d) {
 __device__ __forceinline__ uint32_t shfl_up_t(uint32_t v, int d) { return (uint32_t)__shfl_up((int)v, d, 64); }
 __device__ __forceinline__ int64_t shfl_up_t(int64_t v, int d) { return shfl_up_i64(v, d); }
 
+// Two int64 counters scanned together (trivially constructible, so it can live in LDS).
+struct P64 {
+  int64_t a, b;
+  P64() = default;
+  __device__ P64(int v) : a(v), b(v) {}
+  __device__ P64(int64_t x, int64_t y) : a(x), b(y) {}
+  __device__ P64& operator+=(const P64& o) {
+    a += o.a;
+    b += o.b;
+    return *this;
+  }
+};
+__device__ __forceinline__ P64 operator+(P64 x, const P64& y) { return x += y; }
+__device__ __forceinline__ P64 operator-(P64 x, const P64& y) { return P64(x.a - y.a, x.b - y.b); }
+__device__ __forceinline__ P64 shfl_up_t(P64 v, int d) { return P64(shfl_up_i64(v.a, d), shfl_up_i64(v.b, d)); }
+
 // exclusive scan across a 256-thread block; `tmp` holds 4 entries
 template <typename T>
 __device__ T block_exclusive_scan(T v, T* tmp, T& total) {
@@ -91,17 +115,42 @@ struct LoadI64 {
   __device__ int64_t operator()(int64_t i) const { return p[i]; }
 };
 
+// Elements scanned: the capacity n, or fewer when the count is only known on the device
+// (n_dev non-null: min(n, *n_dev)).  Blocks wholly past that count do nothing, except that the
+// block holding the last element (block 0 when there is none) closes the scan.
+__device__ __forceinline__ int64_t scan_count(const int64_t* n_dev, int64_t n) {
+  if (!n_dev) return n;
+  const int64_t m = *n_dev;
+  return m < 0 ? 0 : (m < n ? m : n);
+}
+// Elements per thread and per block of a scan over T: 16-byte elements take half as many, so
+// that a block's LDS tile stays at 34 KB (four blocks per compute unit).
+template <typename T>
+constexpr int scan_items() { return sizeof(T) > 8 ? kScanItems / 2 : kScanItems; }
+template <typename T>
+constexpr int scan_tile() { return kScanThreads * scan_items<T>(); }
+
+template <typename T>
+__device__ __forceinline__ int64_t scan_last_block(int64_t n_eff) { return n_eff > 0 ? (n_eff - 1) / scan_tile<T>() : 0; }
+
 template <typename T, typename Load>
-__global__ __launch_bounds__(256) void k_scan_reduce(Load ld, int64_t n, T* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_scan_reduce(Load ld, int64_t n, const int64_t* n_dev, T* __restrict__ part) {
   __shared__ T tmp[4];
-  int64_t base = (int64_t)blockIdx.x * kScanTile;   // < n: the grid has div_up(n, kScanTile) blocks
+  const int64_t n_eff = scan_count(n_dev, n);
+  constexpr int kItems = scan_items<T>();
+  const int64_t base = (int64_t)blockIdx.x * scan_tile<T>();   // < n: the grid has div_up(n, tile) blocks
+  if ((int64_t)blockIdx.x > scan_last_block<T>(n_eff)) {      // uniform: contributes nothing
+    if (threadIdx.x == 0) part[blockIdx.x] = (T)0;
+    return;
+  }
+  const int64_t hi = n_eff > 0 ? n_eff - 1 : 0;
   T acc = 0;
-  // indices clamped into [0, n): every load is issued unconditionally, back to back
+  // indices clamped into [0, n_eff): every load is issued unconditionally, back to back
 #pragma unroll 4
-  for (int r = 0; r < kScanItems; ++r) {
+  for (int r = 0; r < kItems; ++r) {
     const int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
-    const T x = ld(i < n ? i : n - 1);
-    acc += i < n ? x : (T)0;
+    const T x = ld(i < hi ? i : hi);
+    acc += i < n_eff ? x : (T)0;
   }
   T total;
   block_exclusive_scan<T>(acc, tmp, total);
@@ -128,24 +177,39 @@ __global__ __launch_bounds__(256) void k_scan_partials(T* __restrict__ part, int
   if (threadIdx.x == 0) part[nb] = carry;
 }
 
-// Block b: exclusive scan of its tile, offset by the total of the blocks before it: with
-// `fused`, the sum of the block totals part[0..b) (read by the block itself; the last block
-// writes the grand total to part[nb]), otherwise part[b] as scanned by k_scan_partials.
-// no per-element work besides the scan
+// Per-element work of a scan, in two phases so that the loads of several elements are issued
+// before any of their stores: In load(i, value) reads what element i needs, then
+// operator()(i, prefix, value, in) writes; finish(total) runs once with the grand total.
 struct NoVisit {
+  struct In {};
   template <typename T>
-  __device__ void operator()(int64_t, T, T) const {}
+  __device__ In load(int64_t, T) const { return In{}; }
+  template <typename T>
+  __device__ void operator()(int64_t, T, T, In) const {}
+  template <typename T>
+  __device__ void finish(T) const {}
 };
 
+// Block b: exclusive scan of its tile, offset by the total of the blocks before it: with
+// `fused`, the sum of the block totals part[0..b) (read by the block itself; the closing block
+// writes the grand total to part[nb]), otherwise part[b] as scanned by k_scan_partials.  Every
+// element i is handed to the visitor with its prefix and its value; the closing block's first
+// thread hands it the grand total (vis.finish).  `out` may be null (visitor only).
 template <typename T, typename Load, typename Visit>
-__global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, T* __restrict__ part, int64_t nb, bool fused,
-                                                   T* __restrict__ out, Visit vis) {
+__global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, const int64_t* n_dev, T* __restrict__ part,
+                                                   int64_t nb, bool fused, T* __restrict__ out, Visit vis) {
   // element li of the tile lives at pad(li) = li + li / 16: a thread's 16 consecutive
   // elements then start 17 apart, which spreads the per-thread pass over the LDS banks
-  __shared__ T tile[kScanTile + kScanTile / kScanItems];
+  constexpr int kItems = scan_items<T>();
+  constexpr int kTile = scan_tile<T>();
+  __shared__ T tile[kTile + kTile / kItems];
   __shared__ T tmp[4];
-  auto pad = [](int li) { return li + (li >> 4); };
-  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  auto pad = [](int li) { return li + li / kItems; };
+  const int64_t n_eff = scan_count(n_dev, n);
+  const int64_t last = scan_last_block<T>(n_eff);
+  if ((int64_t)blockIdx.x > last) return;   // uniform
+  const int64_t hi = n_eff > 0 ? n_eff - 1 : 0;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
   T before;
   if (fused) {
     T pb = 0;
@@ -155,53 +219,77 @@ __global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, T* __rest
     before = part[blockIdx.x];
   }
 #pragma unroll 4
-  for (int r = 0; r < kScanItems; ++r) {
+  for (int r = 0; r < kItems; ++r) {
     const int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
-    const T x = ld(i < n ? i : n - 1);
-    tile[pad(r * kScanThreads + threadIdx.x)] = i < n ? x : (T)0;
+    const T x = ld(i < hi ? i : hi);
+    tile[pad(r * kScanThreads + threadIdx.x)] = i < n_eff ? x : (T)0;
   }
   __syncthreads();
-  T loc[kScanItems];
+  T loc[kItems];
   T acc = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
+  for (int k = 0; k < kItems; ++k) {
     loc[k] = acc;
-    acc += tile[pad(threadIdx.x * kScanItems + k)];
+    acc += tile[pad(threadIdx.x * kItems + k)];
   }
   T total;
   T pre = block_exclusive_scan<T>(acc, tmp, total) + before;
-  if (fused && blockIdx.x == nb - 1 && threadIdx.x == 0) part[nb] = before + total;
+  if ((int64_t)blockIdx.x == last && threadIdx.x == 0) {
+    if (fused) part[nb] = before + total;
+    vis.finish(before + total);
+  }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) tile[pad(threadIdx.x * kScanItems + k)] = pre + loc[k];
+  for (int k = 0; k < kItems; ++k) tile[pad(threadIdx.x * kItems + k)] = pre + loc[k];
   __syncthreads();
   const T end = before + total;   // exclusive prefix after the block
-#pragma unroll 4
-  for (int r = 0; r < kScanItems; ++r) {
-    const int li = r * kScanThreads + threadIdx.x;
-    const int64_t i = base + li;
-    if (i < n) {
-      const T p = tile[pad(li)];
-      out[i] = p;
-      vis(i, p, (li + 1 < kScanTile ? tile[pad(li + 1)] : end) - p);   // element i's value is the gap
+  constexpr int kBatch = 4;
+#pragma unroll
+  for (int r0 = 0; r0 < kItems; r0 += kBatch) {
+    T p[kBatch], gap[kBatch];
+    typename Visit::In in[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int li = (r0 + u) * kScanThreads + threadIdx.x;
+      const int64_t i = base + li;
+      p[u] = tile[pad(li)];
+      gap[u] = (li + 1 < kTile ? tile[pad(li + 1)] : end) - p[u];   // element i's value
+      if (i < n_eff) in[u] = vis.load(i, gap[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int64_t i = base + (r0 + u) * kScanThreads + threadIdx.x;
+      if (i < n_eff) {
+        if (out) out[i] = p[u];
+        vis(i, p[u], gap[u], in[u]);
+      }
     }
   }
 }
 
-// exclusive scan of n elements into out[0..n) (out may alias the loaded array: each block
-// reads its tile before writing it); part[nb] receives the total
+// the scan of no elements: total 0
+template <typename T, typename Visit>
+__global__ void k_scan_empty(T* part, Visit vis) {
+  part[0] = (T)0;
+  vis.finish((T)0);
+}
+
+// exclusive scan of n elements (fewer when n_dev is given, see scan_count) into out[0..n)
+// (out may alias the loaded array: each block reads its tile before writing it; out may be
+// null); part[nb] receives the total
 template <typename T, typename Load, typename Visit = NoVisit>
-hipError_t device_scan(Load ld, int64_t n, T* out, T* part, hipStream_t s, Visit vis = Visit()) {
-  int64_t nb = div_up(n, kScanTile);
+hipError_t device_scan(Load ld, int64_t n, T* out, T* part, hipStream_t s, Visit vis = Visit(),
+                       const int64_t* n_dev = nullptr) {
+  int64_t nb = div_up(n, scan_tile<T>());
   if (nb == 0) {
-    hipLaunchKernelGGL((k_fill<T>), dim3(1), dim3(64), 0, s, part, (int64_t)1, (T)0);
+    hipLaunchKernelGGL((k_scan_empty<T, Visit>), dim3(1), dim3(1), 0, s, part, vis);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL((k_scan_reduce<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, part);
+  hipLaunchKernelGGL((k_scan_reduce<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, n_dev, part);
   const bool fused = nb <= kScanFusedBlocks;
   if (!fused) hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(256), 0, s, part, nb);
-  hipLaunchKernelGGL((k_scan_down<T, Load, Visit>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, part, nb,
-                     fused, out, vis);
+  hipLaunchKernelGGL((k_scan_down<T, Load, Visit>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, n_dev, part,
+                     nb, fused, out, vis);
   return hipGetLastError();
 }
 
@@ -228,31 +316,50 @@ __device__ __forceinline__ int64_t sort_count(const int64_t* n_ptr, int64_t n_ca
 }
 
 // Per-block digit counts of one 4096-key tile, counted with LDS atomics into one histogram per
-// wavefront (order does not matter for counting), written digit-major: hist[d * nb + block].
+// wavefront (order does not matter for counting), written block-major: hist[block * 256 + d].
+// Blocks past the key count write nothing (nothing reads their counts).
 template <typename K>
 __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap,
-                                                    int shift, int bits, uint32_t* __restrict__ hist, int64_t nb) {
+                                                    int shift, int bits, uint32_t* __restrict__ hist) {
   __shared__ uint32_t cnt[4][kRadixBins];
   const int tid = threadIdx.x, wid = tid >> 6;
-  cnt[0][tid] = cnt[1][tid] = cnt[2][tid] = cnt[3][tid] = 0;
-  __syncthreads();
   const int64_t n = sort_count(n_ptr, n_cap);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  const uint32_t mask = (1u << bits) - 1u;
-  if (base < n) {
-    uint32_t d[kScanItems];
-#pragma unroll
-    for (int r = 0; r < kScanItems; ++r) {
-      const int64_t i = base + (int64_t)r * kScanThreads + tid;
-      const uint32_t x = (uint32_t)(keys[i < n ? i : n - 1] >> shift) & mask;   // unconditional load
-      d[r] = i < n ? x : 0xFFFFFFFFu;
-    }
-#pragma unroll
-    for (int r = 0; r < kScanItems; ++r)
-      if (d[r] != 0xFFFFFFFFu) atomicAdd(&cnt[wid][d[r]], 1u);
-  }
+  if (base >= n) return;   // uniform
+  cnt[0][tid] = cnt[1][tid] = cnt[2][tid] = cnt[3][tid] = 0;
   __syncthreads();
-  hist[(int64_t)tid * nb + blockIdx.x] = cnt[0][tid] + cnt[1][tid] + cnt[2][tid] + cnt[3][tid];
+  const uint32_t mask = (1u << bits) - 1u;
+  uint32_t d[kScanItems];
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const int64_t i = base + (int64_t)r * kScanThreads + tid;
+    const uint32_t x = (uint32_t)(keys[i < n ? i : n - 1] >> shift) & mask;   // unconditional load
+    d[r] = i < n ? x : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r)
+    if (d[r] != 0xFFFFFFFFu) atomicAdd(&cnt[wid][d[r]], 1u);
+  __syncthreads();
+  hist[(int64_t)blockIdx.x * kRadixBins + tid] = cnt[0][tid] + cnt[1][tid] + cnt[2][tid] + cnt[3][tid];
+}
+
+// One block per digit d: exclusive scan of the digit's counts over the blocks that hold keys
+// (in place), and the digit's total.
+__global__ __launch_bounds__(256) void k_radix_colscan(uint32_t* __restrict__ hist, const int64_t* n_ptr,
+                                                       int64_t n_cap, uint32_t* __restrict__ coltotal) {
+  __shared__ uint32_t tmp[4];
+  const int d = blockIdx.x;
+  const int64_t nb = (sort_count(n_ptr, n_cap) + kScanTile - 1) / kScanTile;
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+    const int64_t b = b0 + threadIdx.x;
+    const uint32_t x = b < nb ? hist[b * kRadixBins + d] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan<uint32_t>(x, tmp, total);
+    if (b < nb) hist[b * kRadixBins + d] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) coltotal[d] = carry;
 }
 
 // Stable scatter of one block tile (4096 keys).  Wavefront w owns the contiguous quarter
@@ -261,15 +368,17 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
 // count per digit (LDS, touched only by that wavefront) carries the rank across rounds.  One
 // block scan then turns (digit, wavefront) counts into offsets, keys are staged in LDS in digit
 // order and written out so that consecutive lanes write consecutive addresses of a digit's
-// output run (coalesced), at the block's global digit offsets from the scanned histogram.
-template <typename K>
-__global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                       K* __restrict__ kout, uint32_t* __restrict__ vout,
+// output run (coalesced), at the block's global digit offsets: the digit's start (exclusive
+// scan of the digit totals, done here) plus the earlier blocks' counts of the digit.
+template <typename K, typename V>
+__global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin, const V* __restrict__ vin,
+                                                       K* __restrict__ kout, V* __restrict__ vout,
                                                        const int64_t* n_ptr, int64_t n_cap, int shift, int bits,
-                                                       const uint32_t* __restrict__ hist, int64_t nb) {
+                                                       const uint32_t* __restrict__ hist,
+                                                       const uint32_t* __restrict__ coltotal) {
   constexpr int kPerWave = kScanTile / 4;
   __shared__ K s_k[kScanTile];
-  __shared__ uint32_t s_v[kScanTile];
+  __shared__ V s_v[kScanTile];
   __shared__ uint32_t gbase[kRadixBins];
   __shared__ uint32_t lcum[kRadixBins];
   __shared__ uint32_t wc[4][kRadixBins];   // per-wavefront running counts, then offsets
@@ -281,10 +390,15 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   const int cnt = (int)((n - base) < kScanTile ? (n - base) : kScanTile);
   const uint32_t mask = (1u << bits) - 1u;
   const uint64_t lt = lanemask_lt();
-  gbase[tid] = hist[(int64_t)tid * nb + blockIdx.x];
+  {
+    uint32_t dtot;
+    const uint32_t dstart = block_exclusive_scan<uint32_t>(coltotal[tid], tmp, dtot);
+    gbase[tid] = dstart + hist[(int64_t)blockIdx.x * kRadixBins + tid];
+  }
   wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
   K key[kScanItems];
-  uint32_t val[kScanItems], rank[kScanItems];
+  V val[kScanItems];
+  uint32_t rank[kScanItems];
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
     const int li = wid * kPerWave + r * 64 + lane;
@@ -350,12 +464,12 @@ static inline int radix_pass_bits(int total_bits) {
 
 // Sorts (k[cur], v[cur]) stably by key bits [lo_bit, lo_bit + total_bits).  On return `cur`
 // indexes the sorted keys; the sorted values are in v[cur], or in `final_vals` when it is
-// non-null.  n_ptr (device) gives the element count when non-null, capped by n_cap.
-// `first_hist_ready`: the caller already wrote the first pass's digit counts into `hist`.
-template <typename K>
-static hipError_t radix_sort(K* k[2], uint32_t* v[2], int& cur, const int64_t* n_ptr, int64_t n_cap, int lo_bit,
-                             int total_bits, uint32_t* hist, uint32_t* hist_part, uint32_t* final_vals, hipStream_t s,
-                             bool first_hist_ready = false) {
+// non-null.  n_ptr (device) gives the element count when non-null, capped by n_cap; only the
+// blocks that hold keys do work.  Three launches per pass: histograms, per-digit scans over
+// the blocks, scatter.
+template <typename K, typename V>
+static hipError_t radix_sort(K* k[2], V* v[2], int& cur, const int64_t* n_ptr, int64_t n_cap, int lo_bit,
+                             int total_bits, uint32_t* hist, uint32_t* coltotal, V* final_vals, hipStream_t s) {
   if (total_bits < 1) total_bits = 1;
   const int passes = (total_bits + kRadixBits - 1) / kRadixBits;
   const int per = radix_pass_bits(total_bits);   // bits spread evenly over the passes
@@ -364,14 +478,12 @@ static hipError_t radix_sort(K* k[2], uint32_t* v[2], int& cur, const int64_t* n
   for (int p = 0; p < passes; ++p) {
     const int shift = lo_bit + p * per;
     const int bits = (total_bits - p * per) < per ? (total_bits - p * per) : per;
-    if (!(p == 0 && first_hist_ready))
-      hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(256), 0, s, (const K*)k[cur], n_ptr, n_cap, shift,
-                         bits, hist, nb);
-    hipError_t e = device_scan<uint32_t>(LoadU32{hist}, (int64_t)kRadixBins * nb, hist, hist_part, s);
-    if (e != hipSuccess) return e;
-    uint32_t* vdst = (p == passes - 1 && final_vals) ? final_vals : v[1 - cur];
-    hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)nb), dim3(256), 0, s, (const K*)k[cur],
-                       (const uint32_t*)v[cur], k[1 - cur], vdst, n_ptr, n_cap, shift, bits, (const uint32_t*)hist, nb);
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(256), 0, s, (const K*)k[cur], n_ptr, n_cap, shift,
+                       bits, hist);
+    hipLaunchKernelGGL(k_radix_colscan, dim3(kRadixBins), dim3(256), 0, s, hist, n_ptr, n_cap, coltotal);
+    V* vdst = (p == passes - 1 && final_vals) ? final_vals : v[1 - cur];
+    hipLaunchKernelGGL((k_radix_scatter<K, V>), dim3((unsigned)nb), dim3(256), 0, s, (const K*)k[cur], (const V*)v[cur],
+                       k[1 - cur], vdst, n_ptr, n_cap, shift, bits, (const uint32_t*)hist, (const uint32_t*)coltotal);
     cur = 1 - cur;
   }
   return hipGetLastError();
@@ -396,12 +508,6 @@ __device__ __forceinline__ int64_t local_tile_base(const DevSensor* sens, int s)
   return sens[s].tile_base - sens[0].tile_base;
 }
 
-// compaction of the visible records with their float64 depth keys (upper 48 bits)
-struct LoadVisible {
-  const int32_t* n_tiles;
-  __device__ int64_t operator()(int64_t i) const { return n_tiles[i] > 0 ? 1 : 0; }
-};
-
 // 40-bit sort key of a positive float64 depth: 5 bits of binary exponent over [2^-16, 2^16)
 // and the top 35 mantissa bits (2^-35 relative resolution), monotone in the depth; depths
 // outside that range clamp to the first / last key (ties then keep Gaussian-id order).
@@ -414,24 +520,143 @@ __device__ __forceinline__ uint64_t depth_sort_key(unsigned long long bits) {
   return ((uint64_t)e << 35) | ((bits & 0xFFFFFFFFFFFFFull) >> 17);
 }
 
-// The record's tile count rides in the key's top 24 bits (the sort looks only at the low
-// kDepthKeyBits), so that the scan of the counts in depth order reads the sorted keys
-// contiguously instead of gathering by record.  A sensor has fewer than 2^24 tiles.
-__global__ void k_compact_visible(const int32_t* __restrict__ n_tiles, const unsigned long long* __restrict__ dkey,
-                                  const int64_t* __restrict__ pos, int64_t n_rec, uint64_t* __restrict__ keys,
-                                  uint32_t* __restrict__ vals) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_rec) return;
-  const int32_t nt = n_tiles[i];
-  if (nt <= 0) return;
-  int64_t p = pos[i];
-  keys[p] = ((uint64_t)nt << kDepthKeyBits) | depth_sort_key(dkey[i]);
-  vals[p] = (uint32_t)i;
+// Device scalars of one bin/sort call (workspace `scalars`).
+enum : int {
+  kScVisible = 0,    // visible records (n_tiles > 0)
+  kScEntries = 1,    // (tile, Gaussian) entries K, uncapped
+  kScCoarse = 2,     // (supertile, record) entries; 0 when K exceeds the capacity
+  kScItemsX = 3,     // elements of the per-item count array: 64 x items + 1
+  kScCount = 4
+};
+
+// sensor (index into the call's table) of record rec = s * N + g; exact for rec < 2^32
+__device__ __forceinline__ int record_sensor(int64_t rec, int64_t N, int count) {
+  if (count <= 1) return 0;
+  int s = (int)((float)rec * __builtin_amdgcn_rcpf((float)N));
+  s -= ((int64_t)s * N > rec) ? 1 : 0;
+  s += ((int64_t)(s + 1) * N <= rec) ? 1 : 0;
+  return s;
 }
 
-// tile count of the i-th visible record in depth order, from its sorted packed key (entries
-// past the visible count hold stale keys and count zero)
-struct LoadPackedTiles {
+// ---- supertiles --------------------------------------------------------------------------------
+// A sensor's tile grid (camera tiles_x x tiles_y; lidar M_phi x M_omega) is cut into supertiles
+// of kStSide x kStSide tiles, numbered row-major (st_x per row), after the supertiles of the
+// call's earlier sensors.  Tile (row, col) is tile f = (row % 8) * 8 + col % 8 of supertile
+// (row / 8, col / 8).
+__device__ __forceinline__ int grid_stride(const DevSensor& S) { return S.kind == kCamera ? S.tiles_x : S.m_az; }
+__device__ __forceinline__ int grid_rows(const DevSensor& S) { return S.kind == kCamera ? S.tiles_y : S.m_el; }
+
+// Supertiles a rectangle (x0, y0, w, h) meets: rows [r0, r0 + nr) and, in each, the columns
+// [c0, c0 + nc0) followed by [0, nc1) (the second run only for a lidar rectangle that wraps the
+// azimuth seam into supertile columns it does not already cover).
+struct StSpan {
+  int r0, nr, c0, nc0, nc1;
+};
+
+__device__ __forceinline__ StSpan st_span(const DevSensor& S, const int4 rc) {
+  StSpan p;
+  p.r0 = rc.y / kStSide;
+  p.nr = (rc.y + rc.w - 1) / kStSide - p.r0 + 1;
+  const int M = grid_stride(S);
+  if (S.kind == kCamera || rc.x + rc.z <= M) {
+    p.c0 = rc.x / kStSide;
+    p.nc0 = (rc.x + rc.z - 1) / kStSide - p.c0 + 1;
+    p.nc1 = 0;
+  } else {
+    const int a = rc.x / kStSide;                    // [a, st_x) then [0, e]
+    const int e = (rc.x + rc.z - 1 - M) / kStSide;
+    if (e >= a) {                                    // the two runs meet: every column
+      p.c0 = 0;
+      p.nc0 = S.st_x;
+      p.nc1 = 0;
+    } else {
+      p.c0 = a;
+      p.nc0 = S.st_x - a;
+      p.nc1 = e + 1;
+    }
+  }
+  return p;
+}
+
+// Tiles of supertile (sr, sc) inside rectangle rc, as the rows (bit r: tile row sr * 8 + r) and
+// the columns (bit c: tile column sc * 8 + c) it covers there; tile f = r * 8 + c is inside
+// exactly when both bits are set.
+__device__ __forceinline__ void st_rows_cols(const DevSensor& S, const int4 rc, int sr, int sc, uint32_t& rows,
+                                             uint32_t& cols) {
+  const int M = grid_stride(S);
+  cols = 0;
+#pragma unroll
+  for (int c = 0; c < kStSide; ++c) {
+    const int x = sc * kStSide + c;
+    int d = x - rc.x;
+    if (S.kind != kCamera && d < 0) d += M;   // lidar: columns wrap modulo M_phi
+    cols |= (x < M && d >= 0 && d < rc.z) ? (1u << c) : 0u;
+  }
+  const int lo = rc.y - sr * kStSide, hi = rc.y + rc.w - sr * kStSide;   // rows [lo, hi) of the supertile
+  const int a = lo < 0 ? 0 : lo, b = hi > kStSide ? kStSide : hi;
+  rows = b > a ? ((1u << b) - 1u) & ~((1u << a) - 1u) : 0u;
+}
+
+// Visitor of the record-order scan of (visible, tile count) pairs.  A visible record gets its
+// entry base (the record-order prefix of the tile counts: record r owns the adjoint slots
+// [entry_base, entry_base + n_tiles)) and, at its compacted position, its depth key with the
+// number of supertiles it meets in the top 24 bits (read back in depth order by the next scan).
+// The closing block stores the visible and entry counts and the status.
+struct VisibleVisit {
+  const DevSensor* sens;
+  int count;
+  int64_t N;
+  const int4* rect;
+  const unsigned long long* dkey;
+  int64_t* entry_base;
+  uint64_t* keys;
+  uint32_t* vals;
+  int64_t* scalars;
+  int64_t k_cap;
+  SplatStatus* st;
+  struct In {
+    int4 rc;
+    unsigned long long dk;
+  };
+  __device__ In load(int64_t i, P64 v) const {
+    In in;
+    if (v.a != 0) {
+      in.rc = rect[i];
+      in.dk = dkey[i];
+    }
+    return in;
+  }
+  __device__ void operator()(int64_t i, P64 p, P64 v, const In& in) const {
+    if (v.a == 0) return;
+    entry_base[i] = p.b;
+    const DevSensor& S = sens[record_sensor(i, N, count)];
+    const StSpan sp = st_span(S, in.rc);
+    const uint64_t n_st = (uint64_t)(sp.nr * (sp.nc0 + sp.nc1));
+    keys[p.a] = (n_st << kDepthKeyBits) | depth_sort_key(in.dk);
+    vals[p.a] = (uint32_t)i;
+  }
+  __device__ void finish(P64 total) const {
+    scalars[kScVisible] = total.a;
+    scalars[kScEntries] = total.b;
+    if (st) {
+      st->n_isect = (unsigned long long)total.b;
+      st->k_cap = (unsigned long long)k_cap;
+      if (total.b > k_cap) st->overflow = 1u;
+    }
+  }
+};
+
+struct LoadVisibleTiles {
+  const int32_t* n_tiles;
+  __device__ P64 operator()(int64_t i) const {
+    const int32_t nt = n_tiles[i];
+    return nt > 0 ? P64((int64_t)1, (int64_t)nt) : P64(0);
+  }
+};
+
+// supertile count of the i-th visible record in depth order, from its sorted packed key
+// (entries past the visible count hold stale keys and count zero)
+struct LoadPackedCount {
   const uint64_t* keys;
   const int64_t* n_vis;
   __device__ int64_t operator()(int64_t i) const {
@@ -440,177 +665,269 @@ struct LoadPackedTiles {
   }
 };
 
-__global__ void k_finalize_count(const int64_t* __restrict__ total, int64_t k_cap, int64_t* __restrict__ n_sort,
-                                 SplatStatus* st) {
-  int64_t K = *total;
-  *n_sort = K < k_cap ? K : k_cap;
-  if (st) {
-    st->n_isect = (unsigned long long)K;
-    st->k_cap = (unsigned long long)k_cap;
-    if (K > k_cap) st->overflow = 1u;
-  }
-}
-
-constexpr int kEmitTile = kScanTile;   // output slots per workgroup of the emit kernel = one radix tile
-constexpr int kEmitThreads = 512;
-constexpr int kEmitPer = kEmitTile / kEmitThreads;   // consecutive slots per thread
-constexpr int kEmitRecs = kEmitTile + 1;             // records that can meet one workgroup's slots
-static_assert(kEmitPer == 8, "k_emit stores a thread's slots as two 16-byte vectors");
-
-// q = floor(a / b) for 0 <= a < 2^24, b >= 1, from a float reciprocal with an exact correction.
-__device__ __forceinline__ int div_small(int a, int b) {
-  int q = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
-  q -= (q * b > a) ? 1 : 0;
-  q += ((q + 1) * b <= a) ? 1 : 0;
-  return q;
-}
-
-// Thread t emits the kEmitPer consecutive slots k0 + t kEmitPer + j.  Slot k belongs to the
-// visible record r (depth order) with offs[r] <= k < offs[r + 1]; the records that can own a
-// slot of the workgroup are bstart[b] .. bstart[b + 1] (at most kEmitRecs).  They are staged
-// first, all in parallel: every record's first slot relative to k0 and a descriptor
-//   {Gaussian id, key of the rectangle's first tile, width | wrap column << 16, row stride},
-// where the key of entry (row, col) of the rectangle is first + row * stride + col, minus the
-// stride once col reaches the wrap column (lidar azimuth wrap; cameras never wrap).  A thread
-// then finds its first slot's record by binary search and walks its slots through LDS only
-// (every visible record has >= 1 slot, so the walk advances at most one record per slot).
-// Keys and ids are stored straight from registers (each thread's slots are contiguous).  A
-// workgroup's slots are exactly one tile of the radix sort that follows, so it also writes that
-// tile's counts of the first pass's digit (key & digit_mask: hist[d * nb + block], zero
-// for blocks past the last slot).
-__global__ __launch_bounds__(kEmitThreads) void k_emit(const DevSensor* __restrict__ sens, int count, int64_t N,
-                                                       const int4* __restrict__ rect,
-                                                       const uint32_t* __restrict__ order,
-                                                       const int64_t* __restrict__ offs,
-                                                       const int64_t* __restrict__ n_vis,
-                                                       const int64_t* __restrict__ n_slots,
-                                                       const int64_t* __restrict__ bstart, uint32_t* __restrict__ keys,
-                                                       uint32_t* __restrict__ vals, uint32_t* __restrict__ hist,
-                                                       int64_t nb, uint32_t digit_mask) {
-  __shared__ uint4 s_desc[kEmitRecs];
-  __shared__ int16_t s_off[kEmitRecs + 1];   // first slot - k0, clamped to [0, kEmitTile + 1]
-  __shared__ uint32_t s_cnt[kRadixBins];
-  __shared__ int s_off0;                     // first slot - k0 of record 0 (<= 0), unclamped
-  const int tid = threadIdx.x;
-  const int64_t K = *n_slots;
-  const int64_t k0 = (int64_t)blockIdx.x * kEmitTile;
-  if (tid < kRadixBins) s_cnt[tid] = 0;
-  if (k0 >= K) {   // uniform
-    if (tid < kRadixBins) hist[(int64_t)tid * nb + blockIdx.x] = 0;
-    return;
-  }
-  const int64_t r0 = bstart[blockIdx.x];
-  const int64_t used = (K + kEmitTile - 1) / kEmitTile;   // workgroups with slots; bstart is set for each
-  const int64_t r_last = blockIdx.x + 1 < used ? bstart[blockIdx.x + 1] : *n_vis - 1;
-  const int nrec = (int)(r_last - r0 + 1 < kEmitRecs ? r_last - r0 + 1 : kEmitRecs);
-  // stage the records, three rounds per iteration with clamped (always valid) indices so that
-  // their loads are issued together
-  constexpr int kU = 3;
-  for (int i0 = 0; i0 < nrec; i0 += kU * kEmitThreads) {
-    int64_t rel[kU];
-    uint32_t rec[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int i = i0 + u * kEmitThreads + tid;
-      const int64_t r = r0 + (i < nrec ? i : nrec - 1);
-      rel[u] = offs[r] - k0;
-      rec[u] = order[r];
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int i = i0 + u * kEmitThreads + tid;
-      int s = 0;
-      if (count > 1) {
-        s = (int)((float)rec[u] * __builtin_amdgcn_rcpf((float)N));
-        s -= ((int64_t)s * N > (int64_t)rec[u]) ? 1 : 0;
-        s += ((int64_t)(s + 1) * N <= (int64_t)rec[u]) ? 1 : 0;
-      }
-      const DevSensor& S = sens[s];
-      const int4 rc = rect[rec[u]];
-      const bool cam = S.kind == kCamera;
-      const uint32_t stride = (uint32_t)(cam ? S.tiles_x : S.m_az);
-      const uint32_t first = (uint32_t)(S.tile_base - sens[0].tile_base) + (uint32_t)rc.y * stride + (uint32_t)rc.x;
-      const uint32_t wrap = (uint32_t)(cam ? rc.z : S.m_az - rc.x);
-      if (i < nrec) {
-        s_desc[i] = make_uint4(rec[u] - (uint32_t)s * (uint32_t)N, first, (uint32_t)rc.z | (wrap << 16), stride);
-        const int64_t v = rel[u] < 0 ? 0 : (rel[u] > kEmitTile + 1 ? kEmitTile + 1 : rel[u]);
-        s_off[i] = (int16_t)v;
-        if (i == 0) s_off0 = (int)rel[u];
-      }
-    }
-  }
-  if (tid == 0) s_off[nrec] = (int16_t)(kEmitTile + 1);
-  __syncthreads();
-  const int nk = (int)((K - k0) < kEmitTile ? (K - k0) : kEmitTile);
-  const int j0 = tid * kEmitPer;
-  uint32_t kk[kEmitPer], gg[kEmitPer];
-  if (j0 < nk) {
-    int lo = 0, hi = nrec - 1;   // last record with s_off[lo] <= j0 (s_off[0] = 0)
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= j0) lo = mid; else hi = mid - 1;
-    }
-    uint4 d = s_desc[lo];
-    int nxt = s_off[lo + 1];
-    int w = (int)(d.z & 0xFFFFu), wrap = (int)(d.z >> 16);
-    const int jj = j0 - (lo == 0 ? s_off0 : (int)s_off[lo]);
-    int row = div_small(jj, w), col = jj - row * w;
-#pragma unroll
-    for (int j = 0; j < kEmitPer; ++j) {
-      const int q = j0 + j;
-      if (q < nk && q >= nxt) {   // the next record starts here (it is staged: its first slot < nk)
-        ++lo;
-        d = s_desc[lo];
-        nxt = s_off[lo + 1];
-        w = (int)(d.z & 0xFFFFu);
-        wrap = (int)(d.z >> 16);
-        row = 0;
-        col = 0;
-      }
-      const uint32_t key = d.y + (uint32_t)row * d.w + (uint32_t)col - (col >= wrap ? d.w : 0u);
-      kk[j] = key;
-      gg[j] = d.x;
-      if (q < nk) atomicAdd(&s_cnt[key & digit_mask], 1u);
-      if (++col == w) {
-        col = 0;
-        ++row;
-      }
-    }
-    uint32_t* kp = keys + k0 + j0;
-    uint32_t* vp = vals + k0 + j0;
-    if (j0 + kEmitPer <= nk && ((((uintptr_t)kp) | ((uintptr_t)vp)) & 15) == 0) {
-      reinterpret_cast<uint4*>(kp)[0] = make_uint4(kk[0], kk[1], kk[2], kk[3]);
-      reinterpret_cast<uint4*>(kp)[1] = make_uint4(kk[4], kk[5], kk[6], kk[7]);
-      reinterpret_cast<uint4*>(vp)[0] = make_uint4(gg[0], gg[1], gg[2], gg[3]);
-      reinterpret_cast<uint4*>(vp)[1] = make_uint4(gg[4], gg[5], gg[6], gg[7]);
-    } else {
-#pragma unroll
-      for (int j = 0; j < kEmitPer; ++j)
-        if (j0 + j < nk) {
-          kp[j] = kk[j];
-          vp[j] = gg[j];
-        }
-    }
-  }
-  __syncthreads();
-  if (tid < kRadixBins) hist[(int64_t)tid * nb + blockIdx.x] = s_cnt[tid];
-}
-
-// Visitor of the offsets scan over the visible records in depth order: record i (value = its
-// tile count, exclusive prefix a) owns slots [a, a + count); writes entry_base[record] = a and
-// the first record of every emit block whose first slot falls in that range.
-struct EntryVisit {
-  const uint32_t* order;
-  const int64_t* n_vis;
-  int64_t* entry_base;
-  int64_t* bstart;
-  int64_t n_blocks;
-  __device__ void operator()(int64_t i, int64_t a, int64_t cnt) const {
-    if (i >= *n_vis) return;
-    entry_base[order[i]] = a;
-    for (int64_t kb = (a + kEmitTile - 1) / kEmitTile; kb < n_blocks && kb * kEmitTile < a + cnt; ++kb) bstart[kb] = i;
+// Closing step of the depth-order scan of supertile counts: the (supertile, record) entry
+// count, or 0 when the (tile, Gaussian) entries overflow the capacity (the lists are then left
+// empty).
+struct CoarseCount {
+  int64_t* scalars;
+  int64_t cap;
+  struct In {};
+  template <typename T>
+  __device__ In load(int64_t, T) const { return In{}; }
+  template <typename T>
+  __device__ void operator()(int64_t, T, T, In) const {}
+  __device__ void finish(int64_t total) const {
+    scalars[kScCoarse] = (scalars[kScEntries] > cap || total > cap) ? 0 : total;
   }
 };
+
+// A (supertile, record) entry's value: the Gaussian id in the low 32 bits, then the tile rows
+// (bits 32-39) and columns (bits 40-47) of the supertile that the record's rectangle covers.
+__device__ __forceinline__ uint64_t coarse_value(uint32_t gid, uint32_t rows, uint32_t cols) {
+  return (uint64_t)gid | ((uint64_t)rows << 32) | ((uint64_t)cols << 40);
+}
+
+// Visible record i (depth order) writes its (local supertile, record) entries from its offset
+// coff[i] on, row by row of its supertile span (one thread per record).
+__global__ __launch_bounds__(256) void k_coarse_emit(const DevSensor* __restrict__ sens, int count, int64_t N,
+                                                     const int4* __restrict__ rect, const uint32_t* __restrict__ order,
+                                                     const int64_t* __restrict__ coff,
+                                                     const int64_t* __restrict__ scalars, int64_t n_cap,
+                                                     uint32_t* __restrict__ ckeys, uint64_t* __restrict__ cvals,
+                                                     int64_t cap) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_cap || i >= scalars[kScVisible] || scalars[kScCoarse] == 0) return;
+  const uint32_t rec = order[i];
+  const int64_t a = coff[i];
+  const int s = record_sensor(rec, N, count);
+  const DevSensor& S = sens[s];
+  const int4 rc = rect[rec];
+  const StSpan sp = st_span(S, rc);
+  const uint32_t st0 = (uint32_t)(S.st_base - sens[0].st_base);
+  const uint32_t gid = (uint32_t)((int64_t)rec - (int64_t)s * N);
+  const int nc = sp.nc0 + sp.nc1;
+  int64_t q = a;
+  for (int r = 0; r < sp.nr; ++r) {
+    const int sr = sp.r0 + r;
+    const uint32_t row = st0 + (uint32_t)sr * (uint32_t)S.st_x;
+    for (int c = 0; c < nc; ++c, ++q) {
+      const int col = c < sp.nc0 ? sp.c0 + c : c - sp.nc0;
+      uint32_t rows, cols;
+      st_rows_cols(S, rc, sr, col, rows, cols);
+      if (q < cap) {
+        ckeys[q] = row + (uint32_t)col;
+        cvals[q] = coarse_value(gid, rows, cols);
+      }
+    }
+  }
+}
+
+// Coarse entries are cut into items of at most kItemEntries consecutive entries of one
+// supertile; every supertile has at least one item (possibly empty), whose first one also
+// writes the supertile's tile ranges.  One wavefront handles an item.
+constexpr int kItemEntries = 256;
+
+inline int64_t item_capacity(int64_t n_supertiles, int64_t k_cap) { return n_supertiles + div_up(k_cap, kItemEntries); }
+
+struct LoadItemCount {
+  const int2* crange;
+  int64_t n_st;
+  __device__ int64_t operator()(int64_t i) const {
+    if (i >= n_st) return 0;
+    const int2 r = crange[i];
+    const int64_t c = (int64_t)(r.y - r.x);
+    return c > kItemEntries ? (c + kItemEntries - 1) / kItemEntries : 1;
+  }
+};
+
+// the count array: 64 x items counts, then a zero (so that the scan's last element is the total)
+struct LoadCountX {
+  const uint32_t* cnt;
+  const int64_t* n_x;
+  __device__ uint32_t operator()(int64_t i) const { return i + 1 < *n_x ? cnt[i] : 0u; }
+};
+
+// Visitor of the scan of item counts over supertiles: every item of supertile b gets
+// item_st[item] = (b, sensor of b); the closing block stores the count array's size.
+struct ItemsVisit {
+  const DevSensor* sens;
+  int count;
+  int64_t n_st;
+  uint2* item_st;
+  int64_t* scalars;
+  struct In {};
+  template <typename T>
+  __device__ In load(int64_t, T) const { return In{}; }
+  __device__ void operator()(int64_t b, int64_t first, int64_t n, In) const {
+    if (b >= n_st) return;
+    int lo = 0, hi = count - 1;   // last sensor whose first supertile <= b
+    const int64_t b0 = sens[0].st_base;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sens[mid].st_base - b0 <= b) lo = mid; else hi = mid - 1;
+    }
+    for (int64_t j = 0; j < n; ++j) item_st[first + j] = make_uint2((uint32_t)b, (uint32_t)lo);
+  }
+  __device__ void finish(int64_t total) const { scalars[kScItemsX] = total * 64 + 1; }
+};
+
+// the item's supertile (its index in the call and its sensor), first entry and entry count
+struct ItemView {
+  int64_t st, first_item, n_items;
+  int s;
+  int sr, sc;
+  int64_t p0;
+  int cnt;
+};
+
+__device__ __forceinline__ ItemView item_view(const DevSensor* sens, const uint2* item_st, const int64_t* item_first,
+                                              const int2* crange, int64_t it) {
+  ItemView v;
+  const uint2 bs = item_st[it];
+  v.st = bs.x;
+  v.s = (int)bs.y;
+  v.first_item = item_first[bs.x];
+  v.n_items = item_first[bs.x + 1] - v.first_item;
+  const DevSensor& S = sens[v.s];
+  const int q = (int)((int64_t)bs.x - (S.st_base - sens[0].st_base));
+  v.sr = q / S.st_x;
+  v.sc = q - v.sr * S.st_x;
+  const int2 r = crange[bs.x];
+  v.p0 = (int64_t)r.x + (it - v.first_item) * kItemEntries;
+  const int64_t rest = (int64_t)r.y - v.p0;
+  v.cnt = (int)(rest < 0 ? 0 : (rest > kItemEntries ? kItemEntries : rest));
+  return v;
+}
+
+// Position of (item it, tile f of its supertile) in the count array: supertile-major, then f,
+// then the supertile's items, so that one exclusive scan of the array gives every item the
+// first list position of each of its tiles, the supertiles' tiles laid out one after another.
+__device__ __forceinline__ int64_t count_slot(const ItemView& v, int64_t it, int f) {
+  return v.first_item * 64 + (int64_t)f * v.n_items + (it - v.first_item);
+}
+
+// Items are spread over a fixed grid; wavefront w of block b takes items b * 4 + w + k * 4 * grid.
+#define FOR_EACH_ITEM(it)                                                                          \
+  const int64_t n_items_ = (scalars[kScItemsX] - 1) / 64;                                          \
+  for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < n_items_; it += (int64_t)gridDim.x * 4)
+
+// An item's coarse entries (at most kItemEntries = 4 rounds of 64, one per lane), loaded up
+// front; an entry past the item covers nothing.
+constexpr int kItemRounds = kItemEntries / 64;
+static_assert(kItemRounds * 64 == kItemEntries, "items are whole rounds of 64 entries");
+
+struct ItemEntries {
+  uint64_t val[kItemRounds];
+};
+
+__device__ __forceinline__ void load_item(const ItemView& v, const uint64_t* __restrict__ cvals, int lane,
+                                          ItemEntries& e) {
+#pragma unroll
+  for (int k = 0; k < kItemRounds; ++k) {
+    const int j = k * 64 + lane;
+    e.val[k] = j < v.cnt ? cvals[v.p0 + j] : 0ull;
+  }
+}
+
+__device__ __forceinline__ uint32_t entry_rows(uint64_t val) { return (uint32_t)(val >> 32) & 0xFFu; }
+__device__ __forceinline__ uint32_t entry_cols(uint64_t val) { return (uint32_t)(val >> 40) & 0xFFu; }
+
+// Ballots of one round: rb[y] = lanes covering tile row y of the supertile, cb[x] = lanes
+// covering tile column x; the lanes covering tile (y, x) are rb[y] & cb[x].  my = that set for
+// the lane's own tile f = lane.
+struct RoundBallots {
+  uint64_t rb[kStSide], cb[kStSide];
+  uint64_t my;
+};
+
+__device__ __forceinline__ void round_ballots(uint32_t rows, uint32_t cols, int lane, RoundBallots& b) {
+  uint64_t myr = 0, myc = 0;
+#pragma unroll
+  for (int k = 0; k < kStSide; ++k) {
+    b.rb[k] = __ballot((rows >> k) & 1u);
+    b.cb[k] = __ballot((cols >> k) & 1u);
+    myr = (lane >> 3) == k ? b.rb[k] : myr;
+    myc = (lane & 7) == k ? b.cb[k] : myc;
+  }
+  b.my = myr & myc;
+}
+
+// Per item: the number of its coarse entries meeting each tile f of the supertile (lane f
+// accumulates), written to the count array.
+__global__ __launch_bounds__(256) void k_st_count(const DevSensor* __restrict__ sens,
+                                                  const uint64_t* __restrict__ cvals, const int2* __restrict__ crange,
+                                                  const int64_t* __restrict__ item_first,
+                                                  const uint2* __restrict__ item_st,
+                                                  const int64_t* __restrict__ scalars, uint32_t* __restrict__ cnt) {
+  const int lane = threadIdx.x & 63;
+  FOR_EACH_ITEM(it) {
+    const ItemView v = item_view(sens, item_st, item_first, crange, it);
+    ItemEntries e;
+    load_item(v, cvals, lane, e);
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kItemRounds; ++k) {
+      if (k * 64 >= v.cnt) break;   // uniform
+      RoundBallots b;
+      round_ballots(entry_rows(e.val[k]), entry_cols(e.val[k]), lane, b);
+      acc += (uint32_t)__popcll(b.my);
+    }
+    cnt[count_slot(v, it, lane)] = acc;
+  }
+}
+
+// Per item: every coarse entry's Gaussian id goes to each of its tiles' lists, at the item's
+// scanned first position for that tile plus the entry's rank among the item's earlier entries
+// meeting the same tile (lanes below it in the tile's ballot set; lane f carries tile f's next
+// position across rounds), so each list keeps the depth order of the coarse entries.  The
+// tiles are visited in a uniform loop over the round's nonempty (row, column) ballot pairs.
+// The first item of a supertile also writes its tiles' [start, end) ranges.
+__global__ __launch_bounds__(256) void k_st_place(const DevSensor* __restrict__ sens,
+                                                  const uint64_t* __restrict__ cvals, const int2* __restrict__ crange,
+                                                  const int64_t* __restrict__ item_first,
+                                                  const uint2* __restrict__ item_st,
+                                                  const int64_t* __restrict__ scalars,
+                                                  const uint32_t* __restrict__ pos0, int64_t k_cap,
+                                                  int32_t* __restrict__ gauss, int2* __restrict__ tile_range) {
+  const int lane = threadIdx.x & 63;
+  FOR_EACH_ITEM(it) {
+    const ItemView v = item_view(sens, item_st, item_first, crange, it);
+    ItemEntries e;
+    load_item(v, cvals, lane, e);
+    const uint32_t start = pos0[count_slot(v, it, lane)];
+    if (it == v.first_item) {   // the supertile's tile ranges (tiles inside the sensor's grid)
+      const DevSensor& S = sens[v.s];
+      const int row = v.sr * kStSide + (lane >> 3), col = v.sc * kStSide + (lane & 7);
+      if (row < grid_rows(S) && col < grid_stride(S)) {
+        const int64_t t = (S.tile_base - sens[0].tile_base) + (int64_t)row * grid_stride(S) + col;
+        const uint32_t end = pos0[v.first_item * 64 + (int64_t)(lane + 1) * v.n_items];
+        tile_range[t] = make_int2((int)start, (int)end);
+      }
+    }
+    uint32_t run = start;
+#pragma unroll
+    for (int k = 0; k < kItemRounds; ++k) {
+      if (k * 64 >= v.cnt) break;   // uniform
+      const uint32_t rows = entry_rows(e.val[k]), cols = entry_cols(e.val[k]);
+      RoundBallots b;
+      round_ballots(rows, cols, lane, b);
+      const int32_t gid = (int32_t)(uint32_t)e.val[k];
+#pragma unroll
+      for (int y = 0; y < kStSide; ++y) {
+        if (b.rb[y] == 0) continue;   // uniform
+#pragma unroll
+        for (int x = 0; x < kStSide; ++x) {
+          const uint64_t m = b.rb[y] & b.cb[x];
+          if (m == 0) continue;   // uniform
+          const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)run, y * kStSide + x);
+          const uint32_t p = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          if (((rows >> y) & (cols >> x) & 1u) && (int64_t)p < k_cap) gauss[p] = gid;
+        }
+      }
+      run += (uint32_t)__popcll(b.my);
+    }
+  }
+}
 
 constexpr int kRangeItems = 8;   // sorted keys per thread of k_ranges
 
@@ -783,12 +1100,19 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   int64_t max_blocks = div_up(max_n, kScanTile);
   for (int i = 0; i < 2; ++i) w.dkeys[i] = (uint64_t*)take(nrec * 8);
   for (int i = 0; i < 2; ++i) w.dvals[i] = (uint32_t*)take(nrec * 4);
-  w.offs = (int64_t*)take((nrec + 1) * 8);
-  w.scan_part = (int64_t*)take((div_up(nrec > n_tiles + 2 ? nrec : n_tiles + 2, kScanTile) + 2) * 8);
-  for (int i = 0; i < 2; ++i) w.tkeys[i] = (uint32_t*)take(kc * 4);
-  w.tvals = (uint32_t*)take(kc * 4);
+  w.coff = (int64_t*)take(nrec * 8);
+  w.scan_part = take((div_up(nrec > n_tiles + 2 ? nrec : n_tiles + 2, scan_tile<P64>()) + 2) * 16);
+  for (int i = 0; i < 2; ++i) w.ckeys[i] = (uint32_t*)take(kc * 4);
+  for (int i = 0; i < 2; ++i) w.cvals[i] = (uint64_t*)take(kc * 8);
+  const int64_t nst = n_tiles < 1 ? 1 : n_tiles;   // supertiles <= tiles
+  w.crange = (int2*)take(nst * 8);
+  w.item_first = (int64_t*)take((nst + 1) * 8);
+  w.item_st = (uint2*)take(item_capacity(nst, kc) * 8);
+  const int64_t xcap = item_capacity(nst, kc) * 64 + 1;
+  w.xcount = (uint32_t*)take(xcap * 4);
+  w.xpart = (uint32_t*)take((div_up(xcap, kScanTile) + 2) * 4);
   w.hist = (uint32_t*)take((size_t)kRadixBins * max_blocks * 4 + 64);
-  w.hist_part = (uint32_t*)take((div_up((int64_t)kRadixBins * max_blocks, kScanTile) + 2) * 4);
+  w.coltotal = (uint32_t*)take(kRadixBins * 4);
   for (int i = 0; i < 2; ++i) w.rkeys[i] = (uint32_t*)take(nr * 4);
   for (int i = 0; i < 2; ++i) w.rvals[i] = (uint32_t*)take(nr * 4);
   const int64_t wcap = work_capacity(n_tiles, nr) + 1;
@@ -797,8 +1121,7 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   w.qtmp = (int2*)take(wcap * 8);
   w.wcount = (int64_t*)take((n_tiles + 2) * 8);
   w.wpart = (int64_t*)take((div_up(n_tiles + 2, kScanTile) + 2) * 8);
-  w.scalars = (int64_t*)take(4 * 8);
-  w.bstart = (int64_t*)take((size_t)(div_up(kc, kEmitTile) + 1) * 8);
+  w.scalars = (int64_t*)take(kScCount * 8);
   const size_t sort_bytes = off;
   // adjoint buffers start over at the base
   off = 0;
@@ -818,51 +1141,60 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
                            SplatStatus* st, hipStream_t s) {
   const int64_t n_rec = (int64_t)v.count * v.n_gauss;
   hipError_t e;
-  int64_t* n_sort = w.scalars;   // min(K, k_cap)
-  // 1. visible records, compacted in record order, then stably sorted by the 40-bit depth key
-  int64_t* n_vis = n_sort + 1;
-  if ((e = device_scan<int64_t>(LoadVisible{p.n_tiles}, n_rec, w.offs, w.scan_part, s)) != hipSuccess) return e;
-  const int64_t nb0 = div_up(n_rec, kScanTile);
-  hipLaunchKernelGGL(k_copy_i64, dim3(1), dim3(1), 0, s, (const int64_t*)(w.scan_part + nb0), n_vis);
-  if (n_rec > 0)
-    hipLaunchKernelGGL(k_compact_visible, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, (const int32_t*)p.n_tiles,
-                       (const unsigned long long*)p.dkey, (const int64_t*)w.offs, n_rec, w.dkeys[0], w.dvals[0]);
+  int64_t* const sc = w.scalars;
+  // 1. one record-order scan of (visible, tile count): entry bases, the visible records'
+  //    packed depth keys compacted in record order, the counts and the overflow status
+  if ((e = device_scan<P64>(LoadVisibleTiles{p.n_tiles}, n_rec, (P64*)nullptr, (P64*)w.scan_part, s,
+                            VisibleVisit{v.sens, v.count, v.n_gauss, (const int4*)p.rect,
+                                         (const unsigned long long*)p.dkey, L.entry_base, w.dkeys[0], w.dvals[0], sc,
+                                         L.k_cap, st})) != hipSuccess)
+    return e;
+  // 2. stable sort of the visible records by the 40-bit depth key (ties keep record order)
   uint64_t* dk[2] = {w.dkeys[0], w.dkeys[1]};
   uint32_t* dvv[2] = {w.dvals[0], w.dvals[1]};
   int cur = 0;
-  if ((e = radix_sort<uint64_t>(dk, dvv, cur, n_vis, n_rec, 0, kDepthKeyBits, w.hist, w.hist_part,
+  if ((e = radix_sort<uint64_t, uint32_t>(dk, dvv, cur, sc + kScVisible, n_rec, 0, kDepthKeyBits, w.hist, w.coltotal,
                                 nullptr, s)) != hipSuccess)
     return e;
-  const uint32_t* order = dvv[cur];
-  // 2. slot ranges
-  const int64_t emit_blocks = div_up(L.k_cap, kEmitTile);
-  if ((e = device_scan<int64_t>(LoadPackedTiles{dk[cur], n_vis}, n_rec, w.offs, w.scan_part, s,
-                                EntryVisit{order, n_vis, L.entry_base, w.bstart, emit_blocks})) != hipSuccess)
+  // 3. depth-order scan of the supertile counts, emitting (supertile, record) entries in depth
+  //    order
+  if ((e = device_scan<int64_t>(LoadPackedCount{dk[cur], sc + kScVisible}, n_rec, w.coff, (int64_t*)w.scan_part, s,
+                                CoarseCount{sc, L.k_cap}, sc + kScVisible)) != hipSuccess)
     return e;
-  int64_t nb = div_up(n_rec, kScanTile);
-  hipLaunchKernelGGL(k_finalize_count, dim3(1), dim3(1), 0, s, (const int64_t*)(w.scan_part + nb), L.k_cap, n_sort, st);
-  // 3. emit: the final tile-sort pass must land its values in lists->gauss
-  const int tbits = bits_for(v.n_tiles);
-  const int passes = (tbits + kRadixBits - 1) / kRadixBits;
-  uint32_t* tv[2];
-  if (passes % 2 == 0) { tv[0] = (uint32_t*)L.gauss; tv[1] = w.tvals; }
-  else { tv[0] = w.tvals; tv[1] = (uint32_t*)L.gauss; }
-  if (n_rec > 0 && L.k_cap > 0)
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks), dim3(kEmitThreads), 0, s, v.sens, v.count, v.n_gauss,
-                       (const int4*)p.rect, order, (const int64_t*)w.offs, (const int64_t*)n_vis,
-                       (const int64_t*)n_sort, (const int64_t*)w.bstart, w.tkeys[0], tv[0], w.hist,
-                       div_up(L.k_cap, kScanTile), (1u << radix_pass_bits(tbits)) - 1u);
-  // 4. stable sort by tile
-  uint32_t* tk[2] = {w.tkeys[0], w.tkeys[1]};
-  int tcur = 0;
-  if ((e = radix_sort<uint32_t>(tk, tv, tcur, n_sort, L.k_cap, 0, tbits, w.hist, w.hist_part, nullptr, s,
-                                n_rec > 0 && L.k_cap > 0)) != hipSuccess)
+  if (n_rec > 0)
+    hipLaunchKernelGGL(k_coarse_emit, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, v.sens, v.count, v.n_gauss,
+                       (const int4*)p.rect, (const uint32_t*)dvv[cur], (const int64_t*)w.coff, (const int64_t*)sc, n_rec,
+                       w.ckeys[0], w.cvals[0], L.k_cap);
+  // 4. stable sort of the entries by supertile: each supertile's records stay in depth order
+  const int64_t n_st = v.n_supertiles;
+  uint32_t* ck[2] = {w.ckeys[0], w.ckeys[1]};
+  uint64_t* cv[2] = {w.cvals[0], w.cvals[1]};
+  int ccur = 0;
+  if ((e = radix_sort<uint32_t, uint64_t>(ck, cv, ccur, sc + kScCoarse, L.k_cap, 0, bits_for(n_st), w.hist, w.coltotal,
+                                nullptr, s)) != hipSuccess)
     return e;
-  // 5. ranges
-  if ((e = fill<int32_t>(L.tile_range, 2 * v.n_tiles, 0, s)) != hipSuccess) return e;
+  if ((e = fill<int32_t>((int32_t*)w.crange, 2 * n_st, 0, s)) != hipSuccess) return e;
   if (L.k_cap > 0)
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(L.k_cap, 256 * kRangeItems)), dim3(256), 0, s, (const uint32_t*)tk[tcur],
-                       (const int64_t*)n_sort, L.k_cap, (int2*)L.tile_range, 0, (int64_t)0);
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(L.k_cap, 256 * kRangeItems)), dim3(256), 0, s,
+                       (const uint32_t*)ck[ccur], (const int64_t*)(sc + kScCoarse), L.k_cap, w.crange, 0, (int64_t)0);
+  // 5. items of <= kItemEntries entries per supertile; per item and tile the entry counts; their
+  //    scan gives every tile's list range and every item its first positions; placement
+  if ((e = device_scan<int64_t>(LoadItemCount{w.crange, n_st}, n_st + 1, w.item_first, (int64_t*)w.scan_part, s,
+                                ItemsVisit{v.sens, v.count, n_st, w.item_st, sc})) != hipSuccess)
+    return e;
+  const int64_t icap = item_capacity(n_st, L.k_cap);
+  int64_t grid = div_up(icap, 4);
+  const int64_t gmax = (int64_t)(v.n_cu > 0 ? v.n_cu : 256) * 16;
+  if (grid > gmax) grid = gmax;
+  hipLaunchKernelGGL(k_st_count, dim3((unsigned)grid), dim3(256), 0, s, v.sens, (const uint64_t*)cv[ccur],
+                     (const int2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, (const int64_t*)sc,
+                     w.xcount);
+  if ((e = device_scan<uint32_t>(LoadCountX{w.xcount, sc + kScItemsX}, icap * 64 + 1, w.xcount, w.xpart, s,
+                                 NoVisit(), sc + kScItemsX)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_st_place, dim3((unsigned)grid), dim3(256), 0, s, v.sens, (const uint64_t*)cv[ccur],
+                     (const int2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, (const int64_t*)sc,
+                     (const uint32_t*)w.xcount, L.k_cap, L.gauss, (int2*)L.tile_range);
   // 6. lidar rays -> tiles; work items (lidar chunks, and camera tiles in the batched form)
   if (v.has_lidar || v.queue) {
     const int64_t bins = v.n_tiles + 1;
@@ -881,7 +1213,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
       uint32_t* rk[2] = {w.rkeys[0], w.rkeys[1]};
       uint32_t* rv[2] = {w.rvals[0], w.rvals[1]};
       int rcur = 0;
-      if ((e = radix_sort<uint32_t>(rk, rv, rcur, nullptr, nr, 0, bin_bits + cell_bits, w.hist, w.hist_part,
+      if ((e = radix_sort<uint32_t, uint32_t>(rk, rv, rcur, nullptr, nr, 0, bin_bits + cell_bits, w.hist, w.coltotal,
                                     (uint32_t*)L.ray_order, s)) != hipSuccess)
         return e;
       hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(nr, 256 * kRangeItems)), dim3(256), 0, s, (const uint32_t*)rk[rcur],
@@ -904,7 +1236,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
       uint32_t* qv[2] = {w.qvals[0], w.qvals[1]};
       int qcur = 0;
       // item count: the scan total (clamped to the capacity by the sort)
-      if ((e = radix_sort<uint32_t>(qk, qv, qcur, w.wcount + bins, wcap, 0, 8, w.hist, w.hist_part, nullptr, s)) !=
+      if ((e = radix_sort<uint32_t, uint32_t>(qk, qv, qcur, w.wcount + bins, wcap, 0, 8, w.hist, w.coltotal, nullptr, s)) !=
           hipSuccess)
         return e;
       hipLaunchKernelGGL(k_queue_gather, dim3((unsigned)div_up(wcap, 256)), dim3(256), 0, s, (const int2*)w.qtmp,

@@ -44,6 +44,7 @@ struct CallView {
   int32_t count;
   int64_t n_gauss;
   int64_t n_tiles;         // tiles of the call
+  int64_t n_supertiles;    // binning supertiles of the call (<= n_tiles)
   int64_t n_rays;          // rays of the call
   bool lidar;              // plain lidar call (all sensors are lidars)
   bool queue;              // batched form: any mix of sensors, persistent queue rasterisers
@@ -62,14 +63,19 @@ inline int64_t work_capacity(int64_t n_tiles, int64_t n_rays) {
 // ---- workspace carving (sizes in bytes, 256-aligned) ----------------------------------------
 struct Workspace {
   // bin/sort
-  uint64_t* dkeys[2];     // [n_rec] float64 depth keys of the visible records
+  uint64_t* dkeys[2];     // [n_rec] packed depth keys of the visible records
   uint32_t* dvals[2];
-  int64_t* offs;          // [n_rec + 1] exclusive scan of n_tiles in depth order
-  int64_t* scan_part;     // block partials of the int64 scan
-  uint32_t* tkeys[2];     // [k_cap]
-  uint32_t* tvals;        // [k_cap] (ping-pong partner of lists->gauss)
+  int64_t* coff;          // [n_rec] first (supertile, record) entry of each visible record, depth order
+  void* scan_part;        // block partials of the record scans (16 bytes per block)
+  uint32_t* ckeys[2];     // [k_cap] supertile of each (supertile, record) entry
+  uint64_t* cvals[2];     // [k_cap] Gaussian id | covered tile rows << 32 | columns << 40
+  int2* crange;           // [supertiles] [start, end) of each supertile's entries
+  int64_t* item_first;    // [supertiles + 1] first item of each supertile; [n] = items
+  uint2* item_st;         // [items] (supertile, sensor) of each item
+  uint32_t* xcount;       // [64 items + 1] per (item, tile) entry counts, then their scan
+  uint32_t* xpart;
   uint32_t* hist;         // [256 * max_blocks + partials]
-  uint32_t* hist_part;
+  uint32_t* coltotal;     // [256] digit totals of a radix pass
   uint32_t* rkeys[2];     // [n_rays]
   uint32_t* rvals[2];
   int64_t* wcount;        // [n_tiles + 2]
@@ -77,10 +83,9 @@ struct Workspace {
   uint32_t* qkeys[2];     // [work_cap] queue cost keys
   uint32_t* qvals[2];
   int2* qtmp;             // [work_cap] unordered work items
-  int64_t* scalars;       // [4] device scalars: clamped intersection count, visible records
-  int64_t* bstart;        // [emit blocks + 1] first record (depth order) of every emit block
+  int64_t* scalars;       // [4] device scalars of the call (visible records, entry counts, items)
   // adjoint (overlays the bin/sort buffers: the two are never live in one call)
-  float* slots;           // [k_cap, slot_stride] per-entry gradient rows, indexed by emission position
+  float* slots;           // [k_cap, slot_stride] per-entry gradient rows, indexed by entry number
   uint8_t* flags;         // [k_cap] 1 = slot row written by this adjoint call
   float* g2d;             // [n_rec, kNV] atomically accumulated part (lidar tiles split over items)
   uint8_t* rflag;         // [n_rec] 1 = the adjoint produced a gradient for the record

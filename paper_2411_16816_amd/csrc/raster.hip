@@ -12,8 +12,8 @@
 // The adjoint walks the same list back to front from each ray's `last`, recovering
 // T_i = T_{i+1} / (1 - alpha_i) from the saved final transmittance.  Per-Gaussian gradients
 // are summed across the wavefront (reduce-scatter over permlane swaps and DPP), across the
-// workgroup in LDS, and stored as one row per (tile, Gaussian) entry at the entry's emission
-// position, where the projection adjoint sums each record's rows in a fixed order.  Only work
+// workgroup in LDS, and stored as one row per (tile, Gaussian) entry at the entry's number
+// (record-major), where the projection adjoint sums each record's rows in a fixed order.  Only work
 // items of lidar tiles split over several items add their rows with global atomics.
 #include "kernels.hpp"
 #include "wave_ops.hpp"

@@ -20,6 +20,7 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTStop = 1e-4f;
 constexpr int kBlock = 256;                  // lanes per rasterisation workgroup (4 x wave64)
+constexpr int kStSide = 8;                   // tiles per side of a binning supertile (8 x 8 = 64 tiles)
 
 enum SensorKind : int32_t { kCamera = 0, kLidar = 1 };
 
@@ -29,6 +30,8 @@ struct alignas(16) DevSensor {
   int32_t feat_off, n_ch;      // blended feature columns
   int32_t n_tiles;             // tiles of this sensor
   int64_t tile_base;           // global numbering inside the rig
+  int32_t st_x, st_y;          // binning supertiles per row / column of the tile grid
+  int64_t st_base;             // first supertile (global numbering inside the rig)
   int64_t ray_base;
   int64_t feat_base;
   int64_t n_rays;
