@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_scan_reduce(Load ld, int64_t n, const i
 
 // Up to this many blocks every down-sweep block sums the block totals before it itself (one
 // launch fewer); beyond it a single block scans the totals first.
-constexpr int64_t kScanFusedBlocks = 1024;
+constexpr int64_t kScanFusedBlocks = 4096;
 
 // single block: exclusive scan of part[0..nb) in place, part[nb] = total
 template <typename T>
@@ -540,9 +540,9 @@ __device__ __forceinline__ int record_sensor(int64_t rec, int64_t N, int count) 
 
 // ---- supertiles --------------------------------------------------------------------------------
 // A sensor's tile grid (camera tiles_x x tiles_y; lidar M_phi x M_omega) is cut into supertiles
-// of kStSide x kStSide tiles, numbered row-major (st_x per row), after the supertiles of the
-// call's earlier sensors.  Tile (row, col) is tile f = (row % 8) * 8 + col % 8 of supertile
-// (row / 8, col / 8).
+// of 2^st_wl x 2^st_hl tiles, numbered row-major (st_x per row), after the supertiles of the
+// call's earlier sensors.  Tile (row, col) is tile f = (row % h) * 8 + col % w of supertile
+// (row / h, col / w) (tiles are numbered with a stride of 8 whatever the width).
 __device__ __forceinline__ int grid_stride(const DevSensor& S) { return S.kind == kCamera ? S.tiles_x : S.m_az; }
 __device__ __forceinline__ int grid_rows(const DevSensor& S) { return S.kind == kCamera ? S.tiles_y : S.m_el; }
 
@@ -555,17 +555,17 @@ struct StSpan {
 
 __device__ __forceinline__ StSpan st_span(const DevSensor& S, const int4 rc) {
   StSpan p;
-  p.r0 = rc.y / kStSide;
-  p.nr = (rc.y + rc.w - 1) / kStSide - p.r0 + 1;
+  p.r0 = rc.y >> S.st_hl;
+  p.nr = ((rc.y + rc.w - 1) >> S.st_hl) - p.r0 + 1;
   const int M = grid_stride(S);
   if (S.kind == kCamera || rc.x + rc.z <= M) {
-    p.c0 = rc.x / kStSide;
-    p.nc0 = (rc.x + rc.z - 1) / kStSide - p.c0 + 1;
+    p.c0 = rc.x >> S.st_wl;
+    p.nc0 = ((rc.x + rc.z - 1) >> S.st_wl) - p.c0 + 1;
     p.nc1 = 0;
   } else {
-    const int a = rc.x / kStSide;                    // [a, st_x) then [0, e]
-    const int e = (rc.x + rc.z - 1 - M) / kStSide;
-    if (e >= a) {                                    // the two runs meet: every column
+    const int a = rc.x >> S.st_wl;                    // [a, st_x) then [0, e]
+    const int e = (rc.x + rc.z - 1 - M) >> S.st_wl;
+    if (e >= a) {                                     // the two runs meet: every column
       p.c0 = 0;
       p.nc0 = S.st_x;
       p.nc1 = 0;
@@ -578,23 +578,25 @@ __device__ __forceinline__ StSpan st_span(const DevSensor& S, const int4 rc) {
   return p;
 }
 
-// Tiles of supertile (sr, sc) inside rectangle rc, as the rows (bit r: tile row sr * 8 + r) and
-// the columns (bit c: tile column sc * 8 + c) it covers there; tile f = r * 8 + c is inside
-// exactly when both bits are set.
+// bits [max(lo, 0), min(hi, cap)) of a mask of at most 8 bits
+__device__ __forceinline__ uint32_t span_bits(int lo, int hi, int cap) {
+  const int a = lo > 0 ? lo : 0;
+  const int b = hi < cap ? hi : cap;
+  return b > a ? ((1u << b) - 1u) & ~((1u << a) - 1u) : 0u;
+}
+
+// Tiles of supertile (sr, sc) inside rectangle rc, as the rows (bit r: tile row sr * h + r) and
+// the columns (bit c: tile column sc * w + c) it covers there; tile f = r * 8 + c is inside
+// exactly when both bits are set.  A lidar rectangle's columns are [x0, x0 + w) modulo M_phi,
+// i.e. the columns of [x0, x0 + w) and of [x0 - M_phi, x0 + w - M_phi) inside the grid.
 __device__ __forceinline__ void st_rows_cols(const DevSensor& S, const int4 rc, int sr, int sc, uint32_t& rows,
                                              uint32_t& cols) {
   const int M = grid_stride(S);
-  cols = 0;
-#pragma unroll
-  for (int c = 0; c < kStSide; ++c) {
-    const int x = sc * kStSide + c;
-    int d = x - rc.x;
-    if (S.kind != kCamera && d < 0) d += M;   // lidar: columns wrap modulo M_phi
-    cols |= (x < M && d >= 0 && d < rc.z) ? (1u << c) : 0u;
-  }
-  const int lo = rc.y - sr * kStSide, hi = rc.y + rc.w - sr * kStSide;   // rows [lo, hi) of the supertile
-  const int a = lo < 0 ? 0 : lo, b = hi > kStSide ? kStSide : hi;
-  rows = b > a ? ((1u << b) - 1u) & ~((1u << a) - 1u) : 0u;
+  const int x0 = sc << S.st_wl, y0 = sr << S.st_hl;
+  const int wcap = M - x0 < (1 << S.st_wl) ? M - x0 : (1 << S.st_wl);
+  cols = span_bits(rc.x - x0, rc.x + rc.z - x0, wcap);
+  if (S.kind != kCamera) cols |= span_bits(rc.x - M - x0, rc.x + rc.z - M - x0, wcap);
+  rows = span_bits(rc.y - y0, rc.y + rc.w - y0, 1 << S.st_hl);
 }
 
 // Visitor of the record-order scan of (visible, tile count) pairs.  A visible record gets its
@@ -687,8 +689,25 @@ __device__ __forceinline__ uint64_t coarse_value(uint32_t gid, uint32_t rows, ui
   return (uint64_t)gid | ((uint64_t)rows << 32) | ((uint64_t)cols << 40);
 }
 
+// Entry j (row-major over its supertile span) of a record: the supertile key and the value.
+__device__ __forceinline__ void coarse_entry(const DevSensor& S, uint32_t st0, const int4 rc, const StSpan& sp,
+                                             uint32_t gid, int j, uint32_t& key, uint64_t& val) {
+  const int nc = sp.nc0 + sp.nc1;
+  const int r = j / nc, c = j - r * nc;
+  const int sr = sp.r0 + r;
+  const int sc = c < sp.nc0 ? sp.c0 + c : c - sp.nc0;
+  uint32_t rows, cols;
+  st_rows_cols(S, rc, sr, sc, rows, cols);
+  key = st0 + (uint32_t)sr * (uint32_t)S.st_x + (uint32_t)sc;
+  val = coarse_value(gid, rows, cols);
+}
+
 // Visible record i (depth order) writes its (local supertile, record) entries from its offset
-// coff[i] on, row by row of its supertile span (one thread per record).
+// coff[i] on.  Each lane writes the first kEmitOwn entries of its own record; the entries
+// beyond that of the wavefront's larger records are then written by the whole wavefront, one
+// record at a time, 64 entries per step.
+constexpr int kEmitOwn = 4;
+
 __global__ __launch_bounds__(256) void k_coarse_emit(const DevSensor* __restrict__ sens, int count, int64_t N,
                                                      const int4* __restrict__ rect, const uint32_t* __restrict__ order,
                                                      const int64_t* __restrict__ coff,
@@ -696,27 +715,58 @@ __global__ __launch_bounds__(256) void k_coarse_emit(const DevSensor* __restrict
                                                      uint32_t* __restrict__ ckeys, uint64_t* __restrict__ cvals,
                                                      int64_t cap) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_cap || i >= scalars[kScVisible] || scalars[kScCoarse] == 0) return;
-  const uint32_t rec = order[i];
-  const int64_t a = coff[i];
-  const int s = record_sensor(rec, N, count);
-  const DevSensor& S = sens[s];
-  const int4 rc = rect[rec];
-  const StSpan sp = st_span(S, rc);
-  const uint32_t st0 = (uint32_t)(S.st_base - sens[0].st_base);
-  const uint32_t gid = (uint32_t)((int64_t)rec - (int64_t)s * N);
-  const int nc = sp.nc0 + sp.nc1;
-  int64_t q = a;
-  for (int r = 0; r < sp.nr; ++r) {
-    const int sr = sp.r0 + r;
-    const uint32_t row = st0 + (uint32_t)sr * (uint32_t)S.st_x;
-    for (int c = 0; c < nc; ++c, ++q) {
-      const int col = c < sp.nc0 ? sp.c0 + c : c - sp.nc0;
-      uint32_t rows, cols;
-      st_rows_cols(S, rc, sr, col, rows, cols);
-      if (q < cap) {
-        ckeys[q] = row + (uint32_t)col;
-        cvals[q] = coarse_value(gid, rows, cols);
+  const int lane = threadIdx.x & 63;
+  const bool valid = i < n_cap && i < scalars[kScVisible] && scalars[kScCoarse] != 0;
+  uint32_t rec = 0, gid = 0;
+  int64_t q0 = 0;
+  int s = 0, cnt = 0;
+  int4 rc = make_int4(0, 0, 0, 0);
+  StSpan sp{0, 0, 0, 0, 0};
+  if (valid) {
+    rec = order[i];
+    q0 = coff[i];
+    s = record_sensor(rec, N, count);
+    rc = rect[rec];
+    sp = st_span(sens[s], rc);
+    gid = (uint32_t)((int64_t)rec - (int64_t)s * N);
+    cnt = sp.nr * (sp.nc0 + sp.nc1);
+  }
+  if (valid) {
+    const DevSensor& S = sens[s];
+    const uint32_t st0 = (uint32_t)(S.st_base - sens[0].st_base);
+    for (int j = 0; j < cnt && j < kEmitOwn; ++j) {
+      uint32_t key;
+      uint64_t val;
+      coarse_entry(S, st0, rc, sp, gid, j, key, val);
+      if (q0 + j < cap) {
+        ckeys[q0 + j] = key;
+        cvals[q0 + j] = val;
+      }
+    }
+  }
+  uint64_t heavy = __ballot(cnt > kEmitOwn);
+  while (heavy) {   // uniform
+    const int l = __ffsll((unsigned long long)heavy) - 1;
+    heavy &= heavy - 1;
+    const int sl = __builtin_amdgcn_readlane(s, l);
+    const int4 rl = make_int4(__builtin_amdgcn_readlane(rc.x, l), __builtin_amdgcn_readlane(rc.y, l),
+                              __builtin_amdgcn_readlane(rc.z, l), __builtin_amdgcn_readlane(rc.w, l));
+    const StSpan pl{__builtin_amdgcn_readlane(sp.r0, l), __builtin_amdgcn_readlane(sp.nr, l),
+                    __builtin_amdgcn_readlane(sp.c0, l), __builtin_amdgcn_readlane(sp.nc0, l),
+                    __builtin_amdgcn_readlane(sp.nc1, l)};
+    const uint32_t gl = (uint32_t)__builtin_amdgcn_readlane((int)gid, l);
+    const int64_t ql = ((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)q0, l)) |
+                       ((int64_t)__builtin_amdgcn_readlane((int)(q0 >> 32), l) << 32);
+    const int cl = __builtin_amdgcn_readlane(cnt, l);
+    const DevSensor& S = sens[sl];
+    const uint32_t st0 = (uint32_t)(S.st_base - sens[0].st_base);
+    for (int j = kEmitOwn + lane; j < cl; j += 64) {
+      uint32_t key;
+      uint64_t val;
+      coarse_entry(S, st0, rl, pl, gl, j, key, val);
+      if (ql + j < cap) {
+        ckeys[ql + j] = key;
+        cvals[ql + j] = val;
       }
     }
   }
@@ -747,29 +797,32 @@ struct LoadCountX {
   __device__ uint32_t operator()(int64_t i) const { return i + 1 < *n_x ? cnt[i] : 0u; }
 };
 
-// Visitor of the scan of item counts over supertiles: every item of supertile b gets
-// item_st[item] = (b, sensor of b); the closing block stores the count array's size.
+// Closing step of the scan of item counts over supertiles: the count array's size.
 struct ItemsVisit {
-  const DevSensor* sens;
-  int count;
-  int64_t n_st;
-  uint2* item_st;
   int64_t* scalars;
   struct In {};
   template <typename T>
   __device__ In load(int64_t, T) const { return In{}; }
-  __device__ void operator()(int64_t b, int64_t first, int64_t n, In) const {
-    if (b >= n_st) return;
-    int lo = 0, hi = count - 1;   // last sensor whose first supertile <= b
-    const int64_t b0 = sens[0].st_base;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (sens[mid].st_base - b0 <= b) lo = mid; else hi = mid - 1;
-    }
-    for (int64_t j = 0; j < n; ++j) item_st[first + j] = make_uint2((uint32_t)b, (uint32_t)lo);
-  }
+  template <typename T>
+  __device__ void operator()(int64_t, T, T, In) const {}
   __device__ void finish(int64_t total) const { scalars[kScItemsX] = total * 64 + 1; }
 };
+
+// One wavefront per supertile b: item_st[item] = (b, sensor of b) for each of its items.
+__global__ __launch_bounds__(256) void k_item_table(const DevSensor* __restrict__ sens, int count,
+                                                    const int64_t* __restrict__ item_first, int64_t n_st,
+                                                    uint2* __restrict__ item_st) {
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= n_st) return;   // uniform over the wavefront
+  int lo = 0, hi = count - 1;   // last sensor whose first supertile <= b
+  const int64_t b0 = sens[0].st_base;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sens[mid].st_base - b0 <= b) lo = mid; else hi = mid - 1;
+  }
+  const int64_t first = item_first[b], n = item_first[b + 1] - first;
+  for (int64_t j = threadIdx.x & 63; j < n; j += 64) item_st[first + j] = make_uint2((uint32_t)b, (uint32_t)lo);
+}
 
 // the item's supertile (its index in the call and its sensor), first entry and entry count
 struct ItemView {
@@ -806,10 +859,12 @@ __device__ __forceinline__ int64_t count_slot(const ItemView& v, int64_t it, int
   return v.first_item * 64 + (int64_t)f * v.n_items + (it - v.first_item);
 }
 
-// Items are spread over a fixed grid; wavefront w of block b takes items b * 4 + w + k * 4 * grid.
+// The items of supertiles [st_lo, st_hi) are spread over a fixed grid; wavefront w of block b
+// takes items first + b * 4 + w + k * 4 * grid.
 #define FOR_EACH_ITEM(it)                                                                          \
-  const int64_t n_items_ = (scalars[kScItemsX] - 1) / 64;                                          \
-  for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < n_items_; it += (int64_t)gridDim.x * 4)
+  const int64_t it_end_ = item_first[st_hi];                                                       \
+  for (int64_t it = item_first[st_lo] + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < it_end_; \
+       it += (int64_t)gridDim.x * 4)
 
 // An item's coarse entries (at most kItemEntries = 4 rounds of 64, one per lane), loaded up
 // front; an entry past the item covers nothing.
@@ -832,33 +887,40 @@ __device__ __forceinline__ void load_item(const ItemView& v, const uint64_t* __r
 __device__ __forceinline__ uint32_t entry_rows(uint64_t val) { return (uint32_t)(val >> 32) & 0xFFu; }
 __device__ __forceinline__ uint32_t entry_cols(uint64_t val) { return (uint32_t)(val >> 40) & 0xFFu; }
 
-// Ballots of one round: rb[y] = lanes covering tile row y of the supertile, cb[x] = lanes
-// covering tile column x; the lanes covering tile (y, x) are rb[y] & cb[x].  my = that set for
-// the lane's own tile f = lane.
+// Ballots of one round over supertiles of 2^WL x 2^HL tiles: rb[y] = lanes covering tile row
+// y, cb[x] = lanes covering tile column x; the lanes covering tile (y, x) are rb[y] & cb[x].
+// my = that set for the lane's own tile f = lane = y * 8 + x (empty for lanes outside).
+template <int WL, int HL>
 struct RoundBallots {
-  uint64_t rb[kStSide], cb[kStSide];
+  uint64_t rb[1 << HL], cb[1 << WL];
   uint64_t my;
 };
 
-__device__ __forceinline__ void round_ballots(uint32_t rows, uint32_t cols, int lane, RoundBallots& b) {
+template <int WL, int HL>
+__device__ __forceinline__ void round_ballots(uint32_t rows, uint32_t cols, int lane, RoundBallots<WL, HL>& b) {
   uint64_t myr = 0, myc = 0;
 #pragma unroll
-  for (int k = 0; k < kStSide; ++k) {
+  for (int k = 0; k < (1 << HL); ++k) {
     b.rb[k] = __ballot((rows >> k) & 1u);
-    b.cb[k] = __ballot((cols >> k) & 1u);
     myr = (lane >> 3) == k ? b.rb[k] : myr;
+  }
+#pragma unroll
+  for (int k = 0; k < (1 << WL); ++k) {
+    b.cb[k] = __ballot((cols >> k) & 1u);
     myc = (lane & 7) == k ? b.cb[k] : myc;
   }
   b.my = myr & myc;
 }
 
-// Per item: the number of its coarse entries meeting each tile f of the supertile (lane f
-// accumulates), written to the count array.
+// Per item of the supertiles [st_lo, st_hi) (all of one supertile shape): the number of its
+// coarse entries meeting each tile f of the supertile (lane f accumulates), written to the
+// count array.
+template <int WL, int HL>
 __global__ __launch_bounds__(256) void k_st_count(const DevSensor* __restrict__ sens,
                                                   const uint64_t* __restrict__ cvals, const int2* __restrict__ crange,
                                                   const int64_t* __restrict__ item_first,
-                                                  const uint2* __restrict__ item_st,
-                                                  const int64_t* __restrict__ scalars, uint32_t* __restrict__ cnt) {
+                                                  const uint2* __restrict__ item_st, int64_t st_lo, int64_t st_hi,
+                                                  uint32_t* __restrict__ cnt) {
   const int lane = threadIdx.x & 63;
   FOR_EACH_ITEM(it) {
     const ItemView v = item_view(sens, item_st, item_first, crange, it);
@@ -868,25 +930,26 @@ __global__ __launch_bounds__(256) void k_st_count(const DevSensor* __restrict__ 
 #pragma unroll
     for (int k = 0; k < kItemRounds; ++k) {
       if (k * 64 >= v.cnt) break;   // uniform
-      RoundBallots b;
-      round_ballots(entry_rows(e.val[k]), entry_cols(e.val[k]), lane, b);
+      RoundBallots<WL, HL> b;
+      round_ballots<WL, HL>(entry_rows(e.val[k]), entry_cols(e.val[k]), lane, b);
       acc += (uint32_t)__popcll(b.my);
     }
     cnt[count_slot(v, it, lane)] = acc;
   }
 }
 
-// Per item: every coarse entry's Gaussian id goes to each of its tiles' lists, at the item's
-// scanned first position for that tile plus the entry's rank among the item's earlier entries
-// meeting the same tile (lanes below it in the tile's ballot set; lane f carries tile f's next
-// position across rounds), so each list keeps the depth order of the coarse entries.  The
-// tiles are visited in a uniform loop over the round's nonempty (row, column) ballot pairs.
-// The first item of a supertile also writes its tiles' [start, end) ranges.
+// Per item of the supertiles [st_lo, st_hi): every coarse entry's Gaussian id goes to each of
+// its tiles' lists, at the item's scanned first position for that tile plus the entry's rank
+// among the item's earlier entries meeting the same tile (lanes below it in the tile's ballot
+// set; lane f carries tile f's next position across rounds), so each list keeps the depth order
+// of the coarse entries.  The tiles are visited in a uniform loop over the round's nonempty
+// (row, column) ballot pairs.  The first item of a supertile also writes its tiles' [start,
+// end) ranges.
+template <int WL, int HL>
 __global__ __launch_bounds__(256) void k_st_place(const DevSensor* __restrict__ sens,
                                                   const uint64_t* __restrict__ cvals, const int2* __restrict__ crange,
                                                   const int64_t* __restrict__ item_first,
-                                                  const uint2* __restrict__ item_st,
-                                                  const int64_t* __restrict__ scalars,
+                                                  const uint2* __restrict__ item_st, int64_t st_lo, int64_t st_hi,
                                                   const uint32_t* __restrict__ pos0, int64_t k_cap,
                                                   int32_t* __restrict__ gauss, int2* __restrict__ tile_range) {
   const int lane = threadIdx.x & 63;
@@ -897,8 +960,9 @@ __global__ __launch_bounds__(256) void k_st_place(const DevSensor* __restrict__ 
     const uint32_t start = pos0[count_slot(v, it, lane)];
     if (it == v.first_item) {   // the supertile's tile ranges (tiles inside the sensor's grid)
       const DevSensor& S = sens[v.s];
-      const int row = v.sr * kStSide + (lane >> 3), col = v.sc * kStSide + (lane & 7);
-      if (row < grid_rows(S) && col < grid_stride(S)) {
+      const int fy = lane >> 3, fx = lane & 7;
+      const int row = (v.sr << HL) + fy, col = (v.sc << WL) + fx;
+      if (fy < (1 << HL) && fx < (1 << WL) && row < grid_rows(S) && col < grid_stride(S)) {
         const int64_t t = (S.tile_base - sens[0].tile_base) + (int64_t)row * grid_stride(S) + col;
         const uint32_t end = pos0[v.first_item * 64 + (int64_t)(lane + 1) * v.n_items];
         tile_range[t] = make_int2((int)start, (int)end);
@@ -909,17 +973,17 @@ __global__ __launch_bounds__(256) void k_st_place(const DevSensor* __restrict__ 
     for (int k = 0; k < kItemRounds; ++k) {
       if (k * 64 >= v.cnt) break;   // uniform
       const uint32_t rows = entry_rows(e.val[k]), cols = entry_cols(e.val[k]);
-      RoundBallots b;
-      round_ballots(rows, cols, lane, b);
+      RoundBallots<WL, HL> b;
+      round_ballots<WL, HL>(rows, cols, lane, b);
       const int32_t gid = (int32_t)(uint32_t)e.val[k];
 #pragma unroll
-      for (int y = 0; y < kStSide; ++y) {
+      for (int y = 0; y < (1 << HL); ++y) {
         if (b.rb[y] == 0) continue;   // uniform
 #pragma unroll
-        for (int x = 0; x < kStSide; ++x) {
+        for (int x = 0; x < (1 << WL); ++x) {
           const uint64_t m = b.rb[y] & b.cb[x];
           if (m == 0) continue;   // uniform
-          const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)run, y * kStSide + x);
+          const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)run, y * 8 + x);
           const uint32_t p = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
           if (((rows >> y) & (cols >> x) & 1u) && (int64_t)p < k_cap) gauss[p] = gid;
         }
@@ -1180,21 +1244,38 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   // 5. items of <= kItemEntries entries per supertile; per item and tile the entry counts; their
   //    scan gives every tile's list range and every item its first positions; placement
   if ((e = device_scan<int64_t>(LoadItemCount{w.crange, n_st}, n_st + 1, w.item_first, (int64_t*)w.scan_part, s,
-                                ItemsVisit{v.sens, v.count, n_st, w.item_st, sc})) != hipSuccess)
+                                ItemsVisit{sc})) != hipSuccess)
     return e;
+  hipLaunchKernelGGL(k_item_table, dim3((unsigned)div_up(n_st, 4)), dim3(256), 0, s, v.sens, v.count,
+                     (const int64_t*)w.item_first, n_st, w.item_st);
+  // cameras precede lidars: supertiles [0, st_cam) have the camera shape, the rest the lidar one
+  int64_t st_cam = 0;
+  for (int i = 0; i < v.count; ++i)
+    if (v.host[i].kind == kCamera) st_cam += (int64_t)v.host[i].st_x * v.host[i].st_y;
   const int64_t icap = item_capacity(n_st, L.k_cap);
   int64_t grid = div_up(icap, 4);
   const int64_t gmax = (int64_t)(v.n_cu > 0 ? v.n_cu : 256) * 16;
   if (grid > gmax) grid = gmax;
-  hipLaunchKernelGGL(k_st_count, dim3((unsigned)grid), dim3(256), 0, s, v.sens, (const uint64_t*)cv[ccur],
-                     (const int2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, (const int64_t*)sc,
-                     w.xcount);
+  const uint64_t* cvs = cv[ccur];
+  if (st_cam > 0)
+    hipLaunchKernelGGL((k_st_count<kStLogCamera, kStLogCamera>), dim3((unsigned)grid), dim3(256), 0, s, v.sens, cvs,
+                       (const int2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, (int64_t)0, st_cam,
+                       w.xcount);
+  if (st_cam < n_st)
+    hipLaunchKernelGGL((k_st_count<kStLogLidar, kStLogLidar>), dim3((unsigned)grid), dim3(256), 0, s, v.sens, cvs,
+                       (const int2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, st_cam, n_st,
+                       w.xcount);
   if ((e = device_scan<uint32_t>(LoadCountX{w.xcount, sc + kScItemsX}, icap * 64 + 1, w.xcount, w.xpart, s,
                                  NoVisit(), sc + kScItemsX)) != hipSuccess)
     return e;
-  hipLaunchKernelGGL(k_st_place, dim3((unsigned)grid), dim3(256), 0, s, v.sens, (const uint64_t*)cv[ccur],
-                     (const int2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, (const int64_t*)sc,
-                     (const uint32_t*)w.xcount, L.k_cap, L.gauss, (int2*)L.tile_range);
+  if (st_cam > 0)
+    hipLaunchKernelGGL((k_st_place<kStLogCamera, kStLogCamera>), dim3((unsigned)grid), dim3(256), 0, s, v.sens, cvs,
+                       (const int2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, (int64_t)0, st_cam,
+                       (const uint32_t*)w.xcount, L.k_cap, L.gauss, (int2*)L.tile_range);
+  if (st_cam < n_st)
+    hipLaunchKernelGGL((k_st_place<kStLogLidar, kStLogLidar>), dim3((unsigned)grid), dim3(256), 0, s, v.sens, cvs,
+                       (const int2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, st_cam, n_st,
+                       (const uint32_t*)w.xcount, L.k_cap, L.gauss, (int2*)L.tile_range);
   // 6. lidar rays -> tiles; work items (lidar chunks, and camera tiles in the batched form)
   if (v.has_lidar || v.queue) {
     const int64_t bins = v.n_tiles + 1;

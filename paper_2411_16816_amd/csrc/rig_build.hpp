@@ -56,8 +56,9 @@ inline int build_camera(const SplatCamera& c, DevSensor& d) {
   d.tiles_x = (int32_t)tx;
   d.tiles_y = (int32_t)ty;
   d.n_tiles = d.tiles_x * d.tiles_y;
-  d.st_x = (d.tiles_x + kStSide - 1) / kStSide;
-  d.st_y = (d.tiles_y + kStSide - 1) / kStSide;
+  d.st_wl = d.st_hl = kStLogCamera;
+  d.st_x = (d.tiles_x + (1 << d.st_wl) - 1) >> d.st_wl;
+  d.st_y = (d.tiles_y + (1 << d.st_hl) - 1) >> d.st_hl;
   d.n_rays = (int64_t)c.width * c.height;
   return SPLAT_OK;
 }
@@ -104,8 +105,9 @@ inline int build_lidar(const SplatLidar& l, DevSensor& d) {
   d.los_eps = l.los_eps;
   d.ray_prio = l.ray_priority;
   d.n_tiles = l.n_az_tiles * l.n_el_tiles;
-  d.st_x = (d.m_az + kStSide - 1) / kStSide;
-  d.st_y = (d.m_el + kStSide - 1) / kStSide;
+  d.st_wl = d.st_hl = kStLogLidar;
+  d.st_x = (d.m_az + (1 << d.st_wl) - 1) >> d.st_wl;
+  d.st_y = (d.m_el + (1 << d.st_hl) - 1) >> d.st_hl;
   d.n_rays = l.n_rays;
   return SPLAT_OK;
 }

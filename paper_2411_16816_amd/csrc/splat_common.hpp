@@ -20,7 +20,10 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTStop = 1e-4f;
 constexpr int kBlock = 256;                  // lanes per rasterisation workgroup (4 x wave64)
-constexpr int kStSide = 8;                   // tiles per side of a binning supertile (8 x 8 = 64 tiles)
+// Binning supertiles (log2 of their width and height in tiles, at most 8 x 8): camera records
+// cover about six tiles per side, lidar records (azimuth x elevation) about two by four.
+constexpr int kStLogCamera = 3;
+constexpr int kStLogLidar = 2;
 
 enum SensorKind : int32_t { kCamera = 0, kLidar = 1 };
 
@@ -31,6 +34,7 @@ struct alignas(16) DevSensor {
   int32_t n_tiles;             // tiles of this sensor
   int64_t tile_base;           // global numbering inside the rig
   int32_t st_x, st_y;          // binning supertiles per row / column of the tile grid
+  int32_t st_wl, st_hl;        // log2 of a supertile's width / height in tiles
   int64_t st_base;             // first supertile (global numbering inside the rig)
   int64_t ray_base;
   int64_t feat_base;
