@@ -65,7 +65,8 @@ def parse():
                     help="instead of the headline step: the 60-sensor sweep workload (3M Gaussians, 48 lidar sweeps "
                          "+ 12 cameras) with per-sensor latency p50/p99 from in-kernel clocks")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=160, help="rays per sensor in the CPU oracle sample")
+    ap.add_argument("--cpu-rays", type=int, default=256, help="camera pixels in the CPU oracle sample")
+    ap.add_argument("--cpu-lidar-rays", type=int, default=64, help="lidar rays in the CPU oracle sample")
     ap.add_argument("--profile-steps", action="store_true", help="skip parity and CPU legs (for rocprofv3)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the scene's tile shapes")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -276,10 +277,10 @@ def main():
     batched_forms = [m for m in ("batched", "graph") if m in results]
     main_mode = max(batched_forms, key=lambda m: results[m]["value"]) if batched_forms else "plain"
     R = results[main_mode]
-    roof = roofline(results) if "batched" in results else None
+    roof = roofline(results, tiles) if "batched" in results else None
     cpu = None
     if not (args.no_cpu_baseline or args.profile_steps):
-        cpu = cpu_baseline(g, cam, lid, args.cpu_rays)
+        cpu = cpu_baseline(g, cam, lid, args.cpu_rays, args.cpu_lidar_rays)
     out = {
         "metric": METRIC, "value": round(R["value"], 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(R["ms"], 4), "higher_is_better": True, "scaling": "weak",
@@ -397,7 +398,7 @@ def check_parity(passes, rig, g):
 
 
 # kernel whose roofline is reported: the batched adjoint rasteriser, the longest kernel of the step
-ROOF_KERNEL = "k_raster_bwd_queue<16, false>"
+ROOF_KERNEL = "k_raster_bwd_queue<16, 8, false>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_raster_bwd_queue_headline.md")
 KERNEL_SOURCES = ["paper_2411_16816_amd/csrc/raster.hip", "paper_2411_16816_amd/csrc/splat_common.hpp",
                   "paper_2411_16816_amd/csrc/wave_ops.hpp", "paper_2411_16816_amd/csrc/kernels.hpp",
@@ -413,9 +414,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(tiles):
     """HBM bytes per launch of ROOF_KERNEL from the committed rocprofv3 --pmc summary, or None
-    when the summary is missing or was taken on other kernel sources."""
+    when the summary is missing, was taken on other kernel sources or on another tile layout."""
     try:
         txt = open(TRAFFIC_FILE).read()
     except OSError:
@@ -423,13 +424,15 @@ def measured_traffic():
     vals = dict(line[2:].split(": ", 1) for line in txt.splitlines() if line.startswith("- ") and ": " in line)
     if vals.get("source_hash", "").strip() != kernel_source_hash():
         return None
+    if vals.get("tiles", "").strip() != json.dumps(tiles, sort_keys=True):
+        return None
     try:
         return int(vals["traffic_bytes_per_launch"].strip())
     except (KeyError, ValueError):
         return None
 
 
-def roofline(results):
+def roofline(results, tiles):
     """VALU roofline of the batched adjoint rasteriser kernel.  Time: the kernel alone, from
     events the library records around its launch (splat_time_next_raster), averaged over the
     timed steps.  Algorithmic FLOP = evaluated pairs x FLOP per pair x 3."""
@@ -444,12 +447,12 @@ def roofline(results):
     t_bwd = r["kernel_ms"]["k_bwd_both"] * 1e-3
     t_fwd = r["kernel_ms"]["k_fwd_both"] * 1e-3
     ach = flop_bwd / t_bwd / 1e12
-    traffic = measured_traffic()
+    traffic = measured_traffic(tiles)
     return {"bound": "alu", "kernel": ROOF_KERNEL, "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
             "kernel_ms": round(t_bwd * 1e3, 4), "algorithmic_flop": int(flop_bwd), "evaluated_pairs": int(sum(pc)),
             "hbm_gbs": None if traffic is None else round(traffic / t_bwd / 1e9, 1),
-            "forward": {"kernel": "k_raster_fwd_queue<16, false>", "kernel_ms": round(t_fwd * 1e3, 4),
+            "forward": {"kernel": "k_raster_fwd_queue<16, 8, false>", "kernel_ms": round(t_fwd * 1e3, 4),
                         "achieved": round(flop_fwd / t_fwd / 1e12, 3),
                         "frac": round(flop_fwd / t_fwd / 1e12 / PEAK_FP32_TFLOPS, 4)}}
 
@@ -830,24 +833,117 @@ def cnn_bench(args, dev, cam):
             "parity": {"pixels": 576, "max_err_over_tol": round(worst, 4), "pass": bool(worst <= 1.0)}}
 
 
-def cpu_baseline(g, cam, lid, n_rays):
-    """The FP64 oracle, fwd + bwd (autograd), on a bounded seeded sample of rays per sensor."""
+# ---- CPU baseline: the FP64 oracle on the host's cores ----------------------------------------
+_ORC = {}
+
+
+def _oracle_init(n_gauss, barrier):
+    """Pool worker set-up: the seeded scene and its FP64 projections (one thread per worker)."""
+    import torch
+    from oracle import geometry as og
+    from scenes import synthetic as S
+    torch.set_num_threads(1)
+    t0 = time.perf_counter()
+    sc = S.headline(n=n_gauss)
+    p = og.Params.from_gaussians(sc.gaussians)
+    for k, sensor in enumerate((sc.cameras[0], sc.lidars[0])):
+        _ORC[k] = (sensor, og.project(p, sensor), p.features)
+    _ORC["setup_s"] = time.perf_counter() - t0
+    _ORC["barrier"] = barrier
+
+
+def _oracle_ready(_):
+    _ORC["barrier"].wait(timeout=600)   # every worker has finished its set-up
+    return _ORC["setup_s"]
+
+
+def _oracle_task(args):
+    """Render (and differentiate) one chunk of rays against every Gaussian; returns seconds."""
+    import dataclasses
     import torch
     from oracle import grad as ogr
-    from scenes import synthetic as S
+    from oracle import render as rd
+    k, ray_idx, with_grad, seed = args
+    sensor, proj, feats = _ORC[k]
+    rays = rd.lidar_rays(sensor, ray_idx) if k == 1 else rd.camera_rays(sensor, ray_idx)
+    t0 = time.perf_counter()
+    if with_grad:
+        # gradients with respect to the projected records and the features: the adjoint of the
+        # compositing per ray (the projection adjoint is a per-Gaussian cost, like the projection)
+        leaves = {f.name: getattr(proj, f.name).detach().clone().requires_grad_(True)
+                  for f in dataclasses.fields(proj)
+                  if isinstance(getattr(proj, f.name), torch.Tensor) and getattr(proj, f.name).is_floating_point()}
+        pl = dataclasses.replace(proj, **leaves)
+        fl = feats.detach().clone().requires_grad_(True)
+        out = rd.render(pl, sensor, fl, rays)
+        r = np.random.default_rng(seed)
+        n, C = len(ray_idx), sensor.n_channels
+        t = lambda a: torch.from_numpy(a)
+        loss = ogr.weighted_loss(out, t(r.normal(size=(n, C))), t(r.normal(size=n)), t(r.normal(size=n)),
+                                 t(r.normal(size=n)) if k == 1 else None)
+        loss.backward()
+    else:
+        with torch.no_grad():
+            rd.render(proj, sensor, feats, rays)
+    return time.perf_counter() - t0
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, cam, lid, n_cam_rays, n_lid_rays):
+    """The FP64 oracle (brute force over every Gaussian per ray) on the host's cores: a pool of
+    single-threaded worker processes, one per core of this process's CPU share, each holding
+    the seeded scene and its FP64 projections.  A seeded sample of camera pixels and lidar rays is
+    rendered forward only and then forward + backward (the compositing adjoint, down to the
+    projected records and the features); each sensor's wall-clock rate over the pool is combined
+    with the workload's mix of pixels and lidar rays into rays per second of a whole step.  The
+    per-Gaussian work (scene set-up, projection and its adjoint) is a fixed cost per step and is
+    reported, not included."""
+    import multiprocessing as mp
+    cores = len(os.sched_getaffinity(0))
+    share = os.environ.get("OMP_NUM_THREADS")
+    if share and share.isdigit() and int(share) > 0:
+        cores = min(cores, int(share))
     rng = np.random.default_rng(11)
-    total_rays = 0
-    t0 = time.time()
-    for k, sensor in enumerate((cam, lid)):
-        idx = np.sort(rng.choice(sensor.n_rays, size=n_rays, replace=False))
-        dF, dD, dA = S.upstream_grads(2000 + k, n_rays, sensor.n_channels)
-        dlos = np.random.default_rng(2100 + k).normal(size=n_rays) if k == 1 else None
-        ogr.reference_grads(g, sensor, idx, dF, dD, dA, dlos=dlos)
-        total_rays += n_rays
-    dt = time.time() - t0
-    return {"value": round(total_rays / dt / 1e6, 8), "unit": "Mrays/s", "cores": torch.get_num_threads(),
-            "kind": "oracle", "sample": f"{n_rays} camera pixels + {n_rays} lidar rays of the same workload, "
-                                        f"fwd+bwd (FP64 autograd), {dt:.1f}s"}
+    samples = {0: np.sort(rng.choice(cam.n_rays, size=n_cam_rays, replace=False)),
+               1: np.sort(rng.choice(lid.n_rays, size=n_lid_rays, replace=False))}
+    per_task = {0: 8, 1: 2}
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(cores)
+    rates = {}
+    with ctx.Pool(cores, initializer=_oracle_init, initargs=(g.n, barrier)) as pool:
+        setup = pool.map_async(_oracle_ready, range(cores), chunksize=1).get(timeout=900)
+        for with_grad in (False, True):
+            for k in (0, 1):
+                idx = samples[k]
+                tasks = [(k, idx[i:i + per_task[k]], with_grad, 100 + i) for i in range(0, len(idx), per_task[k])]
+                t0 = time.perf_counter()
+                pool.map_async(_oracle_task, tasks, chunksize=1).get(timeout=900)
+                rates[(k, with_grad)] = len(idx) / (time.perf_counter() - t0)
+    n_rays = {0: cam.n_rays, 1: lid.n_rays}
+    step_s = lambda wg: sum(n_rays[k] / rates[(k, wg)] for k in (0, 1))
+    total = cam.n_rays + lid.n_rays
+    fb = total / step_s(True) / 1e6
+    fwd = total / step_s(False) / 1e6
+    return {"value": round(fb, 8), "unit": "Mrays/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_cam_rays} camera pixels + {n_lid_rays} lidar rays of the workload, FP64 brute force, "
+                      f"{cores} single-threaded worker processes; rates per sensor weighted by the step's "
+                      f"{cam.n_rays} pixels and {lid.n_rays} lidar rays; per-Gaussian set-up and projection "
+                      f"({max(setup):.1f} s per worker) not included",
+            "forward_only": round(fwd, 8),
+            "per_sensor_rays_per_s": {"camera_fwd": round(rates[(0, False)], 3), "lidar_fwd": round(rates[(1, False)], 3),
+                                      "camera_fwd_bwd": round(rates[(0, True)], 3),
+                                      "lidar_fwd_bwd": round(rates[(1, True)], 3)},
+            "cpu_model": _cpu_model()}
 
 
 if __name__ == "__main__":

@@ -15,14 +15,19 @@ Candidates:
             and with pairs of them merged (the elevation boundaries are the caller's, so tiles
             can be merged but not split).
 
-This is a setup-time search: it allocates, synchronises the device and takes seconds.  Results
-are cached per process, keyed by the sensor's shape (resolution / beams x azimuth steps, tile
-layout, channel count) and the Gaussian count rounded to a power of two.
+This is a setup-time search: it allocates, synchronises the device and takes seconds.  Each
+candidate is timed as the median of REPEATS runs of STEPS steps.  Results are kept in a JSON
+file (autotune_cache.json beside this module, or the path in SPLAT_AUTOTUNE_CACHE), keyed by
+the GPU architecture, the sensor class and shape (resolution / beams x azimuth steps, tile
+layout, channel count) and the Gaussian count rounded to a power of two, so that later runs
+take the stored layout without searching.
 """
 from __future__ import annotations
 
 import copy
+import json
 import math
+import os
 from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -32,17 +37,59 @@ from . import binding as B
 
 CAMERA_TILES = [(16, 16), (32, 8), (8, 32), (64, 4)]
 KEEP_MARGIN = 0.03   # another layout must be this much faster to replace the caller's
+STEPS = 8            # steps per timing run of a candidate
+REPEATS = 3          # timing runs per candidate (the median is kept)
+CACHE_PATH = os.environ.get("SPLAT_AUTOTUNE_CACHE",
+                            os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json"))
 
-_cache: Dict[tuple, tuple] = {}
+_cache: Dict[str, list] = {}
+_loaded = False
+
+
+def _arch() -> str:
+    try:
+        return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    except Exception:   # no device: only the key's arch field is affected
+        return "unknown"
+
+
+def _load_cache():
+    global _loaded
+    if _loaded:
+        return
+    _loaded = True
+    try:
+        with open(CACHE_PATH) as f:
+            data = json.load(f)
+        if isinstance(data, dict):
+            _cache.update({k: v for k, v in data.items() if isinstance(v, list)})
+    except (OSError, ValueError):
+        pass
+
+
+def _store_cache():
+    try:
+        tmp = CACHE_PATH + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(dict(sorted(_cache.items())), f, indent=1)
+        os.replace(tmp, CACHE_PATH)
+    except OSError:   # a read-only tree keeps the results for this process only
+        pass
+
+
+def _key(parts) -> str:
+    return "|".join(str(p) for p in (_arch(),) + tuple(parts))
 
 
 def _camera_key(cam, n):
-    return ("camera", int(cam.width), int(cam.height), int(cam.n_channels), 1 << max(0, int(n - 1).bit_length()))
+    return _key(("camera", f"{int(cam.width)}x{int(cam.height)}", f"tile{int(cam.tile_w)}x{int(cam.tile_h)}",
+                 f"c{int(cam.n_channels)}", f"n{1 << max(0, int(n - 1).bit_length())}"))
 
 
 def _lidar_key(lid, n):
-    return ("lidar", int(lid.n_rays), int(lid.tile_az), int(lid.n_az_tiles), len(lid.elev_bounds),
-            int(lid.n_channels), 1 << max(0, int(n - 1).bit_length()))
+    return _key(("lidar", f"rays{int(lid.n_rays)}", f"az{int(lid.tile_az)}x{int(lid.n_az_tiles)}",
+                 f"el{len(lid.elev_bounds) - 1}", f"c{int(lid.n_channels)}",
+                 f"n{1 << max(0, int(n - 1).bit_length())}"))
 
 
 def camera_candidates(cam) -> List:
@@ -94,22 +141,27 @@ def _time_step(sensor, is_camera: bool, g: B.GaussTensors, steps: int, warmup: i
         raise B.SplatError(f"autotune: intersection overflow ({st.n_isect} > {st.k_cap})")
     s = torch.cuda.current_stream()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(s)
-    for _ in range(steps):
-        pipe.run()
-    b.record(s)
-    torch.cuda.synchronize()
+    runs = []
+    for _ in range(REPEATS):
+        a.record(s)
+        for _ in range(steps):
+            pipe.run()
+        b.record(s)
+        torch.cuda.synchronize()
+        runs.append(a.elapsed_time(b) / steps)
     pipe.close()
-    return a.elapsed_time(b) / steps
+    return float(np.median(runs))
 
 
-def tune_sensor(sensor, is_camera: bool, g: B.GaussTensors, steps: int = 3, warmup: int = 1,
+def tune_sensor(sensor, is_camera: bool, g: B.GaussTensors, steps: int = STEPS, warmup: int = 2,
                 log=None) -> Tuple[object, List[Tuple[tuple, float]]]:
-    """Fastest tile layout for one sensor; returns (sensor copy with that layout, timings)."""
+    """Fastest tile layout for one sensor; returns (sensor copy with that layout, timings; empty
+    when the layout came from the cache)."""
+    _load_cache()
     key = _camera_key(sensor, g.n) if is_camera else _lidar_key(sensor, g.n)
     cands = camera_candidates(sensor) if is_camera else lidar_candidates(sensor)
     if key in _cache:
-        shape = _cache[key]
+        shape = tuple(_cache[key])
         for c in cands:
             if _shape(c, is_camera) == shape:
                 return c, []
@@ -127,7 +179,8 @@ def tune_sensor(sensor, is_camera: bool, g: B.GaussTensors, steps: int = 3, warm
     for c, (sh, ms) in zip(cands, timings):
         if sh == mine and ms <= best_ms * (1.0 + KEEP_MARGIN):
             best = c
-    _cache[key] = _shape(best, is_camera)
+    _cache[key] = list(_shape(best, is_camera))
+    _store_cache()
     return best, timings
 
 
@@ -137,7 +190,7 @@ def _shape(s, is_camera: bool) -> tuple:
     return (int(s.tile_az), len(s.elev_bounds) - 1)
 
 
-def tune_rig(cameras: Sequence, lidars: Sequence, g: B.GaussTensors, steps: int = 3, warmup: int = 1,
+def tune_rig(cameras: Sequence, lidars: Sequence, g: B.GaussTensors, steps: int = STEPS, warmup: int = 2,
              log=None) -> Tuple[list, list, dict]:
     """Tile layouts for every sensor of a rig (each tuned alone).  Returns new camera and lidar
     lists and a report {sensor index: (chosen shape, [(shape, ms), ...])}."""

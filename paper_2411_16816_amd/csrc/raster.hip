@@ -235,9 +235,10 @@ struct FwdCount {
   }
 };
 
-template <int CMAX, bool LIDAR, bool TILE>
-__device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, int64_t tile, int pos, FwdSmem<CMAX>& sm,
+template <int CMAX, bool LIDAR, bool TILE, typename SM>
+__device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, int64_t tile, int pos, SM& sm,
                                          FwdCount& cnt) {
+  static_assert(sizeof(sm.f) / sizeof(sm.f[0]) >= kBlock * (CMAX / 4), "feature staging");
   RayCtx c;
   setup_ray<LIDAR>(a, tile, pos, c);
   float T = 1.f, D = 0.f, med = 0.f, los = 0.f;
@@ -343,10 +344,13 @@ __device__ __forceinline__ bool item_is_lidar(const RasterArgs& a, int64_t tile)
   return tile >= a.n_tiles || a.sens[sensor_of_tile(a.sens, a.count, tile)].kind == kLidar;
 }
 
-// persistent form: workgroups drain the cost-ordered queue of camera tiles and lidar chunks
-template <int CMAX, bool TILE>
+constexpr int cmax_max(int a, int b) { return a > b ? a : b; }
+
+// persistent form: workgroups drain the cost-ordered queue of camera tiles and lidar chunks;
+// camera items are compiled for the cameras' channel bucket CMC, lidar items for the lidars' CML
+template <int CMC, int CML, bool TILE>
 __global__ __launch_bounds__(kBlock) void k_raster_fwd_queue(RasterArgs a, FwdOut o, int32_t* counter) {
-  __shared__ FwdSmem<CMAX> sm;
+  __shared__ FwdSmem<cmax_max(CMC, CML)> sm;
   __shared__ int s_slot;
   FwdCount cnt;
   const int n_items = a.n_work[0];
@@ -354,8 +358,8 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd_queue(RasterArgs a, FwdOu
     const int it = next_item(counter, &s_slot);
     if (it >= n_items) break;
     const int2 w = a.work[it];
-    if (item_is_lidar(a, w.x)) fwd_item<CMAX, true, TILE>(a, o, w.x, w.y, sm, cnt);
-    else fwd_item<CMAX, false, TILE>(a, o, w.x, 0, sm, cnt);
+    if (item_is_lidar(a, w.x)) fwd_item<CML, true, TILE>(a, o, w.x, w.y, sm, cnt);
+    else fwd_item<CMC, false, TILE>(a, o, w.x, 0, sm, cnt);
   }
   cnt.flush(o);
 }
@@ -373,6 +377,7 @@ constexpr int kBwdBatch = 128;
 
 template <int CMAX>
 struct BwdSmem {
+  static constexpr int kCmax = CMAX;   // the launch's channel bucket: sets the gradient row stride
   float4 mv[kBwdBatch], cn[kBwdBatch], box[kBwdBatch];
   float2 dv[kBwdBatch];
   float4 f[kBwdBatch * (CMAX / 4)];
@@ -382,10 +387,12 @@ struct BwdSmem {
   float toff;   // the item's time-offset gradient, summed over its wavefronts
 };
 
-template <int CMAX, bool LIDAR, bool TILE>
-__device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, int64_t tile, int pos, BwdSmem<CMAX>& sm) {
+template <int CMAX, bool LIDAR, bool TILE, typename SM>
+__device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, int64_t tile, int pos, SM& sm) {
   using SH = BwdShape<CMAX>;
   static_assert(SH::V <= 64, "channels");
+  static_assert(sizeof(sm.acc) / sizeof(sm.acc[0]) >= SH::V, "accumulator rows");
+  static_assert(sizeof(sm.f) / sizeof(sm.f[0]) >= kBwdBatch * (CMAX / 4), "feature staging");
   float4* s_mv = sm.mv;
   float4* s_cn = sm.cn;
   float4* s_box = sm.box;
@@ -432,9 +439,15 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
   const int64_t tile_local = tile - (S.tile_base - a.sens[0].tile_base);
   // a lidar tile with more rays than one item holds is shared by several items
   const bool split = LIDAR && (a.ray_range[tile].y - a.ray_range[tile].x > SPLAT_RAYS_PER_ITEM);
-  constexpr int SW = slot_stride(CMAX);
+  // gradient rows have the stride of the launch's bucket (the workspace's), whatever this
+  // item's own channel bucket
+  constexpr int SW = slot_stride(SM::kCmax);
+  static_assert(SM::kCmax >= CMAX, "row stride");
+  // values reduced across the wavefront: a camera has no range-velocity term (value 9)
+  constexpr int VR = LIDAR ? SH::V : SH::V - 1;
   bool my_store;
-  const int my_idx = scatter_slot<SH::V>(lane, my_store);
+  const int my_slot = scatter_slot<VR>(lane, my_store);
+  const int my_idx = (!LIDAR && my_slot >= kNV - 1) ? my_slot + 1 : my_slot;   // accumulator row
   float S_dot = 0.f;   // sum_c buf_c dF_c, the feature part of the colour behind this Gaussian
   float tacc = 0.f;    // camera: dL/dt of this ray's pairs (mean at time t moves with the velocity)
   for (int64_t b0 = c.start + ((n_proc - 1) / kBwdBatch) * kBwdBatch; b0 >= c.start; b0 -= kBwdBatch) {
@@ -478,8 +491,9 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
       S_dot = SPLAT_FMA(a_eff, fd - S_dot, S_dot);
       bufD = SPLAT_FMA(a_eff, gv - bufD, bufD);
       // line-of-sight sum: its upstream gradient adds directly to the alpha of Gaussians in front
-      const float dlos_a = (LIDAR && gv < c.los_thr) ? dlos : 0.f;
-      const float dalpha = act ? (T * acc + dA * Tf * ra + dlos_a) : 0.f;
+      float dalpha = T * acc + dA * Tf * ra;
+      if (LIDAR) dalpha += (gv < c.los_thr) ? dlos : 0.f;
+      dalpha = act ? dalpha : 0.f;
       const float dg = w * dD;
       const float d_oeff = e.clamped ? 0.f : dalpha * e.G;
       const float dsig = e.clamped ? 0.f : -dalpha * e.alpha;
@@ -496,7 +510,15 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
       v[7] = d_oeff;
       v[8] = dg;
       v[9] = LIDAR ? dg * c.t : 0.f;
-      const float r = wave_reduce_scatter<SH::V>(v);
+      float r;
+      if constexpr (LIDAR) {
+        r = wave_reduce_scatter<VR>(v);
+      } else {   // value 9 is zero for a camera: reduce the others
+        float u[VR];
+#pragma unroll
+        for (int k = 0; k < VR; ++k) u[k] = v[k < kNV - 1 ? k : k + 1];
+        r = wave_reduce_scatter<VR>(u);
+      }
       if (my_store) atomicAdd(&s_acc[my_idx][j], r);
       if (lane == 0) s_used[j] = 1;
     }
@@ -556,18 +578,18 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(RasterArgs a, BwdIn b) {
 
 // at least 4 waves per SIMD (at most 128 VGPRs): the register allocator otherwise drifts above
 // that bound as the item code grows, and the lost occupancy costs more than it saves
-template <int CMAX, bool TILE>
+template <int CMC, int CML, bool TILE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void k_raster_bwd_queue(RasterArgs a, BwdIn b, int32_t* counter) {
-  __shared__ BwdSmem<CMAX> sm;
+  __shared__ BwdSmem<cmax_max(CMC, CML)> sm;
   __shared__ int s_slot;
   const int n_items = a.n_work[0];
   for (;;) {
     const int it = next_item(counter, &s_slot);
     if (it >= n_items) break;
     const int2 w = a.work[it];
-    if (item_is_lidar(a, w.x)) bwd_item<CMAX, true, TILE>(a, b, w.x, w.y, sm);
-    else bwd_item<CMAX, false, TILE>(a, b, w.x, 0, sm);
+    if (item_is_lidar(a, w.x)) bwd_item<CML, true, TILE>(a, b, w.x, w.y, sm);
+    else bwd_item<CMC, false, TILE>(a, b, w.x, 0, sm);
   }
 }
 
@@ -623,18 +645,32 @@ static unsigned persistent_grid(K kernel, const CallView& v, int64_t items) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
-template <int CMAX, bool TILE>
+template <int CMC, int CML, bool TILE>
 static void fwd_queue_launch(const CallView& v, int64_t items, hipStream_t s, const RasterArgs& a, const FwdOut& o,
                              int32_t* counter) {
-  auto k = k_raster_fwd_queue<CMAX, TILE>;
+  auto k = k_raster_fwd_queue<CMC, CML, TILE>;
   hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items)), dim3(kBlock), 0, s, a, o, counter);
 }
 
-template <int CMAX, bool TILE>
+template <int CMC, int CML, bool TILE>
 static void bwd_queue_launch(const CallView& v, int64_t items, hipStream_t s, const RasterArgs& a, const BwdIn& b,
                              int32_t* counter) {
-  auto k = k_raster_bwd_queue<CMAX, TILE>;
+  auto k = k_raster_bwd_queue<CMC, CML, TILE>;
   hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items)), dim3(kBlock), 0, s, a, b, counter);
+}
+
+// Channel buckets of the persistent kernels: the cameras' and the lidars' (a call's lidars with
+// 8 channels beside wider cameras get the 8-channel code; other mixes use one bucket for both).
+static void queue_buckets(const CallView& v, int& cmc, int& cml) {
+  int c_cam = 0, c_lid = 0;
+  for (int i = 0; i < v.count; ++i) {
+    const DevSensor& d = v.host[i];
+    if (d.kind == kCamera) c_cam = d.n_ch > c_cam ? d.n_ch : c_cam;
+    else c_lid = d.n_ch > c_lid ? d.n_ch : c_lid;
+  }
+  cmc = cmax_bucket(v.c_max);
+  cml = cmc;
+  if (c_lid > 0 && cmax_bucket(c_lid) == 8 && cmc > 8) cml = 8;
 }
 
 hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
@@ -652,19 +688,22 @@ hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const S
     hipError_t e = launch_fill_i32(counter, 1, 0, s);
     if (e != hipSuccess) return e;
     const bool tile = support == SPLAT_SUPPORT_TILE;
-#define FWDQ_CASE(CM)                                                         \
-  case CM:                                                                    \
-    if (tile) fwd_queue_launch<CM, true>(v, items, s, a, o, counter);         \
-    else fwd_queue_launch<CM, false>(v, items, s, a, o, counter);             \
-    break;
+    int cmc, cml;
+    queue_buckets(v, cmc, cml);
+#define FWDQ_CASE(CM, CL)                                                     \
+  if (cmc == CM && cml == CL) {                                               \
+    if (tile) fwd_queue_launch<CM, CL, true>(v, items, s, a, o, counter);     \
+    else fwd_queue_launch<CM, CL, false>(v, items, s, a, o, counter);         \
+  }
     if (timer.start) (void)hipEventRecord(timer.start, s);
-    switch (cm) {
-      FWDQ_CASE(4)
-      FWDQ_CASE(8)
-      FWDQ_CASE(16)
-      FWDQ_CASE(32)
-      FWDQ_CASE(48)
-    }
+    FWDQ_CASE(4, 4)
+    FWDQ_CASE(8, 8)
+    FWDQ_CASE(16, 16)
+    FWDQ_CASE(16, 8)
+    FWDQ_CASE(32, 32)
+    FWDQ_CASE(32, 8)
+    FWDQ_CASE(48, 48)
+    FWDQ_CASE(48, 8)
 #undef FWDQ_CASE
     if (timer.stop) (void)hipEventRecord(timer.stop, s);
     return hipGetLastError();
@@ -706,19 +745,22 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
     hipError_t e = launch_fill_i32(counter, 1, 0, s);
     if (e != hipSuccess) return e;
     const bool tile = support == SPLAT_SUPPORT_TILE;
-#define BWDQ_CASE(CM)                                                         \
-  case CM:                                                                    \
-    if (tile) bwd_queue_launch<CM, true>(v, items, s, a, b, counter);         \
-    else bwd_queue_launch<CM, false>(v, items, s, a, b, counter);             \
-    break;
+    int cmc, cml;
+    queue_buckets(v, cmc, cml);
+#define BWDQ_CASE(CM, CL)                                                     \
+  if (cmc == CM && cml == CL) {                                               \
+    if (tile) bwd_queue_launch<CM, CL, true>(v, items, s, a, b, counter);     \
+    else bwd_queue_launch<CM, CL, false>(v, items, s, a, b, counter);         \
+  }
     if (timer.start) (void)hipEventRecord(timer.start, s);
-    switch (cm) {
-      BWDQ_CASE(4)
-      BWDQ_CASE(8)
-      BWDQ_CASE(16)
-      BWDQ_CASE(32)
-      BWDQ_CASE(48)
-    }
+    BWDQ_CASE(4, 4)
+    BWDQ_CASE(8, 8)
+    BWDQ_CASE(16, 16)
+    BWDQ_CASE(16, 8)
+    BWDQ_CASE(32, 32)
+    BWDQ_CASE(32, 8)
+    BWDQ_CASE(48, 48)
+    BWDQ_CASE(48, 8)
 #undef BWDQ_CASE
     if (timer.stop) (void)hipEventRecord(timer.stop, s);
     return hipGetLastError();

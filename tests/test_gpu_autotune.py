@@ -1,5 +1,7 @@
 """Tile-shape autotuner: every candidate layout renders the same result (BOX candidate rule), so
 the tuner's choice is free; it must return one of the candidates."""
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -72,9 +74,12 @@ def test_candidate_layouts_render_identically(kind):
             assert np.linalg.norm(x - y) <= 1e-5 * np.linalg.norm(y), (kind, name)
 
 
-def test_tune_rig_picks_a_candidate():
+def test_tune_rig_picks_a_candidate(tmp_path, monkeypatch):
     b = _binding()
     from paper_2411_16816_amd import autotune as at
+    monkeypatch.setattr(at, "CACHE_PATH", str(tmp_path / "autotune_cache.json"))
+    monkeypatch.setattr(at, "_cache", {})
+    monkeypatch.setattr(at, "_loaded", False)
     g, cam, lid = _scene()
     G = b.GaussTensors.from_numpy(g)
     cams, lids, report = at.tune_rig([cam], [lid], G, steps=2, warmup=1)
@@ -85,3 +90,11 @@ def test_tune_rig_picks_a_candidate():
     cams2, lids2, report2 = at.tune_rig([cam], [lid], G)
     assert report2[0][1] == [] and report2[1][1] == []
     assert (cams2[0].tile_w, cams2[0].tile_h) == (cams[0].tile_w, cams[0].tile_h)
+    # persisted: a fresh process state reads the same choices back from the JSON file
+    stored = json.loads((tmp_path / "autotune_cache.json").read_text())
+    assert len(stored) == 2 and all(k.startswith(at._arch() + "|") for k in stored)
+    monkeypatch.setattr(at, "_cache", {})
+    monkeypatch.setattr(at, "_loaded", False)
+    cams3, lids3, report3 = at.tune_rig([cam], [lid], G)
+    assert report3[0][1] == [] and report3[1][1] == []
+    assert at._shape(lids3[0], False) == at._shape(lids[0], False)
