@@ -125,7 +125,9 @@ def main():
                  "lidar_el_tiles": int(lid.n_el_tiles)}
         tune_report = {("camera" if k == 0 else "lidar"): [[list(sh), round(ms, 4)] for sh, ms in v[1]]
                        for k, v in rep.items()}
-        log(f"autotuned tiles {tiles} in {time.time() - t1:.1f}s")
+        tune_report["source"] = "search" if any(v[1] for v in rep.values()) else \
+            f"cache ({os.path.relpath(autotune.CACHE_PATH, ROOT)})"
+        log(f"autotuned tiles {tiles} in {time.time() - t1:.1f}s ({tune_report['source']})")
     rig = B.Rig([cam], [lid], dev)
     stream = torch.cuda.current_stream()
     stages = ["project", "bin_sort", "raster_fwd", "raster_bwd"]
@@ -835,6 +837,7 @@ def cnn_bench(args, dev, cam):
 
 # ---- CPU baseline: the FP64 oracle on the host's cores ----------------------------------------
 _ORC = {}
+MAX_ORACLE_WORKERS = 15
 
 
 def _oracle_init(n_gauss, barrier):
@@ -913,6 +916,9 @@ def cpu_baseline(g, cam, lid, n_cam_rays, n_lid_rays):
     share = os.environ.get("OMP_NUM_THREADS")
     if share and share.isdigit() and int(share) > 0:
         cores = min(cores, int(share))
+    # this process holds the GPU; the workers get none (hidden before they start), and with
+    # this process they stay within 16 processes even if a worker opened the device
+    cores = max(1, min(cores, MAX_ORACLE_WORKERS))
     rng = np.random.default_rng(11)
     samples = {0: np.sort(rng.choice(cam.n_rays, size=n_cam_rays, replace=False)),
                1: np.sort(rng.choice(lid.n_rays, size=n_lid_rays, replace=False))}
@@ -920,7 +926,19 @@ def cpu_baseline(g, cam, lid, n_cam_rays, n_lid_rays):
     ctx = mp.get_context("spawn")
     barrier = ctx.Barrier(cores)
     rates = {}
-    with ctx.Pool(cores, initializer=_oracle_init, initargs=(g.n, barrier)) as pool:
+    hidden = ("HIP_VISIBLE_DEVICES", "ROCR_VISIBLE_DEVICES", "CUDA_VISIBLE_DEVICES")
+    saved = {k: os.environ.get(k) for k in hidden}
+    for k in hidden:
+        os.environ[k] = ""
+    try:
+        pool = ctx.Pool(cores, initializer=_oracle_init, initargs=(g.n, barrier))
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    with pool:
         setup = pool.map_async(_oracle_ready, range(cores), chunksize=1).get(timeout=900)
         for with_grad in (False, True):
             for k in (0, 1):
