@@ -517,22 +517,24 @@ inline int head_blocks(int64_t n) {
 }
 inline int64_t input_bwd_blocks(int64_t n) { return (n + 255) / 256; }
 
+// base == nullptr: sizes only (every pointer stays null; no arithmetic on the null base)
 inline CnnWs carve_cnn(void* base, int W, int H) {
   CnnWs w;
   const int64_t n = (int64_t)W * H;
   const size_t act = ((size_t)n * kCC * sizeof(float) + 255) / 256 * 256;
   size_t off = 0;
   char* b = (char*)base;
-  for (int i = 0; i < 6; ++i, off += act) w.act[i] = (float*)(b + off);
-  for (int i = 0; i < 3; ++i, off += act) w.g[i] = (float*)(b + off);
-  w.frag = (float*)(b + off);
+  auto at = [&](size_t o) { return b ? (float*)(b + o) : nullptr; };
+  for (int i = 0; i < 6; ++i, off += act) w.act[i] = at(off);
+  for (int i = 0; i < 3; ++i, off += act) w.g[i] = at(off);
+  w.frag = at(off);
   off += (size_t)kFrag * sizeof(float);
   size_t part = (size_t)wgrad_blocks(W, H) * kWOut;
   const size_t hp = (size_t)head_blocks(n) * kHeadOut;
   const size_t ep = (size_t)input_bwd_blocks(n) * 8;
   part = part > hp ? part : hp;
   part = part > ep ? part : ep;
-  w.partial = (float*)(b + off);
+  w.partial = at(off);
   off += (part * sizeof(float) + 255) / 256 * 256;
   w.bytes = off;
   return w;

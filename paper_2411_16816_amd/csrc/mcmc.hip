@@ -252,8 +252,8 @@ inline RelocWs carve_reloc(void* base, int64_t n) {
   RelocWs r;
   char* b = (char*)base;
   size_t off = 0;
-  auto take = [&](size_t bytes) {
-    char* p = b + off;
+  auto take = [&](size_t bytes) {   // base == nullptr: sizes only, pointers stay null
+    char* p = b ? b + off : nullptr;
     off += (bytes + 255) / 256 * 256;
     return p;
   };
