@@ -65,6 +65,7 @@ def parse():
                     help="instead of the headline step: the 60-sensor sweep workload (3M Gaussians, 48 lidar sweeps "
                          "+ 12 cameras) with per-sensor latency p50/p99 from in-kernel clocks")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the per-config (C1-C4) plain / batched lines")
     ap.add_argument("--cpu-rays", type=int, default=256, help="camera pixels in the CPU oracle sample")
     ap.add_argument("--cpu-lidar-rays", type=int, default=64, help="lidar rays in the CPU oracle sample")
     ap.add_argument("--profile-steps", action="store_true", help="skip parity and CPU legs (for rocprofv3)")
@@ -305,6 +306,8 @@ def main():
     }
     for m, r in results.items():
         out["modes"][m]["step_ms"] = r["step_ms"]
+    if not (args.no_configs or args.profile_steps):
+        out["configs"] = {f"C{k}": config_bench(args, dev, k) for k in (1, 2, 3, 4)}
     if not args.no_compose:
         out["compose"] = compose_bench(args, dev)
         out["points_to_rays"] = points_bench(args, dev, lid)
@@ -534,6 +537,111 @@ def c5_latency(args, dev):
                       "latency_ms": {k: {"p50": pct(v, 50), "p99": pct(v, 99), "n": len(v)}
                                      for k, v in lat[phase].items()}}
         log(f"C5 {phase}: {ms[phase]:.3f} ms/step; latency {out[phase]['latency_ms']}")
+    return out
+
+
+CONFIG_NAMES = {1: "C1 plain lidar forward: 4096 Gaussians, 32 x 1024 global-shutter lidar",
+                2: "C2 camera fwd+bwd: 500k Gaussians (road slab), 1920x1080 RS camera",
+                3: "C3 lidar fwd+bwd: 2M Gaussians, 128 x 2048 lidar, 100 ms RS sweep, 15 m/s ego",
+                4: "C4 rig fwd+bwd: 1.5M Gaussians, 6 RS cameras (2x 1920x1080, 2x 1280x720, 2x 960x640) "
+                   "+ 64 x 1800 lidar"}
+
+
+def config_bench(args, dev, k, parity_rays=8):
+    """Config k timed in both forms: plain (one call per stage per sensor) and batched (one call
+    per stage for all sensors, persistent rasterisers); fwd+bwd per step (C1: forward only, as
+    the config states).  Median and p99 over the timed steps; both forms checked against the
+    oracle on the same sampled rays, forward outputs bit-equal between the forms and gradients
+    within 1e-4."""
+    import torch
+    from oracle import render as rd
+    from paper_2411_16816_amd import binding as B
+    from scenes import synthetic as S
+    sc = S.make_config(k)
+    g = sc.gaussians
+    sensors = list(sc.cameras) + list(sc.lidars)
+    G = B.GaussTensors.from_numpy(g, dev)
+    rig = B.Rig(sc.cameras, sc.lidars, dev)
+    fwd_only = k == 1
+    stream = torch.cuda.current_stream()
+    mk = lambda: torch.cuda.Event(enable_timing=True)
+    rng = np.random.default_rng(900 + k)
+    ups = []
+    for s_ in sensors:
+        ups.append((rng.normal(size=s_.n_rays * s_.n_channels).astype(np.float32),
+                    (0.1 * rng.normal(size=s_.n_rays)).astype(np.float32), rng.normal(size=s_.n_rays).astype(np.float32)))
+    prng = np.random.default_rng(1900 + k)
+    pidx = [np.sort(prng.choice(s_.n_rays, size=min(parity_rays, s_.n_rays), replace=False)) for s_ in sensors]
+    refs = [rd.render_sensor(g, s_, idx) for s_, idx in zip(sensors, pidx)]
+    out = {"workload": CONFIG_NAMES[k], "gaussians": g.n, "rays_per_step": int(sum(s_.n_rays for s_ in sensors)),
+           "step": "forward" if fwd_only else "fwd+bwd"}
+    snaps = {}
+    for mode in ("plain", "batched"):
+        if mode == "plain":
+            passes = [B.SensorPass(rig, i, 1, g.n, 1, dev) for i in range(len(sensors))]
+            pups = [[torch.from_numpy(a).to(dev) for a in u] for u in ups]
+        else:
+            passes = [B.SensorPass(rig, 0, len(sensors), g.n, 1, dev, batched=True)]
+            pups = [[torch.from_numpy(np.concatenate([u[j] for u in ups])).to(dev) for j in range(3)]]
+        K = [sp.fit_capacity(G, 1.1) for sp in passes]
+        grads = B.zeros_like_grads(G)
+
+        def step():
+            for sp, u in zip(passes, pups):
+                sp.project(G)
+                sp.bin_sort()
+                sp.raster_fwd(G)
+                if not fwd_only:
+                    sp.raster_bwd(G, *u, grads)
+
+        for _ in range(max(1, args.warmup)):
+            step()
+        torch.cuda.synchronize()
+        evs = [mk() for _ in range(args.steps + 1)]
+        evs[0].record(stream)
+        for i in range(args.steps):
+            step()
+            evs[i + 1].record(stream)
+        torch.cuda.synchronize()
+        per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+        med = float(np.median(per))
+        # parity: the outputs of the last step against the oracle on the sampled rays
+        worst, near, outs = 0.0, 0, []
+        for si, (s_, idx, ref) in enumerate(zip(sensors, pidx, refs)):
+            sp = passes[si] if mode == "plain" else passes[0]
+            kk = 0 if mode == "plain" else si
+            rs, fs, C = sp.sensor_slices(kk)
+            o = sp.outputs()
+            F = o["feat"][fs].reshape(-1, C)[idx].cpu().numpy()
+            D = o["depth"][rs][idx].cpu().numpy()
+            A = o["alpha"][rs][idx].cpu().numpy()
+            ok = ~ref["near"]
+            near += int((~ok).sum())
+            for a, r in ((F, ref["F"].numpy()), (D, ref["D"].numpy()), (A, ref["A"].numpy())):
+                err = np.abs(a[ok] - r[ok]) / (1e-5 + 1e-4 * np.abs(r[ok]))
+                worst = max(worst, float(err.max()) if err.size else 0.0)
+            outs.append((o["feat"][fs].clone(), o["depth"][rs].clone(), o["alpha"][rs].clone()))
+        snaps[mode] = (outs, {n_: getattr(grads, n_).double().clone() for n_ in GRAD_FIELDS
+                              if getattr(grads, n_) is not None})
+        out[mode] = {"ms_per_step": round(med, 4), "p99_ms": round(float(np.percentile(per, 99)), 4),
+                     "Mrays_per_s": round(out["rays_per_step"] / (med * 1e-3) / 1e6, 3), "intersections": K,
+                     "calls_per_stage": len(passes),
+                     "parity": {"rays": int(sum(len(i) for i in pidx)), "near_excluded": near,
+                                "max_err_over_tol": round(worst, 4), "pass": bool(worst <= 1.0)}}
+        log(f"{CONFIG_NAMES[k].split(':')[0]} {mode}: {med:.3f} ms/step, {out[mode]['Mrays_per_s']} Mrays/s, "
+            f"parity {out[mode]['parity']}")
+        del passes, grads
+        torch.cuda.empty_cache()
+    fwd_equal = all(torch.equal(a, b) for x, y in zip(snaps["plain"][0], snaps["batched"][0]) for a, b in zip(x, y))
+    worst = 0.0
+    for n_ in snaps["plain"][1]:
+        x, y = snaps["batched"][1][n_], snaps["plain"][1][n_]
+        ny = float(y.norm())
+        if ny > 0:
+            worst = max(worst, float((x - y).norm()) / ny)
+    out["batched_over_plain"] = round(out["plain"]["ms_per_step"] / out["batched"]["ms_per_step"], 4)
+    out["agreement"] = {"forward_bit_equal": bool(fwd_equal), "grad_rel_err": float(f"{worst:.3g}"),
+                        "pass": bool(fwd_equal and worst <= 1e-4)}
     return out
 
 

@@ -16,7 +16,7 @@ from oracle import grad as ogr
 from oracle import render as rd
 from oracle import tiles as tl
 from scenes import synthetic as S
-from tests.gpu_helpers import assert_grad_close, gpu_outputs, last_ids_gpu, rtol_check, tile_lists_gpu
+from tests.gpu_helpers import grad_mismatch, assert_grad_close, gpu_outputs, last_ids_gpu, rtol_check, tile_lists_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -502,6 +502,49 @@ def test_backward_lidar():
 def test_backward_lidar_split_tiles():
     """64 x 8 = 512 rays per tile: every tile is two work items, whose gradients add atomically."""
     _grad_check("lidar", 9, lidar_tile_az=64)
+
+
+def test_split_tile_atomics_match_fixed_order():
+    """The adjoint's atomic path (lidar tiles of 512 rays, two work items each, adding their
+    per-Gaussian rows with global atomics) against its fixed-order path (tiles of 128 rays, one
+    item each, rows summed in a fixed order) on the same rays and Gaussians: the rendered
+    outputs are identical (the tile layout only changes the candidate search) and the gradients
+    agree to rounding.  Two runs of the atomic path agree to rounding as well."""
+    b = _binding()
+    rng = np.random.default_rng(23)
+    n = 2000
+    mu = np.stack([rng.uniform(-12, 12, n), rng.uniform(-12, 12, n), rng.uniform(-1.5, 1.5, n)], 1)
+    g = S.random_gaussians(rng, mu, 16, rgb=True, moving_frac=0.5, log_scale_mean=-0.6)
+    G = b.GaussTensors.from_numpy(g)
+    up = np.random.default_rng(24)
+    runs = []
+    for tile_az in (16, 64, 64):
+        lid = S.make_lidar((0, 0, 0), 0.0, 16, -15.0, 15.0, 256, tile_az=tile_az, tile_el=8, t_sweep=0.1,
+                           ego_vel_world=(10.0, 1.0, 0), feat_offset=3, n_channels=8)
+        rays_per_tile = tile_az * 8
+        print(f"[split] tile_az {tile_az}: {rays_per_tile} rays per tile", flush=True)
+        rig = b.Rig([], [lid])
+        sp = b.SensorPass(rig, 0, 1, g.n, 1)
+        sp.fit_capacity(G)
+        sp.render(G)
+        if not runs:
+            R, C = lid.n_rays, lid.n_channels
+            ups = [torch.from_numpy(a).cuda() for a in (up.normal(size=R * C).astype(np.float32),
+                                                        (0.1 * up.normal(size=R)).astype(np.float32),
+                                                        up.normal(size=R).astype(np.float32))]
+        grads = b.zeros_like_grads(G)
+        sp.raster_bwd(G, *ups, grads)
+        torch.cuda.synchronize()
+        runs.append((gpu_outputs(sp, 0), {name: getattr(grads, name).cpu().numpy() for name in geo.Params.names}))
+    (o_ref, g_ref), (o_split, g_split), (o_again, g_again) = runs
+    for key in ("F", "D", "A", "T"):
+        np.testing.assert_array_equal(o_split[key], o_ref[key], err_msg=key)
+        np.testing.assert_array_equal(o_again[key], o_ref[key], err_msg=key)
+    for name in geo.Params.names:
+        assert np.abs(g_ref[name]).max() > 0, name
+        for other in (g_split, g_again):
+            bad = grad_mismatch(other[name], g_ref[name], rtol=1e-4, afloor=1e-5)
+            assert not bad.any(), (name, int(bad.sum()))
 
 
 def test_autograd_function_camera():
