@@ -176,22 +176,38 @@ __device__ __forceinline__ void setup_ray(const RasterArgs& a, int64_t tile, int
   // it; a work item of dropped rays renders an empty list
   const bool empty = LIDAR && (c.invalid_bin || c.dropped);
   const int2 tr = a.tile_range[(LIDAR && c.invalid_bin) ? 0 : tile];
-  c.start = empty ? 0 : tr.x;
-  c.end = empty ? 0 : tr.y;
+  // the same for every lane of the work item: say so, so that the list walks count in scalars
+  c.start = __builtin_amdgcn_readfirstlane(empty ? 0 : tr.x);
+  c.end = __builtin_amdgcn_readfirstlane(empty ? 0 : tr.y);
 }
+
+// One staged Gaussian in LDS, contiguous so that one address reaches all of it (float4 units):
+//   [0] mean at t = 0 and its image-plane velocity (mx, my, vx, vy)
+//   [1] conic in conic_exp2 form and opacity (A, B, C, o)
+//   [2] BOX (x0, y0, x1, y1)
+//   [3] depth value and rate, B / 2 and 2 vy (d0, dr, B/2, 2 vy); the last two serve the adjoint
+//   [4 ...] features, CMAX channels (zero past the sensor's)
+// Every lane reads the same record at a time (an LDS broadcast, free of bank conflicts).  The
+// record stride is an odd number of float4 so that the staging writes, one record per lane,
+// spread over all banks.
+constexpr int rec4(int cmax) { return (4 + cmax / 4) | 1; }
 
 template <int CMAX>
 __device__ __forceinline__ void stage_batch(const RasterArgs& a, const RayCtx& c, int64_t b0, int64_t b1,
-                                            float4* s_mv, float4* s_cn, float4* s_box, float2* s_dv, float4* s_f) {
+                                            float4* rec) {
   const int tid = threadIdx.x;
   const int64_t idx = b0 + tid;
   if (idx < b1) {
     const int64_t g = a.gauss[idx];
-    const int64_t rec = (int64_t)c.s * a.N + g;
-    s_mv[tid] = a.mv[rec];
-    s_cn[tid] = a.cn[rec];
-    s_box[tid] = a.box[rec];
-    s_dv[tid] = a.dv[rec];
+    const int64_t r = (int64_t)c.s * a.N + g;
+    float4* o = rec + tid * rec4(CMAX);
+    const float4 mv = a.mv[r];
+    const float4 ce = conic_exp2(a.cn[r]);
+    const float2 dv = a.dv[r];
+    o[0] = mv;
+    o[1] = ce;
+    o[2] = a.box[r];
+    o[3] = make_float4(dv.x, dv.y, 0.5f * ce.y, 2.f * mv.w);
     const DevSensor& S = a.sens[c.s];
     const float* f = a.features + g * a.c_total + S.feat_off;
 #pragma unroll
@@ -201,33 +217,44 @@ __device__ __forceinline__ void stage_batch(const RasterArgs& a, const RayCtx& c
       v.y = (4 * c4 + 1 < c.C) ? f[4 * c4 + 1] : 0.f;
       v.z = (4 * c4 + 2 < c.C) ? f[4 * c4 + 2] : 0.f;
       v.w = (4 * c4 + 3 < c.C) ? f[4 * c4 + 3] : 0.f;
-      s_f[tid * (CMAX / 4) + c4] = v;
+      o[4 + c4] = v;
     }
   }
+}
+
+// wavefront-uniform tests on a lane predicate (scalar compares of the lane mask)
+__device__ __forceinline__ uint64_t lane_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ bool wave_any(bool p) { return lane_mask(p) != 0; }
+
+// Lane mask of a camera's box_contains over the wavefront, combined from one mask per compare:
+// the mask of a single compare is its result register, while that of a combined predicate is
+// rebuilt with two vector instructions.
+__device__ __forceinline__ uint64_t camera_box_mask(float px, float py, float4 b) {
+  return lane_mask(py >= b.y) & lane_mask(py < b.w) & lane_mask(px >= b.x) & lane_mask(px < b.z);
 }
 
 // ------------------------------------------------------------------------------------------
 // forward
 // ------------------------------------------------------------------------------------------
+// Gaussians staged per batch of the forward walk (one per lane of the first kFwdBatch lanes).
+// Half the workgroup: the smaller LDS footprint lets register use, not LDS, bound occupancy.
+constexpr int kFwdBatch = 128;
+
 template <int CMAX>
 struct FwdSmem {
-  float4 mv[kBlock], cn[kBlock], box[kBlock];
-  float2 dv[kBlock];
-  float4 f[kBlock * (CMAX / 4)];
+  float4 rec[kFwdBatch * rec4(CMAX)];
 };
 
-// Counters of a workgroup's forward items, per lane, summed over every item the workgroup
-// renders and added to the status once per wavefront at the end of the kernel (a persistent
-// workgroup renders many items; per-item global atomics on two addresses would contend).
+// Counters of a workgroup's forward items, summed over every item the workgroup renders and
+// added to the status once per wavefront at the end of the kernel (a persistent workgroup
+// renders many items; per-item global atomics on two addresses would contend).  `pairs` is the
+// wavefront's count (uniform over its lanes), `stopped` a per-lane count.
 struct FwdCount {
   unsigned long long pairs = 0, stopped = 0;
   __device__ void flush(const FwdOut& o) {
     if (!o.n_pairs) return;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-      pairs += __shfl_xor(pairs, d, 64);
-      stopped += __shfl_xor(stopped, d, 64);
-    }
+    for (int d = 32; d >= 1; d >>= 1) stopped += __shfl_xor(stopped, d, 64);
     if ((threadIdx.x & 63) == 0) {
       if (pairs) atomicAdd(o.n_pairs, pairs);
       if (stopped) atomicAdd(o.n_stopped, stopped);
@@ -235,10 +262,12 @@ struct FwdCount {
   }
 };
 
-template <int CMAX, bool LIDAR, bool TILE, typename SM>
+// COUNT: also count the evaluated pairs (the counting launch; the others leave the counter out)
+template <int CMAX, bool LIDAR, bool TILE, bool COUNT, typename SM>
 __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, int64_t tile, int pos, SM& sm,
                                          FwdCount& cnt) {
-  static_assert(sizeof(sm.f) / sizeof(sm.f[0]) >= kBlock * (CMAX / 4), "feature staging");
+  constexpr int R4 = rec4(CMAX);
+  static_assert(sizeof(sm.rec) / sizeof(sm.rec[0]) >= kFwdBatch * R4, "record staging");
   RayCtx c;
   setup_ray<LIDAR>(a, tile, pos, c);
   float T = 1.f, D = 0.f, med = 0.f, los = 0.f;
@@ -246,61 +275,80 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
 #pragma unroll
   for (int k = 0; k < CMAX; ++k) F[k] = 0.f;
   int last = 0;
-  unsigned pairs = 0;
-  bool done = !c.valid;
-  bool stopped = false;
-  bool med_set = false;
-  for (int64_t b0 = c.start; b0 < c.end; b0 += kBlock) {
-    if (__syncthreads_count(!done) == 0) break;
-    const int64_t b1 = (b0 + kBlock < c.end) ? b0 + kBlock : c.end;
-    stage_batch<CMAX>(a, c, b0, b1, sm.mv, sm.cn, sm.box, sm.dv, sm.f);
+  unsigned long long pairs = 0;
+  unsigned stopped = 0;
+  // A lane's state is all numbers, no flags carried from one Gaussian to the next (the lane
+  // masks of such flags cost scalar instructions on every iteration): `on` scales the lane's
+  // alphas, 1 while it renders and 0 once it has stopped (or has no ray), so that it blends
+  // nothing more.  `live` is the wavefront's mask of lanes with on = 1.
+  float on = c.valid ? 1.f : 0.f;
+  uint64_t live = lane_mask(c.valid);
+  for (int64_t b0 = c.start; b0 < c.end; b0 += kFwdBatch) {
+    if (__syncthreads_count(on > 0.f) == 0) break;
+    const int64_t b1 = (b0 + kFwdBatch < c.end) ? b0 + kFwdBatch : c.end;
+    if (kFwdBatch == kBlock || threadIdx.x < kFwdBatch) stage_batch<CMAX>(a, c, b0, b1, sm.rec);
     __syncthreads();
     const int nb = (int)(b1 - b0);
-    // Branch-free over the lanes: a lane's decisions (box, skip, stop) become selects, and a
-    // lane that does not blend the Gaussian adds exact zeros.  Only wavefront-uniform branches
-    // remain: stop when every lane has stopped, skip a Gaussian that misses every live lane.
-    for (int j = 0; j < nb; ++j) {
-      if (__ballot(!done) == 0) break;
-      const float4 bx = sm.box[j];
-      const float bxa[4] = {bx.x, bx.y, bx.z, bx.w};
-      bool act = !done && (TILE || box_contains(LIDAR, c.px, c.py, bxa));
-      if (__ballot(act) == 0) continue;
-      const float4 m = sm.mv[j], q = sm.cn[j];
-      const float mva[4] = {m.x, m.y, m.z, m.w}, cna[4] = {q.x, q.y, q.z, q.w};
+    // Branch-free over the lanes: a lane's decisions (box, alpha threshold, stop) become selects,
+    // and a lane that does not blend the Gaussian adds exact zeros.  Only wavefront-uniform
+    // branches remain, tested on lane masks of single compares: skip a Gaussian that no live
+    // lane blends, leave the batch once every lane has stopped (a finished wavefront still
+    // takes part in the workgroup's barriers).
+    for (int j = 0; live != 0 && j < nb; ++j) {
+      const float4* r = sm.rec + j * R4;
+      const float4 bx = r[2], m = r[0], ce = r[1];
+      bool in = true;
+      uint64_t cand = live;
+      if (!TILE) {
+        const float bxa[4] = {bx.x, bx.y, bx.z, bx.w};
+        in = box_contains(LIDAR, c.px, c.py, bxa);
+        cand = LIDAR ? cand & lane_mask(in) : cand & camera_box_mask(c.px, c.py, bx);
+      }
+      if (cand == 0) continue;
+      if (COUNT) pairs += (unsigned long long)__builtin_popcountll(cand);
+      float4 f[CMAX / 4];
+#pragma unroll
+      for (int c4 = 0; c4 < CMAX / 4; ++c4) f[c4] = r[4 + c4];
+      const float2 d = *reinterpret_cast<const float2*>(r + 3);
       PairEval e;
-      eval_pair(LIDAR, c.px, c.py, c.t, mva, cna, e);
-      pairs += act ? 1u : 0u;
-      act = act && e.alpha >= kAlphaMin;
-      const float Tn = T * (1.f - e.alpha);
-      const bool stop = act && Tn < kTStop;
-      done = done || stop;
-      stopped = stopped || stop;
-      act = act && !stop;
-      const float w = act ? e.alpha * T : 0.f;
-      const float2 d = sm.dv[j];
+      eval_pair(LIDAR, c.px, c.py, c.t, m, ce, e);
+      const float alpha = clamp_alpha(e.oG) * on;
+      const bool pass = alpha >= kAlphaMin;
+      const uint64_t blend = cand & lane_mask(pass);
+      if (blend == 0) continue;
+      const float Tn = SPLAT_FMA(-alpha, T, T);
+      const bool low = Tn < kTStop;
+      const uint64_t stop_m = blend & lane_mask(low);
+      const bool act = in && pass && !low;
+      const float w = act ? alpha * T : 0.f;
       const float gv = LIDAR ? SPLAT_FMA(d.y, c.t, d.x) : d.x;
 #pragma unroll
       for (int c4 = 0; c4 < CMAX / 4; ++c4) {
-        const float4 f = sm.f[j * (CMAX / 4) + c4];
-        F[4 * c4 + 0] = SPLAT_FMA(w, f.x, F[4 * c4 + 0]);
-        F[4 * c4 + 1] = SPLAT_FMA(w, f.y, F[4 * c4 + 1]);
-        F[4 * c4 + 2] = SPLAT_FMA(w, f.z, F[4 * c4 + 2]);
-        F[4 * c4 + 3] = SPLAT_FMA(w, f.w, F[4 * c4 + 3]);
+        F[4 * c4 + 0] = SPLAT_FMA(w, f[c4].x, F[4 * c4 + 0]);
+        F[4 * c4 + 1] = SPLAT_FMA(w, f[c4].y, F[4 * c4 + 1]);
+        F[4 * c4 + 2] = SPLAT_FMA(w, f[c4].z, F[4 * c4 + 2]);
+        F[4 * c4 + 3] = SPLAT_FMA(w, f[c4].w, F[4 * c4 + 3]);
       }
       D = SPLAT_FMA(w, gv, D);
-      if (LIDAR) los += (act && gv < c.los_thr) ? e.alpha : 0.f;   // line-of-sight sum
       if (LIDAR) {
-        const bool hit = act && !med_set && Tn < 0.5f;
-        med = hit ? gv : med;
-        med_set = med_set || hit;
+        los += (act && gv < c.los_thr) ? alpha : 0.f;   // line-of-sight sum
+        // median range: the Gaussian across which the transmittance falls below 1/2 (T only
+        // decreases, so this happens at most once)
+        med = (act && T >= 0.5f && Tn < 0.5f) ? gv : med;
       }
       T = act ? Tn : T;
       last = act ? (int)(b0 + j - c.start) + 1 : last;
+      if (stop_m) {   // uniform: some lane stops here
+        const bool stop = in && pass && low;
+        on = stop ? 0.f : on;
+        stopped += stop ? 1u : 0u;
+        live &= ~stop_m;
+      }
     }
   }
   __syncthreads();   // LDS is reused by the next item of a persistent workgroup
   cnt.pairs += pairs;
-  cnt.stopped += stopped ? 1u : 0u;
+  cnt.stopped += stopped;
   if (!(LIDAR && c.invalid_bin)) stamp_done(o.sensor_done, c.s);
   if (!c.valid) return;
   float* fo = o.feat + c.feat_off;
@@ -322,11 +370,13 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(RasterArgs a, FwdOut o) {
   __shared__ FwdSmem<CMAX> sm;
   FwdCount cnt;
   if (!LIDAR) {
-    fwd_item<CMAX, false, TILE>(a, o, blockIdx.x, 0, sm, cnt);
+    if (o.n_pairs) fwd_item<CMAX, false, TILE, true>(a, o, blockIdx.x, 0, sm, cnt);
+    else fwd_item<CMAX, false, TILE, false>(a, o, blockIdx.x, 0, sm, cnt);
   } else {
     if ((int64_t)blockIdx.x >= (int64_t)a.n_work[0]) return;
     const int2 w = a.work[blockIdx.x];
-    fwd_item<CMAX, true, TILE>(a, o, w.x, w.y, sm, cnt);
+    if (o.n_pairs) fwd_item<CMAX, true, TILE, true>(a, o, w.x, w.y, sm, cnt);
+    else fwd_item<CMAX, true, TILE, false>(a, o, w.x, w.y, sm, cnt);
   }
   cnt.flush(o);
 }
@@ -354,12 +404,22 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd_queue(RasterArgs a, FwdOu
   __shared__ int s_slot;
   FwdCount cnt;
   const int n_items = a.n_work[0];
-  for (;;) {
-    const int it = next_item(counter, &s_slot);
-    if (it >= n_items) break;
-    const int2 w = a.work[it];
-    if (item_is_lidar(a, w.x)) fwd_item<CML, true, TILE>(a, o, w.x, w.y, sm, cnt);
-    else fwd_item<CMC, false, TILE>(a, o, w.x, 0, sm, cnt);
+  if (o.n_pairs) {
+    for (;;) {
+      const int it = next_item(counter, &s_slot);
+      if (it >= n_items) break;
+      const int2 w = a.work[it];
+      if (item_is_lidar(a, w.x)) fwd_item<CML, true, TILE, true>(a, o, w.x, w.y, sm, cnt);
+      else fwd_item<CMC, false, TILE, true>(a, o, w.x, 0, sm, cnt);
+    }
+  } else {
+    for (;;) {
+      const int it = next_item(counter, &s_slot);
+      if (it >= n_items) break;
+      const int2 w = a.work[it];
+      if (item_is_lidar(a, w.x)) fwd_item<CML, true, TILE, false>(a, o, w.x, w.y, sm, cnt);
+      else fwd_item<CMC, false, TILE, false>(a, o, w.x, 0, sm, cnt);
+    }
   }
   cnt.flush(o);
 }
@@ -378,26 +438,35 @@ constexpr int kBwdBatch = 128;
 template <int CMAX>
 struct BwdSmem {
   static constexpr int kCmax = CMAX;   // the launch's channel bucket: sets the gradient row stride
-  float4 mv[kBwdBatch], cn[kBwdBatch], box[kBwdBatch];
-  float2 dv[kBwdBatch];
-  float4 f[kBwdBatch * (CMAX / 4)];
+  float4 rec[kBwdBatch * rec4(CMAX)];
   float acc[BwdShape<CMAX>::V][kBwdBatch];
   int used[kBwdBatch];
   int maxlast;
   float toff;   // the item's time-offset gradient, summed over its wavefronts
 };
 
+// The adjoint reduces the geometric values of a pair in the basis of the conic_exp2 form, where
+// they cost the fewest operations; these constants turn a reduced value into the gradient of
+//   0, 1  the mean at t = 0,      2, 3  the velocity,     4, 5, 6  the conic (a, b, c),
+//   7     the opacity o,          8, 9  the depth value and its rate (lidar: range, v_r),
+// (with u = A dx + B dy the value 0 sums dL/ds (2 A dx + B dy) / ln 2, value 1 sums
+// dL/ds (B dx / 2 + C dy) / ln 2, values 4-6 sum dL/ds (dx^2, dx dy, dy^2) / ln 2, where
+// s = log2 exp(-sigma); dx = px - mx gives the sign of the mean's terms).
+__device__ __forceinline__ constexpr float value_scale(int k) {
+  return (k == 0 || k == 2) ? -kLn2
+       : (k == 1 || k == 3) ? -2.f * kLn2
+       : (k == 4 || k == 6) ? -0.5f
+       : (k == 5) ? -1.f
+       : 1.f;
+}
+
 template <int CMAX, bool LIDAR, bool TILE, typename SM>
 __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, int64_t tile, int pos, SM& sm) {
   using SH = BwdShape<CMAX>;
+  constexpr int R4 = rec4(CMAX);
   static_assert(SH::V <= 64, "channels");
   static_assert(sizeof(sm.acc) / sizeof(sm.acc[0]) >= SH::V, "accumulator rows");
-  static_assert(sizeof(sm.f) / sizeof(sm.f[0]) >= kBwdBatch * (CMAX / 4), "feature staging");
-  float4* s_mv = sm.mv;
-  float4* s_cn = sm.cn;
-  float4* s_box = sm.box;
-  float2* s_dv = sm.dv;
-  float4* s_f = sm.f;
+  static_assert(sizeof(sm.rec) / sizeof(sm.rec[0]) >= kBwdBatch * R4, "record staging");
   auto& s_acc = sm.acc;
   int* s_used = sm.used;
   RayCtx c;
@@ -420,6 +489,7 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
     for (int k = 0; k < CMAX; ++k)
       if (k < c.C) dF[k] = g[k];
   }
+  const float dATf = dA * Tf;
   if (tid == 0) {
     sm.maxlast = 0;
     sm.toff = 0.f;
@@ -452,32 +522,39 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
   float tacc = 0.f;    // camera: dL/dt of this ray's pairs (mean at time t moves with the velocity)
   for (int64_t b0 = c.start + ((n_proc - 1) / kBwdBatch) * kBwdBatch; b0 >= c.start; b0 -= kBwdBatch) {
     const int64_t b1 = (b0 + kBwdBatch < c.start + n_proc) ? b0 + kBwdBatch : c.start + n_proc;
-    if (tid < kBwdBatch) stage_batch<CMAX>(a, c, b0, b1, s_mv, s_cn, s_box, s_dv, s_f);
+    if (tid < kBwdBatch) stage_batch<CMAX>(a, c, b0, b1, sm.rec);
     __syncthreads();
     const int nb = (int)(b1 - b0);
     for (int j = nb - 1; j >= 0; --j) {
+      const float4* r = sm.rec + j * R4;
       const int pos = (int)(b0 + j - c.start);
-      bool act = c.valid && pos < last_l;
-      const float4 bx = s_box[j];
-      const float bxa[4] = {bx.x, bx.y, bx.z, bx.w};
-      if (!TILE) act = act && box_contains(LIDAR, c.px, c.py, bxa);
-      if (__ballot(act) == 0) continue;   // uniform over the wavefront
-      const float4 m = s_mv[j], q = s_cn[j];
-      const float mva[4] = {m.x, m.y, m.z, m.w}, cna[4] = {q.x, q.y, q.z, q.w};
+      // an invalid lane has last_l = 0
+      bool act = pos < last_l;
+      uint64_t cand = lane_mask(act);
+      if (!TILE) {
+        const float4 bx = r[2];
+        const float bxa[4] = {bx.x, bx.y, bx.z, bx.w};
+        act = act && box_contains(LIDAR, c.px, c.py, bxa);
+        cand = LIDAR ? lane_mask(act) : cand & camera_box_mask(c.px, c.py, bx);
+      }
+      if (cand == 0) continue;
+      const float4 m = r[0], ce = r[1];
       PairEval e;
-      eval_pair(LIDAR, c.px, c.py, c.t, mva, cna, e);
-      act = act && e.alpha >= kAlphaMin;
-      if (__ballot(act) == 0) continue;   // uniform over the wavefront
+      eval_pair(LIDAR, c.px, c.py, c.t, m, ce, e);
+      const float alpha = clamp_alpha(e.oG);
+      const bool pass = alpha >= kAlphaMin;
+      if ((cand & lane_mask(pass)) == 0) continue;
+      act = act && pass;
       // branch-free: inactive lanes use alpha_eff = 0 and contribute exact zeros
-      const float a_eff = act ? e.alpha : 0.f;
-      const float ra = act ? __builtin_amdgcn_rcpf(1.f - e.alpha) : 1.f;
+      const float a_eff = act ? alpha : 0.f;
+      const float ra = act ? __builtin_amdgcn_rcpf(1.f - alpha) : 1.f;
       T = T * ra;                         // transmittance in front of this Gaussian
       const float w = a_eff * T;
       float v[SH::V];
       float fd = 0.f;
 #pragma unroll
       for (int c4 = 0; c4 < CMAX / 4; ++c4) {
-        const float4 f = s_f[j * (CMAX / 4) + c4];
+        const float4 f = r[4 + c4];
         fd = SPLAT_FMA(f.x, dF[4 * c4 + 0], fd);
         fd = SPLAT_FMA(f.y, dF[4 * c4 + 1], fd);
         fd = SPLAT_FMA(f.z, dF[4 * c4 + 2], fd);
@@ -485,41 +562,42 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
       }
 #pragma unroll
       for (int k = 0; k < CMAX; ++k) v[kNV + k] = w * dF[k];
-      const float2 d = s_dv[j];
+      const float4 d = r[3];
       const float gv = LIDAR ? SPLAT_FMA(d.y, c.t, d.x) : d.x;
-      const float acc = (fd - S_dot) + (gv - bufD) * dD;
-      S_dot = SPLAT_FMA(a_eff, fd - S_dot, S_dot);
-      bufD = SPLAT_FMA(a_eff, gv - bufD, bufD);
+      const float fdS = fd - S_dot, gvB = gv - bufD;
+      const float acc = SPLAT_FMA(gvB, dD, fdS);
+      S_dot = SPLAT_FMA(a_eff, fdS, S_dot);
+      bufD = SPLAT_FMA(a_eff, gvB, bufD);
       // line-of-sight sum: its upstream gradient adds directly to the alpha of Gaussians in front
-      float dalpha = T * acc + dA * Tf * ra;
+      float dalpha = SPLAT_FMA(T, acc, dATf * ra);
       if (LIDAR) dalpha += (gv < c.los_thr) ? dlos : 0.f;
       dalpha = act ? dalpha : 0.f;
+      // Eq. alpha's clamp cuts the dependence on G; ga = dL/ds / ln 2 with s = log2 G
+      const bool clamped = e.oG > kAlphaMax;
+      const float ga = clamped ? 0.f : dalpha * e.oG;
       const float dg = w * dD;
-      const float d_oeff = e.clamped ? 0.f : dalpha * e.G;
-      const float dsig = e.clamped ? 0.f : -dalpha * e.alpha;
-      const float ddx = (q.x * e.dx + q.y * e.dy) * dsig;
-      const float ddy = (q.y * e.dx + q.z * e.dy) * dsig;
-      if (!LIDAR) tacc = SPLAT_FMA(-ddx, m.z, SPLAT_FMA(-ddy, m.w, tacc));
-      v[0] = -ddx;
-      v[1] = -ddy;
-      v[2] = -ddx * c.t;
-      v[3] = -ddy * c.t;
-      v[4] = 0.5f * e.dx * e.dx * dsig;
-      v[5] = e.dx * e.dy * dsig;
-      v[6] = 0.5f * e.dy * e.dy * dsig;
-      v[7] = d_oeff;
+      v[0] = ga * SPLAT_FMA(ce.x, e.dx, e.tx);
+      v[1] = ga * SPLAT_FMA(d.z, e.dx, e.cy);
+      v[2] = v[0] * c.t;
+      v[3] = v[1] * c.t;
+      const float gx = ga * e.dx;
+      v[4] = gx * e.dx;
+      v[5] = gx * e.dy;
+      v[6] = (ga * e.dy) * e.dy;
+      v[7] = clamped ? 0.f : dalpha * e.G;
       v[8] = dg;
       v[9] = LIDAR ? dg * c.t : 0.f;
-      float r;
+      if (!LIDAR) tacc = SPLAT_FMA(v[0], m.z, SPLAT_FMA(v[1], d.w, tacc));
+      float r_own;
       if constexpr (LIDAR) {
-        r = wave_reduce_scatter<VR>(v);
+        r_own = wave_reduce_scatter<VR>(v);
       } else {   // value 9 is zero for a camera: reduce the others
         float u[VR];
 #pragma unroll
         for (int k = 0; k < VR; ++k) u[k] = v[k < kNV - 1 ? k : k + 1];
-        r = wave_reduce_scatter<VR>(u);
+        r_own = wave_reduce_scatter<VR>(u);
       }
-      if (my_store) atomicAdd(&s_acc[my_idx][j], r);
+      if (my_store) atomicAdd(&s_acc[my_idx][j], r_own);
       if (lane == 0) s_used[j] = 1;
     }
     __syncthreads();
@@ -535,14 +613,14 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
         for (int q = 0; q < SW / 4; ++q) {
           float x[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) x[u] = (4 * q + u < SH::V) ? s_acc[4 * q + u][tid] : 0.f;
+          for (int u = 0; u < 4; ++u) x[u] = (4 * q + u < SH::V) ? s_acc[4 * q + u][tid] * value_scale(4 * q + u) : 0.f;
           row[q] = make_float4(x[0], x[1], x[2], x[3]);
         }
         b.flags[p] = 1;
       } else {
         float* gp = b.g2d + rec * kNV;
 #pragma unroll
-        for (int k = 0; k < kNV; ++k) atomicAdd(gp + k, s_acc[k][tid]);
+        for (int k = 0; k < kNV; ++k) atomicAdd(gp + k, s_acc[k][tid] * value_scale(k));
         float* fp = b.dfeat + g * a.c_total + S.feat_off;
 #pragma unroll
         for (int k = 0; k < CMAX; ++k)
@@ -555,6 +633,7 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
     __syncthreads();
   }
   if (!LIDAR && b.d_toff) {   // uniform: the item's time-offset gradient, one global add
+    tacc *= -kLn2;            // the velocity terms of values 0 and 1 (see value_scale)
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) tacc += __shfl_xor(tacc, d, 64);
     if (lane == 0) atomicAdd(&sm.toff, tacc);

@@ -556,10 +556,6 @@ HD void gaussian_M_vjp(const QuatRot& qr, const float s[3], const float dM[9], f
 // ------------------------------------------------------------------------------------------
 // Per (ray, Gaussian) evaluation shared bit-for-bit by the forward and adjoint rasterisers.
 // ------------------------------------------------------------------------------------------
-struct PairEval {
-  float dx, dy, sigma, G, alpha;
-  bool clamped;
-};
 
 // BOX candidacy of a camera pixel / lidar ray (azimuth modular, see lidar_rect)
 HD bool box_contains(bool lidar, float px, float py, const float bx[4]) {
@@ -580,36 +576,53 @@ HD bool box_contains(bool lidar, float px, float py, const float bx[4]) {
 #define SPLAT_FMA(a, b, c) fmaf(a, b, c)
 #endif
 
-HD float fast_exp_neg(float sigma) {
+constexpr float kLog2e = 1.44269504088896340736f;
+constexpr float kLn2 = 0.693147180559945309417f;
+
+// The conic (a, b, c) of Eq. delta in base-2 form: exp(-sigma) = 2^s with
+// s = A dx^2 + B dx dy + C dy^2, A = -a log2(e) / 2, B = -b log2(e), C = -c log2(e) / 2.
+// The rasterisers stage this form (and the opacity in .w), so one exp2 evaluates a Gaussian.
+HD float4 conic_exp2(float4 cn) {
+  return make_float4(cn.x * (-0.5f * kLog2e), cn.y * -kLog2e, cn.z * (-0.5f * kLog2e), cn.w);
+}
+
+HD float exp2_fast(float s) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  return __expf(-sigma);
+  return __builtin_amdgcn_exp2f(s);
 #else
-  return expf(-sigma);
+  return exp2f(s);
 #endif
 }
 
-// Eq. delta, Eq. alpha.  Explicit fma so forward and adjoint evaluate identical arithmetic.
-HD void eval_pair(bool lidar, float px, float py, float t, const float mv[4], const float cn[4], PairEval& e) {
-  float mx = SPLAT_FMA(mv[2], t, mv[0]);
-  float my = SPLAT_FMA(mv[3], t, mv[1]);
-  float dx = px - mx;
-  float dy = py - my;
+struct PairEval {
+  float dx, dy;   // ray minus the mean at the ray's time (lidar azimuth reduced to [-pi, pi))
+  float tx;       // A dx + B dy
+  float cy;       // C dy
+  float G;        // exp(-sigma), Eq. delta
+  float oG;       // opacity x G: Eq. alpha before its clamp
+};
+
+// Eq. delta and the unclamped Eq. alpha for a ray at (px, py, t) and a Gaussian whose mean
+// moves as (mv.x + mv.z t, mv.y + mv.w t), with its conic in conic_exp2 form.  Explicit fma so
+// that the forward and the adjoint evaluate identical arithmetic.
+HD void eval_pair(bool lidar, float px, float py, float t, float4 mv, float4 ce, PairEval& e) {
+  float dx = px - SPLAT_FMA(mv.z, t, mv.x);
+  const float dy = py - SPLAT_FMA(mv.w, t, mv.y);
   if (lidar) {
     // azimuth difference reduced to [-pi, pi): the rolling-shutter shift v t of a Gaussian close
     // to the sensor can span several turns, so the reduction is modular, not a single wrap
-    const float k = floorf((dx + kPi) * kInvTwoPi);
+    const float k = floorf(SPLAT_FMA(dx, kInvTwoPi, 0.5f));
     dx = SPLAT_FMA(-k, kTwoPi, dx);
   }
-  float q = SPLAT_FMA(cn[0] * dx, dx, cn[2] * dy * dy);
-  float sigma = SPLAT_FMA(cn[1] * dx, dy, 0.5f * q);
-  float G = fast_exp_neg(sigma);
-  float alpha = cn[3] * G;
-  e.clamped = alpha > kAlphaMax;
-  e.alpha = e.clamped ? kAlphaMax : alpha;
   e.dx = dx;
   e.dy = dy;
-  e.sigma = sigma;
-  e.G = G;
+  e.tx = SPLAT_FMA(ce.x, dx, ce.y * dy);
+  e.cy = ce.z * dy;
+  e.G = exp2_fast(SPLAT_FMA(dx, e.tx, e.cy * dy));
+  e.oG = ce.w * e.G;
 }
+
+// Eq. alpha's clamp: min(o G, 0.99)
+HD float clamp_alpha(float oG) { return fminf(oG, kAlphaMax); }
 
 }  // namespace splat
