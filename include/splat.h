@@ -344,7 +344,9 @@ int splat_rasterize_bwd_lidar(const SplatGaussians* g, const SplatRig* rig, int3
  * [first, first + count) of a rig, the launches of one step of the batched form: zero *status
  * (fill kernel), zero the gradients (if SPLAT_STEP_ZERO_GRADS), splat_project, splat_bin_sort,
  * splat_rasterize_fwd and, with SPLAT_STEP_BACKWARD, splat_rasterize_bwd, all on the buffers of
- * `step` (validated at creation exactly as those calls validate them).  splat_pipeline_run
+ * `step` (validated at creation exactly as those calls validate them).  The forward is given
+ * the status (and so counts evaluated pairs, a slower walk) only with SPLAT_STEP_COUNT_PAIRS;
+ * projection and bin/sort always report into it.  splat_pipeline_run
  * launches the graph on `stream`: one host call per step instead of one per kernel.
  *   - Graph kernels read the sensor table at run time, so poses, velocities, shutter times and
  *     ray arrays may change between runs through splat_rig_set on the same stream.  A change of
@@ -366,6 +368,7 @@ int splat_time_next_raster(void* start_event, void* stop_event);
 
 #define SPLAT_STEP_BACKWARD 1    /* include the adjoint                                   */
 #define SPLAT_STEP_ZERO_GRADS 2  /* zero every gradient array first (else they accumulate) */
+#define SPLAT_STEP_COUNT_PAIRS 4 /* the forward counts evaluated pairs into status->n_pairs  */
 
 typedef struct SplatStep {
   SplatGaussians gaussians;

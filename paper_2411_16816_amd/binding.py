@@ -446,7 +446,7 @@ class Pipeline:
     named here are captured by address and kept alive by this object; `run` replays the step."""
 
     def __init__(self, sp: SensorPass, g: GaussTensors, support=BOX, grads: Optional[GaussTensors] = None,
-                 dF=None, dD=None, dA=None, zero_grads: bool = True, d_los=None):
+                 dF=None, dD=None, dA=None, zero_grads: bool = True, d_los=None, count_pairs: bool = False):
         if not sp.batched:
             raise ValueError("pipelines run the batched form")
         self.lib, self.sp, self.g = sp.lib, sp, g
@@ -455,7 +455,7 @@ class Pipeline:
         step.gaussians = g.struct()
         step.proj, step.lists, step.out = sp.proj_struct(), sp.lists_struct(), sp.out_struct(d_los=d_los)
         step.support = support
-        step.flags = 0
+        step.flags = st.SPLAT_STEP_COUNT_PAIRS if count_pairs else 0
         if grads is not None:
             step.flags |= st.SPLAT_STEP_BACKWARD | (st.SPLAT_STEP_ZERO_GRADS if zero_grads else 0)
             step.d_feat, step.d_depth, step.d_alpha = _ptr(dF), _ptr(dD), _ptr(dA)

@@ -442,7 +442,8 @@ static int step_launches(const SplatRig* r, int32_t first, int32_t count, const 
   }
   int rc = project_impl(g, r, first, count, -1, &st->proj, st->status, s);
   if (!rc) rc = bin_sort_impl(r, first, count, -1, g->n, &st->proj, &st->lists, st->ws, st->ws_bytes, st->status, s);
-  if (!rc) rc = raster_fwd_impl(g, r, first, count, -1, &st->proj, &st->lists, st->support, &st->out, st->status, s);
+  SplatStatus* const fwd_status = (st->flags & SPLAT_STEP_COUNT_PAIRS) ? st->status : nullptr;
+  if (!rc) rc = raster_fwd_impl(g, r, first, count, -1, &st->proj, &st->lists, st->support, &st->out, fwd_status, s);
   if (!rc && bwd)
     rc = raster_bwd_impl(g, r, first, count, -1, &st->proj, &st->lists, st->support, &st->out, st->d_feat,
                          st->d_depth, st->d_alpha, &st->grads, st->ws, st->ws_bytes, s);

@@ -124,6 +124,7 @@ def lidar_struct(lid, ray_ptrs=(None, None, None), bounds_keepalive=None) -> Spl
 
 SPLAT_STEP_BACKWARD = 1
 SPLAT_STEP_ZERO_GRADS = 2
+SPLAT_STEP_COUNT_PAIRS = 4
 
 
 class SplatStep(C.Structure):

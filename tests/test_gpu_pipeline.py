@@ -76,6 +76,17 @@ def test_pipeline_replays_match_eager():
         if prev is not None:
             assert not np.array_equal(cur, prev)
         prev = cur
+        # the forward counts pairs only when the step asks for it
+        assert s_p.n_pairs == 0 and s_p.n_stopped == 0
+    # a counting pipeline (forward only) reports the eager counting forward's pairs
+    pipe_c = b.Pipeline(sp, G, b.BOX, count_pairs=True)
+    pipe_c.run()
+    ref.status.zero_()
+    ref.raster_fwd(G, count_pairs=True)
+    torch.cuda.synchronize()
+    s_c, s_r = b.read_status(sp.status), b.read_status(ref.status)
+    assert s_c.n_pairs > 0 and s_c.n_pairs == s_r.n_pairs and s_c.n_stopped == s_r.n_stopped
+    pipe_c.close()
     # a sensor with another tile count invalidates the pipeline: nothing is launched
     cam_w, lid_w = _sensors(0, width=192)
     rig.update([cam_w], [lid_w])
