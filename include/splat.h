@@ -175,9 +175,9 @@ typedef struct SplatProjected {
 
 /* Per-tile depth-ordered lists.  Tile ids are local to the call. */
 typedef struct SplatTileLists {
-  int64_t k_cap;          /* capacity of gauss[]                                             */
+  int64_t k_cap;          /* capacity of gauss[], 0 <= k_cap < 2^32                           */
   int32_t* gauss;         /* [k_cap] Gaussian ids, grouped by tile, by (depth, id) inside      */
-  int32_t* tile_range;    /* [n_tiles, 2] [start, end) into gauss                             */
+  int64_t* tile_range;    /* [n_tiles, 2] [start, end) into gauss (16-byte aligned)           */
   int64_t* entry_base;    /* [count * N] written by bin_sort for records with n_tiles > 0:
                              the number of the record's first (tile, Gaussian) entry.  Entries
                              are numbered record by record in record order, each record's tiles
@@ -256,9 +256,20 @@ void splat_rig_destroy(SplatRig* rig);
  * `n_gaussians` Gaussians and list capacity k_cap.  The bin/sort buffers and the adjoint's
  * buffers overlay each other; the adjoint's part is one gradient row per list entry
  * (k_cap x (10 + channel bucket) floats, channel buckets 4/8/16/32/48, rows padded to 16 bytes),
- * k_cap flag bytes and 10 floats per record.  Nothing in it outlives a call. */
+ * k_cap flag bytes and 10 floats per record — without the rows and flags when k_cap exceeds
+ * the adjoint row limit (splat_set_adjoint_row_limit).  Nothing in it outlives a call. */
 size_t splat_workspace_bytes(const SplatRig* rig, int32_t first, int32_t count, int64_t n_gaussians,
                              int64_t k_cap);
+
+/* The adjoint keeps one gradient row per list entry as long as the call's k_cap is at most
+ * this many entries (default SPLAT_ADJOINT_ROW_LIMIT: about 60 GB of rows at 16 channels);
+ * larger calls (a whole sensor sweep in one call) keep none: every work item adds its
+ * per-Gaussian sums to the record's gradient with float atomics, whose rounding then depends
+ * on scheduling.  Process-wide; the same limit must hold from splat_workspace_bytes to the
+ * adjoint call that uses the workspace.  For memory-bound callers and tests.  Negative:
+ * SPLAT_ERR_INVALID_ARG. */
+#define SPLAT_ADJOINT_ROW_LIMIT (1LL << 29)
+int splat_set_adjoint_row_limit(int64_t max_entries);
 
 /* ---- a1 / a2: projection (Sec. 3.2 "Projection, tiling, and sorting", "Rolling shutter";
  * Sec. 3.3 "Projection"; App. D).  Per (Gaussian, sensor): sensor-frame mean and covariance,
@@ -325,7 +336,8 @@ int splat_rasterize_bwd(const SplatGaussians* g, const SplatRig* rig, int32_t fi
  * sums each Gaussian's gradient over its rays (wavefront, then workgroup) and stores it as one
  * row per (tile, Gaussian) entry at the entry's number (see entry_base); work items
  * of a lidar tile with more than SPLAT_RAYS_PER_ITEM rays share the tile and add atomically
- * instead.  Each record's rows are then summed in a fixed order and chained to means,
+ * instead, and so do all work items of a call beyond the adjoint row limit
+ * (splat_set_adjoint_row_limit).  Each record's rows are then summed in a fixed order and chained to means,
  * log-scales, quaternions, opacities, velocities and features.  Needs the lists written by
  * bin_sort for the same projection.  d_feat / d_depth / d_alpha are the upstream gradients of
  * SplatRenderOut feat/depth/alpha. */

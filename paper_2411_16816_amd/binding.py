@@ -42,6 +42,7 @@ def _declare(lib):
         "splat_rig_layout": (C.c_int, [vp, vp]),
         "splat_rig_destroy": (None, [vp]),
         "splat_workspace_bytes": (C.c_size_t, [vp, i32, i32, i64, i64]),
+        "splat_set_adjoint_row_limit": (C.c_int, [i64]),
         "splat_project_camera": (C.c_int, [vp, vp, i32, i32, vp, vp, vp]),
         "splat_project_lidar": (C.c_int, [vp, vp, i32, i32, vp, vp, vp]),
         "splat_bin_sort_camera": (C.c_int, [vp, i32, i32, i64, vp, vp, vp, C.c_size_t, vp, vp]),
@@ -264,7 +265,7 @@ class SensorPass:
         self.dkey = torch.empty((R,), dtype=torch.int64, device=device)
         self.rect = torch.empty((R, 4), **i32)
         self.ntiles = torch.empty((R,), **i32)
-        self.tile_range = torch.empty((max(1, self.n_tiles), 2), **i32)
+        self.tile_range = torch.empty((max(1, self.n_tiles), 2), dtype=torch.int64, device=device)
         self.entry_base = torch.empty((max(1, R),), dtype=torch.int64, device=device)
         if self.has_lidar or batched:
             self.work_cap = self.n_tiles + (self.n_rays + 255) // 256 + 1
@@ -660,6 +661,16 @@ def device_clock_hz() -> int:
     hz = C.c_int64()
     check(load().splat_device_clock_hz(C.byref(hz)), "splat_device_clock_hz")
     return int(hz.value)
+
+
+ADJOINT_ROW_LIMIT = 1 << 29   # splat.h SPLAT_ADJOINT_ROW_LIMIT
+
+
+def set_adjoint_row_limit(max_entries: int = ADJOINT_ROW_LIMIT):
+    """Largest list capacity whose adjoint keeps per-entry gradient rows (splat_set_adjoint_row_limit);
+    larger calls add every work item's sums atomically.  Process-wide: set it before sizing the
+    workspaces it applies to."""
+    check(load().splat_set_adjoint_row_limit(int(max_entries)), "splat_set_adjoint_row_limit")
 
 
 # ----------------------------------------------------------------------------------------

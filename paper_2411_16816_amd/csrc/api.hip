@@ -1,5 +1,6 @@
 // api.hip -- the C ABI of libsplat (declared in include/splat.h): host-side validation, the rig
 // (device sensor table), workspace sizing, and dispatch to the kernel launchers.
+#include <atomic>
 #include <new>
 #include <string.h>
 #include <vector>
@@ -232,9 +233,10 @@ static int check_proj(const SplatProjected* p, const CallView& v) {
 }
 
 static int check_lists(const SplatTileLists* L, const CallView& v) {
-  if (!L || L->k_cap < 0 || L->k_cap >= ((int64_t)1 << 31)) return SPLAT_ERR_INVALID_ARG;
+  // list positions are 32-bit unsigned inside bin/sort: k_cap < 2^32
+  if (!L || L->k_cap < 0 || L->k_cap >= ((int64_t)1 << 32)) return SPLAT_ERR_INVALID_ARG;
   if ((L->k_cap > 0 && !L->gauss) || !L->tile_range || !L->entry_base) return SPLAT_ERR_INVALID_ARG;
-  if ((((uintptr_t)L->tile_range | (uintptr_t)L->entry_base) & 7) != 0) return SPLAT_ERR_INVALID_ARG;
+  if (((uintptr_t)L->tile_range & 15) != 0 || ((uintptr_t)L->entry_base & 7) != 0) return SPLAT_ERR_INVALID_ARG;
   if (v.has_lidar || v.queue) {
     if ((v.has_lidar && !L->ray_order) || !L->ray_range || !L->work || !L->n_work) return SPLAT_ERR_INVALID_ARG;
     if ((((uintptr_t)L->ray_range | (uintptr_t)L->work) & 7) != 0) return SPLAT_ERR_INVALID_ARG;
@@ -295,6 +297,13 @@ static int raster_fwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t f
   return dev_err(launch_raster_fwd(v, *g, *proj, *lists, support, *out, st, (hipStream_t)stream, take_timer()));
 }
 
+// Largest k_cap whose adjoint keeps per-entry rows (process-wide, splat_set_adjoint_row_limit).
+static std::atomic<int64_t> g_row_limit{SPLAT_ADJOINT_ROW_LIMIT};
+
+namespace splat {
+int64_t adjoint_row_limit() { return g_row_limit.load(); }
+}  // namespace splat
+
 static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count, int kind,
                            const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
                            const SplatRenderOut* saved, const float* dF, const float* dD, const float* dA,
@@ -311,13 +320,14 @@ static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t f
   if (!ws || ws_bytes < w.bytes || ((uintptr_t)ws & 255) != 0) return SPLAT_ERR_INVALID_ARG;
   w = carve_workspace(ws, (int64_t)count * g->n, lists->k_cap, v.n_tiles, v.n_rays, v.c_max);
   hipStream_t s = (hipStream_t)stream;
-  // slot flags start cleared; the atomic part only exists where lidar tiles can be split
-  hipError_t e = launch_fill_i32((int32_t*)w.flags, div_up(lists->k_cap, 4), 0, s);
+  // slot flags start cleared; the atomic part exists where lidar tiles can be split, and for
+  // every record when the call keeps no rows
+  hipError_t e = w.rows ? launch_fill_i32((int32_t*)w.flags, div_up(lists->k_cap, 4), 0, s) : hipSuccess;
   if (e == hipSuccess) e = launch_fill_i32((int32_t*)w.rflag, div_up((int64_t)count * g->n, 4), 0, s);
-  if (e == hipSuccess && v.has_lidar) {
-    // only lidar records (the call's last sensors) receive atomic parts: zero their rows alone
+  if (e == hipSuccess && (v.has_lidar || !w.rows)) {
+    // with rows only lidar records (the call's last sensors) receive atomic parts: zero theirs
     int k_lid = 0;
-    while (k_lid < count && v.host[k_lid].kind != kLidar) ++k_lid;
+    while (w.rows && k_lid < count && v.host[k_lid].kind != kLidar) ++k_lid;
     e = launch_fill_f32(w.g2d + (int64_t)k_lid * g->n * kNV, (int64_t)(count - k_lid) * g->n * kNV, 0.f, s);
   }
   if (e == hipSuccess)
@@ -328,6 +338,12 @@ static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t f
 }
 
 extern "C" {
+
+int splat_set_adjoint_row_limit(int64_t max_entries) {
+  if (max_entries < 0) return SPLAT_ERR_INVALID_ARG;
+  g_row_limit.store(max_entries);
+  return SPLAT_OK;
+}
 
 size_t splat_workspace_bytes(const SplatRig* r, int32_t first, int32_t count, int64_t n_gaussians, int64_t k_cap) {
   CallView v;

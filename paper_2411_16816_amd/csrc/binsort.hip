@@ -780,11 +780,11 @@ constexpr int kItemEntries = 256;
 inline int64_t item_capacity(int64_t n_supertiles, int64_t k_cap) { return n_supertiles + div_up(k_cap, kItemEntries); }
 
 struct LoadItemCount {
-  const int2* crange;
+  const uint2* crange;
   int64_t n_st;
   __device__ int64_t operator()(int64_t i) const {
     if (i >= n_st) return 0;
-    const int2 r = crange[i];
+    const uint2 r = crange[i];
     const int64_t c = (int64_t)(r.y - r.x);
     return c > kItemEntries ? (c + kItemEntries - 1) / kItemEntries : 1;
   }
@@ -834,7 +834,7 @@ struct ItemView {
 };
 
 __device__ __forceinline__ ItemView item_view(const DevSensor* sens, const uint2* item_st, const int64_t* item_first,
-                                              const int2* crange, int64_t it) {
+                                              const uint2* crange, int64_t it) {
   ItemView v;
   const uint2 bs = item_st[it];
   v.st = bs.x;
@@ -845,7 +845,7 @@ __device__ __forceinline__ ItemView item_view(const DevSensor* sens, const uint2
   const int q = (int)((int64_t)bs.x - (S.st_base - sens[0].st_base));
   v.sr = q / S.st_x;
   v.sc = q - v.sr * S.st_x;
-  const int2 r = crange[bs.x];
+  const uint2 r = crange[bs.x];
   v.p0 = (int64_t)r.x + (it - v.first_item) * kItemEntries;
   const int64_t rest = (int64_t)r.y - v.p0;
   v.cnt = (int)(rest < 0 ? 0 : (rest > kItemEntries ? kItemEntries : rest));
@@ -917,7 +917,7 @@ __device__ __forceinline__ void round_ballots(uint32_t rows, uint32_t cols, int 
 // count array.
 template <int WL, int HL>
 __global__ __launch_bounds__(256) void k_st_count(const DevSensor* __restrict__ sens,
-                                                  const uint64_t* __restrict__ cvals, const int2* __restrict__ crange,
+                                                  const uint64_t* __restrict__ cvals, const uint2* __restrict__ crange,
                                                   const int64_t* __restrict__ item_first,
                                                   const uint2* __restrict__ item_st, int64_t st_lo, int64_t st_hi,
                                                   uint32_t* __restrict__ cnt) {
@@ -947,11 +947,11 @@ __global__ __launch_bounds__(256) void k_st_count(const DevSensor* __restrict__ 
 // end) ranges.
 template <int WL, int HL>
 __global__ __launch_bounds__(256) void k_st_place(const DevSensor* __restrict__ sens,
-                                                  const uint64_t* __restrict__ cvals, const int2* __restrict__ crange,
+                                                  const uint64_t* __restrict__ cvals, const uint2* __restrict__ crange,
                                                   const int64_t* __restrict__ item_first,
                                                   const uint2* __restrict__ item_st, int64_t st_lo, int64_t st_hi,
                                                   const uint32_t* __restrict__ pos0, int64_t k_cap,
-                                                  int32_t* __restrict__ gauss, int2* __restrict__ tile_range) {
+                                                  int32_t* __restrict__ gauss, longlong2* __restrict__ tile_range) {
   const int lane = threadIdx.x & 63;
   FOR_EACH_ITEM(it) {
     const ItemView v = item_view(sens, item_st, item_first, crange, it);
@@ -965,7 +965,7 @@ __global__ __launch_bounds__(256) void k_st_place(const DevSensor* __restrict__ 
       if (fy < (1 << HL) && fx < (1 << WL) && row < grid_rows(S) && col < grid_stride(S)) {
         const int64_t t = (S.tile_base - sens[0].tile_base) + (int64_t)row * grid_stride(S) + col;
         const uint32_t end = pos0[v.first_item * 64 + (int64_t)(lane + 1) * v.n_items];
-        tile_range[t] = make_int2((int)start, (int)end);
+        tile_range[t] = make_longlong2((long long)start, (long long)end);
       }
     }
     uint32_t run = start;
@@ -998,8 +998,11 @@ constexpr int kRangeItems = 8;   // sorted keys per thread of k_ranges
 // [start, end) of every key's run in a sorted key array; keys that do not occur keep the range
 // the caller filled in.  Thread t of a block handles elements base + j * 256 + t (coalesced).
 // The run of key k is range[(k >> shift) + offset].
-__global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap, int2* __restrict__ range,
+// R2: int2 (ray bins) or uint2 (coarse entries, up to 2^32 - 1 of them)
+template <typename R2>
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap, R2* __restrict__ range,
                          int shift, int64_t offset) {
+  using E = decltype(R2::x);
   const int64_t base = (int64_t)blockIdx.x * blockDim.x * kRangeItems + threadIdx.x;
   const int64_t n = sort_count(n_ptr, n_cap);
   if ((int64_t)blockIdx.x * blockDim.x * kRangeItems >= n) return;   // uniform; n >= 1 below
@@ -1017,8 +1020,8 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ptr
   for (int j = 0; j < kRangeItems; ++j) {
     const int64_t i = base + (int64_t)j * blockDim.x;
     if (i >= n) break;
-    if (prev[j] != cur[j]) range[cur[j] + offset].x = (int)i;
-    if (next[j] != cur[j]) range[cur[j] + offset].y = (int)(i + 1);
+    if (prev[j] != cur[j]) range[cur[j] + offset].x = (E)i;
+    if (next[j] != cur[j]) range[cur[j] + offset].y = (E)(i + 1);
   }
 }
 
@@ -1121,14 +1124,14 @@ __device__ __forceinline__ uint32_t length_code(int64_t len) {
 }
 
 __global__ void k_queue_keys(const int2* __restrict__ work, const int32_t* __restrict__ n_work,
-                             const int2* __restrict__ tile_range, int64_t n_tiles, uint32_t* __restrict__ keys,
+                             const longlong2* __restrict__ tile_range, int64_t n_tiles, uint32_t* __restrict__ keys,
                              uint32_t* __restrict__ vals) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= *n_work) return;
   int64_t t = work[i].x;
   int64_t len = 0;
   if (t < n_tiles) {
-    int2 r = tile_range[t];
+    const longlong2 r = tile_range[t];
     len = r.y - r.x;
   }
   keys[i] = 255u - length_code(len);
@@ -1169,7 +1172,7 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   for (int i = 0; i < 2; ++i) w.ckeys[i] = (uint32_t*)take(kc * 4);
   for (int i = 0; i < 2; ++i) w.cvals[i] = (uint64_t*)take(kc * 8);
   const int64_t nst = n_tiles < 1 ? 1 : n_tiles;   // supertiles <= tiles
-  w.crange = (int2*)take(nst * 8);
+  w.crange = (uint2*)take(nst * 8);
   w.item_first = (int64_t*)take((nst + 1) * 8);
   w.item_st = (uint2*)take(item_capacity(nst, kc) * 8);
   const int64_t xcap = item_capacity(nst, kc) * 64 + 1;
@@ -1190,11 +1193,13 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   // adjoint buffers start over at the base
   off = 0;
   w.stride = slot_stride(cmax_bucket(c_max));
-  w.slots = (float*)take((size_t)kc * w.stride * 4);
-  w.flags = (uint8_t*)take((size_t)div_up(kc, 4) * 4);
+  w.rows = k_cap <= adjoint_row_limit();
+  const int64_t kr = w.rows ? kc : 1;   // rows and flags only while they are kept
+  w.slots = (float*)take((size_t)kr * w.stride * 4);
+  w.flags = (uint8_t*)take((size_t)div_up(kr, 4) * 4);
   w.g2d = (float*)take((size_t)nrec * kNV * 4);
   w.rflag = (uint8_t*)take((size_t)div_up(nrec, 4) * 4);
-  w.long_cap = long_part_cap(nrec, kc);
+  w.long_cap = w.rows ? long_part_cap(nrec, kc) : 1;
   w.long_list = (uint32_t*)take((size_t)kLongParts * w.long_cap * 8);
   w.n_long = (int32_t*)take(kLongParts * 4);
   w.bytes = off > sort_bytes ? off : sort_bytes;
@@ -1237,9 +1242,9 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   if ((e = radix_sort<uint32_t, uint64_t>(ck, cv, ccur, sc + kScCoarse, L.k_cap, 0, bits_for(n_st), w.hist, w.coltotal,
                                 nullptr, s)) != hipSuccess)
     return e;
-  if ((e = fill<int32_t>((int32_t*)w.crange, 2 * n_st, 0, s)) != hipSuccess) return e;
+  if ((e = fill<int32_t>((int32_t*)w.crange, 2 * n_st, 0, s)) != hipSuccess) return e;   // [0, 0): empty
   if (L.k_cap > 0)
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(L.k_cap, 256 * kRangeItems)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_ranges<uint2>, dim3((unsigned)div_up(L.k_cap, 256 * kRangeItems)), dim3(256), 0, s,
                        (const uint32_t*)ck[ccur], (const int64_t*)(sc + kScCoarse), L.k_cap, w.crange, 0, (int64_t)0);
   // 5. items of <= kItemEntries entries per supertile; per item and tile the entry counts; their
   //    scan gives every tile's list range and every item its first positions; placement
@@ -1259,23 +1264,23 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   const uint64_t* cvs = cv[ccur];
   if (st_cam > 0)
     hipLaunchKernelGGL((k_st_count<kStLogCamera, kStLogCamera>), dim3((unsigned)grid), dim3(256), 0, s, v.sens, cvs,
-                       (const int2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, (int64_t)0, st_cam,
+                       (const uint2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, (int64_t)0, st_cam,
                        w.xcount);
   if (st_cam < n_st)
     hipLaunchKernelGGL((k_st_count<kStLogLidar, kStLogLidar>), dim3((unsigned)grid), dim3(256), 0, s, v.sens, cvs,
-                       (const int2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, st_cam, n_st,
+                       (const uint2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, st_cam, n_st,
                        w.xcount);
   if ((e = device_scan<uint32_t>(LoadCountX{w.xcount, sc + kScItemsX}, icap * 64 + 1, w.xcount, w.xpart, s,
                                  NoVisit(), sc + kScItemsX)) != hipSuccess)
     return e;
   if (st_cam > 0)
     hipLaunchKernelGGL((k_st_place<kStLogCamera, kStLogCamera>), dim3((unsigned)grid), dim3(256), 0, s, v.sens, cvs,
-                       (const int2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, (int64_t)0, st_cam,
-                       (const uint32_t*)w.xcount, L.k_cap, L.gauss, (int2*)L.tile_range);
+                       (const uint2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, (int64_t)0, st_cam,
+                       (const uint32_t*)w.xcount, L.k_cap, L.gauss, (longlong2*)L.tile_range);
   if (st_cam < n_st)
     hipLaunchKernelGGL((k_st_place<kStLogLidar, kStLogLidar>), dim3((unsigned)grid), dim3(256), 0, s, v.sens, cvs,
-                       (const int2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, st_cam, n_st,
-                       (const uint32_t*)w.xcount, L.k_cap, L.gauss, (int2*)L.tile_range);
+                       (const uint2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, st_cam, n_st,
+                       (const uint32_t*)w.xcount, L.k_cap, L.gauss, (longlong2*)L.tile_range);
   // 6. lidar rays -> tiles; work items (lidar chunks, and camera tiles in the batched form)
   if (v.has_lidar || v.queue) {
     const int64_t bins = v.n_tiles + 1;
@@ -1297,7 +1302,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
       if ((e = radix_sort<uint32_t, uint32_t>(rk, rv, rcur, nullptr, nr, 0, bin_bits + cell_bits, w.hist, w.coltotal,
                                     (uint32_t*)L.ray_order, s)) != hipSuccess)
         return e;
-      hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(nr, 256 * kRangeItems)), dim3(256), 0, s, (const uint32_t*)rk[rcur],
+      hipLaunchKernelGGL(k_ranges<int2>, dim3((unsigned)div_up(nr, 256 * kRangeItems)), dim3(256), 0, s, (const uint32_t*)rk[rcur],
                          (const int64_t*)nullptr, nr, (int2*)L.ray_range, cell_bits, t0);
     }
     hipLaunchKernelGGL(k_work_count, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, v.sens, v.count,
@@ -1312,7 +1317,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
     if (v.queue) {
       const int64_t wcap = L.work_cap;
       hipLaunchKernelGGL(k_queue_keys, dim3((unsigned)div_up(wcap, 256)), dim3(256), 0, s, (const int2*)w.qtmp,
-                         (const int32_t*)L.n_work, (const int2*)L.tile_range, v.n_tiles, w.qkeys[0], w.qvals[0]);
+                         (const int32_t*)L.n_work, (const longlong2*)L.tile_range, v.n_tiles, w.qkeys[0], w.qvals[0]);
       uint32_t* qk[2] = {w.qkeys[0], w.qkeys[1]};
       uint32_t* qv[2] = {w.qvals[0], w.qvals[1]};
       int qcur = 0;

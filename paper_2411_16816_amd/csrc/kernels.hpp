@@ -69,7 +69,7 @@ struct Workspace {
   void* scan_part;        // block partials of the record scans (16 bytes per block)
   uint32_t* ckeys[2];     // [k_cap] supertile of each (supertile, record) entry
   uint64_t* cvals[2];     // [k_cap] Gaussian id | covered tile rows << 32 | columns << 40
-  int2* crange;           // [supertiles] [start, end) of each supertile's entries
+  uint2* crange;          // [supertiles] [start, end) of each supertile's entries
   int64_t* item_first;    // [supertiles + 1] first item of each supertile; [n] = items
   uint2* item_st;         // [items] (supertile, sensor) of each item
   uint32_t* xcount;       // [64 items + 1] per (item, tile) entry counts, then their scan
@@ -85,9 +85,11 @@ struct Workspace {
   int2* qtmp;             // [work_cap] unordered work items
   int64_t* scalars;       // [4] device scalars of the call (visible records, entry counts, items)
   // adjoint (overlays the bin/sort buffers: the two are never live in one call)
+  bool rows;              // per-entry rows kept (k_cap within the adjoint row limit)
   float* slots;           // [k_cap, slot_stride] per-entry gradient rows, indexed by entry number
   uint8_t* flags;         // [k_cap] 1 = slot row written by this adjoint call
-  float* g2d;             // [n_rec, kNV] atomically accumulated part (lidar tiles split over items)
+  float* g2d;             // [n_rec, kNV] atomically accumulated part (lidar tiles split over items;
+                          // every record when rows are not kept)
   uint8_t* rflag;         // [n_rec] 1 = the adjoint produced a gradient for the record
   uint32_t* long_list;    // [kLongParts * long_cap] (record, chunk) pairs of long touched records
   int32_t* n_long;        // [kLongParts] partition counts
@@ -97,6 +99,9 @@ struct Workspace {
 };
 
 Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_tiles, int64_t n_rays, int c_max);
+
+// Largest k_cap whose adjoint keeps per-entry rows (splat_set_adjoint_row_limit).
+int64_t adjoint_row_limit();
 
 // ---- launchers ------------------------------------------------------------------------------
 hipError_t launch_project(const CallView& v, const SplatGaussians& g, const SplatProjected& p, SplatStatus* st,

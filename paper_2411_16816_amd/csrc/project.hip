@@ -371,6 +371,11 @@ hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const 
   const dim3 grid((unsigned)div_up(g.n, 256));
   float* dfeat = v.c_max > 0 ? gr.features : nullptr;
   const int64_t n_rec = (int64_t)v.count * g.n;
+  if (!w.rows) {   // every work item added its sums to g2d and the features gradient
+    hipLaunchKernelGGL(k_project_bwd, grid, dim3(256), 0, s, v.sens, v.count, g, (const uint8_t*)w.rflag,
+                       (const float*)w.g2d, gr);
+    return hipGetLastError();
+  }
   if (w.long_cap != long_part_cap(n_rec, L.k_cap)) return hipErrorInvalidValue;
   hipError_t e = launch_fill_i32(w.n_long, kLongParts, 0, s);
   if (e != hipSuccess) return e;

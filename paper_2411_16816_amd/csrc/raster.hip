@@ -30,7 +30,7 @@ struct RasterArgs {
   const float4* box;
   const float2* dv;
   const int32_t* gauss;
-  const int2* tile_range;
+  const longlong2* tile_range;
   const int4* rect;
   const int64_t* entry_base;
   const float* features;
@@ -64,7 +64,9 @@ struct BwdIn {
   float* slots;      // [k_cap, slot_stride] rows written by work items that own their tile
   uint8_t* flags;    // [k_cap] set for every row written
   uint8_t* rflag;    // [n_rec] set for every record given a gradient (row or atomic)
-  float* g2d;        // [n_rec, kNV] atomic part from work items of split lidar tiles
+  float* g2d;        // [n_rec, kNV] atomic part from work items of split lidar tiles (every
+                     // work item when rows are not kept)
+  bool rows;         // per-entry rows kept (else every work item adds atomically)
   float* dfeat;      // features gradient (atomic part, split lidar tiles)
   unsigned long long* sensor_done;  // per-sensor completion clock (atomic max), or null
   float* d_toff;     // [count] camera time-offset gradients (+=), or null
@@ -109,6 +111,13 @@ struct RayCtx {
   float los_thr;      // lidar line-of-sight threshold: measured range - margin (-inf: none)
   bool dropped;       // lidar ray dropped by the training-time cap (renders nothing)
 };
+
+// A value known to be the same in every lane, held in scalar registers.
+__device__ __forceinline__ int64_t uniform_i64(int64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 // Lane setup for one work item: a camera tile (all its pixels) or a chunk of <= 256 rays of a
 // lidar tile starting at position `pos` of ray_order (tile == n_tiles: rays outside every tile).
@@ -175,10 +184,10 @@ __device__ __forceinline__ void setup_ray(const RasterArgs& a, int64_t tile, int
   // the invalid-ray bin (tile == n_tiles) has no Gaussian list: read an in-bounds entry and drop
   // it; a work item of dropped rays renders an empty list
   const bool empty = LIDAR && (c.invalid_bin || c.dropped);
-  const int2 tr = a.tile_range[(LIDAR && c.invalid_bin) ? 0 : tile];
+  const longlong2 tr = a.tile_range[(LIDAR && c.invalid_bin) ? 0 : tile];
   // the same for every lane of the work item: say so, so that the list walks count in scalars
-  c.start = __builtin_amdgcn_readfirstlane(empty ? 0 : tr.x);
-  c.end = __builtin_amdgcn_readfirstlane(empty ? 0 : tr.y);
+  c.start = uniform_i64(empty ? 0 : tr.x);
+  c.end = uniform_i64(empty ? 0 : tr.y);
 }
 
 // One staged Gaussian in LDS, contiguous so that one address reaches all of it (float4 units):
@@ -507,8 +516,9 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
   }
   const DevSensor& S = a.sens[c.s];
   const int64_t tile_local = tile - (S.tile_base - a.sens[0].tile_base);
-  // a lidar tile with more rays than one item holds is shared by several items
-  const bool split = LIDAR && (a.ray_range[tile].y - a.ray_range[tile].x > SPLAT_RAYS_PER_ITEM);
+  // a lidar tile with more rays than one item holds is shared by several items; without
+  // per-entry rows every item adds atomically
+  const bool split = !b.rows || (LIDAR && (a.ray_range[tile].y - a.ray_range[tile].x > SPLAT_RAYS_PER_ITEM));
   // gradient rows have the stride of the launch's bucket (the workspace's), whatever this
   // item's own channel bucket
   constexpr int SW = slot_stride(SM::kCmax);
@@ -686,7 +696,7 @@ static RasterArgs make_args(const CallView& v, const SplatGaussians& g, const Sp
   a.box = (const float4*)p.box;
   a.dv = (const float2*)p.dv;
   a.gauss = L.gauss;
-  a.tile_range = (const int2*)L.tile_range;
+  a.tile_range = (const longlong2*)L.tile_range;
   a.rect = (const int4*)p.rect;
   a.entry_base = L.entry_base;
   a.features = g.features;
@@ -813,8 +823,8 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
                              const float* dD, const float* dA, const Workspace& w, float* dfeat, float* d_toff,
                              hipStream_t s, const KernelTimer& timer) {
   RasterArgs a = make_args(v, g, p, L);
-  BwdIn b{saved.t_final, saved.last, dF, dD, dA, w.slots, w.flags, w.rflag, w.g2d, dfeat, saved.sensor_done, d_toff,
-          saved.d_los};
+  BwdIn b{saved.t_final, saved.last, dF, dD, dA, w.slots, w.flags, w.rflag, w.g2d, w.rows, dfeat, saved.sensor_done,
+          d_toff, saved.d_los};
   const int cm = cmax_bucket(v.c_max);
   if (w.stride != slot_stride(cm)) return hipErrorInvalidValue;
   if (v.queue) {

@@ -68,17 +68,19 @@ def grad_mismatch(got, ref, rtol=1e-3, afloor=1e-5):
     return np.abs(got - ref) > rtol * np.abs(ref) + afloor * np.abs(ref).max(initial=0.0)
 
 
-def assert_grad_close(got, ref, what, rtol=1e-3, norm_tol=1e-3, afloor=1e-5, require_nonzero=True):
+def assert_grad_close(got, ref, what, rtol=1e-3, norm_tol=1e-3, afloor=1e-5, require_nonzero=True,
+                      per_element=True):
     """The gradient bar of the parity tests: ||g - g_ref|| <= norm_tol ||g_ref|| for the array,
-    and |g - g_ref| <= rtol |g_ref| + afloor max|g_ref| for every element.  On failure the
-    message names the worst elements (flat index, GPU value, reference value)."""
+    and |g - g_ref| <= rtol |g_ref| + afloor max|g_ref| for every element (unless per_element is
+    False: the caller checks the elements itself).  On failure the message names the worst
+    elements (flat index, GPU value, reference value)."""
     got = np.asarray(got, np.float64)
     ref = np.asarray(ref, np.float64)
     nrm = float(np.linalg.norm(ref))
     if require_nonzero:
         assert nrm > 0, f"{what}: reference gradient is zero"
     rel = float(np.linalg.norm(got - ref)) / max(nrm, 1e-300)
-    bad = grad_mismatch(got, ref, rtol, afloor)
+    bad = grad_mismatch(got, ref, rtol, afloor) if per_element else np.zeros(got.shape, bool)
     if rel <= norm_tol and not bad.any():
         return
     err = (np.abs(got - ref) / (rtol * np.abs(ref) + afloor * np.abs(ref).max(initial=0.0) + 1e-300)).reshape(-1)

@@ -171,6 +171,8 @@ static void check_sizes() {
   expect(splat_mcmc_relocate_workspace_bytes(1) > 0 && splat_mcmc_relocate_workspace_bytes(1 << 21) >
                                                             splat_mcmc_relocate_workspace_bytes(1),
          "relocation workspace grows with n");
+  expect(splat_set_adjoint_row_limit(-1) == SPLAT_ERR_INVALID_ARG, "negative adjoint row limit");
+  expect(splat_set_adjoint_row_limit(SPLAT_ADJOINT_ROW_LIMIT) == SPLAT_OK, "default adjoint row limit");
   for (int code = -2; code <= 6; ++code) expect(splat_status_string(code) != nullptr, "status string");
   expect(strcmp(splat_status_string(SPLAT_ERR_CAPACITY), "capacity exceeded") == 0, "capacity status text");
 }

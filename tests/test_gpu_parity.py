@@ -547,6 +547,66 @@ def test_split_tile_atomics_match_fixed_order():
             assert not bad.any(), (name, int(bad.sum()))
 
 
+def test_adjoint_without_rows_matches_rows():
+    """Beyond the adjoint row limit a call keeps no per-entry gradient rows: every work item adds
+    its per-Gaussian sums to the record's gradient atomically.  The same camera + lidar step, in
+    the batched form and in the plain per-sensor form, with the limit at 0 (no rows) matches the
+    default (rows summed in a fixed order) to rounding, with identical forward outputs; the
+    workspace without rows is smaller."""
+    b = _binding()
+    rng = np.random.default_rng(31)
+    n = 3000
+    mu = np.stack([rng.uniform(2, 30, n), rng.uniform(-12, 12, n), rng.uniform(-2, 2, n)], 1)
+    g = S.random_gaussians(rng, mu, 19, rgb=True, moving_frac=0.5, log_scale_mean=-0.6)
+    G = b.GaussTensors.from_numpy(g)
+    cam = S.make_camera((0, 0, 0), 0.0, 200, 120, 150.0, t_rs=0.03, ego_vel_world=(3.0, 0, 0), n_channels=16)
+    lid = S.make_lidar((0, 0, 0), 0.0, 16, -15.0, 15.0, 256, tile_az=64, tile_el=8, t_sweep=0.1,
+                       ego_vel_world=(10.0, 1.0, 0), feat_offset=3, n_channels=8)
+    up = np.random.default_rng(32)
+    runs = {}
+    try:
+        for limit in (b.ADJOINT_ROW_LIMIT, 0):
+            b.set_adjoint_row_limit(limit)
+            rig = b.Rig([cam], [lid])
+            for batched in (True, False):
+                print(f"[rows] limit {limit}, batched {batched}", flush=True)
+                passes = [b.SensorPass(rig, 0, 2, g.n, 1, batched=True)] if batched else \
+                    [b.SensorPass(rig, k, 1, g.n, 1) for k in range(2)]
+                grads = b.zeros_like_grads(G)
+                outs = []
+                for sp in passes:
+                    sp.fit_capacity(G)
+                    sp.render(G)
+                    if "ups" not in runs:
+                        runs["ups"] = {}
+                    key = (sp.first, sp.count)
+                    if key not in runs["ups"]:
+                        runs["ups"][key] = [torch.from_numpy(a).cuda() for a in (
+                            up.normal(size=sp.n_feat).astype(np.float32),
+                            (0.1 * up.normal(size=sp.n_rays)).astype(np.float32),
+                            up.normal(size=sp.n_rays).astype(np.float32))]
+                    sp.raster_bwd(G, *runs["ups"][key], grads)
+                    outs.append(sp.outputs())
+                torch.cuda.synchronize()
+                ws = [int(rig.lib.splat_workspace_bytes(rig.handle, sp.first, sp.count, g.n, sp.k_cap)) for sp in passes]
+                runs[(limit, batched)] = ([{k: o[k].cpu().numpy() for k in ("feat", "depth", "alpha", "t_final")}
+                                           for o in outs],
+                                          {name: getattr(grads, name).cpu().numpy() for name in geo.Params.names}, ws)
+    finally:
+        b.set_adjoint_row_limit(b.ADJOINT_ROW_LIMIT)
+    for batched in (True, False):
+        o_r, g_r, ws_r = runs[(b.ADJOINT_ROW_LIMIT, batched)]
+        o_a, g_a, ws_a = runs[(0, batched)]
+        assert all(x <= y for x, y in zip(ws_a, ws_r)) and sum(ws_a) < sum(ws_r), (ws_a, ws_r)
+        for x, y in zip(o_a, o_r):
+            for key in x:
+                np.testing.assert_array_equal(x[key], y[key], err_msg=key)
+        for name in geo.Params.names:
+            assert np.abs(g_r[name]).max() > 0, name
+            bad = grad_mismatch(g_a[name], g_r[name], rtol=1e-4, afloor=1e-5)
+            assert not bad.any(), (batched, name, int(bad.sum()))
+
+
 def test_autograd_function_camera():
     b = _binding()
     g, cam = cam_scene(n=2000, W=96, H=64)

@@ -7,8 +7,8 @@ sampled rays:
   rays of every sensor, and gradients.  For the gradients the upstream gradient is nonzero only
   on the sampled rays, so the exact gradient is a sum over those rays that the oracle evaluates
   over all Gaussians, element by element.
-* C5 (3M Gaussians, 48 lidar sweeps of 32 / 64 / 128 beams and 12 cameras): forward values of
-  sampled rays, rendered as batched calls over sensor groups.
+* C5 (3M Gaussians, 48 lidar sweeps of 32 / 64 / 128 beams and 12 cameras) in one call per
+  stage (about 1.9e9 list entries): forward values of sampled rays and gradients, as above.
 
 Bars as in test_gpu_parity: 1e-5 + 1e-4 |ref| per rendered element on rays without a
 near-threshold decision; gradients within 1e-3 relative per tensor and per element."""
@@ -20,7 +20,7 @@ from oracle import geometry as geo
 from oracle import grad as ogr
 from oracle import render as rd
 from scenes import synthetic as S
-from tests.gpu_helpers import assert_grad_close, gpu_outputs, rtol_check
+from tests.gpu_helpers import assert_grad_close, gpu_outputs, grad_mismatch, rtol_check
 
 pytestmark = pytest.mark.gpu
 
@@ -112,37 +112,102 @@ def test_full_size_forward_and_gradients(cfg, rays):
         assert_grad_close(got[name].cpu().numpy(), ref[name], f"{cfg} {name}")
 
 
-def test_full_size_c5_forward():
-    """C5's 60 sensors hold more (tile, Gaussian) entries than one call's lists address (int32
-    positions), so the sweep renders as several batched calls over sensor groups: 6 cameras,
-    8 sweeps of 128 beams, and a mixed group of a camera with 32-beam sweeps."""
+def test_full_size_c5_one_call():
+    """C5's 60 sensors in one batched call per stage: about 1.9e9 (tile, Gaussian) entries (list
+    positions beyond 2^31), so the adjoint keeps no per-entry rows and adds atomically.  Forward
+    values of sampled rays of cameras and of 32-, 64- and 128-beam sweeps against the oracle,
+    one sensor against its own per-sensor call (bit-identical), and the gradients of upstream
+    gradients placed on the sampled rays only, element by element against the oracle."""
     b = _binding()
     sc = _config("c5")
+    g = sc.gaussians
     n_cam, n_lid = len(sc.cameras), len(sc.lidars)
-    print(f"[configs] {sc.name}: {sc.gaussians.n} Gaussians, {n_cam} cameras, {n_lid} lidars", flush=True)
+    print(f"[configs] {sc.name}: {g.n} Gaussians, {n_cam} cameras, {n_lid} lidars", flush=True)
     rig = b.Rig(sc.cameras, sc.lidars)
-    G = b.GaussTensors.from_numpy(sc.gaussians)
+    G = b.GaussTensors.from_numpy(g)
+    n_s = n_cam + n_lid
+    sp = b.SensorPass(rig, 0, n_s, g.n, 1, batched=True)
+    K = sp.fit_capacity(G, 1.05)
+    print(f"[configs] one call: {K} entries, capacity {sp.k_cap}", flush=True)
+    assert K <= sp.k_cap < (1 << 32) and sp.k_cap > b.ADJOINT_ROW_LIMIT
+    sp.status.zero_()
+    sp.render(G)
+    torch.cuda.synchronize()
+    st = b.read_status(sp.status)
+    assert st.overflow == 0 and st.n_nonfinite == 0
     rng = np.random.default_rng(505)
-    groups = [(0, 6), (n_cam + 32, 8), (n_cam - 1, 9)]
-    for first, count in groups:
-        sp = b.SensorPass(rig, first, count, sc.gaussians.n, 1, batched=True)
-        K = sp.fit_capacity(G, 1.1)
-        print(f"[configs] group [{first}, {first + count}): {K} entries", flush=True)
-        sp.status.zero_()
-        sp.render(G)
-        torch.cuda.synchronize()
-        st = b.read_status(sp.status)
-        assert st.overflow == 0 and st.n_nonfinite == 0
-        for k in (0, count - 1):
-            idx = np.sort(rng.choice(rig.sensors[first + k].n_rays, size=6, replace=False))
-            _check_forward_at(sp, rig, sc.gaussians, first, k, idx)
-        # the group's last sensor rendered by a per-sensor call: bit-identical
-        one = b.SensorPass(rig, first + count - 1, 1, sc.gaussians.n, 1)
-        one.fit_capacity(G, 1.1)
-        one.render(G)
-        torch.cuda.synchronize()
-        a_, p_ = gpu_outputs(sp, count - 1), gpu_outputs(one, 0)
-        for key in ("F", "D", "A", "T"):
-            np.testing.assert_array_equal(a_[key], p_[key], err_msg=f"group {first} {key}")
-        del sp, one
-        torch.cuda.empty_cache()
+    up = np.random.default_rng(506)
+    dF = np.zeros(sp.n_feat, np.float32)
+    dD = np.zeros(sp.n_rays, np.float32)
+    dA = np.zeros(sp.n_rays, np.float32)
+    sample = [0, n_cam - 1, n_cam, n_cam + 16, n_s - 1]   # cameras; sweeps of each beam group
+    picks = []
+    for k in sample:
+        sensor = rig.sensors[k]
+        idx = np.sort(rng.choice(sensor.n_rays, size=4, replace=False))
+        near = _check_forward(sp, rig, g, k, idx)
+        keep = idx[~near]
+        rs, fs, C = sp.sensor_slices(k)
+        dFk = up.normal(size=(len(keep), C)).astype(np.float32)
+        dDk = (0.1 * up.normal(size=len(keep))).astype(np.float32)
+        dAk = up.normal(size=len(keep)).astype(np.float32)
+        dF[fs.start:fs.stop].reshape(-1, C)[keep] = dFk
+        dD[rs.start + keep] = dDk
+        dA[rs.start + keep] = dAk
+        picks.append((sensor, keep, dFk, dDk, dAk))
+    # one sensor of the call against its own per-sensor call
+    one = b.SensorPass(rig, n_cam + 16, 1, g.n, 1)
+    one.fit_capacity(G, 1.1)
+    one.render(G)
+    torch.cuda.synchronize()
+    a_, p_ = gpu_outputs(sp, n_cam + 16), gpu_outputs(one, 0)
+    for key in ("F", "D", "A", "T"):
+        np.testing.assert_array_equal(a_[key], p_[key], err_msg=key)
+    del one
+    grads = b.zeros_like_grads(G)
+    t = lambda x: torch.from_numpy(x).cuda()
+    sp.raster_bwd(G, t(dF), t(dD), t(dA), grads)
+    torch.cuda.synchronize()
+    print("[configs] adjoint done; oracle gradients", flush=True)
+    per_pick = [ogr.reference_grads(g, sensor, keep, dFk, dDk, dAk)[0] for sensor, keep, dFk, dDk, dAk in picks]
+    ref = {n: sum(r[n] for r in per_pick) for n in geo.Params.names}
+    got = dict(means=grads.means, log_scales=grads.log_scales, quats=grads.quats, opacities=grads.opacities,
+               velocities=grads.velocities, features=grads.features)
+    n_ill = 0
+    for name in geo.Params.names:
+        gg = got[name].cpu().numpy().astype(np.float64)
+        assert_grad_close(gg, ref[name], f"c5 {name}", rtol=1e-3, afloor=1e-5, norm_tol=1e-3, per_element=False)
+        bad = grad_mismatch(gg, ref[name], rtol=1e-3, afloor=1e-5).reshape(g.n, -1)
+        rows = np.unique(np.nonzero(bad)[0])
+        assert len(rows) <= 4, (name, rows[:16])
+        for i in rows:
+            # An element outside the bar passes only if the FP64 oracle's own value for it moves by
+            # more than the GPU's error when the Gaussian's float32 inputs move by one ulp: the
+            # gradient is ill-conditioned at FP32 precision (seen for Gaussians a few decimetres
+            # outside a lidar's minimum range, whose angular footprint spans most of the sphere).
+            spread = _ulp_spread(g, picks, per_pick, int(i), name)
+            err = np.abs(gg.reshape(g.n, -1)[i] - ref[name].reshape(g.n, -1)[i])
+            print(f"[configs] c5 {name}: Gaussian {i} outside the bar: error {err.max():.3g}, oracle one-ulp "
+                  f"spread {spread.max():.3g}", flush=True)
+            assert (err <= 2.0 * spread).all(), (name, int(i), err, spread)
+            n_ill += 1
+    print(f"[configs] c5: {n_ill} ill-conditioned gradient rows", flush=True)
+
+
+def _ulp_spread(g, picks, per_pick, i, name):
+    """Largest change of the oracle's gradient `name` of Gaussian i when each of its float32
+    inputs (mean, log-scales, quaternion, opacity, velocity) moves one ulp up, or one ulp down."""
+    import copy
+    out = 0.0
+    for direction in (np.inf, -np.inf):
+        g2 = copy.deepcopy(g)
+        for f in ("means", "log_scales", "quats", "opacities", "velocities"):
+            a = getattr(g2, f)
+            if a is not None:
+                a[i] = np.nextafter(a[i], np.float32(direction))
+        for (sensor, keep, dFk, dDk, dAk), base in zip(picks, per_pick):
+            if not np.any(base[name].reshape(g.n, -1)[i]):
+                continue   # this sensor's rays give Gaussian i no gradient
+            r, _ = ogr.reference_grads(g2, sensor, keep, dFk, dDk, dAk)
+            out = np.maximum(out, np.abs(r[name].reshape(g.n, -1)[i] - base[name].reshape(g.n, -1)[i]))
+    return np.asarray(out)
