@@ -122,8 +122,7 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t x) {
 // Lane setup for one work item: a camera tile (all its pixels) or a chunk of <= 256 rays of a
 // lidar tile starting at position `pos` of ray_order (tile == n_tiles: rays outside every tile).
 template <bool LIDAR>
-__device__ __forceinline__ void setup_ray(const RasterArgs& a, int64_t tile, int pos, RayCtx& c) {
-  const int tid = threadIdx.x;
+__device__ __forceinline__ void setup_ray(const RasterArgs& a, int64_t tile, int pos, RayCtx& c, int tid) {
   if (!LIDAR) {
     c.s = sensor_of_tile(a.sens, a.count, tile);
     const DevSensor& S = a.sens[c.s];
@@ -278,7 +277,7 @@ __device__ __forceinline__ void fwd_item(const RasterArgs& a, const FwdOut& o, i
   constexpr int R4 = rec4(CMAX);
   static_assert(sizeof(sm.rec) / sizeof(sm.rec[0]) >= kFwdBatch * R4, "record staging");
   RayCtx c;
-  setup_ray<LIDAR>(a, tile, pos, c);
+  setup_ray<LIDAR>(a, tile, pos, c, threadIdx.x);
   float T = 1.f, D = 0.f, med = 0.f, los = 0.f;
   float F[CMAX];
 #pragma unroll
@@ -442,7 +441,13 @@ struct BwdShape {
   static constexpr int V = kNV + CMAX;   // values reduced per (ray, Gaussian)
 };
 
-constexpr int kBwdBatch = 128;
+// The adjoint runs a work item's 256 rays on 128 lanes (two wavefronts), two rays per lane: a
+// lane adds its two rays' values for a Gaussian before the wavefront reduction, which so runs
+// once per two (ray, Gaussian) pairs.  Camera: wavefront w covers pixel rows 8w .. 8w + 7 of the
+// 16 x 16 tile (its lanes' two 8 x 8 blocks); lidar: ray slots (2w + p) 64 + lane of the item.
+constexpr int kBwdLanes = 128;
+constexpr int kRpl = kBlock / kBwdLanes;   // rays per lane
+constexpr int kBwdBatch = 64;              // Gaussians staged per batch (one per lane of wavefront 0)
 
 template <int CMAX>
 struct BwdSmem {
@@ -473,48 +478,59 @@ template <int CMAX, bool LIDAR, bool TILE, typename SM>
 __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, int64_t tile, int pos, SM& sm) {
   using SH = BwdShape<CMAX>;
   constexpr int R4 = rec4(CMAX);
+  constexpr int P = kRpl;
   static_assert(SH::V <= 64, "channels");
   static_assert(sizeof(sm.acc) / sizeof(sm.acc[0]) >= SH::V, "accumulator rows");
   static_assert(sizeof(sm.rec) / sizeof(sm.rec[0]) >= kBwdBatch * R4, "record staging");
   auto& s_acc = sm.acc;
   int* s_used = sm.used;
-  RayCtx c;
-  setup_ray<LIDAR>(a, tile, pos, c);
-  if (LIDAR && c.invalid_bin) return;    // uniform over the workgroup (not timed)
-  const int tid = threadIdx.x, lane = tid & 63;
-  float T = 1.f, Tf = 1.f, dD = 0.f, dA = 0.f, bufD = 0.f, dlos = 0.f;
-  float dF[CMAX];
-  int last_l = 0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  RayCtx c[P];
 #pragma unroll
-  for (int k = 0; k < CMAX; ++k) dF[k] = 0.f;
-  if (c.valid) {
-    T = Tf = b.t_final[c.ray];
-    last_l = b.last[c.ray];
-    dD = b.dD[c.ray];
-    dA = b.dA[c.ray];
-    if (LIDAR && b.d_los) dlos = b.d_los[c.ray];
-    const float* g = b.dF + c.feat_off;
+  for (int p = 0; p < P; ++p) setup_ray<LIDAR>(a, tile, pos, c[p], (P * wave + p) * 64 + lane);
+  if (LIDAR && c[0].invalid_bin) return;    // uniform over the workgroup (not timed)
+  float T[P], dATf[P], dD[P], bufD[P], dlos[P], S_dot[P];
+  float dF[P][CMAX];
+  int last_l[P];
 #pragma unroll
-    for (int k = 0; k < CMAX; ++k)
-      if (k < c.C) dF[k] = g[k];
+  for (int p = 0; p < P; ++p) {
+    T[p] = 1.f;
+    float dA = 0.f;
+    dD[p] = bufD[p] = dlos[p] = S_dot[p] = 0.f;
+    last_l[p] = 0;
+#pragma unroll
+    for (int k = 0; k < CMAX; ++k) dF[p][k] = 0.f;
+    if (c[p].valid) {
+      T[p] = b.t_final[c[p].ray];
+      last_l[p] = b.last[c[p].ray];
+      dD[p] = b.dD[c[p].ray];
+      dA = b.dA[c[p].ray];
+      if (LIDAR && b.d_los) dlos[p] = b.d_los[c[p].ray];
+      const float* g = b.dF + c[p].feat_off;
+#pragma unroll
+      for (int k = 0; k < CMAX; ++k)
+        if (k < c[p].C) dF[p][k] = g[k];
+    }
+    dATf[p] = dA * T[p];
   }
-  const float dATf = dA * Tf;
   if (tid == 0) {
     sm.maxlast = 0;
     sm.toff = 0.f;
   }
-  for (int k = tid; k < SH::V * kBwdBatch; k += kBlock) (&s_acc[0][0])[k] = 0.f;
+  for (int k = tid; k < SH::V * kBwdBatch; k += kBwdLanes) (&s_acc[0][0])[k] = 0.f;
   if (tid < kBwdBatch) s_used[tid] = 0;
   __syncthreads();
-  if (last_l > 0) atomicMax(&sm.maxlast, last_l);
+  const int my_last = last_l[0] > last_l[1] ? last_l[0] : last_l[1];
+  if (my_last > 0) atomicMax(&sm.maxlast, my_last);
   __syncthreads();
   const int64_t n_proc = sm.maxlast;
   __syncthreads();           // everyone has read maxlast before it can be reset by the next item
   if (n_proc == 0) {         // uniform
-    stamp_done(b.sensor_done, c.s);
+    stamp_done(b.sensor_done, c[0].s);
     return;
   }
-  const DevSensor& S = a.sens[c.s];
+  const int64_t start = c[0].start;
+  const DevSensor& S = a.sens[c[0].s];
   const int64_t tile_local = tile - (S.tile_base - a.sens[0].tile_base);
   // a lidar tile with more rays than one item holds is shared by several items; without
   // per-entry rows every item adds atomically
@@ -528,76 +544,91 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
   bool my_store;
   const int my_slot = scatter_slot<VR>(lane, my_store);
   const int my_idx = (!LIDAR && my_slot >= kNV - 1) ? my_slot + 1 : my_slot;   // accumulator row
-  float S_dot = 0.f;   // sum_c buf_c dF_c, the feature part of the colour behind this Gaussian
-  float tacc = 0.f;    // camera: dL/dt of this ray's pairs (mean at time t moves with the velocity)
-  for (int64_t b0 = c.start + ((n_proc - 1) / kBwdBatch) * kBwdBatch; b0 >= c.start; b0 -= kBwdBatch) {
-    const int64_t b1 = (b0 + kBwdBatch < c.start + n_proc) ? b0 + kBwdBatch : c.start + n_proc;
-    if (tid < kBwdBatch) stage_batch<CMAX>(a, c, b0, b1, sm.rec);
+  float tacc = 0.f;    // camera: dL/dt of this lane's pairs (mean at time t moves with the velocity)
+  for (int64_t b0 = start + ((n_proc - 1) / kBwdBatch) * kBwdBatch; b0 >= start; b0 -= kBwdBatch) {
+    const int64_t b1 = (b0 + kBwdBatch < start + n_proc) ? b0 + kBwdBatch : start + n_proc;
+    if (tid < kBwdBatch) stage_batch<CMAX>(a, c[0], b0, b1, sm.rec);
     __syncthreads();
     const int nb = (int)(b1 - b0);
     for (int j = nb - 1; j >= 0; --j) {
       const float4* r = sm.rec + j * R4;
-      const int pos = (int)(b0 + j - c.start);
-      // an invalid lane has last_l = 0
-      bool act = pos < last_l;
-      uint64_t cand = lane_mask(act);
-      if (!TILE) {
-        const float4 bx = r[2];
-        const float bxa[4] = {bx.x, bx.y, bx.z, bx.w};
-        act = act && box_contains(LIDAR, c.px, c.py, bxa);
-        cand = LIDAR ? lane_mask(act) : cand & camera_box_mask(c.px, c.py, bx);
+      const int posj = (int)(b0 + j - start);
+      bool act[P];
+      uint64_t cand[P];
+      const float4 bx = r[2];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {   // an invalid lane has last_l = 0
+        act[p] = posj < last_l[p];
+        cand[p] = lane_mask(act[p]);
+        if (!TILE) {
+          const float bxa[4] = {bx.x, bx.y, bx.z, bx.w};
+          act[p] = act[p] && box_contains(LIDAR, c[p].px, c[p].py, bxa);
+          cand[p] = LIDAR ? lane_mask(act[p]) : cand[p] & camera_box_mask(c[p].px, c[p].py, bx);
+        }
       }
-      if (cand == 0) continue;
-      const float4 m = r[0], ce = r[1];
-      PairEval e;
-      eval_pair(LIDAR, c.px, c.py, c.t, m, ce, e);
-      const float alpha = clamp_alpha(e.oG);
-      const bool pass = alpha >= kAlphaMin;
-      if ((cand & lane_mask(pass)) == 0) continue;
-      act = act && pass;
-      // branch-free: inactive lanes use alpha_eff = 0 and contribute exact zeros
-      const float a_eff = act ? alpha : 0.f;
-      const float ra = act ? __builtin_amdgcn_rcpf(1.f - alpha) : 1.f;
-      T = T * ra;                         // transmittance in front of this Gaussian
-      const float w = a_eff * T;
+      if ((cand[0] | cand[1]) == 0) continue;
+      const float4 m = r[0], ce = r[1], d = r[3];
+      PairEval e[P];
+      float alpha[P];
+      uint64_t blend = 0;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        eval_pair(LIDAR, c[p].px, c[p].py, c[p].t, m, ce, e[p]);
+        alpha[p] = clamp_alpha(e[p].oG);
+        const bool pass = alpha[p] >= kAlphaMin;
+        blend |= cand[p] & lane_mask(pass);
+        act[p] = act[p] && pass;
+      }
+      if (blend == 0) continue;
       float v[SH::V];
-      float fd = 0.f;
 #pragma unroll
-      for (int c4 = 0; c4 < CMAX / 4; ++c4) {
-        const float4 f = r[4 + c4];
-        fd = SPLAT_FMA(f.x, dF[4 * c4 + 0], fd);
-        fd = SPLAT_FMA(f.y, dF[4 * c4 + 1], fd);
-        fd = SPLAT_FMA(f.z, dF[4 * c4 + 2], fd);
-        fd = SPLAT_FMA(f.w, dF[4 * c4 + 3], fd);
+      for (int k = 0; k < SH::V; ++k) v[k] = 0.f;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        // branch-free: inactive rays use alpha_eff = 0 and contribute exact zeros
+        const float a_eff = act[p] ? alpha[p] : 0.f;
+        const float ra = act[p] ? __builtin_amdgcn_rcpf(1.f - alpha[p]) : 1.f;
+        T[p] = T[p] * ra;                   // transmittance in front of this Gaussian
+        const float w = a_eff * T[p];
+        float fd = 0.f;
+#pragma unroll
+        for (int c4 = 0; c4 < CMAX / 4; ++c4) {
+          const float4 f = r[4 + c4];
+          fd = SPLAT_FMA(f.x, dF[p][4 * c4 + 0], fd);
+          fd = SPLAT_FMA(f.y, dF[p][4 * c4 + 1], fd);
+          fd = SPLAT_FMA(f.z, dF[p][4 * c4 + 2], fd);
+          fd = SPLAT_FMA(f.w, dF[p][4 * c4 + 3], fd);
+        }
+#pragma unroll
+        for (int k = 0; k < CMAX; ++k) v[kNV + k] = SPLAT_FMA(w, dF[p][k], v[kNV + k]);
+        const float gv = LIDAR ? SPLAT_FMA(d.y, c[p].t, d.x) : d.x;
+        const float fdS = fd - S_dot[p], gvB = gv - bufD[p];
+        const float acc = SPLAT_FMA(gvB, dD[p], fdS);
+        S_dot[p] = SPLAT_FMA(a_eff, fdS, S_dot[p]);
+        bufD[p] = SPLAT_FMA(a_eff, gvB, bufD[p]);
+        // line-of-sight sum: its upstream gradient adds directly to the alpha of Gaussians in front
+        float dalpha = SPLAT_FMA(T[p], acc, dATf[p] * ra);
+        if (LIDAR) dalpha += (gv < c[p].los_thr) ? dlos[p] : 0.f;
+        dalpha = act[p] ? dalpha : 0.f;
+        // Eq. alpha's clamp cuts the dependence on G; ga = dL/ds / ln 2 with s = log2 G
+        const bool clamped = e[p].oG > kAlphaMax;
+        const float ga = clamped ? 0.f : dalpha * e[p].oG;
+        const float dg = w * dD[p];
+        const float e0 = ga * SPLAT_FMA(ce.x, e[p].dx, e[p].tx);
+        const float e1 = ga * SPLAT_FMA(d.z, e[p].dx, e[p].cy);
+        v[0] += e0;
+        v[1] += e1;
+        v[2] = SPLAT_FMA(e0, c[p].t, v[2]);
+        v[3] = SPLAT_FMA(e1, c[p].t, v[3]);
+        const float gx = ga * e[p].dx;
+        v[4] = SPLAT_FMA(gx, e[p].dx, v[4]);
+        v[5] = SPLAT_FMA(gx, e[p].dy, v[5]);
+        v[6] = SPLAT_FMA(ga * e[p].dy, e[p].dy, v[6]);
+        v[7] += clamped ? 0.f : dalpha * e[p].G;
+        v[8] += dg;
+        if (LIDAR) v[9] = SPLAT_FMA(dg, c[p].t, v[9]);
+        if (!LIDAR) tacc = SPLAT_FMA(e0, m.z, SPLAT_FMA(e1, d.w, tacc));
       }
-#pragma unroll
-      for (int k = 0; k < CMAX; ++k) v[kNV + k] = w * dF[k];
-      const float4 d = r[3];
-      const float gv = LIDAR ? SPLAT_FMA(d.y, c.t, d.x) : d.x;
-      const float fdS = fd - S_dot, gvB = gv - bufD;
-      const float acc = SPLAT_FMA(gvB, dD, fdS);
-      S_dot = SPLAT_FMA(a_eff, fdS, S_dot);
-      bufD = SPLAT_FMA(a_eff, gvB, bufD);
-      // line-of-sight sum: its upstream gradient adds directly to the alpha of Gaussians in front
-      float dalpha = SPLAT_FMA(T, acc, dATf * ra);
-      if (LIDAR) dalpha += (gv < c.los_thr) ? dlos : 0.f;
-      dalpha = act ? dalpha : 0.f;
-      // Eq. alpha's clamp cuts the dependence on G; ga = dL/ds / ln 2 with s = log2 G
-      const bool clamped = e.oG > kAlphaMax;
-      const float ga = clamped ? 0.f : dalpha * e.oG;
-      const float dg = w * dD;
-      v[0] = ga * SPLAT_FMA(ce.x, e.dx, e.tx);
-      v[1] = ga * SPLAT_FMA(d.z, e.dx, e.cy);
-      v[2] = v[0] * c.t;
-      v[3] = v[1] * c.t;
-      const float gx = ga * e.dx;
-      v[4] = gx * e.dx;
-      v[5] = gx * e.dy;
-      v[6] = (ga * e.dy) * e.dy;
-      v[7] = clamped ? 0.f : dalpha * e.G;
-      v[8] = dg;
-      v[9] = LIDAR ? dg * c.t : 0.f;
-      if (!LIDAR) tacc = SPLAT_FMA(v[0], m.z, SPLAT_FMA(v[1], d.w, tacc));
       float r_own;
       if constexpr (LIDAR) {
         r_own = wave_reduce_scatter<VR>(v);
@@ -613,7 +644,7 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
     __syncthreads();
     if (tid < nb && s_used[tid]) {
       const int64_t g = a.gauss[b0 + tid];
-      const int64_t rec = (int64_t)c.s * a.N + g;
+      const int64_t rec = (int64_t)c[0].s * a.N + g;
       b.rflag[rec] = 1;   // idempotent: every writer stores the same byte
       if (!split) {
         // this item is the only one of its tile: the entry's row is complete, store it
@@ -634,7 +665,7 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
         float* fp = b.dfeat + g * a.c_total + S.feat_off;
 #pragma unroll
         for (int k = 0; k < CMAX; ++k)
-          if (k < c.C) atomicAdd(fp + k, s_acc[kNV + k][tid]);
+          if (k < c[0].C) atomicAdd(fp + k, s_acc[kNV + k][tid]);
       }
 #pragma unroll
       for (int k = 0; k < SH::V; ++k) s_acc[k][tid] = 0.f;
@@ -648,13 +679,13 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
     for (int d = 32; d >= 1; d >>= 1) tacc += __shfl_xor(tacc, d, 64);
     if (lane == 0) atomicAdd(&sm.toff, tacc);
     __syncthreads();
-    if (tid == 0) atomicAdd(b.d_toff + c.s, sm.toff);
+    if (tid == 0) atomicAdd(b.d_toff + c[0].s, sm.toff);
   }
-  stamp_done(b.sensor_done, c.s);
+  stamp_done(b.sensor_done, c[0].s);
 }
 
 template <int CMAX, bool LIDAR, bool TILE>
-__global__ __launch_bounds__(kBlock) void k_raster_bwd(RasterArgs a, BwdIn b) {
+__global__ __launch_bounds__(kBwdLanes) void k_raster_bwd(RasterArgs a, BwdIn b) {
   __shared__ BwdSmem<CMAX> sm;
   if (!LIDAR) {
     bwd_item<CMAX, false, TILE>(a, b, blockIdx.x, 0, sm);
@@ -668,7 +699,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(RasterArgs a, BwdIn b) {
 // at least 4 waves per SIMD (at most 128 VGPRs): the register allocator otherwise drifts above
 // that bound as the item code grows, and the lost occupancy costs more than it saves
 template <int CMC, int CML, bool TILE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(kBwdLanes) __attribute__((amdgpu_waves_per_eu(3)))
 void k_raster_bwd_queue(RasterArgs a, BwdIn b, int32_t* counter) {
   __shared__ BwdSmem<cmax_max(CMC, CML)> sm;
   __shared__ int s_slot;
@@ -719,16 +750,16 @@ static void fwd_dispatch(dim3 grid, hipStream_t s, int support, const RasterArgs
 template <int CMAX, bool LIDAR>
 static void bwd_dispatch(dim3 grid, hipStream_t s, int support, const RasterArgs& a, const BwdIn& b) {
   if (support == SPLAT_SUPPORT_TILE)
-    hipLaunchKernelGGL((k_raster_bwd<CMAX, LIDAR, true>), grid, dim3(kBlock), 0, s, a, b);
+    hipLaunchKernelGGL((k_raster_bwd<CMAX, LIDAR, true>), grid, dim3(kBwdLanes), 0, s, a, b);
   else
-    hipLaunchKernelGGL((k_raster_bwd<CMAX, LIDAR, false>), grid, dim3(kBlock), 0, s, a, b);
+    hipLaunchKernelGGL((k_raster_bwd<CMAX, LIDAR, false>), grid, dim3(kBwdLanes), 0, s, a, b);
 }
 
 // persistent grid: as many workgroups as can be resident at once, capped by the item capacity
 template <typename K>
-static unsigned persistent_grid(K kernel, const CallView& v, int64_t items) {
+static unsigned persistent_grid(K kernel, const CallView& v, int64_t items, int block) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1) per_cu = 1;
   int64_t g = (int64_t)per_cu * (v.n_cu > 0 ? v.n_cu : 256);
   if (g > items) g = items;
   return (unsigned)(g < 1 ? 1 : g);
@@ -738,14 +769,14 @@ template <int CMC, int CML, bool TILE>
 static void fwd_queue_launch(const CallView& v, int64_t items, hipStream_t s, const RasterArgs& a, const FwdOut& o,
                              int32_t* counter) {
   auto k = k_raster_fwd_queue<CMC, CML, TILE>;
-  hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items)), dim3(kBlock), 0, s, a, o, counter);
+  hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items, kBlock)), dim3(kBlock), 0, s, a, o, counter);
 }
 
 template <int CMC, int CML, bool TILE>
 static void bwd_queue_launch(const CallView& v, int64_t items, hipStream_t s, const RasterArgs& a, const BwdIn& b,
                              int32_t* counter) {
   auto k = k_raster_bwd_queue<CMC, CML, TILE>;
-  hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items)), dim3(kBlock), 0, s, a, b, counter);
+  hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items, kBwdLanes)), dim3(kBwdLanes), 0, s, a, b, counter);
 }
 
 // Channel buckets of the persistent kernels: the cameras' and the lidars' (a call's lidars with
