@@ -308,6 +308,9 @@ def main():
         out["modes"][m]["step_ms"] = r["step_ms"]
     if not (args.no_configs or args.profile_steps):
         out["configs"] = {f"C{k}": config_bench(args, dev, k) for k in (1, 2, 3, 4)}
+        # C5 in its batched form only (one call per stage for all 60 sensors): 60 plain passes at
+        # once would hold a list and an adjoint workspace per sensor, beyond the GPU's memory
+        out["configs"]["C5"] = c5_latency(args, dev, parity_sensors=[0, 11, 12, 28, 59])
     if not args.no_compose:
         out["compose"] = compose_bench(args, dev)
         out["points_to_rays"] = points_bench(args, dev, lid)
@@ -462,7 +465,31 @@ def roofline(results, tiles):
                         "frac": round(flop_fwd / t_fwd / 1e12 / PEAK_FP32_TFLOPS, 4)}}
 
 
-def c5_latency(args, dev):
+def c5_parity(sc, sp, first, sensors, rays=4):
+    """Forward outputs of `rays` sampled rays of each listed sensor (rig index) against the oracle."""
+    from oracle import render as rd
+    rig_sensors = list(sc.cameras) + list(sc.lidars)
+    prng = np.random.default_rng(1905)
+    worst, near, n = 0.0, 0, 0
+    o = sp.outputs()
+    for k in sensors:
+        s_ = rig_sensors[k]
+        idx = np.sort(prng.choice(s_.n_rays, size=rays, replace=False))
+        ref = rd.render_sensor(sc.gaussians, s_, idx)
+        rs, fs, C = sp.sensor_slices(k - first)
+        ok = ~ref["near"]
+        near += int((~ok).sum())
+        n += len(idx)
+        for a, r in ((o["feat"][fs].reshape(-1, C)[idx], ref["F"]), (o["depth"][rs][idx], ref["D"]),
+                     (o["alpha"][rs][idx], ref["A"])):
+            a, r = a.cpu().numpy(), r.numpy()
+            err = np.abs(a[ok] - r[ok]) / (1e-5 + 1e-4 * np.abs(r[ok]))
+            worst = max(worst, float(err.max()) if err.size else 0.0)
+    return {"rays": n, "sensors": list(sensors), "near_excluded": near, "max_err_over_tol": round(worst, 4),
+            "pass": bool(worst <= 1.0)}
+
+
+def c5_latency(args, dev, parity_sensors=None):
     """The sweep workload: 3M Gaussians, 48 lidar sweeps (16 each of 32, 64 and 128 beams,
     1024-2048 azimuth steps) and 12 1080p cameras, all 60 sensors in one batched call per stage
     (persistent rasterisers; about 1.9e9 list entries, so the adjoint keeps no per-entry rows).
@@ -524,6 +551,8 @@ def c5_latency(args, dev):
             raise SystemExit(f"C5 group {first}: overflow")
         rays_total += sp.n_rays
         log(f"C5 group [{first}, {first + count}): {K} entries, {sp.n_rays} rays")
+        if parity_sensors:   # the last step's outputs against the oracle on sampled rays
+            parity = c5_parity(sc, sp, first, parity_sensors)
         del sp, grads
         torch.cuda.empty_cache()
     pct = lambda v, q: round(float(np.percentile(np.asarray(v), q)), 4)
@@ -532,6 +561,9 @@ def c5_latency(args, dev):
            "config": {"workload": "3M Gaussians, 48 lidar sweeps (16 x 32 / 64 / 128 beams, 1024-2048 az) + "
                                   "12 RS cameras 1920x1080", "calls_per_step": len(groups),
                       "groups": [list(g_) for g_ in groups], "rays_per_step": rays_total}}
+    if parity_sensors:
+        out["parity"] = parity
+        log(f"C5 parity {parity}")
     for phase in ("fwd", "fwd_bwd"):
         out[phase] = {"ms_per_step": round(ms[phase], 4), "Mrays_per_s": round(rays_total / (ms[phase] * 1e-3) / 1e6, 3),
                       "latency_ms": {k: {"p50": pct(v, 50), "p99": pct(v, 99), "n": len(v)}
