@@ -315,7 +315,7 @@ __device__ __forceinline__ int64_t sort_count(const int64_t* n_ptr, int64_t n_ca
   return n < n_cap ? n : n_cap;
 }
 
-// Per-block digit counts of one 4096-key tile, counted with LDS atomics into one histogram per
+// Per-block digit counts of one kRadixTile-key tile, counted with LDS atomics into one histogram per
 // wavefront (order does not matter for counting), written block-major: hist[block * 256 + d].
 // Blocks past the key count write nothing (nothing reads their counts).
 template <typename K>
@@ -324,20 +324,20 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
   __shared__ uint32_t cnt[4][kRadixBins];
   const int tid = threadIdx.x, wid = tid >> 6;
   const int64_t n = sort_count(n_ptr, n_cap);
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
   if (base >= n) return;   // uniform
   cnt[0][tid] = cnt[1][tid] = cnt[2][tid] = cnt[3][tid] = 0;
   __syncthreads();
   const uint32_t mask = (1u << bits) - 1u;
-  uint32_t d[kScanItems];
+  uint32_t d[kRadixItems];
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
+  for (int r = 0; r < kRadixItems; ++r) {
     const int64_t i = base + (int64_t)r * kScanThreads + tid;
     const uint32_t x = (uint32_t)(keys[i < n ? i : n - 1] >> shift) & mask;   // unconditional load
     d[r] = i < n ? x : 0xFFFFFFFFu;
   }
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r)
+  for (int r = 0; r < kRadixItems; ++r)
     if (d[r] != 0xFFFFFFFFu) atomicAdd(&cnt[wid][d[r]], 1u);
   __syncthreads();
   hist[(int64_t)blockIdx.x * kRadixBins + tid] = cnt[0][tid] + cnt[1][tid] + cnt[2][tid] + cnt[3][tid];
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t* __restrict__ hi
                                                        int64_t n_cap, uint32_t* __restrict__ coltotal) {
   __shared__ uint32_t tmp[4];
   const int d = blockIdx.x;
-  const int64_t nb = (sort_count(n_ptr, n_cap) + kScanTile - 1) / kScanTile;
+  const int64_t nb = (sort_count(n_ptr, n_cap) + kRadixTile - 1) / kRadixTile;
   uint32_t carry = 0;
   for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
     const int64_t b = b0 + threadIdx.x;
@@ -362,8 +362,8 @@ __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t* __restrict__ hi
   if (threadIdx.x == 0) coltotal[d] = carry;
 }
 
-// Stable scatter of one block tile (4096 keys).  Wavefront w owns the contiguous quarter
-// [1024 w, 1024 w + 1024) of the tile and walks it in 16 rounds of 64 keys: ballot matching of
+// Stable scatter of one block tile (kRadixTile keys).  Wavefront w owns the contiguous quarter
+// of the tile and walks it in kRadixItems rounds of 64 keys: ballot matching of
 // the digit gives each key its rank among the round's equal digits, and a wave-private running
 // count per digit (LDS, touched only by that wavefront) carries the rank across rounds.  One
 // block scan then turns (digit, wavefront) counts into offsets, keys are staged in LDS in digit
@@ -376,18 +376,18 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
                                                        const int64_t* n_ptr, int64_t n_cap, int shift, int bits,
                                                        const uint32_t* __restrict__ hist,
                                                        const uint32_t* __restrict__ coltotal) {
-  constexpr int kPerWave = kScanTile / 4;
-  __shared__ K s_k[kScanTile];
-  __shared__ V s_v[kScanTile];
+  constexpr int kPerWave = kRadixTile / 4;
+  __shared__ K s_k[kRadixTile];
+  __shared__ V s_v[kRadixTile];
   __shared__ uint32_t gbase[kRadixBins];
   __shared__ uint32_t lcum[kRadixBins];
   __shared__ uint32_t wc[4][kRadixBins];   // per-wavefront running counts, then offsets
   __shared__ uint32_t tmp[4];
   const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
   const int64_t n = sort_count(n_ptr, n_cap);
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
   if (base >= n) return;   // uniform over the block
-  const int cnt = (int)((n - base) < kScanTile ? (n - base) : kScanTile);
+  const int cnt = (int)((n - base) < kRadixTile ? (n - base) : kRadixTile);
   const uint32_t mask = (1u << bits) - 1u;
   const uint64_t lt = lanemask_lt();
   {
@@ -396,11 +396,11 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     gbase[tid] = dstart + hist[(int64_t)blockIdx.x * kRadixBins + tid];
   }
   wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
-  K key[kScanItems];
-  V val[kScanItems];
-  uint32_t rank[kScanItems];
+  K key[kRadixItems];
+  V val[kRadixItems];
+  uint32_t rank[kRadixItems];
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
+  for (int r = 0; r < kRadixItems; ++r) {
     const int li = wid * kPerWave + r * 64 + lane;
     const int lc = li < cnt ? li : cnt - 1;   // unconditional loads; lanes past cnt are invalid below
     key[r] = kin[base + lc];
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   __syncthreads();
   uint32_t* run = wc[wid];
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
+  for (int r = 0; r < kRadixItems; ++r) {
     const bool valid = wid * kPerWave + r * 64 + lane < cnt;
     const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
     const uint64_t m = match_digit(d, valid);
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   wc[3][tid] = dcum + c0 + c1 + c2;
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
+  for (int r = 0; r < kRadixItems; ++r) {
     if (wid * kPerWave + r * 64 + lane < cnt) {
       const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
       const uint32_t li = wc[wid][d] + rank[r];
@@ -473,7 +473,7 @@ static hipError_t radix_sort(K* k[2], V* v[2], int& cur, const int64_t* n_ptr, i
   if (total_bits < 1) total_bits = 1;
   const int passes = (total_bits + kRadixBits - 1) / kRadixBits;
   const int per = radix_pass_bits(total_bits);   // bits spread evenly over the passes
-  const int64_t nb = div_up(n_cap, kScanTile);
+  const int64_t nb = div_up(n_cap, kRadixTile);
   if (nb == 0) return hipSuccess;
   for (int p = 0; p < passes; ++p) {
     const int shift = lo_bit + p * per;
@@ -1164,7 +1164,7 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   int64_t nr = n_rays < 1 ? 1 : n_rays;
   int64_t max_n = nrec > kc ? nrec : kc;
   max_n = max_n > nr ? max_n : nr;
-  int64_t max_blocks = div_up(max_n, kScanTile);
+  int64_t max_blocks = div_up(max_n, kRadixTile);
   for (int i = 0; i < 2; ++i) w.dkeys[i] = (uint64_t*)take(nrec * 8);
   for (int i = 0; i < 2; ++i) w.dvals[i] = (uint32_t*)take(nrec * 4);
   w.coff = (int64_t*)take(nrec * 8);

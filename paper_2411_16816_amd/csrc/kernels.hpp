@@ -13,6 +13,10 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;     // 4096 elements per block
 constexpr int kRadixBits = 8;
+// radix sort tiles: 2048 keys per 256-thread block (8 per thread); smaller than the scans' so
+// that a few million keys still spread over several blocks per compute unit
+constexpr int kRadixItems = 8;
+constexpr int kRadixTile = kScanThreads * kRadixItems;
 constexpr int kRadixBins = 1 << kRadixBits;
 
 inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
