@@ -165,10 +165,11 @@ typedef struct SplatProjected {
   float* box;       /* [n_records,4] lo_u, lo_v, hi_u, hi_v of the 3-sigma + RS box          */
   float* dv;        /* [n_records,2] depth (z | range) and range velocity (lidar; 0 camera)    */
   unsigned long long* dkey; /* [n_records] IEEE bits of the depth (z | range) evaluated in
-                       float64 from the float32 inputs.  Gaussians are ordered by the 40-bit
-                       key (e << 35) | (mantissa >> 17), e = binary exponent + 16 clamped to
-                       [0, 31] (key 0 below 2^-16, all ones from 2^16 on): 2^-35 relative
-                       resolution; equal keys keep Gaussian-id order                        */
+                       float64 from the float32 inputs.  Gaussians are ordered by the 32-bit
+                       key (e << 27) | (mantissa >> 25), e = binary exponent + 16 clamped to
+                       [0, 31] (key 0 below 2^-16, all ones from 2^16 on): 2^-27 relative
+                       resolution (a float32 depth has 2^-24); equal keys keep Gaussian-id
+                       order                                                                */
   int32_t* rect;    /* [n_records,4] tiles: camera (x0, y0, nx, ny); lidar (az0, el0, naz, nel) */
   int32_t* n_tiles; /* [n_records] tiles touched (0 = culled)                                 */
 } SplatProjected;
@@ -243,7 +244,10 @@ int splat_check_camera(const SplatCamera* cam);
 int splat_check_lidar(const SplatLidar* lidar);
 
 /* ---- rig -------------------------------------------------------------------------------
- * splat_rig_create allocates the rig's device table (not a hot-path call).  splat_rig_set
+ * splat_rig_create allocates the rig's device table, and a second stream (default priority)
+ * with two events on the current device, onto which bin/sort forks the ray binning for the
+ * length of the call (not a hot-path call).  One rig's calls are issued from one host thread
+ * at a time: they share that stream and those events.  splat_rig_set
  * validates the sensors on the host and uploads them asynchronously on `stream` from pinned
  * host memory (it waits only for the rig's previous upload).  Cameras get sensor ids
  * 0..n_cameras-1, lidars n_cameras..n_cameras+n_lidars-1. */
@@ -290,7 +294,9 @@ int splat_project_lidar(const SplatGaussians* g, const SplatRig* rig, int32_t fi
  * of a stable (tile | depth) key sort) with per-tile [start, end) ranges into gauss.  The
  * lists of different tiles are laid out in an order of the library's choosing (tile_range
  * says where each is).  The lidar variant also bins the supplied rays into their tiles (a ray
- * is a box of zero extent, App. A) and cuts every tile's rays into work items of <= 256 rays.
+ * is a box of zero extent, App. A) and cuts every tile's rays into work items of <= 256 rays;
+ * that part reads no Gaussian data and runs on the rig's second stream, forked from `stream`
+ * at the start of the call and joined back before it ends (graph capture included).
  * More than k_cap (tile, Gaussian) pairs: every list is left empty (memory-safe),
  * status->overflow is set and status->n_isect holds the needed capacity. */
 int splat_bin_sort_camera(const SplatRig* rig, int32_t first, int32_t count, int64_t n_gaussians,

@@ -49,7 +49,7 @@ T_STOP = 1e-4
 NEAR_BOX = 2e-6      # box edges, relative to |mean| + extent
 NEAR_ALPHA = 2e-5    # alpha against 1/255 and 0.99
 NEAR_T = 1e-4        # transmittance against the stop (1e-4) and the median (1/2) levels
-NEAR_DEPTH = 1e-10   # depth ties between two Gaussians that both pass the skip rule (an ordering
+NEAR_DEPTH = 1e-8    # depth ties between two Gaussians that both pass the skip rule (an ordering
                      # key of finite precision may order such a pair either way)
 
 

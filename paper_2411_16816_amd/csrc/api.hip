@@ -16,6 +16,9 @@ struct SplatRig {
   DevSensor* h_pinned = nullptr;    // pinned staging for asynchronous uploads
   std::vector<DevSensor> host;      // host copy used for launch configuration
   hipEvent_t uploaded = nullptr;
+  // bin/sort's side stream (default priority) and its fork / join events
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   bool upload_pending = false;
   bool is_set = false;
   int n_cu = 0;                     // compute units of the rig's device (persistent grids)
@@ -99,6 +102,12 @@ int splat_rig_create(int32_t n_cameras, int32_t n_lidars, SplatRig** out) {
     delete r;
     return SPLAT_ERR_DEVICE;
   }
+  if (hipStreamCreateWithFlags(&r->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&r->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&r->join, hipEventDisableTiming) != hipSuccess) {
+    splat_rig_destroy(r);
+    return SPLAT_ERR_DEVICE;
+  }
   memset(&r->layout, 0, sizeof(r->layout));
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -112,6 +121,9 @@ void splat_rig_destroy(SplatRig* r) {
   if (!r) return;
   if (r->upload_pending) (void)hipEventSynchronize(r->uploaded);
   (void)hipEventDestroy(r->uploaded);
+  if (r->join) (void)hipEventDestroy(r->join);
+  if (r->fork) (void)hipEventDestroy(r->fork);
+  if (r->side) (void)hipStreamDestroy(r->side);
   (void)hipFree(r->d_table);
   (void)hipHostFree(r->h_pinned);
   delete r;
@@ -204,6 +216,9 @@ static int make_view(const SplatRig* r, int32_t first, int32_t count, int kind, 
   v.lidar = (kind == kLidar);
   v.queue = (kind < 0);
   v.n_cu = r->n_cu;
+  v.side = r->side;
+  v.fork = r->fork;
+  v.join = r->join;
   if ((int64_t)count * n_gauss >= ((int64_t)1 << 32)) return SPLAT_ERR_UNSUPPORTED;
   // the capped ray sort keys are (lidar bin, 16-bit priority) in 32 bits
   if (v.ray_cap && v.n_tiles + 1 - v.lidar_tile0 > 65536) return SPLAT_ERR_UNSUPPORTED;

@@ -4,7 +4,7 @@
 // Pipeline of one call (all on the stream, no host synchronisation):
 //   1. one scan over the records in record order counts the visible records and their
 //      (tile, Gaussian) entries, gives each visible record its entry numbers (the adjoint's
-//      gradient rows) and compacts the visible records with a 40-bit key of their float64 depth;
+//      gradient rows) and compacts the visible records with a 32-bit key of their float64 depth;
 //   2. the visible records are stably sorted by that key, so equal keys keep record
 //      (= Gaussian id) order;
 //   3. tiles are grouped into supertiles of 8 x 8 tiles; a scan in depth order gives every
@@ -19,6 +19,7 @@
 //      from sorting (tile | depth) keys, while only the compact supertile entries are sorted;
 //   6. lidar: rays are binned into their tiles (a ray is a box of zero extent, App. A), invalid
 //      rays go to an extra bin, and every tile's rays are cut into work items of <= 256 rays.
+//      This reads no Gaussian data: with a side stream it runs beside steps 1-5.
 //
 // The radix sort is an LDS-histogram reduce-then-scan sort with 8-bit digits: per-block digit
 // histograms (wavefront ballots aggregate equal digits before LDS atomics), a device-wide
@@ -47,8 +48,6 @@ hipError_t fill(T* p, int64_t n, T v, hipStream_t s) {
 
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) { return fill<float>(p, n, v, s); }
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) { return fill<int32_t>(p, n, v, s); }
-
-__global__ void k_copy_i64(const int64_t* __restrict__ src, int64_t* __restrict__ dst) { *dst = *src; }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   int lane = threadIdx.x & 63;
@@ -190,6 +189,17 @@ struct NoVisit {
   __device__ void finish(T) const {}
 };
 
+// Writes the grand total to *dst (no per-element work).
+struct StoreTotal {
+  int64_t* dst;
+  struct In {};
+  template <typename T>
+  __device__ In load(int64_t, T) const { return In{}; }
+  template <typename T>
+  __device__ void operator()(int64_t, T, T, In) const {}
+  __device__ void finish(int64_t total) const { *dst = total; }
+};
+
 // Block b: exclusive scan of its tile, offset by the total of the blocks before it: with
 // `fused`, the sum of the block totals part[0..b) (read by the block itself; the closing block
 // writes the grand total to part[nb]), otherwise part[b] as scanned by k_scan_partials.  Every
@@ -285,7 +295,9 @@ hipError_t device_scan(Load ld, int64_t n, T* out, T* part, hipStream_t s, Visit
     hipLaunchKernelGGL((k_scan_empty<T, Visit>), dim3(1), dim3(1), 0, s, part, vis);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL((k_scan_reduce<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, n_dev, part);
+  // one block needs no block totals (the fused down-sweep sums none before block 0)
+  if (nb > 1)
+    hipLaunchKernelGGL((k_scan_reduce<T, Load>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, n_dev, part);
   const bool fused = nb <= kScanFusedBlocks;
   if (!fused) hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(256), 0, s, part, nb);
   hipLaunchKernelGGL((k_scan_down<T, Load, Visit>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, ld, n, n_dev, part,
@@ -508,16 +520,17 @@ __device__ __forceinline__ int64_t local_tile_base(const DevSensor* sens, int s)
   return sens[s].tile_base - sens[0].tile_base;
 }
 
-// 40-bit sort key of a positive float64 depth: 5 bits of binary exponent over [2^-16, 2^16)
-// and the top 35 mantissa bits (2^-35 relative resolution), monotone in the depth; depths
-// outside that range clamp to the first / last key (ties then keep Gaussian-id order).
-constexpr int kDepthKeyBits = 40;
+// 32-bit sort key of a positive float64 depth: 5 bits of binary exponent over [2^-16, 2^16)
+// and the top 27 mantissa bits (2^-27 relative resolution, 8x finer than a float32 depth),
+// monotone in the depth; depths outside that range clamp to the first / last key (ties then
+// keep Gaussian-id order).  Four 8-bit radix passes.
+constexpr int kDepthKeyBits = 32;
 
 __device__ __forceinline__ uint64_t depth_sort_key(unsigned long long bits) {
   const int e = (int)((bits >> 52) & 0x7FF) - (1023 - 16);
   if (e < 0) return 0ull;
   if (e > 31) return (1ull << kDepthKeyBits) - 1ull;
-  return ((uint64_t)e << 35) | ((bits & 0xFFFFFFFFFFFFFull) >> 17);
+  return ((uint64_t)e << 27) | ((bits & 0xFFFFFFFFFFFFFull) >> 25);
 }
 
 // Device scalars of one bin/sort call (workspace `scalars`).
@@ -705,7 +718,8 @@ __device__ __forceinline__ void coarse_entry(const DevSensor& S, uint32_t st0, c
 // Visible record i (depth order) writes its (local supertile, record) entries from its offset
 // coff[i] on.  Each lane writes the first kEmitOwn entries of its own record; the entries
 // beyond that of the wavefront's larger records are then written by the whole wavefront, one
-// record at a time, 64 entries per step.
+// record at a time, 64 entries per step.  The grid also empties the n_st supertile ranges
+// ([0, 0)), which the ranges pass after the supertile sort fills in.
 constexpr int kEmitOwn = 4;
 
 __global__ __launch_bounds__(256) void k_coarse_emit(const DevSensor* __restrict__ sens, int count, int64_t N,
@@ -713,9 +727,10 @@ __global__ __launch_bounds__(256) void k_coarse_emit(const DevSensor* __restrict
                                                      const int64_t* __restrict__ coff,
                                                      const int64_t* __restrict__ scalars, int64_t n_cap,
                                                      uint32_t* __restrict__ ckeys, uint64_t* __restrict__ cvals,
-                                                     int64_t cap) {
+                                                     int64_t cap, uint32_t* __restrict__ crange, int64_t n_st) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
+  for (int64_t z = i; z < 2 * n_st; z += (int64_t)gridDim.x * blockDim.x) crange[z] = 0u;
   const bool valid = i < n_cap && i < scalars[kScVisible] && scalars[kScCoarse] != 0;
   uint32_t rec = 0, gid = 0;
   int64_t q0 = 0;
@@ -1039,11 +1054,13 @@ __device__ __forceinline__ int sensor_of_ray(const DevSensor* sens, int count, i
 // lidar rays [r0, r0 + n) of the call -> (key, ray id) pairs at [0, n); key = ((bin - t0) <<
 // cell_bits) | cell, bin = the ray's tile (n_tiles: outside every tile), t0 = the call's first
 // lidar tile, cell = ray_cell_code inside the tile (0 outside), or the ray's 16-bit priority
-// when its lidar caps the rays per tile (training time)
+// when its lidar caps the rays per tile (training time).  The grid also empties the n_bins ray
+// ranges ([0, 0)), which the ranges pass after the ray sort fills in.
 __global__ void k_ray_keys(const DevSensor* __restrict__ sens, int count, int64_t r0, int64_t n, int64_t n_tiles,
                            int64_t t0, int cell_bits, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                           SplatStatus* st) {
+                           SplatStatus* st, int32_t* __restrict__ ray_range, int64_t n_bins) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t z = q; z < 2 * n_bins; z += (int64_t)gridDim.x * blockDim.x) ray_range[z] = 0;
   if (q >= n) return;
   const int64_t r = r0 + q;
   int s = sensor_of_ray(sens, count, r);
@@ -1180,6 +1197,8 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   w.xpart = (uint32_t*)take((div_up(xcap, kScanTile) + 2) * 4);
   w.hist = (uint32_t*)take((size_t)kRadixBins * max_blocks * 4 + 64);
   w.coltotal = (uint32_t*)take(kRadixBins * 4);
+  w.rhist = (uint32_t*)take((size_t)kRadixBins * div_up(nr, kRadixTile) * 4 + 64);
+  w.rcoltotal = (uint32_t*)take(kRadixBins * 4);
   for (int i = 0; i < 2; ++i) w.rkeys[i] = (uint32_t*)take(nr * 4);
   for (int i = 0; i < 2; ++i) w.rvals[i] = (uint32_t*)take(nr * 4);
   const int64_t wcap = work_capacity(n_tiles, nr) + 1;
@@ -1206,11 +1225,63 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   return w;
 }
 
+// 6. lidar rays -> tiles; work item counts and offsets; work items (lidar chunks, and camera
+//    tiles in the batched form; there into qtmp, ordered by the queue pass).  Reads no Gaussian
+//    data, so it may run on a stream of its own beside steps 1-5.
+static hipError_t launch_ray_bins(const CallView& v, const SplatTileLists& L, const Workspace& w, SplatStatus* st,
+                                  hipStream_t s) {
+  hipError_t e;
+  const int64_t bins = v.n_tiles + 1;
+  const int64_t r0 = v.lidar_ray0;
+  const int64_t nr = v.n_rays - r0;
+  if (nr > 0) {
+    // rays grouped by tile, and inside a tile in Z-order of their cells (compact work items);
+    // the cell code fills the unused bits of the bin's last radix digit, so it adds no pass
+    // (under the training-time cap 16 bits of priority take its place, and add passes)
+    const int64_t t0 = v.lidar_tile0;
+    const int bin_bits = bits_for(bins - t0);
+    const int cell_bits = v.ray_cap ? 16 : ray_cell_bits(bin_bits);   // make_view keeps bin_bits <= 16
+    hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)div_up(nr, 256)), dim3(256), 0, s, v.sens, v.count, r0, nr,
+                       v.n_tiles, t0, cell_bits, w.rkeys[0], w.rvals[0], st, L.ray_range, bins);
+    uint32_t* rk[2] = {w.rkeys[0], w.rkeys[1]};
+    uint32_t* rv[2] = {w.rvals[0], w.rvals[1]};
+    int rcur = 0;
+    if ((e = radix_sort<uint32_t, uint32_t>(rk, rv, rcur, nullptr, nr, 0, bin_bits + cell_bits, w.rhist,
+                                            w.rcoltotal, (uint32_t*)L.ray_order, s)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_ranges<int2>, dim3((unsigned)div_up(nr, 256 * kRangeItems)), dim3(256), 0, s,
+                       (const uint32_t*)rk[rcur], (const int64_t*)nullptr, nr, (int2*)L.ray_range, cell_bits, t0);
+  } else if ((e = fill<int32_t>(L.ray_range, 2 * bins, 0, s)) != hipSuccess) {
+    return e;
+  }
+  hipLaunchKernelGGL(k_work_count, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, v.sens, v.count,
+                     (const int2*)L.ray_range, v.n_tiles, w.wcount);
+  // per-bin offsets, and the total behind them for k_work_emit
+  if ((e = device_scan<int64_t>(LoadI64{w.wcount}, bins, w.wcount, w.wpart, s, StoreTotal{w.wcount + bins})) !=
+      hipSuccess)
+    return e;
+  int2* wdst = v.queue ? w.qtmp : (int2*)L.work;
+  hipLaunchKernelGGL(k_work_emit, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, v.sens, v.count,
+                     (const int2*)L.ray_range, v.n_tiles, (const int64_t*)w.wcount, L.work_cap, wdst, L.n_work);
+  return hipGetLastError();
+}
+
 hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const SplatTileLists& L, const Workspace& w,
                            SplatStatus* st, hipStream_t s) {
   const int64_t n_rec = (int64_t)v.count * v.n_gauss;
   hipError_t e;
   int64_t* const sc = w.scalars;
+  // 6. first, so that it overlaps the rest: on the side stream, forked from the call's stream
+  const bool rays = v.has_lidar || v.queue;
+  const bool fork = rays && v.side && v.fork && v.join;
+  if (rays) {
+    if (fork) {
+      if ((e = hipEventRecord(v.fork, s)) != hipSuccess || (e = hipStreamWaitEvent(v.side, v.fork, 0)) != hipSuccess)
+        return e;
+    }
+    if ((e = launch_ray_bins(v, L, w, st, fork ? v.side : s)) != hipSuccess) return e;
+    if (fork && (e = hipEventRecord(v.join, v.side)) != hipSuccess) return e;
+  }
   // 1. one record-order scan of (visible, tile count): entry bases, the visible records'
   //    packed depth keys compacted in record order, the counts and the overflow status
   if ((e = device_scan<P64>(LoadVisibleTiles{p.n_tiles}, n_rec, (P64*)nullptr, (P64*)w.scan_part, s,
@@ -1218,7 +1289,7 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
                                          (const unsigned long long*)p.dkey, L.entry_base, w.dkeys[0], w.dvals[0], sc,
                                          L.k_cap, st})) != hipSuccess)
     return e;
-  // 2. stable sort of the visible records by the 40-bit depth key (ties keep record order)
+  // 2. stable sort of the visible records by the 32-bit depth key (ties keep record order)
   uint64_t* dk[2] = {w.dkeys[0], w.dkeys[1]};
   uint32_t* dvv[2] = {w.dvals[0], w.dvals[1]};
   int cur = 0;
@@ -1230,24 +1301,25 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   if ((e = device_scan<int64_t>(LoadPackedCount{dk[cur], sc + kScVisible}, n_rec, w.coff, (int64_t*)w.scan_part, s,
                                 CoarseCount{sc, L.k_cap}, sc + kScVisible)) != hipSuccess)
     return e;
+  const int64_t n_st = v.n_supertiles;
   if (n_rec > 0)
     hipLaunchKernelGGL(k_coarse_emit, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, v.sens, v.count, v.n_gauss,
                        (const int4*)p.rect, (const uint32_t*)dvv[cur], (const int64_t*)w.coff, (const int64_t*)sc, n_rec,
-                       w.ckeys[0], w.cvals[0], L.k_cap);
+                       w.ckeys[0], w.cvals[0], L.k_cap, (uint32_t*)w.crange, n_st);
+  else if ((e = fill<int32_t>((int32_t*)w.crange, 2 * n_st, 0, s)) != hipSuccess)   // [0, 0): empty
+    return e;
   // 4. stable sort of the entries by supertile: each supertile's records stay in depth order
-  const int64_t n_st = v.n_supertiles;
   uint32_t* ck[2] = {w.ckeys[0], w.ckeys[1]};
   uint64_t* cv[2] = {w.cvals[0], w.cvals[1]};
   int ccur = 0;
   if ((e = radix_sort<uint32_t, uint64_t>(ck, cv, ccur, sc + kScCoarse, L.k_cap, 0, bits_for(n_st), w.hist, w.coltotal,
                                 nullptr, s)) != hipSuccess)
     return e;
-  if ((e = fill<int32_t>((int32_t*)w.crange, 2 * n_st, 0, s)) != hipSuccess) return e;   // [0, 0): empty
   if (L.k_cap > 0)
     hipLaunchKernelGGL(k_ranges<uint2>, dim3((unsigned)div_up(L.k_cap, 256 * kRangeItems)), dim3(256), 0, s,
                        (const uint32_t*)ck[ccur], (const int64_t*)(sc + kScCoarse), L.k_cap, w.crange, 0, (int64_t)0);
   // 5. items of <= kItemEntries entries per supertile; per item and tile the entry counts; their
-  //    scan gives every tile's list range and every item its first positions; placement
+  //    scan gives every tile its list range and every item its first positions; placement
   if ((e = device_scan<int64_t>(LoadItemCount{w.crange, n_st}, n_st + 1, w.item_first, (int64_t*)w.scan_part, s,
                                 ItemsVisit{sc})) != hipSuccess)
     return e;
@@ -1281,53 +1353,22 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
     hipLaunchKernelGGL((k_st_place<kStLogLidar, kStLogLidar>), dim3((unsigned)grid), dim3(256), 0, s, v.sens, cvs,
                        (const uint2*)w.crange, (const int64_t*)w.item_first, (const uint2*)w.item_st, st_cam, n_st,
                        (const uint32_t*)w.xcount, L.k_cap, L.gauss, (longlong2*)L.tile_range);
-  // 6. lidar rays -> tiles; work items (lidar chunks, and camera tiles in the batched form)
-  if (v.has_lidar || v.queue) {
+  // join the ray binning; the batched form then orders its work items by cost
+  if (fork && (e = hipStreamWaitEvent(s, v.join, 0)) != hipSuccess) return e;
+  if (v.queue) {
     const int64_t bins = v.n_tiles + 1;
-    const int64_t r0 = v.lidar_ray0;
-    const int64_t nr = v.n_rays - r0;
-    if ((e = fill<int32_t>(L.ray_range, 2 * bins, 0, s)) != hipSuccess) return e;
-    if (nr > 0) {
-      // rays grouped by tile, and inside a tile in Z-order of their cells (compact work items);
-      // the cell code fills the unused bits of the bin's last radix digit, so it adds no pass
-      // (under the training-time cap 16 bits of priority take its place, and add passes)
-      const int64_t t0 = v.lidar_tile0;
-      const int bin_bits = bits_for(bins - t0);
-      const int cell_bits = v.ray_cap ? 16 : ray_cell_bits(bin_bits);   // make_view keeps bin_bits <= 16
-      hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)div_up(nr, 256)), dim3(256), 0, s, v.sens, v.count, r0, nr,
-                         v.n_tiles, t0, cell_bits, w.rkeys[0], w.rvals[0], st);
-      uint32_t* rk[2] = {w.rkeys[0], w.rkeys[1]};
-      uint32_t* rv[2] = {w.rvals[0], w.rvals[1]};
-      int rcur = 0;
-      if ((e = radix_sort<uint32_t, uint32_t>(rk, rv, rcur, nullptr, nr, 0, bin_bits + cell_bits, w.hist, w.coltotal,
-                                    (uint32_t*)L.ray_order, s)) != hipSuccess)
-        return e;
-      hipLaunchKernelGGL(k_ranges<int2>, dim3((unsigned)div_up(nr, 256 * kRangeItems)), dim3(256), 0, s, (const uint32_t*)rk[rcur],
-                         (const int64_t*)nullptr, nr, (int2*)L.ray_range, cell_bits, t0);
-    }
-    hipLaunchKernelGGL(k_work_count, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, v.sens, v.count,
-                       (const int2*)L.ray_range, v.n_tiles, w.wcount);
-    if ((e = device_scan<int64_t>(LoadI64{w.wcount}, bins, w.wcount, w.wpart, s)) != hipSuccess) return e;
-    // the total lands in wpart[nb]; copy it behind the per-bin offsets for k_work_emit
-    const int64_t wnb = div_up(bins, kScanTile);
-    hipLaunchKernelGGL(k_copy_i64, dim3(1), dim3(1), 0, s, (const int64_t*)(w.wpart + wnb), w.wcount + bins);
-    int2* wdst = v.queue ? w.qtmp : (int2*)L.work;
-    hipLaunchKernelGGL(k_work_emit, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, v.sens, v.count,
-                       (const int2*)L.ray_range, v.n_tiles, (const int64_t*)w.wcount, L.work_cap, wdst, L.n_work);
-    if (v.queue) {
-      const int64_t wcap = L.work_cap;
-      hipLaunchKernelGGL(k_queue_keys, dim3((unsigned)div_up(wcap, 256)), dim3(256), 0, s, (const int2*)w.qtmp,
-                         (const int32_t*)L.n_work, (const longlong2*)L.tile_range, v.n_tiles, w.qkeys[0], w.qvals[0]);
-      uint32_t* qk[2] = {w.qkeys[0], w.qkeys[1]};
-      uint32_t* qv[2] = {w.qvals[0], w.qvals[1]};
-      int qcur = 0;
-      // item count: the scan total (clamped to the capacity by the sort)
-      if ((e = radix_sort<uint32_t, uint32_t>(qk, qv, qcur, w.wcount + bins, wcap, 0, 8, w.hist, w.coltotal, nullptr, s)) !=
-          hipSuccess)
-        return e;
-      hipLaunchKernelGGL(k_queue_gather, dim3((unsigned)div_up(wcap, 256)), dim3(256), 0, s, (const int2*)w.qtmp,
-                         (const uint32_t*)qv[qcur], (const int32_t*)L.n_work, (int2*)L.work);
-    }
+    const int64_t wcap = L.work_cap;
+    hipLaunchKernelGGL(k_queue_keys, dim3((unsigned)div_up(wcap, 256)), dim3(256), 0, s, (const int2*)w.qtmp,
+                       (const int32_t*)L.n_work, (const longlong2*)L.tile_range, v.n_tiles, w.qkeys[0], w.qvals[0]);
+    uint32_t* qk[2] = {w.qkeys[0], w.qkeys[1]};
+    uint32_t* qv[2] = {w.qvals[0], w.qvals[1]};
+    int qcur = 0;
+    // item count: the scan total (clamped to the capacity by the sort)
+    if ((e = radix_sort<uint32_t, uint32_t>(qk, qv, qcur, w.wcount + bins, wcap, 0, 8, w.hist, w.coltotal, nullptr, s)) !=
+        hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_queue_gather, dim3((unsigned)div_up(wcap, 256)), dim3(256), 0, s, (const int2*)w.qtmp,
+                       (const uint32_t*)qv[qcur], (const int32_t*)L.n_work, (int2*)L.work);
   }
   return hipGetLastError();
 }

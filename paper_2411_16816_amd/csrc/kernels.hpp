@@ -58,6 +58,10 @@ struct CallView {
   int64_t lidar_tile0;     // local id of the first lidar tile
   int c_max;               // max n_channels over the call
   int n_cu;                // compute units of the device (persistent grid)
+  // second stream of the rig's device and two events: bin/sort forks the ray binning (which
+  // reads no Gaussian data) onto it and joins it back before the queue; null: one stream
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 inline int64_t work_capacity(int64_t n_tiles, int64_t n_rays) {
@@ -80,6 +84,8 @@ struct Workspace {
   uint32_t* xpart;
   uint32_t* hist;         // [256 * max_blocks + partials]
   uint32_t* coltotal;     // [256] digit totals of a radix pass
+  uint32_t* rhist;        // the ray sort's own histograms and digit totals (it may run beside the
+  uint32_t* rcoltotal;    // record sorts, on the side stream)
   uint32_t* rkeys[2];     // [n_rays]
   uint32_t* rvals[2];
   int64_t* wcount;        // [n_tiles + 2]

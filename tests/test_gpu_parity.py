@@ -129,12 +129,12 @@ def test_project_lidar():
 # a3 / a4: binning and sorting, bit-exact against the stage check
 # ------------------------------------------------------------------------------------------
 def depth_sort_key(bits):
-    """The library's documented 40-bit ordering key of float64 depth bits (splat.h, dkey)."""
+    """The library's documented 32-bit ordering key of float64 depth bits (splat.h, dkey)."""
     bits = np.asarray(bits, np.uint64)
     e = ((bits >> np.uint64(52)) & np.uint64(0x7FF)).astype(np.int64) - (1023 - 16)
-    key = (np.clip(e, 0, 31).astype(np.uint64) << np.uint64(35)) | ((bits & np.uint64(0xFFFFFFFFFFFFF)) >> np.uint64(17))
+    key = (np.clip(e, 0, 31).astype(np.uint64) << np.uint64(27)) | ((bits & np.uint64(0xFFFFFFFFFFFFF)) >> np.uint64(25))
     key = np.where(e < 0, np.uint64(0), key)
-    return np.where(e > 31, np.uint64((1 << 40) - 1), key)
+    return np.where(e > 31, np.uint64((1 << 32) - 1), key)
 
 
 def ray_cell_codes_f32(lid, n_bins):
