@@ -328,7 +328,8 @@ __device__ __forceinline__ int64_t sort_count(const int64_t* n_ptr, int64_t n_ca
 }
 
 // Per-block digit counts of one kRadixTile-key tile, counted with LDS atomics into one histogram per
-// wavefront (order does not matter for counting), written block-major: hist[block * 256 + d].
+// wavefront (order does not matter for counting), written digit-major: hist[d * nb + block] with
+// nb = the grid's block count, so that the per-digit scans over the blocks read contiguous runs.
 // Blocks past the key count write nothing (nothing reads their counts).
 template <typename K>
 __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, const int64_t* n_ptr, int64_t n_cap,
@@ -352,23 +353,24 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
   for (int r = 0; r < kRadixItems; ++r)
     if (d[r] != 0xFFFFFFFFu) atomicAdd(&cnt[wid][d[r]], 1u);
   __syncthreads();
-  hist[(int64_t)blockIdx.x * kRadixBins + tid] = cnt[0][tid] + cnt[1][tid] + cnt[2][tid] + cnt[3][tid];
+  hist[(int64_t)tid * gridDim.x + blockIdx.x] = cnt[0][tid] + cnt[1][tid] + cnt[2][tid] + cnt[3][tid];
 }
 
 // One block per digit d: exclusive scan of the digit's counts over the blocks that hold keys
-// (in place), and the digit's total.
+// (in place, row d of the nb_grid-wide digit-major table), and the digit's total.
 __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t* __restrict__ hist, const int64_t* n_ptr,
-                                                       int64_t n_cap, uint32_t* __restrict__ coltotal) {
+                                                       int64_t n_cap, int64_t nb_grid, uint32_t* __restrict__ coltotal) {
   __shared__ uint32_t tmp[4];
   const int d = blockIdx.x;
   const int64_t nb = (sort_count(n_ptr, n_cap) + kRadixTile - 1) / kRadixTile;
+  uint32_t* row = hist + (int64_t)d * nb_grid;
   uint32_t carry = 0;
   for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
     const int64_t b = b0 + threadIdx.x;
-    const uint32_t x = b < nb ? hist[b * kRadixBins + d] : 0u;
+    const uint32_t x = b < nb ? row[b] : 0u;
     uint32_t total;
     const uint32_t ex = block_exclusive_scan<uint32_t>(x, tmp, total);
-    if (b < nb) hist[b * kRadixBins + d] = carry + ex;
+    if (b < nb) row[b] = carry + ex;
     carry += total;
   }
   if (threadIdx.x == 0) coltotal[d] = carry;
@@ -405,7 +407,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   {
     uint32_t dtot;
     const uint32_t dstart = block_exclusive_scan<uint32_t>(coltotal[tid], tmp, dtot);
-    gbase[tid] = dstart + hist[(int64_t)blockIdx.x * kRadixBins + tid];
+    gbase[tid] = dstart + hist[(int64_t)tid * gridDim.x + blockIdx.x];
   }
   wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
   K key[kRadixItems];
@@ -492,7 +494,7 @@ static hipError_t radix_sort(K* k[2], V* v[2], int& cur, const int64_t* n_ptr, i
     const int bits = (total_bits - p * per) < per ? (total_bits - p * per) : per;
     hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(256), 0, s, (const K*)k[cur], n_ptr, n_cap, shift,
                        bits, hist);
-    hipLaunchKernelGGL(k_radix_colscan, dim3(kRadixBins), dim3(256), 0, s, hist, n_ptr, n_cap, coltotal);
+    hipLaunchKernelGGL(k_radix_colscan, dim3(kRadixBins), dim3(256), 0, s, hist, n_ptr, n_cap, nb, coltotal);
     V* vdst = (p == passes - 1 && final_vals) ? final_vals : v[1 - cur];
     hipLaunchKernelGGL((k_radix_scatter<K, V>), dim3((unsigned)nb), dim3(256), 0, s, (const K*)k[cur], (const V*)v[cur],
                        k[1 - cur], vdst, n_ptr, n_cap, shift, bits, (const uint32_t*)hist, (const uint32_t*)coltotal);
@@ -1179,8 +1181,10 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   int64_t nrec = n_rec < 1 ? 1 : n_rec;
   int64_t kc = k_cap < 1 ? 1 : k_cap;
   int64_t nr = n_rays < 1 ? 1 : n_rays;
+  // the longest sort sharing `hist`: records, coarse entries or queue entries
+  const int64_t wq = work_capacity(n_tiles, nr) + 1;
   int64_t max_n = nrec > kc ? nrec : kc;
-  max_n = max_n > nr ? max_n : nr;
+  max_n = max_n > wq ? max_n : wq;
   int64_t max_blocks = div_up(max_n, kRadixTile);
   for (int i = 0; i < 2; ++i) w.dkeys[i] = (uint64_t*)take(nrec * 8);
   for (int i = 0; i < 2; ++i) w.dvals[i] = (uint32_t*)take(nrec * 4);
@@ -1357,7 +1361,10 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   if (fork && (e = hipStreamWaitEvent(s, v.join, 0)) != hipSuccess) return e;
   if (v.queue) {
     const int64_t bins = v.n_tiles + 1;
-    const int64_t wcap = L.work_cap;
+    // the work items never exceed work_capacity (the workspace's queue buffers and histograms
+    // are sized for that many), whatever larger capacity the lists declare
+    const int64_t wmax = work_capacity(v.n_tiles, v.n_rays) + 1;
+    const int64_t wcap = L.work_cap < wmax ? L.work_cap : wmax;
     hipLaunchKernelGGL(k_queue_keys, dim3((unsigned)div_up(wcap, 256)), dim3(256), 0, s, (const int2*)w.qtmp,
                        (const int32_t*)L.n_work, (const longlong2*)L.tile_range, v.n_tiles, w.qkeys[0], w.qvals[0]);
     uint32_t* qk[2] = {w.qkeys[0], w.qkeys[1]};
