@@ -381,6 +381,36 @@ def test_batched_equals_plain():
             np.testing.assert_array_equal(a[key], p[key])
 
 
+def test_batched_few_gaussians_many_work_items():
+    """A batched call whose work items outnumber its records, its list capacity and its rays (40
+    Gaussians, one 1920x1080 camera of 8160 tiles, no lidar): the queue's sort still fits the
+    workspace, every camera tile is queued once, and the forward equals the per-sensor call."""
+    b = _binding()
+    g, _ = cam_scene(n=40)
+    cam = S.make_camera((0, 0, 1.5), 3.0, 1920, 1080, 1400.0, t_rs=0.03, ego_vel_world=(12.0, 0.5, 0.0),
+                        n_channels=16)
+    rig = b.Rig([cam], [])
+    G = b.GaussTensors.from_numpy(g)
+    bat = b.SensorPass(rig, 0, 1, g.n, 1, batched=True)
+    bat.fit_capacity(G)
+    assert bat.k_cap < bat.n_tiles and g.n < bat.n_tiles and bat.n_rays == 1920 * 1080
+    bat.render(G)
+    torch.cuda.synchronize()
+    assert b.read_status(bat.status).overflow == 0
+    nw = int(bat.n_work.cpu()[0])
+    work = bat.work.cpu().numpy()[:nw]
+    assert sorted(work[:, 0].tolist()) == list(range(bat.n_tiles))
+    sp = b.SensorPass(rig, 0, 1, g.n, 1)
+    sp.fit_capacity(G)
+    sp.render(G)
+    torch.cuda.synchronize()
+    a_ = gpu_outputs(bat, 0)
+    p_ = gpu_outputs(sp, 0)
+    assert np.any(p_["A"] > 0)
+    for key in ("F", "D", "A", "T", "last"):
+        np.testing.assert_array_equal(a_[key], p_[key])
+
+
 def queue_length_code(lens):
     """The library's documented queue bucket of a list length (binsort.hip, length_code):
     4 bits of binary exponent and 4 bits of mantissa of min(len, 2^20 - 1) + 1."""
