@@ -319,11 +319,13 @@ int splat_rasterize_fwd_lidar(const SplatGaussians* g, const SplatRig* rig, int3
 /* ---- a8: batched form.  The same four steps for any mix of the rig's sensors in one call
  * (cameras and lidars together): one projection launch reading every Gaussian once for all
  * sensors; one bin/sort over every sensor's tiles that also builds a global work queue of
- * camera tiles and lidar ray chunks ordered by descending list length; and persistent
- * rasterisers (forward and adjoint) whose workgroups drain that queue.  Lists need ray_order
- * (if any lidar), ray_range, work and n_work.  Results are bit-identical to the per-sensor
- * calls (BOX support).  Gradients agree with the per-sensor calls to float rounding: a
- * workgroup adds its four wavefronts' partial sums in LDS in scheduling order. */
+ * camera tiles and lidar ray chunks (the lidar chunks first, then the camera tiles, each part
+ * ordered by descending list length); and persistent rasterisers (forward and adjoint) whose
+ * workgroups drain that queue.  A call over a single sensor (count == 1) runs that sensor's
+ * per-kind kernels instead (no queue; work holds lidar chunks only, as in the per-kind call).
+ * Lists need ray_order (if any lidar), ray_range, work and n_work.  Results are bit-identical
+ * to the per-sensor calls (BOX support).  Gradients agree with the per-sensor calls to float
+ * rounding: a workgroup adds its wavefronts' partial sums in LDS in scheduling order. */
 int splat_project(const SplatGaussians* g, const SplatRig* rig, int32_t first, int32_t count,
                   const SplatProjected* out, SplatStatus* status, void* stream);
 int splat_bin_sort(const SplatRig* rig, int32_t first, int32_t count, int64_t n_gaussians,

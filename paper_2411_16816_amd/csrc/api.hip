@@ -213,8 +213,11 @@ static int make_view(const SplatRig* r, int32_t first, int32_t count, int kind, 
     v.lidar_ray0 = v.n_rays;
     v.lidar_tile0 = v.n_tiles;
   }
-  v.lidar = (kind == kLidar);
-  v.queue = (kind < 0);
+  // a batched call over a single sensor runs that sensor's per-kind kernels: with one sensor the
+  // queue has nothing to balance, and a plain grid walks the tiles in image order
+  const bool single = kind < 0 && count == 1;
+  v.lidar = (kind == kLidar) || (single && v.host[0].kind == kLidar);
+  v.queue = kind < 0 && count > 1;
   v.n_cu = r->n_cu;
   v.side = r->side;
   v.fork = r->fork;

@@ -1131,9 +1131,15 @@ __global__ void k_work_emit(const DevSensor* __restrict__ sens, int count, const
     if (o < work_cap) work[o] = make_int2((int)t, p);
 }
 
-// Longest-processing-time order of the persistent queue: items sorted (stably) by descending
-// length of their tile's Gaussian list, in buckets of about 6 %: the key is 255 minus an 8-bit
-// log-scale code of the length (4 bits of exponent, 4 bits of mantissa).
+// Order of the persistent queue: longest processing time first, sorted (stably) by the
+// descending estimated cost of an item, from an 8-bit log-scale code of its tile list length (4
+// bits of exponent, 4 of mantissa: buckets of about 6 %).  Two forms:
+//   grouped (the adjoint keeps per-entry rows): the lidar items, then the camera items, each
+//     part by cost (key (camera << 7) | (127 - code / 2)): each kind's records stay hot in
+//     cache while its items run;
+//   mixed (the adjoint adds every pair atomically): one cost order over both kinds, a lidar
+//     chunk's list counted 4x longer (key 255 - min(255, code + 32 if lidar)): interleaving the
+//     kinds spreads the atomic traffic over the kernel's run.
 __device__ __forceinline__ uint32_t length_code(int64_t len) {
   const uint32_t x = (uint32_t)(len < 0xFFFFF ? len : 0xFFFFF) + 1u;   // >= 1
   const int e = 31 - __clz(x);                                       // 0..20
@@ -1142,9 +1148,10 @@ __device__ __forceinline__ uint32_t length_code(int64_t len) {
   return c < 255u ? c : 255u;
 }
 
+// tiles [0, lidar_tile0) are camera tiles (cameras precede lidars in a call)
 __global__ void k_queue_keys(const int2* __restrict__ work, const int32_t* __restrict__ n_work,
-                             const longlong2* __restrict__ tile_range, int64_t n_tiles, uint32_t* __restrict__ keys,
-                             uint32_t* __restrict__ vals) {
+                             const longlong2* __restrict__ tile_range, int64_t n_tiles, int64_t lidar_tile0,
+                             bool grouped, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= *n_work) return;
   int64_t t = work[i].x;
@@ -1153,7 +1160,14 @@ __global__ void k_queue_keys(const int2* __restrict__ work, const int32_t* __res
     const longlong2 r = tile_range[t];
     len = r.y - r.x;
   }
-  keys[i] = 255u - length_code(len);
+  const bool camera = t < lidar_tile0;
+  const uint32_t c = length_code(len);
+  if (grouped) {
+    keys[i] = (camera ? 128u : 0u) | (127u - (c >> 1));
+  } else {
+    const uint32_t w = c + (camera ? 0u : 32u);
+    keys[i] = 255u - (w < 255u ? w : 255u);
+  }
   vals[i] = (uint32_t)i;
 }
 
@@ -1225,6 +1239,7 @@ Workspace carve_workspace(void* base, int64_t n_rec, int64_t k_cap, int64_t n_ti
   w.long_cap = w.rows ? long_part_cap(nrec, kc) : 1;
   w.long_list = (uint32_t*)take((size_t)kLongParts * w.long_cap * 8);
   w.n_long = (int32_t*)take(kLongParts * 4);
+  w.qctr = (int32_t*)take(4);
   w.bytes = off > sort_bytes ? off : sort_bytes;
   return w;
 }
@@ -1366,7 +1381,8 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
     const int64_t wmax = work_capacity(v.n_tiles, v.n_rays) + 1;
     const int64_t wcap = L.work_cap < wmax ? L.work_cap : wmax;
     hipLaunchKernelGGL(k_queue_keys, dim3((unsigned)div_up(wcap, 256)), dim3(256), 0, s, (const int2*)w.qtmp,
-                       (const int32_t*)L.n_work, (const longlong2*)L.tile_range, v.n_tiles, w.qkeys[0], w.qvals[0]);
+                       (const int32_t*)L.n_work, (const longlong2*)L.tile_range, v.n_tiles, v.lidar_tile0, w.rows,
+                       w.qkeys[0], w.qvals[0]);
     uint32_t* qk[2] = {w.qkeys[0], w.qkeys[1]};
     uint32_t* qv[2] = {w.qvals[0], w.qvals[1]};
     int qcur = 0;

@@ -103,6 +103,7 @@ struct Workspace {
   uint8_t* rflag;         // [n_rec] 1 = the adjoint produced a gradient for the record
   uint32_t* long_list;    // [kLongParts * long_cap] (record, chunk) pairs of long touched records
   int32_t* n_long;        // [kLongParts] partition counts
+  int32_t* qctr;          // [1] queue counter of the persistent adjoint
   int64_t long_cap;       // records per partition
   int stride;             // slot_stride(cmax_bucket(c_max))
   size_t bytes;

@@ -696,20 +696,28 @@ __global__ __launch_bounds__(kBwdLanes) void k_raster_bwd(RasterArgs a, BwdIn b)
   }
 }
 
-// at least 4 waves per SIMD (at most 128 VGPRs): the register allocator otherwise drifts above
-// that bound as the item code grows, and the lost occupancy costs more than it saves
-template <int CMC, int CML, bool TILE>
-__global__ __launch_bounds__(kBwdLanes) __attribute__((amdgpu_waves_per_eu(3)))
-void k_raster_bwd_queue(RasterArgs a, BwdIn b, int32_t* counter) {
+// Item kinds an adjoint queue kernel renders (the queue holds its lidar items first and its
+// n_cam camera items last).  A kernel compiled for one kind gets that kind's register
+// allocation: the camera code fits 128 VGPRs (4 waves per SIMD); the lidar code, and a kernel
+// holding both, take up to 168 (3 waves per SIMD).
+enum : int { kItemsCamera = 1, kItemsLidar = 2, kItemsBoth = 3 };
+
+template <int CMC, int CML, bool TILE, int KINDS>
+__global__ __launch_bounds__(kBwdLanes) __attribute__((amdgpu_waves_per_eu(KINDS == kItemsCamera ? 4 : 3)))
+void k_raster_bwd_queue(RasterArgs a, BwdIn b, int32_t* counter, int n_cam) {
   __shared__ BwdSmem<cmax_max(CMC, CML)> sm;
   __shared__ int s_slot;
   const int n_items = a.n_work[0];
+  const int lo = KINDS == kItemsCamera ? n_items - n_cam : 0;   // this kernel's part of the queue
+  const int hi = KINDS == kItemsLidar ? n_items - n_cam : n_items;
   for (;;) {
-    const int it = next_item(counter, &s_slot);
-    if (it >= n_items) break;
+    const int it = lo + next_item(counter, &s_slot);
+    if (it >= hi) break;
     const int2 w = a.work[it];
-    if (item_is_lidar(a, w.x)) bwd_item<CML, true, TILE>(a, b, w.x, w.y, sm);
-    else bwd_item<CMC, false, TILE>(a, b, w.x, 0, sm);
+    if (KINDS == kItemsLidar || (KINDS == kItemsBoth && item_is_lidar(a, w.x)))
+      bwd_item<CML, true, TILE>(a, b, w.x, w.y, sm);
+    else
+      bwd_item<CMC, false, TILE>(a, b, w.x, 0, sm);
   }
 }
 
@@ -772,11 +780,23 @@ static void fwd_queue_launch(const CallView& v, int64_t items, hipStream_t s, co
   hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items, kBlock)), dim3(kBlock), 0, s, a, o, counter);
 }
 
+// The adjoint over the queue: one persistent kernel, compiled for the call's item kinds (a call
+// of cameras only, or of lidars only, gets that kind's register allocation).
 template <int CMC, int CML, bool TILE>
-static void bwd_queue_launch(const CallView& v, int64_t items, hipStream_t s, const RasterArgs& a, const BwdIn& b,
-                             int32_t* counter) {
-  auto k = k_raster_bwd_queue<CMC, CML, TILE>;
-  hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items, kBwdLanes)), dim3(kBwdLanes), 0, s, a, b, counter);
+static hipError_t bwd_queue_launch(const CallView& v, int64_t items, hipStream_t s, const RasterArgs& a,
+                                   const BwdIn& b, int32_t* counter) {
+  const int n_cam = (int)v.lidar_tile0;   // one item per camera tile
+  if (!v.has_lidar) {
+    auto k = k_raster_bwd_queue<CMC, CML, TILE, kItemsCamera>;
+    hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items, kBwdLanes)), dim3(kBwdLanes), 0, s, a, b, counter, n_cam);
+  } else if (n_cam == 0) {
+    auto k = k_raster_bwd_queue<CMC, CML, TILE, kItemsLidar>;
+    hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items, kBwdLanes)), dim3(kBwdLanes), 0, s, a, b, counter, 0);
+  } else {
+    auto k = k_raster_bwd_queue<CMC, CML, TILE, kItemsBoth>;
+    hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items, kBwdLanes)), dim3(kBwdLanes), 0, s, a, b, counter, n_cam);
+  }
+  return hipGetLastError();
 }
 
 // Channel buckets of the persistent kernels: the cameras' and the lidars' (a call's lidars with
@@ -861,16 +881,16 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
   if (v.queue) {
     const int64_t items = L.work_cap;
     if (items <= 0) return hipSuccess;
-    int32_t* counter = L.n_work + 1;
-    hipError_t e = launch_fill_i32(counter, 1, 0, s);
+    hipError_t e = launch_fill_i32(w.qctr, 1, 0, s);
     if (e != hipSuccess) return e;
     const bool tile = support == SPLAT_SUPPORT_TILE;
     int cmc, cml;
     queue_buckets(v, cmc, cml);
-#define BWDQ_CASE(CM, CL)                                                     \
-  if (cmc == CM && cml == CL) {                                               \
-    if (tile) bwd_queue_launch<CM, CL, true>(v, items, s, a, b, counter);     \
-    else bwd_queue_launch<CM, CL, false>(v, items, s, a, b, counter);         \
+#define BWDQ_CASE(CM, CL)                                                          \
+  if (cmc == CM && cml == CL) {                                                    \
+    e = tile ? bwd_queue_launch<CM, CL, true>(v, items, s, a, b, w.qctr)           \
+             : bwd_queue_launch<CM, CL, false>(v, items, s, a, b, w.qctr);         \
+    if (e != hipSuccess) return e;                                                 \
   }
     if (timer.start) (void)hipEventRecord(timer.start, s);
     BWDQ_CASE(4, 4)

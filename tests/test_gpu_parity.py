@@ -382,33 +382,41 @@ def test_batched_equals_plain():
 
 
 def test_batched_few_gaussians_many_work_items():
-    """A batched call whose work items outnumber its records, its list capacity and its rays (40
-    Gaussians, one 1920x1080 camera of 8160 tiles, no lidar): the queue's sort still fits the
-    workspace, every camera tile is queued once, and the forward equals the per-sensor call."""
+    """A batched call whose work items outnumber its records and its list capacity (40
+    Gaussians, a 1920x1080 camera of 8160 tiles and a small one): the queue's sort still fits
+    the workspace, every camera tile is queued once, and the forward equals the per-sensor
+    calls.  A batched call over the big camera alone runs the per-sensor kernels: same result."""
     b = _binding()
     g, _ = cam_scene(n=40)
     cam = S.make_camera((0, 0, 1.5), 3.0, 1920, 1080, 1400.0, t_rs=0.03, ego_vel_world=(12.0, 0.5, 0.0),
                         n_channels=16)
-    rig = b.Rig([cam], [])
+    cam2 = S.make_camera((0, 0, 1.5), -25.0, 200, 130, 180.0, t_rs=0.02, ego_vel_world=(10.0, 0, 0), n_channels=16)
+    rig = b.Rig([cam, cam2], [])
     G = b.GaussTensors.from_numpy(g)
-    bat = b.SensorPass(rig, 0, 1, g.n, 1, batched=True)
+    bat = b.SensorPass(rig, 0, 2, g.n, 1, batched=True)
     bat.fit_capacity(G)
-    assert bat.k_cap < bat.n_tiles and g.n < bat.n_tiles and bat.n_rays == 1920 * 1080
+    assert bat.k_cap < bat.n_tiles and 2 * g.n < bat.n_tiles
     bat.render(G)
+    one = b.SensorPass(rig, 0, 1, g.n, 1, batched=True)
+    one.fit_capacity(G)
+    one.render(G)
     torch.cuda.synchronize()
     assert b.read_status(bat.status).overflow == 0
     nw = int(bat.n_work.cpu()[0])
     work = bat.work.cpu().numpy()[:nw]
     assert sorted(work[:, 0].tolist()) == list(range(bat.n_tiles))
-    sp = b.SensorPass(rig, 0, 1, g.n, 1)
-    sp.fit_capacity(G)
-    sp.render(G)
-    torch.cuda.synchronize()
-    a_ = gpu_outputs(bat, 0)
-    p_ = gpu_outputs(sp, 0)
-    assert np.any(p_["A"] > 0)
-    for key in ("F", "D", "A", "T", "last"):
-        np.testing.assert_array_equal(a_[key], p_[key])
+    for k in range(2):
+        sp = b.SensorPass(rig, k, 1, g.n, 1)
+        sp.fit_capacity(G)
+        sp.render(G)
+        torch.cuda.synchronize()
+        p_ = gpu_outputs(sp, 0)
+        if k == 0:
+            assert np.any(p_["A"] > 0)
+        for got in ([bat, k], [one, 0]) if k == 0 else ([bat, k],):
+            a_ = gpu_outputs(*got)
+            for key in ("F", "D", "A", "T", "last"):
+                np.testing.assert_array_equal(a_[key], p_[key])
 
 
 def queue_length_code(lens):
@@ -441,8 +449,11 @@ def test_batched_queue_equals_plain():
     work = bat.work.cpu().numpy()[:nw]
     tr = bat.tile_range.cpu().numpy()
     lens = np.array([tr[t, 1] - tr[t, 0] if t < bat.n_tiles else 0 for t in work[:, 0]])
-    assert np.all(np.diff(queue_length_code(lens)) <= 0)
     n_cam_tiles = int(rig.tile_base[2])
+    is_cam = work[:, 0] < n_cam_tiles
+    assert np.all(is_cam[:-1] <= is_cam[1:])   # the lidar items, then the camera items
+    for part in (~is_cam, is_cam):   # grouped form (the adjoint keeps rows): by cost inside each kind
+        assert np.all(np.diff(queue_length_code(lens[part]) >> 1) <= 0)
     assert sorted(work[work[:, 0] < n_cam_tiles, 0].tolist()) == list(range(n_cam_tiles))
     R = bat.n_rays
     up = np.random.default_rng(3)
@@ -618,6 +629,14 @@ def test_adjoint_without_rows_matches_rows():
                     sp.raster_bwd(G, *runs["ups"][key], grads)
                     outs.append(sp.outputs())
                 torch.cuda.synchronize()
+                if batched and limit == 0:   # mixed queue: one cost order, lidar lists counted 4x longer
+                    sp = passes[0]
+                    work = sp.work.cpu().numpy()[:int(sp.n_work.cpu()[0])]
+                    tr = sp.tile_range.cpu().numpy()
+                    lens = np.array([tr[t, 1] - tr[t, 0] if t < sp.n_tiles else 0 for t in work[:, 0]])
+                    lid_item = work[:, 0] >= int(rig.tile_base[1])
+                    cost = np.minimum(queue_length_code(lens) + np.where(lid_item, 32, 0), 255)
+                    assert np.all(np.diff(cost) <= 0) and lid_item.any() and (~lid_item).any()
                 ws = [int(rig.lib.splat_workspace_bytes(rig.handle, sp.first, sp.count, g.n, sp.k_cap)) for sp in passes]
                 runs[(limit, batched)] = ([{k: o[k].cpu().numpy() for k in ("feat", "depth", "alpha", "t_final")}
                                            for o in outs],
