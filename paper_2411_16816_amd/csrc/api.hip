@@ -338,16 +338,21 @@ static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t f
   if (!ws || ws_bytes < w.bytes || ((uintptr_t)ws & 255) != 0) return SPLAT_ERR_INVALID_ARG;
   w = carve_workspace(ws, (int64_t)count * g->n, lists->k_cap, v.n_tiles, v.n_rays, v.c_max);
   hipStream_t s = (hipStream_t)stream;
-  // slot flags start cleared; the atomic part exists where lidar tiles can be split, and for
-  // every record when the call keeps no rows
-  hipError_t e = w.rows ? launch_fill_i32((int32_t*)w.flags, div_up(lists->k_cap, 4), 0, s) : hipSuccess;
-  if (e == hipSuccess) e = launch_fill_i32((int32_t*)w.rflag, div_up((int64_t)count * g->n, 4), 0, s);
-  if (e == hipSuccess && (v.has_lidar || !w.rows)) {
+  // One launch clears what the adjoint accumulates into: the slot flags, the touched-record
+  // flags, the atomic part (where lidar tiles can be split, and for every record when the call
+  // keeps no rows), the queue counter and the long-record list counts.
+  FillSegments f;
+  if (w.rows) f.add(w.flags, div_up(lists->k_cap, 4));
+  f.add(w.rflag, div_up((int64_t)count * g->n, 4));
+  if (v.has_lidar || !w.rows) {
     // with rows only lidar records (the call's last sensors) receive atomic parts: zero theirs
     int k_lid = 0;
     while (w.rows && k_lid < count && v.host[k_lid].kind != kLidar) ++k_lid;
-    e = launch_fill_f32(w.g2d + (int64_t)k_lid * g->n * kNV, (int64_t)(count - k_lid) * g->n * kNV, 0.f, s);
+    f.add(w.g2d + (int64_t)k_lid * g->n * kNV, (int64_t)(count - k_lid) * g->n * kNV);
   }
+  f.add(w.qctr, 1);
+  if (w.rows) f.add(w.n_long, kLongParts);
+  hipError_t e = launch_fill_segments(f, s);
   if (e == hipSuccess)
     e = launch_raster_bwd(v, *g, *proj, *lists, support, *saved, dF, dD, dA, w, gr->features, gr->sensor_time_offset, s,
                           take_timer());

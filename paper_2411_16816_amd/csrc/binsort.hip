@@ -47,6 +47,27 @@ hipError_t fill(T* p, int64_t n, T v, hipStream_t s) {
 }
 
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) { return fill<float>(p, n, v, s); }
+
+// Up to kMaxFillSegs arrays of 32-bit words filled by one launch (each segment grid-strided by
+// the whole grid).
+__global__ void k_fill_segments(FillSegments f) {
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < f.count; ++k) {
+    uint32_t* p = f.seg[k].p;
+    const uint32_t v = f.seg[k].value;
+    for (int64_t i = t0; i < f.seg[k].n; i += stride) p[i] = v;
+  }
+}
+
+hipError_t launch_fill_segments(const FillSegments& f, hipStream_t s) {
+  int64_t most = 0;
+  for (int k = 0; k < f.count; ++k) most = f.seg[k].n > most ? f.seg[k].n : most;
+  if (most <= 0) return hipSuccess;
+  int64_t blocks = div_up(most, 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_segments, dim3((unsigned)blocks), dim3(256), 0, s, f);
+  return hipGetLastError();
+}
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) { return fill<int32_t>(p, n, v, s); }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {

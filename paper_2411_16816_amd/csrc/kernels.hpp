@@ -129,12 +129,28 @@ struct KernelTimer {
 hipError_t launch_raster_fwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
                              const SplatTileLists& L, int support, const SplatRenderOut& o, SplatStatus* st,
                              hipStream_t s, const KernelTimer& timer);
+// The adjoint's launchers expect w.flags (with rows), w.rflag, the atomic part of w.g2d, w.qctr
+// and w.n_long cleared by the caller (one fill launch for all of them).
 hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const SplatProjected& p,
                              const SplatTileLists& L, int support, const SplatRenderOut& saved, const float* dF,
                              const float* dD, const float* dA, const Workspace& w, float* dfeat, float* d_toff,
                              hipStream_t s, const KernelTimer& timer);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+// several word arrays filled by one launch
+constexpr int kMaxFillSegs = 6;
+struct FillSegments {
+  struct Seg {
+    uint32_t* p;
+    int64_t n;        // words
+    uint32_t value;   // bit pattern (0.0f = 0)
+  } seg[kMaxFillSegs];
+  int count = 0;
+  void add(void* p, int64_t n, uint32_t value = 0u) {
+    if (p && n > 0 && count < kMaxFillSegs) seg[count++] = Seg{(uint32_t*)p, n, value};
+  }
+};
+hipError_t launch_fill_segments(const FillSegments& f, hipStream_t s);
 // exclusive scan of in[0..n) into out (may alias in); part: div_up(n, kScanTile) + 1 entries,
 // the last of which receives the total
 hipError_t launch_exclusive_scan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* part, hipStream_t s);

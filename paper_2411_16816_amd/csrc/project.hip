@@ -152,10 +152,13 @@ __global__ __launch_bounds__(256) void k_long_records(const int32_t* __restrict_
   for (int c = 0; c < chunks; ++c) dst[c] = make_uint2((uint32_t)r, (uint32_t)c);
 }
 
-// One wavefront per (record, chunk): every lane sums the flagged rows of its kLanePositions
-// positions, the wavefront reduces, and the chunk's total is stored into the row of the
-// chunk's first position, flagged 2 (zeros if no row was written).  Only this wavefront
-// touches the chunk's rows.  Items are numbered partition by partition.
+// One wavefront per (record, chunk): lane l sums the flagged rows at chunk positions l, l + 64,
+// l + 128, ... (so that each load instruction of the wavefront reads 64 consecutive rows), two
+// rows in flight; the wavefront reduces, and the chunk's total is stored into the row of the
+// chunk's first position, flagged 2 (zeros if no row was written).  Only this wavefront touches
+// the chunk's rows.  Items are numbered partition by partition.
+constexpr int kLongRowsInFlight = 2;
+
 template <int CMAX>
 __global__ __launch_bounds__(256) void k_slot_reduce_long(const uint2* __restrict__ list, int64_t cap,
                                                           const int32_t* __restrict__ n_list,
@@ -164,8 +167,9 @@ __global__ __launch_bounds__(256) void k_slot_reduce_long(const uint2* __restric
                                                           uint8_t* flags, int64_t k_cap) {
   constexpr int V = kNV + CMAX;
   constexpr int SW = slot_stride(CMAX);
+  constexpr int G = kLongRowsInFlight;
   static_assert(kLongParts == 64, "one partition count per lane");
-  static_assert(kLanePositions <= kCoopEntries, "flag_mask range");
+  static_assert(kLanePositions % G == 0, "row groups");
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -186,31 +190,35 @@ __global__ __launch_bounds__(256) void k_slot_reduce_long(const uint2* __restric
     const uint32_t r = item.x;
     const int64_t base = entry_base[r];
     const int n = listed_entries(n_tiles[r], base, k_cap);
-    const int64_t c0 = (int64_t)item.y * kChunk;             // chunk start (record-relative)
-    const int64_t l0 = c0 + lane * kLanePositions;           // this lane's first position
-    int cnt = (int)(n - l0);
-    cnt = cnt < 0 ? 0 : (cnt > kLanePositions ? kLanePositions : cnt);
+    const int64_t c0 = base + (int64_t)item.y * kChunk;       // the chunk's first row
+    const int64_t lim = (int64_t)n - (int64_t)item.y * kChunk;  // positions of the chunk (> 0)
+    uint32_t on = 0;   // bit k: the lane's position k * 64 + lane holds a written row
+#pragma unroll
+    for (int k = 0; k < kLanePositions; ++k) {
+      const int j = k * 64 + lane;
+      const bool w = flags[c0 + (j < lim ? j : 0)] != 0;   // in bounds: position 0 for j >= lim
+      on |= (j < lim && w) ? 1u << k : 0u;
+    }
     float sum_v[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) sum_v[v] = 0.f;
-    uint32_t fm = cnt > 0 ? flag_mask(flags, base + l0, cnt) : 0u;
-    while (fm) {   // two rows in flight per iteration
-      const int j0 = __builtin_ctz(fm);
-      fm &= fm - 1;
-      const bool two = fm != 0;
-      const int j1 = two ? __builtin_ctz(fm) : j0;
-      if (two) fm &= fm - 1;
-      float r0[V], r1[V];
+#pragma unroll 1
+    for (int k0 = 0; k0 < kLanePositions; k0 += G) {
+      float rv[G][V];
 #pragma unroll
-      for (int v = 0; v < V; ++v) r0[v] = r1[v] = 0.f;
-      add_row<SW>(slots + (base + l0 + j0) * SW, r0);
-      add_row<SW>(slots + (base + l0 + j1) * SW, r1);
+      for (int u = 0; u < G; ++u) {
 #pragma unroll
-      for (int v = 0; v < V; ++v) sum_v[v] += two ? r0[v] + r1[v] : r0[v];
+        for (int v = 0; v < V; ++v) rv[u][v] = 0.f;
+        if ((on >> (k0 + u)) & 1u) add_row<SW>(slots + (c0 + (int64_t)(k0 + u) * 64 + lane) * SW, rv[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u)
+#pragma unroll
+        for (int v = 0; v < V; ++v) sum_v[v] += rv[u][v];
     }
     const float sum = wave_reduce_scatter<V>(sum_v);
-    if (store) slots[(base + c0) * SW + idx] = sum;
-    if (lane == 0) flags[base + c0] = 2;
+    if (store) slots[c0 * SW + idx] = sum;
+    if (lane == 0) flags[c0] = 2;
   }
 }
 
@@ -377,8 +385,7 @@ hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const 
     return hipGetLastError();
   }
   if (w.long_cap != long_part_cap(n_rec, L.k_cap)) return hipErrorInvalidValue;
-  hipError_t e = launch_fill_i32(w.n_long, kLongParts, 0, s);
-  if (e != hipSuccess) return e;
+  // w.n_long was cleared by the caller before the rasteriser adjoint
   hipLaunchKernelGGL(k_long_records, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, (const int32_t*)p.n_tiles,
                      (const uint8_t*)w.rflag, (const int64_t*)L.entry_base, n_rec, L.k_cap, (uint2*)w.long_list,
                      w.long_cap, w.n_long);

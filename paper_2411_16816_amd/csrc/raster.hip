@@ -881,8 +881,7 @@ hipError_t launch_raster_bwd(const CallView& v, const SplatGaussians& g, const S
   if (v.queue) {
     const int64_t items = L.work_cap;
     if (items <= 0) return hipSuccess;
-    hipError_t e = launch_fill_i32(w.qctr, 1, 0, s);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;   // w.qctr was cleared by the caller
     const bool tile = support == SPLAT_SUPPORT_TILE;
     int cmc, cml;
     queue_buckets(v, cmc, cml);
