@@ -200,14 +200,16 @@ __device__ __forceinline__ void setup_ray(const RasterArgs& a, int64_t tile, int
 // spread over all banks.
 constexpr int rec4(int cmax) { return (4 + cmax / 4) | 1; }
 
+// Returns the staged Gaussian's record (sensor * N + Gaussian id), -1 for lanes past the batch.
 template <int CMAX>
-__device__ __forceinline__ void stage_batch(const RasterArgs& a, const RayCtx& c, int64_t b0, int64_t b1,
-                                            float4* rec) {
+__device__ __forceinline__ int64_t stage_batch(const RasterArgs& a, const RayCtx& c, int64_t b0, int64_t b1,
+                                               float4* rec) {
   const int tid = threadIdx.x;
   const int64_t idx = b0 + tid;
+  int64_t r = -1;
   if (idx < b1) {
     const int64_t g = a.gauss[idx];
-    const int64_t r = (int64_t)c.s * a.N + g;
+    r = (int64_t)c.s * a.N + g;
     float4* o = rec + tid * rec4(CMAX);
     const float4 mv = a.mv[r];
     const float4 ce = conic_exp2(a.cn[r]);
@@ -228,6 +230,7 @@ __device__ __forceinline__ void stage_batch(const RasterArgs& a, const RayCtx& c
       o[4 + c4] = v;
     }
   }
+  return r;
 }
 
 // wavefront-uniform tests on a lane predicate (scalar compares of the lane mask)
@@ -547,7 +550,13 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
   float tacc = 0.f;    // camera: dL/dt of this lane's pairs (mean at time t moves with the velocity)
   for (int64_t b0 = start + ((n_proc - 1) / kBwdBatch) * kBwdBatch; b0 >= start; b0 -= kBwdBatch) {
     const int64_t b1 = (b0 + kBwdBatch < start + n_proc) ? b0 + kBwdBatch : start + n_proc;
-    if (tid < kBwdBatch) stage_batch<CMAX>(a, c[0], b0, b1, sm.rec);
+    // lane j of wavefront 0 stages Gaussian j of the batch and, after the walk, stores its
+    // results: its record and gradient row are looked up now, beside the staging loads
+    int64_t my_rec = -1, my_row = 0;
+    if (tid < kBwdBatch) {
+      my_rec = stage_batch<CMAX>(a, c[0], b0, b1, sm.rec);
+      if (my_rec >= 0 && !split) my_row = a.entry_base[my_rec] + rect_entry(S, a.rect[my_rec], tile_local);
+    }
     __syncthreads();
     const int nb = (int)(b1 - b0);
     for (int j = nb - 1; j >= 0; --j) {
@@ -643,12 +652,12 @@ __device__ __forceinline__ void bwd_item(const RasterArgs& a, const BwdIn& b, in
     }
     __syncthreads();
     if (tid < nb && s_used[tid]) {
-      const int64_t g = a.gauss[b0 + tid];
-      const int64_t rec = (int64_t)c[0].s * a.N + g;
+      const int64_t rec = my_rec;
+      const int64_t g = rec - (int64_t)c[0].s * a.N;
       b.rflag[rec] = 1;   // idempotent: every writer stores the same byte
       if (!split) {
         // this item is the only one of its tile: the entry's row is complete, store it
-        const int64_t p = a.entry_base[rec] + rect_entry(S, a.rect[rec], tile_local);
+        const int64_t p = my_row;
         float4* row = reinterpret_cast<float4*>(b.slots + p * SW);
 #pragma unroll
         for (int q = 0; q < SW / 4; ++q) {
