@@ -706,13 +706,13 @@ __global__ __launch_bounds__(kBwdLanes) void k_raster_bwd(RasterArgs a, BwdIn b)
 }
 
 // Item kinds an adjoint queue kernel renders (the queue holds its lidar items first and its
-// n_cam camera items last).  A kernel compiled for one kind gets that kind's register
-// allocation: the camera code fits 128 VGPRs (4 waves per SIMD); the lidar code, and a kernel
-// holding both, take up to 168 (3 waves per SIMD).
+// n_cam camera items last).  Every form is held to 128 VGPRs (4 waves per SIMD): the camera-only
+// and lidar-only kernels fit in 119 and 112; the kernel holding both would take 146 and spills
+// 76 bytes per lane in its per-item set-up instead, which measures faster than 3 waves.
 enum : int { kItemsCamera = 1, kItemsLidar = 2, kItemsBoth = 3 };
 
 template <int CMC, int CML, bool TILE, int KINDS>
-__global__ __launch_bounds__(kBwdLanes) __attribute__((amdgpu_waves_per_eu(KINDS == kItemsCamera ? 4 : 3)))
+__global__ __launch_bounds__(kBwdLanes) __attribute__((amdgpu_waves_per_eu(4)))
 void k_raster_bwd_queue(RasterArgs a, BwdIn b, int32_t* counter, int n_cam) {
   __shared__ BwdSmem<cmax_max(CMC, CML)> sm;
   __shared__ int s_slot;
