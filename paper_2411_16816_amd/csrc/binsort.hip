@@ -1,18 +1,19 @@
 // binsort.hip -- tile binning and depth sorting (SplatAD, arXiv 2411.16816: Sec. 3.2
 // "Projection, tiling, and sorting"; Sec. 3.3 "Tiling and sorting"; App. A).
 //
-// Pipeline of one call (all on the stream, no host synchronisation):
+// Pipeline of one call (on the call's stream, step 6 on the rig's side stream when there is
+// one; no host synchronisation):
 //   1. one scan over the records in record order counts the visible records and their
 //      (tile, Gaussian) entries, gives each visible record its entry numbers (the adjoint's
 //      gradient rows) and compacts the visible records with a 32-bit key of their float64 depth;
 //   2. the visible records are stably sorted by that key, so equal keys keep record
 //      (= Gaussian id) order;
-//   3. tiles are grouped into supertiles of 8 x 8 tiles; a scan in depth order gives every
-//      record the place of its (supertile, record) entries, one per supertile its rectangle
-//      meets, and they are written in depth order;
+//   3. tiles are grouped into supertiles (camera 8 x 8 tiles, lidar 4 x 4); a scan in depth
+//      order gives every record the place of its (supertile, record) entries, one per supertile
+//      its rectangle meets, and they are written in depth order;
 //   4. a stable radix sort by supertile groups those entries, each supertile's in depth order;
 //   5. each supertile's entries are cut into items of at most 256; per item, the entries
-//      meeting each of the supertile's 64 tiles are counted (wavefront ballots), one scan of the
+//      meeting each of the supertile's tiles (64 or 16) are counted (wavefront ballots), one scan of the
 //      counts gives every tile its list range and every item its first position in each list,
 //      and the items write the Gaussian ids straight into the lists, ranked by ballot prefix.
 //      Every list holds its tile's Gaussians in (depth, id) order, the ordering the paper gets
