@@ -322,6 +322,25 @@ namespace splat {
 int64_t adjoint_row_limit() { return g_row_limit.load(); }
 }  // namespace splat
 
+// One launch clears what the adjoint accumulates into: the slot flags, the touched-record flags,
+// the atomic part (where lidar tiles can be split, and for every record when the call keeps no
+// rows), the queue counter and the long-record list counts.
+static hipError_t adjoint_clears(const CallView& v, const Workspace& w, int64_t k_cap, int64_t n_gauss,
+                                 hipStream_t s) {
+  FillSegments f;
+  if (w.rows) f.add(w.flags, div_up(k_cap, 4));
+  f.add(w.rflag, div_up((int64_t)v.count * n_gauss, 4));
+  if (v.has_lidar || !w.rows) {
+    // with rows only lidar records (the call's last sensors) receive atomic parts: zero theirs
+    int k_lid = 0;
+    while (w.rows && k_lid < v.count && v.host[k_lid].kind != kLidar) ++k_lid;
+    f.add(w.g2d + (int64_t)k_lid * n_gauss * kNV, (int64_t)(v.count - k_lid) * n_gauss * kNV);
+  }
+  f.add(w.qctr, 1);
+  if (w.rows) f.add(w.n_long, kLongParts);
+  return launch_fill_segments(f, s);
+}
+
 static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t first, int32_t count, int kind,
                            const SplatProjected* proj, const SplatTileLists* lists, int32_t support,
                            const SplatRenderOut* saved, const float* dF, const float* dD, const float* dA,
@@ -338,21 +357,7 @@ static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t f
   if (!ws || ws_bytes < w.bytes || ((uintptr_t)ws & 255) != 0) return SPLAT_ERR_INVALID_ARG;
   w = carve_workspace(ws, (int64_t)count * g->n, lists->k_cap, v.n_tiles, v.n_rays, v.c_max);
   hipStream_t s = (hipStream_t)stream;
-  // One launch clears what the adjoint accumulates into: the slot flags, the touched-record
-  // flags, the atomic part (where lidar tiles can be split, and for every record when the call
-  // keeps no rows), the queue counter and the long-record list counts.
-  FillSegments f;
-  if (w.rows) f.add(w.flags, div_up(lists->k_cap, 4));
-  f.add(w.rflag, div_up((int64_t)count * g->n, 4));
-  if (v.has_lidar || !w.rows) {
-    // with rows only lidar records (the call's last sensors) receive atomic parts: zero theirs
-    int k_lid = 0;
-    while (w.rows && k_lid < count && v.host[k_lid].kind != kLidar) ++k_lid;
-    f.add(w.g2d + (int64_t)k_lid * g->n * kNV, (int64_t)(count - k_lid) * g->n * kNV);
-  }
-  f.add(w.qctr, 1);
-  if (w.rows) f.add(w.n_long, kLongParts);
-  hipError_t e = launch_fill_segments(f, s);
+  hipError_t e = adjoint_clears(v, w, lists->k_cap, g->n, s);
   if (e == hipSuccess)
     e = launch_raster_bwd(v, *g, *proj, *lists, support, *saved, dF, dD, dA, w, gr->features, gr->sensor_time_offset, s,
                           take_timer());
@@ -467,16 +472,18 @@ static int step_launches(const SplatRig* r, int32_t first, int32_t count, const 
     hipError_t e = launch_fill_i32((int32_t*)st->status, sizeof(SplatStatus) / 4, 0, s);
     if (e != hipSuccess) return dev_err(e);
   }
-  if (bwd && (st->flags & SPLAT_STEP_ZERO_GRADS)) {
+  if (bwd && (st->flags & SPLAT_STEP_ZERO_GRADS)) {   // the gradient accumulators, one launch
     const SplatGrads& gr = st->grads;
     const int64_t n = g->n;
     if (!gr.means || !gr.log_scales || !gr.quats || !gr.opacities) return SPLAT_ERR_INVALID_ARG;
-    hipError_t e = launch_fill_f32(gr.means, 3 * n, 0.f, s);
-    if (e == hipSuccess) e = launch_fill_f32(gr.log_scales, 3 * n, 0.f, s);
-    if (e == hipSuccess) e = launch_fill_f32(gr.quats, 4 * n, 0.f, s);
-    if (e == hipSuccess) e = launch_fill_f32(gr.opacities, n, 0.f, s);
-    if (e == hipSuccess && gr.velocities) e = launch_fill_f32(gr.velocities, 3 * n, 0.f, s);
-    if (e == hipSuccess && gr.features) e = launch_fill_f32(gr.features, n * g->c_total, 0.f, s);
+    FillSegments f;
+    f.add(gr.means, 3 * n);
+    f.add(gr.log_scales, 3 * n);
+    f.add(gr.quats, 4 * n);
+    f.add(gr.opacities, n);
+    f.add(gr.velocities, 3 * n);
+    f.add(gr.features, n * g->c_total);
+    hipError_t e = launch_fill_segments(f, s);
     if (e != hipSuccess) return dev_err(e);
   }
   int rc = project_impl(g, r, first, count, -1, &st->proj, st->status, s);
