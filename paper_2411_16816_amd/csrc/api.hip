@@ -3,6 +3,7 @@
 #include <atomic>
 #include <new>
 #include <string.h>
+#include <unordered_map>
 #include <vector>
 
 #include "kernels.hpp"
@@ -19,6 +20,9 @@ struct SplatRig {
   // bin/sort's side stream (default priority) and its fork / join events
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  // queue order of the last batched bin/sort per lists (keyed by the work buffer): true when it
+  // grouped the items by kind, which the adjoint's two-loop kernel relies on
+  mutable std::unordered_map<const void*, bool> grouped_queue;
   bool upload_pending = false;
   bool is_set = false;
   int n_cu = 0;                     // compute units of the rig's device (persistent grids)
@@ -290,7 +294,10 @@ static int bin_sort_impl(const SplatRig* r, int32_t first, int32_t count, int ki
   Workspace w = carve_workspace(nullptr, (int64_t)count * n_gaussians, lists->k_cap, v.n_tiles, v.n_rays, v.c_max);
   if (!ws || ws_bytes < w.bytes || ((uintptr_t)ws & 255) != 0) return SPLAT_ERR_INVALID_ARG;
   w = carve_workspace(ws, (int64_t)count * n_gaussians, lists->k_cap, v.n_tiles, v.n_rays, v.c_max);
-  return dev_err(launch_bin_sort(v, *proj, *lists, w, st, (hipStream_t)stream));
+  const int rc2 = dev_err(launch_bin_sort(v, *proj, *lists, w, st, (hipStream_t)stream));
+  if (v.queue) r->grouped_queue[lists->work] = rc2 == SPLAT_OK && w.rows;
+  else if (lists->work) r->grouped_queue.erase(lists->work);
+  return rc2;
 }
 
 // Measurement hook (splat_time_next_raster): consumed by the next rasterise call of this thread.
@@ -356,6 +363,10 @@ static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t f
   Workspace w = carve_workspace(nullptr, (int64_t)count * g->n, lists->k_cap, v.n_tiles, v.n_rays, v.c_max);
   if (!ws || ws_bytes < w.bytes || ((uintptr_t)ws & 255) != 0) return SPLAT_ERR_INVALID_ARG;
   w = carve_workspace(ws, (int64_t)count * g->n, lists->k_cap, v.n_tiles, v.n_rays, v.c_max);
+  if (v.queue) {
+    const auto q = r->grouped_queue.find(lists->work);
+    v.queue_grouped = q != r->grouped_queue.end() && q->second;
+  }
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = adjoint_clears(v, w, lists->k_cap, g->n, s);
   if (e == hipSuccess)

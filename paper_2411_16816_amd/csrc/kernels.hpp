@@ -62,6 +62,9 @@ struct CallView {
   // reads no Gaussian data) onto it and joins it back before the queue; null: one stream
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  // the adjoint's queue is known to hold its lidar items first, then its camera items (the
+  // order bin/sort built for these lists when the adjoint keeps rows)
+  bool queue_grouped = false;
 };
 
 inline int64_t work_capacity(int64_t n_tiles, int64_t n_rays) {

@@ -709,7 +709,9 @@ __global__ __launch_bounds__(kBwdLanes) void k_raster_bwd(RasterArgs a, BwdIn b)
 // n_cam camera items last).  Every form is held to 128 VGPRs (4 waves per SIMD): the camera-only
 // and lidar-only kernels fit in 119 and 112; the kernel holding both would take 146 and spills
 // 76 bytes per lane in its per-item set-up instead, which measures faster than 3 waves.
-enum : int { kItemsCamera = 1, kItemsLidar = 2, kItemsBoth = 3 };
+// kItemsGrouped: both kinds, the queue grouped by kind (the adjoint keeps rows): one loop over
+// the lidar part, then one over the camera part, which halves the combined kernel's spills.
+enum : int { kItemsCamera = 1, kItemsLidar = 2, kItemsBoth = 3, kItemsGrouped = 4 };
 
 template <int CMC, int CML, bool TILE, int KINDS>
 __global__ __launch_bounds__(kBwdLanes) __attribute__((amdgpu_waves_per_eu(4)))
@@ -719,14 +721,27 @@ void k_raster_bwd_queue(RasterArgs a, BwdIn b, int32_t* counter, int n_cam) {
   const int n_items = a.n_work[0];
   const int lo = KINDS == kItemsCamera ? n_items - n_cam : 0;   // this kernel's part of the queue
   const int hi = KINDS == kItemsLidar ? n_items - n_cam : n_items;
-  for (;;) {
-    const int it = lo + next_item(counter, &s_slot);
-    if (it >= hi) break;
-    const int2 w = a.work[it];
-    if (KINDS == kItemsLidar || (KINDS == kItemsBoth && item_is_lidar(a, w.x)))
+  if constexpr (KINDS == kItemsGrouped) {
+    int it = next_item(counter, &s_slot);
+    for (; it < n_items; it = next_item(counter, &s_slot)) {   // the lidar items come first
+      const int2 w = a.work[it];
+      if (!item_is_lidar(a, w.x)) break;   // uniform over the workgroup
       bwd_item<CML, true, TILE>(a, b, w.x, w.y, sm);
-    else
+    }
+    for (; it < n_items; it = next_item(counter, &s_slot)) {
+      const int2 w = a.work[it];
       bwd_item<CMC, false, TILE>(a, b, w.x, 0, sm);
+    }
+  } else {
+    for (;;) {
+      const int it = lo + next_item(counter, &s_slot);
+      if (it >= hi) break;
+      const int2 w = a.work[it];
+      if (KINDS == kItemsLidar || (KINDS == kItemsBoth && item_is_lidar(a, w.x)))
+        bwd_item<CML, true, TILE>(a, b, w.x, w.y, sm);
+      else
+        bwd_item<CMC, false, TILE>(a, b, w.x, 0, sm);
+    }
   }
 }
 
@@ -801,6 +816,9 @@ static hipError_t bwd_queue_launch(const CallView& v, int64_t items, hipStream_t
   } else if (n_cam == 0) {
     auto k = k_raster_bwd_queue<CMC, CML, TILE, kItemsLidar>;
     hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items, kBwdLanes)), dim3(kBwdLanes), 0, s, a, b, counter, 0);
+  } else if (v.queue_grouped && b.rows) {   // the queue is grouped by kind (binsort.hip, k_queue_keys)
+    auto k = k_raster_bwd_queue<CMC, CML, TILE, kItemsGrouped>;
+    hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items, kBwdLanes)), dim3(kBwdLanes), 0, s, a, b, counter, n_cam);
   } else {
     auto k = k_raster_bwd_queue<CMC, CML, TILE, kItemsBoth>;
     hipLaunchKernelGGL(k, dim3(persistent_grid(k, v, items, kBwdLanes)), dim3(kBwdLanes), 0, s, a, b, counter, n_cam);

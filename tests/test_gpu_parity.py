@@ -632,6 +632,52 @@ def test_split_tile_atomics_match_fixed_order():
             assert not bad.any(), (name, int(bad.sum()))
 
 
+def test_adjoint_after_row_limit_change_between_calls():
+    """bin/sort orders the persistent queue by the adjoint row limit of its own call (grouped by
+    kind with rows, one mixed cost order without).  An adjoint run after the limit changed,
+    on lists binned under the other limit, must still render every work item: the rig remembers
+    each lists' queue order and the adjoint picks its kernel by it.  Gradients match a run that
+    kept the default limit throughout."""
+    b = _binding()
+    rng = np.random.default_rng(33)
+    n = 3000
+    mu = np.stack([rng.uniform(2, 30, n), rng.uniform(-12, 12, n), rng.uniform(-2, 2, n)], 1)
+    g = S.random_gaussians(rng, mu, 19, rgb=True, moving_frac=0.5, log_scale_mean=-0.6)
+    G = b.GaussTensors.from_numpy(g)
+    cam = S.make_camera((0, 0, 0), 0.0, 200, 120, 150.0, t_rs=0.03, ego_vel_world=(3.0, 0, 0), n_channels=16)
+    lid = S.make_lidar((0, 0, 0), 0.0, 16, -15.0, 15.0, 256, tile_az=16, tile_el=8, t_sweep=0.1,
+                       ego_vel_world=(10.0, 1.0, 0), feat_offset=3, n_channels=8)
+    rig = b.Rig([cam], [lid])
+    up = np.random.default_rng(34)
+    grads, outs = [], []
+    try:
+        for binned_without_rows in (False, True):
+            b.set_adjoint_row_limit(b.ADJOINT_ROW_LIMIT)
+            sp = b.SensorPass(rig, 0, 2, g.n, 1, batched=True)
+            sp.fit_capacity(G)   # workspace sized with rows
+            if binned_without_rows:
+                b.set_adjoint_row_limit(0)   # this bin/sort builds the mixed queue order
+            sp.render(G)
+            b.set_adjoint_row_limit(b.ADJOINT_ROW_LIMIT)   # the adjoint keeps rows
+            if not grads:
+                ups = [torch.from_numpy(a).cuda() for a in (
+                    up.normal(size=sp.n_feat).astype(np.float32),
+                    (0.1 * up.normal(size=sp.n_rays)).astype(np.float32),
+                    up.normal(size=sp.n_rays).astype(np.float32))]
+            gr = b.zeros_like_grads(G)
+            sp.raster_bwd(G, *ups, gr)
+            torch.cuda.synchronize()
+            grads.append({name: getattr(gr, name).cpu().numpy().astype(np.float64) for name in geo.Params.names})
+            outs.append(sp.outputs()["feat"].cpu().numpy())
+    finally:
+        b.set_adjoint_row_limit(b.ADJOINT_ROW_LIMIT)
+    np.testing.assert_array_equal(outs[0], outs[1])
+    for name in geo.Params.names:
+        x, y = grads[1][name], grads[0][name]
+        assert np.linalg.norm(y) > 0, name
+        assert np.linalg.norm(x - y) <= 1e-5 * np.linalg.norm(y), name
+
+
 def test_adjoint_without_rows_matches_rows():
     """Beyond the adjoint row limit a call keeps no per-entry gradient rows: every work item adds
     its per-Gaussian sums to the record's gradient atomically.  The same camera + lidar step, in
