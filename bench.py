@@ -406,7 +406,7 @@ def check_parity(passes, rig, g):
 
 
 # kernel whose roofline is reported: the batched adjoint rasteriser, the longest kernel of the step
-ROOF_KERNEL = "k_raster_bwd_queue<16, 8, false, 3>"   # both item kinds (camera + lidar call)
+ROOF_KERNEL = "k_raster_bwd_queue<16, 8, false, 4>"   # camera + lidar call, queue grouped by kind
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_raster_bwd_queue_headline.md")
 KERNEL_SOURCES = ["paper_2411_16816_amd/csrc/raster.hip", "paper_2411_16816_amd/csrc/splat_common.hpp",
                   "paper_2411_16816_amd/csrc/wave_ops.hpp", "paper_2411_16816_amd/csrc/kernels.hpp",
