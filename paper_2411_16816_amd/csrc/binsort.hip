@@ -406,12 +406,16 @@ __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t* __restrict__ hi
 // order and written out so that consecutive lanes write consecutive addresses of a digit's
 // output run (coalesced), at the block's global digit offsets: the digit's start (exclusive
 // scan of the digit totals, done here) plus the earlier blocks' counts of the digit.
+//
+// range_out (single-pass sorts, may be null): block 0 also writes every digit d < n_range its
+// output run [start, end), which for a sort over one digit is the key's range in the output.
 template <typename K, typename V>
 __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin, const V* __restrict__ vin,
                                                        K* __restrict__ kout, V* __restrict__ vout,
                                                        const int64_t* n_ptr, int64_t n_cap, int shift, int bits,
                                                        const uint32_t* __restrict__ hist,
-                                                       const uint32_t* __restrict__ coltotal) {
+                                                       const uint32_t* __restrict__ coltotal,
+                                                       uint2* __restrict__ range_out, int n_range) {
   constexpr int kPerWave = kRadixTile / 4;
   __shared__ K s_k[kRadixTile];
   __shared__ V s_v[kRadixTile];
@@ -422,15 +426,19 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
   const int64_t n = sort_count(n_ptr, n_cap);
   const int64_t base = (int64_t)blockIdx.x * kRadixTile;
-  if (base >= n) return;   // uniform over the block
+  const bool ranges = range_out && blockIdx.x == 0;   // block 0 writes them even with no keys
+  if (base >= n && !ranges) return;                   // both uniform over the block
+  {
+    uint32_t dtot;
+    const uint32_t c = coltotal[tid];
+    const uint32_t dstart = block_exclusive_scan<uint32_t>(c, tmp, dtot);
+    if (ranges && tid < n_range) range_out[tid] = make_uint2(dstart, dstart + c);
+    if (base >= n) return;
+    gbase[tid] = dstart + hist[(int64_t)tid * gridDim.x + blockIdx.x];
+  }
   const int cnt = (int)((n - base) < kRadixTile ? (n - base) : kRadixTile);
   const uint32_t mask = (1u << bits) - 1u;
   const uint64_t lt = lanemask_lt();
-  {
-    uint32_t dtot;
-    const uint32_t dstart = block_exclusive_scan<uint32_t>(coltotal[tid], tmp, dtot);
-    gbase[tid] = dstart + hist[(int64_t)tid * gridDim.x + blockIdx.x];
-  }
   wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
   K key[kRadixItems];
   V val[kRadixItems];
@@ -502,12 +510,15 @@ static inline int radix_pass_bits(int total_bits) {
 // indexes the sorted keys; the sorted values are in v[cur], or in `final_vals` when it is
 // non-null.  n_ptr (device) gives the element count when non-null, capped by n_cap; only the
 // blocks that hold keys do work.  Three launches per pass: histograms, per-digit scans over
-// the blocks, scatter.
+// the blocks, scatter.  range_out (may be null): for a sort of one pass, the [start, end) of
+// every key value below n_range is also written, by the scatter; nothing for more passes.
 template <typename K, typename V>
 static hipError_t radix_sort(K* k[2], V* v[2], int& cur, const int64_t* n_ptr, int64_t n_cap, int lo_bit,
-                             int total_bits, uint32_t* hist, uint32_t* coltotal, V* final_vals, hipStream_t s) {
+                             int total_bits, uint32_t* hist, uint32_t* coltotal, V* final_vals, hipStream_t s,
+                             uint2* range_out = nullptr, int n_range = 0) {
   if (total_bits < 1) total_bits = 1;
   const int passes = (total_bits + kRadixBits - 1) / kRadixBits;
+  if (passes > 1) range_out = nullptr;
   const int per = radix_pass_bits(total_bits);   // bits spread evenly over the passes
   const int64_t nb = div_up(n_cap, kRadixTile);
   if (nb == 0) return hipSuccess;
@@ -519,7 +530,8 @@ static hipError_t radix_sort(K* k[2], V* v[2], int& cur, const int64_t* n_ptr, i
     hipLaunchKernelGGL(k_radix_colscan, dim3(kRadixBins), dim3(256), 0, s, hist, n_ptr, n_cap, nb, coltotal);
     V* vdst = (p == passes - 1 && final_vals) ? final_vals : v[1 - cur];
     hipLaunchKernelGGL((k_radix_scatter<K, V>), dim3((unsigned)nb), dim3(256), 0, s, (const K*)k[cur], (const V*)v[cur],
-                       k[1 - cur], vdst, n_ptr, n_cap, shift, bits, (const uint32_t*)hist, (const uint32_t*)coltotal);
+                       k[1 - cur], vdst, n_ptr, n_cap, shift, bits, (const uint32_t*)hist, (const uint32_t*)coltotal,
+                       range_out, n_range);
     cur = 1 - cur;
   }
   return hipGetLastError();
@@ -742,8 +754,8 @@ __device__ __forceinline__ void coarse_entry(const DevSensor& S, uint32_t st0, c
 // Visible record i (depth order) writes its (local supertile, record) entries from its offset
 // coff[i] on.  Each lane writes the first kEmitOwn entries of its own record; the entries
 // beyond that of the wavefront's larger records are then written by the whole wavefront, one
-// record at a time, 64 entries per step.  The grid also empties the n_st supertile ranges
-// ([0, 0)), which the ranges pass after the supertile sort fills in.
+// record at a time, 64 entries per step.  The grid also empties the first n_st supertile
+// ranges ([0, 0)) when the supertile sort leaves them to a ranges pass (n_st = 0 otherwise).
 constexpr int kEmitOwn = 4;
 
 __global__ __launch_bounds__(256) void k_coarse_emit(const DevSensor* __restrict__ sens, int count, int64_t N,
@@ -1343,10 +1355,13 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
                                 CoarseCount{sc, L.k_cap}, sc + kScVisible)) != hipSuccess)
     return e;
   const int64_t n_st = v.n_supertiles;
+  // with at most kRadixBins supertiles step 4 is one radix pass, whose scatter writes the
+  // supertile ranges; otherwise the emit clears them and a ranges pass fills them in
+  const bool one_pass = n_st <= kRadixBins && L.k_cap > 0;
   if (n_rec > 0)
     hipLaunchKernelGGL(k_coarse_emit, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, v.sens, v.count, v.n_gauss,
                        (const int4*)p.rect, (const uint32_t*)dvv[cur], (const int64_t*)w.coff, (const int64_t*)sc, n_rec,
-                       w.ckeys[0], w.cvals[0], L.k_cap, (uint32_t*)w.crange, n_st);
+                       w.ckeys[0], w.cvals[0], L.k_cap, (uint32_t*)w.crange, one_pass ? (int64_t)0 : n_st);
   else if ((e = fill<int32_t>((int32_t*)w.crange, 2 * n_st, 0, s)) != hipSuccess)   // [0, 0): empty
     return e;
   // 4. stable sort of the entries by supertile: each supertile's records stay in depth order
@@ -1354,9 +1369,9 @@ hipError_t launch_bin_sort(const CallView& v, const SplatProjected& p, const Spl
   uint64_t* cv[2] = {w.cvals[0], w.cvals[1]};
   int ccur = 0;
   if ((e = radix_sort<uint32_t, uint64_t>(ck, cv, ccur, sc + kScCoarse, L.k_cap, 0, bits_for(n_st), w.hist, w.coltotal,
-                                nullptr, s)) != hipSuccess)
+                                nullptr, s, one_pass ? w.crange : nullptr, (int)(one_pass ? n_st : 0))) != hipSuccess)
     return e;
-  if (L.k_cap > 0)
+  if (L.k_cap > 0 && !one_pass)
     hipLaunchKernelGGL(k_ranges<uint2>, dim3((unsigned)div_up(L.k_cap, 256 * kRangeItems)), dim3(256), 0, s,
                        (const uint32_t*)ck[ccur], (const int64_t*)(sc + kScCoarse), L.k_cap, w.crange, 0, (int64_t)0);
   // 5. items of <= kItemEntries entries per supertile; per item and tile the entry counts; their
