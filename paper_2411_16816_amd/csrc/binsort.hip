@@ -242,6 +242,13 @@ __global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, const int
   if ((int64_t)blockIdx.x > last) return;   // uniform
   const int64_t hi = n_eff > 0 ? n_eff - 1 : 0;
   const int64_t base = (int64_t)blockIdx.x * kTile;
+  T xs[kItems];   // the tile's loads are issued first and stay in flight while the blocks
+                  // before this one are summed
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
+    xs[r] = ld(i < hi ? i : hi);
+  }
   T before;
   if (fused) {
     T pb = 0;
@@ -250,11 +257,10 @@ __global__ __launch_bounds__(256) void k_scan_down(Load ld, int64_t n, const int
   } else {
     before = part[blockIdx.x];
   }
-#pragma unroll 4
+#pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
-    const T x = ld(i < hi ? i : hi);
-    tile[pad(r * kScanThreads + threadIdx.x)] = i < n_eff ? x : (T)0;
+    tile[pad(r * kScanThreads + threadIdx.x)] = i < n_eff ? xs[r] : (T)0;
   }
   __syncthreads();
   T loc[kItems];
