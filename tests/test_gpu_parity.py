@@ -179,10 +179,21 @@ def _expected_lists(sp, sensor, g_n):
     return tl.tile_lists(per, depth, keep, n_t)
 
 
-@pytest.mark.parametrize("kind", ["camera", "lidar"])
+@pytest.mark.parametrize("kind", ["camera", "camera_256_supertiles", "camera_many_supertiles", "lidar"])
 def test_bin_sort_bit_exact(kind):
     if kind == "camera":
         g, sensor = cam_scene(n=8000)
+        rig, G, sp = _pass([sensor], [], g)
+    elif kind == "camera_256_supertiles":
+        # 128 x 128 tiles of 4 x 4 pixels: 16 x 16 = 256 supertiles, every digit of the one-pass
+        # supertile sort in use
+        g, sensor = cam_scene(n=8000, W=512, H=512, tile=(4, 4))
+        rig, G, sp = _pass([sensor], [], g)
+    elif kind == "camera_many_supertiles":
+        # 200 x 150 tiles of 8 x 8 pixels: 25 x 19 = 475 supertiles, more than one radix digit, so
+        # the supertile sort takes two passes and a separate ranges pass (6 supertiles above: one
+        # pass whose scatter writes the ranges)
+        g, sensor = cam_scene(n=8000, W=1600, H=1200, tile=(8, 8))
         rig, G, sp = _pass([sensor], [], g)
     else:
         g, sensor = lidar_rs_scene()
