@@ -11,7 +11,9 @@
 //   3. tiles are grouped into supertiles (camera 8 x 8 tiles, lidar 4 x 4); a scan in depth
 //      order gives every record the place of its (supertile, record) entries, one per supertile
 //      its rectangle meets, and they are written in depth order;
-//   4. a stable radix sort by supertile groups those entries, each supertile's in depth order;
+//   4. a stable radix sort by supertile groups those entries, each supertile's in depth order,
+//      and gives each supertile its range of entries (with at most 256 supertiles the sort is
+//      one pass and its scatter writes the ranges from the digit totals; else a ranges pass);
 //   5. each supertile's entries are cut into items of at most 256; per item, the entries
 //      meeting each of the supertile's tiles (64 or 16) are counted (wavefront ballots), one scan of the
 //      counts gives every tile its list range and every item its first position in each list,
