@@ -124,32 +124,47 @@ __device__ __forceinline__ int listed_entries(int nt, int64_t base, int64_t k_ca
 }
 
 // Work items (record, chunk) for every record that the adjoint touched and that has more than
-// kCoopEntries listed entries, appended to partition (wavefront index % kLongParts) of `list`:
-// one atomic per wavefront, spread over kLongParts counters.  The list order varies from run
-// to run; the sums do not.
+// kCoopEntries listed entries, appended to partition ((record / 64) % kLongParts) of `list`:
+// one atomic per 64 records that hold such a record, spread over kLongParts counters.  A
+// wavefront covers 64 x kRecPerLane records (lane l: records l, l + 64, ...).  The list order
+// varies from run to run; the sums do not.
+constexpr int kRecPerLane = 4;
+
 __global__ __launch_bounds__(256) void k_long_records(const int32_t* __restrict__ n_tiles,
                                                       const uint8_t* __restrict__ rflag,
                                                       const int64_t* __restrict__ entry_base, int64_t n_rec,
                                                       int64_t k_cap, uint2* __restrict__ list, int64_t cap,
                                                       int32_t* __restrict__ n_list) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int chunks = 0;
-  if (r < n_rec && n_tiles[r] > kCoopEntries && rflag[r] != 0)
-    chunks = (listed_entries(n_tiles[r], entry_base[r], k_cap) + kChunk - 1) / kChunk;
-  if (__ballot(chunks > 0) == 0) return;   // uniform over the wavefront
   const int lane = threadIdx.x & 63;
-  int incl = chunks;   // inclusive prefix over the wavefront
+  const int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 * kRecPerLane) + lane;
+  int nt[kRecPerLane];
+  bool hit[kRecPerLane];
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
+  for (int j = 0; j < kRecPerLane; ++j) {   // unconditional loads, in bounds, all in flight together
+    const int64_t r = r0 + 64 * j;
+    const int64_t rc = r < n_rec ? r : n_rec - 1;
+    nt[j] = n_tiles[rc];
+    hit[j] = r < n_rec && rflag[rc] != 0;
   }
-  const int part = (int)((r >> 6) % kLongParts);
-  int first = 0;
-  if (lane == 63) first = atomicAdd(n_list + part, incl);
-  first = __shfl(first, 63, 64);
-  uint2* dst = list + part * cap + first + (incl - chunks);
-  for (int c = 0; c < chunks; ++c) dst[c] = make_uint2((uint32_t)r, (uint32_t)c);
+#pragma unroll
+  for (int j = 0; j < kRecPerLane; ++j) {
+    const int64_t r = r0 + 64 * j;
+    int chunks = 0;
+    if (hit[j] && nt[j] > kCoopEntries) chunks = (listed_entries(nt[j], entry_base[r], k_cap) + kChunk - 1) / kChunk;
+    if (__ballot(chunks > 0) == 0) continue;   // uniform over the wavefront
+    int incl = chunks;   // inclusive prefix over the wavefront
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    const int part = (int)((r >> 6) % kLongParts);   // one partition per 64 consecutive records
+    int first = 0;
+    if (lane == 63) first = atomicAdd(n_list + part, incl);
+    first = __shfl(first, 63, 64);
+    uint2* dst = list + part * cap + first + (incl - chunks);
+    for (int c = 0; c < chunks; ++c) dst[c] = make_uint2((uint32_t)r, (uint32_t)c);
+  }
 }
 
 // One wavefront per (record, chunk): lane l sums the flagged rows at chunk positions l, l + 64,
@@ -222,8 +237,11 @@ __global__ __launch_bounds__(256) void k_slot_reduce_long(const uint2* __restric
   }
 }
 
-// Gradient of every touched record, one thread per Gaussian and sensor loop: the sum of the
-// rasteriser's rows over the record's entries (positions [entry_base, entry_base + n_tiles) of
+constexpr int kGaussPerLane = 4;   // Gaussians per lane of the projection adjoint and the row sums
+
+// Gradient of every touched record, 64 x kGaussPerLane Gaussians per wavefront (lane l:
+// Gaussians l, l + 64, ...; the flags of one sensor's records loaded together), sensors in
+// order per Gaussian: the sum of the rasteriser's rows over the record's entries (positions [entry_base, entry_base + n_tiles) of
 // the slot array, rows whose flag is set; a long record's total sits in its first row), taken
 // in a fixed order so that the result does not depend on scheduling.  The geometric part (kNV
 // values) goes to g2d[rec] (added to the atomic part of split lidar tiles when `accumulate`),
@@ -240,74 +258,73 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const DevSensor* __restrict
                                                      float* __restrict__ dfeat) {
   constexpr int V = kNV + CMAX;
   constexpr int SW = slot_stride(CMAX);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t i0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 * kGaussPerLane) + lane;
   for (int k = 0; k < count; ++k) {
-    const int64_t r = (int64_t)k * N + i;
-    if (rflag[r] == 0) continue;
-    const int nt = n_tiles[r];
-    const int64_t base = entry_base[r];
-    const int n = listed_entries(nt, base, k_cap);
-    float acc[V];
+    uint32_t tm = 0;   // bit j: record (k, i0 + 64 j) was touched; flags loaded together
 #pragma unroll
-    for (int v = 0; v < V; ++v) acc[v] = 0.f;
-    if (nt > kCoopEntries) {
-      // chunk totals from k_slot_reduce_long, in chunk order
-      const int nc = (n + kChunk - 1) / kChunk;
-      for (int c = 0; c < nc; ++c) add_row<SW>(slots + (base + (int64_t)c * kChunk) * SW, acc);
-    } else if (n > 0) {
-      uint32_t fm = flag_mask(flags, base, n);
-      while (fm) {   // two rows in flight per iteration
-        const int j0 = __builtin_ctz(fm);
-        fm &= fm - 1;
-        const bool two = fm != 0;
-        const int j1 = two ? __builtin_ctz(fm) : j0;
-        if (two) fm &= fm - 1;
-        float r0[V], r1[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) r0[v] = r1[v] = 0.f;
-        add_row<SW>(slots + (base + j0) * SW, r0);
-        add_row<SW>(slots + (base + j1) * SW, r1);
-#pragma unroll
-        for (int v = 0; v < V; ++v) acc[v] += two ? r0[v] + r1[v] : r0[v];
-      }
+    for (int j = 0; j < kGaussPerLane; ++j) {
+      const int64_t i = i0 + 64 * j;
+      const int64_t ic = i < N ? i : N - 1;   // unconditional loads, in bounds
+      tm |= (rflag[(int64_t)k * N + ic] != 0 && i < N) ? 1u << j : 0u;
     }
-    // lidar records add to the atomic part of split tiles; camera rows are only ever written here
-    float* q = g2d + r * kNV;
-    const bool add = accumulate && sens[k].kind == kLidar;
+    for (; tm != 0; tm &= tm - 1) {
+      const int64_t i = i0 + 64 * __builtin_ctz(tm);
+      const int64_t r = (int64_t)k * N + i;
+      const int nt = n_tiles[r];
+      const int64_t base = entry_base[r];
+      const int n = listed_entries(nt, base, k_cap);
+      float acc[V];
 #pragma unroll
-    for (int v = 0; v < kNV; ++v) q[v] = add ? q[v] + acc[v] : acc[v];
-    if (dfeat) {
-      const DevSensor& S = sens[k];
-      float* fp = dfeat + i * c_total + S.feat_off;
+      for (int v = 0; v < V; ++v) acc[v] = 0.f;
+      if (nt > kCoopEntries) {
+        // chunk totals from k_slot_reduce_long, in chunk order
+        const int nc = (n + kChunk - 1) / kChunk;
+        for (int c = 0; c < nc; ++c) add_row<SW>(slots + (base + (int64_t)c * kChunk) * SW, acc);
+      } else if (n > 0) {
+        uint32_t fm = flag_mask(flags, base, n);
+        while (fm) {   // two rows in flight per iteration
+          const int j0 = __builtin_ctz(fm);
+          fm &= fm - 1;
+          const bool two = fm != 0;
+          const int j1 = two ? __builtin_ctz(fm) : j0;
+          if (two) fm &= fm - 1;
+          float r0[V], r1[V];
 #pragma unroll
-      for (int c = 0; c < CMAX; ++c)
-        if (c < S.n_ch) fp[c] += acc[kNV + c];
+          for (int v = 0; v < V; ++v) r0[v] = r1[v] = 0.f;
+          add_row<SW>(slots + (base + j0) * SW, r0);
+          add_row<SW>(slots + (base + j1) * SW, r1);
+#pragma unroll
+          for (int v = 0; v < V; ++v) acc[v] += two ? r0[v] + r1[v] : r0[v];
+        }
+      }
+      // lidar records add to the atomic part of split tiles; camera rows are only ever written here
+      float* q = g2d + r * kNV;
+      const bool add = accumulate && sens[k].kind == kLidar;
+#pragma unroll
+      for (int v = 0; v < kNV; ++v) q[v] = add ? q[v] + acc[v] : acc[v];
+      if (dfeat) {
+        const DevSensor& S = sens[k];
+        float* fp = dfeat + i * c_total + S.feat_off;
+#pragma unroll
+        for (int c = 0; c < CMAX; ++c)
+          if (c < S.n_ch) fp[c] += acc[kNV + c];
+      }
     }
   }
 }
 
-// Projection adjoint, one thread per Gaussian: chains every record's g2d gradient (mean.x,
-// mean.y, vel.x, vel.y, conic a, b, c, o_eff, depth (z | r), v_r) through the projection.
-// Projection adjoint, one thread per Gaussian over the call's sensors.  With sensor-velocity
-// gradients requested, every touched record also contributes dL/dlin = -g and dL/dang = g x mu_s
-// (g = dL/dvrel, mu_s the sensor-frame mean), summed per sensor over the wavefront with a
-// reduce-scatter and one atomic per value.
-__global__ __launch_bounds__(256) void k_project_bwd(const DevSensor* __restrict__ sens, int count, SplatGaussians g,
-                                                     const uint8_t* __restrict__ rflag, const float* __restrict__ g2d,
-                                                     SplatGrads gr) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool in = i < g.n;
-  const bool want_s = gr.sensor_lin_vel || gr.sensor_ang_vel;   // uniform
-  bool touched = false;
-  if (in)
-    for (int k = 0; k < count && !touched; ++k) touched = rflag[(int64_t)k * g.n + i] != 0;
-  if (!want_s) {
-    if (!in || !touched) return;
-  } else if (__ballot(in && touched) == 0) {
-    return;   // uniform over the wavefront: nothing to add
-  }
-  const bool live = in && touched;
+// Projection adjoint of one Gaussian (i < N, with a gradient in at least one record when `live`):
+// chains every touched record's g2d gradient (mean.x, mean.y, vel.x, vel.y, conic a, b, c,
+// o_eff, depth (z | r), v_r) through the projection, the call's sensors in order, and adds the
+// result to the Gaussian's gradients.  With sensor-velocity gradients requested (uniform), every
+// touched record also contributes dL/dlin = -g and dL/dang = g x mu_s (g = dL/dvrel, mu_s the
+// sensor-frame mean), summed per sensor over the wavefront with a reduce-scatter and one atomic
+// per value; then every lane of the wavefront calls this together.
+__device__ __forceinline__ void project_bwd_one(const DevSensor* __restrict__ sens, int count, const SplatGaussians& g,
+                                                const uint8_t* __restrict__ rflag, const float* __restrict__ g2d,
+                                                const SplatGrads& gr, int64_t i, bool live, bool want_s, int slot,
+                                                bool store) {
   GaussLoad G;
   QuatRot qr;
   float s[3], M[9];
@@ -318,8 +335,6 @@ __global__ __launch_bounds__(256) void k_project_bwd(const DevSensor* __restrict
   float dmu[3] = {0.f, 0.f, 0.f}, dM[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, dvg[3] = {0.f, 0.f, 0.f};
   float dop = 0.f;
   bool any = false;
-  bool store = false;
-  const int slot = want_s ? scatter_slot<6>(threadIdx.x & 63, store) : 0;
   for (int k = 0; k < count; ++k) {
     const int64_t r = (int64_t)k * g.n + i;
     const bool hit = live && rflag[r] != 0;   // a gradient reached this record
@@ -363,6 +378,39 @@ __global__ __launch_bounds__(256) void k_project_bwd(const DevSensor* __restrict
   }
 }
 
+// Projection adjoint over the call's Gaussians.  A wavefront covers 64 x kGaussPerLane of them
+// (lane l: Gaussians l, l + 64, ...): the gradient flags of all of them are loaded first, all
+// in flight together, and only the groups of 64 that hold a touched Gaussian run the projection
+// adjoint — most Gaussians of a scene receive no gradient, and the kernel's register use (3
+// wavefronts per SIMD) would otherwise spend most of its time launching wavefronts that only
+// test their flags.
+__global__ __launch_bounds__(256) void k_project_bwd(const DevSensor* __restrict__ sens, int count, SplatGaussians g,
+                                                     const uint8_t* __restrict__ rflag, const float* __restrict__ g2d,
+                                                     SplatGrads gr) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 * kGaussPerLane) + lane;
+  uint32_t tm = 0;   // bit j: Gaussian i0 + 64 j received a gradient in some record
+  for (int k = 0; k < count; ++k) {
+#pragma unroll
+    for (int j = 0; j < kGaussPerLane; ++j) {
+      const int64_t i = i0 + 64 * j;
+      const int64_t ic = i < g.n ? i : g.n - 1;   // unconditional loads, in bounds
+      const bool f = rflag[(int64_t)k * g.n + ic] != 0;
+      tm |= (f && i < g.n) ? 1u << j : 0u;
+    }
+  }
+  if (__ballot(tm != 0) == 0) return;   // uniform over the wavefront
+  const bool want_s = gr.sensor_lin_vel || gr.sensor_ang_vel;   // uniform
+  bool store = false;
+  const int slot = want_s ? scatter_slot<6>(lane, store) : 0;
+#pragma unroll 1
+  for (int j = 0; j < kGaussPerLane; ++j) {
+    const bool live = ((tm >> j) & 1u) != 0;
+    if (__ballot(live) == 0) continue;   // uniform: nothing to add for this group
+    project_bwd_one(sens, count, g, rflag, g2d, gr, i0 + 64 * j, live, want_s, slot, store);
+  }
+}
+
 hipError_t launch_project(const CallView& v, const SplatGaussians& g, const SplatProjected& p, SplatStatus* st,
                           hipStream_t s) {
   if (g.n <= 0) return hipSuccess;
@@ -377,16 +425,17 @@ hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const 
   const int cm = cmax_bucket(v.c_max);
   if (w.stride != slot_stride(cm)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)div_up(g.n, 256));
+  const dim3 grid_bwd((unsigned)div_up(g.n, 256 * kGaussPerLane));
   float* dfeat = v.c_max > 0 ? gr.features : nullptr;
   const int64_t n_rec = (int64_t)v.count * g.n;
   if (!w.rows) {   // every work item added its sums to g2d and the features gradient
-    hipLaunchKernelGGL(k_project_bwd, grid, dim3(256), 0, s, v.sens, v.count, g, (const uint8_t*)w.rflag,
+    hipLaunchKernelGGL(k_project_bwd, grid_bwd, dim3(256), 0, s, v.sens, v.count, g, (const uint8_t*)w.rflag,
                        (const float*)w.g2d, gr);
     return hipGetLastError();
   }
   if (w.long_cap != long_part_cap(n_rec, L.k_cap)) return hipErrorInvalidValue;
   // w.n_long was cleared by the caller before the rasteriser adjoint
-  hipLaunchKernelGGL(k_long_records, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, (const int32_t*)p.n_tiles,
+  hipLaunchKernelGGL(k_long_records, dim3((unsigned)div_up(n_rec, 256 * kRecPerLane)), dim3(256), 0, s, (const int32_t*)p.n_tiles,
                      (const uint8_t*)w.rflag, (const int64_t*)L.entry_base, n_rec, L.k_cap, (uint2*)w.long_list,
                      w.long_cap, w.n_long);
   const int64_t long_blocks = div_up(n_rec, 4) < 4096 ? div_up(n_rec, 4) : 4096;
@@ -395,7 +444,7 @@ hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const 
     hipLaunchKernelGGL(k_slot_reduce_long<CM>, dim3((unsigned)long_blocks), dim3(256), 0, s,                      \
                        (const uint2*)w.long_list, w.long_cap, (const int32_t*)w.n_long,                           \
                        (const int32_t*)p.n_tiles, (const int64_t*)L.entry_base, w.slots, w.flags, L.k_cap);       \
-    hipLaunchKernelGGL(k_slot_reduce<CM>, grid, dim3(256), 0, s, v.sens, v.count, g.n, g.c_total,                 \
+    hipLaunchKernelGGL(k_slot_reduce<CM>, grid_bwd, dim3(256), 0, s, v.sens, v.count, g.n, g.c_total,                 \
                        (const int32_t*)p.n_tiles, (const uint8_t*)w.rflag, (const int64_t*)L.entry_base,          \
                        (const float*)w.slots, (const uint8_t*)w.flags, L.k_cap, v.has_lidar, w.g2d, dfeat);      \
     break;
@@ -407,7 +456,7 @@ hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const 
     SR_CASE(48)
   }
 #undef SR_CASE
-  hipLaunchKernelGGL(k_project_bwd, grid, dim3(256), 0, s, v.sens, v.count, g, (const uint8_t*)w.rflag,
+  hipLaunchKernelGGL(k_project_bwd, grid_bwd, dim3(256), 0, s, v.sens, v.count, g, (const uint8_t*)w.rflag,
                      (const float*)w.g2d, gr);
   return hipGetLastError();
 }
