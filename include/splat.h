@@ -191,7 +191,9 @@ typedef struct SplatTileLists {
                              invalid rays                                                      */
   int32_t* work;          /* [work_cap, 2] work items (tile, first position in ray_order; camera
                              tiles of a batched call are items (tile, 0))                       */
-  int32_t* n_work;        /* [2] number of work items; queue counter of the persistent kernels  */
+  int32_t* n_work;        /* [3] number of work items; queue counter of the persistent kernels;
+                             1 when a lidar tile of the call has more than SPLAT_RAYS_PER_ITEM
+                             rays (its items add their gradients atomically), else 0          */
   int64_t work_cap;       /* >= n_tiles + ceil(n_rays / 256) + 1                               */
 } SplatTileLists;
 

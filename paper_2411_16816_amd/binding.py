@@ -274,7 +274,7 @@ class SensorPass:
             self.ray_order = torch.empty((max(1, n_lidar_rays),), **i32)
             self.ray_range = torch.empty((self.n_tiles + 1, 2), **i32)
             self.work = torch.empty((self.work_cap, 2), **i32)
-            self.n_work = torch.zeros((2,), **i32)
+            self.n_work = torch.zeros((3,), **i32)
         else:
             self.work_cap = 0
             self.ray_order = self.ray_range = self.work = self.n_work = None

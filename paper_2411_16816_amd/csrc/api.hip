@@ -332,16 +332,18 @@ int64_t adjoint_row_limit() { return g_row_limit.load(); }
 // One launch clears what the adjoint accumulates into: the slot flags, the touched-record flags,
 // the atomic part (where lidar tiles can be split, and for every record when the call keeps no
 // rows), the queue counter and the long-record list counts.
-static hipError_t adjoint_clears(const CallView& v, const Workspace& w, int64_t k_cap, int64_t n_gauss,
+static hipError_t adjoint_clears(const CallView& v, const Workspace& w, const SplatTileLists& L, int64_t n_gauss,
                                  hipStream_t s) {
   FillSegments f;
-  if (w.rows) f.add(w.flags, div_up(k_cap, 4));
+  if (w.rows) f.add(w.flags, div_up(L.k_cap, 4));
   f.add(w.rflag, div_up((int64_t)v.count * n_gauss, 4));
   if (v.has_lidar || !w.rows) {
-    // with rows only lidar records (the call's last sensors) receive atomic parts: zero theirs
+    // with rows only lidar records (the call's last sensors) receive atomic parts, from the
+    // items of split lidar tiles: zero theirs when bin_sort found such a tile (n_work[2])
     int k_lid = 0;
     while (w.rows && k_lid < v.count && v.host[k_lid].kind != kLidar) ++k_lid;
-    f.add(w.g2d + (int64_t)k_lid * n_gauss * kNV, (int64_t)(v.count - k_lid) * n_gauss * kNV);
+    f.add(w.g2d + (int64_t)k_lid * n_gauss * kNV, (int64_t)(v.count - k_lid) * n_gauss * kNV, 0u,
+          w.rows ? L.n_work + 2 : nullptr);
   }
   f.add(w.qctr, 1);
   if (w.rows) f.add(w.n_long, kLongParts);
@@ -368,7 +370,7 @@ static int raster_bwd_impl(const SplatGaussians* g, const SplatRig* r, int32_t f
     v.queue_grouped = q != r->grouped_queue.end() && q->second;
   }
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = adjoint_clears(v, w, lists->k_cap, g->n, s);
+  hipError_t e = adjoint_clears(v, w, *lists, g->n, s);
   if (e == hipSuccess)
     e = launch_raster_bwd(v, *g, *proj, *lists, support, *saved, dF, dD, dA, w, gr->features, gr->sensor_time_offset, s,
                           take_timer());

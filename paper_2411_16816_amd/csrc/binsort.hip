@@ -56,6 +56,7 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) { return
 __global__ void k_fill_segments(FillSegments f) {
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
   for (int k = 0; k < f.count; ++k) {
+    if (f.seg[k].cond && *f.seg[k].cond == 0) continue;   // uniform: the segment is not needed
     uint32_t* p = f.seg[k].p;
     const uint32_t v = f.seg[k].value;
     for (int64_t i = t0; i < f.seg[k].n; i += stride) p[i] = v;
@@ -1140,10 +1141,12 @@ __device__ __forceinline__ bool camera_tile(const DevSensor* sens, int count, in
 }
 
 // work items per bin: one per camera tile, ceil(rays / 256) per lidar tile and for the bin of
-// rays outside every tile (bin n_tiles)
+// rays outside every tile (bin n_tiles); also clears the split flag n_work[2], which k_work_emit
+// sets
 __global__ void k_work_count(const DevSensor* __restrict__ sens, int count, const int2* __restrict__ range,
-                             int64_t n_tiles, int64_t* __restrict__ cnt) {
+                             int64_t n_tiles, int64_t* __restrict__ cnt, int32_t* __restrict__ n_work) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) n_work[2] = 0;
   if (t > n_tiles) return;
   if (camera_tile(sens, count, t, n_tiles)) {
     cnt[t] = 1;
@@ -1169,6 +1172,7 @@ __global__ void k_work_emit(const DevSensor* __restrict__ sens, int count, const
     return;
   }
   int2 r = range[t];
+  if (t < n_tiles && r.y - r.x > SPLAT_RAYS_PER_ITEM) n_work[2] = 1;   // a split lidar tile
   for (int p = r.x; p < r.y; p += SPLAT_RAYS_PER_ITEM, ++o)
     if (o < work_cap) work[o] = make_int2((int)t, p);
 }
@@ -1316,7 +1320,7 @@ static hipError_t launch_ray_bins(const CallView& v, const SplatTileLists& L, co
     return e;
   }
   hipLaunchKernelGGL(k_work_count, dim3((unsigned)div_up(bins, 256)), dim3(256), 0, s, v.sens, v.count,
-                     (const int2*)L.ray_range, v.n_tiles, w.wcount);
+                     (const int2*)L.ray_range, v.n_tiles, w.wcount, L.n_work);
   // per-bin offsets, and the total behind them for k_work_emit
   if ((e = device_scan<int64_t>(LoadI64{w.wcount}, bins, w.wcount, w.wpart, s, StoreTotal{w.wcount + bins})) !=
       hipSuccess)

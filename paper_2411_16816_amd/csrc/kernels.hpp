@@ -145,12 +145,13 @@ constexpr int kMaxFillSegs = 6;
 struct FillSegments {
   struct Seg {
     uint32_t* p;
-    int64_t n;        // words
-    uint32_t value;   // bit pattern (0.0f = 0)
+    int64_t n;             // words
+    uint32_t value;        // bit pattern (0.0f = 0)
+    const int32_t* cond;   // device flag: the segment is filled only if *cond != 0 (null: always)
   } seg[kMaxFillSegs];
   int count = 0;
-  void add(void* p, int64_t n, uint32_t value = 0u) {
-    if (p && n > 0 && count < kMaxFillSegs) seg[count++] = Seg{(uint32_t*)p, n, value};
+  void add(void* p, int64_t n, uint32_t value = 0u, const int32_t* cond = nullptr) {
+    if (p && n > 0 && count < kMaxFillSegs) seg[count++] = Seg{(uint32_t*)p, n, value, cond};
   }
 };
 hipError_t launch_fill_segments(const FillSegments& f, hipStream_t s);

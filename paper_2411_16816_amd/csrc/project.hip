@@ -244,9 +244,9 @@ constexpr int kGaussPerLane = 4;   // Gaussians per lane of the projection adjoi
 // order per Gaussian: the sum of the rasteriser's rows over the record's entries (positions [entry_base, entry_base + n_tiles) of
 // the slot array, rows whose flag is set; a long record's total sits in its first row), taken
 // in a fixed order so that the result does not depend on scheduling.  The geometric part (kNV
-// values) goes to g2d[rec] (added to the atomic part of split lidar tiles when `accumulate`),
-// the channel part to the features gradient.  Untouched records have no gradient and are
-// skipped here and in the projection adjoint.
+// values) goes to g2d[rec] (added to the atomic part of split lidar tiles when `accumulate` and
+// bin_sort found such a tile, *split != 0), the channel part to the features gradient.
+// Untouched records have no gradient and are skipped here and in the projection adjoint.
 template <int CMAX>
 __global__ __launch_bounds__(256) void k_slot_reduce(const DevSensor* __restrict__ sens, int count, int64_t N,
                                                      int c_total, const int32_t* __restrict__ n_tiles,
@@ -254,8 +254,8 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const DevSensor* __restrict
                                                      const int64_t* __restrict__ entry_base,
                                                      const float* __restrict__ slots,
                                                      const uint8_t* __restrict__ flags, int64_t k_cap,
-                                                     bool accumulate, float* __restrict__ g2d,
-                                                     float* __restrict__ dfeat) {
+                                                     bool accumulate, const int32_t* __restrict__ split,
+                                                     float* __restrict__ g2d, float* __restrict__ dfeat) {
   constexpr int V = kNV + CMAX;
   constexpr int SW = slot_stride(CMAX);
   const int lane = threadIdx.x & 63;
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const DevSensor* __restrict
       }
       // lidar records add to the atomic part of split tiles; camera rows are only ever written here
       float* q = g2d + r * kNV;
-      const bool add = accumulate && sens[k].kind == kLidar;
+      const bool add = accumulate && sens[k].kind == kLidar && *split != 0;
 #pragma unroll
       for (int v = 0; v < kNV; ++v) q[v] = add ? q[v] + acc[v] : acc[v];
       if (dfeat) {
@@ -446,7 +446,8 @@ hipError_t launch_project_bwd(const CallView& v, const SplatGaussians& g, const 
                        (const int32_t*)p.n_tiles, (const int64_t*)L.entry_base, w.slots, w.flags, L.k_cap);       \
     hipLaunchKernelGGL(k_slot_reduce<CM>, grid_bwd, dim3(256), 0, s, v.sens, v.count, g.n, g.c_total,                 \
                        (const int32_t*)p.n_tiles, (const uint8_t*)w.rflag, (const int64_t*)L.entry_base,          \
-                       (const float*)w.slots, (const uint8_t*)w.flags, L.k_cap, v.has_lidar, w.g2d, dfeat);      \
+                       (const float*)w.slots, (const uint8_t*)w.flags, L.k_cap, v.has_lidar,                      \
+                       (const int32_t*)L.n_work + 2, w.g2d, dfeat);                                               \
     break;
   switch (cm) {
     SR_CASE(4)
