@@ -560,6 +560,14 @@ def _grad_check(kind, seed, lidar_tile_az=16):
     sp = b.SensorPass(rig, 0, 1, g.n, 1)
     sp.fit_capacity(G)
     sp.render(G)
+    if kind != "camera":
+        # bin_sort's split flag (n_work[2]): set exactly when a tile holds more than 256 rays; the
+        # adjoint clears the lidar records' atomic accumulators only then
+        torch.cuda.synchronize()
+        rr = sp.ray_range.cpu().numpy().reshape(-1, 2)[:-1]
+        split = int(np.any(rr[:, 1] - rr[:, 0] > 256))
+        assert split == (1 if lidar_tile_az * 8 > 256 else 0)
+        assert int(sp.n_work.cpu()[2]) == split
     R = sensor.n_rays
     C = sensor.n_channels
     up = np.random.default_rng(seed + 1)
